@@ -1,0 +1,207 @@
+/*
+ * bgv.h -- C ABI of the MI355X (gfx950) BigGraphVis hot path.
+ *
+ * The library implements the data-parallel core of BigGraphVis (Moradi & Mondal,
+ * arXiv 2108.00529): an edge list goes in; community labels, a count-min-sketch
+ * weighted supergraph and 2-D ForceAtlas2 positions of that supergraph come out
+ * (Algorithm 3 and Section 4.1).  Every step runs in hand-written HIP kernels.
+ *
+ * Conventions shared by every entry point
+ *   - Pointers marked "dev" are device memory (hipMalloc'd, e.g. a torch tensor's
+ *     data_ptr()); pointers marked "host" are host memory.  Every buffer is owned by
+ *     the caller and is never freed or reallocated by the library.
+ *   - Scratch memory comes only from the caller's workspace `ws` (dev), at least the
+ *     size returned by the matching *_workspace() query, 256-byte aligned.  The
+ *     library itself never calls hipMalloc.
+ *   - Work is enqueued on `stream` and is asynchronous, except where an entry point
+ *     says it synchronises.  Calls on distinct streams need distinct workspaces.
+ *   - Arguments are validated on the host before any HIP call; a rejected call
+ *     touches no device memory.  No C++ exception crosses this boundary.
+ *   - Integer results are identical for every launch configuration; floating-point
+ *     results are identical run to run (fixed reduction orders, no FP atomics).
+ *   - Edge lists are int32 (m, 2) row-major: edge i is (edges[2i], edges[2i+1]), and
+ *     i is its position in the stream.  Node ids must lie in [0, n).
+ */
+#ifndef BGV_H
+#define BGV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *bgv_stream_t; /* a hipStream_t; NULL = the null stream */
+
+typedef int32_t bgv_status;
+#define BGV_OK 0
+#define BGV_E_INVALID (-1)     /* an argument is out of its documented range      */
+#define BGV_E_WORKSPACE (-3)   /* ws is NULL, misaligned or smaller than required */
+#define BGV_E_HIP (-4)         /* a HIP call failed; see bgv_last_error()          */
+
+/* Human-readable name of a status code (static storage). */
+const char *bgv_status_string(bgv_status s);
+/* Message of the last failing call on this host thread ("" if none). */
+const char *bgv_last_error(void);
+
+/* ---------------------------------------------------------------------------- */
+/* Streaming community detection                                                 */
+/* ---------------------------------------------------------------------------- */
+/*
+ * Paper: Section 3.2 (the streaming rule), Section 3.2.1 and Algorithm 3 (parallel
+ * passes with a growing threshold).  Every streamed edge raises the degree counter
+ * of both endpoints; when both counters are at most the pass threshold, the endpoint
+ * with the smaller counter joins the community of the other; equal counters do
+ * nothing; self-loops are ignored.  Counters accumulate over passes (Algorithm 3
+ * initialises them once).  Pass p (0-based) uses threshold D1 * growth^p, saturating
+ * at INT32_MAX.
+ *
+ * Parallel semantics (batch-synchronous): each pass is cut into chunks of `chunk`
+ * consecutive edges.  Within a chunk all counter increments happen first; then every
+ * edge decides with the chunk-end counters and the labels as they stood when the
+ * chunk began; a node proposed to by several edges takes the label from the edge of
+ * smallest stream index.  chunk = 1 is the sequential rule; `chunk` is part of the
+ * result's definition, not a tuning knob.
+ */
+typedef struct {
+    int32_t threshold; /* D1 >= 0: threshold of the first pass                   */
+    int32_t passes;    /* P >= 1                                                 */
+    int32_t growth;    /* >= 1: threshold factor between passes                   */
+    int32_t reserved;  /* must be 0                                              */
+    int64_t chunk;     /* >= 1: edges per synchronous chunk                        */
+} bgv_cd_params;
+
+/* Workspace bytes for bgv_community (0 only on invalid arguments). */
+size_t bgv_community_workspace(int32_t n, int64_t m, const bgv_cd_params *p);
+
+/*
+ * n in [1, 2^31-1]; m in [0, 2^31-1]; edges: dev int32 (m,2), ids in [0,n).
+ * Outputs (dev): labels int32[n] (community label = id of a node, the node's own id
+ * if it never joined), degree int32[n] (true degree: occurrences as an endpoint of a
+ * non-loop edge), volume int64[n] or NULL (volume[c] = sum of degree over nodes with
+ * label c; the exact weight the sketch estimates).  Ids outside [0, n) are undefined
+ * behaviour (not checked on the device).
+ */
+bgv_status bgv_community(int32_t n, int64_t m, const int32_t *edges, const bgv_cd_params *p,
+                         int32_t *labels, int32_t *degree, int64_t *volume,
+                         void *ws, size_t ws_bytes, bgv_stream_t stream);
+
+/* ---------------------------------------------------------------------------- */
+/* Count-min-sketch supergraph                                                   */
+/* ---------------------------------------------------------------------------- */
+/*
+ * Paper: Section 3.3 and Algorithm 2 (count-min sketch: r rows of c counters, one
+ * pairwise-independent hash per row, estimate = minimum over the rows),
+ * Section 4.1 (supernode weight: each node v adds its degree to row i at column
+ * hash_i(com(v))), Algorithm 3 (the supergraph handed to ForceAtlas2).
+ *
+ * Supernodes are the distinct labels, numbered by ascending label (sid).  Sketch 1
+ * estimates each supernode's weight (sum of its nodes' degrees).  Sketch 2 counts
+ * inter-community edges: every non-loop edge with labels a != b adds 1 at the key
+ * (min(a,b), max(a,b)).  Superedges are the distinct such keys as (sid_lo, sid_hi)
+ * pairs, sid_lo < sid_hi, sorted ascending; their weight is the sketch-2 estimate.
+ *
+ * Hash of row r with coefficients (A, B, C) (64-bit, arithmetic mod 2^64):
+ *   key x:        t = A*x + B;          column = ((t >> 32) * cols) >> 32
+ *   pair (a < b): t = A*a + C*b + B;    column = ((t >> 32) * cols) >> 32
+ * The coefficients are the random draws of the hash family and are inputs.
+ */
+typedef struct {
+    int32_t rows;          /* 1..8                                                  */
+    int32_t cols;          /* 1..2^31-1                                             */
+    const uint64_t *coef1; /* host, rows*3 values (A,B,C per row) for sketch 1      */
+    const uint64_t *coef2; /* host, rows*3 values for sketch 2                      */
+} bgv_sketch_params;
+
+size_t bgv_supergraph_workspace(int32_t n, int64_t m, const bgv_sketch_params *s);
+
+/*
+ * Inputs (dev): edges (m,2), labels int32[n] and degree int32[n] from bgv_community.
+ * Outputs: K (host int32) supernodes and E_S (host int64) superedges;
+ *   super_label  dev int32[cap n]    label of supernode sid (ascending)
+ *   super_size   dev uint32[cap n]   sketch-1 estimate of the supernode weight
+ *   node_super   dev int32[n] or NULL   sid of each node's community
+ *   superedges   dev int32[cap m][2] (sid_lo, sid_hi), sorted
+ *   se_weight    dev uint32[cap m]   sketch-2 estimate of the superedge multiplicity
+ *   M1, M2       dev uint32[rows][cols] the two sketches (required)
+ * Synchronises `stream` (K and E_S are returned on the host).
+ */
+bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges, const int32_t *labels,
+                          const int32_t *degree, const bgv_sketch_params *s,
+                          int32_t *K, int64_t *E_S, int32_t *super_label, uint32_t *super_size,
+                          int32_t *node_super, int32_t *superedges, uint32_t *se_weight,
+                          uint32_t *M1, uint32_t *M2,
+                          void *ws, size_t ws_bytes, bgv_stream_t stream);
+
+/* ---------------------------------------------------------------------------- */
+/* ForceAtlas2 layout                                                            */
+/* ---------------------------------------------------------------------------- */
+/*
+ * Paper: Section 3.1 and Algorithm 1 (gravity, Barnes-Hut repulsion, attraction,
+ * swing-based speeds, displacement), in the force and speed laws of the cited
+ * ForceAtlas2 publication.  For node i with mass m_i:
+ *   repulsion  kr m_i m_j (x_i - x_j) / |x_i - x_j|^2   from every j != i (0 if coincident)
+ *   attraction a_e (x_j - x_i)                          along every edge e = (i, j)
+ *   gravity    -kg m_i x_i / |x_i|                      (0 at the origin)
+ * Per iteration, with F' the previous force (zero initially) and s the global speed
+ * (1 initially): swing_i = |F_i - F'_i|, traction_i = |F_i + F'_i| / 2;
+ * s = min(tau * sum m_i traction_i / sum m_i swing_i, 1.5 s) when the swing sum is
+ * positive; s_i = ks s / (1 + s sqrt(swing_i)), at most ksmax / |F_i|;
+ * x_i += s_i F_i; F' = F.
+ * Barnes-Hut (exact = 0): bodies are quantised in FP32 to a 2^16 x 2^16 grid over
+ * their bounding square and Morton-sorted; the tree splits a code range at its first
+ * differing bit; a range of equal codes is one leaf; a node with a P-bit common
+ * prefix has cell size s0 / 2^floor(P/2).  A node not containing i is replaced by
+ * its centre of mass when size^2 < theta^2 * dist^2; leaves are summed directly.
+ */
+typedef struct {
+    int32_t iters; /* >= 0                                                        */
+    int32_t exact; /* 1: all-pairs repulsion; 0: Barnes-Hut                        */
+    float theta;   /* Barnes-Hut opening parameter (>= 0)                          */
+    float kr;      /* repulsion constant                                           */
+    float kg;      /* gravity constant                                             */
+    float tau;     /* swing tolerance of the global speed                          */
+    float ks;      /* local speed constant                                         */
+    float ksmax;   /* cap of the displacement length                               */
+} bgv_fa2_params;
+
+size_t bgv_fa2_workspace(int32_t K, int64_t E, const bgv_fa2_params *p);
+
+/*
+ * K >= 1 nodes, E >= 0 undirected edges (dev int32 (E,2), ids in [0,K), no self-loops;
+ * repeated pairs count repeatedly).  attr_w dev float[E] (a_e) or NULL (a_e = 1);
+ * mass dev float[K] or NULL (m_i = number of incident edges + 1).
+ * In/out (dev): pos float (K,2); fprev float (K,2) (zeros for a fresh start);
+ * speed float[1] (1.0 for a fresh start).  Passing the state back in continues the
+ * run exactly where it stopped.
+ */
+bgv_status bgv_fa2_layout(int32_t K, int64_t E, const int32_t *edges, const float *attr_w,
+                          const float *mass, float *pos, float *fprev, float *speed,
+                          const bgv_fa2_params *p, void *ws, size_t ws_bytes, bgv_stream_t stream);
+
+/*
+ * ForceAtlas2 energy, whose negative gradient is the force field above (exact
+ * repulsion):  E = sum_e a_e |x_i - x_j|^2 / 2 - kr sum_{i<j} m_i m_j ln|x_i - x_j|
+ *                  + kg sum_i m_i |x_i|    (coincident pairs contribute 0).
+ * energy: dev double[1].  Pair terms in FP32, partial sums combined in FP64 in a
+ * fixed order.
+ */
+size_t bgv_fa2_energy_workspace(int32_t K, int64_t E);
+bgv_status bgv_fa2_energy(int32_t K, int64_t E, const int32_t *edges, const float *attr_w,
+                          const float *mass, const float *pos, float kr, float kg, double *energy,
+                          void *ws, size_t ws_bytes, bgv_stream_t stream);
+
+/*
+ * Gradient of that energy: grad = -F(pos) * g, with g = *grad_out (dev float[1]) or
+ * 1 when grad_out is NULL.  grad: dev float (K,2).  Same workspace as the energy.
+ */
+bgv_status bgv_fa2_grad(int32_t K, int64_t E, const int32_t *edges, const float *attr_w,
+                        const float *mass, const float *pos, float kr, float kg,
+                        const float *grad_out, float *grad,
+                        void *ws, size_t ws_bytes, bgv_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BGV_H */

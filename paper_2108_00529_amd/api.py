@@ -1,0 +1,219 @@
+"""Python binding of the C ABI (include/bgv.h): argument marshalling only.
+
+Every step of the hot path runs in the HIP kernels of libbgv.so; torch supplies device
+memory (outputs and workspaces) and the current stream.  Inputs must already be CUDA
+(HIP) tensors of the documented dtype.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _need(t, dtype, name, shape=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+    assert ws.data_ptr() % 256 == 0
+    return ws
+
+
+def validate_edges(edges: torch.Tensor, n: int) -> None:
+    """Host-side guard used before launches on untrusted input: ids in [0, n)."""
+    if edges.numel():
+        lo, hi = int(edges.min()), int(edges.max())
+        if lo < 0 or hi >= n:
+            raise ValueError(f"edge ids must lie in [0, {n}), got [{lo}, {hi}]")
+
+
+# ------------------------------------------------------------------- community --
+def community(edges: torch.Tensor, n: int, threshold: int, passes: int = 1, growth: int = 2,
+              chunk: int = 1, volume: bool = False, ws: torch.Tensor | None = None, stream=None):
+    """Streaming community detection.  Returns (labels int32[n], degree int32[n],
+    volume int64[n] or None)."""
+    m = edges.shape[0] if edges.dim() == 2 else 0
+    _need(edges, torch.int32, "edges", (m, 2))
+    p = L.CdParams(int(threshold), int(passes), int(growth), 0, int(chunk))
+    need = L.bgv_community_workspace(int(n), m, C.byref(p))
+    if need == 0:
+        raise L.BgvError(f"invalid community arguments (n={n}, m={m}, {threshold}, {passes}, {growth}, {chunk})")
+    dev = edges.device
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, dev)
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
+    degree = torch.empty(n, dtype=torch.int32, device=dev)
+    vol = torch.empty(n, dtype=torch.int64, device=dev) if volume else None
+    L.check(L.bgv_community(int(n), m, _ptr(edges), C.byref(p), _ptr(labels), _ptr(degree), _ptr(vol),
+                            _ptr(ws), ws.numel(), _stream(stream)), "bgv_community")
+    return labels, degree, vol
+
+
+# ------------------------------------------------------------------ supergraph --
+def supergraph(edges: torch.Tensor, labels: torch.Tensor, degree: torch.Tensor, rows: int, cols: int,
+               coef1: np.ndarray, coef2: np.ndarray, ws: torch.Tensor | None = None, stream=None):
+    """Count-min-sketch supergraph.  Synchronises the stream.  Returns a dict with K,
+    super_label, super_size, node_super, superedges (E,2), se_weight, M1, M2."""
+    n = labels.shape[0]
+    m = edges.shape[0]
+    _need(edges, torch.int32, "edges", (m, 2))
+    _need(labels, torch.int32, "labels", (n,))
+    _need(degree, torch.int32, "degree", (n,))
+    c1 = np.ascontiguousarray(coef1, dtype=np.uint64).reshape(rows, 3)
+    c2 = np.ascontiguousarray(coef2, dtype=np.uint64).reshape(rows, 3)
+    sp = L.SketchParams(int(rows), int(cols), c1.ctypes.data_as(C.c_void_p), c2.ctypes.data_as(C.c_void_p))
+    need = L.bgv_supergraph_workspace(int(n), int(m), C.byref(sp))
+    if need == 0:
+        raise L.BgvError(f"invalid supergraph arguments (n={n}, m={m}, rows={rows}, cols={cols})")
+    dev = edges.device
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, dev)
+    super_label = torch.empty(n, dtype=torch.int32, device=dev)
+    super_size = torch.empty(n, dtype=torch.int32, device=dev)       # uint32 bits
+    node_super = torch.empty(n, dtype=torch.int32, device=dev)
+    superedges = torch.empty((max(m, 1), 2), dtype=torch.int32, device=dev)
+    se_weight = torch.empty(max(m, 1), dtype=torch.int32, device=dev)  # uint32 bits
+    M1 = torch.empty((rows, cols), dtype=torch.int32, device=dev)      # uint32 bits
+    M2 = torch.empty((rows, cols), dtype=torch.int32, device=dev)
+    K = L.i32(0)
+    E = L.i64(0)
+    L.check(L.bgv_supergraph(int(n), int(m), _ptr(edges), _ptr(labels), _ptr(degree), C.byref(sp), C.byref(K),
+                             C.byref(E), _ptr(super_label), _ptr(super_size), _ptr(node_super), _ptr(superedges),
+                             _ptr(se_weight), _ptr(M1), _ptr(M2), _ptr(ws), ws.numel(), _stream(stream)),
+            "bgv_supergraph")
+    k, e = K.value, E.value
+    return dict(K=k, E=e, super_label=super_label[:k], super_size=super_size[:k], node_super=node_super,
+                superedges=superedges[:e], se_weight=se_weight[:e], M1=M1, M2=M2)
+
+
+# ----------------------------------------------------------------- ForceAtlas2 --
+def fa2_params(iters: int, exact: bool, theta: float = 1.2, kr: float = 1.0, kg: float = 1.0, tau: float = 1.0,
+               ks: float = 0.1, ksmax: float = 10.0) -> L.Fa2Params:
+    return L.Fa2Params(int(iters), 1 if exact else 0, float(theta), float(kr), float(kg), float(tau), float(ks),
+                       float(ksmax))
+
+
+def fa2_layout(superedges: torch.Tensor, pos: torch.Tensor, iters: int, exact: bool = True, theta: float = 1.2,
+               kr: float = 1.0, kg: float = 1.0, tau: float = 1.0, ks: float = 0.1, ksmax: float = 10.0,
+               attr_w: torch.Tensor | None = None, mass: torch.Tensor | None = None,
+               fprev: torch.Tensor | None = None, speed: torch.Tensor | None = None,
+               ws: torch.Tensor | None = None, stream=None):
+    """ForceAtlas2 iterations; pos (K,2) float32 is updated in place.  Returns
+    (pos, fprev, speed); pass fprev/speed back in to continue a run."""
+    K = pos.shape[0]
+    E = superedges.shape[0]
+    _need(pos, torch.float32, "pos", (K, 2))
+    _need(superedges, torch.int32, "superedges", (E, 2))
+    if attr_w is not None:
+        _need(attr_w, torch.float32, "attr_w", (E,))
+    if mass is not None:
+        _need(mass, torch.float32, "mass", (K,))
+    dev = pos.device
+    if fprev is None:
+        fprev = torch.zeros((K, 2), dtype=torch.float32, device=dev)
+    if speed is None:
+        speed = torch.ones(1, dtype=torch.float32, device=dev)
+    _need(fprev, torch.float32, "fprev", (K, 2))
+    _need(speed, torch.float32, "speed", (1,))
+    p = fa2_params(iters, exact, theta, kr, kg, tau, ks, ksmax)
+    need = L.bgv_fa2_workspace(int(K), int(E), C.byref(p))
+    if need == 0:
+        raise L.BgvError(f"invalid fa2 arguments (K={K}, E={E})")
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, dev)
+    L.check(L.bgv_fa2_layout(int(K), int(E), _ptr(superedges), _ptr(attr_w), _ptr(mass), _ptr(pos), _ptr(fprev),
+                             _ptr(speed), C.byref(p), _ptr(ws), ws.numel(), _stream(stream)), "bgv_fa2_layout")
+    return pos, fprev, speed
+
+
+def fa2_energy(superedges: torch.Tensor, pos: torch.Tensor, kr: float = 1.0, kg: float = 1.0,
+               attr_w: torch.Tensor | None = None, mass: torch.Tensor | None = None, ws=None, stream=None):
+    """ForceAtlas2 energy (device float64 scalar tensor)."""
+    K, E = pos.shape[0], superedges.shape[0]
+    _need(pos, torch.float32, "pos", (K, 2))
+    _need(superedges, torch.int32, "superedges", (E, 2))
+    need = L.bgv_fa2_energy_workspace(int(K), int(E))
+    if need == 0:
+        raise L.BgvError(f"invalid energy arguments (K={K}, E={E})")
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, pos.device)
+    out = torch.empty(1, dtype=torch.float64, device=pos.device)
+    L.check(L.bgv_fa2_energy(int(K), int(E), _ptr(superedges), _ptr(attr_w), _ptr(mass), _ptr(pos), float(kr),
+                             float(kg), _ptr(out), _ptr(ws), ws.numel(), _stream(stream)), "bgv_fa2_energy")
+    return out[0]
+
+
+def fa2_grad(superedges: torch.Tensor, pos: torch.Tensor, kr: float = 1.0, kg: float = 1.0,
+             attr_w: torch.Tensor | None = None, mass: torch.Tensor | None = None,
+             grad_out: torch.Tensor | None = None, ws=None, stream=None):
+    """Gradient of the ForceAtlas2 energy (= -force * grad_out), (K,2) float32."""
+    K, E = pos.shape[0], superedges.shape[0]
+    _need(pos, torch.float32, "pos", (K, 2))
+    _need(superedges, torch.int32, "superedges", (E, 2))
+    if grad_out is not None:
+        _need(grad_out, torch.float32, "grad_out", (1,))
+    need = L.bgv_fa2_energy_workspace(int(K), int(E))
+    if need == 0:
+        raise L.BgvError(f"invalid gradient arguments (K={K}, E={E})")
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, pos.device)
+    g = torch.empty((K, 2), dtype=torch.float32, device=pos.device)
+    L.check(L.bgv_fa2_grad(int(K), int(E), _ptr(superedges), _ptr(attr_w), _ptr(mass), _ptr(pos), float(kr),
+                           float(kg), _ptr(grad_out), _ptr(g), _ptr(ws), ws.numel(), _stream(stream)),
+            "bgv_fa2_grad")
+    return g
+
+
+class FA2Energy(torch.autograd.Function):
+    """Energy of a layout as an autograd function: forward = bgv_fa2_energy, backward =
+    bgv_fa2_grad (the ForceAtlas2 force field, hand-written kernel)."""
+
+    @staticmethod
+    def forward(ctx, pos, superedges, kr=1.0, kg=1.0, attr_w=None, mass=None):
+        pos_c = pos.detach().contiguous()
+        ctx.save_for_backward(pos_c, superedges, attr_w, mass)
+        ctx.kr, ctx.kg = kr, kg
+        return fa2_energy(superedges, pos_c, kr, kg, attr_w, mass).to(torch.float32)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        pos, superedges, attr_w, mass = ctx.saved_tensors
+        go = grad_out.detach().to(torch.float32).reshape(1).contiguous()
+        g = fa2_grad(superedges, pos, ctx.kr, ctx.kg, attr_w, mass, grad_out=go)
+        return g, None, None, None, None, None
+
+
+# ------------------------------------------------------------------ whole path --
+def pipeline(edges: torch.Tensor, n: int, wl: dict, coef1: np.ndarray, coef2: np.ndarray, pos0: torch.Tensor,
+             volume: bool = False, stream=None):
+    """Community passes + supergraph + ForceAtlas2 layout of the supergraph for one
+    workload description ``wl`` (threshold, passes, growth, chunk, rows, cols,
+    fa2_iters, exact, theta, kr, kg, tau, ks, ksmax).  pos0 (>= K rows) seeds the layout."""
+    labels, degree, vol = community(edges, n, wl["threshold"], wl["passes"], wl["growth"], wl["chunk"],
+                                    volume=volume, stream=stream)
+    sg = supergraph(edges, labels, degree, wl["rows"], wl["cols"], coef1, coef2, stream=stream)
+    pos = pos0[: sg["K"]].clone()
+    pos, fprev, speed = fa2_layout(sg["superedges"], pos, wl["fa2_iters"], wl["exact"], wl["theta"], wl["kr"],
+                                   wl["kg"], wl["tau"], wl["ks"], wl["ksmax"], stream=stream)
+    return dict(labels=labels, degree=degree, volume=vol, sg=sg, pos=pos, fprev=fprev, speed=speed)

@@ -1,0 +1,91 @@
+// Internal helpers shared by the HIP translation units of libbgv (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "bgv.h"
+
+namespace bgv {
+
+constexpr int kWave = 64;  // CDNA wavefront width
+
+// Thread-local error message behind bgv_last_error().
+void set_error(const char *fmt, ...);
+void clear_error();
+
+#define BGV_CHECK_HIP(call)                                                              \
+    do {                                                                                 \
+        hipError_t _e = (call);                                                          \
+        if (_e != hipSuccess) {                                                          \
+            ::bgv::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(_e),      \
+                             __FILE__, __LINE__);                                        \
+            return BGV_E_HIP;                                                            \
+        }                                                                                \
+    } while (0)
+
+#define BGV_CHECK_LAUNCH() BGV_CHECK_HIP(hipGetLastError())
+
+#define BGV_TRY(expr)                                                                    \
+    do {                                                                                 \
+        bgv_status _s = (expr);                                                          \
+        if (_s != BGV_OK) return _s;                                                     \
+    } while (0)
+
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// Carves 256-byte-aligned sub-buffers out of a caller workspace.  With base == nullptr
+// it only counts, so the same code computes the workspace size and the layout.
+struct Carver {
+    char *base;
+    size_t off = 0;
+    explicit Carver(void *b) : base(static_cast<char *>(b)) {}
+    template <class T>
+    T *take(size_t count) {
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += align_up(sizeof(T) * (count ? count : 1));
+        return p;
+    }
+    size_t size() const { return off; }
+};
+
+inline bgv_status check_ws(void *ws, size_t have, size_t need) {
+    if (need == 0) return BGV_OK;
+    if (ws == nullptr || have < need || (reinterpret_cast<uintptr_t>(ws) & 255u) != 0) {
+        set_error("workspace: need %zu bytes, 256-byte aligned (got %zu at %p)", need, have, ws);
+        return BGV_E_WORKSPACE;
+    }
+    return BGV_OK;
+}
+
+inline unsigned grid_for(int64_t items, int per_block, unsigned cap = 1u << 20) {
+    int64_t g = (items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return static_cast<unsigned>(g);
+}
+
+// ---------------------------------------------------------------- primitives ----
+// Device-wide fill (a kernel, so it is safe inside captured graphs).
+template <class T>
+bgv_status fill(T *p, T value, int64_t count, hipStream_t s);
+
+// Exclusive prefix sum of `in[0..n)` into `out` (may alias `in`); writes the total
+// to *total (device) if non-null.  Scratch from scan_workspace(n).
+size_t scan_workspace(int64_t n);
+bgv_status exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total,
+                              void *scratch, hipStream_t s);
+template <class T>  // instantiated for uint32_t and double
+bgv_status exclusive_scan(const T *in, T *out, int64_t n, T *total, void *scratch, hipStream_t s);
+
+// Stable LSD radix sort of 64-bit keys on bits [0, nbits), with an optional uint32
+// payload.  keys/alt (and vals/vals_alt) are ping-pong buffers of n entries; the
+// sorted result ends in *keys_out/*vals_out (one of the two).  Scratch from
+// radix_workspace(n).
+size_t radix_workspace(int64_t n);
+bgv_status radix_sort_u64(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, uint32_t *vals_alt,
+                          int64_t n, int nbits, uint64_t **keys_out, uint32_t **vals_out,
+                          void *scratch, hipStream_t s);
+
+}  // namespace bgv

@@ -1,0 +1,274 @@
+// Device-wide primitives written for gfx950: fill, exclusive scan (reduce-then-scan)
+// and a stable LSD radix sort (8-bit digits, per-tile histograms, wave-ballot ranking).
+#include <stdarg.h>
+#include <stdio.h>
+
+#include "common.h"
+
+namespace bgv {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+void clear_error() { g_err[0] = '\0'; }
+const char *last_error() { return g_err; }
+
+// ------------------------------------------------------------------------ fill ---
+template <class T>
+__global__ void k_fill(T *p, T v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+template <class T>
+bgv_status fill(T *p, T value, int64_t count, hipStream_t s) {
+    if (count <= 0) return BGV_OK;
+    hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(count, 256 * 4, 8192)), dim3(256), 0, s, p, value, count);
+    BGV_CHECK_LAUNCH();
+    return BGV_OK;
+}
+template bgv_status fill<int32_t>(int32_t *, int32_t, int64_t, hipStream_t);
+template bgv_status fill<uint32_t>(uint32_t *, uint32_t, int64_t, hipStream_t);
+template bgv_status fill<int64_t>(int64_t *, int64_t, int64_t, hipStream_t);
+template bgv_status fill<uint64_t>(uint64_t *, uint64_t, int64_t, hipStream_t);
+template bgv_status fill<float>(float *, float, int64_t, hipStream_t);
+template bgv_status fill<double>(double *, double, int64_t, hipStream_t);
+
+// ------------------------------------------------------------------------ scan ---
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+template <class T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        T t = __shfl_up(v, o, kWave);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Exclusive block scan of one value per thread; returns the exclusive prefix and
+// the block total in *total.  blockDim.x must be a multiple of 64, <= 1024.  The
+// combination order depends only on the thread index (deterministic for FP types).
+template <class T>
+__device__ __forceinline__ T block_excl_scan(T v, T *total) {
+    __shared__ T wsum[17];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int nw = blockDim.x / kWave;
+    T incl = wave_incl_scan(v);
+    if (lane == kWave - 1) wsum[w] = incl;
+    __syncthreads();
+    if (w == 0) {
+        T x = lane < nw ? wsum[lane] : T(0);
+        T xi = wave_incl_scan(x);
+        if (lane < nw) wsum[lane] = xi - x;
+        if (lane == nw - 1) wsum[16] = xi;
+    }
+    __syncthreads();
+    T res = (incl - v) + wsum[w];
+    *total = wsum[16];
+    __syncthreads();
+    return res;
+}
+
+template <class T>
+__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const T *in, int64_t n, T *part) {
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    T acc = T(0);
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j)
+        if (base + j < n) acc += in[base + j];
+    T tot;
+    block_excl_scan<T>(acc, &tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+template <class T>
+__global__ void __launch_bounds__(1024) k_scan_partials(T *part, int64_t nb, T *total) {
+    const int64_t per = (nb + blockDim.x - 1) / blockDim.x;
+    const int64_t lo = threadIdx.x * per;
+    const int64_t hi = lo + per < nb ? lo + per : nb;
+    T acc = T(0);
+    for (int64_t i = lo; i < hi; ++i) acc += part[i];
+    T tot;
+    T pre = block_excl_scan<T>(acc, &tot);
+    for (int64_t i = lo; i < hi; ++i) {
+        T v = part[i];
+        part[i] = pre;
+        pre += v;
+    }
+    if (threadIdx.x == 0 && total) *total = tot;
+}
+
+template <class T>
+__global__ void __launch_bounds__(kScanThreads) k_scan_down(const T *in, T *out, int64_t n, const T *part) {
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    T v[kScanItems];
+    T acc = T(0);
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        v[j] = (base + j < n) ? in[base + j] : T(0);
+        acc += v[j];
+    }
+    T tot;
+    T pre = block_excl_scan<T>(acc, &tot) + part[blockIdx.x];
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        if (base + j < n) out[base + j] = pre;
+        pre += v[j];
+    }
+}
+
+size_t scan_workspace(int64_t n) {
+    int64_t nb = (n + kScanTile - 1) / kScanTile;
+    return align_up(sizeof(double) * (size_t)(nb > 0 ? nb : 1));
+}
+
+template <class T>
+bgv_status exclusive_scan(const T *in, T *out, int64_t n, T *total, void *scratch, hipStream_t s) {
+    if (n <= 0) {
+        if (total) BGV_TRY(fill<T>(total, T(0), 1, s));
+        return BGV_OK;
+    }
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    T *part = static_cast<T *>(scratch);
+    hipLaunchKernelGGL(k_scan_reduce<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, part);
+    BGV_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_scan_partials<T>, dim3(1), dim3(1024), 0, s, part, nb, total);
+    BGV_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_scan_down<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, out, n, part);
+    BGV_CHECK_LAUNCH();
+    return BGV_OK;
+}
+template bgv_status exclusive_scan<uint32_t>(const uint32_t *, uint32_t *, int64_t, uint32_t *, void *, hipStream_t);
+template bgv_status exclusive_scan<double>(const double *, double *, int64_t, double *, void *, hipStream_t);
+
+bgv_status exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total, void *scratch,
+                              hipStream_t s) {
+    return exclusive_scan<uint32_t>(in, out, n, total, scratch, s);
+}
+
+// ------------------------------------------------------------------ radix sort ---
+constexpr int kRsThreads = 256;
+constexpr int kRsItems = 16;
+constexpr int kRsTile = kRsThreads * kRsItems;
+constexpr int kRsWaves = kRsThreads / kWave;
+
+__global__ void __launch_bounds__(kRsThreads) k_rs_upsweep(const uint64_t *keys, int64_t n, int shift,
+                                                            uint32_t *counts, int64_t nb) {
+    __shared__ uint32_t hist[256];
+    hist[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRsTile;
+#pragma unroll 4
+    for (int j = 0; j < kRsItems; ++j) {
+        int64_t i = base + (int64_t)j * kRsThreads + threadIdx.x;
+        if (i < n) atomicAdd(&hist[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    counts[(int64_t)threadIdx.x * nb + blockIdx.x] = hist[threadIdx.x];
+}
+
+// Stable scatter: the tile is consumed in rounds of 256 consecutive keys; within a
+// round the rank of a key among equal digits is (keys of that digit in earlier waves)
+// + (equal-digit lanes below it in its wave, from 8 ballots).
+__global__ void __launch_bounds__(kRsThreads) k_rs_downsweep(const uint64_t *keys, uint64_t *keys_out,
+                                                              const uint32_t *vals, uint32_t *vals_out,
+                                                              int64_t n, int shift, const uint32_t *offsets,
+                                                              int64_t nb) {
+    __shared__ uint32_t running[256];
+    __shared__ uint32_t wcnt[kRsWaves][256];
+    const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
+    running[t] = offsets[(int64_t)t * nb + blockIdx.x];
+#pragma unroll
+    for (int q = 0; q < kRsWaves; ++q) wcnt[q][t] = 0;
+    __syncthreads();
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t base = (int64_t)blockIdx.x * kRsTile;
+    for (int j = 0; j < kRsItems; ++j) {
+        const int64_t i = base + (int64_t)j * kRsThreads + t;
+        const bool valid = i < n;
+        uint64_t key = valid ? keys[i] : 0ull;
+        uint32_t val = (valid && vals) ? vals[i] : 0u;
+        const uint32_t d = (uint32_t)(key >> shift) & 255u;
+        uint64_t match = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            match &= bit ? bb : ~bb;
+        }
+        const uint32_t rank = __popcll(match & lt_mask);
+        if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(match);
+        __syncthreads();
+        if (valid) {
+            uint32_t pre = running[d] + rank;
+            for (int q = 0; q < w; ++q) pre += wcnt[q][d];
+            keys_out[pre] = key;
+            if (vals) vals_out[pre] = val;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+#pragma unroll
+        for (int q = 0; q < kRsWaves; ++q) {
+            add += wcnt[q][t];
+            wcnt[q][t] = 0;
+        }
+        running[t] += add;
+        __syncthreads();
+    }
+}
+
+size_t radix_workspace(int64_t n) {
+    int64_t nb = (n + kRsTile - 1) / kRsTile;
+    if (nb < 1) nb = 1;
+    return align_up(sizeof(uint32_t) * 256 * (size_t)nb) + scan_workspace(256 * nb);
+}
+
+bgv_status radix_sort_u64(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, uint32_t *vals_alt,
+                          int64_t n, int nbits, uint64_t **keys_out, uint32_t **vals_out,
+                          void *scratch, hipStream_t s) {
+    uint64_t *src = keys, *dst = keys_alt;
+    uint32_t *vsrc = vals, *vdst = vals_alt;
+    if (n > 1) {
+        const int64_t nb = (n + kRsTile - 1) / kRsTile;
+        uint32_t *counts = static_cast<uint32_t *>(scratch);
+        void *scan_scratch = static_cast<char *>(scratch) + align_up(sizeof(uint32_t) * 256 * (size_t)nb);
+        for (int shift = 0; shift < nbits; shift += 8) {
+            hipLaunchKernelGGL(k_rs_upsweep, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, n, shift, counts, nb);
+            BGV_CHECK_LAUNCH();
+            BGV_TRY(exclusive_scan_u32(counts, counts, 256 * nb, nullptr, scan_scratch, s));
+            hipLaunchKernelGGL(k_rs_downsweep, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, dst, vsrc, vdst, n,
+                               shift, counts, nb);
+            BGV_CHECK_LAUNCH();
+            uint64_t *tk = src; src = dst; dst = tk;
+            uint32_t *tv = vsrc; vsrc = vdst; vdst = tv;
+        }
+    }
+    *keys_out = src;
+    if (vals_out) *vals_out = vsrc;
+    return BGV_OK;
+}
+
+}  // namespace bgv
+
+extern "C" const char *bgv_status_string(bgv_status s) {
+    switch (s) {
+        case BGV_OK: return "BGV_OK";
+        case BGV_E_INVALID: return "BGV_E_INVALID";
+        case BGV_E_WORKSPACE: return "BGV_E_WORKSPACE";
+        case BGV_E_HIP: return "BGV_E_HIP";
+        default: return "BGV_E_UNKNOWN";
+    }
+}
+
+extern "C" const char *bgv_last_error(void) { return bgv::last_error(); }

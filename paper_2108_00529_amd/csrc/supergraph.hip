@@ -1,0 +1,295 @@
+// Count-min-sketch supergraph (Section 3.3 / Algorithm 2, Section 4.1, Algorithm 3).
+//   1. flag used labels, exclusive scan -> sid (supernodes numbered by ascending label)
+//   2. sketch 1: every node adds its degree at column h_r(label) of each row
+//   3. sketch 2: every inter-community edge adds 1 at g_r(min label, max label) and
+//      emits its packed (sid_lo, sid_hi) key
+//   4. LSD radix sort of the keys, unique -> superedges; weights = min over rows of
+//      sketch 2; supernode sizes = min over rows of sketch 1
+#include "common.h"
+
+namespace bgv {
+
+constexpr int kSgThreads = 256;
+constexpr int kMaxRows = 8;
+
+struct HashRows {
+    uint64_t a[kMaxRows], b[kMaxRows], c[kMaxRows];
+};
+
+__device__ __forceinline__ uint32_t col_key(uint64_t A, uint64_t B, uint32_t x, uint32_t cols) {
+    const uint64_t t = A * (uint64_t)x + B;
+    return (uint32_t)(((t >> 32) * (uint64_t)cols) >> 32);
+}
+__device__ __forceinline__ uint32_t col_pair(uint64_t A, uint64_t B, uint64_t C, uint32_t lo, uint32_t hi,
+                                             uint32_t cols) {
+    const uint64_t t = A * (uint64_t)lo + C * (uint64_t)hi + B;
+    return (uint32_t)(((t >> 32) * (uint64_t)cols) >> 32);
+}
+
+__global__ void k_sg_flag(const int32_t *__restrict__ labels, int32_t n, uint32_t *__restrict__ flag) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        flag[labels[v]] = 1u;
+}
+
+// flag[] still holds the 0/1 flags; sid[] is its exclusive scan.
+__global__ void k_sg_compact(const uint32_t *__restrict__ flag, const uint32_t *__restrict__ sid, int32_t n,
+                             int32_t *__restrict__ super_label) {
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x)
+        if (flag[c]) super_label[sid[c]] = (int32_t)c;
+}
+
+// Sketch 1, global-memory counters (any width).
+__global__ void k_sg_sketch_nodes(const int32_t *__restrict__ labels, const int32_t *__restrict__ degree,
+                                  int32_t n, HashRows h, int32_t rows, uint32_t cols, uint32_t *__restrict__ M1) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t d = (uint32_t)degree[v];
+        if (d == 0) continue;
+        const uint32_t lab = (uint32_t)labels[v];
+        for (int r = 0; r < rows; ++r) atomicAdd(&M1[(size_t)r * cols + col_key(h.a[r], h.b[r], lab, cols)], d);
+    }
+}
+
+// Sketch 1 with the whole sketch privatised in LDS (rows*cols <= kLdsCounters).
+constexpr int kLdsCounters = 16384;
+__global__ void __launch_bounds__(kSgThreads) k_sg_sketch_nodes_lds(const int32_t *__restrict__ labels,
+                                                                     const int32_t *__restrict__ degree, int32_t n,
+                                                                     HashRows h, int32_t rows, uint32_t cols,
+                                                                     uint32_t *__restrict__ M1) {
+    __shared__ uint32_t loc[kLdsCounters];
+    const int total = rows * (int)cols;
+    for (int i = threadIdx.x; i < total; i += blockDim.x) loc[i] = 0;
+    __syncthreads();
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t d = (uint32_t)degree[v];
+        if (d == 0) continue;
+        const uint32_t lab = (uint32_t)labels[v];
+        for (int r = 0; r < rows; ++r) atomicAdd(&loc[r * cols + col_key(h.a[r], h.b[r], lab, cols)], d);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < total; i += blockDim.x)
+        if (loc[i]) atomicAdd(&M1[i], loc[i]);
+}
+
+__global__ void k_sg_super_size(const int32_t *__restrict__ super_label, const uint32_t *__restrict__ Kp,
+                                HashRows h, int32_t rows, uint32_t cols, const uint32_t *__restrict__ M1,
+                                uint32_t *__restrict__ super_size) {
+    const int64_t K = *Kp;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < K; k += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t lab = (uint32_t)super_label[k];
+        uint32_t best = 0xffffffffu;
+        for (int r = 0; r < rows; ++r) best = min(best, M1[(size_t)r * cols + col_key(h.a[r], h.b[r], lab, cols)]);
+        super_size[k] = best;
+    }
+}
+
+// Sketch 2 + key emission.  Keys are appended through one atomic per wave.
+__global__ void __launch_bounds__(kSgThreads) k_sg_sketch_edges(const int2 *__restrict__ edges, int64_t m,
+                                                                 const int32_t *__restrict__ labels,
+                                                                 const uint32_t *__restrict__ sid, HashRows h,
+                                                                 int32_t rows, uint32_t cols, uint32_t *__restrict__ M2,
+                                                                 int kbits, uint64_t *__restrict__ keys,
+                                                                 unsigned long long *__restrict__ nkeys) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // every lane of a wave runs the same number of iterations (ballots stay uniform)
+    const int64_t first = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~(kWave - 1));
+    for (int64_t i0 = first; i0 < m; i0 += stride) {
+        const int64_t i = i0 + lane;
+        bool inter = false;
+        uint32_t lo = 0, hi = 0;
+        if (i < m) {
+            const int2 e = edges[i];
+            if (e.x != e.y) {
+                const int32_t a = labels[e.x], b = labels[e.y];
+                if (a != b) {
+                    inter = true;
+                    lo = (uint32_t)min(a, b);
+                    hi = (uint32_t)max(a, b);
+                    for (int r = 0; r < rows; ++r)
+                        atomicAdd(&M2[(size_t)r * cols + col_pair(h.a[r], h.b[r], h.c[r], lo, hi, cols)], 1u);
+                }
+            }
+        }
+        const uint64_t mask = __ballot(inter);
+        if (mask == 0) continue;
+        const int leader = __ffsll((unsigned long long)mask) - 1;
+        unsigned long long base = 0;
+        if (lane == leader) base = atomicAdd(nkeys, (unsigned long long)__popcll(mask));
+        base = __shfl(base, leader, kWave);
+        if (inter) {
+            const uint64_t below = lane ? (mask & (~0ull >> (64 - lane))) : 0ull;
+            keys[base + __popcll(below)] = ((uint64_t)sid[lo] << kbits) | (uint64_t)sid[hi];
+        }
+    }
+}
+
+__global__ void k_sg_unique_flag(const uint64_t *__restrict__ keys, int64_t nk, uint32_t *__restrict__ flag) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nk; i += (int64_t)gridDim.x * blockDim.x)
+        flag[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
+}
+
+__global__ void k_sg_unique_write(const uint64_t *__restrict__ keys, int64_t nk, const uint32_t *__restrict__ flag,
+                                  const uint32_t *__restrict__ pos, int kbits, const int32_t *__restrict__ super_label,
+                                  HashRows h, int32_t rows, uint32_t cols, const uint32_t *__restrict__ M2,
+                                  int32_t *__restrict__ superedges, uint32_t *__restrict__ se_weight) {
+    const uint64_t lowmask = (1ull << kbits) - 1ull;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nk; i += (int64_t)gridDim.x * blockDim.x) {
+        if (!flag[i]) continue;
+        const uint64_t k = keys[i];
+        const int32_t sa = (int32_t)(k >> kbits), sb = (int32_t)(k & lowmask);
+        const uint32_t j = pos[i];
+        superedges[2 * (int64_t)j] = sa;
+        superedges[2 * (int64_t)j + 1] = sb;
+        const uint32_t la = (uint32_t)super_label[sa], lb = (uint32_t)super_label[sb];
+        uint32_t best = 0xffffffffu;
+        for (int r = 0; r < rows; ++r)
+            best = min(best, M2[(size_t)r * cols + col_pair(h.a[r], h.b[r], h.c[r], la, lb, cols)]);
+        se_weight[j] = best;
+    }
+}
+
+__global__ void k_sg_node_super(const int32_t *__restrict__ labels, const uint32_t *__restrict__ sid, int32_t n,
+                                int32_t *__restrict__ node_super) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        node_super[v] = (int32_t)sid[labels[v]];
+}
+
+struct SgWs {
+    uint32_t *flag, *sid, *counters, *uflag, *upos;
+    uint64_t *keys, *keys_alt;
+    void *scan_scratch, *sort_scratch;
+};
+
+static size_t sg_layout(Carver &c, int32_t n, int64_t m, SgWs *w) {
+    const int64_t mm = m > 0 ? m : 1;
+    w->flag = c.take<uint32_t>((size_t)n);
+    w->sid = c.take<uint32_t>((size_t)n);
+    w->counters = c.take<uint32_t>(8);  // [0] K, [1] E_S, [2..3] key count (u64, 8-byte aligned)
+    w->keys = c.take<uint64_t>((size_t)mm);
+    w->keys_alt = c.take<uint64_t>((size_t)mm);
+    w->uflag = c.take<uint32_t>((size_t)mm);
+    w->upos = c.take<uint32_t>((size_t)mm);
+    const int64_t big = n > mm ? n : mm;
+    w->scan_scratch = c.take<char>(scan_workspace(big));
+    w->sort_scratch = c.take<char>(radix_workspace(mm));
+    return c.size();
+}
+
+static bool sg_valid(int32_t n, int64_t m, const bgv_sketch_params *s) {
+    return s && n >= 1 && m >= 0 && m <= INT32_MAX && s->rows >= 1 && s->rows <= kMaxRows && s->cols >= 1 &&
+           s->coef1 && s->coef2;
+}
+
+static HashRows make_rows(const uint64_t *coef, int rows) {
+    HashRows h{};
+    for (int r = 0; r < rows; ++r) {
+        h.a[r] = coef[3 * r];
+        h.b[r] = coef[3 * r + 1];
+        h.c[r] = coef[3 * r + 2];
+    }
+    return h;
+}
+
+}  // namespace bgv
+
+using namespace bgv;
+
+extern "C" size_t bgv_supergraph_workspace(int32_t n, int64_t m, const bgv_sketch_params *s) {
+    if (!sg_valid(n, m, s)) return 0;
+    Carver c(nullptr);
+    SgWs w;
+    return sg_layout(c, n, m, &w);
+}
+
+extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges, const int32_t *labels,
+                                     const int32_t *degree, const bgv_sketch_params *sp, int32_t *K_out,
+                                     int64_t *E_out, int32_t *super_label, uint32_t *super_size,
+                                     int32_t *node_super, int32_t *superedges, uint32_t *se_weight, uint32_t *M1,
+                                     uint32_t *M2, void *ws, size_t ws_bytes, bgv_stream_t stream) {
+    clear_error();
+    if (!sg_valid(n, m, sp)) {
+        set_error("bgv_supergraph: invalid arguments (n=%d m=%lld)", n, (long long)m);
+        return BGV_E_INVALID;
+    }
+    if ((m > 0 && (!edges || !superedges || !se_weight)) || !labels || !degree || !K_out || !E_out ||
+        !super_label || !super_size || !M1 || !M2) {
+        set_error("bgv_supergraph: null pointer");
+        return BGV_E_INVALID;
+    }
+    BGV_TRY(check_ws(ws, ws_bytes, bgv_supergraph_workspace(n, m, sp)));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    Carver c(ws);
+    SgWs w;
+    sg_layout(c, n, m, &w);
+    const int rows = sp->rows;
+    const uint32_t cols = (uint32_t)sp->cols;
+    const HashRows h1 = make_rows(sp->coef1, rows), h2 = make_rows(sp->coef2, rows);
+    const int2 *e2 = reinterpret_cast<const int2 *>(edges);
+    const unsigned gn = grid_for(n, kSgThreads, 65536);
+
+    // supernodes
+    BGV_TRY(fill<uint32_t>(w.flag, 0u, n, s));
+    BGV_TRY(fill<uint32_t>(w.counters, 0u, 8, s));
+    hipLaunchKernelGGL(k_sg_flag, dim3(gn), dim3(kSgThreads), 0, s, labels, n, w.flag);
+    BGV_CHECK_LAUNCH();
+    BGV_TRY(exclusive_scan_u32(w.flag, w.sid, n, &w.counters[0], w.scan_scratch, s));
+    hipLaunchKernelGGL(k_sg_compact, dim3(gn), dim3(kSgThreads), 0, s, w.flag, w.sid, n, super_label);
+    BGV_CHECK_LAUNCH();
+
+    // sketch 1 and sizes
+    const int64_t cells = (int64_t)rows * cols;
+    BGV_TRY(fill<uint32_t>(M1, 0u, cells, s));
+    BGV_TRY(fill<uint32_t>(M2, 0u, cells, s));
+    if (cells <= kLdsCounters) {
+        hipLaunchKernelGGL(k_sg_sketch_nodes_lds, dim3(grid_for(n, kSgThreads * 16, 1024)), dim3(kSgThreads), 0, s,
+                           labels, degree, n, h1, rows, cols, M1);
+    } else {
+        hipLaunchKernelGGL(k_sg_sketch_nodes, dim3(gn), dim3(kSgThreads), 0, s, labels, degree, n, h1, rows, cols, M1);
+    }
+    BGV_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_sg_super_size, dim3(gn), dim3(kSgThreads), 0, s, super_label, &w.counters[0], h1, rows, cols,
+                       M1, super_size);
+    BGV_CHECK_LAUNCH();
+    if (node_super) {
+        hipLaunchKernelGGL(k_sg_node_super, dim3(gn), dim3(kSgThreads), 0, s, labels, w.sid, n, node_super);
+        BGV_CHECK_LAUNCH();
+    }
+
+    // K is needed to size the packed superedge keys
+    uint32_t Kh = 0;
+    BGV_CHECK_HIP(hipMemcpyAsync(&Kh, &w.counters[0], sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    BGV_CHECK_HIP(hipStreamSynchronize(s));
+    *K_out = (int32_t)Kh;
+    int kbits = 1;
+    while (kbits < 31 && (1u << kbits) < Kh) ++kbits;
+
+    // sketch 2 + keys
+    unsigned long long *nkeys_d = reinterpret_cast<unsigned long long *>(&w.counters[2]);
+    if (m > 0) {
+        hipLaunchKernelGGL(k_sg_sketch_edges, dim3(grid_for(m, kSgThreads * 4, 16384)), dim3(kSgThreads), 0, s, e2, m,
+                           labels, w.sid, h2, rows, cols, M2, kbits, w.keys, nkeys_d);
+        BGV_CHECK_LAUNCH();
+    }
+    unsigned long long nk = 0;
+    BGV_CHECK_HIP(hipMemcpyAsync(&nk, nkeys_d, sizeof nk, hipMemcpyDeviceToHost, s));
+    BGV_CHECK_HIP(hipStreamSynchronize(s));
+    int64_t E = 0;
+    if (nk > 0) {
+        uint64_t *sorted;
+        BGV_TRY(radix_sort_u64(w.keys, w.keys_alt, nullptr, nullptr, (int64_t)nk, 2 * kbits, &sorted, nullptr,
+                               w.sort_scratch, s));
+        const unsigned gk = grid_for((int64_t)nk, kSgThreads, 65536);
+        hipLaunchKernelGGL(k_sg_unique_flag, dim3(gk), dim3(kSgThreads), 0, s, sorted, (int64_t)nk, w.uflag);
+        BGV_CHECK_LAUNCH();
+        BGV_TRY(exclusive_scan_u32(w.uflag, w.upos, (int64_t)nk, &w.counters[1], w.scan_scratch, s));
+        hipLaunchKernelGGL(k_sg_unique_write, dim3(gk), dim3(kSgThreads), 0, s, sorted, (int64_t)nk, w.uflag, w.upos,
+                           kbits, super_label, h2, rows, cols, M2, superedges, se_weight);
+        BGV_CHECK_LAUNCH();
+        uint32_t Eh = 0;
+        BGV_CHECK_HIP(hipMemcpyAsync(&Eh, &w.counters[1], sizeof Eh, hipMemcpyDeviceToHost, s));
+        BGV_CHECK_HIP(hipStreamSynchronize(s));
+        E = Eh;
+    }
+    *E_out = E;
+    return BGV_OK;
+}

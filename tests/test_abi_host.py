@@ -1,0 +1,98 @@
+"""Host-only checks of the C ABI: the library loads, exports every symbol the header
+declares, answers workspace queries and rejects bad arguments before any HIP call
+(so these run without a GPU)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bgv.h")
+
+L = pytest.importorskip("paper_2108_00529_amd._lib", reason="libbgv.so not built")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bgv_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = _declared()
+    assert len(names) >= 11
+    for name in names:
+        assert hasattr(L.lib, name), name
+    assert sorted(L.EXPORTED) == names
+
+
+def test_status_strings():
+    assert L.bgv_status_string(0) == b"BGV_OK"
+    assert L.bgv_status_string(-1) == b"BGV_E_INVALID"
+    assert L.bgv_status_string(-3) == b"BGV_E_WORKSPACE"
+    assert L.bgv_status_string(-4) == b"BGV_E_HIP"
+
+
+def test_community_validation_and_workspace():
+    p = L.CdParams(16, 1, 2, 0, 256)
+    ws = L.bgv_community_workspace(2000, 10000, C.byref(p))
+    assert ws >= 2000 * 16 + 256 * 4
+    ws2 = L.bgv_community_workspace(2000, 100, C.byref(p))  # chunk clipped to m
+    assert ws2 < ws
+    for bad in [L.CdParams(-1, 1, 2, 0, 1), L.CdParams(1, 0, 2, 0, 1), L.CdParams(1, 1, 0, 0, 1),
+                L.CdParams(1, 1, 2, 0, 0), L.CdParams(1, 1, 2, 7, 1)]:
+        assert L.bgv_community_workspace(10, 10, C.byref(bad)) == 0
+        assert L.bgv_community(10, 10, C.c_void_p(1), C.byref(bad), C.c_void_p(1), C.c_void_p(1), None,
+                               None, 0, None) == -1
+    assert L.bgv_community(0, 10, C.c_void_p(1), C.byref(p), C.c_void_p(1), C.c_void_p(1), None, None, 0, None) == -1
+    assert L.bgv_community(10, -1, C.c_void_p(1), C.byref(p), C.c_void_p(1), C.c_void_p(1), None, None, 0, None) == -1
+    assert L.bgv_community(10, 2**31, C.c_void_p(1), C.byref(p), C.c_void_p(1), C.c_void_p(1), None, None, 0,
+                           None) == -1
+    # null outputs
+    assert L.bgv_community(10, 5, C.c_void_p(1), C.byref(p), None, C.c_void_p(1), None, None, 0, None) == -1
+    # workspace too small / missing / misaligned -> BGV_E_WORKSPACE, before any HIP call
+    need = L.bgv_community_workspace(10, 5, C.byref(p))
+    assert L.bgv_community(10, 5, C.c_void_p(256), C.byref(p), C.c_void_p(256), C.c_void_p(256), None,
+                           None, 0, None) == -3
+    assert L.bgv_community(10, 5, C.c_void_p(256), C.byref(p), C.c_void_p(256), C.c_void_p(256), None,
+                           C.c_void_p(512), need - 1, None) == -3
+    assert L.bgv_community(10, 5, C.c_void_p(256), C.byref(p), C.c_void_p(256), C.c_void_p(256), None,
+                           C.c_void_p(513), need, None) == -3
+    assert b"workspace" in L.bgv_last_error()
+
+
+def test_supergraph_validation():
+    import numpy as np
+    coef = np.zeros((8, 3), np.uint64)
+    cp = coef.ctypes.data_as(C.c_void_p)
+    ok = L.SketchParams(4, 1024, cp, cp)
+    assert L.bgv_supergraph_workspace(100, 1000, C.byref(ok)) > 0
+    for bad in [L.SketchParams(0, 1024, cp, cp), L.SketchParams(9, 1024, cp, cp), L.SketchParams(4, 0, cp, cp),
+                L.SketchParams(4, 16, None, cp), L.SketchParams(4, 16, cp, None)]:
+        assert L.bgv_supergraph_workspace(100, 1000, C.byref(bad)) == 0
+    K, E = L.i32(0), L.i64(0)
+    one = C.c_void_p(256)
+    assert L.bgv_supergraph(100, 1000, one, one, one, C.byref(bad), C.byref(K), C.byref(E), one, one, None, one,
+                            one, one, one, one, 1 << 30, None) == -1
+    assert L.bgv_supergraph(100, 1000, one, one, one, C.byref(ok), C.byref(K), C.byref(E), one, one, None, one,
+                            one, None, one, one, 1 << 30, None) == -1   # M1 required
+
+
+def test_fa2_validation():
+    ok = L.Fa2Params(10, 1, 1.2, 1.0, 1.0, 1.0, 0.1, 10.0)
+    assert L.bgv_fa2_workspace(100, 300, C.byref(ok)) > 0
+    bh = L.Fa2Params(10, 0, 1.2, 1.0, 1.0, 1.0, 0.1, 10.0)
+    assert L.bgv_fa2_workspace(100, 300, C.byref(bh)) > L.bgv_fa2_workspace(100, 300, C.byref(ok))
+    for bad in [L.Fa2Params(-1, 1, 1.2, 1, 1, 1, .1, 10), L.Fa2Params(1, 2, 1.2, 1, 1, 1, .1, 10),
+                L.Fa2Params(1, 0, -1.0, 1, 1, 1, .1, 10), L.Fa2Params(1, 1, 1.2, 1, 1, 0.0, .1, 10),
+                L.Fa2Params(1, 1, 1.2, 1, 1, 1, .1, 0.0)]:
+        assert L.bgv_fa2_workspace(100, 300, C.byref(bad)) == 0
+    one = C.c_void_p(256)
+    assert L.bgv_fa2_workspace(0, 3, C.byref(ok)) == 0
+    assert L.bgv_fa2_layout(0, 3, one, None, None, one, one, one, C.byref(ok), one, 1 << 30, None) == -1
+    assert L.bgv_fa2_layout(10, 3, one, None, None, None, one, one, C.byref(ok), one, 1 << 30, None) == -1
+    assert L.bgv_fa2_energy_workspace(0, 0) == 0
+    assert L.bgv_fa2_energy_workspace(10, 20) > 0
+    assert L.bgv_fa2_energy(0, 0, None, None, None, one, 1.0, 1.0, one, one, 1 << 20, None) == -1
+    assert L.bgv_fa2_grad(10, 0, None, None, None, one, 1.0, 1.0, None, None, one, 1 << 20, None) == -1

@@ -1,0 +1,284 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the same
+seeded inputs.  Integer outputs (labels, degrees, volumes, sketches, supergraph) must
+be bit-exact; FP32 layouts must match the FP64 oracle within
+
+    max_i |p_gpu_i - p_ref_i| <= 1e-4 * max_i |p_ref_i - centroid(p_ref)|
+
+(positions), and forces within 1e-4 of the largest oracle force magnitude."""
+import numpy as np
+import pytest
+import torch
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def bgv():
+    import paper_2108_00529_amd as b
+    return b
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def u32(t):
+    return host(t).view(np.uint32)
+
+
+def pos_err(p, ref):
+    ref = np.asarray(ref, np.float64)
+    scale = np.linalg.norm(ref - ref.mean(0), axis=1).max()
+    return float(np.linalg.norm(np.asarray(p, np.float64) - ref, axis=1).max() / scale)
+
+
+def sketch_coefs(rows, seed):
+    return graphgen.hash_coeffs(rows, seed), graphgen.hash_coeffs(rows, seed ^ 0x9E3779B97F4A7C15)
+
+
+# --------------------------------------------------------------- community -------
+def check_community(bgv, n, e, D, P, f, B):
+    say(f"  community n={n} m={len(e)} D={D} P={P} f={f} B={B}")
+    lab_r, cnt_r = oracle.bs_community(n, e, D, P, f, B)
+    deg_r, vol_r = oracle.degree_volume(lab_r, cnt_r, P)
+    ed = dev(e.reshape(-1, 2).astype(np.int32))
+    lab, deg, vol = bgv.community(ed, n, D, P, f, B, volume=True)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(host(lab), lab_r)
+    np.testing.assert_array_equal(host(deg), deg_r)
+    np.testing.assert_array_equal(host(vol), vol_r)
+    return lab_r, deg_r
+
+
+def test_community_tiny_and_degenerate(bgv):
+    rng = np.random.default_rng(17)
+    check_community(bgv, 1, np.zeros((0, 2), np.int32), 4, 2, 2, 3)            # n = 1, m = 0
+    check_community(bgv, 5, np.zeros((0, 2), np.int32), 4, 1, 2, 1)            # m = 0
+    check_community(bgv, 3, np.array([[1, 1], [2, 2]], np.int32), 4, 2, 2, 1)  # only self-loops
+    for trial in range(40):
+        n = int(rng.integers(1, 60))
+        m = int(rng.integers(1, 400))
+        e = graphgen.random_tiny_graph(rng, n, m)
+        if trial % 4 == 0:
+            loop = rng.random(m) < 0.1
+            e[loop, 1] = e[loop, 0]
+        B = int(rng.choice([1, 2, 3, 5, 17, 64, 1000]))
+        check_community(bgv, n, e, int(rng.integers(0, 20)), int(rng.integers(1, 4)), int(rng.integers(1, 4)), B)
+
+
+@pytest.fixture(scope="module")
+def planted():
+    wl = graphgen.WORKLOADS["planted_2k"]
+    e, blk = graphgen.make_graph("planted_2k")
+    return wl, e, blk
+
+
+def test_community_planted_2k(bgv, planted):
+    wl, e, blk = planted
+    for B in (1, 7, 256, 257, 10**7):
+        check_community(bgv, wl["n"], e, wl["threshold"], wl["passes"], wl["growth"], B)
+    check_community(bgv, wl["n"], e, wl["threshold"], 3, 2, wl["chunk"])
+
+
+def check_supergraph(bgv, n, e, lab, deg, rows, cols, seed):
+    say(f"  supergraph n={n} m={len(e)} rows={rows} cols={cols}")
+    c1, c2 = sketch_coefs(rows, seed)
+    ref = oracle.supergraph(n, e, lab, deg, rows, cols, c1, c2)
+    sg = bgv.supergraph(dev(e), dev(lab), dev(deg), rows, cols, c1, c2)
+    assert sg["K"] == ref["K"]
+    assert sg["E"] == len(ref["superedges"])
+    np.testing.assert_array_equal(host(sg["super_label"]), ref["super_label"])
+    np.testing.assert_array_equal(u32(sg["super_size"]), ref["super_size"])
+    np.testing.assert_array_equal(u32(sg["M1"]), ref["M1"])
+    np.testing.assert_array_equal(u32(sg["M2"]), ref["M2"])
+    np.testing.assert_array_equal(host(sg["superedges"]), ref["superedges"])
+    np.testing.assert_array_equal(u32(sg["se_weight"]), ref["se_weight"])
+    np.testing.assert_array_equal(host(sg["node_super"]), ref["sid_of_label"][lab])
+    return sg, ref
+
+
+def test_supergraph_planted_2k(bgv, planted):
+    wl, e, blk = planted
+    lab, cnt = oracle.bs_community(wl["n"], e, wl["threshold"], wl["passes"], wl["growth"], wl["chunk"])
+    deg, _ = oracle.degree_volume(lab, cnt, wl["passes"])
+    check_supergraph(bgv, wl["n"], e, lab, deg, wl["rows"], wl["cols"], wl["sketch_seed"])       # LDS sketch path
+    check_supergraph(bgv, wl["n"], e, lab, deg, 5, 1 << 16, 77)                                  # global path
+    check_supergraph(bgv, wl["n"], e, lab, deg, 1, 3, 78)                                        # tiny sketch
+    # every node its own community: all edges are inter-community
+    ident = np.arange(wl["n"], dtype=np.int32)
+    check_supergraph(bgv, wl["n"], e, ident, deg, 4, 1024, 79)
+    # one community: no superedges
+    one = np.zeros(wl["n"], np.int32)
+    check_supergraph(bgv, wl["n"], e, one, deg, 4, 1024, 80)
+
+
+def test_supergraph_tiny_random(bgv):
+    rng = np.random.default_rng(5)
+    for trial in range(15):
+        n = int(rng.integers(1, 80))
+        m = int(rng.integers(0, 300))
+        e = graphgen.random_tiny_graph(rng, n, m) if m else np.zeros((0, 2), np.int32)
+        if m and trial % 3 == 0:
+            loop = rng.random(m) < 0.2
+            e[loop, 1] = e[loop, 0]
+        lab, cnt = oracle.bs_community(n, e, 5, 2, 2, 7)
+        deg, _ = oracle.degree_volume(lab, cnt, 2)
+        check_supergraph(bgv, n, e, lab, deg, int(rng.integers(1, 9)), int(rng.integers(1, 5000)), 100 + trial)
+
+
+# ---------------------------------------------------------------- ForceAtlas2 ----
+@pytest.fixture(scope="module")
+def planted_sg(planted):
+    wl, e, blk = planted
+    lab, cnt = oracle.bs_community(wl["n"], e, wl["threshold"], wl["passes"], wl["growth"], wl["chunk"])
+    deg, _ = oracle.degree_volume(lab, cnt, wl["passes"])
+    c1, c2 = sketch_coefs(wl["rows"], wl["sketch_seed"])
+    sg = oracle.supergraph(wl["n"], e, lab, deg, wl["rows"], wl["cols"], c1, c2)
+    pos0 = graphgen.initial_positions(sg["K"], wl["pos_seed"])
+    return wl, sg, pos0
+
+
+def test_fa2_exact_planted_2k(bgv, planted_sg):
+    wl, sg, pos0 = planted_sg
+    se = sg["superedges"]
+    say(f"  fa2 exact K={sg['K']} E={len(se)} iters={wl['fa2_iters']}")
+    ref, _, sp_ref = oracle.fa2_layout(pos0, se, iters=wl["fa2_iters"], exact=True, kr=wl["kr"], kg=wl["kg"])
+    pos = dev(pos0)
+    pos, fprev, speed = bgv.fa2_layout(dev(se), pos, wl["fa2_iters"], exact=True, kr=wl["kr"], kg=wl["kg"])
+    err = pos_err(host(pos), ref)
+    say(f"  fa2 exact position error {err:.3e}, speed gpu {float(speed):.6g} oracle {sp_ref:.6g}")
+    assert err <= TOL
+    assert abs(float(speed) - sp_ref) <= 1e-3 * sp_ref
+
+
+def test_fa2_first_step_and_forces(bgv, planted_sg):
+    """After one iteration fprev holds the forces at pos0 and the speed is tau/2."""
+    wl, sg, pos0 = planted_sg
+    se = sg["superedges"]
+    mass = oracle.fa2_mass(sg["K"], se)
+    F_ref = oracle.fa2_forces(pos0.astype(np.float64), se, mass, kr=1.0, kg=1.0, exact=True)
+    pos, fprev, speed = bgv.fa2_layout(dev(se), dev(pos0), 1, exact=True)
+    F = host(fprev)
+    assert np.abs(F - F_ref).max() <= TOL * np.abs(F_ref).max()
+    assert float(speed) == 0.5
+
+
+def test_fa2_resume_is_exact(bgv, planted_sg):
+    wl, sg, pos0 = planted_sg
+    se = dev(sg["superedges"])
+    p_a, f_a, s_a = bgv.fa2_layout(se, dev(pos0), 60, exact=True)
+    p_b, f_b, s_b = bgv.fa2_layout(se, dev(pos0), 25, exact=True)
+    p_b, f_b, s_b = bgv.fa2_layout(se, p_b, 35, exact=True, fprev=f_b, speed=s_b)
+    assert torch.equal(p_a, p_b) and torch.equal(f_a, f_b) and torch.equal(s_a, s_b)
+
+
+def test_fa2_run_to_run_identical(bgv, planted_sg):
+    wl, sg, pos0 = planted_sg
+    se = dev(sg["superedges"])
+    a = bgv.fa2_layout(se, dev(pos0), 30, exact=True)[0]
+    b = bgv.fa2_layout(se, dev(pos0), 30, exact=True)[0]
+    c = bgv.fa2_layout(se, dev(pos0), 30, exact=False, theta=1.2)[0]
+    d = bgv.fa2_layout(se, dev(pos0), 30, exact=False, theta=1.2)[0]
+    assert torch.equal(a, b) and torch.equal(c, d)
+
+
+def test_fa2_weights_and_masses(bgv, planted_sg):
+    wl, sg, pos0 = planted_sg
+    se = sg["superedges"]
+    rng = np.random.default_rng(3)
+    aw = rng.uniform(0.2, 3.0, len(se))
+    mass = rng.uniform(1.0, 20.0, sg["K"])
+    ref, _, _ = oracle.fa2_layout(pos0, se, mass=mass, aw=aw, iters=50, exact=True, kr=2.0, kg=0.5)
+    pos = bgv.fa2_layout(dev(se), dev(pos0), 50, exact=True, kr=2.0, kg=0.5,
+                         attr_w=dev(aw.astype(np.float32)), mass=dev(mass.astype(np.float32)))[0]
+    # the FP32 copies of weights/masses are what the GPU sees: give the oracle the same
+    ref32, _, _ = oracle.fa2_layout(pos0, se, mass=mass.astype(np.float32), aw=aw.astype(np.float32), iters=50,
+                                    exact=True, kr=2.0, kg=0.5)
+    assert pos_err(host(pos), ref32) <= TOL
+
+
+def test_fa2_tiny_graphs(bgv):
+    """K = 1, no edges, coincident nodes, a node at the origin."""
+    cases = [
+        (np.array([[0.3, -0.2]], np.float32), np.zeros((0, 2), np.int32)),
+        (np.array([[0.0, 0.0], [1.0, 0.0]], np.float32), np.array([[0, 1]], np.int32)),
+        (np.array([[0.5, 0.5], [0.5, 0.5], [-0.3, 0.1]], np.float32), np.array([[0, 2]], np.int32)),
+        (np.array([[0.1, 0.2], [-0.4, 0.3], [0.2, -0.5], [0.7, 0.7]], np.float32), np.zeros((0, 2), np.int32)),
+    ]
+    for pos0, se in cases:
+        for exact in (True, False):
+            say(f"  tiny fa2 K={len(pos0)} E={len(se)} exact={exact}")
+            ref, _, _ = oracle.fa2_layout(pos0, se, iters=20, exact=exact, theta=1.2)
+            pos = bgv.fa2_layout(dev(se), dev(pos0), 20, exact=exact, theta=1.2)[0]
+            p = host(pos)
+            assert np.all(np.isfinite(p))
+            scale = max(1.0, np.abs(ref).max())
+            assert np.abs(p - ref).max() <= TOL * scale
+
+
+# ----------------------------------------------------------------- Barnes-Hut ----
+def bh_force_check(bgv, pos32, se, theta, label):
+    mass = oracle.fa2_mass(len(pos32), se)
+    F_ref = oracle.fa2_forces(pos32.astype(np.float64), se, mass, exact=False, theta=theta)
+    _, fprev, _ = bgv.fa2_layout(dev(se), dev(pos32), 1, exact=False, theta=theta)
+    F = host(fprev).astype(np.float64)
+    err = np.linalg.norm(F - F_ref, axis=1)
+    scale = np.linalg.norm(F_ref, axis=1).max()
+    bad = err > TOL * scale
+    say(f"  BH {label}: K={len(pos32)} max err/scale {err.max() / scale:.3e}, bodies over tol: {int(bad.sum())}")
+    return F, F_ref, bad
+
+
+def test_bh_theta_zero_equals_exact_oracle(bgv):
+    rng = np.random.default_rng(9)
+    K = 3000
+    pos32 = rng.uniform(-5, 5, (K, 2)).astype(np.float32)
+    se = np.array(sorted({(min(a, b), max(a, b)) for a, b in rng.integers(0, K, (6000, 2)).tolist() if a != b}),
+                  np.int32)
+    mass = oracle.fa2_mass(K, se)
+    F_ex = oracle.fa2_forces(pos32.astype(np.float64), se, mass, exact=True)
+    _, fprev, _ = bgv.fa2_layout(dev(se), dev(pos32), 1, exact=False, theta=0.0)
+    assert np.abs(host(fprev) - F_ex).max() <= TOL * np.abs(F_ex).max()
+
+
+def test_bh_one_step_random(bgv):
+    rng = np.random.default_rng(10)
+    K = 5000
+    pos32 = (rng.standard_normal((K, 2)) * np.array([3.0, 1.0])).astype(np.float32)
+    pos32[:20] = pos32[20]  # a multi-body cell
+    se = np.array(sorted({(min(a, b), max(a, b)) for a, b in rng.integers(0, K, (9000, 2)).tolist() if a != b}),
+                  np.int32)
+    F, F_ref, bad = bh_force_check(bgv, pos32, se, 1.2, "random")
+    assert bad.mean() <= 1e-3
+
+
+# ------------------------------------------------------------- full-size LFR -----
+@pytest.fixture(scope="module")
+def lfr():
+    wl = graphgen.WORKLOADS["lfr_1m"]
+    say("  generating lfr_1m ...")
+    e, com = graphgen.make_graph("lfr_1m")
+    return wl, e
+
+
+def test_lfr_1m_community_supergraph_bh(bgv, lfr):
+    wl, e = lfr
+    n = wl["n"]
+    lab, deg = check_community(bgv, n, e, wl["threshold"], wl["passes"], wl["growth"], wl["chunk"])
+    sg, ref = check_supergraph(bgv, n, e, lab, deg, wl["rows"], wl["cols"], wl["sketch_seed"])
+    pos0 = graphgen.initial_positions(ref["K"], wl["pos_seed"])
+    F, F_ref, bad = bh_force_check(bgv, pos0, ref["superedges"], wl["theta"], "lfr_1m supergraph")
+    assert bad.mean() <= 1e-3
