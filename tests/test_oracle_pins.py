@@ -502,3 +502,29 @@ def test_barnes_hut_opening_criterion_by_hand():
     assert np.allclose(Fa[0], approx, rtol=1e-12, atol=0)
     assert np.allclose(Fe[0], exact, rtol=1e-12, atol=0)
     assert not np.allclose(approx, exact, rtol=1e-6, atol=0)
+
+
+def test_fa2_trajectory_amplifies_rounding():
+    """Why layouts are compared step by step: on the 2,000-node planted supergraph a
+    1e-7 relative perturbation of the start positions grows past 1e-3 (normalised
+    layout distance) within 5 FP64 iterations, so no FP32 implementation can track the
+    FP64 trajectory for 200 iterations; each single step, however, is well conditioned."""
+    wl = graphgen.WORKLOADS["planted_2k"]
+    e, _ = graphgen.make_graph("planted_2k")
+    lab, cnt = oracle.bs_community(2000, e, wl["threshold"], 1, 2, wl["chunk"])
+    deg, _ = oracle.degree_volume(lab, cnt, 1)
+    c1 = graphgen.hash_coeffs(4, wl["sketch_seed"])
+    c2 = graphgen.hash_coeffs(4, wl["sketch_seed"] ^ 0x9E3779B97F4A7C15)
+    sg = oracle.supergraph(2000, e, lab, deg, 4, 1024, c1, c2)
+    x0 = graphgen.initial_positions(sg["K"], wl["pos_seed"]).astype(np.float64)
+    x1 = x0 * (1 + 1e-7 * np.random.default_rng(0).standard_normal(x0.shape))
+
+    def dist(p, r):
+        return np.linalg.norm(p - r, axis=1).max() / np.linalg.norm(r - r.mean(0), axis=1).max()
+
+    a1 = oracle.fa2_layout(x0, sg["superedges"], iters=1)[0]
+    b1 = oracle.fa2_layout(x1, sg["superedges"], iters=1)[0]
+    a5 = oracle.fa2_layout(x0, sg["superedges"], iters=5)[0]
+    b5 = oracle.fa2_layout(x1, sg["superedges"], iters=5)[0]
+    assert dist(b1, a1) < 1e-4
+    assert dist(b5, a5) > 1e-3
