@@ -124,6 +124,7 @@ size_t bgv_supergraph_workspace(int32_t n, int64_t m, const bgv_sketch_params *s
  *   node_super   dev int32[n] or NULL   sid of each node's community
  *   superedges   dev int32[cap m][2] (sid_lo, sid_hi), sorted
  *   se_weight    dev uint32[cap m]   sketch-2 estimate of the superedge multiplicity
+ *   se_count     dev uint32[cap m] or NULL   exact multiplicity (number of edges)
  *   M1, M2       dev uint32[rows][cols] the two sketches (required)
  * Synchronises `stream` (K and E_S are returned on the host).
  */
@@ -131,7 +132,7 @@ bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges, const int3
                           const int32_t *degree, const bgv_sketch_params *s,
                           int32_t *K, int64_t *E_S, int32_t *super_label, uint32_t *super_size,
                           int32_t *node_super, int32_t *superedges, uint32_t *se_weight,
-                          uint32_t *M1, uint32_t *M2,
+                          uint32_t *se_count, uint32_t *M1, uint32_t *M2,
                           void *ws, size_t ws_bytes, bgv_stream_t stream);
 
 /* ---------------------------------------------------------------------------- */

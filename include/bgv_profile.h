@@ -1,0 +1,34 @@
+/*
+ * bgv_profile.h -- optional per-kernel timing of libbgv launches.
+ *
+ * When enabled, every kernel launch of the library is bracketed by two HIP events
+ * recorded on the stream the kernel is launched on, so a caller can obtain the
+ * average device duration of each kernel over a region of its own.  Disabled by
+ * default; enabling adds two event records per launch.  Not thread-safe across
+ * concurrent callers of enable/reset.
+ */
+#ifndef BGV_PROFILE_H
+#define BGV_PROFILE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Start (on != 0) or stop recording events around library kernel launches. */
+void bgv_profile_enable(int on);
+/* Forget every recorded launch. */
+void bgv_profile_reset(void);
+/* Number of distinct kernels recorded since the last reset.  Waits for the recorded
+ * events to complete (host synchronisation on them). */
+int bgv_profile_count(void);
+/* Kernel idx in [0, count): its name (static storage until the next reset), number
+ * of launches and summed device time in milliseconds.  Returns 0, or -1 if idx is out
+ * of range. */
+int bgv_profile_get(int idx, const char **name, int64_t *launches, double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BGV_PROFILE_H */

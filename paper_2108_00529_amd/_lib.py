@@ -56,7 +56,7 @@ bgv_community_workspace = _sig("bgv_community_workspace", SZ, [i32, i64, C.POINT
 bgv_community = _sig("bgv_community", i32, [i32, i64, P, C.POINTER(CdParams), P, P, P, P, SZ, P])
 bgv_supergraph_workspace = _sig("bgv_supergraph_workspace", SZ, [i32, i64, C.POINTER(SketchParams)])
 bgv_supergraph = _sig("bgv_supergraph", i32, [i32, i64, P, P, P, C.POINTER(SketchParams), C.POINTER(i32),
-                                              C.POINTER(i64), P, P, P, P, P, P, P, P, SZ, P])
+                                              C.POINTER(i64), P, P, P, P, P, P, P, P, P, SZ, P])
 bgv_fa2_workspace = _sig("bgv_fa2_workspace", SZ, [i32, i64, C.POINTER(Fa2Params)])
 bgv_fa2_layout = _sig("bgv_fa2_layout", i32, [i32, i64, P, P, P, P, P, P, C.POINTER(Fa2Params), P, SZ, P])
 bgv_fa2_energy_workspace = _sig("bgv_fa2_energy_workspace", SZ, [i32, i64])
@@ -65,7 +65,8 @@ bgv_fa2_grad = _sig("bgv_fa2_grad", i32, [i32, i64, P, P, P, P, f32, f32, P, P, 
 
 EXPORTED = ["bgv_status_string", "bgv_last_error", "bgv_community_workspace", "bgv_community",
             "bgv_supergraph_workspace", "bgv_supergraph", "bgv_fa2_workspace", "bgv_fa2_layout",
-            "bgv_fa2_energy_workspace", "bgv_fa2_energy", "bgv_fa2_grad"]
+            "bgv_fa2_energy_workspace", "bgv_fa2_energy", "bgv_fa2_grad",
+            "bgv_profile_enable", "bgv_profile_reset", "bgv_profile_count", "bgv_profile_get"]
 
 
 def check(status: int, what: str) -> None:

@@ -70,11 +70,28 @@ def community(edges: torch.Tensor, n: int, threshold: int, passes: int = 1, grow
     return labels, degree, vol
 
 
+def community_workspace(edges: torch.Tensor, n: int, wl: dict) -> torch.Tensor:
+    """A workspace tensor for community() on this graph and workload."""
+    p = L.CdParams(int(wl["threshold"]), int(wl["passes"]), int(wl["growth"]), 0, int(wl["chunk"]))
+    need = L.bgv_community_workspace(int(n), int(edges.shape[0]), C.byref(p))
+    return _workspace(need, edges.device)
+
+
+def supergraph_workspace(edges: torch.Tensor, n: int, wl: dict) -> torch.Tensor:
+    """A workspace tensor for supergraph() on this graph and workload."""
+    z = np.zeros((int(wl["rows"]), 3), np.uint64)
+    sp = L.SketchParams(int(wl["rows"]), int(wl["cols"]), z.ctypes.data_as(C.c_void_p), z.ctypes.data_as(C.c_void_p))
+    need = L.bgv_supergraph_workspace(int(n), int(edges.shape[0]), C.byref(sp))
+    return _workspace(need, edges.device)
+
+
 # ------------------------------------------------------------------ supergraph --
 def supergraph(edges: torch.Tensor, labels: torch.Tensor, degree: torch.Tensor, rows: int, cols: int,
-               coef1: np.ndarray, coef2: np.ndarray, ws: torch.Tensor | None = None, stream=None):
+               coef1: np.ndarray, coef2: np.ndarray, ws: torch.Tensor | None = None, stream=None,
+               exact_counts: bool = False):
     """Count-min-sketch supergraph.  Synchronises the stream.  Returns a dict with K,
-    super_label, super_size, node_super, superedges (E,2), se_weight, M1, M2."""
+    super_label, super_size, node_super, superedges (E,2), se_weight, se_count (exact
+    multiplicities, if asked for), M1, M2."""
     n = labels.shape[0]
     m = edges.shape[0]
     _need(edges, torch.int32, "edges", (m, 2))
@@ -94,17 +111,20 @@ def supergraph(edges: torch.Tensor, labels: torch.Tensor, degree: torch.Tensor, 
     node_super = torch.empty(n, dtype=torch.int32, device=dev)
     superedges = torch.empty((max(m, 1), 2), dtype=torch.int32, device=dev)
     se_weight = torch.empty(max(m, 1), dtype=torch.int32, device=dev)  # uint32 bits
+    se_count = torch.empty(max(m, 1), dtype=torch.int32, device=dev) if exact_counts else None
     M1 = torch.empty((rows, cols), dtype=torch.int32, device=dev)      # uint32 bits
     M2 = torch.empty((rows, cols), dtype=torch.int32, device=dev)
     K = L.i32(0)
     E = L.i64(0)
     L.check(L.bgv_supergraph(int(n), int(m), _ptr(edges), _ptr(labels), _ptr(degree), C.byref(sp), C.byref(K),
                              C.byref(E), _ptr(super_label), _ptr(super_size), _ptr(node_super), _ptr(superedges),
-                             _ptr(se_weight), _ptr(M1), _ptr(M2), _ptr(ws), ws.numel(), _stream(stream)),
+                             _ptr(se_weight), _ptr(se_count), _ptr(M1), _ptr(M2), _ptr(ws), ws.numel(),
+                             _stream(stream)),
             "bgv_supergraph")
     k, e = K.value, E.value
     return dict(K=k, E=e, super_label=super_label[:k], super_size=super_size[:k], node_super=node_super,
-                superedges=superedges[:e], se_weight=se_weight[:e], M1=M1, M2=M2)
+                superedges=superedges[:e], se_weight=se_weight[:e],
+                se_count=None if se_count is None else se_count[:e], M1=M1, M2=M2)
 
 
 # ----------------------------------------------------------------- ForceAtlas2 --

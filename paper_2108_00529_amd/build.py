@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libbgv.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["primitives.hip", "community.hip", "supergraph.hip", "fa2.hip", "energy.hip"]
+SOURCES = ["primitives.hip", "profile.hip", "community.hip", "supergraph.hip", "fa2.hip", "energy.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -27,6 +27,20 @@ void clear_error();
 
 #define BGV_CHECK_LAUNCH() BGV_CHECK_HIP(hipGetLastError())
 
+// Optional per-kernel event timing (include/bgv_profile.h).
+bool prof_on();
+void *prof_begin(const char *name, hipStream_t s);
+void prof_end(void *token, hipStream_t s);
+
+// Launch + error check; brackets the launch with events when profiling is enabled.
+#define BGV_LAUNCH(kernel, grid, block, shmem, stream, ...)                                \
+    do {                                                                                   \
+        void *_bgv_tok = ::bgv::prof_on() ? ::bgv::prof_begin(#kernel, (stream)) : nullptr; \
+        hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);               \
+        BGV_CHECK_LAUNCH();                                                                \
+        if (_bgv_tok) ::bgv::prof_end(_bgv_tok, (stream));                                 \
+    } while (0)
+
 #define BGV_TRY(expr)                                                                    \
     do {                                                                                 \
         bgv_status _s = (expr);                                                          \

@@ -149,8 +149,7 @@ extern "C" bgv_status bgv_community(int32_t n, int64_t m, const int32_t *edges, 
     cd_layout(c, n, m, p, &st, &prop);
     const int2 *e2 = reinterpret_cast<const int2 *>(edges);
 
-    hipLaunchKernelGGL(k_cd_init, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, st, n);
-    BGV_CHECK_LAUNCH();
+    BGV_LAUNCH(k_cd_init, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, st, n);
     if (volume) BGV_TRY(fill<int64_t>(volume, 0, n, s));
 
     const int64_t B = p->chunk;
@@ -161,23 +160,19 @@ extern "C" bgv_status bgv_community(int32_t n, int64_t m, const int32_t *edges, 
         for (int64_t k = 0; k < nchunk; ++k) {
             const int64_t cs = k * B, ce = (cs + B < m) ? cs + B : m;
             const int64_t work = (pe - ps) > (ce - cs) ? (pe - ps) : (ce - cs);
-            hipLaunchKernelGGL(k_cd_apply_hist, dim3(grid_for(work, kCdThreads * 4, 16384)), dim3(kCdThreads), 0, s,
+            BGV_LAUNCH(k_cd_apply_hist, dim3(grid_for(work, kCdThreads * 4, 16384)), dim3(kCdThreads), 0, s,
                                st, e2, prop, ps, pe, cs, ce);
-            BGV_CHECK_LAUNCH();
-            hipLaunchKernelGGL(k_cd_decide, dim3(grid_for(ce - cs, kCdThreads * 4, 16384)), dim3(kCdThreads), 0, s,
+            BGV_LAUNCH(k_cd_decide, dim3(grid_for(ce - cs, kCdThreads * 4, 16384)), dim3(kCdThreads), 0, s,
                                st, e2, prop, cs, ce, D);
-            BGV_CHECK_LAUNCH();
             ps = cs;
             pe = ce;
         }
     }
     if (pe > ps) {
-        hipLaunchKernelGGL(k_cd_apply_hist, dim3(grid_for(pe - ps, kCdThreads * 4, 16384)), dim3(kCdThreads), 0, s,
+        BGV_LAUNCH(k_cd_apply_hist, dim3(grid_for(pe - ps, kCdThreads * 4, 16384)), dim3(kCdThreads), 0, s,
                            st, e2, prop, ps, pe, (int64_t)0, (int64_t)0);
-        BGV_CHECK_LAUNCH();
     }
-    hipLaunchKernelGGL(k_cd_finish, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, st, n, p->passes,
+    BGV_LAUNCH(k_cd_finish, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, st, n, p->passes,
                        labels, degree, reinterpret_cast<unsigned long long *>(volume));
-    BGV_CHECK_LAUNCH();
     return BGV_OK;
 }

@@ -250,17 +250,13 @@ extern "C" bgv_status bgv_fa2_energy(int32_t K, int64_t E, const int32_t *edges,
     if (!m) BGV_TRY(build_csr(K, E, edges, attr_w, nullptr, w.csr, s, &m));
     const float2 *x = reinterpret_cast<const float2 *>(pos);
     const int64_t ntri = en_tri_blocks(K);
-    hipLaunchKernelGGL(k_energy_pairs, dim3((unsigned)ntri), dim3(kEnThreads), 0, s, K, en_tiles(K), x, m, w.prep);
-    BGV_CHECK_LAUNCH();
+    BGV_LAUNCH(k_energy_pairs, dim3((unsigned)ntri), dim3(kEnThreads), 0, s, K, en_tiles(K), x, m, w.prep);
     const int ne = en_edge_blocks(E), ng = en_grav_blocks(K);
-    hipLaunchKernelGGL(k_energy_edges, dim3(ne), dim3(kEnThreads), 0, s, E, reinterpret_cast<const int2 *>(edges),
+    BGV_LAUNCH(k_energy_edges, dim3(ne), dim3(kEnThreads), 0, s, E, reinterpret_cast<const int2 *>(edges),
                        attr_w, x, w.patt);
-    BGV_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_energy_grav, dim3(ng), dim3(kEnThreads), 0, s, K, x, m, w.pgrav);
-    BGV_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kEnThreads), 0, s, w.prep, (int)ntri, w.patt, ne, w.pgrav, ng,
+    BGV_LAUNCH(k_energy_grav, dim3(ng), dim3(kEnThreads), 0, s, K, x, m, w.pgrav);
+    BGV_LAUNCH(k_energy_final, dim3(1), dim3(kEnThreads), 0, s, w.prep, (int)ntri, w.patt, ne, w.pgrav, ng,
                        kr, kg, energy);
-    BGV_CHECK_LAUNCH();
     return BGV_OK;
 }
 
@@ -282,10 +278,8 @@ extern "C" bgv_status bgv_fa2_grad(int32_t K, int64_t E, const int32_t *edges, c
     const float2 *x = reinterpret_cast<const float2 *>(pos);
     const int T = en_tiles(K), ns = en_splits(K);
     const int per = (T + ns - 1) / ns;
-    hipLaunchKernelGGL(k_grad_rep, dim3(T, ns), dim3(kEnThreads), 0, s, K, per, x, m, w.gsplit);
-    BGV_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_grad_final, dim3(grid_for(K, kEnThreads, 65536)), dim3(kEnThreads), 0, s, K, ns, w.gsplit, x,
+    BGV_LAUNCH(k_grad_rep, dim3(T, ns), dim3(kEnThreads), 0, s, K, per, x, m, w.gsplit);
+    BGV_LAUNCH(k_grad_final, dim3(grid_for(K, kEnThreads, 65536)), dim3(kEnThreads), 0, s, K, ns, w.gsplit, x,
                        m, w.csr.row, w.csr.col, w.csr.wt, kr, kg, grad_out, reinterpret_cast<float2 *>(grad));
-    BGV_CHECK_LAUNCH();
     return BGV_OK;
 }

@@ -12,6 +12,7 @@
 //   both:   k_update        global speed from the partials (every block reduces them in
 //                           the same order), local speeds, displacement
 // No floating-point atomics anywhere: results are identical run to run.
+#include "block_scan.h"
 #include "common.h"
 #include "fa2_internal.h"
 
@@ -79,22 +80,19 @@ bgv_status build_csr(int32_t K, int64_t E, const int32_t *edges, const float *at
         BGV_TRY(fill<uint32_t>(w.row, 0u, (int64_t)K + 1, s));
     } else {
         const int kb = bits_for(K);
-        hipLaunchKernelGGL(k_csr_keys, dim3(grid_for(E, kFaThreads, 65536)), dim3(kFaThreads), 0, s,
+        BGV_LAUNCH(k_csr_keys, dim3(grid_for(E, kFaThreads, 65536)), dim3(kFaThreads), 0, s,
                            reinterpret_cast<const int2 *>(edges), E, kb, w.keys, w.vals);
-        BGV_CHECK_LAUNCH();
         uint64_t *sk;
         uint32_t *sv;
         BGV_TRY(radix_sort_u64(w.keys, w.keys_alt, w.vals, w.vals_alt, 2 * E, 2 * kb, &sk, &sv, w.sort_scratch, s));
-        hipLaunchKernelGGL(k_csr_fill, dim3(grid_for(2 * E, kFaThreads, 65536)), dim3(kFaThreads), 0, s, sk, sv,
+        BGV_LAUNCH(k_csr_fill, dim3(grid_for(2 * E, kFaThreads, 65536)), dim3(kFaThreads), 0, s, sk, sv,
                            2 * E, kb, K, attr_w, w.row, w.col, w.wt);
-        BGV_CHECK_LAUNCH();
     }
     if (mass_in) {
         *mass_out = mass_in;
     } else {
-        hipLaunchKernelGGL(k_csr_mass, dim3(grid_for(K, kFaThreads, 65536)), dim3(kFaThreads), 0, s, w.row, K,
+        BGV_LAUNCH(k_csr_mass, dim3(grid_for(K, kFaThreads, 65536)), dim3(kFaThreads), 0, s, w.row, K,
                            w.mass);
-        BGV_CHECK_LAUNCH();
         *mass_out = w.mass;
     }
     return BGV_OK;
@@ -122,20 +120,38 @@ __device__ __forceinline__ double2 block_sum2(double2 v) {
     return r;  // valid in thread 0
 }
 
-// Attraction along CSR row i, gravity, then the swing/traction terms of node i.
-__device__ __forceinline__ float2 attract_gravity(int32_t i, float2 xi, float mi, float2 frep,
-                                                  const uint32_t *__restrict__ row, const int32_t *__restrict__ col,
-                                                  const float *__restrict__ wt, const float2 *__restrict__ pos,
-                                                  float kg) {
-    float ax = 0.f, ay = 0.f;
-    const uint32_t r0 = row[i], r1 = row[i + 1];
-    for (uint32_t k = r0; k < r1; ++k) {
-        const float2 xj = pos[col[k]];
-        const float a = wt[k];
-        ax += a * (xj.x - xi.x);
-        ay += a * (xj.y - xi.y);
+// Attraction: one wavefront per node; lanes stride over the CSR row and the partial
+// sums are combined by a fixed butterfly, so the result does not depend on timing.
+// Power-law supernode degrees (rows of thousands of entries next to rows of a few)
+// are why a row is not given to a single thread.
+__global__ void __launch_bounds__(kFaThreads) k_attract(int32_t K, const float2 *__restrict__ pos,
+                                                         const uint32_t *__restrict__ row,
+                                                         const int32_t *__restrict__ col,
+                                                         const float *__restrict__ wt, float2 *__restrict__ A) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t nw = (int64_t)gridDim.x * (kFaThreads / kWave);
+    for (int64_t i = (blockIdx.x * (int64_t)kFaThreads + threadIdx.x) / kWave; i < K; i += nw) {
+        const float2 xi = pos[i];
+        float ax = 0.f, ay = 0.f;
+        const uint32_t r1 = row[i + 1];
+        for (uint32_t k = row[i] + lane; k < r1; k += kWave) {
+            const float2 xj = pos[col[k]];
+            const float a = wt[k];
+            ax += a * (xj.x - xi.x);
+            ay += a * (xj.y - xi.y);
+        }
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+            ax += __shfl_xor(ax, o, kWave);
+            ay += __shfl_xor(ay, o, kWave);
+        }
+        if (lane == 0) A[i] = make_float2(ax, ay);
     }
-    float fx = frep.x + ax, fy = frep.y + ay;
+}
+
+// Repulsion + precomputed attraction + gravity of node i.
+__device__ __forceinline__ float2 attract_gravity(float2 xi, float mi, float2 frep, float2 att, float kg) {
+    float fx = frep.x + att.x, fy = frep.y + att.y;
     const float r = sqrtf(xi.x * xi.x + xi.y * xi.y);
     if (r > 0.f) {
         const float g = kg * mi / r;
@@ -156,9 +172,7 @@ __device__ __forceinline__ double2 swing_traction(float2 F, float2 Fp, float mi)
 // ------------------------------------------------------------------ exact ------
 __global__ void __launch_bounds__(kFaThreads) k_force_exact(int32_t K, const float2 *__restrict__ pos,
                                                              const float *__restrict__ mass,
-                                                             const uint32_t *__restrict__ row,
-                                                             const int32_t *__restrict__ col,
-                                                             const float *__restrict__ wt, float kr, float kg,
+                                                             const float2 *__restrict__ att, float kr, float kg,
                                                              const float2 *__restrict__ fprev, float2 *__restrict__ F,
                                                              double2 *__restrict__ part) {
     __shared__ float4 tile[kFaThreads];
@@ -190,7 +204,7 @@ __global__ void __launch_bounds__(kFaThreads) k_force_exact(int32_t K, const flo
     double2 st = make_double2(0.0, 0.0);
     if (live) {
         const float c = kr * mi;
-        const float2 f = attract_gravity(i, xi, mi, make_float2(c * fx, c * fy), row, col, wt, pos, kg);
+        const float2 f = attract_gravity(xi, mi, make_float2(c * fx, c * fy), att[i], kg);
         F[i] = f;
         st = swing_traction(f, fprev[i], mi);
     }
@@ -199,12 +213,45 @@ __global__ void __launch_bounds__(kFaThreads) k_force_exact(int32_t K, const flo
 }
 
 // ----------------------------------------------------------------- update ------
+// Bounding box (xmin, xmax, ymin, ymax) of the block's points; result in every thread.
+// min/max are order-independent, so any reduction order gives the same box.
+__device__ __forceinline__ float4 block_bbox(float4 b) {
+    __shared__ float4 ws[kFaThreads / kWave];
+    __shared__ float4 res;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        b.x = fminf(b.x, __shfl_down(b.x, o, kWave));
+        b.y = fmaxf(b.y, __shfl_down(b.y, o, kWave));
+        b.z = fminf(b.z, __shfl_down(b.z, o, kWave));
+        b.w = fmaxf(b.w, __shfl_down(b.w, o, kWave));
+    }
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    if (lane == 0) ws[w] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float4 r = ws[0];
+        for (int q = 1; q < kFaThreads / kWave; ++q) {
+            r.x = fminf(r.x, ws[q].x);
+            r.y = fmaxf(r.y, ws[q].y);
+            r.z = fminf(r.z, ws[q].z);
+            r.w = fmaxf(r.w, ws[q].w);
+        }
+        res = r;
+    }
+    __syncthreads();
+    return res;
+}
+
+constexpr float kInf = __builtin_huge_valf();
+
+// Global speed, local speeds, displacement.  With bbox_part != nullptr each block also
+// writes the bounding box of the positions it just moved (for the next tree build).
 __global__ void __launch_bounds__(kFaThreads) k_update(int32_t K, float2 *__restrict__ pos,
                                                         float2 *__restrict__ fprev, const float2 *__restrict__ F,
                                                         const double2 *__restrict__ part, int32_t nparts,
                                                         const float *__restrict__ speed_in,
                                                         float *__restrict__ speed_out, float tau, float ks,
-                                                        float ksmax) {
+                                                        float ksmax, float4 *__restrict__ bbox_part) {
     __shared__ float s_speed;
     double2 acc = make_double2(0.0, 0.0);
     for (int p = threadIdx.x; p < nparts; p += kFaThreads) {
@@ -221,6 +268,7 @@ __global__ void __launch_bounds__(kFaThreads) k_update(int32_t K, float2 *__rest
     }
     __syncthreads();
     const float s = s_speed;
+    float4 bb = make_float4(kInf, -kInf, kInf, -kInf);
     for (int32_t i = blockIdx.x * kFaThreads + threadIdx.x; i < K; i += gridDim.x * kFaThreads) {
         const float2 f = F[i], fp = fprev[i];
         const float sx = f.x - fp.x, sy = f.y - fp.y;
@@ -233,45 +281,27 @@ __global__ void __launch_bounds__(kFaThreads) k_update(int32_t K, float2 *__rest
         p.y += si * f.y;
         pos[i] = p;
         fprev[i] = f;
+        bb = make_float4(fminf(bb.x, p.x), fmaxf(bb.y, p.x), fminf(bb.z, p.y), fmaxf(bb.w, p.y));
+    }
+    if (bbox_part) {
+        bb = block_bbox(bb);
+        if (threadIdx.x == 0) bbox_part[blockIdx.x] = bb;
     }
 }
 
 __global__ void k_copy_f32(const float *__restrict__ a, float *__restrict__ b) { *b = *a; }
 
 // ------------------------------------------------------------------ Barnes-Hut --
-constexpr int kBboxBlocks = 64;
-
+// One bounding-box partial per block of kFaThreads positions (same grid as k_update).
 __global__ void __launch_bounds__(kFaThreads) k_bh_bbox(int32_t K, const float2 *__restrict__ pos,
                                                          float4 *__restrict__ part) {
-    float xmn = INFINITY, xmx = -INFINITY, ymn = INFINITY, ymx = -INFINITY;
+    float4 bb = make_float4(kInf, -kInf, kInf, -kInf);
     for (int32_t i = blockIdx.x * kFaThreads + threadIdx.x; i < K; i += gridDim.x * kFaThreads) {
         const float2 p = pos[i];
-        xmn = fminf(xmn, p.x);
-        xmx = fmaxf(xmx, p.x);
-        ymn = fminf(ymn, p.y);
-        ymx = fmaxf(ymx, p.y);
+        bb = make_float4(fminf(bb.x, p.x), fmaxf(bb.y, p.x), fminf(bb.z, p.y), fmaxf(bb.w, p.y));
     }
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) {
-        xmn = fminf(xmn, __shfl_down(xmn, o, kWave));
-        xmx = fmaxf(xmx, __shfl_down(xmx, o, kWave));
-        ymn = fminf(ymn, __shfl_down(ymn, o, kWave));
-        ymx = fmaxf(ymx, __shfl_down(ymx, o, kWave));
-    }
-    __shared__ float4 ws[kFaThreads / kWave];
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    if (lane == 0) ws[w] = make_float4(xmn, xmx, ymn, ymx);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        float4 r = ws[0];
-        for (int q = 1; q < kFaThreads / kWave; ++q) {
-            r.x = fminf(r.x, ws[q].x);
-            r.y = fmaxf(r.y, ws[q].y);
-            r.z = fminf(r.z, ws[q].z);
-            r.w = fmaxf(r.w, ws[q].w);
-        }
-        part[blockIdx.x] = r;
-    }
+    bb = block_bbox(bb);
+    if (threadIdx.x == 0) part[blockIdx.x] = bb;
 }
 
 __device__ __forceinline__ uint32_t spread16(uint32_t v) {
@@ -288,18 +318,12 @@ __global__ void __launch_bounds__(kFaThreads) k_bh_codes(int32_t K, const float2
                                                           const float4 *__restrict__ part, int nparts,
                                                           uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
                                                           float *__restrict__ s0_out) {
-    __shared__ float4 bb;
-    if (threadIdx.x == 0) {
-        float4 r = part[0];
-        for (int q = 1; q < nparts; ++q) {
-            r.x = fminf(r.x, part[q].x);
-            r.y = fmaxf(r.y, part[q].y);
-            r.z = fminf(r.z, part[q].z);
-            r.w = fmaxf(r.w, part[q].w);
-        }
-        bb = r;
+    float4 bb = make_float4(kInf, -kInf, kInf, -kInf);
+    for (int q = threadIdx.x; q < nparts; q += kFaThreads) {
+        const float4 r = part[q];
+        bb = make_float4(fminf(bb.x, r.x), fmaxf(bb.y, r.y), fminf(bb.z, r.z), fmaxf(bb.w, r.w));
     }
-    __syncthreads();
+    bb = block_bbox(bb);
     const float xmin = bb.x, ymin = bb.z;
     const float ex = bb.y - bb.x, ey = bb.w - bb.z;
     float s0 = ex > ey ? ex : ey;
@@ -315,6 +339,51 @@ __global__ void __launch_bounds__(kFaThreads) k_bh_codes(int32_t K, const float2
         qy = qy > 65535 ? 65535 : qy;
         keys[i] = (uint64_t)(spread16((uint32_t)qx) | (spread16((uint32_t)qy) << 1));
         vals[i] = (uint32_t)i;
+    }
+}
+
+// Up to kGsMaxK bodies: one workgroup gathers the bodies in Morton order and writes the
+// exclusive FP64 prefix sums of m, m*x, m*y (one launch instead of a gather and three
+// device-wide scans).  Each thread owns a contiguous run of bodies.
+constexpr int kGsThreads = 1024;
+constexpr int32_t kGsMaxK = 1 << 18;
+__global__ void __launch_bounds__(kGsThreads) k_bh_gather_scan(int32_t K, const float2 *__restrict__ pos,
+                                                                const float *__restrict__ mass,
+                                                                const uint64_t *__restrict__ skeys,
+                                                                const uint32_t *__restrict__ order,
+                                                                float4 *__restrict__ body,
+                                                                uint32_t *__restrict__ code, double *__restrict__ PM,
+                                                                double *__restrict__ PX, double *__restrict__ PY) {
+    const int32_t per = (K + kGsThreads - 1) / kGsThreads;
+    const int32_t lo = min(K, (int32_t)threadIdx.x * per), hi = min(K, lo + per);
+    double sm = 0.0, sx = 0.0, sy = 0.0;
+    for (int32_t k = lo; k < hi; ++k) {
+        const uint32_t b = order[k];
+        const float2 p = pos[b];
+        const float m = mass[b];
+        body[k] = make_float4(p.x, p.y, m, __int_as_float((int)b));
+        code[k] = (uint32_t)skeys[k];
+        sm += (double)m;
+        sx += (double)m * (double)p.x;
+        sy += (double)m * (double)p.y;
+    }
+    double tm, tx, ty;
+    double pm = block_excl_scan<double>(sm, &tm);
+    double px = block_excl_scan<double>(sx, &tx);
+    double py = block_excl_scan<double>(sy, &ty);
+    for (int32_t k = lo; k < hi; ++k) {
+        const float4 bd = body[k];
+        PM[k] = pm;
+        PX[k] = px;
+        PY[k] = py;
+        pm += (double)bd.z;
+        px += (double)bd.z * (double)bd.x;
+        py += (double)bd.z * (double)bd.y;
+    }
+    if (threadIdx.x == 0) {
+        PM[K] = tm;
+        PX[K] = tx;
+        PY[K] = ty;
     }
 }
 
@@ -401,10 +470,7 @@ __device__ __forceinline__ void add_pair(float2 xi, float4 bj, float &fx, float 
 __global__ void __launch_bounds__(kFaThreads) k_bh_force(int32_t K, const float4 *__restrict__ body,
                                                           const float4 *__restrict__ nodeA,
                                                           const int4 *__restrict__ nodeB, float theta2,
-                                                          const float2 *__restrict__ pos,
-                                                          const uint32_t *__restrict__ row,
-                                                          const int32_t *__restrict__ col,
-                                                          const float *__restrict__ wt, float kr, float kg,
+                                                          const float2 *__restrict__ att, float kr, float kg,
                                                           const float2 *__restrict__ fprev, float2 *__restrict__ F,
                                                           double2 *__restrict__ part, int *__restrict__ overflow) {
     __shared__ int stack[kStackDepth][kFaThreads];
@@ -462,7 +528,7 @@ __global__ void __launch_bounds__(kFaThreads) k_bh_force(int32_t K, const float4
             }
         }
         const float c = kr * mi;
-        const float2 f = attract_gravity(b, xi, mi, make_float2(c * fx, c * fy), row, col, wt, pos, kg);
+        const float2 f = attract_gravity(xi, mi, make_float2(c * fx, c * fy), att[b], kg);
         F[b] = f;
         st = swing_traction(f, fprev[b], mi);
     }
@@ -486,7 +552,7 @@ struct BhWs {
 
 struct FaWs {
     CsrWs csr;
-    float2 *F;
+    float2 *F, *A;
     double2 *part;
     float *speed;  // [2] ping-pong
     BhWs bh;
@@ -496,11 +562,12 @@ static size_t fa_layout(Carver &c, int32_t K, int64_t E, const bgv_fa2_params *p
     csr_layout(c, K, E, &w->csr);
     const int64_t nb = (K + kFaThreads - 1) / kFaThreads;
     w->F = c.take<float2>((size_t)K);
+    w->A = c.take<float2>((size_t)K);
     w->part = c.take<double2>((size_t)nb);
     w->speed = c.take<float>(2);
     if (!p->exact) {
         BhWs &b = w->bh;
-        b.bbox = c.take<float4>(kBboxBlocks);
+        b.bbox = c.take<float4>((size_t)nb);
         b.s0 = c.take<float>(1);
         b.keys = c.take<uint64_t>((size_t)K);
         b.keys_alt = c.take<uint64_t>((size_t)K);
@@ -533,29 +600,29 @@ static bgv_status bh_forces(int32_t K, const float2 *pos, const float *mass, con
                             float kg, const float2 *fprev, FaWs &w, hipStream_t s) {
     BhWs &b = w.bh;
     const unsigned nb = (unsigned)((K + kFaThreads - 1) / kFaThreads);
-    const int nbb = (int)grid_for(K, kFaThreads, kBboxBlocks);
-    hipLaunchKernelGGL(k_bh_bbox, dim3(nbb), dim3(kFaThreads), 0, s, K, pos, b.bbox);
-    BGV_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_bh_codes, dim3(grid_for(K, kFaThreads, 4096)), dim3(kFaThreads), 0, s, K, pos, b.bbox, nbb,
-                       b.keys, b.vals, b.s0);
-    BGV_CHECK_LAUNCH();
+    // b.bbox holds one box per block of positions (written by k_bh_bbox before the first
+    // iteration and by k_update after each one)
+    BGV_LAUNCH(k_bh_codes, dim3(grid_for(K, kFaThreads, 4096)), dim3(kFaThreads), 0, s, K, pos, b.bbox, (int)nb,
+               b.keys, b.vals, b.s0);
     uint64_t *sk;
     uint32_t *sv;
     BGV_TRY(radix_sort_u64(b.keys, b.keys_alt, b.vals, b.vals_alt, K, 32, &sk, &sv, b.sort_scratch, s));
-    hipLaunchKernelGGL(k_bh_gather, dim3(nb), dim3(kFaThreads), 0, s, K, pos, mass, sk, sv, b.body, b.code, b.dm,
-                       b.dmx, b.dmy);
-    BGV_CHECK_LAUNCH();
-    BGV_TRY(exclusive_scan<double>(b.dm, b.PM, K, b.PM + K, b.scan_scratch, s));
-    BGV_TRY(exclusive_scan<double>(b.dmx, b.PX, K, b.PX + K, b.scan_scratch, s));
-    BGV_TRY(exclusive_scan<double>(b.dmy, b.PY, K, b.PY + K, b.scan_scratch, s));
-    if (K > 1) {
-        hipLaunchKernelGGL(k_bh_build, dim3(grid_for(K - 1, kFaThreads, 65536)), dim3(kFaThreads), 0, s, K, b.code,
-                           b.PM, b.PX, b.PY, b.s0, b.nodeA, b.nodeB);
-        BGV_CHECK_LAUNCH();
+    if (K <= kGsMaxK) {
+        BGV_LAUNCH(k_bh_gather_scan, dim3(1), dim3(kGsThreads), 0, s, K, pos, mass, sk, sv, b.body, b.code, b.PM,
+                   b.PX, b.PY);
+    } else {
+        BGV_LAUNCH(k_bh_gather, dim3(nb), dim3(kFaThreads), 0, s, K, pos, mass, sk, sv, b.body, b.code, b.dm, b.dmx,
+                   b.dmy);
+        BGV_TRY(exclusive_scan<double>(b.dm, b.PM, K, b.PM + K, b.scan_scratch, s));
+        BGV_TRY(exclusive_scan<double>(b.dmx, b.PX, K, b.PX + K, b.scan_scratch, s));
+        BGV_TRY(exclusive_scan<double>(b.dmy, b.PY, K, b.PY + K, b.scan_scratch, s));
     }
-    hipLaunchKernelGGL(k_bh_force, dim3(nb), dim3(kFaThreads), 0, s, K, b.body, b.nodeA, b.nodeB, theta * theta, pos,
-                       csr.row, csr.col, csr.wt, kr, kg, fprev, w.F, w.part, b.overflow);
-    BGV_CHECK_LAUNCH();
+    if (K > 1) {
+        BGV_LAUNCH(k_bh_build, dim3(grid_for(K - 1, kFaThreads, 65536)), dim3(kFaThreads), 0, s, K, b.code,
+                           b.PM, b.PX, b.PY, b.s0, b.nodeA, b.nodeB);
+    }
+    BGV_LAUNCH(k_bh_force, dim3(nb), dim3(kFaThreads), 0, s, K, b.body, b.nodeA, b.nodeB, theta * theta, w.A, kr,
+               kg, fprev, w.F, w.part, b.overflow);
     return BGV_OK;
 }
 
@@ -594,21 +661,21 @@ extern "C" bgv_status bgv_fa2_layout(int32_t K, int64_t E, const int32_t *edges,
     float2 *x = reinterpret_cast<float2 *>(pos);
     float2 *fp = reinterpret_cast<float2 *>(fprev);
     const int32_t nb = (K + kFaThreads - 1) / kFaThreads;
-    hipLaunchKernelGGL(k_copy_f32, dim3(1), dim3(1), 0, s, speed, w.speed);
-    BGV_CHECK_LAUNCH();
+    BGV_LAUNCH(k_copy_f32, dim3(1), dim3(1), 0, s, speed, w.speed);
+    float4 *bbox = p->exact ? nullptr : w.bh.bbox;
+    if (bbox && p->iters > 0) BGV_LAUNCH(k_bh_bbox, dim3(nb), dim3(kFaThreads), 0, s, K, x, bbox);
     for (int32_t it = 0; it < p->iters; ++it) {
+        BGV_LAUNCH(k_attract, dim3(grid_for(K, kFaThreads / kWave, 16384)), dim3(kFaThreads), 0, s, K, x, w.csr.row,
+                   w.csr.col, w.csr.wt, w.A);
         if (p->exact) {
-            hipLaunchKernelGGL(k_force_exact, dim3(nb), dim3(kFaThreads), 0, s, K, x, m, w.csr.row, w.csr.col,
-                               w.csr.wt, p->kr, p->kg, fp, w.F, w.part);
-            BGV_CHECK_LAUNCH();
+            BGV_LAUNCH(k_force_exact, dim3(nb), dim3(kFaThreads), 0, s, K, x, m, w.A, p->kr, p->kg, fp, w.F,
+                       w.part);
         } else {
             BGV_TRY(bh_forces(K, x, m, w.csr, p->theta, p->kr, p->kg, fp, w, s));
         }
-        hipLaunchKernelGGL(k_update, dim3(nb), dim3(kFaThreads), 0, s, K, x, fp, w.F, w.part, nb,
-                           w.speed + (it & 1), w.speed + ((it + 1) & 1), p->tau, p->ks, p->ksmax);
-        BGV_CHECK_LAUNCH();
+        BGV_LAUNCH(k_update, dim3(nb), dim3(kFaThreads), 0, s, K, x, fp, w.F, w.part, nb, w.speed + (it & 1),
+                   w.speed + ((it + 1) & 1), p->tau, p->ks, p->ksmax, bbox);
     }
-    hipLaunchKernelGGL(k_copy_f32, dim3(1), dim3(1), 0, s, w.speed + (p->iters & 1), speed);
-    BGV_CHECK_LAUNCH();
+    BGV_LAUNCH(k_copy_f32, dim3(1), dim3(1), 0, s, w.speed + (p->iters & 1), speed);
     return BGV_OK;
 }

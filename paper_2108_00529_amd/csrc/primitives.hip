@@ -4,6 +4,7 @@
 #include <stdio.h>
 
 #include "common.h"
+#include "block_scan.h"
 
 namespace bgv {
 
@@ -29,8 +30,7 @@ __global__ void k_fill(T *p, T v, int64_t n) {
 template <class T>
 bgv_status fill(T *p, T value, int64_t count, hipStream_t s) {
     if (count <= 0) return BGV_OK;
-    hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(count, 256 * 4, 8192)), dim3(256), 0, s, p, value, count);
-    BGV_CHECK_LAUNCH();
+    BGV_LAUNCH(k_fill<T>, dim3(grid_for(count, 256 * 4, 8192)), dim3(256), 0, s, p, value, count);
     return BGV_OK;
 }
 template bgv_status fill<int32_t>(int32_t *, int32_t, int64_t, hipStream_t);
@@ -44,41 +44,6 @@ template bgv_status fill<double>(double *, double, int64_t, hipStream_t);
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
-
-template <class T>
-__device__ __forceinline__ T wave_incl_scan(T v) {
-    const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        T t = __shfl_up(v, o, kWave);
-        if (lane >= o) v += t;
-    }
-    return v;
-}
-
-// Exclusive block scan of one value per thread; returns the exclusive prefix and
-// the block total in *total.  blockDim.x must be a multiple of 64, <= 1024.  The
-// combination order depends only on the thread index (deterministic for FP types).
-template <class T>
-__device__ __forceinline__ T block_excl_scan(T v, T *total) {
-    __shared__ T wsum[17];
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    const int nw = blockDim.x / kWave;
-    T incl = wave_incl_scan(v);
-    if (lane == kWave - 1) wsum[w] = incl;
-    __syncthreads();
-    if (w == 0) {
-        T x = lane < nw ? wsum[lane] : T(0);
-        T xi = wave_incl_scan(x);
-        if (lane < nw) wsum[lane] = xi - x;
-        if (lane == nw - 1) wsum[16] = xi;
-    }
-    __syncthreads();
-    T res = (incl - v) + wsum[w];
-    *total = wsum[16];
-    __syncthreads();
-    return res;
-}
 
 template <class T>
 __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const T *in, int64_t n, T *part) {
@@ -141,12 +106,9 @@ bgv_status exclusive_scan(const T *in, T *out, int64_t n, T *total, void *scratc
     }
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
     T *part = static_cast<T *>(scratch);
-    hipLaunchKernelGGL(k_scan_reduce<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, part);
-    BGV_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_scan_partials<T>, dim3(1), dim3(1024), 0, s, part, nb, total);
-    BGV_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_scan_down<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, out, n, part);
-    BGV_CHECK_LAUNCH();
+    BGV_LAUNCH(k_scan_reduce<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, part);
+    BGV_LAUNCH(k_scan_partials<T>, dim3(1), dim3(1024), 0, s, part, nb, total);
+    BGV_LAUNCH(k_scan_down<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, out, n, part);
     return BGV_OK;
 }
 template bgv_status exclusive_scan<uint32_t>(const uint32_t *, uint32_t *, int64_t, uint32_t *, void *, hipStream_t);
@@ -162,6 +124,7 @@ constexpr int kRsThreads = 256;
 constexpr int kRsItems = 16;
 constexpr int kRsTile = kRsThreads * kRsItems;
 constexpr int kRsWaves = kRsThreads / kWave;
+constexpr int kRsLocalOffsetTiles = 64;  // up to this many tiles the scatter kernel scans the counts itself
 
 __global__ void __launch_bounds__(kRsThreads) k_rs_upsweep(const uint64_t *keys, int64_t n, int shift,
                                                             uint32_t *counts, int64_t nb) {
@@ -184,11 +147,24 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_upsweep(const uint64_t *keys,
 __global__ void __launch_bounds__(kRsThreads) k_rs_downsweep(const uint64_t *keys, uint64_t *keys_out,
                                                               const uint32_t *vals, uint32_t *vals_out,
                                                               int64_t n, int shift, const uint32_t *offsets,
-                                                              int64_t nb) {
+                                                              int64_t nb, int raw_counts) {
     __shared__ uint32_t running[256];
     __shared__ uint32_t wcnt[kRsWaves][256];
     const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
-    running[t] = offsets[(int64_t)t * nb + blockIdx.x];
+    if (raw_counts) {
+        // few tiles: derive this tile's digit offsets from the raw per-tile counts here
+        // instead of a separate device-wide scan
+        uint32_t tot = 0, pre = 0;
+        for (int64_t b = 0; b < nb; ++b) {
+            const uint32_t c = offsets[(int64_t)t * nb + b];
+            if (b < (int64_t)blockIdx.x) pre += c;
+            tot += c;
+        }
+        uint32_t all;
+        running[t] = block_excl_scan<uint32_t>(tot, &all) + pre;
+    } else {
+        running[t] = offsets[(int64_t)t * nb + blockIdx.x];
+    }
 #pragma unroll
     for (int q = 0; q < kRsWaves; ++q) wcnt[q][t] = 0;
     __syncthreads();
@@ -243,13 +219,12 @@ bgv_status radix_sort_u64(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, ui
         const int64_t nb = (n + kRsTile - 1) / kRsTile;
         uint32_t *counts = static_cast<uint32_t *>(scratch);
         void *scan_scratch = static_cast<char *>(scratch) + align_up(sizeof(uint32_t) * 256 * (size_t)nb);
+        const int raw = nb <= kRsLocalOffsetTiles ? 1 : 0;
         for (int shift = 0; shift < nbits; shift += 8) {
-            hipLaunchKernelGGL(k_rs_upsweep, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, n, shift, counts, nb);
-            BGV_CHECK_LAUNCH();
-            BGV_TRY(exclusive_scan_u32(counts, counts, 256 * nb, nullptr, scan_scratch, s));
-            hipLaunchKernelGGL(k_rs_downsweep, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, dst, vsrc, vdst, n,
-                               shift, counts, nb);
-            BGV_CHECK_LAUNCH();
+            BGV_LAUNCH(k_rs_upsweep, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, n, shift, counts, nb);
+            if (!raw) BGV_TRY(exclusive_scan_u32(counts, counts, 256 * nb, nullptr, scan_scratch, s));
+            BGV_LAUNCH(k_rs_downsweep, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, dst, vsrc, vdst, n, shift,
+                       counts, nb, raw);
             uint64_t *tk = src; src = dst; dst = tk;
             uint32_t *tv = vsrc; vsrc = vdst; vdst = tv;
         }

@@ -82,13 +82,15 @@ __global__ void k_sg_super_size(const int32_t *__restrict__ super_label, const u
     }
 }
 
-// Sketch 2 + key emission.  Keys are appended through one atomic per wave.
-__global__ void __launch_bounds__(kSgThreads) k_sg_sketch_edges(const int2 *__restrict__ edges, int64_t m,
-                                                                 const int32_t *__restrict__ labels,
-                                                                 const uint32_t *__restrict__ sid, HashRows h,
-                                                                 int32_t rows, uint32_t cols, uint32_t *__restrict__ M2,
-                                                                 int kbits, uint64_t *__restrict__ keys,
-                                                                 unsigned long long *__restrict__ nkeys) {
+// Inter-community edges: emit the packed (sid_lo, sid_hi) key of each, appended
+// through one atomic per wave.  Sketch 2 is filled after the keys are sorted: each
+// distinct key adds its multiplicity once (the same integer sums as one increment per
+// edge, without same-address contention on popular community pairs).
+__global__ void __launch_bounds__(kSgThreads) k_sg_edge_keys(const int2 *__restrict__ edges, int64_t m,
+                                                              const int32_t *__restrict__ labels,
+                                                              const uint32_t *__restrict__ sid, int kbits,
+                                                              uint64_t *__restrict__ keys,
+                                                              unsigned long long *__restrict__ nkeys) {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     // every lane of a wave runs the same number of iterations (ballots stay uniform)
@@ -105,8 +107,6 @@ __global__ void __launch_bounds__(kSgThreads) k_sg_sketch_edges(const int2 *__re
                     inter = true;
                     lo = (uint32_t)min(a, b);
                     hi = (uint32_t)max(a, b);
-                    for (int r = 0; r < rows; ++r)
-                        atomicAdd(&M2[(size_t)r * cols + col_pair(h.a[r], h.b[r], h.c[r], lo, hi, cols)], 1u);
                 }
             }
         }
@@ -128,19 +128,45 @@ __global__ void k_sg_unique_flag(const uint64_t *__restrict__ keys, int64_t nk, 
         flag[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
 }
 
+// Distinct keys: superedge j = (sid_lo, sid_hi) and the position of its run.
 __global__ void k_sg_unique_write(const uint64_t *__restrict__ keys, int64_t nk, const uint32_t *__restrict__ flag,
-                                  const uint32_t *__restrict__ pos, int kbits, const int32_t *__restrict__ super_label,
-                                  HashRows h, int32_t rows, uint32_t cols, const uint32_t *__restrict__ M2,
-                                  int32_t *__restrict__ superedges, uint32_t *__restrict__ se_weight) {
+                                  const uint32_t *__restrict__ pos, int kbits, int32_t *__restrict__ superedges,
+                                  uint32_t *__restrict__ run_start) {
     const uint64_t lowmask = (1ull << kbits) - 1ull;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nk; i += (int64_t)gridDim.x * blockDim.x) {
         if (!flag[i]) continue;
         const uint64_t k = keys[i];
-        const int32_t sa = (int32_t)(k >> kbits), sb = (int32_t)(k & lowmask);
         const uint32_t j = pos[i];
-        superedges[2 * (int64_t)j] = sa;
-        superedges[2 * (int64_t)j + 1] = sb;
-        const uint32_t la = (uint32_t)super_label[sa], lb = (uint32_t)super_label[sb];
+        superedges[2 * (int64_t)j] = (int32_t)(k >> kbits);
+        superedges[2 * (int64_t)j + 1] = (int32_t)(k & lowmask);
+        run_start[j] = (uint32_t)i;
+    }
+}
+
+// Sketch 2: each distinct key adds its multiplicity (run length) at g_r(key).
+__global__ void k_sg_sketch_pairs(const int32_t *__restrict__ superedges, const uint32_t *__restrict__ run_start,
+                                  const uint32_t *__restrict__ Ep, uint32_t nk, const int32_t *__restrict__ super_label,
+                                  HashRows h, int32_t rows, uint32_t cols, uint32_t *__restrict__ M2,
+                                  uint32_t *__restrict__ se_count) {
+    const int64_t E = *Ep;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < E; j += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t cnt = (j + 1 < E ? run_start[j + 1] : nk) - run_start[j];
+        const uint32_t la = (uint32_t)super_label[superedges[2 * j]];
+        const uint32_t lb = (uint32_t)super_label[superedges[2 * j + 1]];
+        for (int r = 0; r < rows; ++r)
+            atomicAdd(&M2[(size_t)r * cols + col_pair(h.a[r], h.b[r], h.c[r], la, lb, cols)], cnt);
+        if (se_count) se_count[j] = cnt;
+    }
+}
+
+// Superedge weight = count-min estimate (minimum over the rows of sketch 2).
+__global__ void k_sg_pair_weights(const int32_t *__restrict__ superedges, const uint32_t *__restrict__ Ep,
+                                  const int32_t *__restrict__ super_label, HashRows h, int32_t rows, uint32_t cols,
+                                  const uint32_t *__restrict__ M2, uint32_t *__restrict__ se_weight) {
+    const int64_t E = *Ep;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < E; j += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t la = (uint32_t)super_label[superedges[2 * j]];
+        const uint32_t lb = (uint32_t)super_label[superedges[2 * j + 1]];
         uint32_t best = 0xffffffffu;
         for (int r = 0; r < rows; ++r)
             best = min(best, M2[(size_t)r * cols + col_pair(h.a[r], h.b[r], h.c[r], la, lb, cols)]);
@@ -155,7 +181,7 @@ __global__ void k_sg_node_super(const int32_t *__restrict__ labels, const uint32
 }
 
 struct SgWs {
-    uint32_t *flag, *sid, *counters, *uflag, *upos;
+    uint32_t *flag, *sid, *counters, *uflag, *upos, *run_start;
     uint64_t *keys, *keys_alt;
     void *scan_scratch, *sort_scratch;
 };
@@ -169,6 +195,7 @@ static size_t sg_layout(Carver &c, int32_t n, int64_t m, SgWs *w) {
     w->keys_alt = c.take<uint64_t>((size_t)mm);
     w->uflag = c.take<uint32_t>((size_t)mm);
     w->upos = c.take<uint32_t>((size_t)mm);
+    w->run_start = c.take<uint32_t>((size_t)mm);
     const int64_t big = n > mm ? n : mm;
     w->scan_scratch = c.take<char>(scan_workspace(big));
     w->sort_scratch = c.take<char>(radix_workspace(mm));
@@ -204,8 +231,9 @@ extern "C" size_t bgv_supergraph_workspace(int32_t n, int64_t m, const bgv_sketc
 extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges, const int32_t *labels,
                                      const int32_t *degree, const bgv_sketch_params *sp, int32_t *K_out,
                                      int64_t *E_out, int32_t *super_label, uint32_t *super_size,
-                                     int32_t *node_super, int32_t *superedges, uint32_t *se_weight, uint32_t *M1,
-                                     uint32_t *M2, void *ws, size_t ws_bytes, bgv_stream_t stream) {
+                                     int32_t *node_super, int32_t *superedges, uint32_t *se_weight,
+                                     uint32_t *se_count, uint32_t *M1, uint32_t *M2, void *ws, size_t ws_bytes,
+                                     bgv_stream_t stream) {
     clear_error();
     if (!sg_valid(n, m, sp)) {
         set_error("bgv_supergraph: invalid arguments (n=%d m=%lld)", n, (long long)m);
@@ -230,29 +258,24 @@ extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges,
     // supernodes
     BGV_TRY(fill<uint32_t>(w.flag, 0u, n, s));
     BGV_TRY(fill<uint32_t>(w.counters, 0u, 8, s));
-    hipLaunchKernelGGL(k_sg_flag, dim3(gn), dim3(kSgThreads), 0, s, labels, n, w.flag);
-    BGV_CHECK_LAUNCH();
+    BGV_LAUNCH(k_sg_flag, dim3(gn), dim3(kSgThreads), 0, s, labels, n, w.flag);
     BGV_TRY(exclusive_scan_u32(w.flag, w.sid, n, &w.counters[0], w.scan_scratch, s));
-    hipLaunchKernelGGL(k_sg_compact, dim3(gn), dim3(kSgThreads), 0, s, w.flag, w.sid, n, super_label);
-    BGV_CHECK_LAUNCH();
+    BGV_LAUNCH(k_sg_compact, dim3(gn), dim3(kSgThreads), 0, s, w.flag, w.sid, n, super_label);
 
     // sketch 1 and sizes
     const int64_t cells = (int64_t)rows * cols;
     BGV_TRY(fill<uint32_t>(M1, 0u, cells, s));
     BGV_TRY(fill<uint32_t>(M2, 0u, cells, s));
     if (cells <= kLdsCounters) {
-        hipLaunchKernelGGL(k_sg_sketch_nodes_lds, dim3(grid_for(n, kSgThreads * 16, 1024)), dim3(kSgThreads), 0, s,
-                           labels, degree, n, h1, rows, cols, M1);
+        BGV_LAUNCH(k_sg_sketch_nodes_lds, dim3(grid_for(n, kSgThreads * 16, 1024)), dim3(kSgThreads), 0, s,
+                   labels, degree, n, h1, rows, cols, M1);
     } else {
-        hipLaunchKernelGGL(k_sg_sketch_nodes, dim3(gn), dim3(kSgThreads), 0, s, labels, degree, n, h1, rows, cols, M1);
+        BGV_LAUNCH(k_sg_sketch_nodes, dim3(gn), dim3(kSgThreads), 0, s, labels, degree, n, h1, rows, cols, M1);
     }
-    BGV_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_sg_super_size, dim3(gn), dim3(kSgThreads), 0, s, super_label, &w.counters[0], h1, rows, cols,
+    BGV_LAUNCH(k_sg_super_size, dim3(gn), dim3(kSgThreads), 0, s, super_label, &w.counters[0], h1, rows, cols,
                        M1, super_size);
-    BGV_CHECK_LAUNCH();
     if (node_super) {
-        hipLaunchKernelGGL(k_sg_node_super, dim3(gn), dim3(kSgThreads), 0, s, labels, w.sid, n, node_super);
-        BGV_CHECK_LAUNCH();
+        BGV_LAUNCH(k_sg_node_super, dim3(gn), dim3(kSgThreads), 0, s, labels, w.sid, n, node_super);
     }
 
     // K is needed to size the packed superedge keys
@@ -263,12 +286,11 @@ extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges,
     int kbits = 1;
     while (kbits < 31 && (1u << kbits) < Kh) ++kbits;
 
-    // sketch 2 + keys
+    // inter-community keys, sorted and made unique, then sketch 2 and the weights
     unsigned long long *nkeys_d = reinterpret_cast<unsigned long long *>(&w.counters[2]);
     if (m > 0) {
-        hipLaunchKernelGGL(k_sg_sketch_edges, dim3(grid_for(m, kSgThreads * 4, 16384)), dim3(kSgThreads), 0, s, e2, m,
-                           labels, w.sid, h2, rows, cols, M2, kbits, w.keys, nkeys_d);
-        BGV_CHECK_LAUNCH();
+        BGV_LAUNCH(k_sg_edge_keys, dim3(grid_for(m, kSgThreads * 4, 16384)), dim3(kSgThreads), 0, s, e2, m, labels,
+                   w.sid, kbits, w.keys, nkeys_d);
     }
     unsigned long long nk = 0;
     BGV_CHECK_HIP(hipMemcpyAsync(&nk, nkeys_d, sizeof nk, hipMemcpyDeviceToHost, s));
@@ -279,12 +301,14 @@ extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges,
         BGV_TRY(radix_sort_u64(w.keys, w.keys_alt, nullptr, nullptr, (int64_t)nk, 2 * kbits, &sorted, nullptr,
                                w.sort_scratch, s));
         const unsigned gk = grid_for((int64_t)nk, kSgThreads, 65536);
-        hipLaunchKernelGGL(k_sg_unique_flag, dim3(gk), dim3(kSgThreads), 0, s, sorted, (int64_t)nk, w.uflag);
-        BGV_CHECK_LAUNCH();
+        BGV_LAUNCH(k_sg_unique_flag, dim3(gk), dim3(kSgThreads), 0, s, sorted, (int64_t)nk, w.uflag);
         BGV_TRY(exclusive_scan_u32(w.uflag, w.upos, (int64_t)nk, &w.counters[1], w.scan_scratch, s));
-        hipLaunchKernelGGL(k_sg_unique_write, dim3(gk), dim3(kSgThreads), 0, s, sorted, (int64_t)nk, w.uflag, w.upos,
-                           kbits, super_label, h2, rows, cols, M2, superedges, se_weight);
-        BGV_CHECK_LAUNCH();
+        BGV_LAUNCH(k_sg_unique_write, dim3(gk), dim3(kSgThreads), 0, s, sorted, (int64_t)nk, w.uflag, w.upos, kbits,
+                   superedges, w.run_start);
+        BGV_LAUNCH(k_sg_sketch_pairs, dim3(gk), dim3(kSgThreads), 0, s, superedges, w.run_start, &w.counters[1],
+                   (uint32_t)nk, super_label, h2, rows, cols, M2, se_count);
+        BGV_LAUNCH(k_sg_pair_weights, dim3(gk), dim3(kSgThreads), 0, s, superedges, &w.counters[1], super_label, h2,
+                   rows, cols, M2, se_weight);
         uint32_t Eh = 0;
         BGV_CHECK_HIP(hipMemcpyAsync(&Eh, &w.counters[1], sizeof Eh, hipMemcpyDeviceToHost, s));
         BGV_CHECK_HIP(hipStreamSynchronize(s));

@@ -1,0 +1,38 @@
+"""Per-kernel device timing of libbgv launches (include/bgv_profile.h): HIP events
+recorded on the launching stream around every library kernel while enabled."""
+from __future__ import annotations
+
+import ctypes as C
+
+from ._lib import lib
+
+lib.bgv_profile_enable.argtypes = [C.c_int]
+lib.bgv_profile_enable.restype = None
+lib.bgv_profile_reset.argtypes = []
+lib.bgv_profile_reset.restype = None
+lib.bgv_profile_count.argtypes = []
+lib.bgv_profile_count.restype = C.c_int
+lib.bgv_profile_get.argtypes = [C.c_int, C.POINTER(C.c_char_p), C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+lib.bgv_profile_get.restype = C.c_int
+
+
+def enable(on: bool = True) -> None:
+    lib.bgv_profile_enable(1 if on else 0)
+
+
+def reset() -> None:
+    lib.bgv_profile_reset()
+
+
+def stats() -> dict:
+    """{kernel name: {"launches": n, "total_ms": t}} since the last reset."""
+    out = {}
+    for i in range(lib.bgv_profile_count()):
+        name = C.c_char_p()
+        cnt = C.c_int64()
+        ms = C.c_double()
+        if lib.bgv_profile_get(i, C.byref(name), C.byref(cnt), C.byref(ms)) == 0:
+            key = name.value.decode()
+            key = key[2:] if key.startswith("k_") else key
+            out[key] = {"launches": int(cnt.value), "total_ms": float(ms.value)}
+    return out

@@ -97,7 +97,7 @@ def check_supergraph(bgv, n, e, lab, deg, rows, cols, seed):
     say(f"  supergraph n={n} m={len(e)} rows={rows} cols={cols}")
     c1, c2 = sketch_coefs(rows, seed)
     ref = oracle.supergraph(n, e, lab, deg, rows, cols, c1, c2)
-    sg = bgv.supergraph(dev(e), dev(lab), dev(deg), rows, cols, c1, c2)
+    sg = bgv.supergraph(dev(e), dev(lab), dev(deg), rows, cols, c1, c2, exact_counts=True)
     assert sg["K"] == ref["K"]
     assert sg["E"] == len(ref["superedges"])
     np.testing.assert_array_equal(host(sg["super_label"]), ref["super_label"])
@@ -106,6 +106,7 @@ def check_supergraph(bgv, n, e, lab, deg, rows, cols, seed):
     np.testing.assert_array_equal(u32(sg["M2"]), ref["M2"])
     np.testing.assert_array_equal(host(sg["superedges"]), ref["superedges"])
     np.testing.assert_array_equal(u32(sg["se_weight"]), ref["se_weight"])
+    np.testing.assert_array_equal(u32(sg["se_count"]), ref["se_count"])
     np.testing.assert_array_equal(host(sg["node_super"]), ref["sid_of_label"][lab])
     return sg, ref
 
