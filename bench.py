@@ -37,11 +37,31 @@ def parse():
     ap.add_argument("--workload", default="lfr_1m")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-fa2-iters", type=int, default=20)
+    ap.add_argument("--no-kernel-timing", action="store_true",
+                    help="do not bracket launches with HIP events (for hardware-counter runs)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (5 times), to scale HBM counters")
     return ap.parse_args()
+
+
+def calibrate_copy(mib: int) -> None:
+    """A plain copy kernel of known size: FETCH_SIZE / WRITE_SIZE of one dispatch should
+    read mib MiB each; the ratio scales the counters read for the path's kernels."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.arange(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_mib": mib, "bytes_per_copy": n * 4}))
 
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
               file=sys.stderr)
@@ -88,12 +108,12 @@ def main():
         return sg
 
     for _ in range(args.warmup):
-        sg = step()
+        step()
     torch.cuda.synchronize()
-    print(f"[bench] warmup done: K={sg['K']} E_S={sg['E']}", file=sys.stderr, flush=True)
+    print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
 
-    prof.enable(True)
     prof.reset()
+    prof.enable(not args.no_kernel_timing)
     cd_ms, fa_ms = [], []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -106,6 +126,10 @@ def main():
     t_total = time.perf_counter() - t_start
     prof.enable(False)
     kstats = prof.stats()
+    inter = prof.counter("bh_interactions")
+    for k in kstats:
+        if k.startswith("bh_force") and inter:
+            kstats[k]["bh_interactions"] = inter
     print(f"[bench] timed {args.steps} steps in {t_total:.2f}s", file=sys.stderr, flush=True)
 
     ms_per_step = 1000.0 * t_total / args.steps
@@ -166,16 +190,38 @@ def roofline_report(kstats, wl, n, m, K, E):
     avg_s = st["total_ms"] / 1000.0 / max(st["launches"], 1)
     if top in rows:
         r = rows[top]
-    elif top == "bh_force" and "bh_interactions" in st:
+    elif top.startswith("bh_force") and "bh_interactions" in st:
         flops = BH_INTERACTION_FLOPS * st["bh_interactions"] / max(st["launches"], 1)
-        r = dict(bound="alu", achieved=flops / avg_s / 1e12, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s")
+        r = dict(bound="alu", achieved=flops / avg_s / 1e12, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                 interactions_per_launch=st["bh_interactions"] / max(st["launches"], 1))
     else:
         r = dict(bound="unknown", achieved=None, peak=None, unit=None)
-    r = dict(r, kernel=top, avg_ms=avg_s * 1000.0, traffic=None)
+    r = dict(r, kernel=top, avg_ms=avg_s * 1000.0, traffic=measured_traffic(top))
     if r.get("achieved") is not None:
         r["frac"] = r["achieved"] / r["peak"]
     extra["roofline_edge_stream"] = {k: dict(v, frac=v["achieved"] / v["peak"]) for k, v in rows.items()}
     return r, extra
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of the dominant kernel, from the committed rocprofv3 counter
+    summary, or None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    import re
+    if not kernel.startswith("bh_force"):
+        return None
+    summary = os.path.join(ROOT, "profiles", "bh_force_lfr_1m.md")
+    src = os.path.join(ROOT, "paper_2108_00529_amd", "csrc", "fa2.hip")
+    try:
+        text = open(summary).read()
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    m_hash = re.search(r"fa2\.hip when measured: ([0-9a-f]{16})", text)
+    m_bytes = re.search(r"traffic_bytes_per_launch: (\d+)", text)
+    if not m_hash or not m_bytes or m_hash.group(1) != digest:
+        return None
+    return int(m_bytes.group(1))
 
 
 def cpu_baseline(edges_np, n, wl, c1, c2, pos0_np, fa2_iters):

@@ -27,6 +27,11 @@ int bgv_profile_count(void);
  * of launches and summed device time in milliseconds.  Returns 0, or -1 if idx is out
  * of range. */
 int bgv_profile_get(int idx, const char **name, int64_t *launches, double *total_ms);
+/* Device-side work counters accumulated while profiling is enabled (reset by
+ * bgv_profile_reset).  "bh_interactions": number of Barnes-Hut force terms summed
+ * (body-body pairs plus body-cell centre-of-mass terms) over all layout iterations.
+ * Synchronises the device.  Returns 0, or -1 for an unknown name or a HIP error. */
+int bgv_profile_counter(const char *name, uint64_t *value);
 
 #ifdef __cplusplus
 }

@@ -66,7 +66,8 @@ bgv_fa2_grad = _sig("bgv_fa2_grad", i32, [i32, i64, P, P, P, P, f32, f32, P, P, 
 EXPORTED = ["bgv_status_string", "bgv_last_error", "bgv_community_workspace", "bgv_community",
             "bgv_supergraph_workspace", "bgv_supergraph", "bgv_fa2_workspace", "bgv_fa2_layout",
             "bgv_fa2_energy_workspace", "bgv_fa2_energy", "bgv_fa2_grad",
-            "bgv_profile_enable", "bgv_profile_reset", "bgv_profile_count", "bgv_profile_get"]
+            "bgv_profile_enable", "bgv_profile_reset", "bgv_profile_count", "bgv_profile_get",
+            "bgv_profile_counter"]
 
 
 def check(status: int, what: str) -> None:

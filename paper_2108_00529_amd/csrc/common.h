@@ -27,8 +27,10 @@ void clear_error();
 
 #define BGV_CHECK_LAUNCH() BGV_CHECK_HIP(hipGetLastError())
 
-// Optional per-kernel event timing (include/bgv_profile.h).
+// Optional per-kernel event timing and counters (include/bgv_profile.h).
 bool prof_on();
+int prof_read_counter(const char *name, uint64_t *value);
+void prof_reset_counters();
 void *prof_begin(const char *name, hipStream_t s);
 void prof_end(void *token, hipStream_t s);
 

@@ -156,9 +156,7 @@ __global__ void __launch_bounds__(kEnThreads) k_grad_rep(int32_t K, int jtiles_p
 __global__ void __launch_bounds__(kEnThreads) k_grad_final(int32_t K, int nsplit, const float2 *__restrict__ prep,
                                                             const float2 *__restrict__ pos,
                                                             const float *__restrict__ mass,
-                                                            const uint32_t *__restrict__ row,
-                                                            const int32_t *__restrict__ col,
-                                                            const float *__restrict__ wt, float kr, float kg,
+                                                            const float2 *__restrict__ att, float kr, float kg,
                                                             const float *__restrict__ grad_out,
                                                             float2 *__restrict__ grad) {
     for (int32_t i = blockIdx.x * kEnThreads + threadIdx.x; i < K; i += gridDim.x * kEnThreads) {
@@ -171,14 +169,9 @@ __global__ void __launch_bounds__(kEnThreads) k_grad_final(int32_t K, int nsplit
         const float2 xi = pos[i];
         const float mi = mass[i];
         float fx = kr * mi * rx, fy = kr * mi * ry;
-        float ax = 0.f, ay = 0.f;
-        for (uint32_t k = row[i]; k < row[i + 1]; ++k) {
-            const float2 xj = pos[col[k]];
-            ax += wt[k] * (xj.x - xi.x);
-            ay += wt[k] * (xj.y - xi.y);
-        }
-        fx += ax;
-        fy += ay;
+        const float2 a = att[i];
+        fx += a.x;
+        fy += a.y;
         const float r = sqrtf(xi.x * xi.x + xi.y * xi.y);
         if (r > 0.f) {
             const float g = kg * mi / r;
@@ -193,7 +186,7 @@ __global__ void __launch_bounds__(kEnThreads) k_grad_final(int32_t K, int nsplit
 struct EnWs {
     CsrWs csr;
     double *prep, *patt, *pgrav;
-    float2 *gsplit;
+    float2 *gsplit, *att;
 };
 
 static int en_tiles(int32_t K) { return (K + kEnThreads - 1) / kEnThreads; }
@@ -217,6 +210,7 @@ static size_t en_layout(Carver &c, int32_t K, int64_t E, EnWs *w) {
     w->patt = c.take<double>((size_t)en_edge_blocks(E));
     w->pgrav = c.take<double>((size_t)en_grav_blocks(K));
     w->gsplit = c.take<float2>((size_t)en_splits(K) * (size_t)K);
+    w->att = c.take<float2>((size_t)K);
     return c.size();
 }
 
@@ -279,7 +273,8 @@ extern "C" bgv_status bgv_fa2_grad(int32_t K, int64_t E, const int32_t *edges, c
     const int T = en_tiles(K), ns = en_splits(K);
     const int per = (T + ns - 1) / ns;
     BGV_LAUNCH(k_grad_rep, dim3(T, ns), dim3(kEnThreads), 0, s, K, per, x, m, w.gsplit);
-    BGV_LAUNCH(k_grad_final, dim3(grid_for(K, kEnThreads, 65536)), dim3(kEnThreads), 0, s, K, ns, w.gsplit, x,
-                       m, w.csr.row, w.csr.col, w.csr.wt, kr, kg, grad_out, reinterpret_cast<float2 *>(grad));
+    BGV_TRY(attraction(K, x, w.csr, w.att, s));
+    BGV_LAUNCH(k_grad_final, dim3(grid_for(K, kEnThreads, 65536)), dim3(kEnThreads), 0, s, K, ns, w.gsplit, x, m,
+               w.att, kr, kg, grad_out, reinterpret_cast<float2 *>(grad));
     return BGV_OK;
 }

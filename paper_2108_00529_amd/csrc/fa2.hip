@@ -12,6 +12,8 @@
 //   both:   k_update        global speed from the partials (every block reduces them in
 //                           the same order), local speeds, displacement
 // No floating-point atomics anywhere: results are identical run to run.
+#include <cstring>
+
 #include "block_scan.h"
 #include "common.h"
 #include "fa2_internal.h"
@@ -35,13 +37,12 @@ __global__ void k_csr_keys(const int2 *__restrict__ edges, int64_t E, int kb, ui
 
 __global__ void k_csr_fill(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals, int64_t nent,
                            int kb, int32_t K, const float *__restrict__ attr_w, uint32_t *__restrict__ row,
-                           int32_t *__restrict__ col, float *__restrict__ w) {
+                           int2 *__restrict__ cw) {
     const uint64_t mask = (1ull << kb) - 1ull;
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nent; k += (int64_t)gridDim.x * blockDim.x) {
         const uint64_t key = keys[k];
         const int64_t src = (int64_t)(key >> kb);
-        col[k] = (int32_t)(key & mask);
-        w[k] = attr_w ? attr_w[vals[k]] : 1.0f;
+        cw[k] = make_int2((int32_t)(key & mask), __float_as_int(attr_w ? attr_w[vals[k]] : 1.0f));
         const int64_t prev = k ? (int64_t)(keys[k - 1] >> kb) : -1;
         for (int64_t r = prev + 1; r <= src; ++r) row[r] = (uint32_t)k;
         if (k == nent - 1)
@@ -63,8 +64,7 @@ static int bits_for(int64_t K) {
 size_t csr_layout(Carver &c, int32_t K, int64_t E, CsrWs *w) {
     const int64_t nent = 2 * E > 0 ? 2 * E : 1;
     w->row = c.take<uint32_t>((size_t)K + 1);
-    w->col = c.take<int32_t>((size_t)nent);
-    w->wt = c.take<float>((size_t)nent);
+    w->cw = c.take<int2>((size_t)nent);
     w->mass = c.take<float>((size_t)K);
     w->keys = c.take<uint64_t>((size_t)nent);
     w->keys_alt = c.take<uint64_t>((size_t)nent);
@@ -86,7 +86,7 @@ bgv_status build_csr(int32_t K, int64_t E, const int32_t *edges, const float *at
         uint32_t *sv;
         BGV_TRY(radix_sort_u64(w.keys, w.keys_alt, w.vals, w.vals_alt, 2 * E, 2 * kb, &sk, &sv, w.sort_scratch, s));
         BGV_LAUNCH(k_csr_fill, dim3(grid_for(2 * E, kFaThreads, 65536)), dim3(kFaThreads), 0, s, sk, sv,
-                           2 * E, kb, K, attr_w, w.row, w.col, w.wt);
+                           2 * E, kb, K, attr_w, w.row, w.cw);
     }
     if (mass_in) {
         *mass_out = mass_in;
@@ -126,19 +126,32 @@ __device__ __forceinline__ double2 block_sum2(double2 v) {
 // are why a row is not given to a single thread.
 __global__ void __launch_bounds__(kFaThreads) k_attract(int32_t K, const float2 *__restrict__ pos,
                                                          const uint32_t *__restrict__ row,
-                                                         const int32_t *__restrict__ col,
-                                                         const float *__restrict__ wt, float2 *__restrict__ A) {
+                                                         const int2 *__restrict__ cw, float2 *__restrict__ A) {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t nw = (int64_t)gridDim.x * (kFaThreads / kWave);
     for (int64_t i = (blockIdx.x * (int64_t)kFaThreads + threadIdx.x) / kWave; i < K; i += nw) {
         const float2 xi = pos[i];
         float ax = 0.f, ay = 0.f;
         const uint32_t r1 = row[i + 1];
-        for (uint32_t k = row[i] + lane; k < r1; k += kWave) {
-            const float2 xj = pos[col[k]];
-            const float a = wt[k];
-            ax += a * (xj.x - xi.x);
-            ay += a * (xj.y - xi.y);
+        uint32_t k = row[i] + lane;
+        // four entries per lane in flight, then the remainder
+        for (; k + 3 * kWave < r1; k += 4 * kWave) {
+            const int2 e0 = cw[k], e1 = cw[k + kWave], e2 = cw[k + 2 * kWave], e3 = cw[k + 3 * kWave];
+            const float2 x0 = pos[e0.x], x1 = pos[e1.x], x2 = pos[e2.x], x3 = pos[e3.x];
+            ax += __int_as_float(e0.y) * (x0.x - xi.x);
+            ay += __int_as_float(e0.y) * (x0.y - xi.y);
+            ax += __int_as_float(e1.y) * (x1.x - xi.x);
+            ay += __int_as_float(e1.y) * (x1.y - xi.y);
+            ax += __int_as_float(e2.y) * (x2.x - xi.x);
+            ay += __int_as_float(e2.y) * (x2.y - xi.y);
+            ax += __int_as_float(e3.y) * (x3.x - xi.x);
+            ay += __int_as_float(e3.y) * (x3.y - xi.y);
+        }
+        for (; k < r1; k += kWave) {
+            const int2 e = cw[k];
+            const float2 xj = pos[e.x];
+            ax += __int_as_float(e.y) * (xj.x - xi.x);
+            ay += __int_as_float(e.y) * (xj.y - xi.y);
         }
 #pragma unroll
         for (int o = kWave / 2; o > 0; o >>= 1) {
@@ -147,6 +160,12 @@ __global__ void __launch_bounds__(kFaThreads) k_attract(int32_t K, const float2 
         }
         if (lane == 0) A[i] = make_float2(ax, ay);
     }
+}
+
+bgv_status attraction(int32_t K, const float2 *pos, const CsrWs &csr, float2 *A, hipStream_t s) {
+    BGV_LAUNCH(k_attract, dim3(grid_for(K, kFaThreads / kWave, 16384)), dim3(kFaThreads), 0, s, K, pos, csr.row,
+               csr.cw, A);
+    return BGV_OK;
 }
 
 // Repulsion + precomputed attraction + gravity of node i.
@@ -342,65 +361,74 @@ __global__ void __launch_bounds__(kFaThreads) k_bh_codes(int32_t K, const float2
     }
 }
 
-// Up to kGsMaxK bodies: one workgroup gathers the bodies in Morton order and writes the
-// exclusive FP64 prefix sums of m, m*x, m*y (one launch instead of a gather and three
-// device-wide scans).  Each thread owns a contiguous run of bodies.
-constexpr int kGsThreads = 1024;
-constexpr int32_t kGsMaxK = 1 << 18;
-__global__ void __launch_bounds__(kGsThreads) k_bh_gather_scan(int32_t K, const float2 *__restrict__ pos,
-                                                                const float *__restrict__ mass,
-                                                                const uint64_t *__restrict__ skeys,
-                                                                const uint32_t *__restrict__ order,
-                                                                float4 *__restrict__ body,
-                                                                uint32_t *__restrict__ code, double *__restrict__ PM,
-                                                                double *__restrict__ PX, double *__restrict__ PY) {
-    const int32_t per = (K + kGsThreads - 1) / kGsThreads;
-    const int32_t lo = min(K, (int32_t)threadIdx.x * per), hi = min(K, lo + per);
-    double sm = 0.0, sx = 0.0, sy = 0.0;
-    for (int32_t k = lo; k < hi; ++k) {
+// Bodies in Morton order (one per thread, grid of ceil(K/kFaThreads) blocks) and the
+// block totals of the FP64 mass moments m, m*x, m*y.
+__global__ void __launch_bounds__(kFaThreads) k_bh_gather(int32_t K, const float2 *__restrict__ pos,
+                                                           const float *__restrict__ mass,
+                                                           const uint64_t *__restrict__ skeys,
+                                                           const uint32_t *__restrict__ order,
+                                                           float4 *__restrict__ body, uint32_t *__restrict__ code,
+                                                           double *__restrict__ part3) {
+    const int32_t k = blockIdx.x * kFaThreads + threadIdx.x;
+    double m = 0.0, mx = 0.0, my = 0.0;
+    if (k < K) {
         const uint32_t b = order[k];
         const float2 p = pos[b];
-        const float m = mass[b];
-        body[k] = make_float4(p.x, p.y, m, __int_as_float((int)b));
+        const float mf = mass[b];
+        body[k] = make_float4(p.x, p.y, mf, __int_as_float((int)b));
         code[k] = (uint32_t)skeys[k];
-        sm += (double)m;
-        sx += (double)m * (double)p.x;
-        sy += (double)m * (double)p.y;
+        m = (double)mf;
+        mx = m * (double)p.x;
+        my = m * (double)p.y;
     }
-    double tm, tx, ty;
-    double pm = block_excl_scan<double>(sm, &tm);
-    double px = block_excl_scan<double>(sx, &tx);
-    double py = block_excl_scan<double>(sy, &ty);
-    for (int32_t k = lo; k < hi; ++k) {
-        const float4 bd = body[k];
-        PM[k] = pm;
-        PX[k] = px;
-        PY[k] = py;
-        pm += (double)bd.z;
-        px += (double)bd.z * (double)bd.x;
-        py += (double)bd.z * (double)bd.y;
-    }
+    double t0, t1, t2;
+    block_excl_scan<double>(m, &t0);
+    block_excl_scan<double>(mx, &t1);
+    block_excl_scan<double>(my, &t2);
     if (threadIdx.x == 0) {
-        PM[K] = tm;
-        PX[K] = tx;
-        PY[K] = ty;
+        part3[3 * blockIdx.x] = t0;
+        part3[3 * blockIdx.x + 1] = t1;
+        part3[3 * blockIdx.x + 2] = t2;
     }
 }
 
-// Bodies in Morton order: positions, masses, and FP64 mass moments for the prefix sums.
-__global__ void k_bh_gather(int32_t K, const float2 *__restrict__ pos, const float *__restrict__ mass,
-                            const uint64_t *__restrict__ skeys, const uint32_t *__restrict__ order,
-                            float4 *__restrict__ body, uint32_t *__restrict__ code, double *__restrict__ dm,
-                            double *__restrict__ dmx, double *__restrict__ dmy) {
-    for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < K; k += gridDim.x * blockDim.x) {
-        const uint32_t b = order[k];
-        const float2 p = pos[b];
-        const float m = mass[b];
-        body[k] = make_float4(p.x, p.y, m, __int_as_float((int)b));
-        code[k] = (uint32_t)skeys[k];
-        dm[k] = (double)m;
-        dmx[k] = (double)m * (double)p.x;
-        dmy[k] = (double)m * (double)p.y;
+// Exclusive FP64 prefix sums PM/PX/PY (K+1 entries) of the mass moments in Morton
+// order: block offset = fixed-order sum of the preceding block totals, then a block scan.
+__global__ void __launch_bounds__(kFaThreads) k_bh_prefix(int32_t K, const float4 *__restrict__ body,
+                                                           const double *__restrict__ part3,
+                                                           double *__restrict__ PM, double *__restrict__ PX,
+                                                           double *__restrict__ PY) {
+    double b0 = 0.0, b1 = 0.0, b2 = 0.0;
+    for (int q = threadIdx.x; q < (int)blockIdx.x; q += kFaThreads) {
+        b0 += part3[3 * q];
+        b1 += part3[3 * q + 1];
+        b2 += part3[3 * q + 2];
+    }
+    double base0, base1, base2;
+    block_excl_scan<double>(b0, &base0);
+    block_excl_scan<double>(b1, &base1);
+    block_excl_scan<double>(b2, &base2);
+    const int32_t k = blockIdx.x * kFaThreads + threadIdx.x;
+    double m = 0.0, mx = 0.0, my = 0.0;
+    if (k < K) {
+        const float4 bd = body[k];
+        m = (double)bd.z;
+        mx = m * (double)bd.x;
+        my = m * (double)bd.y;
+    }
+    double t0, t1, t2;
+    const double e0 = block_excl_scan<double>(m, &t0);
+    const double e1 = block_excl_scan<double>(mx, &t1);
+    const double e2 = block_excl_scan<double>(my, &t2);
+    if (k < K) {
+        PM[k] = base0 + e0;
+        PX[k] = base1 + e1;
+        PY[k] = base2 + e2;
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+        PM[K] = base0 + t0;
+        PX[K] = base1 + t1;
+        PY[K] = base2 + t2;
     }
 }
 
@@ -456,7 +484,8 @@ __global__ void k_bh_build(int32_t K, const uint32_t *__restrict__ code, const d
     }
 }
 
-__device__ __forceinline__ void add_pair(float2 xi, float4 bj, float &fx, float &fy) {
+__device__ __forceinline__ void add_pair(float2 xi, float4 bj, float &fx, float &fy, uint32_t &ic) {
+    ++ic;
     const float dx = xi.x - bj.x, dy = xi.y - bj.y;
     const float d2 = dx * dx + dy * dy;
     if (d2 > 0.f) {
@@ -466,24 +495,80 @@ __device__ __forceinline__ void add_pair(float2 xi, float4 bj, float &fx, float 
     }
 }
 
-// One thread per body in Morton order (neighbouring threads walk similar paths).
-__global__ void __launch_bounds__(kFaThreads) k_bh_force(int32_t K, const float4 *__restrict__ body,
+// Barnes-Hut repulsion.  Bodies are taken in Morton order (neighbouring bodies walk
+// similar paths) and each body's traversal is split over G = 2^D lanes: lane L follows
+// the path given by its D bits through the top D tree levels, deciding every node on
+// the way exactly as a single traversal would (a node that is summed whole -- by its
+// centre of mass, as a cell of equal codes, or as one body -- is added once, by the
+// lowest lane below it), then walks its own subtree with a stack.  The lanes' partial
+// sums are combined by a fixed butterfly.  Splitting multiplies the number of
+// wavefronts by G: the walk is a chain of dependent L2 loads, so latency hiding needs
+// many more wavefronts than one per body gives.
+constexpr int kBhThreads = 64;
+constexpr int kBhLanes = 8;
+
+template <int G>
+__global__ void __launch_bounds__(kBhThreads) k_bh_force(int32_t K, const float4 *__restrict__ body,
                                                           const float4 *__restrict__ nodeA,
                                                           const int4 *__restrict__ nodeB, float theta2,
                                                           const float2 *__restrict__ att, float kr, float kg,
                                                           const float2 *__restrict__ fprev, float2 *__restrict__ F,
-                                                          double2 *__restrict__ part, int *__restrict__ overflow) {
-    __shared__ int stack[kStackDepth][kFaThreads];
-    const int32_t r = blockIdx.x * kFaThreads + threadIdx.x;
+                                                          double2 *__restrict__ part, int *__restrict__ overflow,
+                                                          uint32_t *__restrict__ icount) {
+    static_assert(G >= 1 && G <= kWave && (G & (G - 1)) == 0, "lanes per body: power of two <= 64");
+    __shared__ int stack[kStackDepth][kBhThreads];
+    const int64_t tid = (int64_t)blockIdx.x * kBhThreads + threadIdx.x;
+    const int32_t r = (int32_t)(tid / G);
+    const int L = (int)(tid % G);
     double2 st = make_double2(0.0, 0.0);
+    float fx = 0.f, fy = 0.f;
+    uint32_t ic = 0;  // interactions summed by this lane (body pairs + centres of mass)
+    float4 me = make_float4(0.f, 0.f, 0.f, 0.f);
     if (r < K) {
-        const float4 me = body[r];
+        me = body[r];
         const float2 xi = make_float2(me.x, me.y);
-        const float mi = me.z;
-        const int32_t b = __float_as_int(me.w);
-        float fx = 0.f, fy = 0.f;
         int sp = 0;
-        if (K > 1) stack[sp++][threadIdx.x] = 0;
+        // descend the top levels along this lane's path
+        int node = 0, lo = 0, span = G;
+        bool walk = K > 1;
+        while (walk && span > 1) {
+            const float4 A = nodeA[node];
+            const int4 Bn = nodeB[node];
+            const bool owner = L == lo;
+            if (A.w < 0.f) {  // a cell of equal codes: direct sum, once
+                if (owner)
+                    for (int k = Bn.z; k <= Bn.w; ++k)
+                        if (k != r) add_pair(xi, body[k], fx, fy, ic);
+                walk = false;
+                break;
+            }
+            if (r < Bn.z || r > Bn.w) {
+                const float dx = xi.x - A.x, dy = xi.y - A.y;
+                const float d2 = dx * dx + dy * dy;
+                if (d2 > 0.f && A.w < theta2 * d2) {
+                    if (owner) {
+                        const float f = A.z / d2;
+                        fx += f * dx;
+                        fy += f * dy;
+                        ++ic;
+                    }
+                    walk = false;
+                    break;
+                }
+            }
+            span >>= 1;  // opened: the lower half of the lanes takes the left child
+            const bool right = (L - lo) >= span;
+            const int child = right ? Bn.y : Bn.x;
+            if (right) lo += span;
+            if (child < 0) {  // a single body
+                const int j = ~child;
+                if (L == lo && j != r) add_pair(xi, body[j], fx, fy, ic);
+                walk = false;
+                break;
+            }
+            node = child;
+        }
+        if (walk) stack[sp++][threadIdx.x] = node;
         while (sp > 0) {
             const int node = stack[--sp][threadIdx.x];
             const float4 A = nodeA[node];
@@ -491,7 +576,7 @@ __global__ void __launch_bounds__(kFaThreads) k_bh_force(int32_t K, const float4
             bool open;
             if (A.w < 0.f) {  // a cell of equal codes: direct sum
                 for (int k = Bn.z; k <= Bn.w; ++k)
-                    if (k != r) add_pair(xi, body[k], fx, fy);
+                    if (k != r) add_pair(xi, body[k], fx, fy, ic);
                 continue;
             } else if (r >= Bn.z && r <= Bn.w) {
                 open = true;
@@ -502,6 +587,7 @@ __global__ void __launch_bounds__(kFaThreads) k_bh_force(int32_t K, const float4
                     const float f = A.z / d2;
                     fx += f * dx;
                     fy += f * dy;
+                    ++ic;
                     open = false;
                 } else {
                     open = true;
@@ -511,7 +597,7 @@ __global__ void __launch_bounds__(kFaThreads) k_bh_force(int32_t K, const float4
                 // right first onto the stack so the left subtree is summed first
                 if (Bn.y < 0) {
                     const int j = ~Bn.y;
-                    if (j != r) add_pair(xi, body[j], fx, fy);
+                    if (j != r) add_pair(xi, body[j], fx, fy, ic);
                 } else if (sp < kStackDepth) {
                     stack[sp++][threadIdx.x] = Bn.y;
                 } else {
@@ -519,7 +605,7 @@ __global__ void __launch_bounds__(kFaThreads) k_bh_force(int32_t K, const float4
                 }
                 if (Bn.x < 0) {
                     const int j = ~Bn.x;
-                    if (j != r) add_pair(xi, body[j], fx, fy);
+                    if (j != r) add_pair(xi, body[j], fx, fy, ic);
                 } else if (sp < kStackDepth) {
                     stack[sp++][threadIdx.x] = Bn.x;
                 } else {
@@ -527,13 +613,58 @@ __global__ void __launch_bounds__(kFaThreads) k_bh_force(int32_t K, const float4
                 }
             }
         }
+    }
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {
+        fx += __shfl_xor(fx, o, kWave);
+        fy += __shfl_xor(fy, o, kWave);
+    }
+    if (r < K && L == 0) {
+        const float2 xi = make_float2(me.x, me.y);
+        const float mi = me.z;
+        const int32_t b = __float_as_int(me.w);
         const float c = kr * mi;
         const float2 f = attract_gravity(xi, mi, make_float2(c * fx, c * fy), att[b], kg);
         F[b] = f;
         st = swing_traction(f, fprev[b], mi);
     }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) ic += __shfl_xor(ic, o, kWave);
     st = block_sum2(st);
-    if (threadIdx.x == 0) part[blockIdx.x] = st;
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = st;
+        icount[blockIdx.x] += ic;  // one slot per workgroup, accumulated over iterations
+    }
+}
+
+static_assert(kBhThreads == kWave, "the interaction tally reduces over one wavefront per workgroup");
+
+// Profiling only: total Barnes-Hut interactions, readable with bgv_profile_counter().
+__device__ unsigned long long g_bh_interactions;
+
+__global__ void __launch_bounds__(kFaThreads) k_count_total(const uint32_t *__restrict__ icount, int32_t n) {
+    unsigned long long acc = 0;
+    for (int32_t i = threadIdx.x; i < n; i += kFaThreads) acc += icount[i];
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&g_bh_interactions, acc);
+}
+
+int prof_read_counter(const char *name, uint64_t *value) {
+    if (std::strcmp(name, "bh_interactions") != 0) return -1;
+    unsigned long long v = 0;
+    if (hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_bh_interactions), sizeof v) != hipSuccess) return -1;
+    *value = v;
+    return 0;
+}
+
+void prof_reset_counters() {
+    const unsigned long long z = 0;
+    (void)hipMemcpyToSymbol(HIP_SYMBOL(g_bh_interactions), &z, sizeof z);
+}
+
+static int32_t bh_force_blocks(int32_t K) {
+    return (int32_t)(((int64_t)K * kBhLanes + kBhThreads - 1) / kBhThreads);
 }
 
 struct BhWs {
@@ -543,11 +674,12 @@ struct BhWs {
     uint32_t *vals, *vals_alt;
     float4 *body;
     uint32_t *code;
-    double *dm, *dmx, *dmy, *PM, *PX, *PY;
+    double *part3, *PM, *PX, *PY;
     float4 *nodeA;
     int4 *nodeB;
     int *overflow;
-    void *sort_scratch, *scan_scratch;
+    uint32_t *icount;  // interactions per force workgroup, summed over the call's iterations
+    void *sort_scratch;
 };
 
 struct FaWs {
@@ -563,7 +695,7 @@ static size_t fa_layout(Carver &c, int32_t K, int64_t E, const bgv_fa2_params *p
     const int64_t nb = (K + kFaThreads - 1) / kFaThreads;
     w->F = c.take<float2>((size_t)K);
     w->A = c.take<float2>((size_t)K);
-    w->part = c.take<double2>((size_t)nb);
+    w->part = c.take<double2>((size_t)(nb > bh_force_blocks(K) ? nb : bh_force_blocks(K)));
     w->speed = c.take<float>(2);
     if (!p->exact) {
         BhWs &b = w->bh;
@@ -575,17 +707,15 @@ static size_t fa_layout(Carver &c, int32_t K, int64_t E, const bgv_fa2_params *p
         b.vals_alt = c.take<uint32_t>((size_t)K);
         b.body = c.take<float4>((size_t)K);
         b.code = c.take<uint32_t>((size_t)K);
-        b.dm = c.take<double>((size_t)K);
-        b.dmx = c.take<double>((size_t)K);
-        b.dmy = c.take<double>((size_t)K);
+        b.part3 = c.take<double>(3 * (size_t)nb);
         b.PM = c.take<double>((size_t)K + 1);
         b.PX = c.take<double>((size_t)K + 1);
         b.PY = c.take<double>((size_t)K + 1);
         b.nodeA = c.take<float4>((size_t)K);
         b.nodeB = c.take<int4>((size_t)K);
         b.overflow = c.take<int>(1);
+        b.icount = c.take<uint32_t>((size_t)bh_force_blocks(K));
         b.sort_scratch = c.take<char>(radix_workspace(K));
-        b.scan_scratch = c.take<char>(scan_workspace(K));
     }
     return c.size();
 }
@@ -607,22 +737,15 @@ static bgv_status bh_forces(int32_t K, const float2 *pos, const float *mass, con
     uint64_t *sk;
     uint32_t *sv;
     BGV_TRY(radix_sort_u64(b.keys, b.keys_alt, b.vals, b.vals_alt, K, 32, &sk, &sv, b.sort_scratch, s));
-    if (K <= kGsMaxK) {
-        BGV_LAUNCH(k_bh_gather_scan, dim3(1), dim3(kGsThreads), 0, s, K, pos, mass, sk, sv, b.body, b.code, b.PM,
-                   b.PX, b.PY);
-    } else {
-        BGV_LAUNCH(k_bh_gather, dim3(nb), dim3(kFaThreads), 0, s, K, pos, mass, sk, sv, b.body, b.code, b.dm, b.dmx,
-                   b.dmy);
-        BGV_TRY(exclusive_scan<double>(b.dm, b.PM, K, b.PM + K, b.scan_scratch, s));
-        BGV_TRY(exclusive_scan<double>(b.dmx, b.PX, K, b.PX + K, b.scan_scratch, s));
-        BGV_TRY(exclusive_scan<double>(b.dmy, b.PY, K, b.PY + K, b.scan_scratch, s));
-    }
+    BGV_LAUNCH(k_bh_gather, dim3(nb), dim3(kFaThreads), 0, s, K, pos, mass, sk, sv, b.body, b.code, b.part3);
+    BGV_LAUNCH(k_bh_prefix, dim3(nb), dim3(kFaThreads), 0, s, K, b.body, b.part3, b.PM, b.PX, b.PY);
     if (K > 1) {
         BGV_LAUNCH(k_bh_build, dim3(grid_for(K - 1, kFaThreads, 65536)), dim3(kFaThreads), 0, s, K, b.code,
                            b.PM, b.PX, b.PY, b.s0, b.nodeA, b.nodeB);
     }
-    BGV_LAUNCH(k_bh_force, dim3(nb), dim3(kFaThreads), 0, s, K, b.body, b.nodeA, b.nodeB, theta * theta, w.A, kr,
-               kg, fprev, w.F, w.part, b.overflow);
+    BGV_LAUNCH(k_bh_force<kBhLanes>, dim3(bh_force_blocks(K)), dim3(kBhThreads), 0, s, K, b.body, b.nodeA,
+               b.nodeB, theta * theta, w.A, kr,
+               kg, fprev, w.F, w.part, b.overflow, b.icount);
     return BGV_OK;
 }
 
@@ -656,7 +779,10 @@ extern "C" bgv_status bgv_fa2_layout(int32_t K, int64_t E, const int32_t *edges,
     fa_layout(c, K, E, p, &w);
     const float *m = nullptr;
     BGV_TRY(build_csr(K, E, edges, attr_w, mass, w.csr, s, &m));
-    if (!p->exact) BGV_TRY(fill<int>(w.bh.overflow, 0, 1, s));
+    if (!p->exact) {
+        BGV_TRY(fill<int>(w.bh.overflow, 0, 1, s));
+        BGV_TRY(fill<uint32_t>(w.bh.icount, 0u, bh_force_blocks(K), s));
+    }
 
     float2 *x = reinterpret_cast<float2 *>(pos);
     float2 *fp = reinterpret_cast<float2 *>(fprev);
@@ -665,17 +791,19 @@ extern "C" bgv_status bgv_fa2_layout(int32_t K, int64_t E, const int32_t *edges,
     float4 *bbox = p->exact ? nullptr : w.bh.bbox;
     if (bbox && p->iters > 0) BGV_LAUNCH(k_bh_bbox, dim3(nb), dim3(kFaThreads), 0, s, K, x, bbox);
     for (int32_t it = 0; it < p->iters; ++it) {
-        BGV_LAUNCH(k_attract, dim3(grid_for(K, kFaThreads / kWave, 16384)), dim3(kFaThreads), 0, s, K, x, w.csr.row,
-                   w.csr.col, w.csr.wt, w.A);
+        BGV_TRY(attraction(K, x, w.csr, w.A, s));
         if (p->exact) {
             BGV_LAUNCH(k_force_exact, dim3(nb), dim3(kFaThreads), 0, s, K, x, m, w.A, p->kr, p->kg, fp, w.F,
                        w.part);
         } else {
             BGV_TRY(bh_forces(K, x, m, w.csr, p->theta, p->kr, p->kg, fp, w, s));
         }
-        BGV_LAUNCH(k_update, dim3(nb), dim3(kFaThreads), 0, s, K, x, fp, w.F, w.part, nb, w.speed + (it & 1),
+        const int32_t nparts = p->exact ? nb : bh_force_blocks(K);
+        BGV_LAUNCH(k_update, dim3(nb), dim3(kFaThreads), 0, s, K, x, fp, w.F, w.part, nparts, w.speed + (it & 1),
                    w.speed + ((it + 1) & 1), p->tau, p->ks, p->ksmax, bbox);
     }
     BGV_LAUNCH(k_copy_f32, dim3(1), dim3(1), 0, s, w.speed + (p->iters & 1), speed);
+    if (!p->exact && p->iters > 0 && prof_on())
+        BGV_LAUNCH(k_count_total, dim3(1), dim3(kFaThreads), 0, s, w.bh.icount, bh_force_blocks(K));
     return BGV_OK;
 }

@@ -4,12 +4,11 @@
 
 namespace bgv {
 
-// Directed CSR of an undirected edge list: row[K+1], col/wt[2E] (neighbours of node i
-// in ascending (neighbour, edge index) order), mass[K] = row length + 1.
+// Directed CSR of an undirected edge list: row[K+1]; cw[2E] = (neighbour, weight bits)
+// of node i's entries in ascending (neighbour, edge index) order; mass[K] = row length + 1.
 struct CsrWs {
     uint32_t *row;
-    int32_t *col;
-    float *wt;
+    int2 *cw;
     float *mass;
     uint64_t *keys, *keys_alt;
     uint32_t *vals, *vals_alt;
@@ -17,6 +16,8 @@ struct CsrWs {
 };
 
 size_t csr_layout(Carver &c, int32_t K, int64_t E, CsrWs *w);
+// A[i] = sum over node i's CSR entries of w * (x_j - x_i), one wavefront per node.
+bgv_status attraction(int32_t K, const float2 *pos, const CsrWs &csr, float2 *A, hipStream_t s);
 // Builds the CSR; *mass_out = mass_in if given, else the degree-based masses.
 bgv_status build_csr(int32_t K, int64_t E, const int32_t *edges, const float *attr_w, const float *mass_in,
                      CsrWs &w, hipStream_t s, const float **mass_out);

@@ -121,19 +121,25 @@ bgv_status exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint
 
 // ------------------------------------------------------------------ radix sort ---
 constexpr int kRsThreads = 256;
-constexpr int kRsItems = 16;
-constexpr int kRsTile = kRsThreads * kRsItems;
 constexpr int kRsWaves = kRsThreads / kWave;
 constexpr int kRsLocalOffsetTiles = 64;  // up to this many tiles the scatter kernel scans the counts itself
+// Keys per thread: 16 for large sorts; 4 for sorts of at most kRsSmallN keys, so that
+// small sorts (the per-iteration Morton sort) spread over 4x more workgroups.
+constexpr int kRsItemsLarge = 16;
+constexpr int kRsItemsSmall = 4;
+constexpr int64_t kRsSmallN = (int64_t)kRsLocalOffsetTiles * kRsThreads * kRsItemsSmall;
 
+static int64_t rs_items(int64_t n) { return n <= kRsSmallN ? kRsItemsSmall : kRsItemsLarge; }
+
+template <int ITEMS>
 __global__ void __launch_bounds__(kRsThreads) k_rs_upsweep(const uint64_t *keys, int64_t n, int shift,
                                                             uint32_t *counts, int64_t nb) {
     __shared__ uint32_t hist[256];
     hist[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kRsTile;
+    const int64_t base = (int64_t)blockIdx.x * (kRsThreads * ITEMS);
 #pragma unroll 4
-    for (int j = 0; j < kRsItems; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
         int64_t i = base + (int64_t)j * kRsThreads + threadIdx.x;
         if (i < n) atomicAdd(&hist[(keys[i] >> shift) & 255u], 1u);
     }
@@ -144,6 +150,7 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_upsweep(const uint64_t *keys,
 // Stable scatter: the tile is consumed in rounds of 256 consecutive keys; within a
 // round the rank of a key among equal digits is (keys of that digit in earlier waves)
 // + (equal-digit lanes below it in its wave, from 8 ballots).
+template <int ITEMS>
 __global__ void __launch_bounds__(kRsThreads) k_rs_downsweep(const uint64_t *keys, uint64_t *keys_out,
                                                               const uint32_t *vals, uint32_t *vals_out,
                                                               int64_t n, int shift, const uint32_t *offsets,
@@ -169,8 +176,8 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_downsweep(const uint64_t *key
     for (int q = 0; q < kRsWaves; ++q) wcnt[q][t] = 0;
     __syncthreads();
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int64_t base = (int64_t)blockIdx.x * kRsTile;
-    for (int j = 0; j < kRsItems; ++j) {
+    const int64_t base = (int64_t)blockIdx.x * (kRsThreads * ITEMS);
+    for (int j = 0; j < ITEMS; ++j) {
         const int64_t i = base + (int64_t)j * kRsThreads + t;
         const bool valid = i < n;
         uint64_t key = valid ? keys[i] : 0ull;
@@ -204,10 +211,15 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_downsweep(const uint64_t *key
     }
 }
 
+// Bound for any sort of at most n keys: small sorts use more (smaller) tiles than a
+// large sort of n keys would, so both tile counts are covered.
 size_t radix_workspace(int64_t n) {
-    int64_t nb = (n + kRsTile - 1) / kRsTile;
-    if (nb < 1) nb = 1;
-    return align_up(sizeof(uint32_t) * 256 * (size_t)nb) + scan_workspace(256 * nb);
+    const int64_t ns = n < kRsSmallN ? n : kRsSmallN;
+    const int64_t nb_small = (ns + kRsThreads * kRsItemsSmall - 1) / (kRsThreads * kRsItemsSmall);
+    int64_t nb_large = (n + kRsThreads * kRsItemsLarge - 1) / (kRsThreads * kRsItemsLarge);
+    if (nb_large < 1) nb_large = 1;
+    const int64_t nb = nb_small > nb_large ? nb_small : nb_large;
+    return align_up(sizeof(uint32_t) * 256 * (size_t)nb) + scan_workspace(256 * nb_large);
 }
 
 bgv_status radix_sort_u64(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, uint32_t *vals_alt,
@@ -216,15 +228,26 @@ bgv_status radix_sort_u64(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, ui
     uint64_t *src = keys, *dst = keys_alt;
     uint32_t *vsrc = vals, *vdst = vals_alt;
     if (n > 1) {
-        const int64_t nb = (n + kRsTile - 1) / kRsTile;
+        const bool small = rs_items(n) == kRsItemsSmall;
+        const int64_t tile = kRsThreads * rs_items(n);
+        const int64_t nb = (n + tile - 1) / tile;
         uint32_t *counts = static_cast<uint32_t *>(scratch);
         void *scan_scratch = static_cast<char *>(scratch) + align_up(sizeof(uint32_t) * 256 * (size_t)nb);
         const int raw = nb <= kRsLocalOffsetTiles ? 1 : 0;
         for (int shift = 0; shift < nbits; shift += 8) {
-            BGV_LAUNCH(k_rs_upsweep, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, n, shift, counts, nb);
+            if (small)
+                BGV_LAUNCH(k_rs_upsweep<kRsItemsSmall>, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, n, shift,
+                           counts, nb);
+            else
+                BGV_LAUNCH(k_rs_upsweep<kRsItemsLarge>, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, n, shift,
+                           counts, nb);
             if (!raw) BGV_TRY(exclusive_scan_u32(counts, counts, 256 * nb, nullptr, scan_scratch, s));
-            BGV_LAUNCH(k_rs_downsweep, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, dst, vsrc, vdst, n, shift,
-                       counts, nb, raw);
+            if (small)
+                BGV_LAUNCH(k_rs_downsweep<kRsItemsSmall>, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, dst, vsrc,
+                           vdst, n, shift, counts, nb, raw);
+            else
+                BGV_LAUNCH(k_rs_downsweep<kRsItemsLarge>, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, dst, vsrc,
+                           vdst, n, shift, counts, nb, raw);
             uint64_t *tk = src; src = dst; dst = tk;
             uint32_t *tv = vsrc; vsrc = vdst; vdst = tv;
         }

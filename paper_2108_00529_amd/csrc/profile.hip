@@ -1,5 +1,8 @@
 // Optional per-kernel event timing (include/bgv_profile.h): host-side registry of
-// (start, stop) HIP event pairs recorded around library launches.
+// (start, stop) HIP event pairs recorded around library launches.  Completed pairs are
+// harvested as new events are needed, so the number of live events stays near the
+// number of launches in flight instead of growing with the length of the run.
+#include <deque>
 #include <map>
 #include <mutex>
 #include <string>
@@ -11,21 +14,49 @@
 namespace bgv {
 
 namespace {
-struct Pending {
-    hipEvent_t a, b;
-};
 struct KStat {
     int64_t launches = 0;
     double total_ms = 0.0;
-    std::vector<Pending> pending;
+};
+struct Pending {
+    KStat *stat;
+    hipEvent_t a, b;
 };
 std::mutex g_mu;
 bool g_on = false;
 std::map<std::string, KStat> g_stats;
+std::deque<Pending> g_pending;  // in launch order
 std::vector<hipEvent_t> g_pool;
 std::vector<std::string> g_names;
+constexpr size_t kMaxEvents = 1024;  // created events before waiting on the oldest pair
+
+size_t g_created = 0;
+
+void harvest(const Pending &p) {
+    float ms = 0.f;
+    if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+        p.stat->total_ms += ms;
+        p.stat->launches += 1;
+    }
+    g_pool.push_back(p.a);
+    g_pool.push_back(p.b);
+}
+
+// Harvest finished pairs from the front (non-blocking), or the oldest one (blocking)
+// when the event budget is exhausted.
+void reclaim(bool must) {
+    while (!g_pending.empty() && hipEventQuery(g_pending.front().b) == hipSuccess) {
+        harvest(g_pending.front());
+        g_pending.pop_front();
+    }
+    if (must && g_pool.empty() && !g_pending.empty()) {
+        harvest(g_pending.front());
+        g_pending.pop_front();
+    }
+}
 
 hipEvent_t take_event() {
+    if (g_pool.empty()) reclaim(g_created >= kMaxEvents);
     if (!g_pool.empty()) {
         hipEvent_t e = g_pool.back();
         g_pool.pop_back();
@@ -33,21 +64,14 @@ hipEvent_t take_event() {
     }
     hipEvent_t e = nullptr;
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    ++g_created;
     return e;
 }
 
 void resolve_all() {
-    for (auto &kv : g_stats) {
-        for (auto &p : kv.second.pending) {
-            float ms = 0.f;
-            if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
-                kv.second.total_ms += ms;
-                kv.second.launches += 1;
-            }
-            g_pool.push_back(p.a);
-            g_pool.push_back(p.b);
-        }
-        kv.second.pending.clear();
+    while (!g_pending.empty()) {
+        harvest(g_pending.front());
+        g_pending.pop_front();
     }
 }
 }  // namespace
@@ -55,7 +79,7 @@ void resolve_all() {
 bool prof_on() { return g_on; }
 
 struct Token {
-    std::string name;
+    KStat *stat;
     hipEvent_t a;
 };
 
@@ -64,7 +88,7 @@ void *prof_begin(const char *name, hipStream_t s) {
     hipEvent_t a = take_event();
     if (!a) return nullptr;
     hipEventRecord(a, s);
-    return new Token{name, a};
+    return new Token{&g_stats[name], a};
 }
 
 void prof_end(void *token, hipStream_t s) {
@@ -73,7 +97,7 @@ void prof_end(void *token, hipStream_t s) {
     hipEvent_t b = take_event();
     if (b) {
         hipEventRecord(b, s);
-        g_stats[t->name].pending.push_back({t->a, b});
+        g_pending.push_back({t->stat, t->a, b});
     } else {
         g_pool.push_back(t->a);
     }
@@ -94,6 +118,12 @@ extern "C" void bgv_profile_reset(void) {
     resolve_all();
     g_stats.clear();
     g_names.clear();
+    prof_reset_counters();
+}
+
+extern "C" int bgv_profile_counter(const char *name, uint64_t *value) {
+    if (!name || !value) return -1;
+    return prof_read_counter(name, value);
 }
 
 extern "C" int bgv_profile_count(void) {

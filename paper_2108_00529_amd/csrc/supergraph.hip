@@ -1,10 +1,11 @@
 // Count-min-sketch supergraph (Section 3.3 / Algorithm 2, Section 4.1, Algorithm 3).
 //   1. flag used labels, exclusive scan -> sid (supernodes numbered by ascending label)
 //   2. sketch 1: every node adds its degree at column h_r(label) of each row
-//   3. sketch 2: every inter-community edge adds 1 at g_r(min label, max label) and
-//      emits its packed (sid_lo, sid_hi) key
-//   4. LSD radix sort of the keys, unique -> superedges; weights = min over rows of
+//   3. every inter-community edge emits its packed (sid_lo, sid_hi) key
+//   4. LSD radix sort of the keys, unique -> superedges; sketch 2 gets each distinct
+//      pair's multiplicity at g_r(min label, max label); weights = min over rows of
 //      sketch 2; supernode sizes = min over rows of sketch 1
+#include "block_scan.h"
 #include "common.h"
 
 namespace bgv {
@@ -82,45 +83,47 @@ __global__ void k_sg_super_size(const int32_t *__restrict__ super_label, const u
     }
 }
 
-// Inter-community edges: emit the packed (sid_lo, sid_hi) key of each, appended
-// through one atomic per wave.  Sketch 2 is filled after the keys are sorted: each
+// Inter-community edges: emit the packed (sid_lo, sid_hi) key of each; a block
+// compacts its tile with a block scan and reserves output space with one atomic (the
+// order of tiles is arbitrary; the sort below makes the result deterministic).
+// Sketch 2 is filled after the keys are sorted: each
 // distinct key adds its multiplicity once (the same integer sums as one increment per
 // edge, without same-address contention on popular community pairs).
+constexpr int kKeyItems = 16;  // edges per thread; a block compacts kSgThreads*kKeyItems edges
 __global__ void __launch_bounds__(kSgThreads) k_sg_edge_keys(const int2 *__restrict__ edges, int64_t m,
                                                               const int32_t *__restrict__ labels,
                                                               const uint32_t *__restrict__ sid, int kbits,
                                                               uint64_t *__restrict__ keys,
                                                               unsigned long long *__restrict__ nkeys) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    // every lane of a wave runs the same number of iterations (ballots stay uniform)
-    const int64_t first = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~(kWave - 1));
-    for (int64_t i0 = first; i0 < m; i0 += stride) {
-        const int64_t i = i0 + lane;
-        bool inter = false;
-        uint32_t lo = 0, hi = 0;
+    __shared__ unsigned long long s_base;
+    const int64_t tile = (int64_t)blockIdx.x * (kSgThreads * kKeyItems);
+    uint64_t k[kKeyItems];
+    uint32_t flags = 0, cnt = 0;
+#pragma unroll
+    for (int j = 0; j < kKeyItems; ++j) {
+        const int64_t i = tile + (int64_t)j * kSgThreads + threadIdx.x;
+        k[j] = 0;
         if (i < m) {
             const int2 e = edges[i];
             if (e.x != e.y) {
                 const int32_t a = labels[e.x], b = labels[e.y];
                 if (a != b) {
-                    inter = true;
-                    lo = (uint32_t)min(a, b);
-                    hi = (uint32_t)max(a, b);
+                    const uint32_t lo = (uint32_t)min(a, b), hi = (uint32_t)max(a, b);
+                    k[j] = ((uint64_t)sid[lo] << kbits) | (uint64_t)sid[hi];
+                    flags |= 1u << j;
+                    ++cnt;
                 }
             }
         }
-        const uint64_t mask = __ballot(inter);
-        if (mask == 0) continue;
-        const int leader = __ffsll((unsigned long long)mask) - 1;
-        unsigned long long base = 0;
-        if (lane == leader) base = atomicAdd(nkeys, (unsigned long long)__popcll(mask));
-        base = __shfl(base, leader, kWave);
-        if (inter) {
-            const uint64_t below = lane ? (mask & (~0ull >> (64 - lane))) : 0ull;
-            keys[base + __popcll(below)] = ((uint64_t)sid[lo] << kbits) | (uint64_t)sid[hi];
-        }
     }
+    uint32_t total;
+    const uint32_t pre = block_excl_scan<uint32_t>(cnt, &total);
+    if (threadIdx.x == 0) s_base = total ? atomicAdd(nkeys, (unsigned long long)total) : 0ull;
+    __syncthreads();
+    unsigned long long at = s_base + pre;
+#pragma unroll
+    for (int j = 0; j < kKeyItems; ++j)
+        if ((flags >> j) & 1u) keys[at++] = k[j];
 }
 
 __global__ void k_sg_unique_flag(const uint64_t *__restrict__ keys, int64_t nk, uint32_t *__restrict__ flag) {
@@ -289,7 +292,7 @@ extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges,
     // inter-community keys, sorted and made unique, then sketch 2 and the weights
     unsigned long long *nkeys_d = reinterpret_cast<unsigned long long *>(&w.counters[2]);
     if (m > 0) {
-        BGV_LAUNCH(k_sg_edge_keys, dim3(grid_for(m, kSgThreads * 4, 16384)), dim3(kSgThreads), 0, s, e2, m, labels,
+        BGV_LAUNCH(k_sg_edge_keys, dim3((unsigned)((m + kSgThreads * kKeyItems - 1) / (kSgThreads * kKeyItems))), dim3(kSgThreads), 0, s, e2, m, labels,
                    w.sid, kbits, w.keys, nkeys_d);
     }
     unsigned long long nk = 0;

@@ -16,6 +16,16 @@ lib.bgv_profile_get.argtypes = [C.c_int, C.POINTER(C.c_char_p), C.POINTER(C.c_in
 lib.bgv_profile_get.restype = C.c_int
 
 
+lib.bgv_profile_counter.argtypes = [C.c_char_p, C.POINTER(C.c_uint64)]
+lib.bgv_profile_counter.restype = C.c_int
+
+
+def counter(name: str) -> int | None:
+    """A device work counter (e.g. "bh_interactions"), or None if unknown."""
+    v = C.c_uint64()
+    return int(v.value) if lib.bgv_profile_counter(name.encode(), C.byref(v)) == 0 else None
+
+
 def enable(on: bool = True) -> None:
     lib.bgv_profile_enable(1 if on else 0)
 

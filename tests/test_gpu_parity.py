@@ -350,3 +350,15 @@ def test_lfr_1m_community_supergraph_bh(bgv, lfr):
     pos0 = graphgen.initial_positions(ref["K"], wl["pos_seed"])
     F, F_ref, bad = bh_force_check(bgv, pos0, ref["superedges"], wl["theta"], "lfr_1m supergraph")
     assert bad.mean() <= 1e-3
+
+
+def test_supergraph_few_inter_edges_on_a_long_stream(bgv):
+    """Few inter-community keys (small sort) inside workspace sized for a long stream."""
+    rng = np.random.default_rng(21)
+    n, m = 200_000, 300_000
+    e = graphgen.random_tiny_graph(rng, n, m)
+    lab = np.zeros(n, np.int32)
+    lab[rng.choice(n, 300, replace=False)] = rng.integers(1, 50, 300)
+    deg = np.bincount(e.ravel(), minlength=n).astype(np.int32)
+    sg, ref = check_supergraph(bgv, n, e, lab, deg, 4, 1 << 12, 90)
+    assert 0 < len(ref["superedges"]) and int(ref["se_count"].sum()) < 65536
