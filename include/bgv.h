@@ -202,6 +202,39 @@ bgv_status bgv_fa2_grad(int32_t K, int64_t E, const int32_t *edges, const float 
                         const float *grad_out, float *grad,
                         void *ws, size_t ws_bytes, bgv_stream_t stream);
 
+/* ---------------------------------------------------------------------------- */
+/* Batched form: many independent graphs in one persistent launch                 */
+/* ---------------------------------------------------------------------------- */
+/*
+ * The whole path above (community passes, count-min supergraph, exact ForceAtlas2) for
+ * G graphs at once; graph g is processed by one workgroup from start to end, graphs are
+ * taken from a queue in `order` (e.g. largest first; NULL = 0..G-1).  Per graph the
+ * results equal those of bgv_community + bgv_supergraph + bgv_fa2_layout (exact
+ * repulsion, attraction weights 1, masses = degree + 1), with the same parameters.
+ *
+ * Graph g owns nodes [node_off[g], node_off[g+1]) and edges [edge_off[g], edge_off[g+1])
+ * of the concatenated arrays (node_off, edge_off: dev int64[G+1], non-decreasing,
+ * node_off[G] = n_total, edge_off[G] = m_total); its edges use local ids in
+ * [0, n_g).  Sketch shape: rows * cols <= 8192 (each graph's sketches live in LDS).
+ * fa->exact must be 1.  wg_threads: 256, 512 or 1024 (0 = 512), a launch parameter that
+ * does not change any result.
+ * Outputs (dev; per-node arrays indexed from node_off[g], per-edge arrays from
+ * edge_off[g]): labels, degree int32[n_total]; K, E_S int32[G]; super_label int32 and
+ * super_size uint32 [n_total] (first K[g] entries of each graph); superedges int32
+ * (m_total, 2) and se_weight uint32[m_total] (first E_S[g] of each graph).
+ * In/out: pos, fprev float (n_total, 2) -- each graph's first K[g] rows are the layout
+ * (initial positions in, final out; fprev zeros for a fresh start); speed float[G]
+ * (1.0 for a fresh start).
+ */
+size_t bgv_batched_workspace(int32_t G, int64_t n_total, int64_t m_total);
+bgv_status bgv_batched(int32_t G, int64_t n_total, int64_t m_total, const int64_t *node_off,
+                       const int64_t *edge_off, const int32_t *order, const int32_t *edges,
+                       const bgv_cd_params *cd, const bgv_sketch_params *sk, const bgv_fa2_params *fa,
+                       int32_t wg_threads, int32_t *labels, int32_t *degree, int32_t *K, int32_t *E_S,
+                       int32_t *super_label, uint32_t *super_size, int32_t *superedges,
+                       uint32_t *se_weight, float *pos, float *fprev, float *speed,
+                       void *ws, size_t ws_bytes, bgv_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

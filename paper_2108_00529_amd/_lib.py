@@ -20,7 +20,7 @@ class BgvError(RuntimeError):
 
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2108_00529_amd.build` "
+    raise ImportError(f"{LIB_PATH} is not built; run `python paper_2108_00529_amd/build.py` "
                       "(or __graft_entry__.build()) first")
 
 lib = C.CDLL(LIB_PATH, mode=C.RTLD_GLOBAL)
@@ -63,11 +63,15 @@ bgv_fa2_energy_workspace = _sig("bgv_fa2_energy_workspace", SZ, [i32, i64])
 bgv_fa2_energy = _sig("bgv_fa2_energy", i32, [i32, i64, P, P, P, P, f32, f32, P, P, SZ, P])
 bgv_fa2_grad = _sig("bgv_fa2_grad", i32, [i32, i64, P, P, P, P, f32, f32, P, P, P, SZ, P])
 
+bgv_batched_workspace = _sig("bgv_batched_workspace", SZ, [i32, i64, i64])
+bgv_batched = _sig("bgv_batched", i32, [i32, i64, i64, P, P, P, P, C.POINTER(CdParams), C.POINTER(SketchParams),
+                                        C.POINTER(Fa2Params), i32, P, P, P, P, P, P, P, P, P, P, P, P, SZ, P])
+
 EXPORTED = ["bgv_status_string", "bgv_last_error", "bgv_community_workspace", "bgv_community",
             "bgv_supergraph_workspace", "bgv_supergraph", "bgv_fa2_workspace", "bgv_fa2_layout",
             "bgv_fa2_energy_workspace", "bgv_fa2_energy", "bgv_fa2_grad",
             "bgv_profile_enable", "bgv_profile_reset", "bgv_profile_count", "bgv_profile_get",
-            "bgv_profile_counter"]
+            "bgv_profile_counter", "bgv_batched_workspace", "bgv_batched"]
 
 
 def check(status: int, what: str) -> None:

@@ -237,3 +237,73 @@ def pipeline(edges: torch.Tensor, n: int, wl: dict, coef1: np.ndarray, coef2: np
     pos, fprev, speed = fa2_layout(sg["superedges"], pos, wl["fa2_iters"], wl["exact"], wl["theta"], wl["kr"],
                                    wl["kg"], wl["tau"], wl["ks"], wl["ksmax"], stream=stream)
     return dict(labels=labels, degree=degree, volume=vol, sg=sg, pos=pos, fprev=fprev, speed=speed)
+
+
+# --------------------------------------------------------------------- batched --
+def pack_graphs(graphs, device):
+    """Concatenate [(n_g, edges_g (m_g,2) int32 numpy with local ids), ...] for
+    batched(): returns (edges (m_total,2) int32, node_off int64[G+1], edge_off int64[G+1]
+    on the device, and the host offsets)."""
+    ns = np.array([int(n) for n, _ in graphs], dtype=np.int64)
+    ms = np.array([int(np.asarray(e).reshape(-1, 2).shape[0]) for _, e in graphs], dtype=np.int64)
+    node_off = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+    edge_off = np.concatenate([[0], np.cumsum(ms)]).astype(np.int64)
+    parts = [np.asarray(e, dtype=np.int32).reshape(-1, 2) for _, e in graphs]
+    cat = np.concatenate(parts) if parts else np.zeros((0, 2), np.int32)
+    return (torch.from_numpy(np.ascontiguousarray(cat)).to(device), torch.from_numpy(node_off).to(device),
+            torch.from_numpy(edge_off).to(device), node_off, edge_off)
+
+
+def batched(edges: torch.Tensor, node_off: torch.Tensor, edge_off: torch.Tensor, n_total: int, wl: dict,
+            coef1: np.ndarray, coef2: np.ndarray, pos: torch.Tensor, order: torch.Tensor | None = None,
+            fprev: torch.Tensor | None = None, speed: torch.Tensor | None = None, wg_threads: int = 0,
+            ws: torch.Tensor | None = None, stream=None):
+    """The whole path for G graphs in one persistent launch (include/bgv.h,
+    bgv_batched).  pos (n_total, 2) float32 holds each graph's initial positions and is
+    updated in place.  Returns a dict of device tensors."""
+    G = node_off.shape[0] - 1
+    m_total = edges.shape[0]
+    dev = edges.device
+    _need(edges, torch.int32, "edges", (m_total, 2))
+    _need(node_off, torch.int64, "node_off", (G + 1,))
+    _need(edge_off, torch.int64, "edge_off", (G + 1,))
+    _need(pos, torch.float32, "pos", (n_total, 2))
+    if order is not None:
+        _need(order, torch.int32, "order", (G,))
+    if fprev is None:
+        fprev = torch.zeros((n_total, 2), dtype=torch.float32, device=dev)
+    if speed is None:
+        speed = torch.ones(G, dtype=torch.float32, device=dev)
+    _need(fprev, torch.float32, "fprev", (n_total, 2))
+    _need(speed, torch.float32, "speed", (G,))
+    rows, cols = int(wl["rows"]), int(wl["cols"])
+    c1 = np.ascontiguousarray(coef1, dtype=np.uint64).reshape(rows, 3)
+    c2 = np.ascontiguousarray(coef2, dtype=np.uint64).reshape(rows, 3)
+    cd = L.CdParams(int(wl["threshold"]), int(wl["passes"]), int(wl["growth"]), 0, int(wl["chunk"]))
+    sp = L.SketchParams(rows, cols, c1.ctypes.data_as(C.c_void_p), c2.ctypes.data_as(C.c_void_p))
+    fa = fa2_params(wl["fa2_iters"], True, wl.get("theta", 1.2), wl["kr"], wl["kg"], wl["tau"], wl["ks"],
+                    wl["ksmax"])
+    need = L.bgv_batched_workspace(int(G), int(n_total), int(m_total))
+    if need == 0:
+        raise L.BgvError(f"invalid batched arguments (G={G}, n_total={n_total}, m_total={m_total})")
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, dev)
+    nn, mm = max(n_total, 1), max(m_total, 1)
+    out = dict(labels=torch.empty(nn, dtype=torch.int32, device=dev),
+               degree=torch.empty(nn, dtype=torch.int32, device=dev),
+               K=torch.empty(G, dtype=torch.int32, device=dev), E=torch.empty(G, dtype=torch.int32, device=dev),
+               super_label=torch.empty(nn, dtype=torch.int32, device=dev),
+               super_size=torch.empty(nn, dtype=torch.int32, device=dev),
+               superedges=torch.empty((mm, 2), dtype=torch.int32, device=dev),
+               se_weight=torch.empty(mm, dtype=torch.int32, device=dev))
+    L.check(L.bgv_batched(int(G), int(n_total), int(m_total), _ptr(node_off), _ptr(edge_off), _ptr(order),
+                          _ptr(edges), C.byref(cd), C.byref(sp), C.byref(fa), int(wg_threads), _ptr(out["labels"]),
+                          _ptr(out["degree"]), _ptr(out["K"]), _ptr(out["E"]), _ptr(out["super_label"]),
+                          _ptr(out["super_size"]), _ptr(out["superedges"]), _ptr(out["se_weight"]), _ptr(pos),
+                          _ptr(fprev), _ptr(speed), _ptr(ws), ws.numel(), _stream(stream)), "bgv_batched")
+    out.update(pos=pos, fprev=fprev, speed=speed)
+    return out
+
+
+def batched_workspace(G: int, n_total: int, m_total: int, device) -> torch.Tensor:
+    return _workspace(L.bgv_batched_workspace(int(G), int(n_total), int(m_total)), device)

@@ -1,6 +1,6 @@
 """Build libbgv.so (the HIP kernels + C ABI) in-tree with hipcc for gfx950.
 
-    python -m paper_2108_00529_amd.build
+    python paper_2108_00529_amd/build.py
 """
 from __future__ import annotations
 
@@ -16,7 +16,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libbgv.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["primitives.hip", "profile.hip", "community.hip", "supergraph.hip", "fa2.hip", "energy.hip"]
+SOURCES = ["primitives.hip", "profile.hip", "community.hip", "supergraph.hip", "fa2.hip", "energy.hip",
+           "batched.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

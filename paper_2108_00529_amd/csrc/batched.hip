@@ -1,0 +1,533 @@
+// Batched form of the whole path: many independent graphs in one persistent launch.
+// Each workgroup pops graphs from a queue (in the caller's order, e.g. largest first)
+// and runs, with workgroup barriers only:
+//   community passes (Section 3.2 rule, batch-synchronous chunks as in community.hip)
+//   -> supernodes (ascending labels) -> sketch 1 in LDS -> inter-community keys ->
+//   workgroup LSD radix sort -> superedges, sketch 2 in LDS, weights -> directed CSR ->
+//   exact ForceAtlas2 iterations (Section 3.1 / Algorithm 1).
+// The layout reproduces the plain exact path operation for operation: repulsion summed
+// over j in order, the same per-row attraction wavefront, per-256-node partial sums of
+// swing and traction in the plain kernels' fixed order, the same speed and move
+// arithmetic (fa2_math.h).  Integer results equal the plain path's by construction.
+#include "block_scan.h"
+#include "common.h"
+#include "fa2_math.h"
+#include "sketch_hash.h"
+
+namespace bgv {
+
+constexpr int kBtMaxCells = 8192;  // rows*cols of a per-graph sketch, held in LDS
+
+struct BtArgs {
+    int32_t G;
+    const int64_t *node_off, *edge_off;  // device, G+1
+    const int32_t *order;                // device, G, or null for 0..G-1
+    const int2 *edges;                   // concatenated, local ids
+    int32_t threshold, passes, growth;
+    int64_t chunk;
+    int32_t rows;
+    uint32_t cols;
+    HashRows h1, h2;
+    int32_t iters;
+    float kr, kg, tau, ks, ksmax;
+    // outputs (per-node arrays at node_off, per-edge arrays at edge_off)
+    int32_t *labels, *degree, *K, *E, *super_label;
+    uint32_t *super_size;
+    int2 *superedges;
+    uint32_t *se_weight;
+    float2 *pos, *fprev;
+    float *speed;
+    // workspace
+    int32_t *cnt, *lab, *prop, *row_base;
+    unsigned long long *win;
+    uint32_t *sid, *row;
+    uint64_t *keyA, *keyB;  // 2 * m_total each
+    int2 *cw;               // 2 * m_total
+    float *mass;
+    float2 *F, *att;
+    double2 *vpart;         // floor(n_total/256) + G + 1
+    unsigned int *queue;
+};
+
+// Exclusive scan of in[0, n) into out (may alias); returns the total.
+template <int NT>
+__device__ uint32_t wg_scan(const uint32_t *in, uint32_t *out, int64_t n) {
+    uint32_t carry = 0;
+    for (int64_t t0 = 0; t0 < n; t0 += NT) {
+        const int64_t i = t0 + threadIdx.x;
+        const uint32_t v = i < n ? in[i] : 0u;
+        uint32_t tot;
+        const uint32_t e = block_excl_scan<uint32_t>(v, &tot);
+        if (i < n) out[i] = carry + e;
+        carry += tot;
+    }
+    return carry;
+}
+
+// Stable LSD radix sort of keys[0, n) on bits [0, nbits) by one workgroup (8-bit digits;
+// ranks within a round of NT keys from wavefront ballots).  Returns the buffer holding
+// the result (keys or alt).
+template <int NT>
+__device__ uint64_t *wg_radix_sort(uint64_t *keys, uint64_t *alt, int64_t n, int nbits, uint32_t *hist,
+                                   uint32_t *running, uint32_t (*wcnt)[256]) {
+    constexpr int NW = NT / kWave;
+    const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    uint64_t *src = keys, *dst = alt;
+    for (int shift = 0; shift < nbits; shift += 8) {
+        for (int d = t; d < 256; d += NT) hist[d] = 0;
+        __syncthreads();
+        for (int64_t i = t; i < n; i += NT) atomicAdd(&hist[(uint32_t)(src[i] >> shift) & 255u], 1u);
+        __syncthreads();
+        uint32_t tot;
+        const uint32_t e = block_excl_scan<uint32_t>(t < 256 ? hist[t] : 0u, &tot);
+        if (t < 256) running[t] = e;
+        for (int q = 0; q < NW; ++q)
+            for (int d = t; d < 256; d += NT) wcnt[q][d] = 0;
+        __syncthreads();
+        for (int64_t r0 = 0; r0 < n; r0 += NT) {
+            const int64_t i = r0 + t;
+            const bool valid = i < n;
+            const uint64_t key = valid ? src[i] : 0ull;
+            const uint32_t d = (uint32_t)(key >> shift) & 255u;
+            uint64_t match = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t bb = __ballot(bit);
+                match &= bit ? bb : ~bb;
+            }
+            const uint32_t rank = __popcll(match & lt);
+            if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(match);
+            __syncthreads();
+            if (valid) {
+                uint32_t p = running[d] + rank;
+                for (int q = 0; q < w; ++q) p += wcnt[q][d];
+                dst[p] = key;
+            }
+            __syncthreads();
+            for (int d2 = t; d2 < 256; d2 += NT) {
+                uint32_t add = 0;
+                for (int q = 0; q < NW; ++q) {
+                    add += wcnt[q][d2];
+                    wcnt[q][d2] = 0;
+                }
+                running[d2] += add;
+            }
+            __syncthreads();
+        }
+        uint64_t *tmp = src;
+        src = dst;
+        dst = tmp;
+    }
+    return src;
+}
+
+__device__ __forceinline__ int32_t bt_threshold(int32_t D1, int32_t growth, int32_t p) {
+    int64_t D = D1;
+    for (int32_t k = 0; k < p; ++k) {
+        D *= growth;
+        if (D > INT32_MAX) return INT32_MAX;
+    }
+    return (int32_t)D;
+}
+
+template <int NT>
+__global__ void __launch_bounds__(NT) k_batched(BtArgs a) {
+    constexpr int NW = NT / kWave;
+    constexpr int NV = NT / 256;  // 256-node groups handled side by side in the layout
+    static_assert(NT % 256 == 0 && NT <= 1024, "workgroup of 256, 512 or 1024 threads");
+    __shared__ uint32_t sk[kBtMaxCells];
+    __shared__ uint32_t hist[256], running[256];
+    __shared__ uint32_t wcnt[NW][256];
+    __shared__ float4 tile[NT];
+    __shared__ double2 ws[NW];
+    __shared__ int s_g;
+    __shared__ uint32_t s_count;
+    __shared__ float s_speed;
+    const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
+
+    for (;;) {
+        if (t == 0) s_g = (int)atomicAdd(a.queue, 1u);
+        __syncthreads();
+        const int qi = s_g;
+        __syncthreads();
+        if (qi >= a.G) break;
+        const int g = a.order ? a.order[qi] : qi;
+        const int64_t n0 = a.node_off[g], e0 = a.edge_off[g];
+        const int32_t n = (int32_t)(a.node_off[g + 1] - n0);
+        const int64_t m = a.edge_off[g + 1] - e0;
+        const int2 *edges = a.edges + e0;
+        int32_t *cnt = a.cnt + n0, *lab = a.lab + n0, *prop = a.prop + e0;
+        unsigned long long *win = a.win + n0;
+        uint32_t *sid = a.sid + n0;
+
+        // ---- community passes, chunk by chunk -------------------------------------
+        for (int32_t v = t; v < n; v += NT) {
+            cnt[v] = 0;
+            lab[v] = v;
+            win[v] = ~0ull;
+        }
+        __syncthreads();
+        for (int32_t pass = 0; pass < a.passes; ++pass) {
+            const int32_t D = bt_threshold(a.threshold, a.growth, pass);
+            for (int64_t cs = 0; cs < m; cs += a.chunk) {
+                const int64_t ce = cs + a.chunk < m ? cs + a.chunk : m;
+                for (int64_t i = cs + t; i < ce; i += NT) {
+                    const int2 e = edges[i];
+                    if (e.x != e.y) {
+                        __hip_atomic_fetch_add(&cnt[e.x], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        __hip_atomic_fetch_add(&cnt[e.y], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                }
+                __syncthreads();
+                for (int64_t i = cs + t; i < ce; i += NT) {
+                    const int2 e = edges[i];
+                    int32_t target = -1;
+                    if (e.x != e.y) {
+                        const int32_t du = cnt[e.x], dv = cnt[e.y];
+                        if (du <= D && dv <= D && du != dv) {
+                            const bool u_low = du < dv;
+                            target = u_low ? e.x : e.y;
+                            const int32_t l = u_low ? lab[e.y] : lab[e.x];
+                            __hip_atomic_fetch_min(&win[target], ((unsigned long long)i << 32) | (uint32_t)l,
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        }
+                    }
+                    prop[i] = target;
+                }
+                __syncthreads();
+                for (int64_t i = cs + t; i < ce; i += NT) {
+                    const int32_t x = prop[i];
+                    if (x >= 0) {
+                        const unsigned long long wv = win[x];
+                        if ((int64_t)(wv >> 32) == i) {
+                            lab[x] = (int32_t)(uint32_t)(wv & 0xffffffffull);
+                            win[x] = ~0ull;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int32_t v = t; v < n; v += NT) {
+            a.labels[n0 + v] = lab[v];
+            a.degree[n0 + v] = cnt[v] / a.passes;
+            sid[v] = 0u;
+        }
+        __syncthreads();
+
+        // ---- supernodes: distinct labels in ascending order ---------------------
+        for (int32_t v = t; v < n; v += NT) sid[lab[v]] = 1u;
+        __syncthreads();
+        uint32_t *flag = reinterpret_cast<uint32_t *>(win);  // free after the passes
+        for (int32_t v = t; v < n; v += NT) flag[v] = sid[v];
+        __syncthreads();
+        const uint32_t K = wg_scan<NT>(sid, sid, n);
+        int kb = 1;
+        while (kb < 31 && (1u << kb) < K) ++kb;
+        for (int32_t c = t; c < n; c += NT)
+            if (flag[c]) a.super_label[n0 + sid[c]] = c;
+        const int32_t cells = a.rows * (int32_t)a.cols;
+        for (int32_t c = t; c < cells; c += NT) sk[c] = 0u;
+        __syncthreads();
+
+        // ---- sketch 1: community weights ------------------------------------------
+        for (int32_t v = t; v < n; v += NT) {
+            const uint32_t d = (uint32_t)(cnt[v] / a.passes);
+            if (d == 0) continue;
+            const uint32_t l = (uint32_t)lab[v];
+            for (int r = 0; r < a.rows; ++r) atomicAdd(&sk[r * a.cols + col_key(a.h1.a[r], a.h1.b[r], l, a.cols)], d);
+        }
+        __syncthreads();
+        for (uint32_t k = t; k < K; k += NT) {
+            const uint32_t l = (uint32_t)a.super_label[n0 + k];
+            uint32_t best = 0xffffffffu;
+            for (int r = 0; r < a.rows; ++r) best = min(best, sk[r * a.cols + col_key(a.h1.a[r], a.h1.b[r], l, a.cols)]);
+            a.super_size[n0 + k] = best;
+        }
+        __syncthreads();  // every read of sketch 1 is done before it is cleared for sketch 2
+        if (t == 0) s_count = 0u;
+        for (int32_t c = t; c < cells; c += NT) sk[c] = 0u;
+        __syncthreads();
+
+        // ---- inter-community keys, sorted -----------------------------------------
+        uint64_t *keyA = a.keyA + 2 * e0, *keyB = a.keyB + 2 * e0;
+        for (int64_t i = t; i < m; i += NT) {
+            const int2 e = edges[i];
+            if (e.x == e.y) continue;
+            const int32_t la = lab[e.x], lb = lab[e.y];
+            if (la == lb) continue;
+            const uint32_t lo = (uint32_t)min(la, lb), hi = (uint32_t)max(la, lb);
+            const uint32_t at = atomicAdd(&s_count, 1u);
+            keyA[at] = ((uint64_t)sid[lo] << kb) | (uint64_t)sid[hi];
+        }
+        __syncthreads();
+        const uint32_t nk = s_count;
+        __syncthreads();
+        const uint64_t *sorted = wg_radix_sort<NT>(keyA, keyB, nk, 2 * kb, hist, running, wcnt);
+
+        // ---- superedges: distinct keys, multiplicities into sketch 2, weights -----
+        const uint64_t lowmask = (1ull << kb) - 1ull;
+        int2 *se = a.superedges + e0;
+        uint32_t *run = reinterpret_cast<uint32_t *>(prop);  // run starts; prop is free now
+        uint32_t E = 0;
+        for (int64_t t0 = 0; t0 < nk; t0 += NT) {
+            const int64_t i = t0 + t;
+            const bool first = i < nk && (i == 0 || sorted[i] != sorted[i - 1]);
+            uint32_t tot;
+            const uint32_t j = E + block_excl_scan<uint32_t>(first ? 1u : 0u, &tot);
+            if (first) {
+                const uint64_t k = sorted[i];
+                se[j] = make_int2((int32_t)(k >> kb), (int32_t)(k & lowmask));
+                run[j] = (uint32_t)i;
+            }
+            E += tot;
+        }
+        __syncthreads();
+        for (uint32_t j = t; j < E; j += NT) {
+            const uint32_t c = (j + 1 < E ? run[j + 1] : nk) - run[j];
+            const uint32_t la = (uint32_t)a.super_label[n0 + se[j].x], lb = (uint32_t)a.super_label[n0 + se[j].y];
+            for (int r = 0; r < a.rows; ++r)
+                atomicAdd(&sk[r * a.cols + col_pair(a.h2.a[r], a.h2.b[r], a.h2.c[r], la, lb, a.cols)], c);
+        }
+        __syncthreads();
+        for (uint32_t j = t; j < E; j += NT) {
+            const uint32_t la = (uint32_t)a.super_label[n0 + se[j].x], lb = (uint32_t)a.super_label[n0 + se[j].y];
+            uint32_t best = 0xffffffffu;
+            for (int r = 0; r < a.rows; ++r)
+                best = min(best, sk[r * a.cols + col_pair(a.h2.a[r], a.h2.b[r], a.h2.c[r], la, lb, a.cols)]);
+            a.se_weight[e0 + j] = best;
+        }
+        if (t == 0) {
+            a.K[g] = (int32_t)K;
+            a.E[g] = (int32_t)E;
+        }
+
+        // ---- directed CSR of the supergraph (neighbours ascending) ----------------
+        for (uint32_t j = t; j < E; j += NT) {
+            const int2 p = se[j];
+            keyA[2 * j] = ((uint64_t)(uint32_t)p.x << kb) | (uint32_t)p.y;
+            keyA[2 * j + 1] = ((uint64_t)(uint32_t)p.y << kb) | (uint32_t)p.x;
+        }
+        __syncthreads();
+        const uint64_t *dk = wg_radix_sort<NT>(keyA, keyB, 2 * (int64_t)E, 2 * kb, hist, running, wcnt);
+        uint32_t *row = a.row + n0 + g;
+        int2 *cw = a.cw + 2 * e0;
+        const int64_t nent = 2 * (int64_t)E;
+        for (int64_t k = t; k < nent; k += NT) {
+            const uint64_t key = dk[k];
+            const int64_t src = (int64_t)(key >> kb);
+            cw[k] = make_int2((int32_t)(key & lowmask), __float_as_int(1.0f));
+            const int64_t prev = k ? (int64_t)(dk[k - 1] >> kb) : -1;
+            for (int64_t r = prev + 1; r <= src; ++r) row[r] = (uint32_t)k;
+            if (k == nent - 1)
+                for (int64_t r = src + 1; r <= (int64_t)K; ++r) row[r] = (uint32_t)nent;
+        }
+        if (nent == 0)
+            for (uint32_t r = t; r <= K; r += NT) row[r] = 0u;
+        __syncthreads();
+        float *mass = a.mass + n0;
+        for (uint32_t i = t; i < K; i += NT) mass[i] = (float)(row[i + 1] - row[i]) + 1.0f;
+
+        // ---- exact ForceAtlas2 iterations -------------------------------------------
+        float2 *pos = a.pos + n0, *fprev = a.fprev + n0, *F = a.F + n0, *att = a.att + n0;
+        double2 *vpart = a.vpart + (n0 / 256) + g;
+        if (t == 0) s_speed = a.speed[g];
+        __syncthreads();
+        const int32_t nvb = (int32_t)((K + 255) / 256);
+        for (int32_t it = 0; it < a.iters; ++it) {
+            for (uint32_t i = w; i < K; i += NW) {
+                const float2 f = fa2_row_attraction(pos, cw, row[i], row[i + 1], pos[i], lane);
+                if (lane == 0) att[i] = f;
+            }
+            __syncthreads();
+            for (int32_t vb0 = 0; vb0 < nvb; vb0 += NV) {
+                const int32_t vb = vb0 + t / 256;
+                const uint32_t i = (uint32_t)vb * 256u + (uint32_t)(t & 255);
+                const bool live = vb < nvb && i < K;
+                const float2 xi = live ? pos[i] : make_float2(0.f, 0.f);
+                const float mi = live ? mass[i] : 0.f;
+                float rx = 0.f, ry = 0.f;
+                for (uint32_t j0 = 0; j0 < K; j0 += NT) {
+                    const uint32_t j = j0 + t;
+                    if (j < K) {
+                        const float2 xj = pos[j];
+                        tile[t] = make_float4(xj.x, xj.y, mass[j], 0.f);
+                    }
+                    __syncthreads();
+                    const uint32_t c = min((uint32_t)NT, K - j0);
+                    for (uint32_t q = 0; q < c; ++q) fa2_rep_term(xi, tile[q], rx, ry);
+                    __syncthreads();
+                }
+                double2 st = make_double2(0.0, 0.0);
+                if (live) {
+                    const float2 f = fa2_net_force(xi, mi, a.kr, rx, ry, att[i], a.kg);
+                    F[i] = f;
+                    st = fa2_swing_traction(f, fprev[i], mi);
+                }
+                st = fa2_sum256(st, ws);
+                if ((t & 255) == 0 && vb < nvb) vpart[vb] = st;
+            }
+            __syncthreads();
+            double2 acc = make_double2(0.0, 0.0);
+            if (t < 256)
+                for (int32_t p = t; p < nvb; p += 256) {
+                    acc.x += vpart[p].x;
+                    acc.y += vpart[p].y;
+                }
+            acc = fa2_sum256(acc, ws);
+            if (t == 0) s_speed = fa2_global_speed(acc.x, acc.y, s_speed, a.tau);
+            __syncthreads();
+            const float s = s_speed;
+            for (uint32_t i = t; i < K; i += NT) {
+                const float2 f = F[i];
+                pos[i] = fa2_move(pos[i], f, fprev[i], s, a.ks, a.ksmax);
+                fprev[i] = f;
+            }
+            __syncthreads();
+        }
+        if (t == 0) a.speed[g] = s_speed;
+        __syncthreads();
+    }
+}
+
+struct BtWs {
+    int32_t *cnt, *lab, *prop;
+    unsigned long long *win;
+    uint32_t *sid, *row;
+    uint64_t *keyA, *keyB;
+    int2 *cw;
+    float *mass;
+    float2 *F, *att;
+    double2 *vpart;
+    unsigned int *queue;
+};
+
+static size_t bt_layout(Carver &c, int32_t G, int64_t n_total, int64_t m_total, BtWs *w) {
+    const size_t n = (size_t)(n_total > 0 ? n_total : 1), m = (size_t)(m_total > 0 ? m_total : 1);
+    w->cnt = c.take<int32_t>(n);
+    w->lab = c.take<int32_t>(n);
+    w->win = c.take<unsigned long long>(n);
+    w->sid = c.take<uint32_t>(n);
+    w->prop = c.take<int32_t>(m);
+    w->keyA = c.take<uint64_t>(2 * m);
+    w->keyB = c.take<uint64_t>(2 * m);
+    w->cw = c.take<int2>(2 * m);
+    w->row = c.take<uint32_t>(n + (size_t)G);
+    w->mass = c.take<float>(n);
+    w->F = c.take<float2>(n);
+    w->att = c.take<float2>(n);
+    w->vpart = c.take<double2>(n / 256 + (size_t)G + 1);
+    w->queue = c.take<unsigned int>(1);
+    return c.size();
+}
+
+static bool bt_valid(int32_t G, int64_t n_total, int64_t m_total, const bgv_cd_params *cd,
+                     const bgv_sketch_params *sk, const bgv_fa2_params *fa) {
+    return G >= 1 && n_total >= 0 && n_total <= INT32_MAX && m_total >= 0 && m_total <= INT32_MAX && cd && sk &&
+           fa && cd->threshold >= 0 && cd->passes >= 1 && cd->growth >= 1 && cd->chunk >= 1 && cd->reserved == 0 &&
+           sk->rows >= 1 && sk->rows <= kMaxRows && sk->cols >= 1 && (int64_t)sk->rows * sk->cols <= kBtMaxCells &&
+           sk->coef1 && sk->coef2 && fa->iters >= 0 && fa->exact == 1 && fa->tau > 0.f && fa->ks >= 0.f &&
+           fa->ksmax > 0.f;
+}
+
+}  // namespace bgv
+
+using namespace bgv;
+
+extern "C" size_t bgv_batched_workspace(int32_t G, int64_t n_total, int64_t m_total) {
+    if (G < 1 || n_total < 0 || m_total < 0) return 0;
+    Carver c(nullptr);
+    BtWs w;
+    return bt_layout(c, G, n_total, m_total, &w);
+}
+
+extern "C" bgv_status bgv_batched(int32_t G, int64_t n_total, int64_t m_total, const int64_t *node_off,
+                                  const int64_t *edge_off, const int32_t *order, const int32_t *edges,
+                                  const bgv_cd_params *cd, const bgv_sketch_params *sk, const bgv_fa2_params *fa,
+                                  int32_t wg_threads, int32_t *labels, int32_t *degree, int32_t *K, int32_t *E_S,
+                                  int32_t *super_label, uint32_t *super_size, int32_t *superedges,
+                                  uint32_t *se_weight, float *pos, float *fprev, float *speed, void *ws,
+                                  size_t ws_bytes, bgv_stream_t stream) {
+    clear_error();
+    if (!bt_valid(G, n_total, m_total, cd, sk, fa)) {
+        set_error("bgv_batched: invalid arguments (G=%d n_total=%lld m_total=%lld)", G, (long long)n_total,
+                  (long long)m_total);
+        return BGV_E_INVALID;
+    }
+    if (wg_threads == 0) wg_threads = 512;
+    if (wg_threads != 256 && wg_threads != 512 && wg_threads != 1024) {
+        set_error("bgv_batched: wg_threads must be 0, 256, 512 or 1024 (got %d)", wg_threads);
+        return BGV_E_INVALID;
+    }
+    if (!node_off || !edge_off || (m_total > 0 && (!edges || !superedges || !se_weight)) || !labels || !degree ||
+        !K || !E_S || !super_label || !super_size || !pos || !fprev || !speed) {
+        set_error("bgv_batched: null pointer");
+        return BGV_E_INVALID;
+    }
+    BGV_TRY(check_ws(ws, ws_bytes, bgv_batched_workspace(G, n_total, m_total)));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    Carver c(ws);
+    BtWs w;
+    bt_layout(c, G, n_total, m_total, &w);
+
+    BtArgs a{};
+    a.G = G;
+    a.node_off = node_off;
+    a.edge_off = edge_off;
+    a.order = order;
+    a.edges = reinterpret_cast<const int2 *>(edges);
+    a.threshold = cd->threshold;
+    a.passes = cd->passes;
+    a.growth = cd->growth;
+    a.chunk = cd->chunk;
+    a.rows = sk->rows;
+    a.cols = (uint32_t)sk->cols;
+    a.h1 = make_hash_rows(sk->coef1, sk->rows);
+    a.h2 = make_hash_rows(sk->coef2, sk->rows);
+    a.iters = fa->iters;
+    a.kr = fa->kr;
+    a.kg = fa->kg;
+    a.tau = fa->tau;
+    a.ks = fa->ks;
+    a.ksmax = fa->ksmax;
+    a.labels = labels;
+    a.degree = degree;
+    a.K = K;
+    a.E = E_S;
+    a.super_label = super_label;
+    a.super_size = super_size;
+    a.superedges = reinterpret_cast<int2 *>(superedges);
+    a.se_weight = se_weight;
+    a.pos = reinterpret_cast<float2 *>(pos);
+    a.fprev = reinterpret_cast<float2 *>(fprev);
+    a.speed = speed;
+    a.cnt = w.cnt;
+    a.lab = w.lab;
+    a.prop = w.prop;
+    a.win = w.win;
+    a.sid = w.sid;
+    a.row = w.row;
+    a.keyA = w.keyA;
+    a.keyB = w.keyB;
+    a.cw = w.cw;
+    a.mass = w.mass;
+    a.F = w.F;
+    a.att = w.att;
+    a.vpart = w.vpart;
+    a.queue = w.queue;
+
+    int dev = 0, cus = 256;
+    BGV_CHECK_HIP(hipGetDevice(&dev));
+    BGV_CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int per_cu = wg_threads == 1024 ? 1 : 2;
+    const int grid = G < cus * per_cu ? G : cus * per_cu;
+    BGV_TRY(fill<uint32_t>(w.queue, 0u, 1, s));
+    switch (wg_threads) {
+        case 256: BGV_LAUNCH(k_batched<256>, dim3(grid), dim3(256), 0, s, a); break;
+        case 512: BGV_LAUNCH(k_batched<512>, dim3(grid), dim3(512), 0, s, a); break;
+        default: BGV_LAUNCH(k_batched<1024>, dim3(grid), dim3(1024), 0, s, a); break;
+    }
+    return BGV_OK;
+}

@@ -17,6 +17,7 @@
 #include "block_scan.h"
 #include "common.h"
 #include "fa2_internal.h"
+#include "fa2_math.h"
 
 namespace bgv {
 
@@ -130,35 +131,8 @@ __global__ void __launch_bounds__(kFaThreads) k_attract(int32_t K, const float2 
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t nw = (int64_t)gridDim.x * (kFaThreads / kWave);
     for (int64_t i = (blockIdx.x * (int64_t)kFaThreads + threadIdx.x) / kWave; i < K; i += nw) {
-        const float2 xi = pos[i];
-        float ax = 0.f, ay = 0.f;
-        const uint32_t r1 = row[i + 1];
-        uint32_t k = row[i] + lane;
-        // four entries per lane in flight, then the remainder
-        for (; k + 3 * kWave < r1; k += 4 * kWave) {
-            const int2 e0 = cw[k], e1 = cw[k + kWave], e2 = cw[k + 2 * kWave], e3 = cw[k + 3 * kWave];
-            const float2 x0 = pos[e0.x], x1 = pos[e1.x], x2 = pos[e2.x], x3 = pos[e3.x];
-            ax += __int_as_float(e0.y) * (x0.x - xi.x);
-            ay += __int_as_float(e0.y) * (x0.y - xi.y);
-            ax += __int_as_float(e1.y) * (x1.x - xi.x);
-            ay += __int_as_float(e1.y) * (x1.y - xi.y);
-            ax += __int_as_float(e2.y) * (x2.x - xi.x);
-            ay += __int_as_float(e2.y) * (x2.y - xi.y);
-            ax += __int_as_float(e3.y) * (x3.x - xi.x);
-            ay += __int_as_float(e3.y) * (x3.y - xi.y);
-        }
-        for (; k < r1; k += kWave) {
-            const int2 e = cw[k];
-            const float2 xj = pos[e.x];
-            ax += __int_as_float(e.y) * (xj.x - xi.x);
-            ay += __int_as_float(e.y) * (xj.y - xi.y);
-        }
-#pragma unroll
-        for (int o = kWave / 2; o > 0; o >>= 1) {
-            ax += __shfl_xor(ax, o, kWave);
-            ay += __shfl_xor(ay, o, kWave);
-        }
-        if (lane == 0) A[i] = make_float2(ax, ay);
+        const float2 a = fa2_row_attraction(pos, cw, row[i], row[i + 1], pos[i], lane);
+        if (lane == 0) A[i] = a;
     }
 }
 
@@ -168,26 +142,6 @@ bgv_status attraction(int32_t K, const float2 *pos, const CsrWs &csr, float2 *A,
     return BGV_OK;
 }
 
-// Repulsion + precomputed attraction + gravity of node i.
-__device__ __forceinline__ float2 attract_gravity(float2 xi, float mi, float2 frep, float2 att, float kg) {
-    float fx = frep.x + att.x, fy = frep.y + att.y;
-    const float r = sqrtf(xi.x * xi.x + xi.y * xi.y);
-    if (r > 0.f) {
-        const float g = kg * mi / r;
-        fx -= g * xi.x;
-        fy -= g * xi.y;
-    }
-    return make_float2(fx, fy);
-}
-
-__device__ __forceinline__ double2 swing_traction(float2 F, float2 Fp, float mi) {
-    const float sx = F.x - Fp.x, sy = F.y - Fp.y;
-    const float tx = F.x + Fp.x, ty = F.y + Fp.y;
-    const float sw = sqrtf(sx * sx + sy * sy);
-    const float tr = 0.5f * sqrtf(tx * tx + ty * ty);
-    return make_double2((double)mi * (double)sw, (double)mi * (double)tr);
-}
-
 // ------------------------------------------------------------------ exact ------
 __global__ void __launch_bounds__(kFaThreads) k_force_exact(int32_t K, const float2 *__restrict__ pos,
                                                              const float *__restrict__ mass,
@@ -195,6 +149,7 @@ __global__ void __launch_bounds__(kFaThreads) k_force_exact(int32_t K, const flo
                                                              const float2 *__restrict__ fprev, float2 *__restrict__ F,
                                                              double2 *__restrict__ part) {
     __shared__ float4 tile[kFaThreads];
+    __shared__ double2 ws[kFaThreads / kWave];
     const int32_t i = blockIdx.x * kFaThreads + threadIdx.x;
     const bool live = i < K;
     const float2 xi = live ? pos[i] : make_float2(0.f, 0.f);
@@ -208,26 +163,16 @@ __global__ void __launch_bounds__(kFaThreads) k_force_exact(int32_t K, const flo
         }
         __syncthreads();
         const int cnt = min(kFaThreads, K - t0);
-        for (int q = 0; q < cnt; ++q) {
-            const float4 p = tile[q];
-            const float dx = xi.x - p.x, dy = xi.y - p.y;
-            const float d2 = dx * dx + dy * dy;
-            if (d2 > 0.f) {
-                const float f = p.z / d2;
-                fx += f * dx;
-                fy += f * dy;
-            }
-        }
+        for (int q = 0; q < cnt; ++q) fa2_rep_term(xi, tile[q], fx, fy);
         __syncthreads();
     }
     double2 st = make_double2(0.0, 0.0);
     if (live) {
-        const float c = kr * mi;
-        const float2 f = attract_gravity(xi, mi, make_float2(c * fx, c * fy), att[i], kg);
+        const float2 f = fa2_net_force(xi, mi, kr, fx, fy, att[i], kg);
         F[i] = f;
-        st = swing_traction(f, fprev[i], mi);
+        st = fa2_swing_traction(f, fprev[i], mi);
     }
-    st = block_sum2(st);
+    st = fa2_sum256(st, ws);
     if (threadIdx.x == 0) part[blockIdx.x] = st;
 }
 
@@ -272,16 +217,15 @@ __global__ void __launch_bounds__(kFaThreads) k_update(int32_t K, float2 *__rest
                                                         float *__restrict__ speed_out, float tau, float ks,
                                                         float ksmax, float4 *__restrict__ bbox_part) {
     __shared__ float s_speed;
+    __shared__ double2 ws[kFaThreads / kWave];
     double2 acc = make_double2(0.0, 0.0);
     for (int p = threadIdx.x; p < nparts; p += kFaThreads) {
         acc.x += part[p].x;
         acc.y += part[p].y;
     }
-    acc = block_sum2(acc);
+    acc = fa2_sum256(acc, ws);
     if (threadIdx.x == 0) {
-        const float sp = *speed_in;
-        float s = sp;
-        if (acc.x > 0.0) s = (float)fmin((double)tau * acc.y / acc.x, 1.5 * (double)sp);
+        const float s = fa2_global_speed(acc.x, acc.y, *speed_in, tau);
         s_speed = s;
         if (blockIdx.x == 0) *speed_out = s;
     }
@@ -289,15 +233,8 @@ __global__ void __launch_bounds__(kFaThreads) k_update(int32_t K, float2 *__rest
     const float s = s_speed;
     float4 bb = make_float4(kInf, -kInf, kInf, -kInf);
     for (int32_t i = blockIdx.x * kFaThreads + threadIdx.x; i < K; i += gridDim.x * kFaThreads) {
-        const float2 f = F[i], fp = fprev[i];
-        const float sx = f.x - fp.x, sy = f.y - fp.y;
-        const float sw = sqrtf(sx * sx + sy * sy);
-        float si = ks * s / (1.0f + s * sqrtf(sw));
-        const float fn = sqrtf(f.x * f.x + f.y * f.y);
-        if (fn > 0.f && si > ksmax / fn) si = ksmax / fn;
-        float2 p = pos[i];
-        p.x += si * f.x;
-        p.y += si * f.y;
+        const float2 f = F[i];
+        const float2 p = fa2_move(pos[i], f, fprev[i], s, ks, ksmax);
         pos[i] = p;
         fprev[i] = f;
         bb = make_float4(fminf(bb.x, p.x), fmaxf(bb.y, p.x), fminf(bb.z, p.y), fmaxf(bb.w, p.y));
@@ -486,13 +423,7 @@ __global__ void k_bh_build(int32_t K, const uint32_t *__restrict__ code, const d
 
 __device__ __forceinline__ void add_pair(float2 xi, float4 bj, float &fx, float &fy, uint32_t &ic) {
     ++ic;
-    const float dx = xi.x - bj.x, dy = xi.y - bj.y;
-    const float d2 = dx * dx + dy * dy;
-    if (d2 > 0.f) {
-        const float f = bj.z / d2;
-        fx += f * dx;
-        fy += f * dy;
-    }
+    fa2_rep_term(xi, bj, fx, fy);
 }
 
 // Barnes-Hut repulsion.  Bodies are taken in Morton order (neighbouring bodies walk
@@ -623,10 +554,9 @@ __global__ void __launch_bounds__(kBhThreads) k_bh_force(int32_t K, const float4
         const float2 xi = make_float2(me.x, me.y);
         const float mi = me.z;
         const int32_t b = __float_as_int(me.w);
-        const float c = kr * mi;
-        const float2 f = attract_gravity(xi, mi, make_float2(c * fx, c * fy), att[b], kg);
+        const float2 f = fa2_net_force(xi, mi, kr, fx, fy, att[b], kg);
         F[b] = f;
-        st = swing_traction(f, fprev[b], mi);
+        st = fa2_swing_traction(f, fprev[b], mi);
     }
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) ic += __shfl_xor(ic, o, kWave);

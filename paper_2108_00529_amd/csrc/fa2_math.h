@@ -1,0 +1,120 @@
+// ForceAtlas2 per-pair and per-node arithmetic shared by the plain and batched layout
+// kernels, so that both evaluate every force and speed with the same operation
+// sequence (Section 3.1 / Algorithm 1, in the force and speed laws of the cited
+// ForceAtlas2 publication).
+#pragma once
+#include "common.h"
+
+namespace bgv {
+
+// Repulsion from one body p = (x, y, mass): (x_i - x_j) * m_j / |x_i - x_j|^2, none if
+// coincident.  The caller scales the sum by kr * m_i.
+__device__ __forceinline__ void fa2_rep_term(float2 xi, float4 p, float &fx, float &fy) {
+    const float dx = xi.x - p.x, dy = xi.y - p.y;
+    const float d2 = dx * dx + dy * dy;
+    if (d2 > 0.f) {
+        const float f = p.z / d2;
+        fx += f * dx;
+        fy += f * dy;
+    }
+}
+
+// Attraction on node i = sum over its CSR entries [r0, r1) of w * (x_j - x_i), by one
+// wavefront: lane l takes entries r0 + l, r0 + l + 64, ... (four loads in flight), then a
+// fixed butterfly combines the lanes; every lane returns the total.
+__device__ __forceinline__ float2 fa2_row_attraction(const float2 *__restrict__ pos, const int2 *__restrict__ cw,
+                                                     uint32_t r0, uint32_t r1, float2 xi, int lane) {
+    float ax = 0.f, ay = 0.f;
+    uint32_t k = r0 + lane;
+    for (; k + 3 * kWave < r1; k += 4 * kWave) {
+        const int2 e0 = cw[k], e1 = cw[k + kWave], e2 = cw[k + 2 * kWave], e3 = cw[k + 3 * kWave];
+        const float2 x0 = pos[e0.x], x1 = pos[e1.x], x2 = pos[e2.x], x3 = pos[e3.x];
+        ax += __int_as_float(e0.y) * (x0.x - xi.x);
+        ay += __int_as_float(e0.y) * (x0.y - xi.y);
+        ax += __int_as_float(e1.y) * (x1.x - xi.x);
+        ay += __int_as_float(e1.y) * (x1.y - xi.y);
+        ax += __int_as_float(e2.y) * (x2.x - xi.x);
+        ay += __int_as_float(e2.y) * (x2.y - xi.y);
+        ax += __int_as_float(e3.y) * (x3.x - xi.x);
+        ay += __int_as_float(e3.y) * (x3.y - xi.y);
+    }
+    for (; k < r1; k += kWave) {
+        const int2 e = cw[k];
+        const float2 xj = pos[e.x];
+        ax += __int_as_float(e.y) * (xj.x - xi.x);
+        ay += __int_as_float(e.y) * (xj.y - xi.y);
+    }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        ax += __shfl_xor(ax, o, kWave);
+        ay += __shfl_xor(ay, o, kWave);
+    }
+    return make_float2(ax, ay);
+}
+
+// Fixed-pattern sum of one double2 per thread over a group of 256 threads (4
+// wavefronts): shuffle-down within each wavefront, then the 4 wavefront sums in order.
+// ws must hold blockDim/64 entries; the result is valid in the group's first thread.
+// Contains a barrier: every thread of the workgroup must call it.
+__device__ __forceinline__ double2 fa2_sum256(double2 v, double2 *ws) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        v.x += __shfl_down(v.x, o, kWave);
+        v.y += __shfl_down(v.y, o, kWave);
+    }
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    if (lane == 0) ws[w] = v;
+    __syncthreads();
+    double2 r = make_double2(0.0, 0.0);
+    if ((threadIdx.x & 255) == 0)
+        for (int q = 0; q < 4; ++q) {
+            r.x += ws[w + q].x;
+            r.y += ws[w + q].y;
+        }
+    __syncthreads();
+    return r;
+}
+
+// Net force: repulsion kr*m_i*sum + attraction + gravity (-kg m_i x / |x|, none at 0).
+__device__ __forceinline__ float2 fa2_net_force(float2 xi, float mi, float kr, float rx, float ry, float2 att,
+                                                float kg) {
+    const float c = kr * mi;
+    float fx = c * rx + att.x, fy = c * ry + att.y;
+    const float r = sqrtf(xi.x * xi.x + xi.y * xi.y);
+    if (r > 0.f) {
+        const float g = kg * mi / r;
+        fx -= g * xi.x;
+        fy -= g * xi.y;
+    }
+    return make_float2(fx, fy);
+}
+
+// (m_i * swing_i, m_i * traction_i) with swing = |F - F'|, traction = |F + F'| / 2.
+__device__ __forceinline__ double2 fa2_swing_traction(float2 F, float2 Fp, float mi) {
+    const float sx = F.x - Fp.x, sy = F.y - Fp.y;
+    const float tx = F.x + Fp.x, ty = F.y + Fp.y;
+    const float sw = sqrtf(sx * sx + sy * sy);
+    const float tr = 0.5f * sqrtf(tx * tx + ty * ty);
+    return make_double2((double)mi * (double)sw, (double)mi * (double)tr);
+}
+
+// Global speed from the swing and traction sums: min(tau T / S, 1.5 s), kept if S = 0.
+__device__ __forceinline__ float fa2_global_speed(double S, double T, float sp, float tau) {
+    float s = sp;
+    if (S > 0.0) s = (float)fmin((double)tau * T / S, 1.5 * (double)sp);
+    return s;
+}
+
+// Local speed ks s / (1 + s sqrt(swing)), capped so the step is at most ksmax; moves p.
+__device__ __forceinline__ float2 fa2_move(float2 p, float2 f, float2 fp, float s, float ks, float ksmax) {
+    const float sx = f.x - fp.x, sy = f.y - fp.y;
+    const float sw = sqrtf(sx * sx + sy * sy);
+    float si = ks * s / (1.0f + s * sqrtf(sw));
+    const float fn = sqrtf(f.x * f.x + f.y * f.y);
+    if (fn > 0.f && si > ksmax / fn) si = ksmax / fn;
+    p.x += si * f.x;
+    p.y += si * f.y;
+    return p;
+}
+
+}  // namespace bgv

@@ -7,25 +7,11 @@
 //      sketch 2; supernode sizes = min over rows of sketch 1
 #include "block_scan.h"
 #include "common.h"
+#include "sketch_hash.h"
 
 namespace bgv {
 
 constexpr int kSgThreads = 256;
-constexpr int kMaxRows = 8;
-
-struct HashRows {
-    uint64_t a[kMaxRows], b[kMaxRows], c[kMaxRows];
-};
-
-__device__ __forceinline__ uint32_t col_key(uint64_t A, uint64_t B, uint32_t x, uint32_t cols) {
-    const uint64_t t = A * (uint64_t)x + B;
-    return (uint32_t)(((t >> 32) * (uint64_t)cols) >> 32);
-}
-__device__ __forceinline__ uint32_t col_pair(uint64_t A, uint64_t B, uint64_t C, uint32_t lo, uint32_t hi,
-                                             uint32_t cols) {
-    const uint64_t t = A * (uint64_t)lo + C * (uint64_t)hi + B;
-    return (uint32_t)(((t >> 32) * (uint64_t)cols) >> 32);
-}
 
 __global__ void k_sg_flag(const int32_t *__restrict__ labels, int32_t n, uint32_t *__restrict__ flag) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
@@ -210,15 +196,6 @@ static bool sg_valid(int32_t n, int64_t m, const bgv_sketch_params *s) {
            s->coef1 && s->coef2;
 }
 
-static HashRows make_rows(const uint64_t *coef, int rows) {
-    HashRows h{};
-    for (int r = 0; r < rows; ++r) {
-        h.a[r] = coef[3 * r];
-        h.b[r] = coef[3 * r + 1];
-        h.c[r] = coef[3 * r + 2];
-    }
-    return h;
-}
 
 }  // namespace bgv
 
@@ -254,7 +231,7 @@ extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges,
     sg_layout(c, n, m, &w);
     const int rows = sp->rows;
     const uint32_t cols = (uint32_t)sp->cols;
-    const HashRows h1 = make_rows(sp->coef1, rows), h2 = make_rows(sp->coef2, rows);
+    const HashRows h1 = make_hash_rows(sp->coef1, rows), h2 = make_hash_rows(sp->coef2, rows);
     const int2 *e2 = reinterpret_cast<const int2 *>(edges);
     const unsigned gn = grid_for(n, kSgThreads, 65536);
 
