@@ -37,6 +37,7 @@ def parse():
     ap.add_argument("--workload", default="lfr_1m")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-fa2-iters", type=int, default=20)
+    ap.add_argument("--no-forms", action="store_true", help="skip the batched and gradient comparisons")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="do not bracket launches with HIP events (for hardware-counter runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -112,8 +113,25 @@ def main():
     torch.cuda.synchronize()
     print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
 
+    # one untimed step with every kernel bracketed by events: the per-kernel breakdown,
+    # and which kernel dominates the device time
+    kbreak = {}
+    dominant = None
+    if not args.no_kernel_timing:
+        prof.reset()
+        prof.only(None)
+        prof.enable(True)
+        step()
+        torch.cuda.synchronize()
+        prof.enable(False)
+        kbreak = prof.stats()
+        dominant = max(kbreak.items(), key=lambda kv: kv[1]["total_ms"])[0] if kbreak else None
+        print(f"[bench] breakdown step done; dominant kernel {dominant}", file=sys.stderr, flush=True)
+
+    # timed steps: events only around the dominant kernel, so the rest runs unbracketed
     prof.reset()
-    prof.enable(not args.no_kernel_timing)
+    prof.only(dominant)
+    prof.enable(dominant is not None)
     cd_ms, fa_ms = [], []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -125,6 +143,7 @@ def main():
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     prof.enable(False)
+    prof.only(None)
     kstats = prof.stats()
     inter = prof.counter("bh_interactions")
     for k in kstats:
@@ -138,7 +157,7 @@ def main():
     K, E = sg["K"], sg["E"]
     value = m / (cd / 1000.0)
 
-    roofline, extra = roofline_report(kstats, wl, n, m, K, E)
+    roofline, extra = roofline_report(kstats, kbreak, wl, n, m, K, E)
 
     out = {
         "metric": "edges/s through community pass+sketch; FA2 iters/s; batched/grad vs plain",
@@ -166,7 +185,145 @@ def main():
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(edges_np, n, wl, c1, c2, pos0_np, args.cpu_fa2_iters)
+    if not args.no_forms:
+        del edges, pos0
+        torch.cuda.empty_cache()
+        out["forms"] = {"batched": batched_form(torch, bgv, graphgen),
+                        "gradient": gradient_form(torch, bgv, graphgen)}
     print(json.dumps(out))
+
+
+def _timed(torch, fn, repeats=1):
+    """Best device time (ms) of fn() over `repeats` runs, HIP events on the current stream."""
+    best = float("inf")
+    for _ in range(repeats):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b))
+    return best
+
+
+def batched_form(torch, bgv, graphgen):
+    """512 uneven planted graphs: one batched launch (eager and replayed from a captured
+    graph) against 512 sequential plain pipelines, same outputs."""
+    from paper_2108_00529_amd import autotune
+    wl = graphgen.WORKLOADS["batched_512"]
+    t0 = time.time()
+    graphs = graphgen.batched_planted(wl["G"], wl["graph_seed"])
+    G = len(graphs)
+    c1 = graphgen.hash_coeffs(wl["rows"], wl["sketch_seed"])
+    c2 = graphgen.hash_coeffs(wl["rows"], wl["sketch_seed"] ^ 0x9E3779B97F4A7C15)
+    pos0 = [graphgen.initial_positions(n, wl["pos_seed"] + g) for g, (n, _, _) in enumerate(graphs)]
+    dev = torch.device("cuda:0")
+    edges, noff, eoff, noff_h, eoff_h = bgv.pack_graphs([(n, e) for n, e, _ in graphs], dev)
+    n_total, m_total = int(noff_h[-1]), int(eoff_h[-1])
+    print(f"[bench] batched: {G} graphs, {n_total} nodes, {m_total} edges generated in {time.time() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    order = torch.from_numpy(np.argsort(-np.diff(eoff_h), kind="stable").astype(np.int32)).to(dev)
+    pos_init = torch.from_numpy(np.concatenate(pos0)).to(dev)
+    wg, tune = autotune.tune_batched(edges, noff, eoff, n_total, wl, c1, c2, pos_init, order=order, repeats=1,
+                                     use_cache=False)
+    ws = bgv.batched_workspace(G, n_total, m_total, dev)
+    pos = pos_init.clone()
+    fprev = torch.zeros_like(pos)
+    speed = torch.ones(G, dtype=torch.float32, device=dev)
+
+    def run_batched():
+        pos.copy_(pos_init)
+        fprev.zero_()
+        speed.fill_(1.0)
+        return bgv.batched(edges, noff, eoff, n_total, wl, c1, c2, pos, order=order, fprev=fprev, speed=speed,
+                           wg_threads=wg, ws=ws)
+
+    run_batched()
+    eager_ms = _timed(torch, run_batched, repeats=3)
+    # capture the whole batched launch once, replay it
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        run_batched()
+    torch.cuda.current_stream().wait_stream(side)
+    with torch.cuda.graph(graph):
+        res = run_batched()
+    graph.replay()
+    torch.cuda.synchronize()
+    graph_ms = _timed(torch, graph.replay, repeats=3)
+    K_b = res["K"].cpu().numpy()
+    # the same graphs one by one through the plain entry points
+    pos0_d = [torch.from_numpy(p).to(dev) for p in pos0]
+    edges_g = [torch.from_numpy(e).to(dev) for _, e, _ in graphs]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    K_p = []
+    for g, (n, _, _) in enumerate(graphs):
+        o = bgv.pipeline(edges_g[g], n, wl, c1, c2, pos0_d[g])
+        K_p.append(o["sg"]["K"])
+    torch.cuda.synchronize()
+    seq_ms = 1000.0 * (time.perf_counter() - t)
+    return {"graphs": G, "nodes": n_total, "edges": m_total, "wg_threads": wg, "autotune_ms": tune["ms"],
+            "batched_ms": eager_ms, "batched_graph_replay_ms": graph_ms, "sequential_plain_ms": seq_ms,
+            "speedup_vs_sequential": seq_ms / min(eager_ms, graph_ms),
+            "graphs_per_s": G / (min(eager_ms, graph_ms) / 1000.0),
+            "supernodes_equal": bool(np.array_equal(K_b, np.array(K_p)))}
+
+
+def gradient_form(torch, bgv, graphgen, fa2_iters=500, lrs=(1.0, 3.0, 10.0), max_steps=3000):
+    """Weighted supergraph of ~50k supernodes (planted communities of 100 nodes of a
+    5M-node LFR-style graph; superedge weights from a 5 x 2^22 sketch): exact FA2 with
+    its adaptive speeds for `fa2_iters` iterations vs Adam on the FA2 energy (autograd
+    function with the hand-written gradient) until it reaches the same energy."""
+    t0 = time.time()
+    n, m = 5_000_000, 25_000_000
+    e, comm = graphgen.lfr_style(n, m, gamma=2.3, beta=1.5, mu=0.04, seed=1005, smin=100, smax=100)
+    print(f"[bench] gradient form: source graph generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    ed = torch.from_numpy(e).to(dev)
+    del e
+    lab = torch.from_numpy(comm).to(dev)
+    _, degree, _ = bgv.community(ed, n, 0, 1, 2, 1 << 22)  # threshold 0: degrees only
+    c1 = graphgen.hash_coeffs(5, 0xB16A0005)
+    c2 = graphgen.hash_coeffs(5, 0xB16A0005 ^ 0x9E3779B97F4A7C15)
+    sg = bgv.supergraph(ed, lab, degree, 5, 1 << 22, c1, c2)
+    del ed, lab, degree
+    torch.cuda.empty_cache()
+    K, E = sg["K"], sg["E"]
+    se = sg["superedges"].contiguous()
+    w = sg["se_weight"].to(torch.float32).contiguous()
+    pos0 = torch.from_numpy(graphgen.initial_positions(K, 2005, -50.0, 50.0)).to(dev)
+    p = pos0.clone()
+    ms_fa2 = _timed(torch, lambda: bgv.fa2_layout(se, p, fa2_iters, exact=True, attr_w=w))
+    e_fa2 = float(bgv.fa2_energy(se, p, attr_w=w))
+    e_start = float(bgv.fa2_energy(se, pos0, attr_w=w))
+    adam = {}
+    for lr in lrs:
+        x = pos0.clone().requires_grad_(True)
+        opt = torch.optim.Adam([x], lr=lr)
+        steps, reached, energy = 0, False, e_start
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        while steps < max_steps:
+            opt.zero_grad(set_to_none=True)
+            en = bgv.FA2Energy.apply(x, se, 1.0, 1.0, w, None)
+            en.backward()
+            opt.step()
+            steps += 1
+            if steps % 25 == 0:
+                energy = float(en.detach())
+                if energy <= e_fa2:
+                    reached = True
+                    break
+        torch.cuda.synchronize()
+        adam[str(lr)] = {"steps": steps, "ms": 1000.0 * (time.perf_counter() - t), "reached_fa2_energy": reached,
+                         "energy": energy}
+    ok = [v for v in adam.values() if v["reached_fa2_energy"]]
+    return {"supernodes": K, "superedges": E, "fa2_iterations": fa2_iters, "fa2_ms": ms_fa2,
+            "energy_start": e_start, "energy_fa2": e_fa2, "adam": adam,
+            "adam_best_ms_to_fa2_energy": min(v["ms"] for v in ok) if ok else None}
 
 
 # algorithmic bytes / flops per unit (see DESIGN.md)
@@ -174,29 +331,32 @@ EDGE_PASS_BYTES = 8            # one int32 (u,v) pair read per edge per pass
 BH_INTERACTION_FLOPS = 20      # body-node or body-body interaction, n-body convention
 
 
-def roofline_report(kstats, wl, n, m, K, E):
-    """Roofline of the dominant kernel (by total time) plus the edge-stream kernels."""
+def roofline_report(kstats, kbreak, wl, n, m, K, E):
+    """Roofline of the dominant kernel, from the events recorded around it in the timed
+    steps (kstats), plus the per-kernel breakdown of one untimed fully bracketed step
+    (kbreak) and the edge-stream kernels' rates from it."""
     if not kstats:
         return None, {}
-    by_time = sorted(kstats.items(), key=lambda kv: -kv[1]["total_ms"])
-    extra = {"kernel_ms": {k: round(v["total_ms"] / max(v["launches"], 1), 5) for k, v in by_time}}
+    extra = {"kernel_ms_breakdown_step": {k: {"launches": v["launches"], "avg_ms": round(v["total_ms"] / max(v["launches"], 1), 5),
+                                              "total_ms": round(v["total_ms"], 4)}
+                                          for k, v in sorted(kbreak.items(), key=lambda kv: -kv[1]["total_ms"])}}
     rows = {}
-    for name, st in kstats.items():
+    for name, st in kbreak.items():
         avg_s = st["total_ms"] / 1000.0 / max(st["launches"], 1)
         if name in ("cd_apply_hist", "cd_decide"):
             per_launch = EDGE_PASS_BYTES * wl["chunk"]
             rows[name] = dict(bound="hbm", achieved=per_launch / avg_s / 1e9, peak=HBM_PEAK_GBS, unit="GB/s")
-    top, st = by_time[0]
+    top, st = max(kstats.items(), key=lambda kv: kv[1]["total_ms"])
     avg_s = st["total_ms"] / 1000.0 / max(st["launches"], 1)
-    if top in rows:
-        r = rows[top]
+    if top in ("cd_apply_hist", "cd_decide"):
+        r = dict(bound="hbm", achieved=EDGE_PASS_BYTES * wl["chunk"] / avg_s / 1e9, peak=HBM_PEAK_GBS, unit="GB/s")
     elif top.startswith("bh_force") and "bh_interactions" in st:
         flops = BH_INTERACTION_FLOPS * st["bh_interactions"] / max(st["launches"], 1)
         r = dict(bound="alu", achieved=flops / avg_s / 1e12, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
                  interactions_per_launch=st["bh_interactions"] / max(st["launches"], 1))
     else:
         r = dict(bound="unknown", achieved=None, peak=None, unit=None)
-    r = dict(r, kernel=top, avg_ms=avg_s * 1000.0, traffic=measured_traffic(top))
+    r = dict(r, kernel=top, avg_ms=avg_s * 1000.0, launches_timed=st["launches"], traffic=measured_traffic(top))
     if r.get("achieved") is not None:
         r["frac"] = r["achieved"] / r["peak"]
     extra["roofline_edge_stream"] = {k: dict(v, frac=v["achieved"] / v["peak"]) for k, v in rows.items()}

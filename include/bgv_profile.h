@@ -18,6 +18,10 @@ extern "C" {
 
 /* Start (on != 0) or stop recording events around library kernel launches. */
 void bgv_profile_enable(int on);
+/* Record only launches of kernels whose name starts with prefix (e.g. "k_bh_force"),
+ * so that a timed region carries the events of the kernel under study alone.  NULL or
+ * "" records every kernel (the default).  Takes effect for later launches. */
+void bgv_profile_filter(const char *prefix);
 /* Forget every recorded launch. */
 void bgv_profile_reset(void);
 /* Number of distinct kernels recorded since the last reset.  Waits for the recorded

@@ -2,6 +2,7 @@
 // (start, stop) HIP event pairs recorded around library launches.  Completed pairs are
 // harvested as new events are needed, so the number of live events stays near the
 // number of launches in flight instead of growing with the length of the run.
+#include <cstring>
 #include <deque>
 #include <map>
 #include <mutex>
@@ -24,6 +25,7 @@ struct Pending {
 };
 std::mutex g_mu;
 bool g_on = false;
+std::string g_filter;  // record only kernels whose name starts with this ("" = all)
 std::map<std::string, KStat> g_stats;
 std::deque<Pending> g_pending;  // in launch order
 std::vector<hipEvent_t> g_pool;
@@ -85,6 +87,8 @@ struct Token {
 
 void *prof_begin(const char *name, hipStream_t s) {
     std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_filter.empty() && std::strncmp(name, g_filter.c_str(), g_filter.size()) != 0)
+        return nullptr;
     hipEvent_t a = take_event();
     if (!a) return nullptr;
     hipEventRecord(a, s);
@@ -111,6 +115,11 @@ using namespace bgv;
 extern "C" void bgv_profile_enable(int on) {
     std::lock_guard<std::mutex> lk(g_mu);
     g_on = on != 0;
+}
+
+extern "C" void bgv_profile_filter(const char *prefix) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_filter = prefix ? prefix : "";
 }
 
 extern "C" void bgv_profile_reset(void) {

@@ -8,6 +8,8 @@ from ._lib import lib
 
 lib.bgv_profile_enable.argtypes = [C.c_int]
 lib.bgv_profile_enable.restype = None
+lib.bgv_profile_filter.argtypes = [C.c_char_p]
+lib.bgv_profile_filter.restype = None
 lib.bgv_profile_reset.argtypes = []
 lib.bgv_profile_reset.restype = None
 lib.bgv_profile_count.argtypes = []
@@ -28,6 +30,12 @@ def counter(name: str) -> int | None:
 
 def enable(on: bool = True) -> None:
     lib.bgv_profile_enable(1 if on else 0)
+
+
+def only(kernel: str | None) -> None:
+    """Record only kernels whose name starts with `kernel` (the name as stats() reports
+    it, without the "k_" prefix); None records every kernel."""
+    lib.bgv_profile_filter(None if not kernel else ("k_" + kernel).encode())
 
 
 def reset() -> None:

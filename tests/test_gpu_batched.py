@@ -129,3 +129,43 @@ def test_autotuner_picks_a_candidate(bgv, batch):
     choice, entry = autotune.tune_batched(edges, noff, eoff, int(noff_h[-1]), dict(wl, fa2_iters=5), c1, c2, pos,
                                           repeats=1, use_cache=False)
     assert choice in autotune.CANDIDATES and len(entry["ms"]) == len(autotune.CANDIDATES)
+
+
+def test_captured_batched_replays_match_eager(bgv, batch):
+    """The whole batched launch captured once in a graph and replayed repeatedly (with
+    eager work and synchronisations between replays) gives the eager result each time."""
+    wl, graphs, c1, c2, pos0 = batch
+    dev = torch.device("cuda")
+    edges, noff, eoff, noff_h, eoff_h = bgv.pack_graphs([(n, e) for n, e, _ in graphs], dev)
+    n_total, G = int(noff_h[-1]), len(graphs)
+    pos_init = torch.from_numpy(np.concatenate(pos0)).to(dev)
+    ws = bgv.batched_workspace(G, n_total, edges.shape[0], dev)
+    pos, fprev = pos_init.clone(), torch.zeros_like(pos_init)
+    speed = torch.ones(G, dtype=torch.float32, device=dev)
+
+    def run():
+        pos.copy_(pos_init)
+        fprev.zero_()
+        speed.fill_(1.0)
+        return bgv.batched(edges, noff, eoff, n_total, wl, c1, c2, pos, fprev=fprev, speed=speed, ws=ws)
+
+    eager = {k: v.clone() for k, v in run().items()}
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        run()
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        cap = run()
+    for rep in range(3):
+        graph.replay()
+        torch.cuda.synchronize()
+        for g in range(G):
+            a, b = per_graph(cap, noff_h, eoff_h, g), per_graph(eager, noff_h, eoff_h, g)
+            for k in a:
+                assert np.array_equal(a[k], b[k]), (rep, g, k)
+        # unrelated eager work between replays
+        junk = torch.randn(1 << 20, device=dev)
+        (junk * 2).sum().item()

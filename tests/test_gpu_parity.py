@@ -333,6 +333,35 @@ def test_bh_one_step_random(bgv):
     assert bad.mean() <= 1e-3
 
 
+def test_profile_filter_and_results_unchanged(bgv):
+    """Kernel timing is measurement only: with every launch bracketed, with only the
+    force kernel bracketed, or with none, the layout is bit for bit the same; the filter
+    limits the recorded kernels to the named one."""
+    from paper_2108_00529_amd import profile as prof
+    rng = np.random.default_rng(11)
+    K = 3000
+    pos0 = rng.uniform(-1, 1, (K, 2)).astype(np.float32)
+    se = np.array(sorted({(min(a, b), max(a, b)) for a, b in rng.integers(0, K, (6000, 2)).tolist() if a != b}),
+                  np.int32)
+    outs, recorded = [], []
+    for filt, on in ((None, False), (None, True), ("bh_force", True)):
+        prof.reset()
+        prof.only(filt)
+        prof.enable(on)
+        p, _, _ = bgv.fa2_layout(dev(se), dev(pos0), 5, exact=False, theta=1.2)
+        torch.cuda.synchronize()
+        prof.enable(False)
+        prof.only(None)
+        outs.append(host(p))
+        recorded.append(prof.stats())
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    assert recorded[0] == {}
+    assert len(recorded[1]) > 3 and any(k.startswith("bh_force") for k in recorded[1])
+    assert recorded[2] and all(k.startswith("bh_force") for k in recorded[2])
+    assert all(v["launches"] == 5 for v in recorded[2].values())
+    prof.reset()
+
+
 # ------------------------------------------------------------- full-size LFR -----
 @pytest.fixture(scope="module")
 def lfr():
