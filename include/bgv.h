@@ -72,7 +72,9 @@ typedef struct {
     int64_t chunk;     /* >= 1: edges per synchronous chunk                        */
 } bgv_cd_params;
 
-/* Workspace bytes for bgv_community (0 only on invalid arguments). */
+/* Workspace bytes for bgv_community (0 only on invalid arguments): 16 bytes per node,
+ * 4 per edge of a chunk, and with passes > 1 another 8 per edge (each edge's pass-0
+ * endpoint counters, from which later passes' counters follow without increments). */
 size_t bgv_community_workspace(int32_t n, int64_t m, const bgv_cd_params *p);
 
 /*

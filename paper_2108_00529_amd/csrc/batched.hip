@@ -137,6 +137,7 @@ __global__ void __launch_bounds__(NT) k_batched(BtArgs a) {
     constexpr int NW = NT / kWave;
     constexpr int NV = NT / 256;  // 256-node groups handled side by side in the layout
     static_assert(NT % 256 == 0 && NT <= 1024, "workgroup of 256, 512 or 1024 threads");
+    static_assert(kRepSegment % NT == 0, "repulsion segments must hold whole LDS tiles");
     __shared__ uint32_t sk[kBtMaxCells];
     __shared__ uint32_t hist[256], running[256];
     __shared__ uint32_t wcnt[NW][256];
@@ -348,8 +349,20 @@ __global__ void __launch_bounds__(NT) k_batched(BtArgs a) {
                 const bool live = vb < nvb && i < K;
                 const float2 xi = live ? pos[i] : make_float2(0.f, 0.f);
                 const float mi = live ? mass[i] : 0.f;
-                float rx = 0.f, ry = 0.f;
+                // the plain kernels' order: segments of kRepSegment bodies (a multiple of
+                // NT, so no tile straddles two), each from zero, then added in order
+                float rx = 0.f, ry = 0.f, sx = 0.f, sy = 0.f;
                 for (uint32_t j0 = 0; j0 < K; j0 += NT) {
+                    if (j0 != 0 && j0 % (uint32_t)kRepSegment == 0) {
+                        if (j0 == (uint32_t)kRepSegment) {
+                            rx = sx;
+                            ry = sy;
+                        } else {
+                            rx += sx;
+                            ry += sy;
+                        }
+                        sx = sy = 0.f;
+                    }
                     const uint32_t j = j0 + t;
                     if (j < K) {
                         const float2 xj = pos[j];
@@ -357,8 +370,15 @@ __global__ void __launch_bounds__(NT) k_batched(BtArgs a) {
                     }
                     __syncthreads();
                     const uint32_t c = min((uint32_t)NT, K - j0);
-                    for (uint32_t q = 0; q < c; ++q) fa2_rep_term(xi, tile[q], rx, ry);
+                    for (uint32_t q = 0; q < c; ++q) fa2_rep_term(xi, tile[q], sx, sy);
                     __syncthreads();
+                }
+                if (K <= (uint32_t)kRepSegment) {
+                    rx = sx;
+                    ry = sy;
+                } else {
+                    rx += sx;
+                    ry += sy;
                 }
                 double2 st = make_double2(0.0, 0.0);
                 if (live) {

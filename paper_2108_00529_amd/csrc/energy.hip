@@ -6,6 +6,7 @@
 // several blocks per i tile and sums the splits in order, so no FP atomics are used.
 #include "common.h"
 #include "fa2_internal.h"
+#include "fa2_math.h"
 
 namespace bgv {
 
@@ -62,12 +63,21 @@ __global__ void __launch_bounds__(kEnThreads) k_energy_pairs(int32_t K, int T, c
         const float2 xi = pos[i];
         const int cnt = min(kEnThreads, K - j0);
         float s = 0.f;
-        for (int q = 0; q < cnt; ++q) {
-            if (j0 + q <= i) continue;
-            const float4 p = tile[q];
-            const float dx = xi.x - p.x, dy = xi.y - p.y;
-            const float d2 = dx * dx + dy * dy;
-            if (d2 > 0.f) s += p.z * logf(d2);
+        if (J > I && cnt == kEnThreads) {  // every j of the tile is above i
+#pragma unroll 8
+            for (int q = 0; q < kEnThreads; ++q) {
+                const float4 p = tile[q];
+                const float dx = xi.x - p.x, dy = xi.y - p.y;
+                const float d2 = dx * dx + dy * dy;
+                s += d2 > 0.f ? p.z * logf(d2) : 0.f;
+            }
+        } else {
+            for (int q = 0; q < cnt; ++q) {
+                const float4 p = tile[q];
+                const float dx = xi.x - p.x, dy = xi.y - p.y;
+                const float d2 = dx * dx + dy * dy;
+                s += (j0 + q > i && d2 > 0.f) ? p.z * logf(d2) : 0.f;
+            }
         }
         acc = 0.5 * (double)mass[i] * (double)s;
     }
@@ -137,15 +147,10 @@ __global__ void __launch_bounds__(kEnThreads) k_grad_rep(int32_t K, int jtiles_p
         }
         __syncthreads();
         const int cnt = min(kEnThreads, K - j0);
-        for (int q = 0; q < cnt; ++q) {
-            const float4 p = tile[q];
-            const float dx = xi.x - p.x, dy = xi.y - p.y;
-            const float d2 = dx * dx + dy * dy;
-            if (d2 > 0.f) {
-                const float f = p.z / d2;
-                fx += f * dx;
-                fy += f * dy;
-            }
+        if (cnt == kEnThreads) {
+fa2_rep_run(xi, tile, kEnThreads, fx, fy);
+        } else {
+            for (int q = 0; q < cnt; ++q) fa2_rep_term(xi, tile[q], fx, fy);
         }
         __syncthreads();
     }

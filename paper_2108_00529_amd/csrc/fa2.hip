@@ -37,13 +37,19 @@ __global__ void k_csr_keys(const int2 *__restrict__ edges, int64_t E, int kb, ui
 }
 
 __global__ void k_csr_fill(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals, int64_t nent,
-                           int kb, int32_t K, const float *__restrict__ attr_w, uint32_t *__restrict__ row,
+                           int kb, int32_t K, const float *__restrict__ attr_w, int fmt, uint32_t *__restrict__ row,
                            int2 *__restrict__ cw) {
     const uint64_t mask = (1ull << kb) - 1ull;
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nent; k += (int64_t)gridDim.x * blockDim.x) {
         const uint64_t key = keys[k];
         const int64_t src = (int64_t)(key >> kb);
-        cw[k] = make_int2((int32_t)(key & mask), __float_as_int(attr_w ? attr_w[vals[k]] : 1.0f));
+        const int32_t nb = (int32_t)(key & mask);
+        if (fmt == kCsrWeighted)
+            cw[k] = make_int2(nb, __float_as_int(attr_w[vals[k]]));
+        else if (fmt == kCsrIds32)
+            reinterpret_cast<uint32_t *>(cw)[k] = (uint32_t)nb;
+        else
+            reinterpret_cast<uint16_t *>(cw)[k] = (uint16_t)nb;
         const int64_t prev = k ? (int64_t)(keys[k - 1] >> kb) : -1;
         for (int64_t r = prev + 1; r <= src; ++r) row[r] = (uint32_t)k;
         if (k == nent - 1)
@@ -77,6 +83,7 @@ size_t csr_layout(Carver &c, int32_t K, int64_t E, CsrWs *w) {
 
 bgv_status build_csr(int32_t K, int64_t E, const int32_t *edges, const float *attr_w, const float *mass_in,
                      CsrWs &w, hipStream_t s, const float **mass_out) {
+    w.fmt = attr_w ? kCsrWeighted : (K <= 65536 ? kCsrIds16 : kCsrIds32);
     if (E == 0) {
         BGV_TRY(fill<uint32_t>(w.row, 0u, (int64_t)K + 1, s));
     } else {
@@ -87,7 +94,7 @@ bgv_status build_csr(int32_t K, int64_t E, const int32_t *edges, const float *at
         uint32_t *sv;
         BGV_TRY(radix_sort_u64(w.keys, w.keys_alt, w.vals, w.vals_alt, 2 * E, 2 * kb, &sk, &sv, w.sort_scratch, s));
         BGV_LAUNCH(k_csr_fill, dim3(grid_for(2 * E, kFaThreads, 65536)), dim3(kFaThreads), 0, s, sk, sv,
-                           2 * E, kb, K, attr_w, w.row, w.cw);
+                           2 * E, kb, K, attr_w, w.fmt, w.row, w.cw);
     }
     if (mass_in) {
         *mass_out = mass_in;
@@ -125,9 +132,10 @@ __device__ __forceinline__ double2 block_sum2(double2 v) {
 // sums are combined by a fixed butterfly, so the result does not depend on timing.
 // Power-law supernode degrees (rows of thousands of entries next to rows of a few)
 // are why a row is not given to a single thread.
+template <typename E>
 __global__ void __launch_bounds__(kFaThreads) k_attract(int32_t K, const float2 *__restrict__ pos,
-                                                         const uint32_t *__restrict__ row,
-                                                         const int2 *__restrict__ cw, float2 *__restrict__ A) {
+                                                         const uint32_t *__restrict__ row, const E *__restrict__ cw,
+                                                         float2 *__restrict__ A) {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t nw = (int64_t)gridDim.x * (kFaThreads / kWave);
     for (int64_t i = (blockIdx.x * (int64_t)kFaThreads + threadIdx.x) / kWave; i < K; i += nw) {
@@ -137,43 +145,107 @@ __global__ void __launch_bounds__(kFaThreads) k_attract(int32_t K, const float2 
 }
 
 bgv_status attraction(int32_t K, const float2 *pos, const CsrWs &csr, float2 *A, hipStream_t s) {
-    BGV_LAUNCH(k_attract, dim3(grid_for(K, kFaThreads / kWave, 16384)), dim3(kFaThreads), 0, s, K, pos, csr.row,
-               csr.cw, A);
+    const dim3 grid(grid_for(K, kFaThreads / kWave, 16384));
+    if (csr.fmt == kCsrWeighted)
+        BGV_LAUNCH(k_attract<int2>, grid, dim3(kFaThreads), 0, s, K, pos, csr.row, csr.cw, A);
+    else if (csr.fmt == kCsrIds32)
+        BGV_LAUNCH(k_attract<uint32_t>, grid, dim3(kFaThreads), 0, s, K, pos, csr.row,
+                   reinterpret_cast<const uint32_t *>(csr.cw), A);
+    else
+        BGV_LAUNCH(k_attract<uint16_t>, grid, dim3(kFaThreads), 0, s, K, pos, csr.row,
+                   reinterpret_cast<const uint16_t *>(csr.cw), A);
     return BGV_OK;
 }
 
 // ------------------------------------------------------------------ exact ------
+// Repulsion of the i tile of block x over the j segment of block y (all of [0, K) when
+// kSegmented is false), bodies staged through LDS 256 at a time.  With one segment the
+// kernel finishes the force (attraction, gravity, swing, traction and the block's FP64
+// partials); with several it stores the segment sums for k_force_combine.
+template <bool kSegmented>
 __global__ void __launch_bounds__(kFaThreads) k_force_exact(int32_t K, const float2 *__restrict__ pos,
                                                              const float *__restrict__ mass,
                                                              const float2 *__restrict__ att, float kr, float kg,
                                                              const float2 *__restrict__ fprev, float2 *__restrict__ F,
-                                                             double2 *__restrict__ part) {
+                                                             double2 *__restrict__ part, float2 *__restrict__ seg) {
     __shared__ float4 tile[kFaThreads];
     __shared__ double2 ws[kFaThreads / kWave];
     const int32_t i = blockIdx.x * kFaThreads + threadIdx.x;
     const bool live = i < K;
     const float2 xi = live ? pos[i] : make_float2(0.f, 0.f);
-    const float mi = live ? mass[i] : 0.f;
+    const int32_t jb = kSegmented ? (int32_t)blockIdx.y * kRepSegment : 0;
+    const int32_t je = kSegmented ? min(K, jb + kRepSegment) : K;
     float fx = 0.f, fy = 0.f;
-    for (int32_t t0 = 0; t0 < K; t0 += kFaThreads) {
+    for (int32_t t0 = jb; t0 < je; t0 += kFaThreads) {
         const int32_t j = t0 + threadIdx.x;
-        if (j < K) {
+        if (j < je) {
             const float2 xj = pos[j];
             tile[threadIdx.x] = make_float4(xj.x, xj.y, mass[j], 0.f);
         }
         __syncthreads();
-        const int cnt = min(kFaThreads, K - t0);
-        for (int q = 0; q < cnt; ++q) fa2_rep_term(xi, tile[q], fx, fy);
+        const int cnt = min(kFaThreads, je - t0);
+        if (cnt == kFaThreads) {
+fa2_rep_run(xi, tile, kFaThreads, fx, fy);
+        } else {
+            for (int q = 0; q < cnt; ++q) fa2_rep_term(xi, tile[q], fx, fy);
+        }
         __syncthreads();
+    }
+    if (kSegmented) {
+        if (live) seg[(int64_t)blockIdx.y * K + i] = make_float2(fx, fy);
+        return;
     }
     double2 st = make_double2(0.0, 0.0);
     if (live) {
-        const float2 f = fa2_net_force(xi, mi, kr, fx, fy, att[i], kg);
+        const float2 f = fa2_net_force(xi, mass[i], kr, fx, fy, att[i], kg);
         F[i] = f;
-        st = fa2_swing_traction(f, fprev[i], mi);
+        st = fa2_swing_traction(f, fprev[i], mass[i]);
     }
     st = fa2_sum256(st, ws);
     if (threadIdx.x == 0) part[blockIdx.x] = st;
+}
+
+// Segment sums of body i added in ascending segment order, then the rest of the force.
+__global__ void __launch_bounds__(kFaThreads) k_force_combine(int32_t K, int32_t nseg,
+                                                               const float2 *__restrict__ seg,
+                                                               const float2 *__restrict__ pos,
+                                                               const float *__restrict__ mass,
+                                                               const float2 *__restrict__ att, float kr, float kg,
+                                                               const float2 *__restrict__ fprev,
+                                                               float2 *__restrict__ F, double2 *__restrict__ part) {
+    __shared__ double2 ws[kFaThreads / kWave];
+    const int32_t i = blockIdx.x * kFaThreads + threadIdx.x;
+    double2 st = make_double2(0.0, 0.0);
+    if (i < K) {
+        float2 r = seg[i];
+        for (int32_t q = 1; q < nseg; ++q) {
+            const float2 v = seg[(int64_t)q * K + i];
+            r.x += v.x;
+            r.y += v.y;
+        }
+        const float f_mi = mass[i];
+        const float2 f = fa2_net_force(pos[i], f_mi, kr, r.x, r.y, att[i], kg);
+        F[i] = f;
+        st = fa2_swing_traction(f, fprev[i], f_mi);
+    }
+    st = fa2_sum256(st, ws);
+    if (threadIdx.x == 0) part[blockIdx.x] = st;
+}
+
+static bgv_status exact_forces(int32_t K, const float2 *pos, const float *mass, const float2 *A, float kr, float kg,
+                               const float2 *fprev, float2 *F, double2 *part, float2 *seg, hipStream_t s) {
+    const unsigned nb = (unsigned)((K + kFaThreads - 1) / kFaThreads);
+    const int32_t nseg = fa2_rep_segments(K);
+    if (nseg <= 1) {
+        BGV_LAUNCH(k_force_exact<false>, dim3(nb), dim3(kFaThreads), 0, s, K, pos, mass, A, kr, kg, fprev, F, part,
+                   seg);
+    } else {
+        BGV_LAUNCH(k_force_exact<true>, dim3(nb, (unsigned)nseg), dim3(kFaThreads), 0, s, K, pos, mass, A, kr, kg,
+                   fprev, F, part, seg);
+        BGV_LAUNCH(k_force_combine, dim3(nb), dim3(kFaThreads), 0, s, K, nseg, seg, pos, mass, A, kr, kg, fprev, F,
+                   part);
+    }
+    return BGV_OK;
 }
 
 // ----------------------------------------------------------------- update ------
@@ -436,7 +508,13 @@ __device__ __forceinline__ void add_pair(float2 xi, float4 bj, float &fx, float 
 // wavefronts by G: the walk is a chain of dependent L2 loads, so latency hiding needs
 // many more wavefronts than one per body gives.
 constexpr int kBhThreads = 64;
-constexpr int kBhLanes = 8;
+#ifndef BGV_BH_LANES
+#define BGV_BH_LANES 8
+#endif
+#ifndef BGV_BH_SHARED
+#define BGV_BH_SHARED 1
+#endif
+constexpr int kBhLanes = BGV_BH_LANES;
 
 template <int G>
 __global__ void __launch_bounds__(kBhThreads) k_bh_force(int32_t K, const float4 *__restrict__ body,
@@ -478,7 +556,7 @@ __global__ void __launch_bounds__(kBhThreads) k_bh_force(int32_t K, const float4
                 const float d2 = dx * dx + dy * dy;
                 if (d2 > 0.f && A.w < theta2 * d2) {
                     if (owner) {
-                        const float f = A.z / d2;
+                        const float f = A.z * __builtin_amdgcn_rcpf(d2);
                         fx += f * dx;
                         fy += f * dy;
                         ++ic;
@@ -515,7 +593,7 @@ __global__ void __launch_bounds__(kBhThreads) k_bh_force(int32_t K, const float4
                 const float dx = xi.x - A.x, dy = xi.y - A.y;
                 const float d2 = dx * dx + dy * dy;
                 if (d2 > 0.f && A.w < theta2 * d2) {
-                    const float f = A.z / d2;
+                    const float f = A.z * __builtin_amdgcn_rcpf(d2);
                     fx += f * dx;
                     fy += f * dy;
                     ++ic;
@@ -567,6 +645,127 @@ __global__ void __launch_bounds__(kBhThreads) k_bh_force(int32_t K, const float4
     }
 }
 
+// Barnes-Hut repulsion with a shared stack per body.  The G lanes of a body pop the top
+// (up to) G entries of the body's LDS stack together, decide each exactly as a single
+// traversal would (a cell of equal codes or a body is summed directly, a node far
+// enough away by its centre of mass, any other node is opened) and push the children
+// of the opened nodes.  Work is shared out afresh every step, so no lane waits on
+// another's subtree; each step costs one dependent load per lane.  Entries are node
+// indices (>= 0) or bodies (~j).  Children are pushed in reverse lane order, so the
+// deepest entries stay on top and the stack is sorted by depth; a step that pops an
+// entry of depth d then pops every deeper entry, so at most 2G entries of any one
+// depth are ever on the stack, and 2G per level of the tree bounds it.  The order of
+// the additions depends only on G and the tree: results are identical run to run.
+constexpr int kBhTreeLevels = 34;  // 32-bit Morton codes: root, 32 prefix lengths, equal-code cells
+
+template <int G>
+__global__ void __launch_bounds__(kBhThreads) k_bh_force_shared(int32_t K, const float4 *__restrict__ body,
+                                                                 const float4 *__restrict__ nodeA,
+                                                                 const int4 *__restrict__ nodeB, float theta2,
+                                                                 const float2 *__restrict__ att, float kr, float kg,
+                                                                 const float2 *__restrict__ fprev,
+                                                                 float2 *__restrict__ F, double2 *__restrict__ part,
+                                                                 int *__restrict__ overflow,
+                                                                 uint32_t *__restrict__ icount) {
+    static_assert(G >= 2 && G <= kWave && (G & (G - 1)) == 0, "lanes per body: power of two in [2, 64]");
+    constexpr int kGroups = kBhThreads / G;
+    constexpr int kDepth = 2 * G * kBhTreeLevels;
+    __shared__ int stk[kGroups][kDepth];
+    const int64_t tid = (int64_t)blockIdx.x * kBhThreads + threadIdx.x;
+    const int32_t r = (int32_t)(tid / G);
+    const int L = (int)(tid % G);
+    int *st_g = stk[threadIdx.x / G];
+    double2 st = make_double2(0.0, 0.0);
+    float fx = 0.f, fy = 0.f;
+    uint32_t ic = 0;
+    float4 me = make_float4(0.f, 0.f, 0.f, 0.f);
+    int size = 0;
+    if (r < K) {
+        me = body[r];
+        if (K > 1) size = 1;
+    }
+    if (L == 0) st_g[0] = 0;  // the root
+    const float2 xi = make_float2(me.x, me.y);
+    while (__any(size > 0)) {
+        const int take = size < G ? size : G;
+        const bool has = L < take;
+        const int e = has ? st_g[size - 1 - L] : 0;
+        size -= take;
+        int c_left = 0, c_right = 0, np = 0;
+        if (has) {
+            if (e < 0) {
+                const int j = ~e;
+                if (j != r) add_pair(xi, body[j], fx, fy, ic);
+            } else {
+                const float4 A = nodeA[e];
+                const int4 Bn = nodeB[e];
+                if (A.w < 0.f) {  // a cell of equal codes: direct sum
+                    for (int k = Bn.z; k <= Bn.w; ++k)
+                        if (k != r) add_pair(xi, body[k], fx, fy, ic);
+                } else {
+                    bool open = r >= Bn.z && r <= Bn.w;
+                    if (!open) {
+                        const float dx = xi.x - A.x, dy = xi.y - A.y;
+                        const float d2 = dx * dx + dy * dy;
+                        if (d2 > 0.f && A.w < theta2 * d2) {
+                            const float f = A.z * __builtin_amdgcn_rcpf(d2);
+                            fx += f * dx;
+                            fy += f * dy;
+                            ++ic;
+                        } else {
+                            open = true;
+                        }
+                    }
+                    if (open) {
+                        c_left = Bn.x;
+                        c_right = Bn.y;
+                        np = 2;
+                    }
+                }
+            }
+        }
+        // inclusive scan of the pushes from the highest lane down, so lane 0 (the
+        // deepest popped entry) writes last, on top
+        int incl = np;
+#pragma unroll
+        for (int o = 1; o < G; o <<= 1) {
+            const int v = __shfl_down(incl, o, G);
+            if (L + o < G) incl += v;
+        }
+        const int total = __shfl(incl, 0, G);
+        if (np) {
+            const int at = size + incl - np;  // this lane's two slots: at, at + 1
+            if (at + 1 < kDepth) {
+                st_g[at] = c_right;
+                st_g[at + 1] = c_left;  // left on top: popped first
+            } else {
+                *overflow = 1;
+            }
+        }
+        size += total;
+        if (size > kDepth) size = kDepth;
+    }
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {
+        fx += __shfl_xor(fx, o, kWave);
+        fy += __shfl_xor(fy, o, kWave);
+    }
+    if (r < K && L == 0) {
+        const float mi = me.z;
+        const int32_t b = __float_as_int(me.w);
+        const float2 f = fa2_net_force(xi, mi, kr, fx, fy, att[b], kg);
+        F[b] = f;
+        st = fa2_swing_traction(f, fprev[b], mi);
+    }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) ic += __shfl_xor(ic, o, kWave);
+    st = block_sum2(st);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = st;
+        icount[blockIdx.x] += ic;
+    }
+}
+
 static_assert(kBhThreads == kWave, "the interaction tally reduces over one wavefront per workgroup");
 
 // Profiling only: total Barnes-Hut interactions, readable with bgv_profile_counter().
@@ -615,6 +814,7 @@ struct BhWs {
 struct FaWs {
     CsrWs csr;
     float2 *F, *A;
+    float2 *seg;  // exact repulsion: per-segment sums [segments][K] when K spans several segments
     double2 *part;
     float *speed;  // [2] ping-pong
     BhWs bh;
@@ -627,6 +827,8 @@ static size_t fa_layout(Carver &c, int32_t K, int64_t E, const bgv_fa2_params *p
     w->A = c.take<float2>((size_t)K);
     w->part = c.take<double2>((size_t)(nb > bh_force_blocks(K) ? nb : bh_force_blocks(K)));
     w->speed = c.take<float>(2);
+    w->seg = nullptr;
+    if (p->exact && fa2_rep_segments(K) > 1) w->seg = c.take<float2>((size_t)fa2_rep_segments(K) * (size_t)K);
     if (!p->exact) {
         BhWs &b = w->bh;
         b.bbox = c.take<float4>((size_t)nb);
@@ -673,9 +875,14 @@ static bgv_status bh_forces(int32_t K, const float2 *pos, const float *mass, con
         BGV_LAUNCH(k_bh_build, dim3(grid_for(K - 1, kFaThreads, 65536)), dim3(kFaThreads), 0, s, K, b.code,
                            b.PM, b.PX, b.PY, b.s0, b.nodeA, b.nodeB);
     }
+#if BGV_BH_SHARED
+    BGV_LAUNCH(k_bh_force_shared<kBhLanes>, dim3(bh_force_blocks(K)), dim3(kBhThreads), 0, s, K, b.body, b.nodeA,
+               b.nodeB, theta * theta, w.A, kr, kg, fprev, w.F, w.part, b.overflow, b.icount);
+#else
     BGV_LAUNCH(k_bh_force<kBhLanes>, dim3(bh_force_blocks(K)), dim3(kBhThreads), 0, s, K, b.body, b.nodeA,
                b.nodeB, theta * theta, w.A, kr,
                kg, fprev, w.F, w.part, b.overflow, b.icount);
+#endif
     return BGV_OK;
 }
 
@@ -723,8 +930,7 @@ extern "C" bgv_status bgv_fa2_layout(int32_t K, int64_t E, const int32_t *edges,
     for (int32_t it = 0; it < p->iters; ++it) {
         BGV_TRY(attraction(K, x, w.csr, w.A, s));
         if (p->exact) {
-            BGV_LAUNCH(k_force_exact, dim3(nb), dim3(kFaThreads), 0, s, K, x, m, w.A, p->kr, p->kg, fp, w.F,
-                       w.part);
+            BGV_TRY(exact_forces(K, x, m, w.A, p->kr, p->kg, fp, w.F, w.part, w.seg, s));
         } else {
             BGV_TRY(bh_forces(K, x, m, w.csr, p->theta, p->kr, p->kg, fp, w, s));
         }

@@ -4,11 +4,16 @@
 
 namespace bgv {
 
-// Directed CSR of an undirected edge list: row[K+1]; cw[2E] = (neighbour, weight bits)
-// of node i's entries in ascending (neighbour, edge index) order; mass[K] = row length + 1.
+// Directed CSR of an undirected edge list: row[K+1]; cw[2E] = node i's entries in
+// ascending (neighbour, edge index) order, as (neighbour, weight bits) when weights are
+// given and as bare neighbour ids (16-bit when K <= 65536) when they are all 1;
+// mass[K] = row length + 1.
+enum CsrFormat { kCsrWeighted = 0, kCsrIds32 = 1, kCsrIds16 = 2 };
+
 struct CsrWs {
     uint32_t *row;
-    int2 *cw;
+    int2 *cw;        // room for 2E int2 entries; holds the format below
+    int fmt;         // kCsrWeighted: int2 (id, weight bits); kCsrIds32 / kCsrIds16: ids only (unit weights)
     float *mass;
     uint64_t *keys, *keys_alt;
     uint32_t *vals, *vals_alt;

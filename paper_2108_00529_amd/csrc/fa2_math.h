@@ -8,41 +8,78 @@
 namespace bgv {
 
 // Repulsion from one body p = (x, y, mass): (x_i - x_j) * m_j / |x_i - x_j|^2, none if
-// coincident.  The caller scales the sum by kr * m_i.
+// coincident.  The caller scales the sum by kr * m_i.  Branch-free so that unrolled
+// loops keep several LDS reads in flight; 1/d^2 is the hardware reciprocal (within one
+// ulp), the quotient's rounding being far below the layout's tolerance.
 __device__ __forceinline__ void fa2_rep_term(float2 xi, float4 p, float &fx, float &fy) {
     const float dx = xi.x - p.x, dy = xi.y - p.y;
     const float d2 = dx * dx + dy * dy;
-    if (d2 > 0.f) {
-        const float f = p.z / d2;
-        fx += f * dx;
-        fy += f * dy;
+    const float f = d2 > 0.f ? p.z * __builtin_amdgcn_rcpf(d2) : 0.f;
+    fx += f * dx;
+    fy += f * dy;
+}
+
+// fa2_rep_term over n consecutive LDS bodies in ascending order, n a multiple of 8: each
+// group of eight is read before any of it is used, so the reads overlap.
+__device__ __forceinline__ void fa2_rep_run(float2 xi, const float4 *tile, int n, float &fx, float &fy) {
+    for (int q = 0; q < n; q += 8) {
+        float4 b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) b[u] = tile[q + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) fa2_rep_term(xi, b[u], fx, fy);
     }
+}
+
+// Exact repulsion on body i is summed over j in consecutive segments of kRepSegment
+// bodies: each segment in ascending j starting from zero, then the segment sums in
+// ascending order (the first one taken as is).  Segments let one body's sum be split
+// over several workgroups while fixing the order of every addition, so any launch shape
+// gives the same bits.  A multiple of every workgroup size the kernels use.
+constexpr int32_t kRepSegment = 4096;
+
+__host__ __device__ __forceinline__ int32_t fa2_rep_segments(int32_t K) {
+    return (K + kRepSegment - 1) / kRepSegment;
+}
+
+// CSR entries: (neighbour, weight bits) when edges are weighted, the bare neighbour id
+// (32 or 16 bits) when every weight is 1.  Adding w * d with w = 1 rounds exactly like
+// adding d (fused or not), so all three give the same bits for unit weights.
+__device__ __forceinline__ int32_t fa2_entry_id(int2 e) { return e.x; }
+__device__ __forceinline__ int32_t fa2_entry_id(uint32_t e) { return (int32_t)e; }
+__device__ __forceinline__ int32_t fa2_entry_id(uint16_t e) { return (int32_t)e; }
+
+__device__ __forceinline__ void fa2_entry_add(int2 e, float2 xj, float2 xi, float &ax, float &ay) {
+    const float w = __int_as_float(e.y);
+    ax += w * (xj.x - xi.x);
+    ay += w * (xj.y - xi.y);
+}
+template <typename E>
+__device__ __forceinline__ void fa2_entry_add(E, float2 xj, float2 xi, float &ax, float &ay) {
+    ax += xj.x - xi.x;
+    ay += xj.y - xi.y;
 }
 
 // Attraction on node i = sum over its CSR entries [r0, r1) of w * (x_j - x_i), by one
 // wavefront: lane l takes entries r0 + l, r0 + l + 64, ... (four loads in flight), then a
 // fixed butterfly combines the lanes; every lane returns the total.
-__device__ __forceinline__ float2 fa2_row_attraction(const float2 *__restrict__ pos, const int2 *__restrict__ cw,
+template <typename E>
+__device__ __forceinline__ float2 fa2_row_attraction(const float2 *__restrict__ pos, const E *__restrict__ cw,
                                                      uint32_t r0, uint32_t r1, float2 xi, int lane) {
     float ax = 0.f, ay = 0.f;
     uint32_t k = r0 + lane;
     for (; k + 3 * kWave < r1; k += 4 * kWave) {
-        const int2 e0 = cw[k], e1 = cw[k + kWave], e2 = cw[k + 2 * kWave], e3 = cw[k + 3 * kWave];
-        const float2 x0 = pos[e0.x], x1 = pos[e1.x], x2 = pos[e2.x], x3 = pos[e3.x];
-        ax += __int_as_float(e0.y) * (x0.x - xi.x);
-        ay += __int_as_float(e0.y) * (x0.y - xi.y);
-        ax += __int_as_float(e1.y) * (x1.x - xi.x);
-        ay += __int_as_float(e1.y) * (x1.y - xi.y);
-        ax += __int_as_float(e2.y) * (x2.x - xi.x);
-        ay += __int_as_float(e2.y) * (x2.y - xi.y);
-        ax += __int_as_float(e3.y) * (x3.x - xi.x);
-        ay += __int_as_float(e3.y) * (x3.y - xi.y);
+        const E e0 = cw[k], e1 = cw[k + kWave], e2 = cw[k + 2 * kWave], e3 = cw[k + 3 * kWave];
+        const float2 x0 = pos[fa2_entry_id(e0)], x1 = pos[fa2_entry_id(e1)], x2 = pos[fa2_entry_id(e2)],
+                     x3 = pos[fa2_entry_id(e3)];
+        fa2_entry_add(e0, x0, xi, ax, ay);
+        fa2_entry_add(e1, x1, xi, ax, ay);
+        fa2_entry_add(e2, x2, xi, ax, ay);
+        fa2_entry_add(e3, x3, xi, ax, ay);
     }
     for (; k < r1; k += kWave) {
-        const int2 e = cw[k];
-        const float2 xj = pos[e.x];
-        ax += __int_as_float(e.y) * (xj.x - xi.x);
-        ay += __int_as_float(e.y) * (xj.y - xi.y);
+        const E e = cw[k];
+        fa2_entry_add(e, pos[fa2_entry_id(e)], xi, ax, ay);
     }
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) {

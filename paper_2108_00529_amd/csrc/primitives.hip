@@ -147,16 +147,24 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_upsweep(const uint64_t *keys,
     counts[(int64_t)threadIdx.x * nb + blockIdx.x] = hist[threadIdx.x];
 }
 
-// Stable scatter: the tile is consumed in rounds of 256 consecutive keys; within a
-// round the rank of a key among equal digits is (keys of that digit in earlier waves)
-// + (equal-digit lanes below it in its wave, from 8 ballots).
+// Stable scatter of one tile of kRsThreads * ITEMS consecutive keys.  Wave w owns the
+// tile's w-th quarter and reads it in rounds of 64 consecutive keys; a key's rank among
+// the equal digits of its wave = (equal digits in the wave's earlier rounds, kept in a
+// per-wave LDS histogram) + (equal-digit lanes below it in its round, from 8 ballots).
+// Ranks are turned into tile positions (digits in order, waves in order within a digit),
+// the tile is reordered by digit in LDS, and written out in that order: each digit's
+// keys leave as one contiguous run, so the stores coalesce.
 template <int ITEMS>
 __global__ void __launch_bounds__(kRsThreads) k_rs_downsweep(const uint64_t *keys, uint64_t *keys_out,
                                                               const uint32_t *vals, uint32_t *vals_out,
                                                               int64_t n, int shift, const uint32_t *offsets,
                                                               int64_t nb, int raw_counts) {
-    __shared__ uint32_t running[256];
-    __shared__ uint32_t wcnt[kRsWaves][256];
+    constexpr int kTile = kRsThreads * ITEMS;
+    __shared__ uint32_t running[256];  // where each digit of this tile starts in the output
+    __shared__ uint32_t lstart[256];   // where each digit starts inside the tile
+    __shared__ uint32_t hist[kRsWaves][256];
+    __shared__ uint64_t skey[kTile];
+    __shared__ uint32_t sval[kTile];
     const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
     if (raw_counts) {
         // few tiles: derive this tile's digit offsets from the raw per-tile counts here
@@ -173,16 +181,23 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_downsweep(const uint64_t *key
         running[t] = offsets[(int64_t)t * nb + blockIdx.x];
     }
 #pragma unroll
-    for (int q = 0; q < kRsWaves; ++q) wcnt[q][t] = 0;
+    for (int q = 0; q < kRsWaves; ++q) hist[q][t] = 0;
     __syncthreads();
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int64_t base = (int64_t)blockIdx.x * (kRsThreads * ITEMS);
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    const int64_t wbase = base + (int64_t)w * (kWave * ITEMS);
+    uint64_t key[ITEMS];
+    uint32_t val[ITEMS], rk[ITEMS];
+#pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-        const int64_t i = base + (int64_t)j * kRsThreads + t;
-        const bool valid = i < n;
-        uint64_t key = valid ? keys[i] : 0ull;
-        uint32_t val = (valid && vals) ? vals[i] : 0u;
-        const uint32_t d = (uint32_t)(key >> shift) & 255u;
+        const int64_t i = wbase + (int64_t)j * kWave + lane;
+        key[j] = i < n ? keys[i] : 0ull;
+        val[j] = (i < n && vals) ? vals[i] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const bool valid = wbase + (int64_t)j * kWave + lane < n;
+        const uint32_t d = (uint32_t)(key[j] >> shift) & 255u;
         uint64_t match = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -190,24 +205,43 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_downsweep(const uint64_t *key
             const uint64_t bb = __ballot(bit);
             match &= bit ? bb : ~bb;
         }
-        const uint32_t rank = __popcll(match & lt_mask);
-        if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(match);
-        __syncthreads();
-        if (valid) {
-            uint32_t pre = running[d] + rank;
-            for (int q = 0; q < w; ++q) pre += wcnt[q][d];
-            keys_out[pre] = key;
-            if (vals) vals_out[pre] = val;
-        }
-        __syncthreads();
-        uint32_t add = 0;
+        const uint32_t below = (uint32_t)__popcll(match & lt_mask);
+        const uint32_t before = hist[w][d];
+        rk[j] = before + below;
+        // every lane of the round has read the histogram; the lowest lane of each digit
+        // group then adds the group's size (LDS operations of a wave take effect in order)
+        if (valid && below == 0) hist[w][d] = before + (uint32_t)__popcll(match);
+    }
+    __syncthreads();
+    {
+        uint32_t acc = 0;
 #pragma unroll
         for (int q = 0; q < kRsWaves; ++q) {
-            add += wcnt[q][t];
-            wcnt[q][t] = 0;
+            const uint32_t c = hist[q][t];
+            hist[q][t] = acc;  // equal digits in lower waves of the tile
+            acc += c;
         }
-        running[t] += add;
-        __syncthreads();
+        uint32_t all;
+        lstart[t] = block_excl_scan<uint32_t>(acc, &all);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        if (wbase + (int64_t)j * kWave + lane < n) {
+            const uint32_t d = (uint32_t)(key[j] >> shift) & 255u;
+            const uint32_t lp = lstart[d] + hist[w][d] + rk[j];
+            skey[lp] = key[j];
+            sval[lp] = val[j];
+        }
+    }
+    __syncthreads();
+    const int cnt = (int)((n - base) < kTile ? (n - base) : kTile);
+    for (int p = t; p < cnt; p += kRsThreads) {
+        const uint64_t k = skey[p];
+        const uint32_t d = (uint32_t)(k >> shift) & 255u;
+        const uint32_t dst = running[d] + ((uint32_t)p - lstart[d]);
+        keys_out[dst] = k;
+        if (vals) vals_out[dst] = sval[p];
     }
 }
 
