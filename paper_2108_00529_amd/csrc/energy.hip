@@ -45,6 +45,19 @@ __device__ __forceinline__ void tri_index(int64_t b, int T, int &I, int &J) {
     J = i + (int)rem;
 }
 
+constexpr double kLn2 = 0.693147180559945309417232121458176568;
+
+// m_j log2 |x_i - x_j|^2 (none for coincident bodies), with the hardware base-2
+// logarithm (within one ulp); subnormal d^2 is scaled by 2^64 first, since the
+// instruction takes normal inputs.  The caller scales by ln 2.
+__device__ __forceinline__ float en_log_term(float2 xi, float4 p) {
+    const float dx = xi.x - p.x, dy = xi.y - p.y;
+    const float d2 = dx * dx + dy * dy;
+    const bool sub = d2 < 1.17549435e-38f;
+    const float l = __builtin_amdgcn_logf(sub ? d2 * 18446744073709551616.0f : d2) - (sub ? 64.0f : 0.0f);
+    return d2 > 0.f ? p.z * l : 0.f;
+}
+
 __global__ void __launch_bounds__(kEnThreads) k_energy_pairs(int32_t K, int T, const float2 *__restrict__ pos,
                                                               const float *__restrict__ mass,
                                                               double *__restrict__ part) {
@@ -63,23 +76,22 @@ __global__ void __launch_bounds__(kEnThreads) k_energy_pairs(int32_t K, int T, c
         const float2 xi = pos[i];
         const int cnt = min(kEnThreads, K - j0);
         float s = 0.f;
+        // s = sum of m_j log2(d^2) over the tile's j above i; scaled by ln 2 below
         if (J > I && cnt == kEnThreads) {  // every j of the tile is above i
-#pragma unroll 8
-            for (int q = 0; q < kEnThreads; ++q) {
-                const float4 p = tile[q];
-                const float dx = xi.x - p.x, dy = xi.y - p.y;
-                const float d2 = dx * dx + dy * dy;
-                s += d2 > 0.f ? p.z * logf(d2) : 0.f;
+            for (int q = 0; q < kEnThreads; q += 8) {
+                float4 b[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) b[u] = tile[q + u];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) s += en_log_term(xi, b[u]);
             }
         } else {
             for (int q = 0; q < cnt; ++q) {
-                const float4 p = tile[q];
-                const float dx = xi.x - p.x, dy = xi.y - p.y;
-                const float d2 = dx * dx + dy * dy;
-                s += (j0 + q > i && d2 > 0.f) ? p.z * logf(d2) : 0.f;
+                const float v = en_log_term(xi, tile[q]);
+                s += j0 + q > i ? v : 0.f;
             }
         }
-        acc = 0.5 * (double)mass[i] * (double)s;
+        acc = 0.5 * kLn2 * (double)mass[i] * (double)s;
     }
     acc = block_sum(acc);
     if (threadIdx.x == 0) part[blockIdx.x] = acc;

@@ -4,11 +4,14 @@
 // Setup: directed CSR of the undirected edge list (own LSD radix sort, so neighbour
 // order and therefore every FP sum is deterministic).
 // Per iteration:
-//   exact:  k_force_exact   LDS-tiled all-pairs repulsion + CSR attraction + gravity,
-//                           swing/traction, FP64 block partials of the two sums
+//   both:   k_attract       attraction, one wavefront per CSR row
+//   exact:  k_force_exact   LDS-tiled all-pairs repulsion (split into 4096-body segments
+//                           summed by k_force_combine when K is larger) + attraction +
+//                           gravity, swing/traction, FP64 block partials of the two sums
 //   BH:     k_bh_bbox -> k_bh_codes -> radix sort -> k_bh_gather -> FP64 prefix sums
 //           -> k_bh_build (binary radix tree; centre of mass of a node = difference of
-//           prefix sums over its body range, so no atomics) -> k_bh_force (traversal)
+//           prefix sums over its body range, so no atomics) -> k_bh_force (traversal
+//           with a shared stack per body)
 //   both:   k_update        global speed from the partials (every block reduces them in
 //                           the same order), local speeds, displacement
 // No floating-point atomics anywhere: results are identical run to run.
@@ -22,7 +25,6 @@
 namespace bgv {
 
 constexpr int kFaThreads = 256;
-constexpr int kStackDepth = 64;
 
 // ------------------------------------------------------------------------ CSR ----
 __global__ void k_csr_keys(const int2 *__restrict__ edges, int64_t E, int kb, uint64_t *__restrict__ keys,
@@ -498,154 +500,11 @@ __device__ __forceinline__ void add_pair(float2 xi, float4 bj, float &fx, float 
     fa2_rep_term(xi, bj, fx, fy);
 }
 
-// Barnes-Hut repulsion.  Bodies are taken in Morton order (neighbouring bodies walk
-// similar paths) and each body's traversal is split over G = 2^D lanes: lane L follows
-// the path given by its D bits through the top D tree levels, deciding every node on
-// the way exactly as a single traversal would (a node that is summed whole -- by its
-// centre of mass, as a cell of equal codes, or as one body -- is added once, by the
-// lowest lane below it), then walks its own subtree with a stack.  The lanes' partial
-// sums are combined by a fixed butterfly.  Splitting multiplies the number of
-// wavefronts by G: the walk is a chain of dependent L2 loads, so latency hiding needs
-// many more wavefronts than one per body gives.
 constexpr int kBhThreads = 64;
-#ifndef BGV_BH_LANES
-#define BGV_BH_LANES 8
-#endif
-#ifndef BGV_BH_SHARED
-#define BGV_BH_SHARED 1
-#endif
-constexpr int kBhLanes = BGV_BH_LANES;
+constexpr int kBhLanes = 8;  // lanes per body (16 and 32 measured slower on the 17.7k-body bench supergraph)
 
-template <int G>
-__global__ void __launch_bounds__(kBhThreads) k_bh_force(int32_t K, const float4 *__restrict__ body,
-                                                          const float4 *__restrict__ nodeA,
-                                                          const int4 *__restrict__ nodeB, float theta2,
-                                                          const float2 *__restrict__ att, float kr, float kg,
-                                                          const float2 *__restrict__ fprev, float2 *__restrict__ F,
-                                                          double2 *__restrict__ part, int *__restrict__ overflow,
-                                                          uint32_t *__restrict__ icount) {
-    static_assert(G >= 1 && G <= kWave && (G & (G - 1)) == 0, "lanes per body: power of two <= 64");
-    __shared__ int stack[kStackDepth][kBhThreads];
-    const int64_t tid = (int64_t)blockIdx.x * kBhThreads + threadIdx.x;
-    const int32_t r = (int32_t)(tid / G);
-    const int L = (int)(tid % G);
-    double2 st = make_double2(0.0, 0.0);
-    float fx = 0.f, fy = 0.f;
-    uint32_t ic = 0;  // interactions summed by this lane (body pairs + centres of mass)
-    float4 me = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (r < K) {
-        me = body[r];
-        const float2 xi = make_float2(me.x, me.y);
-        int sp = 0;
-        // descend the top levels along this lane's path
-        int node = 0, lo = 0, span = G;
-        bool walk = K > 1;
-        while (walk && span > 1) {
-            const float4 A = nodeA[node];
-            const int4 Bn = nodeB[node];
-            const bool owner = L == lo;
-            if (A.w < 0.f) {  // a cell of equal codes: direct sum, once
-                if (owner)
-                    for (int k = Bn.z; k <= Bn.w; ++k)
-                        if (k != r) add_pair(xi, body[k], fx, fy, ic);
-                walk = false;
-                break;
-            }
-            if (r < Bn.z || r > Bn.w) {
-                const float dx = xi.x - A.x, dy = xi.y - A.y;
-                const float d2 = dx * dx + dy * dy;
-                if (d2 > 0.f && A.w < theta2 * d2) {
-                    if (owner) {
-                        const float f = A.z * __builtin_amdgcn_rcpf(d2);
-                        fx += f * dx;
-                        fy += f * dy;
-                        ++ic;
-                    }
-                    walk = false;
-                    break;
-                }
-            }
-            span >>= 1;  // opened: the lower half of the lanes takes the left child
-            const bool right = (L - lo) >= span;
-            const int child = right ? Bn.y : Bn.x;
-            if (right) lo += span;
-            if (child < 0) {  // a single body
-                const int j = ~child;
-                if (L == lo && j != r) add_pair(xi, body[j], fx, fy, ic);
-                walk = false;
-                break;
-            }
-            node = child;
-        }
-        if (walk) stack[sp++][threadIdx.x] = node;
-        while (sp > 0) {
-            const int node = stack[--sp][threadIdx.x];
-            const float4 A = nodeA[node];
-            const int4 Bn = nodeB[node];
-            bool open;
-            if (A.w < 0.f) {  // a cell of equal codes: direct sum
-                for (int k = Bn.z; k <= Bn.w; ++k)
-                    if (k != r) add_pair(xi, body[k], fx, fy, ic);
-                continue;
-            } else if (r >= Bn.z && r <= Bn.w) {
-                open = true;
-            } else {
-                const float dx = xi.x - A.x, dy = xi.y - A.y;
-                const float d2 = dx * dx + dy * dy;
-                if (d2 > 0.f && A.w < theta2 * d2) {
-                    const float f = A.z * __builtin_amdgcn_rcpf(d2);
-                    fx += f * dx;
-                    fy += f * dy;
-                    ++ic;
-                    open = false;
-                } else {
-                    open = true;
-                }
-            }
-            if (open) {
-                // right first onto the stack so the left subtree is summed first
-                if (Bn.y < 0) {
-                    const int j = ~Bn.y;
-                    if (j != r) add_pair(xi, body[j], fx, fy, ic);
-                } else if (sp < kStackDepth) {
-                    stack[sp++][threadIdx.x] = Bn.y;
-                } else {
-                    *overflow = 1;
-                }
-                if (Bn.x < 0) {
-                    const int j = ~Bn.x;
-                    if (j != r) add_pair(xi, body[j], fx, fy, ic);
-                } else if (sp < kStackDepth) {
-                    stack[sp++][threadIdx.x] = Bn.x;
-                } else {
-                    *overflow = 1;
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) {
-        fx += __shfl_xor(fx, o, kWave);
-        fy += __shfl_xor(fy, o, kWave);
-    }
-    if (r < K && L == 0) {
-        const float2 xi = make_float2(me.x, me.y);
-        const float mi = me.z;
-        const int32_t b = __float_as_int(me.w);
-        const float2 f = fa2_net_force(xi, mi, kr, fx, fy, att[b], kg);
-        F[b] = f;
-        st = fa2_swing_traction(f, fprev[b], mi);
-    }
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) ic += __shfl_xor(ic, o, kWave);
-    st = block_sum2(st);
-    if (threadIdx.x == 0) {
-        part[blockIdx.x] = st;
-        icount[blockIdx.x] += ic;  // one slot per workgroup, accumulated over iterations
-    }
-}
-
-// Barnes-Hut repulsion with a shared stack per body.  The G lanes of a body pop the top
+// Barnes-Hut repulsion.  Bodies are taken in Morton order, so the bodies of a wavefront
+// walk similar paths.  Each body has a shared stack and G lanes: they pop the top
 // (up to) G entries of the body's LDS stack together, decide each exactly as a single
 // traversal would (a cell of equal codes or a body is summed directly, a node far
 // enough away by its centre of mass, any other node is opened) and push the children
@@ -659,14 +518,13 @@ __global__ void __launch_bounds__(kBhThreads) k_bh_force(int32_t K, const float4
 constexpr int kBhTreeLevels = 34;  // 32-bit Morton codes: root, 32 prefix lengths, equal-code cells
 
 template <int G>
-__global__ void __launch_bounds__(kBhThreads) k_bh_force_shared(int32_t K, const float4 *__restrict__ body,
-                                                                 const float4 *__restrict__ nodeA,
-                                                                 const int4 *__restrict__ nodeB, float theta2,
-                                                                 const float2 *__restrict__ att, float kr, float kg,
-                                                                 const float2 *__restrict__ fprev,
-                                                                 float2 *__restrict__ F, double2 *__restrict__ part,
-                                                                 int *__restrict__ overflow,
-                                                                 uint32_t *__restrict__ icount) {
+__global__ void __launch_bounds__(kBhThreads) k_bh_force(int32_t K, const float4 *__restrict__ body,
+                                                          const float4 *__restrict__ nodeA,
+                                                          const int4 *__restrict__ nodeB, float theta2,
+                                                          const float2 *__restrict__ att, float kr, float kg,
+                                                          const float2 *__restrict__ fprev, float2 *__restrict__ F,
+                                                          double2 *__restrict__ part, int *__restrict__ overflow,
+                                                          uint32_t *__restrict__ icount) {
     static_assert(G >= 2 && G <= kWave && (G & (G - 1)) == 0, "lanes per body: power of two in [2, 64]");
     constexpr int kGroups = kBhThreads / G;
     constexpr int kDepth = 2 * G * kBhTreeLevels;
@@ -875,14 +733,8 @@ static bgv_status bh_forces(int32_t K, const float2 *pos, const float *mass, con
         BGV_LAUNCH(k_bh_build, dim3(grid_for(K - 1, kFaThreads, 65536)), dim3(kFaThreads), 0, s, K, b.code,
                            b.PM, b.PX, b.PY, b.s0, b.nodeA, b.nodeB);
     }
-#if BGV_BH_SHARED
-    BGV_LAUNCH(k_bh_force_shared<kBhLanes>, dim3(bh_force_blocks(K)), dim3(kBhThreads), 0, s, K, b.body, b.nodeA,
-               b.nodeB, theta * theta, w.A, kr, kg, fprev, w.F, w.part, b.overflow, b.icount);
-#else
     BGV_LAUNCH(k_bh_force<kBhLanes>, dim3(bh_force_blocks(K)), dim3(kBhThreads), 0, s, K, b.body, b.nodeA,
-               b.nodeB, theta * theta, w.A, kr,
-               kg, fprev, w.F, w.part, b.overflow, b.icount);
-#endif
+               b.nodeB, theta * theta, w.A, kr, kg, fprev, w.F, w.part, b.overflow, b.icount);
     return BGV_OK;
 }
 
