@@ -26,6 +26,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+PROFILE_SAMPLE = 10            # timed steps bracket one in this many dominant-kernel launches
 FP32_PEAK_TFLOPS = 157.3       # MI355X vector FP32, published
 
 
@@ -128,9 +129,11 @@ def main():
         dominant = max(kbreak.items(), key=lambda kv: kv[1]["total_ms"])[0] if kbreak else None
         print(f"[bench] breakdown step done; dominant kernel {dominant}", file=sys.stderr, flush=True)
 
-    # timed steps: events only around the dominant kernel, so the rest runs unbracketed
+    # timed steps: events only around one in PROFILE_SAMPLE launches of the dominant
+    # kernel, so the rest runs unbracketed
     prof.reset()
     prof.only(dominant)
+    prof.sample(PROFILE_SAMPLE)
     prof.enable(dominant is not None)
     cd_ms, fa_ms = [], []
     torch.cuda.synchronize()
@@ -144,11 +147,13 @@ def main():
     t_total = time.perf_counter() - t_start
     prof.enable(False)
     prof.only(None)
+    prof.sample(1)
     kstats = prof.stats()
     inter = prof.counter("bh_interactions")
     for k in kstats:
         if k.startswith("bh_force") and inter:
-            kstats[k]["bh_interactions"] = inter
+            # the counter covers every launch of the timed steps, not only the sampled ones
+            kstats[k]["bh_interactions_per_launch"] = inter / (args.steps * wl["fa2_iters"])
     print(f"[bench] timed {args.steps} steps in {t_total:.2f}s", file=sys.stderr, flush=True)
 
     ms_per_step = 1000.0 * t_total / args.steps
@@ -326,15 +331,50 @@ def gradient_form(torch, bgv, graphgen, fa2_iters=500, lrs=(1.0, 3.0, 10.0), max
             "adam_best_ms_to_fa2_energy": min(v["ms"] for v in ok) if ok else None}
 
 
-# algorithmic bytes / flops per unit
+# algorithmic work per unit: bytes (HBM-bound kernels) or flops (ALU-bound)
 EDGE_PASS_BYTES = 8            # one int32 (u,v) pair read per edge per pass
 BH_INTERACTION_FLOPS = 20      # body-node or body-body interaction, n-body convention
+CSR_ENTRY_BYTES = {"attract<uint16_t>": 2, "attract<uint32_t>": 4, "attract<int2>": 8}
+
+
+def kernel_model(name, K, E, inter_per_launch=None):
+    """(bound, algorithmic work per launch, unit) of a layout kernel on a K-body,
+    E-superedge supergraph, or None for kernels without a model."""
+    if name.startswith("bh_force") and inter_per_launch:
+        return "alu", BH_INTERACTION_FLOPS * inter_per_launch, "flop"
+    if name in CSR_ENTRY_BYTES:  # CSR entries + row offsets, own and neighbour positions, result
+        return "hbm", CSR_ENTRY_BYTES[name] * 2 * E + 28 * K, "byte"
+    per_body = {"rs_downsweep<kRsItemsSmall>": 24,  # Morton sort pass: key and index read + written
+                "rs_upsweep<kRsItemsSmall>": 8,     # key read
+                "bh_codes": 20,                     # position read, key and index written
+                "bh_gather": 44,                    # key, index, position, mass read; body and code written
+                "bh_prefix": 40,                    # body read; three FP64 prefix sums written
+                "bh_build": 60,                     # codes and prefix sums read; node written
+                "update": 48}                       # position, force, previous force read; two written
+    if name in per_body:
+        return "hbm", per_body[name] * K, "byte"
+    return None
+
+
+def roofline_of(name, avg_s, K, E, inter_per_launch=None):
+    mdl = kernel_model(name, K, E, inter_per_launch)
+    if mdl is None:
+        return dict(bound="unknown", achieved=None, peak=None, unit=None)
+    bound, work, unit = mdl
+    if bound == "alu":
+        r = dict(bound="alu", achieved=work / avg_s / 1e12, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s")
+    else:
+        r = dict(bound="hbm", achieved=work / avg_s / 1e9, peak=HBM_PEAK_GBS, unit="GB/s")
+    r["frac"] = r["achieved"] / r["peak"]
+    r["work_per_launch"] = work
+    return r
 
 
 def roofline_report(kstats, kbreak, wl, n, m, K, E):
     """Roofline of the dominant kernel, from the events recorded around it in the timed
     steps (kstats), plus the per-kernel breakdown of one untimed fully bracketed step
-    (kbreak) and the edge-stream kernels' rates from it."""
+    (kbreak) with each layout kernel's roofline and the community passes' edge-stream
+    rate."""
     if not kstats:
         return None, {}
     extra = {"kernel_ms_breakdown_step": {k: {"launches": v["launches"], "avg_ms": round(v["total_ms"] / max(v["launches"], 1), 5),
@@ -347,40 +387,48 @@ def roofline_report(kstats, kbreak, wl, n, m, K, E):
     if cd_ms > 0:
         rows["community_passes"] = dict(bound="hbm", achieved=EDGE_PASS_BYTES * m * wl["passes"] / (cd_ms / 1e3) / 1e9,
                                         peak=HBM_PEAK_GBS, unit="GB/s", device_ms=cd_ms)
+    extra["roofline_edge_stream"] = {k: dict(v, frac=v["achieved"] / v["peak"]) for k, v in rows.items()}
+    inter = next((v.get("bh_interactions_per_launch") for k, v in kstats.items() if k.startswith("bh_force")), None)
+    layout = {}
+    for name, st in kbreak.items():
+        if kernel_model(name, K, E, inter) is not None:
+            layout[name] = roofline_of(name, st["total_ms"] / 1e3 / max(st["launches"], 1), K, E, inter)
+    extra["roofline_layout_kernels_breakdown_step"] = layout
     top, st = max(kstats.items(), key=lambda kv: kv[1]["total_ms"])
     avg_s = st["total_ms"] / 1000.0 / max(st["launches"], 1)
-    if top.startswith("bh_force") and "bh_interactions" in st:
-        flops = BH_INTERACTION_FLOPS * st["bh_interactions"] / max(st["launches"], 1)
-        r = dict(bound="alu", achieved=flops / avg_s / 1e12, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
-                 interactions_per_launch=st["bh_interactions"] / max(st["launches"], 1))
-    else:
-        r = dict(bound="unknown", achieved=None, peak=None, unit=None)
-    r = dict(r, kernel=top, avg_ms=avg_s * 1000.0, launches_timed=st["launches"], traffic=measured_traffic(top))
-    if r.get("achieved") is not None:
-        r["frac"] = r["achieved"] / r["peak"]
-    extra["roofline_edge_stream"] = {k: dict(v, frac=v["achieved"] / v["peak"]) for k, v in rows.items()}
+    r = roofline_of(top, avg_s, K, E, st.get("bh_interactions_per_launch"))
+    if st.get("bh_interactions_per_launch"):
+        r["interactions_per_launch"] = st["bh_interactions_per_launch"]
+    r = dict(r, kernel=top, avg_ms=avg_s * 1000.0, launches_sampled=st["launches"], traffic=measured_traffic(top))
     return r, extra
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of the dominant kernel, from the committed rocprofv3 counter
-    summary, or None when the kernel source has changed since the counters were taken."""
+def csrc_digest() -> str:
+    """sha256 (16 hex digits) over the library's kernel sources, in name order."""
     import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2108_00529_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        h.update(f.encode())
+        h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when it has no entry or the
+    kernel sources have changed since the counters were taken."""
     import re
-    if not kernel.startswith("bh_force"):
-        return None
-    summary = os.path.join(ROOT, "profiles", "bh_force_lfr_1m.md")
-    src = os.path.join(ROOT, "paper_2108_00529_amd", "csrc", "fa2.hip")
+    summary = os.path.join(ROOT, "profiles", "hbm_traffic_lfr_1m.md")
     try:
         text = open(summary).read()
-        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     except OSError:
         return None
-    m_hash = re.search(r"fa2\.hip when measured: ([0-9a-f]{16})", text)
-    m_bytes = re.search(r"traffic_bytes_per_launch: (\d+)", text)
-    if not m_hash or not m_bytes or m_hash.group(1) != digest:
+    m_hash = re.search(r"kernel sources when measured: ([0-9a-f]{16})", text)
+    if not m_hash or m_hash.group(1) != csrc_digest():
         return None
-    return int(m_bytes.group(1))
+    m_bytes = re.search(r"traffic_bytes_per_launch\[" + re.escape(kernel) + r"\]: (\d+)", text)
+    return int(m_bytes.group(1)) if m_bytes else None
 
 
 def cpu_baseline(edges_np, n, wl, c1, c2, pos0_np, fa2_iters):

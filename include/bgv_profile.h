@@ -22,6 +22,10 @@ void bgv_profile_enable(int on);
  * so that a timed region carries the events of the kernel under study alone.  NULL or
  * "" records every kernel (the default).  Takes effect for later launches. */
 void bgv_profile_filter(const char *prefix);
+/* Record one in `every` of the launches that pass the filter (the first, then every
+ * every-th), so long runs are sampled with a fraction of the event overhead; 1 or less
+ * records all (the default).  Statistics count the recorded launches only. */
+void bgv_profile_sample(int every);
 /* Forget every recorded launch. */
 void bgv_profile_reset(void);
 /* Number of distinct kernels recorded since the last reset.  Waits for the recorded

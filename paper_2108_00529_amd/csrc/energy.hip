@@ -173,7 +173,8 @@ fa2_rep_run(xi, tile, kEnThreads, fx, fy);
 __global__ void __launch_bounds__(kEnThreads) k_grad_final(int32_t K, int nsplit, const float2 *__restrict__ prep,
                                                             const float2 *__restrict__ pos,
                                                             const float *__restrict__ mass,
-                                                            const float2 *__restrict__ att, float kr, float kg,
+                                                            const float2 *__restrict__ att,
+                                                            const uint32_t *__restrict__ item_of, float kr, float kg,
                                                             const float *__restrict__ grad_out,
                                                             float2 *__restrict__ grad) {
     for (int32_t i = blockIdx.x * kEnThreads + threadIdx.x; i < K; i += gridDim.x * kEnThreads) {
@@ -186,7 +187,7 @@ __global__ void __launch_bounds__(kEnThreads) k_grad_final(int32_t K, int nsplit
         const float2 xi = pos[i];
         const float mi = mass[i];
         float fx = kr * mi * rx, fy = kr * mi * ry;
-        const float2 a = att[i];
+        const float2 a = fa2_att_combine(att, item_of, i);
         fx += a.x;
         fy += a.y;
         const float r = sqrtf(xi.x * xi.x + xi.y * xi.y);
@@ -227,7 +228,7 @@ static size_t en_layout(Carver &c, int32_t K, int64_t E, EnWs *w) {
     w->patt = c.take<double>((size_t)en_edge_blocks(E));
     w->pgrav = c.take<double>((size_t)en_grav_blocks(K));
     w->gsplit = c.take<float2>((size_t)en_splits(K) * (size_t)K);
-    w->att = c.take<float2>((size_t)K);
+    w->att = c.take<float2>((size_t)w->csr.items_bound);
     return c.size();
 }
 
@@ -292,6 +293,6 @@ extern "C" bgv_status bgv_fa2_grad(int32_t K, int64_t E, const int32_t *edges, c
     BGV_LAUNCH(k_grad_rep, dim3(T, ns), dim3(kEnThreads), 0, s, K, per, x, m, w.gsplit);
     BGV_TRY(attraction(K, x, w.csr, w.att, s));
     BGV_LAUNCH(k_grad_final, dim3(grid_for(K, kEnThreads, 65536)), dim3(kEnThreads), 0, s, K, ns, w.gsplit, x, m,
-               w.att, kr, kg, grad_out, reinterpret_cast<float2 *>(grad));
+               w.att, w.csr.item_of, kr, kg, grad_out, reinterpret_cast<float2 *>(grad));
     return BGV_OK;
 }

@@ -70,17 +70,41 @@ static int bits_for(int64_t K) {
     return kb;
 }
 
+int64_t att_items_cap(int32_t K, int64_t E) { return (int64_t)K + (2 * E) / kAttBlock + 1; }
+
 size_t csr_layout(Carver &c, int32_t K, int64_t E, CsrWs *w) {
     const int64_t nent = 2 * E > 0 ? 2 * E : 1;
     w->row = c.take<uint32_t>((size_t)K + 1);
     w->cw = c.take<int2>((size_t)nent);
     w->mass = c.take<float>((size_t)K);
+    w->items_bound = att_items_cap(K, E);
+    w->item_of = c.take<uint32_t>((size_t)K + 1);
+    w->item_row = c.take<uint32_t>((size_t)w->items_bound);
     w->keys = c.take<uint64_t>((size_t)nent);
     w->keys_alt = c.take<uint64_t>((size_t)nent);
     w->vals = c.take<uint32_t>((size_t)nent);
     w->vals_alt = c.take<uint32_t>((size_t)nent);
-    w->sort_scratch = c.take<char>(radix_workspace(nent));
+    const size_t rs = radix_workspace(nent), sc = scan_workspace((int64_t)K + 1);
+    w->sort_scratch = c.take<char>(rs > sc ? rs : sc);
     return c.size();
+}
+
+// Work items of the attraction: max(1, ceil(row length / kAttBlock)) per row, turned
+// into first-item offsets by an exclusive scan, then each item's row.
+__global__ void k_att_item_counts(const uint32_t *__restrict__ row, int32_t K, uint32_t *__restrict__ item_of) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= K; i += (int64_t)gridDim.x * blockDim.x) {
+        if (i == K) {
+            item_of[i] = 0u;
+        } else {
+            const uint32_t len = row[i + 1] - row[i];
+            item_of[i] = len > kAttBlock ? (len + kAttBlock - 1) / kAttBlock : 1u;
+        }
+    }
+}
+
+__global__ void k_att_item_rows(const uint32_t *__restrict__ item_of, int32_t K, uint32_t *__restrict__ item_row) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < K; i += (int64_t)gridDim.x * blockDim.x)
+        for (uint32_t t = item_of[i]; t < item_of[i + 1]; ++t) item_row[t] = (uint32_t)i;
 }
 
 bgv_status build_csr(int32_t K, int64_t E, const int32_t *edges, const float *attr_w, const float *mass_in,
@@ -98,6 +122,11 @@ bgv_status build_csr(int32_t K, int64_t E, const int32_t *edges, const float *at
         BGV_LAUNCH(k_csr_fill, dim3(grid_for(2 * E, kFaThreads, 65536)), dim3(kFaThreads), 0, s, sk, sv,
                            2 * E, kb, K, attr_w, w.fmt, w.row, w.cw);
     }
+    BGV_LAUNCH(k_att_item_counts, dim3(grid_for((int64_t)K + 1, kFaThreads, 65536)), dim3(kFaThreads), 0, s, w.row,
+               K, w.item_of);
+    BGV_TRY(exclusive_scan_u32(w.item_of, w.item_of, (int64_t)K + 1, nullptr, w.sort_scratch, s));
+    BGV_LAUNCH(k_att_item_rows, dim3(grid_for(K, kFaThreads, 65536)), dim3(kFaThreads), 0, s, w.item_of, K,
+               w.item_row);
     if (mass_in) {
         *mass_out = mass_in;
     } else {
@@ -137,25 +166,34 @@ __device__ __forceinline__ double2 block_sum2(double2 v) {
 template <typename E>
 __global__ void __launch_bounds__(kFaThreads) k_attract(int32_t K, const float2 *__restrict__ pos,
                                                          const uint32_t *__restrict__ row, const E *__restrict__ cw,
+                                                         const uint32_t *__restrict__ item_of,
+                                                         const uint32_t *__restrict__ item_row,
                                                          float2 *__restrict__ A) {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t nw = (int64_t)gridDim.x * (kFaThreads / kWave);
-    for (int64_t i = (blockIdx.x * (int64_t)kFaThreads + threadIdx.x) / kWave; i < K; i += nw) {
-        const float2 a = fa2_row_attraction(pos, cw, row[i], row[i + 1], pos[i], lane);
-        if (lane == 0) A[i] = a;
+    const uint32_t T = item_of[K];
+    for (int64_t t = (blockIdx.x * (int64_t)kFaThreads + threadIdx.x) / kWave; t < T; t += nw) {
+        const uint32_t r = item_row[t];
+        const uint32_t r1 = row[r + 1];
+        const uint32_t b0 = row[r] + ((uint32_t)t - item_of[r]) * kAttBlock;
+        const uint32_t b1 = r1 - b0 > kAttBlock ? b0 + kAttBlock : r1;
+        const float2 a = fa2_block_attraction(pos, cw, b0, b1, pos[r], lane);
+        if (lane == 0) A[t] = a;
     }
 }
 
 bgv_status attraction(int32_t K, const float2 *pos, const CsrWs &csr, float2 *A, hipStream_t s) {
-    const dim3 grid(grid_for(K, kFaThreads / kWave, 16384));
+    // one wavefront per item; the item count is only known on the device, so the grid
+    // covers the bound and the kernel reads the count
+    const dim3 grid(grid_for(csr.items_bound, kFaThreads / kWave, 16384));
     if (csr.fmt == kCsrWeighted)
-        BGV_LAUNCH(k_attract<int2>, grid, dim3(kFaThreads), 0, s, K, pos, csr.row, csr.cw, A);
+        BGV_LAUNCH(k_attract<int2>, grid, dim3(kFaThreads), 0, s, K, pos, csr.row, csr.cw, csr.item_of, csr.item_row, A);
     else if (csr.fmt == kCsrIds32)
         BGV_LAUNCH(k_attract<uint32_t>, grid, dim3(kFaThreads), 0, s, K, pos, csr.row,
-                   reinterpret_cast<const uint32_t *>(csr.cw), A);
+                   reinterpret_cast<const uint32_t *>(csr.cw), csr.item_of, csr.item_row, A);
     else
         BGV_LAUNCH(k_attract<uint16_t>, grid, dim3(kFaThreads), 0, s, K, pos, csr.row,
-                   reinterpret_cast<const uint16_t *>(csr.cw), A);
+                   reinterpret_cast<const uint16_t *>(csr.cw), csr.item_of, csr.item_row, A);
     return BGV_OK;
 }
 
@@ -167,7 +205,8 @@ bgv_status attraction(int32_t K, const float2 *pos, const CsrWs &csr, float2 *A,
 template <bool kSegmented>
 __global__ void __launch_bounds__(kFaThreads) k_force_exact(int32_t K, const float2 *__restrict__ pos,
                                                              const float *__restrict__ mass,
-                                                             const float2 *__restrict__ att, float kr, float kg,
+                                                             const float2 *__restrict__ att,
+                                                             const uint32_t *__restrict__ item_of, float kr, float kg,
                                                              const float2 *__restrict__ fprev, float2 *__restrict__ F,
                                                              double2 *__restrict__ part, float2 *__restrict__ seg) {
     __shared__ float4 tile[kFaThreads];
@@ -199,7 +238,7 @@ fa2_rep_run(xi, tile, kFaThreads, fx, fy);
     }
     double2 st = make_double2(0.0, 0.0);
     if (live) {
-        const float2 f = fa2_net_force(xi, mass[i], kr, fx, fy, att[i], kg);
+        const float2 f = fa2_net_force(xi, mass[i], kr, fx, fy, fa2_att_combine(att, item_of, i), kg);
         F[i] = f;
         st = fa2_swing_traction(f, fprev[i], mass[i]);
     }
@@ -212,7 +251,8 @@ __global__ void __launch_bounds__(kFaThreads) k_force_combine(int32_t K, int32_t
                                                                const float2 *__restrict__ seg,
                                                                const float2 *__restrict__ pos,
                                                                const float *__restrict__ mass,
-                                                               const float2 *__restrict__ att, float kr, float kg,
+                                                               const float2 *__restrict__ att,
+                                                               const uint32_t *__restrict__ item_of, float kr, float kg,
                                                                const float2 *__restrict__ fprev,
                                                                float2 *__restrict__ F, double2 *__restrict__ part) {
     __shared__ double2 ws[kFaThreads / kWave];
@@ -226,7 +266,7 @@ __global__ void __launch_bounds__(kFaThreads) k_force_combine(int32_t K, int32_t
             r.y += v.y;
         }
         const float f_mi = mass[i];
-        const float2 f = fa2_net_force(pos[i], f_mi, kr, r.x, r.y, att[i], kg);
+        const float2 f = fa2_net_force(pos[i], f_mi, kr, r.x, r.y, fa2_att_combine(att, item_of, i), kg);
         F[i] = f;
         st = fa2_swing_traction(f, fprev[i], f_mi);
     }
@@ -234,18 +274,19 @@ __global__ void __launch_bounds__(kFaThreads) k_force_combine(int32_t K, int32_t
     if (threadIdx.x == 0) part[blockIdx.x] = st;
 }
 
-static bgv_status exact_forces(int32_t K, const float2 *pos, const float *mass, const float2 *A, float kr, float kg,
-                               const float2 *fprev, float2 *F, double2 *part, float2 *seg, hipStream_t s) {
+static bgv_status exact_forces(int32_t K, const float2 *pos, const float *mass, const float2 *A,
+                               const uint32_t *item_of, float kr, float kg, const float2 *fprev, float2 *F,
+                               double2 *part, float2 *seg, hipStream_t s) {
     const unsigned nb = (unsigned)((K + kFaThreads - 1) / kFaThreads);
     const int32_t nseg = fa2_rep_segments(K);
     if (nseg <= 1) {
-        BGV_LAUNCH(k_force_exact<false>, dim3(nb), dim3(kFaThreads), 0, s, K, pos, mass, A, kr, kg, fprev, F, part,
-                   seg);
+        BGV_LAUNCH(k_force_exact<false>, dim3(nb), dim3(kFaThreads), 0, s, K, pos, mass, A, item_of, kr, kg, fprev,
+                   F, part, seg);
     } else {
-        BGV_LAUNCH(k_force_exact<true>, dim3(nb, (unsigned)nseg), dim3(kFaThreads), 0, s, K, pos, mass, A, kr, kg,
-                   fprev, F, part, seg);
-        BGV_LAUNCH(k_force_combine, dim3(nb), dim3(kFaThreads), 0, s, K, nseg, seg, pos, mass, A, kr, kg, fprev, F,
-                   part);
+        BGV_LAUNCH(k_force_exact<true>, dim3(nb, (unsigned)nseg), dim3(kFaThreads), 0, s, K, pos, mass, A, item_of,
+                   kr, kg, fprev, F, part, seg);
+        BGV_LAUNCH(k_force_combine, dim3(nb), dim3(kFaThreads), 0, s, K, nseg, seg, pos, mass, A, item_of, kr, kg,
+                   fprev, F, part);
     }
     return BGV_OK;
 }
@@ -521,7 +562,8 @@ template <int G>
 __global__ void __launch_bounds__(kBhThreads) k_bh_force(int32_t K, const float4 *__restrict__ body,
                                                           const float4 *__restrict__ nodeA,
                                                           const int4 *__restrict__ nodeB, float theta2,
-                                                          const float2 *__restrict__ att, float kr, float kg,
+                                                          const float2 *__restrict__ att,
+                                                          const uint32_t *__restrict__ item_of, float kr, float kg,
                                                           const float2 *__restrict__ fprev, float2 *__restrict__ F,
                                                           double2 *__restrict__ part, int *__restrict__ overflow,
                                                           uint32_t *__restrict__ icount) {
@@ -611,7 +653,7 @@ __global__ void __launch_bounds__(kBhThreads) k_bh_force(int32_t K, const float4
     if (r < K && L == 0) {
         const float mi = me.z;
         const int32_t b = __float_as_int(me.w);
-        const float2 f = fa2_net_force(xi, mi, kr, fx, fy, att[b], kg);
+        const float2 f = fa2_net_force(xi, mi, kr, fx, fy, fa2_att_combine(att, item_of, b), kg);
         F[b] = f;
         st = fa2_swing_traction(f, fprev[b], mi);
     }
@@ -682,7 +724,7 @@ static size_t fa_layout(Carver &c, int32_t K, int64_t E, const bgv_fa2_params *p
     csr_layout(c, K, E, &w->csr);
     const int64_t nb = (K + kFaThreads - 1) / kFaThreads;
     w->F = c.take<float2>((size_t)K);
-    w->A = c.take<float2>((size_t)K);
+    w->A = c.take<float2>((size_t)w->csr.items_bound);
     w->part = c.take<double2>((size_t)(nb > bh_force_blocks(K) ? nb : bh_force_blocks(K)));
     w->speed = c.take<float>(2);
     w->seg = nullptr;
@@ -734,7 +776,7 @@ static bgv_status bh_forces(int32_t K, const float2 *pos, const float *mass, con
                            b.PM, b.PX, b.PY, b.s0, b.nodeA, b.nodeB);
     }
     BGV_LAUNCH(k_bh_force<kBhLanes>, dim3(bh_force_blocks(K)), dim3(kBhThreads), 0, s, K, b.body, b.nodeA,
-               b.nodeB, theta * theta, w.A, kr, kg, fprev, w.F, w.part, b.overflow, b.icount);
+               b.nodeB, theta * theta, w.A, csr.item_of, kr, kg, fprev, w.F, w.part, b.overflow, b.icount);
     return BGV_OK;
 }
 
@@ -782,7 +824,7 @@ extern "C" bgv_status bgv_fa2_layout(int32_t K, int64_t E, const int32_t *edges,
     for (int32_t it = 0; it < p->iters; ++it) {
         BGV_TRY(attraction(K, x, w.csr, w.A, s));
         if (p->exact) {
-            BGV_TRY(exact_forces(K, x, m, w.A, p->kr, p->kg, fp, w.F, w.part, w.seg, s));
+            BGV_TRY(exact_forces(K, x, m, w.A, w.csr.item_of, p->kr, p->kg, fp, w.F, w.part, w.seg, s));
         } else {
             BGV_TRY(bh_forces(K, x, m, w.csr, p->theta, p->kr, p->kg, fp, w, s));
         }

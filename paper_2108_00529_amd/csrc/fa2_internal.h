@@ -15,13 +15,22 @@ struct CsrWs {
     int2 *cw;        // room for 2E int2 entries; holds the format below
     int fmt;         // kCsrWeighted: int2 (id, weight bits); kCsrIds32 / kCsrIds16: ids only (unit weights)
     float *mass;
+    // attraction work items: row i's entries are cut into blocks of kAttBlock entries
+    // (at least one block per row); item_of[i] = first item of row i (K+1 entries,
+    // item_of[K] = number of items), item_row[t] = row of item t
+    uint32_t *item_of, *item_row;
+    int64_t items_bound;  // att_items_cap(K, E)
     uint64_t *keys, *keys_alt;
     uint32_t *vals, *vals_alt;
     void *sort_scratch;
 };
 
+// Upper bound on the number of attraction work items (block sums) of K rows holding 2E
+// entries.
+int64_t att_items_cap(int32_t K, int64_t E);
 size_t csr_layout(Carver &c, int32_t K, int64_t E, CsrWs *w);
-// A[i] = sum over node i's CSR entries of w * (x_j - x_i), one wavefront per node.
+// A[t] = attraction block sum of work item t (att_items_cap(K, E) entries), one
+// wavefront per item; node i's attraction is fa2_att_combine(A, csr.item_of, i).
 bgv_status attraction(int32_t K, const float2 *pos, const CsrWs &csr, float2 *A, hipStream_t s);
 // Builds the CSR; *mass_out = mass_in if given, else the degree-based masses.
 bgv_status build_csr(int32_t K, int64_t E, const int32_t *edges, const float *attr_w, const float *mass_in,

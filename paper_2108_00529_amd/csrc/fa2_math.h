@@ -60,15 +60,17 @@ __device__ __forceinline__ void fa2_entry_add(E, float2 xj, float2 xi, float &ax
     ay += xj.y - xi.y;
 }
 
-// Attraction on node i = sum over its CSR entries [r0, r1) of w * (x_j - x_i), by one
-// wavefront: lane l takes entries r0 + l, r0 + l + 64, ... (four loads in flight), then a
-// fixed butterfly combines the lanes; every lane returns the total.
+// Attraction over the CSR entries [b0, b1) of one block (at most kAttBlock entries), by
+// one wavefront: lane l takes entries b0 + l, b0 + l + 64, ... in order (four loads in
+// flight), then a fixed butterfly combines the lanes; every lane returns the total.
+constexpr uint32_t kAttBlock = 16 * kWave;
+
 template <typename E>
-__device__ __forceinline__ float2 fa2_row_attraction(const float2 *__restrict__ pos, const E *__restrict__ cw,
-                                                     uint32_t r0, uint32_t r1, float2 xi, int lane) {
+__device__ __forceinline__ float2 fa2_block_attraction(const float2 *__restrict__ pos, const E *__restrict__ cw,
+                                                       uint32_t b0, uint32_t b1, float2 xi, int lane) {
     float ax = 0.f, ay = 0.f;
-    uint32_t k = r0 + lane;
-    for (; k + 3 * kWave < r1; k += 4 * kWave) {
+    uint32_t k = b0 + lane;
+    for (; k + 3 * kWave < b1; k += 4 * kWave) {
         const E e0 = cw[k], e1 = cw[k + kWave], e2 = cw[k + 2 * kWave], e3 = cw[k + 3 * kWave];
         const float2 x0 = pos[fa2_entry_id(e0)], x1 = pos[fa2_entry_id(e1)], x2 = pos[fa2_entry_id(e2)],
                      x3 = pos[fa2_entry_id(e3)];
@@ -77,7 +79,7 @@ __device__ __forceinline__ float2 fa2_row_attraction(const float2 *__restrict__ 
         fa2_entry_add(e2, x2, xi, ax, ay);
         fa2_entry_add(e3, x3, xi, ax, ay);
     }
-    for (; k < r1; k += kWave) {
+    for (; k < b1; k += kWave) {
         const E e = cw[k];
         fa2_entry_add(e, pos[fa2_entry_id(e)], xi, ax, ay);
     }
@@ -87,6 +89,37 @@ __device__ __forceinline__ float2 fa2_row_attraction(const float2 *__restrict__ 
         ay += __shfl_xor(ay, o, kWave);
     }
     return make_float2(ax, ay);
+}
+
+// Attraction on node i = sum over its CSR entries [r0, r1) of w * (x_j - x_i): the row
+// is cut into blocks of kAttBlock entries, each summed as above, and the block sums are
+// added in order (the first taken as is).  A row of up to kAttBlock entries is a single
+// block.  The blocks of a long (hub) row can then be summed by different wavefronts and
+// combined afterwards with the same additions (fa2_att_combine).
+template <typename E>
+__device__ __forceinline__ float2 fa2_row_attraction(const float2 *__restrict__ pos, const E *__restrict__ cw,
+                                                     uint32_t r0, uint32_t r1, float2 xi, int lane) {
+    float2 t = fa2_block_attraction(pos, cw, r0, r1 - r0 > kAttBlock ? r0 + kAttBlock : r1, xi, lane);
+    for (uint32_t b = r0 + kAttBlock; b < r1; b += kAttBlock) {
+        const float2 v = fa2_block_attraction(pos, cw, b, r1 - b > kAttBlock ? b + kAttBlock : r1, xi, lane);
+        t.x += v.x;
+        t.y += v.y;
+    }
+    return t;
+}
+
+// Node i's attraction from its block sums attb[item_of[i] .. item_of[i + 1]), added in
+// block order exactly as fa2_row_attraction adds them.
+__device__ __forceinline__ float2 fa2_att_combine(const float2 *__restrict__ attb, const uint32_t *__restrict__ item_of,
+                                                  int32_t i) {
+    const uint32_t a = item_of[i], b = item_of[i + 1];
+    float2 t = attb[a];
+    for (uint32_t q = a + 1; q < b; ++q) {
+        const float2 v = attb[q];
+        t.x += v.x;
+        t.y += v.y;
+    }
+    return t;
 }
 
 // Fixed-pattern sum of one double2 per thread over a group of 256 threads (4

@@ -131,11 +131,14 @@ constexpr int64_t kRsSmallN = (int64_t)kRsLocalOffsetTiles * kRsThreads * kRsIte
 
 static int64_t rs_items(int64_t n) { return n <= kRsSmallN ? kRsItemsSmall : kRsItemsLarge; }
 
+// Per-tile digit counts (counts[digit * nb + tile]).  `zero` (or null): a 256 x nb count
+// buffer this launch clears for the next pass.
 template <int ITEMS>
 __global__ void __launch_bounds__(kRsThreads) k_rs_upsweep(const uint64_t *keys, int64_t n, int shift,
-                                                            uint32_t *counts, int64_t nb) {
+                                                            uint32_t *counts, int64_t nb, uint32_t *zero) {
     __shared__ uint32_t hist[256];
     hist[threadIdx.x] = 0;
+    if (zero) zero[(int64_t)blockIdx.x * 256 + threadIdx.x] = 0u;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * (kRsThreads * ITEMS);
 #pragma unroll 4
@@ -154,11 +157,16 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_upsweep(const uint64_t *keys,
 // Ranks are turned into tile positions (digits in order, waves in order within a digit),
 // the tile is reordered by digit in LDS, and written out in that order: each digit's
 // keys leave as one contiguous run, so the stores coalesce.
+// With `next` (raw-count mode only), the launch also counts the next pass's digit of
+// every key it writes into next[digit * nb + destination tile] (integer atomics, so the
+// counts do not depend on timing), which replaces the next pass's counting launch;
+// `zero` (or null) is a count buffer it clears for the pass after that.
 template <int ITEMS>
 __global__ void __launch_bounds__(kRsThreads) k_rs_downsweep(const uint64_t *keys, uint64_t *keys_out,
                                                               const uint32_t *vals, uint32_t *vals_out,
                                                               int64_t n, int shift, const uint32_t *offsets,
-                                                              int64_t nb, int raw_counts) {
+                                                              int64_t nb, int raw_counts, uint32_t *next,
+                                                              int next_shift, uint32_t *zero) {
     constexpr int kTile = kRsThreads * ITEMS;
     __shared__ uint32_t running[256];  // where each digit of this tile starts in the output
     __shared__ uint32_t lstart[256];   // where each digit starts inside the tile
@@ -169,11 +177,19 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_downsweep(const uint64_t *key
     if (raw_counts) {
         // few tiles: derive this tile's digit offsets from the raw per-tile counts here
         // instead of a separate device-wide scan
+        // eight independent loads at a time (a dependent chain of nb L2 round trips
+        // otherwise dominates small sorts)
         uint32_t tot = 0, pre = 0;
-        for (int64_t b = 0; b < nb; ++b) {
-            const uint32_t c = offsets[(int64_t)t * nb + b];
-            if (b < (int64_t)blockIdx.x) pre += c;
-            tot += c;
+        const uint32_t *row = offsets + (int64_t)t * nb;
+        for (int64_t b0 = 0; b0 < nb; b0 += 8) {
+            uint32_t c[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) c[u] = b0 + u < nb ? row[b0 + u] : 0u;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (b0 + u < (int64_t)blockIdx.x) pre += c[u];
+                tot += c[u];
+            }
         }
         uint32_t all;
         running[t] = block_excl_scan<uint32_t>(tot, &all) + pre;
@@ -242,18 +258,27 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_downsweep(const uint64_t *key
         const uint32_t dst = running[d] + ((uint32_t)p - lstart[d]);
         keys_out[dst] = k;
         if (vals) vals_out[dst] = sval[p];
+        if (next) atomicAdd(&next[(int64_t)((k >> next_shift) & 255u) * nb + dst / (uint32_t)kTile], 1u);
     }
+    if (zero) zero[(int64_t)blockIdx.x * 256 + t] = 0u;
 }
 
-// Bound for any sort of at most n keys: small sorts use more (smaller) tiles than a
-// large sort of n keys would, so both tile counts are covered.
-size_t radix_workspace(int64_t n) {
+// Tile count bound for any sort of at most n keys: small sorts use more (smaller)
+// tiles than a large sort of n keys would, so both tile counts are covered.
+static int64_t radix_tiles_bound(int64_t n) {
     const int64_t ns = n < kRsSmallN ? n : kRsSmallN;
     const int64_t nb_small = (ns + kRsThreads * kRsItemsSmall - 1) / (kRsThreads * kRsItemsSmall);
     int64_t nb_large = (n + kRsThreads * kRsItemsLarge - 1) / (kRsThreads * kRsItemsLarge);
     if (nb_large < 1) nb_large = 1;
-    const int64_t nb = nb_small > nb_large ? nb_small : nb_large;
-    return align_up(sizeof(uint32_t) * 256 * (size_t)nb) + scan_workspace(256 * nb_large);
+    return nb_small > nb_large ? nb_small : nb_large;
+}
+
+// Layout: per-tile counts [256][tiles], scan scratch, three [256][64] count buffers for
+// the few-tile path.
+size_t radix_workspace(int64_t n) {
+    const int64_t nb = radix_tiles_bound(n);
+    return align_up(sizeof(uint32_t) * 256 * (size_t)nb) + scan_workspace(256 * nb) +
+           align_up(3 * sizeof(uint32_t) * 256 * (size_t)kRsLocalOffsetTiles);
 }
 
 bgv_status radix_sort_u64(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, uint32_t *vals_alt,
@@ -265,25 +290,49 @@ bgv_status radix_sort_u64(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, ui
         const bool small = rs_items(n) == kRsItemsSmall;
         const int64_t tile = kRsThreads * rs_items(n);
         const int64_t nb = (n + tile - 1) / tile;
+        const size_t counts_bytes = align_up(sizeof(uint32_t) * 256 * (size_t)radix_tiles_bound(n));
         uint32_t *counts = static_cast<uint32_t *>(scratch);
-        void *scan_scratch = static_cast<char *>(scratch) + align_up(sizeof(uint32_t) * 256 * (size_t)nb);
-        const int raw = nb <= kRsLocalOffsetTiles ? 1 : 0;
-        for (int shift = 0; shift < nbits; shift += 8) {
+        void *scan_scratch = static_cast<char *>(scratch) + counts_bytes;
+        const int npass = (nbits + 7) / 8;
+        if (nb <= kRsLocalOffsetTiles) {
+            // few tiles: every scatter derives its offsets from the raw counts and counts
+            // the next pass's digits itself, so only pass 0 has a counting launch; three
+            // count buffers rotate (read by pass i, filled during pass i-1, cleared two
+            // passes ahead)
+            uint32_t *cb = reinterpret_cast<uint32_t *>(static_cast<char *>(scan_scratch) +
+                                                        scan_workspace(256 * radix_tiles_bound(n)));
+            uint32_t *buf[3] = {cb, cb + 256 * kRsLocalOffsetTiles, cb + 2 * 256 * kRsLocalOffsetTiles};
+            uint32_t *zero1 = npass > 1 ? buf[1] : nullptr;
             if (small)
-                BGV_LAUNCH(k_rs_upsweep<kRsItemsSmall>, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, n, shift,
-                           counts, nb);
+                BGV_LAUNCH(k_rs_upsweep<kRsItemsSmall>, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, n, 0,
+                           buf[0], nb, zero1);
             else
+                BGV_LAUNCH(k_rs_upsweep<kRsItemsLarge>, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, n, 0,
+                           buf[0], nb, zero1);
+            for (int pass = 0; pass < npass; ++pass) {
+                const int shift = 8 * pass;
+                uint32_t *next = pass + 1 < npass ? buf[(pass + 1) % 3] : nullptr;
+                uint32_t *zero = pass + 2 < npass ? buf[(pass + 2) % 3] : nullptr;
+                if (small)
+                    BGV_LAUNCH(k_rs_downsweep<kRsItemsSmall>, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, dst,
+                               vsrc, vdst, n, shift, buf[pass % 3], nb, 1, next, shift + 8, zero);
+                else
+                    BGV_LAUNCH(k_rs_downsweep<kRsItemsLarge>, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, dst,
+                               vsrc, vdst, n, shift, buf[pass % 3], nb, 1, next, shift + 8, zero);
+                uint64_t *tk = src; src = dst; dst = tk;
+                uint32_t *tv = vsrc; vsrc = vdst; vdst = tv;
+            }
+        } else {
+            for (int pass = 0; pass < npass; ++pass) {
+                const int shift = 8 * pass;
                 BGV_LAUNCH(k_rs_upsweep<kRsItemsLarge>, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, n, shift,
-                           counts, nb);
-            if (!raw) BGV_TRY(exclusive_scan_u32(counts, counts, 256 * nb, nullptr, scan_scratch, s));
-            if (small)
-                BGV_LAUNCH(k_rs_downsweep<kRsItemsSmall>, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, dst, vsrc,
-                           vdst, n, shift, counts, nb, raw);
-            else
+                           counts, nb, (uint32_t *)nullptr);
+                BGV_TRY(exclusive_scan_u32(counts, counts, 256 * nb, nullptr, scan_scratch, s));
                 BGV_LAUNCH(k_rs_downsweep<kRsItemsLarge>, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, dst, vsrc,
-                           vdst, n, shift, counts, nb, raw);
-            uint64_t *tk = src; src = dst; dst = tk;
-            uint32_t *tv = vsrc; vsrc = vdst; vdst = tv;
+                           vdst, n, shift, counts, nb, 0, (uint32_t *)nullptr, 0, (uint32_t *)nullptr);
+                uint64_t *tk = src; src = dst; dst = tk;
+                uint32_t *tv = vsrc; vsrc = vdst; vdst = tv;
+            }
         }
     }
     *keys_out = src;

@@ -26,6 +26,8 @@ struct Pending {
 std::mutex g_mu;
 bool g_on = false;
 std::string g_filter;  // record only kernels whose name starts with this ("" = all)
+int64_t g_every = 1;   // record one in g_every of the launches that pass the filter
+int64_t g_seen = 0;
 std::map<std::string, KStat> g_stats;
 std::deque<Pending> g_pending;  // in launch order
 std::vector<hipEvent_t> g_pool;
@@ -89,6 +91,7 @@ void *prof_begin(const char *name, hipStream_t s) {
     std::lock_guard<std::mutex> lk(g_mu);
     if (!g_filter.empty() && std::strncmp(name, g_filter.c_str(), g_filter.size()) != 0)
         return nullptr;
+    if (g_every > 1 && (g_seen++ % g_every) != 0) return nullptr;
     hipEvent_t a = take_event();
     if (!a) return nullptr;
     hipEventRecord(a, s);
@@ -120,6 +123,12 @@ extern "C" void bgv_profile_enable(int on) {
 extern "C" void bgv_profile_filter(const char *prefix) {
     std::lock_guard<std::mutex> lk(g_mu);
     g_filter = prefix ? prefix : "";
+}
+
+extern "C" void bgv_profile_sample(int every) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_every = every > 1 ? every : 1;
+    g_seen = 0;
 }
 
 extern "C" void bgv_profile_reset(void) {

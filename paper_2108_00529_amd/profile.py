@@ -10,6 +10,8 @@ lib.bgv_profile_enable.argtypes = [C.c_int]
 lib.bgv_profile_enable.restype = None
 lib.bgv_profile_filter.argtypes = [C.c_char_p]
 lib.bgv_profile_filter.restype = None
+lib.bgv_profile_sample.argtypes = [C.c_int]
+lib.bgv_profile_sample.restype = None
 lib.bgv_profile_reset.argtypes = []
 lib.bgv_profile_reset.restype = None
 lib.bgv_profile_count.argtypes = []
@@ -36,6 +38,11 @@ def only(kernel: str | None) -> None:
     """Record only kernels whose name starts with `kernel` (the name as stats() reports
     it, without the "k_" prefix); None records every kernel."""
     lib.bgv_profile_filter(None if not kernel else ("k_" + kernel).encode())
+
+
+def sample(every: int) -> None:
+    """Record one in `every` of the launches that pass the filter (1: all)."""
+    lib.bgv_profile_sample(int(every))
 
 
 def reset() -> None:
