@@ -38,7 +38,8 @@ def parse():
     ap.add_argument("--workload", default="lfr_1m")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-fa2-iters", type=int, default=20)
-    ap.add_argument("--no-forms", action="store_true", help="skip the batched and gradient comparisons")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the batched, gradient and largest-graph comparisons")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="do not bracket launches with HIP events (for hardware-counter runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -194,7 +195,8 @@ def main():
         del edges, pos0
         torch.cuda.empty_cache()
         out["forms"] = {"batched": batched_form(torch, bgv, graphgen),
-                        "gradient": gradient_form(torch, bgv, graphgen)}
+                        "gradient": gradient_form(torch, bgv, graphgen),
+                        "largest_graph": largest_graph_form(torch, bgv, graphgen)}
     print(json.dumps(out))
 
 
@@ -277,29 +279,84 @@ def batched_form(torch, bgv, graphgen):
             "supernodes_equal": bool(np.array_equal(K_b, np.array(K_p)))}
 
 
-def gradient_form(torch, bgv, graphgen, fa2_iters=500, lrs=(1.0, 3.0, 10.0), max_steps=3000):
-    """Weighted supergraph of ~50k supernodes (planted communities of 100 nodes of a
-    5M-node LFR-style graph; superedge weights from a 5 x 2^22 sketch): exact FA2 with
-    its adaptive speeds for `fa2_iters` iterations vs Adam on the FA2 energy (autograd
-    function with the hand-written gradient) until it reaches the same energy."""
+def largest_graph_form(torch, bgv, graphgen, cpu_fa2_iters=10):
+    """The lfr_3m workload (3.2M nodes, 34M edges) end to end on the GPU (community
+    passes, supergraph, 1,000 Barnes-Hut iterations) against the oracle on the host:
+    the oracle runs the community passes and supergraph in full (one thread) and
+    `cpu_fa2_iters` layout iterations (all OpenMP threads), scaled to the workload's
+    iteration count."""
+    import oracle
+    wl = graphgen.WORKLOADS["lfr_3m"]
     t0 = time.time()
-    n, m = 5_000_000, 25_000_000
-    e, comm = graphgen.lfr_style(n, m, gamma=2.3, beta=1.5, mu=0.04, seed=1005, smin=100, smax=100)
+    e, _ = graphgen.make_graph("lfr_3m")
+    print(f"[bench] largest graph: generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    n, m = wl["n"], e.shape[0]
+    c1 = graphgen.hash_coeffs(wl["rows"], wl["sketch_seed"])
+    c2 = graphgen.hash_coeffs(wl["rows"], wl["sketch_seed"] ^ 0x9E3779B97F4A7C15)
+    pos_all = graphgen.initial_positions(n, wl["pos_seed"])
+    dev = torch.device("cuda:0")
+    ed = torch.from_numpy(e).to(dev)
+    pos_d = torch.from_numpy(pos_all).to(dev)
+    ws_cd = bgv.api.community_workspace(ed, n, wl)
+    ws_sg = bgv.api.supergraph_workspace(ed, n, wl)
+
+    def run():
+        labels, degree, _ = bgv.community(ed, n, wl["threshold"], wl["passes"], wl["growth"], wl["chunk"], ws=ws_cd)
+        sg = bgv.supergraph(ed, labels, degree, wl["rows"], wl["cols"], c1, c2, ws=ws_sg)
+        pos = pos_d[: sg["K"]].clone()
+        bgv.fa2_layout(sg["superedges"], pos, wl["fa2_iters"], exact=False, theta=wl["theta"], kr=wl["kr"],
+                       kg=wl["kg"], tau=wl["tau"], ks=wl["ks"], ksmax=wl["ksmax"])
+        return sg
+
+    run()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    sg = run()
+    torch.cuda.synchronize()
+    gpu_ms = 1000.0 * (time.perf_counter() - t)
+    del ed, pos_d
+    torch.cuda.empty_cache()
+    t = time.perf_counter()
+    lab, cnt = oracle.bs_community(n, e, wl["threshold"], wl["passes"], wl["growth"], wl["chunk"])
+    deg, _ = oracle.degree_volume(lab, cnt, wl["passes"])
+    ref = oracle.supergraph(n, e, lab, deg, wl["rows"], wl["cols"], c1, c2)
+    cpu_cd_s = time.perf_counter() - t
+    t = time.perf_counter()
+    oracle.fa2_layout(pos_all[: ref["K"]], ref["superedges"], iters=cpu_fa2_iters, exact=False, theta=wl["theta"])
+    cpu_fa_s = (time.perf_counter() - t) * wl["fa2_iters"] / cpu_fa2_iters
+    cpu_ms = 1000.0 * (cpu_cd_s + cpu_fa_s)
+    return {"nodes": n, "edges": m, "supernodes": sg["K"], "superedges": sg["E"],
+            "supernodes_equal_oracle": bool(sg["K"] == ref["K"]), "fa2_iterations": wl["fa2_iters"],
+            "gpu_end_to_end_ms": gpu_ms, "oracle_end_to_end_ms": cpu_ms,
+            "oracle_sample": f"community + supergraph in full on 1 thread ({cpu_cd_s:.1f}s); {cpu_fa2_iters} "
+                             f"Barnes-Hut iterations scaled to {wl['fa2_iters']}",
+            "speedup_vs_oracle": cpu_ms / gpu_ms}
+
+
+def gradient_form(torch, bgv, graphgen, lrs=(3.0, 10.0, 30.0), max_steps=3000):
+    """The grad_50k workload: weighted supergraph of 50,000 supernodes (planted
+    communities of a 5M-node LFR-style graph; weights from a 5 x 2^22 sketch).  Exact FA2
+    with its adaptive speeds for the workload's iterations vs Adam on the FA2 energy
+    (autograd function with the hand-written gradient) until it reaches the same energy."""
+    wl = graphgen.WORKLOADS["grad_50k"]
+    t0 = time.time()
+    e, comm = graphgen.make_graph("grad_50k")
     print(f"[bench] gradient form: source graph generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     dev = torch.device("cuda:0")
     ed = torch.from_numpy(e).to(dev)
     del e
     lab = torch.from_numpy(comm).to(dev)
-    _, degree, _ = bgv.community(ed, n, 0, 1, 2, 1 << 22)  # threshold 0: degrees only
-    c1 = graphgen.hash_coeffs(5, 0xB16A0005)
-    c2 = graphgen.hash_coeffs(5, 0xB16A0005 ^ 0x9E3779B97F4A7C15)
-    sg = bgv.supergraph(ed, lab, degree, 5, 1 << 22, c1, c2)
+    _, degree, _ = bgv.community(ed, wl["n"], 0, 1, 2, 1 << 22)  # threshold 0: degrees only
+    c1 = graphgen.hash_coeffs(wl["rows"], wl["sketch_seed"])
+    c2 = graphgen.hash_coeffs(wl["rows"], wl["sketch_seed"] ^ 0x9E3779B97F4A7C15)
+    sg = bgv.supergraph(ed, lab, degree, wl["rows"], wl["cols"], c1, c2)
     del ed, lab, degree
     torch.cuda.empty_cache()
     K, E = sg["K"], sg["E"]
     se = sg["superedges"].contiguous()
     w = sg["se_weight"].to(torch.float32).contiguous()
-    pos0 = torch.from_numpy(graphgen.initial_positions(K, 2005, -50.0, 50.0)).to(dev)
+    pos0 = torch.from_numpy(graphgen.initial_positions(K, wl["pos_seed"], wl["pos_lo"], wl["pos_hi"])).to(dev)
+    fa2_iters = wl["fa2_iters"]
     p = pos0.clone()
     ms_fa2 = _timed(torch, lambda: bgv.fa2_layout(se, p, fa2_iters, exact=True, attr_w=w))
     e_fa2 = float(bgv.fa2_energy(se, p, attr_w=w))

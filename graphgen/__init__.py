@@ -285,6 +285,17 @@ WORKLOADS = {
         fa2_iters=300, exact=True, theta=1.2, kr=1.0, kg=1.0, tau=1.0, ks=0.1, ksmax=10.0,
         pos_seed=2004,
     ),
+    # Gradient form: a weighted supergraph of 50,000 supernodes, the planted communities
+    # (all of size 100) of a 5M-node LFR-style graph; mixing 0.04 leaves about 1.0M
+    # distinct inter-community pairs.  Weights are the sketch estimates (5 x 2^22);
+    # exact repulsion; positions uniform in [-50, 50]^2.
+    "grad_50k": dict(
+        kind="lfr", n=5_000_000, m=25_000_000, gamma=2.3, beta=1.5, mu=0.04, graph_seed=1005,
+        smin=100, smax=100,
+        rows=5, cols=1 << 22, sketch_seed=0xB16A0005,
+        fa2_iters=500, exact=True, theta=1.2, kr=1.0, kg=1.0, tau=1.0, ks=0.1, ksmax=10.0,
+        pos_seed=2005, pos_lo=-50.0, pos_hi=50.0,
+    ),
 }
 
 
@@ -294,5 +305,6 @@ def make_graph(name: str):
     if w["kind"] == "planted":
         return planted_partition(w["n"], w["blocks"], w["p_in"], w["p_out"], w["graph_seed"])
     if w["kind"] == "lfr":
-        return lfr_style(w["n"], w["m"], w["gamma"], w["beta"], w["mu"], w["graph_seed"])
+        return lfr_style(w["n"], w["m"], w["gamma"], w["beta"], w["mu"], w["graph_seed"], smin=w.get("smin", 20),
+                         smax=w.get("smax"))
     raise ValueError(name)

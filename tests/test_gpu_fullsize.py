@@ -1,0 +1,130 @@
+"""GPU parity at the full sizes of the named workloads, through the C ABI:
+
+- lfr_3m (3.2M nodes, 34M edges, 3 passes, sketch 5 x 2^22): labels, degrees, volumes,
+  both sketches and the supergraph bit-exact against the oracle; Barnes-Hut forces on the
+  whole supergraph against the oracle's.
+- batched_512 (all 512 graphs in one launch, largest first, 1024-thread workgroups):
+  sampled graphs (the largest, the smallest and four seeded picks) bit-exact against the
+  oracle's integers, their last layout step against one oracle step.
+- grad_50k (50,000 weighted supernodes from a 5M-node graph): the supergraph bit-exact,
+  the gradient against FP64 central finite differences of the oracle's per-node energy
+  on 500 seeded supernodes, and the energy against the oracle's.
+"""
+import numpy as np
+import pytest
+import torch
+
+import graphgen
+import oracle
+from test_gpu_parity import TOL, bh_force_check, check_community, check_supergraph, dev, host, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bgv():
+    import paper_2108_00529_amd as b
+    return b
+
+
+def test_lfr_3m_full_size(bgv):
+    wl = graphgen.WORKLOADS["lfr_3m"]
+    say("  generating lfr_3m ...")
+    e, _ = graphgen.make_graph("lfr_3m")
+    n = wl["n"]
+    lab, deg = check_community(bgv, n, e, wl["threshold"], wl["passes"], wl["growth"], wl["chunk"])
+    sg, ref = check_supergraph(bgv, n, e, lab, deg, wl["rows"], wl["cols"], wl["sketch_seed"])
+    say(f"  lfr_3m supergraph: K={ref['K']} E={len(ref['superedges'])}")
+    pos0 = graphgen.initial_positions(ref["K"], wl["pos_seed"])
+    _, _, bad = bh_force_check(bgv, pos0, ref["superedges"], wl["theta"], "lfr_3m supergraph")
+    assert bad.mean() <= 1e-3
+
+
+def _per_graph(out, noff, eoff, g):
+    n0, e0 = noff[g], eoff[g]
+    K, E = int(out["K"][g]), int(out["E"][g])
+    return dict(labels=host(out["labels"][n0:noff[g + 1]]), degree=host(out["degree"][n0:noff[g + 1]]), K=K,
+                super_label=host(out["super_label"][n0:n0 + K]),
+                super_size=host(out["super_size"][n0:n0 + K]).view(np.uint32),
+                superedges=host(out["superedges"][e0:e0 + E]), se_weight=host(out["se_weight"][e0:e0 + E]).view(np.uint32),
+                pos=host(out["pos"][n0:n0 + K]), fprev=host(out["fprev"][n0:n0 + K]), speed=float(out["speed"][g]))
+
+
+def test_batched_512_full_size_sampled(bgv):
+    wl = graphgen.WORKLOADS["batched_512"]
+    graphs = graphgen.batched_planted(wl["G"], wl["graph_seed"])
+    c1 = graphgen.hash_coeffs(wl["rows"], wl["sketch_seed"])
+    c2 = graphgen.hash_coeffs(wl["rows"], wl["sketch_seed"] ^ 0x9E3779B97F4A7C15)
+    pos0 = [graphgen.initial_positions(n, wl["pos_seed"] + g) for g, (n, _, _) in enumerate(graphs)]
+    d = torch.device("cuda")
+    edges, noff, eoff, noff_h, eoff_h = bgv.pack_graphs([(n, e) for n, e, _ in graphs], d)
+    order = torch.from_numpy(np.argsort(-np.diff(eoff_h), kind="stable").astype(np.int32)).to(d)
+    T = wl["fa2_iters"]
+    runs = {}
+    for iters in (T - 1, T):
+        pos = torch.from_numpy(np.concatenate(pos0)).to(d)
+        runs[iters] = bgv.batched(edges, noff, eoff, int(noff_h[-1]), dict(wl, fa2_iters=iters), c1, c2, pos,
+                                  order=order, wg_threads=1024)
+        torch.cuda.synchronize()
+    sizes = np.diff(eoff_h)
+    rng = np.random.default_rng(5)
+    sample = [int(np.argmax(sizes)), int(np.argmin(sizes))] + [int(g) for g in rng.choice(len(graphs), 4, replace=False)]
+    for g in sample:
+        n, e, _ = graphs[g]
+        a = _per_graph(runs[T - 1], noff_h, eoff_h, g)
+        b = _per_graph(runs[T], noff_h, eoff_h, g)
+        lab, cnt = oracle.bs_community(n, e, wl["threshold"], wl["passes"], wl["growth"], wl["chunk"])
+        deg, _ = oracle.degree_volume(lab, cnt, wl["passes"])
+        ref = oracle.supergraph(n, e, lab, deg, wl["rows"], wl["cols"], c1, c2)
+        np.testing.assert_array_equal(b["labels"], lab)
+        np.testing.assert_array_equal(b["degree"], deg)
+        assert b["K"] == ref["K"]
+        np.testing.assert_array_equal(b["super_label"], ref["super_label"])
+        np.testing.assert_array_equal(b["super_size"], ref["super_size"])
+        np.testing.assert_array_equal(b["superedges"], ref["superedges"])
+        np.testing.assert_array_equal(b["se_weight"], ref["se_weight"])
+        r1, _, _ = oracle.fa2_layout(a["pos"], a["superedges"], iters=1, exact=True, kr=wl["kr"], kg=wl["kg"],
+                                     Fprev=a["fprev"], speed=a["speed"])
+        err = np.linalg.norm(b["pos"] - r1, axis=1).max() / np.linalg.norm(r1 - r1.mean(0), axis=1).max()
+        say(f"  graph {g}: n={n} m={len(e)} K={b['K']} last-step error {err:.2e}")
+        assert err <= TOL
+
+
+def test_grad_50k_full_size(bgv):
+    wl = graphgen.WORKLOADS["grad_50k"]
+    say("  generating grad_50k source graph ...")
+    e, comm = graphgen.make_graph("grad_50k")
+    n = wl["n"]
+    ed = dev(e)
+    _, degree, _ = bgv.community(ed, n, 0, 1, 2, 1 << 22)
+    deg_ref = np.bincount(e[e[:, 0] != e[:, 1]].ravel(), minlength=n).astype(np.int32)
+    np.testing.assert_array_equal(host(degree), deg_ref)
+    sg, ref = check_supergraph(bgv, n, e, comm.astype(np.int32), deg_ref, wl["rows"], wl["cols"], wl["sketch_seed"])
+    K, se = ref["K"], ref["superedges"]
+    say(f"  grad_50k supergraph: K={K} E={len(se)}")
+    assert K == 50_000
+    w32 = ref["se_weight"].astype(np.float32)
+    pos = graphgen.initial_positions(K, wl["pos_seed"], wl["pos_lo"], wl["pos_hi"])
+    g = host(bgv.fa2_grad(dev(se), dev(pos), wl["kr"], wl["kg"], attr_w=dev(w32))).astype(np.float64)
+    mass = oracle.fa2_mass(K, se)
+    x = pos.astype(np.float64)
+    aw = w32.astype(np.float64)
+    nodes = np.random.default_rng(50).choice(K, 500, replace=False)
+    h = 1e-4
+    fd = np.zeros((len(nodes), 2))
+    for r, i in enumerate(nodes):
+        for c in range(2):
+            xp = x.copy()
+            xp[i, c] += h
+            xm = x.copy()
+            xm[i, c] -= h
+            fd[r, c] = (oracle.fa2_node_energy(xp, se, mass, i, aw, wl["kr"], wl["kg"]) -
+                        oracle.fa2_node_energy(xm, se, mass, i, aw, wl["kr"], wl["kg"])) / (2 * h)
+    err = np.linalg.norm(g[nodes] - fd, axis=1)
+    scale = np.linalg.norm(fd, axis=1).max()
+    say(f"  gradient vs FP64 finite differences on 500 supernodes: max err/scale {err.max() / scale:.2e}")
+    assert err.max() <= TOL * scale
+    e_gpu = float(bgv.fa2_energy(dev(se), dev(pos), wl["kr"], wl["kg"], attr_w=dev(w32)))
+    e_ref = oracle.fa2_energy(x, se, mass, aw, wl["kr"], wl["kg"])
+    say(f"  energy gpu {e_gpu:.10g} oracle {e_ref:.10g}")
+    assert abs(e_gpu - e_ref) <= TOL * abs(e_ref)
