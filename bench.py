@@ -26,7 +26,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-PROFILE_SAMPLE = 10            # timed steps bracket one in this many dominant-kernel launches
+PROFILE_SAMPLE = 1             # timed steps time one in this many dominant-kernel launches
 FP32_PEAK_TFLOPS = 157.3       # MI355X vector FP32, published
 
 
@@ -42,6 +42,8 @@ def parse():
                     help="skip the batched, gradient and largest-graph comparisons")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="do not bracket launches with HIP events (for hardware-counter runs)")
+    ap.add_argument("--profile-sample", type=int, default=PROFILE_SAMPLE, metavar="N",
+                    help="time one in N launches of the dominant kernel in the timed steps")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (5 times), to scale HBM counters")
     return ap.parse_args()
@@ -130,11 +132,11 @@ def main():
         dominant = max(kbreak.items(), key=lambda kv: kv[1]["total_ms"])[0] if kbreak else None
         print(f"[bench] breakdown step done; dominant kernel {dominant}", file=sys.stderr, flush=True)
 
-    # timed steps: events only around one in PROFILE_SAMPLE launches of the dominant
-    # kernel, so the rest runs unbracketed
+    # timed steps: start/stop events on the launches of the dominant kernel only (one in
+    # --profile-sample of them), so the rest runs without events
     prof.reset()
     prof.only(dominant)
-    prof.sample(PROFILE_SAMPLE)
+    prof.sample(args.profile_sample)
     prof.enable(dominant is not None)
     cd_ms, fa_ms = [], []
     torch.cuda.synchronize()
@@ -156,6 +158,10 @@ def main():
             # the counter covers every launch of the timed steps, not only the sampled ones
             kstats[k]["bh_interactions_per_launch"] = inter / (args.steps * wl["fa2_iters"])
     print(f"[bench] timed {args.steps} steps in {t_total:.2f}s", file=sys.stderr, flush=True)
+    # one more step with no kernel events at all: the layout rate without measurement
+    step(record=True)
+    ev["c"].synchronize()
+    fa_unprofiled = ev["b"].elapsed_time(ev["c"])
 
     ms_per_step = 1000.0 * t_total / args.steps
     cd = float(np.mean(cd_ms))
@@ -185,6 +191,7 @@ def main():
                    "nodes": n, "edges": m, "supernodes": K, "superedges": E},
         "parts": {"community_sketch_ms": cd, "fa2_ms": fa,
                   "fa2_iters_per_s": wl["fa2_iters"] / (fa / 1000.0),
+                  "fa2_iters_per_s_without_kernel_events": wl["fa2_iters"] / (fa_unprofiled / 1000.0),
                   "pipeline_edges_per_s": m / ((cd + fa) / 1000.0)},
         "roofline": roofline,
         **extra,

@@ -1,11 +1,11 @@
 /*
  * bgv_profile.h -- optional per-kernel timing of libbgv launches.
  *
- * When enabled, every kernel launch of the library is bracketed by two HIP events
- * recorded on the stream the kernel is launched on, so a caller can obtain the
- * average device duration of each kernel over a region of its own.  Disabled by
- * default; enabling adds two event records per launch.  Not thread-safe across
- * concurrent callers of enable/reset.
+ * When enabled, kernel launches of the library carry a start and a stop HIP event that
+ * the launch itself records (hipExtLaunchKernelGGL on the kernel's stream), so the
+ * events hold the kernel's own execution interval, and a caller can obtain the average
+ * device duration of each kernel over a region of its own.  Disabled by default.  Not
+ * thread-safe across concurrent callers of enable/reset.
  */
 #ifndef BGV_PROFILE_H
 #define BGV_PROFILE_H

@@ -1,6 +1,7 @@
 // Internal helpers shared by the HIP translation units of libbgv (gfx950 only).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -28,19 +29,31 @@ void clear_error();
 #define BGV_CHECK_LAUNCH() BGV_CHECK_HIP(hipGetLastError())
 
 // Optional per-kernel event timing and counters (include/bgv_profile.h).
+struct ProfPair {
+    hipEvent_t start, stop;
+    void *stat;
+};
 bool prof_on();
 int prof_read_counter(const char *name, uint64_t *value);
 void prof_reset_counters();
-void *prof_begin(const char *name, hipStream_t s);
-void prof_end(void *token, hipStream_t s);
+// True if this launch of `name` is to be timed; then *p holds the two events.
+bool prof_take(const char *name, ProfPair *p);
+void prof_commit(const ProfPair &p);
 
-// Launch + error check; brackets the launch with events when profiling is enabled.
-#define BGV_LAUNCH(kernel, grid, block, shmem, stream, ...)                                \
-    do {                                                                                   \
-        void *_bgv_tok = ::bgv::prof_on() ? ::bgv::prof_begin(#kernel, (stream)) : nullptr; \
-        hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);               \
-        BGV_CHECK_LAUNCH();                                                                \
-        if (_bgv_tok) ::bgv::prof_end(_bgv_tok, (stream));                                 \
+// Launch + error check.  A timed launch passes its events to the launch itself
+// (hipExtLaunchKernelGGL), so they carry the kernel's own start and end times and no
+// host-side gap before the dispatch.
+#define BGV_LAUNCH(kernel, grid, block, shmem, stream, ...)                                              \
+    do {                                                                                                 \
+        ::bgv::ProfPair _bgv_p;                                                                          \
+        const bool _bgv_t = ::bgv::prof_on() && ::bgv::prof_take(#kernel, &_bgv_p);                      \
+        if (_bgv_t)                                                                                      \
+            hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, _bgv_p.start, _bgv_p.stop, 0u,     \
+                                  __VA_ARGS__);                                                          \
+        else                                                                                             \
+            hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                         \
+        BGV_CHECK_LAUNCH();                                                                              \
+        if (_bgv_t) ::bgv::prof_commit(_bgv_p);                                                          \
     } while (0)
 
 #define BGV_TRY(expr)                                                                    \

@@ -1,5 +1,5 @@
 // Optional per-kernel event timing (include/bgv_profile.h): host-side registry of
-// (start, stop) HIP event pairs recorded around library launches.  Completed pairs are
+// (start, stop) HIP event pairs attached to library launches.  Completed pairs are
 // harvested as new events are needed, so the number of live events stays near the
 // number of launches in flight instead of growing with the length of the run.
 #include <cstring>
@@ -82,33 +82,26 @@ void resolve_all() {
 
 bool prof_on() { return g_on; }
 
-struct Token {
-    KStat *stat;
-    hipEvent_t a;
-};
-
-void *prof_begin(const char *name, hipStream_t s) {
+bool prof_take(const char *name, ProfPair *p) {
     std::lock_guard<std::mutex> lk(g_mu);
-    if (!g_filter.empty() && std::strncmp(name, g_filter.c_str(), g_filter.size()) != 0)
-        return nullptr;
-    if (g_every > 1 && (g_seen++ % g_every) != 0) return nullptr;
+    if (!g_filter.empty() && std::strncmp(name, g_filter.c_str(), g_filter.size()) != 0) return false;
+    if (g_every > 1 && (g_seen++ % g_every) != 0) return false;
     hipEvent_t a = take_event();
-    if (!a) return nullptr;
-    hipEventRecord(a, s);
-    return new Token{&g_stats[name], a};
+    if (!a) return false;
+    hipEvent_t b = take_event();
+    if (!b) {
+        g_pool.push_back(a);
+        return false;
+    }
+    p->start = a;
+    p->stop = b;
+    p->stat = &g_stats[name];
+    return true;
 }
 
-void prof_end(void *token, hipStream_t s) {
-    Token *t = static_cast<Token *>(token);
+void prof_commit(const ProfPair &p) {
     std::lock_guard<std::mutex> lk(g_mu);
-    hipEvent_t b = take_event();
-    if (b) {
-        hipEventRecord(b, s);
-        g_pending.push_back({t->stat, t->a, b});
-    } else {
-        g_pool.push_back(t->a);
-    }
-    delete t;
+    g_pending.push_back({static_cast<KStat *>(p.stat), p.start, p.stop});
 }
 
 }  // namespace bgv

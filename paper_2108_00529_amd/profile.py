@@ -1,5 +1,5 @@
-"""Per-kernel device timing of libbgv launches (include/bgv_profile.h): HIP events
-recorded on the launching stream around every library kernel while enabled."""
+"""Per-kernel device timing of libbgv launches (include/bgv_profile.h): start and stop
+HIP events attached to library kernel launches while enabled."""
 from __future__ import annotations
 
 import ctypes as C
