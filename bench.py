@@ -488,7 +488,7 @@ def measured_traffic(kernel: str):
         text = open(summary).read()
     except OSError:
         return None
-    m_hash = re.search(r"kernel sources when measured: ([0-9a-f]{16})", text)
+    m_hash = re.search(r"kernel sources when measured: ([0-9a-f]{16})", text, re.IGNORECASE)
     if not m_hash or m_hash.group(1) != csrc_digest():
         return None
     m_bytes = re.search(r"traffic_bytes_per_launch\[" + re.escape(kernel) + r"\]: (\d+)", text)
