@@ -18,22 +18,23 @@ __global__ void k_sg_flag(const int32_t *__restrict__ labels, int32_t n, uint32_
         flag[labels[v]] = 1u;
 }
 
+// Flags as above, plus each community's volume vol[c] = sum of d(v) over its nodes
+// (below 2^32: at most twice the number of edges).
+__global__ void k_sg_flag_volume(const int32_t *__restrict__ labels, const int32_t *__restrict__ degree, int32_t n,
+                                 uint32_t *__restrict__ flag, uint32_t *__restrict__ vol) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t lab = labels[v];
+        flag[lab] = 1u;
+        const uint32_t d = (uint32_t)degree[v];
+        if (d) atomicAdd(&vol[lab], d);
+    }
+}
+
 // flag[] still holds the 0/1 flags; sid[] is its exclusive scan.
 __global__ void k_sg_compact(const uint32_t *__restrict__ flag, const uint32_t *__restrict__ sid, int32_t n,
                              int32_t *__restrict__ super_label) {
     for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x)
         if (flag[c]) super_label[sid[c]] = (int32_t)c;
-}
-
-// Sketch 1, global-memory counters (any width).
-__global__ void k_sg_sketch_nodes(const int32_t *__restrict__ labels, const int32_t *__restrict__ degree,
-                                  int32_t n, HashRows h, int32_t rows, uint32_t cols, uint32_t *__restrict__ M1) {
-    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t d = (uint32_t)degree[v];
-        if (d == 0) continue;
-        const uint32_t lab = (uint32_t)labels[v];
-        for (int r = 0; r < rows; ++r) atomicAdd(&M1[(size_t)r * cols + col_key(h.a[r], h.b[r], lab, cols)], d);
-    }
 }
 
 // Sketch 1 with the whole sketch privatised in LDS (rows*cols <= kLdsCounters).
@@ -55,6 +56,21 @@ __global__ void __launch_bounds__(kSgThreads) k_sg_sketch_nodes_lds(const int32_
     __syncthreads();
     for (int i = threadIdx.x; i < total; i += blockDim.x)
         if (loc[i]) atomicAdd(&M1[i], loc[i]);
+}
+
+// Sketch 1 from the community volumes: M1[r][h_r(c)] += vol[c] once per community c,
+// the same integer sums as adding d(v) once per node (a quarter of the atomics and
+// fewer: one per community and row instead of one per node and row).
+__global__ void k_sg_sketch_volumes(const int32_t *__restrict__ super_label, const uint32_t *__restrict__ Kp,
+                                    const uint32_t *__restrict__ vol, HashRows h, int32_t rows, uint32_t cols,
+                                    uint32_t *__restrict__ M1) {
+    const int64_t K = *Kp;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < K; k += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t lab = (uint32_t)super_label[k];
+        const uint32_t v = vol[lab];
+        if (v == 0) continue;
+        for (int r = 0; r < rows; ++r) atomicAdd(&M1[(size_t)r * cols + col_key(h.a[r], h.b[r], lab, cols)], v);
+    }
 }
 
 __global__ void k_sg_super_size(const int32_t *__restrict__ super_label, const uint32_t *__restrict__ Kp,
@@ -170,7 +186,7 @@ __global__ void k_sg_node_super(const int32_t *__restrict__ labels, const uint32
 }
 
 struct SgWs {
-    uint32_t *flag, *sid, *counters, *uflag, *upos, *run_start;
+    uint32_t *flag, *sid, *vol, *counters, *uflag, *upos, *run_start;
     uint64_t *keys, *keys_alt;
     void *scan_scratch, *sort_scratch;
 };
@@ -179,6 +195,7 @@ static size_t sg_layout(Carver &c, int32_t n, int64_t m, SgWs *w) {
     const int64_t mm = m > 0 ? m : 1;
     w->flag = c.take<uint32_t>((size_t)n);
     w->sid = c.take<uint32_t>((size_t)n);
+    w->vol = c.take<uint32_t>((size_t)n);
     w->counters = c.take<uint32_t>(8);  // [0] K, [1] E_S, [2..3] key count (u64, 8-byte aligned)
     w->keys = c.take<uint64_t>((size_t)mm);
     w->keys_alt = c.take<uint64_t>((size_t)mm);
@@ -236,21 +253,30 @@ extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges,
     const unsigned gn = grid_for(n, kSgThreads, 65536);
 
     // supernodes
+    // a sketch small enough for LDS takes the node degrees directly; a larger one is
+    // filled from the communities' volumes
+    const int64_t cells = (int64_t)rows * cols;
+    const bool lds_sketch = cells <= kLdsCounters;
     BGV_TRY(fill<uint32_t>(w.flag, 0u, n, s));
     BGV_TRY(fill<uint32_t>(w.counters, 0u, 8, s));
-    BGV_LAUNCH(k_sg_flag, dim3(gn), dim3(kSgThreads), 0, s, labels, n, w.flag);
+    if (lds_sketch) {
+        BGV_LAUNCH(k_sg_flag, dim3(gn), dim3(kSgThreads), 0, s, labels, n, w.flag);
+    } else {
+        BGV_TRY(fill<uint32_t>(w.vol, 0u, n, s));
+        BGV_LAUNCH(k_sg_flag_volume, dim3(gn), dim3(kSgThreads), 0, s, labels, degree, n, w.flag, w.vol);
+    }
     BGV_TRY(exclusive_scan_u32(w.flag, w.sid, n, &w.counters[0], w.scan_scratch, s));
     BGV_LAUNCH(k_sg_compact, dim3(gn), dim3(kSgThreads), 0, s, w.flag, w.sid, n, super_label);
 
     // sketch 1 and sizes
-    const int64_t cells = (int64_t)rows * cols;
     BGV_TRY(fill<uint32_t>(M1, 0u, cells, s));
     BGV_TRY(fill<uint32_t>(M2, 0u, cells, s));
-    if (cells <= kLdsCounters) {
+    if (lds_sketch) {
         BGV_LAUNCH(k_sg_sketch_nodes_lds, dim3(grid_for(n, kSgThreads * 16, 1024)), dim3(kSgThreads), 0, s,
                    labels, degree, n, h1, rows, cols, M1);
     } else {
-        BGV_LAUNCH(k_sg_sketch_nodes, dim3(gn), dim3(kSgThreads), 0, s, labels, degree, n, h1, rows, cols, M1);
+        BGV_LAUNCH(k_sg_sketch_volumes, dim3(gn), dim3(kSgThreads), 0, s, super_label, &w.counters[0], w.vol, h1,
+                   rows, cols, M1);
     }
     BGV_LAUNCH(k_sg_super_size, dim3(gn), dim3(kSgThreads), 0, s, super_label, &w.counters[0], h1, rows, cols,
                        M1, super_size);
