@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched, gradient and largest-graph comparisons")
     ap.add_argument("--no-kernel-timing", action="store_true",
-                    help="do not bracket launches with HIP events (for hardware-counter runs)")
+                    help="do not time launches with HIP events (for hardware-counter runs)")
     ap.add_argument("--profile-sample", type=int, default=PROFILE_SAMPLE, metavar="N",
                     help="time one in N launches of the dominant kernel in the timed steps")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -117,7 +117,7 @@ def main():
     torch.cuda.synchronize()
     print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
 
-    # one untimed step with every kernel bracketed by events: the per-kernel breakdown,
+    # one untimed step with every kernel launch timed by events: the per-kernel breakdown,
     # and which kernel dominates the device time
     kbreak = {}
     dominant = None
@@ -436,7 +436,7 @@ def roofline_of(name, avg_s, K, E, inter_per_launch=None):
 
 def roofline_report(kstats, kbreak, wl, n, m, K, E):
     """Roofline of the dominant kernel, from the events recorded around it in the timed
-    steps (kstats), plus the per-kernel breakdown of one untimed fully bracketed step
+    steps (kstats), plus the per-kernel breakdown of one untimed step with every launch timed
     (kbreak) with each layout kernel's roofline and the community passes' edge-stream
     rate."""
     if not kstats:

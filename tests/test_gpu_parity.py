@@ -366,8 +366,8 @@ def test_bh_one_step_random(bgv):
 
 
 def test_profile_filter_and_results_unchanged(bgv):
-    """Kernel timing is measurement only: with every launch bracketed, with only the
-    force kernel bracketed, or with none, the layout is bit for bit the same; the filter
+    """Kernel timing is measurement only: with every launch timed, with only the force
+    kernel timed, or with none, the layout is bit for bit the same; the filter
     limits the recorded kernels to the named one."""
     from paper_2108_00529_amd import profile as prof
     rng = np.random.default_rng(11)
