@@ -37,7 +37,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="lfr_1m")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    ap.add_argument("--cpu-fa2-iters", type=int, default=20)
+    ap.add_argument("--cpu-fa2-iters", type=int, default=500,
+                    help="layout iterations the CPU oracle runs for the baseline (the workload has 500)")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched, gradient and largest-graph comparisons")
     ap.add_argument("--no-kernel-timing", action="store_true",
@@ -201,7 +202,8 @@ def main():
     if not args.no_forms:
         del edges, pos0
         torch.cuda.empty_cache()
-        out["forms"] = {"batched": batched_form(torch, bgv, graphgen),
+        out["forms"] = {"small_graph": small_graph_form(torch, bgv, graphgen),
+                        "batched": batched_form(torch, bgv, graphgen),
                         "gradient": gradient_form(torch, bgv, graphgen),
                         "largest_graph": largest_graph_form(torch, bgv, graphgen)}
     print(json.dumps(out))
@@ -284,6 +286,48 @@ def batched_form(torch, bgv, graphgen):
             "speedup_vs_sequential": seq_ms / min(eager_ms, graph_ms),
             "graphs_per_s": G / (min(eager_ms, graph_ms) / 1000.0),
             "supernodes_equal": bool(np.array_equal(K_b, np.array(K_p)))}
+
+
+def small_graph_form(torch, bgv, graphgen, repeats=5):
+    """The planted_2k workload (2,000 nodes, ~11k edges, 1 pass with 256-edge chunks,
+    200 exact layout iterations) end to end: through the plain entry points (a launch or
+    more per chunk and per iteration) and as a one-graph batch (the whole path in one
+    persistent launch).  Median wall time of `repeats` runs each, same outputs."""
+    wl = graphgen.WORKLOADS["planted_2k"]
+    e, _ = graphgen.make_graph("planted_2k")
+    n = wl["n"]
+    c1 = graphgen.hash_coeffs(wl["rows"], wl["sketch_seed"])
+    c2 = graphgen.hash_coeffs(wl["rows"], wl["sketch_seed"] ^ 0x9E3779B97F4A7C15)
+    dev = torch.device("cuda:0")
+    ed = torch.from_numpy(e).to(dev)
+    pos0 = torch.from_numpy(graphgen.initial_positions(n, wl["pos_seed"])).to(dev)
+    edges_b, noff, eoff, noff_h, _ = bgv.pack_graphs([(n, e)], dev)
+
+    def plain():
+        return bgv.pipeline(ed, n, wl, c1, c2, pos0)
+
+    def batched():
+        return bgv.batched(edges_b, noff, eoff, n, wl, c1, c2, pos0.clone(), wg_threads=1024)
+
+    def wall(fn):
+        ts = []
+        for _ in range(repeats):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            ts.append(1000.0 * (time.perf_counter() - t))
+        return float(np.median(ts)), out
+
+    plain()
+    batched()
+    plain_ms, po = wall(plain)
+    batch_ms, bo = wall(batched)
+    K = po["sg"]["K"]
+    same = bool(int(bo["K"][0]) == K and torch.equal(bo["pos"][:K], po["pos"]))
+    return {"nodes": n, "edges": int(e.shape[0]), "supernodes": K, "fa2_iterations": wl["fa2_iters"],
+            "plain_ms": plain_ms, "one_graph_batch_ms": batch_ms, "speedup": plain_ms / batch_ms,
+            "fa2_iters_per_s_in_batch": wl["fa2_iters"] / (batch_ms / 1000.0), "same_positions": same}
 
 
 def largest_graph_form(torch, bgv, graphgen, cpu_fa2_iters=10):
