@@ -370,7 +370,9 @@ __global__ void __launch_bounds__(NT) k_batched(BtArgs a) {
                     }
                     __syncthreads();
                     const uint32_t c = min((uint32_t)NT, K - j0);
-                    for (uint32_t q = 0; q < c; ++q) fa2_rep_term(xi, tile[q], sx, sy);
+                    const uint32_t c8 = c & ~7u;  // groups of eight LDS reads in flight, then the rest
+                    fa2_rep_run(xi, tile, (int)c8, sx, sy);
+                    for (uint32_t q = c8; q < c; ++q) fa2_rep_term(xi, tile[q], sx, sy);
                     __syncthreads();
                 }
                 if (K <= (uint32_t)kRepSegment) {
