@@ -241,8 +241,8 @@ def batched_form(torch, bgv, graphgen):
           file=sys.stderr, flush=True)
     order = torch.from_numpy(np.argsort(-np.diff(eoff_h), kind="stable").astype(np.int32)).to(dev)
     pos_init = torch.from_numpy(np.concatenate(pos0)).to(dev)
-    wg, tune = autotune.tune_batched(edges, noff, eoff, n_total, wl, c1, c2, pos_init, order=order, repeats=1,
-                                     use_cache=False)
+    (wg, big_k), tune = autotune.tune_batched(edges, noff, eoff, n_total, wl, c1, c2, pos_init, order=order,
+                                              repeats=1, use_cache=False)
     ws = bgv.batched_workspace(G, n_total, m_total, dev)
     pos = pos_init.clone()
     fprev = torch.zeros_like(pos)
@@ -253,7 +253,7 @@ def batched_form(torch, bgv, graphgen):
         fprev.zero_()
         speed.fill_(1.0)
         return bgv.batched(edges, noff, eoff, n_total, wl, c1, c2, pos, order=order, fprev=fprev, speed=speed,
-                           wg_threads=wg, ws=ws)
+                           wg_threads=wg, big_k=big_k, ws=ws)
 
     run_batched()
     eager_ms = _timed(torch, run_batched, repeats=3)
@@ -281,7 +281,7 @@ def batched_form(torch, bgv, graphgen):
         K_p.append(o["sg"]["K"])
     torch.cuda.synchronize()
     seq_ms = 1000.0 * (time.perf_counter() - t)
-    return {"graphs": G, "nodes": n_total, "edges": m_total, "wg_threads": wg, "autotune_ms": tune["ms"],
+    return {"graphs": G, "nodes": n_total, "edges": m_total, "wg_threads": wg, "big_k": big_k, "autotune_ms": tune["ms"],
             "batched_ms": eager_ms, "batched_graph_replay_ms": graph_ms, "sequential_plain_ms": seq_ms,
             "speedup_vs_sequential": seq_ms / min(eager_ms, graph_ms),
             "graphs_per_s": G / (min(eager_ms, graph_ms) / 1000.0),

@@ -209,8 +209,8 @@ bgv_status bgv_fa2_grad(int32_t K, int64_t E, const int32_t *edges, const float 
 /* ---------------------------------------------------------------------------- */
 /*
  * The whole path above (community passes, count-min supergraph, exact ForceAtlas2) for
- * G graphs at once; graph g is processed by one workgroup from start to end, graphs are
- * taken from a queue in `order` (e.g. largest first; NULL = 0..G-1).  Per graph the
+ * G graphs at once; graph g is processed by one workgroup from start to end (but see
+ * big_k), graphs are taken from a queue in `order` (e.g. largest first; NULL = 0..G-1).  Per graph the
  * results equal those of bgv_community + bgv_supergraph + bgv_fa2_layout (exact
  * repulsion, attraction weights 1, masses = degree + 1), with the same parameters.
  *
@@ -219,7 +219,12 @@ bgv_status bgv_fa2_grad(int32_t K, int64_t E, const int32_t *edges, const float 
  * node_off[G] = n_total, edge_off[G] = m_total); its edges use local ids in
  * [0, n_g).  Sketch shape: rows * cols <= 8192 (each graph's sketches live in LDS).
  * fa->exact must be 1.  wg_threads: 256, 512 or 1024 (0 = 512), a launch parameter that
- * does not change any result.
+ * does not change any result.  big_k >= 0, another such parameter: a graph whose
+ * supergraph has more than big_k nodes (and at most 4096) is laid out after the
+ * persistent launch by kernels that spread each graph's tiles over many workgroups
+ * (a fixed sequence of three launches per iteration, sizes read on the device), so that
+ * a few large graphs do not each hold one compute unit for the whole layout; 0 keeps
+ * every layout in the persistent launch.
  * Outputs (dev; per-node arrays indexed from node_off[g], per-edge arrays from
  * edge_off[g]): labels, degree int32[n_total]; K, E_S int32[G]; super_label int32 and
  * super_size uint32 [n_total] (first K[g] entries of each graph); superedges int32
@@ -232,7 +237,7 @@ size_t bgv_batched_workspace(int32_t G, int64_t n_total, int64_t m_total);
 bgv_status bgv_batched(int32_t G, int64_t n_total, int64_t m_total, const int64_t *node_off,
                        const int64_t *edge_off, const int32_t *order, const int32_t *edges,
                        const bgv_cd_params *cd, const bgv_sketch_params *sk, const bgv_fa2_params *fa,
-                       int32_t wg_threads, int32_t *labels, int32_t *degree, int32_t *K, int32_t *E_S,
+                       int32_t wg_threads, int32_t big_k, int32_t *labels, int32_t *degree, int32_t *K, int32_t *E_S,
                        int32_t *super_label, uint32_t *super_size, int32_t *superedges,
                        uint32_t *se_weight, float *pos, float *fprev, float *speed,
                        void *ws, size_t ws_bytes, bgv_stream_t stream);

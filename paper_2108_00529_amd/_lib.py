@@ -65,7 +65,7 @@ bgv_fa2_grad = _sig("bgv_fa2_grad", i32, [i32, i64, P, P, P, P, f32, f32, P, P, 
 
 bgv_batched_workspace = _sig("bgv_batched_workspace", SZ, [i32, i64, i64])
 bgv_batched = _sig("bgv_batched", i32, [i32, i64, i64, P, P, P, P, C.POINTER(CdParams), C.POINTER(SketchParams),
-                                        C.POINTER(Fa2Params), i32, P, P, P, P, P, P, P, P, P, P, P, P, SZ, P])
+                                        C.POINTER(Fa2Params), i32, i32, P, P, P, P, P, P, P, P, P, P, P, P, SZ, P])
 
 EXPORTED = ["bgv_status_string", "bgv_last_error", "bgv_community_workspace", "bgv_community",
             "bgv_supergraph_workspace", "bgv_supergraph", "bgv_fa2_workspace", "bgv_fa2_layout",

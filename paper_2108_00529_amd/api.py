@@ -257,10 +257,11 @@ def pack_graphs(graphs, device):
 def batched(edges: torch.Tensor, node_off: torch.Tensor, edge_off: torch.Tensor, n_total: int, wl: dict,
             coef1: np.ndarray, coef2: np.ndarray, pos: torch.Tensor, order: torch.Tensor | None = None,
             fprev: torch.Tensor | None = None, speed: torch.Tensor | None = None, wg_threads: int = 0,
-            ws: torch.Tensor | None = None, stream=None):
+            big_k: int = 0, ws: torch.Tensor | None = None, stream=None):
     """The whole path for G graphs in one persistent launch (include/bgv.h,
-    bgv_batched).  pos (n_total, 2) float32 holds each graph's initial positions and is
-    updated in place.  Returns a dict of device tensors."""
+    bgv_batched); with big_k > 0, supergraphs larger than big_k nodes are laid out by
+    multi-workgroup kernels after it.  pos (n_total, 2) float32 holds each graph's
+    initial positions and is updated in place.  Returns a dict of device tensors."""
     G = node_off.shape[0] - 1
     m_total = edges.shape[0]
     dev = edges.device
@@ -297,7 +298,8 @@ def batched(edges: torch.Tensor, node_off: torch.Tensor, edge_off: torch.Tensor,
                superedges=torch.empty((mm, 2), dtype=torch.int32, device=dev),
                se_weight=torch.empty(mm, dtype=torch.int32, device=dev))
     L.check(L.bgv_batched(int(G), int(n_total), int(m_total), _ptr(node_off), _ptr(edge_off), _ptr(order),
-                          _ptr(edges), C.byref(cd), C.byref(sp), C.byref(fa), int(wg_threads), _ptr(out["labels"]),
+                          _ptr(edges), C.byref(cd), C.byref(sp), C.byref(fa), int(wg_threads), int(big_k),
+                          _ptr(out["labels"]),
                           _ptr(out["degree"]), _ptr(out["K"]), _ptr(out["E"]), _ptr(out["super_label"]),
                           _ptr(out["super_size"]), _ptr(out["superedges"]), _ptr(out["se_weight"]), _ptr(pos),
                           _ptr(fprev), _ptr(speed), _ptr(ws), ws.numel(), _stream(stream)), "bgv_batched")

@@ -47,6 +47,11 @@ struct BtArgs {
     float2 *F, *att;
     double2 *vpart;         // floor(n_total/256) + G + 1
     unsigned int *queue;
+    // graphs with more than big_k supernodes (and at most one repulsion segment) are
+    // listed in big[0, *nbig) and laid out afterwards by the k_bt_* kernels; 0: none
+    int32_t big_k;
+    int32_t *big;
+    unsigned int *nbig;
 };
 
 // Exclusive scan of in[0, n) into out (may alias); returns the total.
@@ -330,6 +335,13 @@ __global__ void __launch_bounds__(NT) k_batched(BtArgs a) {
         __syncthreads();
         float *mass = a.mass + n0;
         for (uint32_t i = t; i < K; i += NT) mass[i] = (float)(row[i + 1] - row[i]) + 1.0f;
+        if (a.big_k > 0 && a.iters > 0 && K > (uint32_t)a.big_k && K <= (uint32_t)kRepSegment) {
+            // a large supergraph is laid out by the multi-workgroup kernels afterwards,
+            // so that it does not hold one compute unit for the whole layout
+            if (t == 0) a.big[atomicAdd(a.nbig, 1u)] = g;
+            __syncthreads();
+            continue;
+        }
 
         // ---- exact ForceAtlas2 iterations -------------------------------------------
         float2 *pos = a.pos + n0, *fprev = a.fprev + n0, *F = a.F + n0, *att = a.att + n0;
@@ -414,6 +426,120 @@ __global__ void __launch_bounds__(NT) k_batched(BtArgs a) {
     }
 }
 
+// ---- layout of the listed large graphs, all of them per launch ------------------
+// Work items are the listed graphs' CSR rows (attraction) or 256-node tiles (forces,
+// update), numbered through exclusive prefix sums over the list; an item finds its
+// graph by binary search.  Each graph goes through exactly the plain path's tile
+// functions, so its result equals a plain layout of it bit for bit.
+struct BtBig {
+    const int64_t *node_off, *edge_off;
+    const int32_t *K;
+    const int32_t *big;
+    const unsigned int *nbig;
+    uint32_t *tile_off, *row_off;  // G+1 each: prefix sums of tiles / rows over the list
+    const uint32_t *row;
+    const int2 *cw;
+    const float *mass;
+    float2 *pos, *fprev, *F, *att;
+    double2 *vpart;
+    float *speed;                  // caller's per-graph speeds (initial and final)
+    float *bspeed;                 // 2 per graph: ping-pong across iterations
+    float kr, kg, tau, ks, ksmax;
+};
+
+// Prefix sums of tiles and rows over the list; initial speeds into the ping-pong pair.
+__global__ void __launch_bounds__(1024) k_bt_plan(BtBig b) {
+    const uint32_t nb = *b.nbig;
+    uint32_t ct = 0, cr = 0;
+    for (uint32_t s0 = 0; s0 < nb; s0 += 1024) {
+        const uint32_t sl = s0 + threadIdx.x;
+        uint32_t tiles = 0, rows = 0;
+        if (sl < nb) {
+            const int32_t g = b.big[sl];
+            rows = (uint32_t)b.K[g];
+            tiles = (rows + kFa2Tile - 1) / kFa2Tile;
+            b.bspeed[2 * g] = b.speed[g];
+        }
+        uint32_t tt, tr;
+        const uint32_t et = block_excl_scan<uint32_t>(tiles, &tt);
+        const uint32_t er = block_excl_scan<uint32_t>(rows, &tr);
+        if (sl < nb) {
+            b.tile_off[sl] = ct + et;
+            b.row_off[sl] = cr + er;
+        }
+        ct += tt;
+        cr += tr;
+    }
+    if (threadIdx.x == 0) {
+        b.tile_off[nb] = ct;
+        b.row_off[nb] = cr;
+    }
+}
+
+// Largest slot s with off[s] <= x (off ascending, off[0] = 0, x < off[nb]).
+__device__ __forceinline__ uint32_t bt_slot(const uint32_t *off, uint32_t nb, uint32_t x) {
+    uint32_t lo = 0, hi = nb;  // off[lo] <= x < off[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (off[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(kFa2Tile) k_bt_attract(BtBig b) {
+    const uint32_t nb = *b.nbig;
+    const uint32_t R = b.row_off[nb];
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t nw = gridDim.x * (kFa2Tile / kWave);
+    for (uint32_t r = (blockIdx.x * kFa2Tile + threadIdx.x) / kWave; r < R; r += nw) {
+        const uint32_t sl = bt_slot(b.row_off, nb, r);
+        const int32_t g = b.big[sl];
+        const uint32_t i = r - b.row_off[sl];
+        const int64_t n0 = b.node_off[g];
+        const uint32_t *row = b.row + n0 + g;
+        const float2 *pos = b.pos + n0;
+        const float2 f = fa2_row_attraction(pos, b.cw + 2 * b.edge_off[g], row[i], row[i + 1], pos[i], lane);
+        if (lane == 0) b.att[n0 + i] = f;
+    }
+}
+
+__global__ void __launch_bounds__(kFa2Tile) k_bt_force(BtBig b) {
+    const uint32_t nb = *b.nbig;
+    const uint32_t T = b.tile_off[nb];
+    for (uint32_t x = blockIdx.x; x < T; x += gridDim.x) {
+        const uint32_t sl = bt_slot(b.tile_off, nb, x);
+        const int32_t g = b.big[sl];
+        const int64_t n0 = b.node_off[g];
+        fa2_exact_force_tile<false>((int32_t)(x - b.tile_off[sl]), 0, b.K[g], b.pos + n0, b.mass + n0, b.att + n0,
+                                    nullptr, b.kr, b.kg, b.fprev + n0, b.F + n0, b.vpart + (n0 / 256) + g, nullptr);
+        __syncthreads();  // the tile function's LDS is reused by the next item
+    }
+}
+
+__global__ void __launch_bounds__(kFa2Tile) k_bt_update(BtBig b, int32_t it) {
+    const uint32_t nb = *b.nbig;
+    const uint32_t T = b.tile_off[nb];
+    for (uint32_t x = blockIdx.x; x < T; x += gridDim.x) {
+        const uint32_t sl = bt_slot(b.tile_off, nb, x);
+        const int32_t g = b.big[sl];
+        const int64_t n0 = b.node_off[g];
+        const int32_t ntiles = (int32_t)(b.tile_off[sl + 1] - b.tile_off[sl]);
+        fa2_update_tile((int32_t)(x - b.tile_off[sl]), ntiles, b.K[g], b.pos + n0, b.fprev + n0, b.F + n0,
+                        b.vpart + (n0 / 256) + g, ntiles, b.bspeed + 2 * g + (it & 1),
+                        b.bspeed + 2 * g + ((it + 1) & 1), b.tau, b.ks, b.ksmax);
+        __syncthreads();  // the tile function's LDS is reused by the next item
+    }
+}
+
+__global__ void k_bt_finish(BtBig b, int32_t iters) {
+    const uint32_t nb = *b.nbig;
+    for (uint32_t sl = blockIdx.x * blockDim.x + threadIdx.x; sl < nb; sl += gridDim.x * blockDim.x) {
+        const int32_t g = b.big[sl];
+        b.speed[g] = b.bspeed[2 * g + (iters & 1)];
+    }
+}
+
 struct BtWs {
     int32_t *cnt, *lab, *prop;
     unsigned long long *win;
@@ -424,6 +550,10 @@ struct BtWs {
     float2 *F, *att;
     double2 *vpart;
     unsigned int *queue;
+    int32_t *big;
+    unsigned int *nbig;
+    uint32_t *tile_off, *row_off;
+    float *bspeed;
 };
 
 static size_t bt_layout(Carver &c, int32_t G, int64_t n_total, int64_t m_total, BtWs *w) {
@@ -442,6 +572,11 @@ static size_t bt_layout(Carver &c, int32_t G, int64_t n_total, int64_t m_total, 
     w->att = c.take<float2>(n);
     w->vpart = c.take<double2>(n / 256 + (size_t)G + 1);
     w->queue = c.take<unsigned int>(1);
+    w->big = c.take<int32_t>((size_t)G);
+    w->nbig = c.take<unsigned int>(1);
+    w->tile_off = c.take<uint32_t>((size_t)G + 1);
+    w->row_off = c.take<uint32_t>((size_t)G + 1);
+    w->bspeed = c.take<float>(2 * (size_t)G);
     return c.size();
 }
 
@@ -468,7 +603,7 @@ extern "C" size_t bgv_batched_workspace(int32_t G, int64_t n_total, int64_t m_to
 extern "C" bgv_status bgv_batched(int32_t G, int64_t n_total, int64_t m_total, const int64_t *node_off,
                                   const int64_t *edge_off, const int32_t *order, const int32_t *edges,
                                   const bgv_cd_params *cd, const bgv_sketch_params *sk, const bgv_fa2_params *fa,
-                                  int32_t wg_threads, int32_t *labels, int32_t *degree, int32_t *K, int32_t *E_S,
+                                  int32_t wg_threads, int32_t big_k, int32_t *labels, int32_t *degree, int32_t *K, int32_t *E_S,
                                   int32_t *super_label, uint32_t *super_size, int32_t *superedges,
                                   uint32_t *se_weight, float *pos, float *fprev, float *speed, void *ws,
                                   size_t ws_bytes, bgv_stream_t stream) {
@@ -476,6 +611,10 @@ extern "C" bgv_status bgv_batched(int32_t G, int64_t n_total, int64_t m_total, c
     if (!bt_valid(G, n_total, m_total, cd, sk, fa)) {
         set_error("bgv_batched: invalid arguments (G=%d n_total=%lld m_total=%lld)", G, (long long)n_total,
                   (long long)m_total);
+        return BGV_E_INVALID;
+    }
+    if (big_k < 0) {
+        set_error("bgv_batched: big_k must be >= 0 (got %d)", big_k);
         return BGV_E_INVALID;
     }
     if (wg_threads == 0) wg_threads = 512;
@@ -539,6 +678,9 @@ extern "C" bgv_status bgv_batched(int32_t G, int64_t n_total, int64_t m_total, c
     a.att = w.att;
     a.vpart = w.vpart;
     a.queue = w.queue;
+    a.big_k = big_k;
+    a.big = w.big;
+    a.nbig = w.nbig;
 
     // compute-unit count, queried once per device so that a captured launch makes no query
     static int cu_count[64] = {0};
@@ -554,10 +696,51 @@ extern "C" bgv_status bgv_batched(int32_t G, int64_t n_total, int64_t m_total, c
     const int per_cu = wg_threads == 1024 ? 1 : 2;
     const int grid = G < cus * per_cu ? G : cus * per_cu;
     BGV_TRY(fill<uint32_t>(w.queue, 0u, 1, s));
+    BGV_TRY(fill<uint32_t>(w.nbig, 0u, 1, s));
     switch (wg_threads) {
         case 256: BGV_LAUNCH(k_batched<256>, dim3(grid), dim3(256), 0, s, a); break;
         case 512: BGV_LAUNCH(k_batched<512>, dim3(grid), dim3(512), 0, s, a); break;
         default: BGV_LAUNCH(k_batched<1024>, dim3(grid), dim3(1024), 0, s, a); break;
+    }
+    if (big_k > 0 && fa->iters > 0) {
+        // the listed large graphs: a fixed sequence of launches whose sizes are read on
+        // the device, so the whole call can still be captured in a graph
+        BtBig b{};
+        b.node_off = node_off;
+        b.edge_off = edge_off;
+        b.K = K;
+        b.big = w.big;
+        b.nbig = w.nbig;
+        b.tile_off = w.tile_off;
+        b.row_off = w.row_off;
+        b.row = w.row;
+        b.cw = w.cw;
+        b.mass = w.mass;
+        b.pos = a.pos;
+        b.fprev = a.fprev;
+        b.F = w.F;
+        b.att = w.att;
+        b.vpart = w.vpart;
+        b.speed = speed;
+        b.bspeed = w.bspeed;
+        b.kr = fa->kr;
+        b.kg = fa->kg;
+        b.tau = fa->tau;
+        b.ks = fa->ks;
+        b.ksmax = fa->ksmax;
+        // item bounds known on the host (tiles <= n_total/256 + G, rows <= n_total); wide
+        // grids, since a workgroup holding two tiles of a large graph doubles the path
+        // (measured: 512 workgroups looping over the items were 1.4x slower than 4096)
+        const unsigned tiles_bound = (unsigned)(n_total / kFa2Tile + G);
+        const unsigned gt = tiles_bound < 4096u ? (tiles_bound > 0 ? tiles_bound : 1u) : 4096u;
+        const unsigned ga = grid_for(n_total > 0 ? n_total : 1, kFa2Tile / kWave, 4096);
+        BGV_LAUNCH(k_bt_plan, dim3(1), dim3(1024), 0, s, b);
+        for (int32_t it = 0; it < fa->iters; ++it) {
+            BGV_LAUNCH(k_bt_attract, dim3(ga), dim3(kFa2Tile), 0, s, b);
+            BGV_LAUNCH(k_bt_force, dim3(gt), dim3(kFa2Tile), 0, s, b);
+            BGV_LAUNCH(k_bt_update, dim3(gt), dim3(kFa2Tile), 0, s, b, it);
+        }
+        BGV_LAUNCH(k_bt_finish, dim3(1), dim3(256), 0, s, b, fa->iters);
     }
     return BGV_OK;
 }

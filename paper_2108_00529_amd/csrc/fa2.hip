@@ -25,6 +25,7 @@
 namespace bgv {
 
 constexpr int kFaThreads = 256;
+static_assert(kFaThreads == kFa2Tile, "the layout kernels work on 256-node tiles");
 
 // ------------------------------------------------------------------------ CSR ----
 __global__ void k_csr_keys(const int2 *__restrict__ edges, int64_t E, int kb, uint64_t *__restrict__ keys,
@@ -209,41 +210,8 @@ __global__ void __launch_bounds__(kFaThreads) k_force_exact(int32_t K, const flo
                                                              const uint32_t *__restrict__ item_of, float kr, float kg,
                                                              const float2 *__restrict__ fprev, float2 *__restrict__ F,
                                                              double2 *__restrict__ part, float2 *__restrict__ seg) {
-    __shared__ float4 tile[kFaThreads];
-    __shared__ double2 ws[kFaThreads / kWave];
-    const int32_t i = blockIdx.x * kFaThreads + threadIdx.x;
-    const bool live = i < K;
-    const float2 xi = live ? pos[i] : make_float2(0.f, 0.f);
-    const int32_t jb = kSegmented ? (int32_t)blockIdx.y * kRepSegment : 0;
-    const int32_t je = kSegmented ? min(K, jb + kRepSegment) : K;
-    float fx = 0.f, fy = 0.f;
-    for (int32_t t0 = jb; t0 < je; t0 += kFaThreads) {
-        const int32_t j = t0 + threadIdx.x;
-        if (j < je) {
-            const float2 xj = pos[j];
-            tile[threadIdx.x] = make_float4(xj.x, xj.y, mass[j], 0.f);
-        }
-        __syncthreads();
-        const int cnt = min(kFaThreads, je - t0);
-        if (cnt == kFaThreads) {
-fa2_rep_run(xi, tile, kFaThreads, fx, fy);
-        } else {
-            for (int q = 0; q < cnt; ++q) fa2_rep_term(xi, tile[q], fx, fy);
-        }
-        __syncthreads();
-    }
-    if (kSegmented) {
-        if (live) seg[(int64_t)blockIdx.y * K + i] = make_float2(fx, fy);
-        return;
-    }
-    double2 st = make_double2(0.0, 0.0);
-    if (live) {
-        const float2 f = fa2_net_force(xi, mass[i], kr, fx, fy, fa2_att_combine(att, item_of, i), kg);
-        F[i] = f;
-        st = fa2_swing_traction(f, fprev[i], mass[i]);
-    }
-    st = fa2_sum256(st, ws);
-    if (threadIdx.x == 0) part[blockIdx.x] = st;
+    fa2_exact_force_tile<kSegmented>((int32_t)blockIdx.x, (int32_t)blockIdx.y, K, pos, mass, att, item_of, kr, kg,
+                                     fprev, F, part, seg);
 }
 
 // Segment sums of body i added in ascending segment order, then the rest of the force.
@@ -331,29 +299,8 @@ __global__ void __launch_bounds__(kFaThreads) k_update(int32_t K, float2 *__rest
                                                         const float *__restrict__ speed_in,
                                                         float *__restrict__ speed_out, float tau, float ks,
                                                         float ksmax, float4 *__restrict__ bbox_part) {
-    __shared__ float s_speed;
-    __shared__ double2 ws[kFaThreads / kWave];
-    double2 acc = make_double2(0.0, 0.0);
-    for (int p = threadIdx.x; p < nparts; p += kFaThreads) {
-        acc.x += part[p].x;
-        acc.y += part[p].y;
-    }
-    acc = fa2_sum256(acc, ws);
-    if (threadIdx.x == 0) {
-        const float s = fa2_global_speed(acc.x, acc.y, *speed_in, tau);
-        s_speed = s;
-        if (blockIdx.x == 0) *speed_out = s;
-    }
-    __syncthreads();
-    const float s = s_speed;
-    float4 bb = make_float4(kInf, -kInf, kInf, -kInf);
-    for (int32_t i = blockIdx.x * kFaThreads + threadIdx.x; i < K; i += gridDim.x * kFaThreads) {
-        const float2 f = F[i];
-        const float2 p = fa2_move(pos[i], f, fprev[i], s, ks, ksmax);
-        pos[i] = p;
-        fprev[i] = f;
-        bb = make_float4(fminf(bb.x, p.x), fmaxf(bb.y, p.x), fminf(bb.z, p.y), fmaxf(bb.w, p.y));
-    }
+    float4 bb = fa2_update_tile((int32_t)blockIdx.x, (int32_t)gridDim.x, K, pos, fprev, F, part, nparts, speed_in,
+                                speed_out, tau, ks, ksmax);
     if (bbox_part) {
         bb = block_bbox(bb);
         if (threadIdx.x == 0) bbox_part[blockIdx.x] = bb;

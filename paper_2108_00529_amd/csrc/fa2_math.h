@@ -187,4 +187,96 @@ __device__ __forceinline__ float2 fa2_move(float2 p, float2 f, float2 fp, float 
     return p;
 }
 
+// ---- whole-tile bodies shared by the plain kernels and the batched big-graph path ----
+// A tile is 256 consecutive nodes handled by one 256-thread workgroup.
+constexpr int kFa2Tile = 256;
+
+// Node i's attraction: its CSR block sums combined (item_of != null) or a final value.
+__device__ __forceinline__ float2 fa2_att_value(const float2 *__restrict__ att, const uint32_t *__restrict__ item_of,
+                                                int32_t i) {
+    return item_of ? fa2_att_combine(att, item_of, i) : att[i];
+}
+
+// Exact repulsion of the nodes of tile bx over the bodies of j segment by (all of
+// [0, K) when kSegmented is false), bodies staged through LDS 256 at a time.  With one
+// segment the tile's forces are finished (attraction, gravity, swing, traction and the
+// tile's FP64 partial sums into part[bx]); with several, the segment sums go to seg.
+template <bool kSegmented>
+__device__ __forceinline__ void fa2_exact_force_tile(int32_t bx, int32_t by, int32_t K, const float2 *__restrict__ pos,
+                                                     const float *__restrict__ mass, const float2 *__restrict__ att,
+                                                     const uint32_t *__restrict__ item_of, float kr, float kg,
+                                                     const float2 *__restrict__ fprev, float2 *__restrict__ F,
+                                                     double2 *__restrict__ part, float2 *__restrict__ seg) {
+    __shared__ float4 tile[kFa2Tile];
+    __shared__ double2 ws[kFa2Tile / kWave];
+    const int32_t i = bx * kFa2Tile + threadIdx.x;
+    const bool live = i < K;
+    const float2 xi = live ? pos[i] : make_float2(0.f, 0.f);
+    const int32_t jb = kSegmented ? by * kRepSegment : 0;
+    const int32_t je = kSegmented ? min(K, jb + kRepSegment) : K;
+    float fx = 0.f, fy = 0.f;
+    for (int32_t t0 = jb; t0 < je; t0 += kFa2Tile) {
+        const int32_t j = t0 + threadIdx.x;
+        if (j < je) {
+            const float2 xj = pos[j];
+            tile[threadIdx.x] = make_float4(xj.x, xj.y, mass[j], 0.f);
+        }
+        __syncthreads();
+        const int cnt = min(kFa2Tile, je - t0);
+        if (cnt == kFa2Tile) {
+            fa2_rep_run(xi, tile, kFa2Tile, fx, fy);
+        } else {
+            for (int q = 0; q < cnt; ++q) fa2_rep_term(xi, tile[q], fx, fy);
+        }
+        __syncthreads();
+    }
+    if (kSegmented) {
+        if (live) seg[(int64_t)by * K + i] = make_float2(fx, fy);
+        return;
+    }
+    double2 st = make_double2(0.0, 0.0);
+    if (live) {
+        const float2 f = fa2_net_force(xi, mass[i], kr, fx, fy, fa2_att_value(att, item_of, i), kg);
+        F[i] = f;
+        st = fa2_swing_traction(f, fprev[i], mass[i]);
+    }
+    st = fa2_sum256(st, ws);
+    if (threadIdx.x == 0) part[bx] = st;
+}
+
+// Global speed from part[0, nparts) (every tile reduces them in the same order; tile 0
+// stores it), then local speeds and displacement of the nodes bx*256 + t + q*stride.
+// Returns the thread's bounding box (xmin, xmax, ymin, ymax) of the moved positions.
+__device__ __forceinline__ float4 fa2_update_tile(int32_t bx, int32_t stride, int32_t K, float2 *__restrict__ pos,
+                                                  float2 *__restrict__ fprev, const float2 *__restrict__ F,
+                                                  const double2 *__restrict__ part, int32_t nparts,
+                                                  const float *__restrict__ speed_in, float *__restrict__ speed_out,
+                                                  float tau, float ks, float ksmax) {
+    __shared__ float s_speed;
+    __shared__ double2 ws[kFa2Tile / kWave];
+    double2 acc = make_double2(0.0, 0.0);
+    for (int p = threadIdx.x; p < nparts; p += kFa2Tile) {
+        acc.x += part[p].x;
+        acc.y += part[p].y;
+    }
+    acc = fa2_sum256(acc, ws);
+    if (threadIdx.x == 0) {
+        const float s = fa2_global_speed(acc.x, acc.y, *speed_in, tau);
+        s_speed = s;
+        if (bx == 0) *speed_out = s;
+    }
+    __syncthreads();
+    const float s = s_speed;
+    const float inf = __builtin_huge_valf();
+    float4 bb = make_float4(inf, -inf, inf, -inf);
+    for (int32_t i = bx * kFa2Tile + threadIdx.x; i < K; i += stride * kFa2Tile) {
+        const float2 f = F[i];
+        const float2 p = fa2_move(pos[i], f, fprev[i], s, ks, ksmax);
+        pos[i] = p;
+        fprev[i] = f;
+        bb = make_float4(fminf(bb.x, p.x), fmaxf(bb.y, p.x), fminf(bb.z, p.y), fmaxf(bb.w, p.y));
+    }
+    return bb;
+}
+
 }  // namespace bgv

@@ -42,7 +42,7 @@ def batch():
     return wl, graphs, c1, c2, pos0
 
 
-def run_batched(bgv, wl, graphs, c1, c2, pos0, wg_threads=0, largest_first=False, iters=None):
+def run_batched(bgv, wl, graphs, c1, c2, pos0, wg_threads=0, largest_first=False, iters=None, big_k=0):
     dev = torch.device("cuda")
     w = dict(wl) if iters is None else dict(wl, fa2_iters=iters)
     edges, noff, eoff, noff_h, eoff_h = bgv.pack_graphs([(n, e) for n, e, _ in graphs], dev)
@@ -50,7 +50,8 @@ def run_batched(bgv, wl, graphs, c1, c2, pos0, wg_threads=0, largest_first=False
     order = None
     if largest_first:
         order = torch.from_numpy(np.argsort(-np.diff(eoff_h), kind="stable").astype(np.int32)).to(dev)
-    out = bgv.batched(edges, noff, eoff, int(noff_h[-1]), w, c1, c2, pos, order=order, wg_threads=wg_threads)
+    out = bgv.batched(edges, noff, eoff, int(noff_h[-1]), w, c1, c2, pos, order=order, wg_threads=wg_threads,
+                      big_k=big_k)
     torch.cuda.synchronize()
     return out, noff_h, eoff_h
 
@@ -112,15 +113,19 @@ def test_batched_last_step_matches_oracle(bgv, batch):
 
 
 def test_batched_launch_parameters_change_nothing(bgv, batch):
+    """Workgroup size, queue order and the size above which a layout leaves the
+    persistent launch (big_k: 16 sends most of these supergraphs, 1 all but the
+    single-node ones, to the multi-workgroup kernels) change no bit."""
     wl, graphs, c1, c2, pos0 = batch
     ref, noff, eoff = run_batched(bgv, wl, graphs, c1, c2, pos0)
-    for wg in (256, 1024):
-        for largest in (False, True):
-            out, _, _ = run_batched(bgv, wl, graphs, c1, c2, pos0, wg_threads=wg, largest_first=largest)
-            for g in range(len(graphs)):
-                a, b = per_graph(out, noff, eoff, g), per_graph(ref, noff, eoff, g)
-                for k in a:
-                    assert np.array_equal(a[k], b[k]), (wg, largest, g, k)
+    K = [int(k) for k in ref["K"].cpu()]
+    assert sum(k > 16 for k in K) >= 5
+    for wg, largest, bk in ((256, False, 0), (1024, True, 0), (1024, False, 16), (256, True, 1), (512, True, 64)):
+        out, _, _ = run_batched(bgv, wl, graphs, c1, c2, pos0, wg_threads=wg, largest_first=largest, big_k=bk)
+        for g in range(len(graphs)):
+            a, b = per_graph(out, noff, eoff, g), per_graph(ref, noff, eoff, g)
+            for k in a:
+                assert np.array_equal(a[k], b[k]), (wg, largest, bk, g, k)
 
 
 def test_autotuner_picks_a_candidate(bgv, batch):
@@ -132,6 +137,7 @@ def test_autotuner_picks_a_candidate(bgv, batch):
     choice, entry = autotune.tune_batched(edges, noff, eoff, int(noff_h[-1]), dict(wl, fa2_iters=5), c1, c2, pos,
                                           repeats=1, use_cache=False)
     assert choice in autotune.CANDIDATES and len(entry["ms"]) == len(autotune.CANDIDATES)
+    assert entry["wg_threads"] == choice[0] and entry["big_k"] == choice[1]
 
 
 def test_captured_batched_replays_match_eager(bgv, batch):
