@@ -221,8 +221,9 @@ bgv_status bgv_fa2_grad(int32_t K, int64_t E, const int32_t *edges, const float 
  * fa->exact must be 1.  wg_threads: 256, 512 or 1024 (0 = 512), a launch parameter that
  * does not change any result.  big_k >= 0, another such parameter: a graph whose
  * supergraph has more than big_k nodes (and at most 4096) is laid out after the
- * persistent launch by kernels that spread each graph's tiles over many workgroups
- * (a fixed sequence of three launches per iteration, sizes read on the device), so that
+ * persistent launch by kernels that spread each graph's tiles and repulsion segments
+ * over many workgroups (a fixed sequence of three launches per iteration, sizes read on
+ * the device), so that
  * a few large graphs do not each hold one compute unit for the whole layout; 0 keeps
  * every layout in the persistent launch.
  * Outputs (dev; per-node arrays indexed from node_off[g], per-edge arrays from

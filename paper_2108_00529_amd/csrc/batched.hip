@@ -17,6 +17,10 @@
 namespace bgv {
 
 constexpr int kBtMaxCells = 8192;  // rows*cols of a per-graph sketch, held in LDS
+// Largest supergraph laid out by the multi-workgroup kernels after the persistent launch,
+// and the repulsion segments it has at most (segment sums: that many per node).
+constexpr int32_t kBtBigMax = 4096;
+constexpr int32_t kBtMaxSeg = kBtBigMax / kRepSegment;
 
 struct BtArgs {
     int32_t G;
@@ -47,8 +51,8 @@ struct BtArgs {
     float2 *F, *att;
     double2 *vpart;         // floor(n_total/256) + G + 1
     unsigned int *queue;
-    // graphs with more than big_k supernodes (and at most one repulsion segment) are
-    // listed in big[0, *nbig) and laid out afterwards by the k_bt_* kernels; 0: none
+    // graphs with more than big_k and at most kBtBigMax supernodes are listed in
+    // big[0, *nbig) and laid out afterwards by the k_bt_* kernels; 0: none
     int32_t big_k;
     int32_t *big;
     unsigned int *nbig;
@@ -142,7 +146,7 @@ __global__ void __launch_bounds__(NT) k_batched(BtArgs a) {
     constexpr int NW = NT / kWave;
     constexpr int NV = NT / 256;  // 256-node groups handled side by side in the layout
     static_assert(NT % 256 == 0 && NT <= 1024, "workgroup of 256, 512 or 1024 threads");
-    static_assert(kRepSegment % NT == 0, "repulsion segments must hold whole LDS tiles");
+    static_assert(NT % kRepSegment == 0 || kRepSegment % NT == 0, "segment boundaries fall on LDS tile halves");
     __shared__ uint32_t sk[kBtMaxCells];
     __shared__ uint32_t hist[256], running[256];
     __shared__ uint32_t wcnt[NW][256];
@@ -335,7 +339,7 @@ __global__ void __launch_bounds__(NT) k_batched(BtArgs a) {
         __syncthreads();
         float *mass = a.mass + n0;
         for (uint32_t i = t; i < K; i += NT) mass[i] = (float)(row[i + 1] - row[i]) + 1.0f;
-        if (a.big_k > 0 && a.iters > 0 && K > (uint32_t)a.big_k && K <= (uint32_t)kRepSegment) {
+        if (a.big_k > 0 && a.iters > 0 && K > (uint32_t)a.big_k && K <= (uint32_t)kBtBigMax) {
             // a large supergraph is laid out by the multi-workgroup kernels afterwards,
             // so that it does not hold one compute unit for the whole layout
             if (t == 0) a.big[atomicAdd(a.nbig, 1u)] = g;
@@ -361,20 +365,10 @@ __global__ void __launch_bounds__(NT) k_batched(BtArgs a) {
                 const bool live = vb < nvb && i < K;
                 const float2 xi = live ? pos[i] : make_float2(0.f, 0.f);
                 const float mi = live ? mass[i] : 0.f;
-                // the plain kernels' order: segments of kRepSegment bodies (a multiple of
-                // NT, so no tile straddles two), each from zero, then added in order
+                // the plain kernels' order: segments of kRepSegment bodies, each summed
+                // from zero, then added in order; a segment boundary can fall inside a tile
                 float rx = 0.f, ry = 0.f, sx = 0.f, sy = 0.f;
                 for (uint32_t j0 = 0; j0 < K; j0 += NT) {
-                    if (j0 != 0 && j0 % (uint32_t)kRepSegment == 0) {
-                        if (j0 == (uint32_t)kRepSegment) {
-                            rx = sx;
-                            ry = sy;
-                        } else {
-                            rx += sx;
-                            ry += sy;
-                        }
-                        sx = sy = 0.f;
-                    }
                     const uint32_t j = j0 + t;
                     if (j < K) {
                         const float2 xj = pos[j];
@@ -382,9 +376,24 @@ __global__ void __launch_bounds__(NT) k_batched(BtArgs a) {
                     }
                     __syncthreads();
                     const uint32_t c = min((uint32_t)NT, K - j0);
-                    const uint32_t c8 = c & ~7u;  // groups of eight LDS reads in flight, then the rest
-                    fa2_rep_run(xi, tile, (int)c8, sx, sy);
-                    for (uint32_t q = c8; q < c; ++q) fa2_rep_term(xi, tile[q], sx, sy);
+                    for (uint32_t q0 = 0; q0 < c;) {
+                        const uint32_t jj = j0 + q0;
+                        if (jj != 0 && jj % (uint32_t)kRepSegment == 0) {
+                            if (jj == (uint32_t)kRepSegment) {
+                                rx = sx;
+                                ry = sy;
+                            } else {
+                                rx += sx;
+                                ry += sy;
+                            }
+                            sx = sy = 0.f;
+                        }
+                        const uint32_t q1 = min(c, (jj / (uint32_t)kRepSegment + 1u) * (uint32_t)kRepSegment - j0);
+                        const uint32_t n8 = (q1 - q0) & ~7u;  // groups of eight LDS reads in flight
+                        fa2_rep_run(xi, tile + q0, (int)n8, sx, sy);
+                        for (uint32_t q = q0 + n8; q < q1; ++q) fa2_rep_term(xi, tile[q], sx, sy);
+                        q0 = q1;
+                    }
                     __syncthreads();
                 }
                 if (K <= (uint32_t)kRepSegment) {
@@ -427,52 +436,64 @@ __global__ void __launch_bounds__(NT) k_batched(BtArgs a) {
 }
 
 // ---- layout of the listed large graphs, all of them per launch ------------------
-// Work items are the listed graphs' CSR rows (attraction) or 256-node tiles (forces,
-// update), numbered through exclusive prefix sums over the list; an item finds its
-// graph by binary search.  Each graph goes through exactly the plain path's tile
-// functions, so its result equals a plain layout of it bit for bit.
+// Work items are the listed graphs' CSR rows (attraction), (256-node tile, repulsion
+// segment) pairs (repulsion) or tiles (segment sums, update), numbered through
+// exclusive prefix sums over the list; an item finds its graph by a table made once
+// per call.  Each graph goes through exactly the plain path's tile functions, so its
+// result equals a plain layout of it bit for bit.
 struct BtBig {
     const int64_t *node_off, *edge_off;
     const int32_t *K;
     const int32_t *big;
     const unsigned int *nbig;
     uint32_t *tile_off, *row_off;  // G+1 each: prefix sums of tiles / rows over the list
+    uint32_t *fitem_off;           // G+1: prefix sums of tiles x segments over the list
+    uint32_t *tile_slot;           // list slot of every tile item
+    uint32_t *fitem_slot;          // list slot of every (tile, segment) item
+    uint4 *row_desc;               // per row item: CSR entries [x, y) in cw, node z, graph base w
     const uint32_t *row;
     const int2 *cw;
     const float *mass;
     float2 *pos, *fprev, *F, *att;
+    float2 *seg;                   // segment sums: kBtMaxSeg per node from the graph's first node
     double2 *vpart;
     float *speed;                  // caller's per-graph speeds (initial and final)
     float *bspeed;                 // 2 per graph: ping-pong across iterations
     float kr, kg, tau, ks, ksmax;
 };
 
-// Prefix sums of tiles and rows over the list; initial speeds into the ping-pong pair.
+// Prefix sums of tiles, rows and (tile, segment) items over the list; initial speeds
+// into the ping-pong pair.
 __global__ void __launch_bounds__(1024) k_bt_plan(BtBig b) {
     const uint32_t nb = *b.nbig;
-    uint32_t ct = 0, cr = 0;
+    uint32_t ct = 0, cr = 0, cf = 0;
     for (uint32_t s0 = 0; s0 < nb; s0 += 1024) {
         const uint32_t sl = s0 + threadIdx.x;
-        uint32_t tiles = 0, rows = 0;
+        uint32_t tiles = 0, rows = 0, fitems = 0;
         if (sl < nb) {
             const int32_t g = b.big[sl];
             rows = (uint32_t)b.K[g];
             tiles = (rows + kFa2Tile - 1) / kFa2Tile;
+            fitems = tiles * (uint32_t)fa2_rep_segments((int32_t)rows);
             b.bspeed[2 * g] = b.speed[g];
         }
-        uint32_t tt, tr;
+        uint32_t tt, tr, tf;
         const uint32_t et = block_excl_scan<uint32_t>(tiles, &tt);
         const uint32_t er = block_excl_scan<uint32_t>(rows, &tr);
+        const uint32_t ef = block_excl_scan<uint32_t>(fitems, &tf);
         if (sl < nb) {
             b.tile_off[sl] = ct + et;
             b.row_off[sl] = cr + er;
+            b.fitem_off[sl] = cf + ef;
         }
         ct += tt;
         cr += tr;
+        cf += tf;
     }
     if (threadIdx.x == 0) {
         b.tile_off[nb] = ct;
         b.row_off[nb] = cr;
+        b.fitem_off[nb] = cf;
     }
 }
 
@@ -487,32 +508,66 @@ __device__ __forceinline__ uint32_t bt_slot(const uint32_t *off, uint32_t nb, ui
     return lo;
 }
 
-__global__ void __launch_bounds__(kFa2Tile) k_bt_attract(BtBig b) {
+// Per-call maps: each row item's descriptor and each tile and (tile, segment) item's
+// slot, found once instead of once per iteration.
+__global__ void __launch_bounds__(kFa2Tile) k_bt_maps(BtBig b) {
     const uint32_t nb = *b.nbig;
-    const uint32_t R = b.row_off[nb];
-    const int lane = threadIdx.x & (kWave - 1);
-    const uint32_t nw = gridDim.x * (kFa2Tile / kWave);
-    for (uint32_t r = (blockIdx.x * kFa2Tile + threadIdx.x) / kWave; r < R; r += nw) {
+    const uint32_t R = b.row_off[nb], T = b.tile_off[nb], FI = b.fitem_off[nb];
+    const uint32_t stride = gridDim.x * kFa2Tile;
+    for (uint32_t r = blockIdx.x * kFa2Tile + threadIdx.x; r < R; r += stride) {
         const uint32_t sl = bt_slot(b.row_off, nb, r);
         const int32_t g = b.big[sl];
         const uint32_t i = r - b.row_off[sl];
         const int64_t n0 = b.node_off[g];
         const uint32_t *row = b.row + n0 + g;
-        const float2 *pos = b.pos + n0;
-        const float2 f = fa2_row_attraction(pos, b.cw + 2 * b.edge_off[g], row[i], row[i + 1], pos[i], lane);
-        if (lane == 0) b.att[n0 + i] = f;
+        const uint32_t c0 = (uint32_t)(2 * b.edge_off[g]);
+        b.row_desc[r] = make_uint4(c0 + row[i], c0 + row[i + 1], (uint32_t)n0 + i, (uint32_t)n0);
+    }
+    for (uint32_t x = blockIdx.x * kFa2Tile + threadIdx.x; x < T; x += stride) b.tile_slot[x] = bt_slot(b.tile_off, nb, x);
+    for (uint32_t x = blockIdx.x * kFa2Tile + threadIdx.x; x < FI; x += stride)
+        b.fitem_slot[x] = bt_slot(b.fitem_off, nb, x);
+}
+
+// Repulsion of every (tile, segment) item into the segment sums, then attraction of the
+// listed graphs' rows, one wavefront per row as in the persistent kernel (the row
+// descriptor: absolute CSR range, node, graph base, in one load).  A graph of one
+// segment takes the same path: its one segment sum is its repulsion.
+__global__ void __launch_bounds__(kFa2Tile) k_bt_force(BtBig b) {
+    const uint32_t nb = *b.nbig;
+    const uint32_t FI = b.fitem_off[nb], R = b.row_off[nb];
+    for (uint32_t x = blockIdx.x; x < FI; x += gridDim.x) {
+        const uint32_t sl = b.fitem_slot[x];
+        const int32_t g = b.big[sl];
+        const int64_t n0 = b.node_off[g];
+        const uint32_t ntiles = b.tile_off[sl + 1] - b.tile_off[sl];
+        const uint32_t q = x - b.fitem_off[sl];
+        fa2_exact_force_tile<true>((int32_t)(q % ntiles), (int32_t)(q / ntiles), b.K[g], b.pos + n0, b.mass + n0,
+                                   nullptr, nullptr, b.kr, b.kg, nullptr, nullptr, nullptr,
+                                   b.seg + kBtMaxSeg * n0);
+        __syncthreads();  // the tile function's LDS is reused by the next item
+    }
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t nw = gridDim.x * (kFa2Tile / kWave);
+    for (uint32_t r = (blockIdx.x * kFa2Tile + threadIdx.x) / kWave; r < R; r += nw) {
+        const uint4 d = b.row_desc[r];  // (first entry, end entry, node, graph's first node)
+        const float2 *pos = b.pos + d.w;
+        const float2 f = fa2_row_attraction(pos, b.cw, d.x, d.y, b.pos[d.z], lane);
+        if (lane == 0) b.att[d.z] = f;
     }
 }
 
-__global__ void __launch_bounds__(kFa2Tile) k_bt_force(BtBig b) {
+// Segment sums added in order, then the rest of every force and the tiles' partials.
+__global__ void __launch_bounds__(kFa2Tile) k_bt_combine(BtBig b) {
     const uint32_t nb = *b.nbig;
     const uint32_t T = b.tile_off[nb];
     for (uint32_t x = blockIdx.x; x < T; x += gridDim.x) {
-        const uint32_t sl = bt_slot(b.tile_off, nb, x);
+        const uint32_t sl = b.tile_slot[x];
         const int32_t g = b.big[sl];
         const int64_t n0 = b.node_off[g];
-        fa2_exact_force_tile<false>((int32_t)(x - b.tile_off[sl]), 0, b.K[g], b.pos + n0, b.mass + n0, b.att + n0,
-                                    nullptr, b.kr, b.kg, b.fprev + n0, b.F + n0, b.vpart + (n0 / 256) + g, nullptr);
+        const int32_t K = b.K[g];
+        fa2_combine_tile((int32_t)(x - b.tile_off[sl]), K, fa2_rep_segments(K), b.seg + kBtMaxSeg * n0, b.pos + n0,
+                         b.mass + n0, b.att + n0, nullptr, b.kr, b.kg, b.fprev + n0, b.F + n0,
+                         b.vpart + (n0 / 256) + g);
         __syncthreads();  // the tile function's LDS is reused by the next item
     }
 }
@@ -521,7 +576,7 @@ __global__ void __launch_bounds__(kFa2Tile) k_bt_update(BtBig b, int32_t it) {
     const uint32_t nb = *b.nbig;
     const uint32_t T = b.tile_off[nb];
     for (uint32_t x = blockIdx.x; x < T; x += gridDim.x) {
-        const uint32_t sl = bt_slot(b.tile_off, nb, x);
+        const uint32_t sl = b.tile_slot[x];
         const int32_t g = b.big[sl];
         const int64_t n0 = b.node_off[g];
         const int32_t ntiles = (int32_t)(b.tile_off[sl + 1] - b.tile_off[sl]);
@@ -552,7 +607,9 @@ struct BtWs {
     unsigned int *queue;
     int32_t *big;
     unsigned int *nbig;
-    uint32_t *tile_off, *row_off;
+    uint32_t *tile_off, *row_off, *fitem_off, *tile_slot, *fitem_slot;
+    uint4 *row_desc;
+    float2 *seg;
     float *bspeed;
 };
 
@@ -576,6 +633,12 @@ static size_t bt_layout(Carver &c, int32_t G, int64_t n_total, int64_t m_total, 
     w->nbig = c.take<unsigned int>(1);
     w->tile_off = c.take<uint32_t>((size_t)G + 1);
     w->row_off = c.take<uint32_t>((size_t)G + 1);
+    w->fitem_off = c.take<uint32_t>((size_t)G + 1);
+    w->tile_slot = c.take<uint32_t>(n / kFa2Tile + (size_t)G + 1);
+    // a listed graph has K <= kBtBigMax supernodes, at most kBtMaxSeg segments of them
+    w->fitem_slot = c.take<uint32_t>((size_t)kBtMaxSeg * (n / kFa2Tile + (size_t)G + 1));
+    w->row_desc = c.take<uint4>(n);
+    w->seg = c.take<float2>((size_t)kBtMaxSeg * n);
     w->bspeed = c.take<float>(2 * (size_t)G);
     return c.size();
 }
@@ -713,6 +776,11 @@ extern "C" bgv_status bgv_batched(int32_t G, int64_t n_total, int64_t m_total, c
         b.nbig = w.nbig;
         b.tile_off = w.tile_off;
         b.row_off = w.row_off;
+        b.fitem_off = w.fitem_off;
+        b.tile_slot = w.tile_slot;
+        b.fitem_slot = w.fitem_slot;
+        b.row_desc = w.row_desc;
+        b.seg = w.seg;
         b.row = w.row;
         b.cw = w.cw;
         b.mass = w.mass;
@@ -729,15 +797,16 @@ extern "C" bgv_status bgv_batched(int32_t G, int64_t n_total, int64_t m_total, c
         b.ks = fa->ks;
         b.ksmax = fa->ksmax;
         // item bounds known on the host (tiles <= n_total/256 + G, rows <= n_total); wide
-        // grids, since a workgroup holding two tiles of a large graph doubles the path
+        // grids, since a workgroup holding two items of a large graph doubles the path
         // (measured: 512 workgroups looping over the items were 1.4x slower than 4096)
         const unsigned tiles_bound = (unsigned)(n_total / kFa2Tile + G);
         const unsigned gt = tiles_bound < 4096u ? (tiles_bound > 0 ? tiles_bound : 1u) : 4096u;
-        const unsigned ga = grid_for(n_total > 0 ? n_total : 1, kFa2Tile / kWave, 4096);
+        const unsigned gf = gt * (unsigned)kBtMaxSeg < 16384u ? gt * (unsigned)kBtMaxSeg : 16384u;
         BGV_LAUNCH(k_bt_plan, dim3(1), dim3(1024), 0, s, b);
+        BGV_LAUNCH(k_bt_maps, dim3(grid_for(n_total > 0 ? n_total : 1, kFa2Tile, 4096)), dim3(kFa2Tile), 0, s, b);
         for (int32_t it = 0; it < fa->iters; ++it) {
-            BGV_LAUNCH(k_bt_attract, dim3(ga), dim3(kFa2Tile), 0, s, b);
-            BGV_LAUNCH(k_bt_force, dim3(gt), dim3(kFa2Tile), 0, s, b);
+            BGV_LAUNCH(k_bt_force, dim3(gf), dim3(kFa2Tile), 0, s, b);
+            BGV_LAUNCH(k_bt_combine, dim3(gt), dim3(kFa2Tile), 0, s, b);
             BGV_LAUNCH(k_bt_update, dim3(gt), dim3(kFa2Tile), 0, s, b, it);
         }
         BGV_LAUNCH(k_bt_finish, dim3(1), dim3(256), 0, s, b, fa->iters);

@@ -5,7 +5,7 @@
 // order and therefore every FP sum is deterministic).
 // Per iteration:
 //   both:   k_attract       attraction, one wavefront per CSR row
-//   exact:  k_force_exact   LDS-tiled all-pairs repulsion (split into 4096-body segments
+//   exact:  k_force_exact   LDS-tiled all-pairs repulsion (split into 512-body segments
 //                           summed by k_force_combine when K is larger) + attraction +
 //                           gravity, swing/traction, FP64 block partials of the two sums
 //   BH:     k_bh_bbox -> k_bh_codes -> radix sort -> k_bh_gather -> FP64 prefix sums
@@ -223,23 +223,7 @@ __global__ void __launch_bounds__(kFaThreads) k_force_combine(int32_t K, int32_t
                                                                const uint32_t *__restrict__ item_of, float kr, float kg,
                                                                const float2 *__restrict__ fprev,
                                                                float2 *__restrict__ F, double2 *__restrict__ part) {
-    __shared__ double2 ws[kFaThreads / kWave];
-    const int32_t i = blockIdx.x * kFaThreads + threadIdx.x;
-    double2 st = make_double2(0.0, 0.0);
-    if (i < K) {
-        float2 r = seg[i];
-        for (int32_t q = 1; q < nseg; ++q) {
-            const float2 v = seg[(int64_t)q * K + i];
-            r.x += v.x;
-            r.y += v.y;
-        }
-        const float f_mi = mass[i];
-        const float2 f = fa2_net_force(pos[i], f_mi, kr, r.x, r.y, fa2_att_combine(att, item_of, i), kg);
-        F[i] = f;
-        st = fa2_swing_traction(f, fprev[i], f_mi);
-    }
-    st = fa2_sum256(st, ws);
-    if (threadIdx.x == 0) part[blockIdx.x] = st;
+    fa2_combine_tile((int32_t)blockIdx.x, K, nseg, seg, pos, mass, att, item_of, kr, kg, fprev, F, part);
 }
 
 static bgv_status exact_forces(int32_t K, const float2 *pos, const float *mass, const float2 *A,

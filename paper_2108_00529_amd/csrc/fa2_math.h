@@ -35,8 +35,9 @@ __device__ __forceinline__ void fa2_rep_run(float2 xi, const float4 *tile, int n
 // bodies: each segment in ascending j starting from zero, then the segment sums in
 // ascending order (the first one taken as is).  Segments let one body's sum be split
 // over several workgroups while fixing the order of every addition, so any launch shape
-// gives the same bits.  A multiple of every workgroup size the kernels use.
-constexpr int32_t kRepSegment = 4096;
+// gives the same bits.  A multiple of the 256-body LDS tiles; short enough that a
+// supergraph of a few thousand nodes spreads over many workgroups.
+constexpr int32_t kRepSegment = 512;
 
 __host__ __device__ __forceinline__ int32_t fa2_rep_segments(int32_t K) {
     return (K + kRepSegment - 1) / kRepSegment;
@@ -239,6 +240,32 @@ __device__ __forceinline__ void fa2_exact_force_tile(int32_t bx, int32_t by, int
         const float2 f = fa2_net_force(xi, mass[i], kr, fx, fy, fa2_att_value(att, item_of, i), kg);
         F[i] = f;
         st = fa2_swing_traction(f, fprev[i], mass[i]);
+    }
+    st = fa2_sum256(st, ws);
+    if (threadIdx.x == 0) part[bx] = st;
+}
+
+// Segment sums of the nodes of tile bx added in ascending segment order, then the rest
+// of the force as in fa2_exact_force_tile.
+__device__ __forceinline__ void fa2_combine_tile(int32_t bx, int32_t K, int32_t nseg, const float2 *__restrict__ seg,
+                                                 const float2 *__restrict__ pos, const float *__restrict__ mass,
+                                                 const float2 *__restrict__ att, const uint32_t *__restrict__ item_of,
+                                                 float kr, float kg, const float2 *__restrict__ fprev,
+                                                 float2 *__restrict__ F, double2 *__restrict__ part) {
+    __shared__ double2 ws[kFa2Tile / kWave];
+    const int32_t i = bx * kFa2Tile + threadIdx.x;
+    double2 st = make_double2(0.0, 0.0);
+    if (i < K) {
+        float2 r = seg[i];
+        for (int32_t q = 1; q < nseg; ++q) {
+            const float2 v = seg[(int64_t)q * K + i];
+            r.x += v.x;
+            r.y += v.y;
+        }
+        const float f_mi = mass[i];
+        const float2 f = fa2_net_force(pos[i], f_mi, kr, r.x, r.y, fa2_att_value(att, item_of, i), kg);
+        F[i] = f;
+        st = fa2_swing_traction(f, fprev[i], f_mi);
     }
     st = fa2_sum256(st, ws);
     if (threadIdx.x == 0) part[bx] = st;

@@ -33,9 +33,11 @@ def batch():
     graphs = graphgen.batched_planted(24, seed=77, median=300, sigma=0.9, nmin=20, nmax=3000)
     graphs[3] = (1, np.zeros((0, 2), np.int32), np.zeros(1, np.int32))                # one node, no edge
     graphs[7] = (5, np.array([[1, 1], [2, 2], [3, 3]], np.int32), np.zeros(5, np.int32))  # only loops
-    # no edges at all: every node is its own supernode, so the layout spans two
-    # repulsion segments of 4096 bodies
+    # no edges at all: every node is its own supernode, so the layouts span several
+    # repulsion segments of 512 bodies; 4500 is above the largest size the
+    # multi-workgroup kernels take, 3000 within it
     graphs[11] = (4500, np.zeros((0, 2), np.int32), np.zeros(4500, np.int32))
+    graphs[13] = (3000, np.zeros((0, 2), np.int32), np.zeros(3000, np.int32))
     c1 = graphgen.hash_coeffs(wl["rows"], wl["sketch_seed"])
     c2 = graphgen.hash_coeffs(wl["rows"], wl["sketch_seed"] ^ 0x9E3779B97F4A7C15)
     pos0 = [graphgen.initial_positions(n, wl["pos_seed"] + g) for g, (n, _, _) in enumerate(graphs)]
