@@ -72,9 +72,12 @@ typedef struct {
     int64_t chunk;     /* >= 1: edges per synchronous chunk                        */
 } bgv_cd_params;
 
-/* Workspace bytes for bgv_community (0 only on invalid arguments): 16 bytes per node,
- * 4 per edge of a chunk, and with passes > 1 another 8 per edge (each edge's pass-0
- * endpoint counters, from which later passes' counters follow without increments). */
+/* Workspace bytes for bgv_community (0 only on invalid arguments).  Up to 2^24 nodes:
+ * 8 bytes per node and, per 1024-edge tile of a chunk, 16 KiB of grouped proposals and
+ * endpoints plus two offset rows of 4 * (ceil(n / 4096) + 1) bytes.  Above: 16 bytes per
+ * node and 4 per edge of a chunk.  With passes > 1 another 8 per edge (each edge's
+ * pass-0 endpoint counters, from which later passes' counters follow without
+ * increments). */
 size_t bgv_community_workspace(int32_t n, int64_t m, const bgv_cd_params *p);
 
 /*

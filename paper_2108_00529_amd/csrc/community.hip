@@ -1,14 +1,31 @@
 // Streaming community detection (Section 3.2 rule, Section 3.2.1 / Algorithm 3 passes),
-// batch-synchronous form.  Per chunk of the edge stream:
-//   kernel A  = apply(previous chunk) + counter increments(this chunk, pass 0 only)
-//   kernel B  = decide(this chunk): every edge reads the chunk-end counters and the
-//               chunk-start labels and proposes with a 64-bit atomicMin keyed by its
-//               stream index (smallest index wins)
-// The apply of chunk k only touches labels/proposal slots and the increments of chunk
-// k+1 only touch counters, so the two are fused into one launch.
+// batch-synchronous form: per chunk of the edge stream, every edge reads its endpoints'
+// counters at the end of the chunk and their labels at its start; an edge whose two
+// counters are at most the pass threshold and differ proposes that the endpoint with
+// the smaller counter join the other's community, and of the proposals to one node the
+// one from the smallest stream index wins.
 //
-// Per-node state is one 16-byte record {counter, label, proposal}: the counter
-// atomics, the decision gathers and the proposal atomic of a node hit one cache line.
+// Two implementations give the same integers.
+//
+// Bucketed (n <= kCdMaxBuckets * kCdBucket): node records {counter, label} (8 bytes)
+// and no global atomics.  Nodes fall into buckets of kCdBucket consecutive ids.
+//   group (pass 0)  each 1024-edge tile of the chunk writes its endpoints grouped by
+//                   bucket, one segment per (tile, bucket), offsets in a per-tile table
+//   decide          each 1024-edge tile writes its proposals (target, stream index,
+//                   label) grouped by the target's bucket in the same way
+//   resolve         one workgroup per bucket reads its segments from every tile: the
+//                   smallest proposing index per target by LDS atomicMin, the winners'
+//                   labels written, and in pass 0 the next chunk's counter increments
+//                   summed in LDS and added to the records, which no other workgroup
+//                   touches.
+// Device-scope atomics run at a small fraction of the LDS rate on this chip, and the
+// grouping costs two coalesced streams per chunk instead.
+//
+// Atomic (larger n): one 16-byte record {counter, label, proposal} per node;
+//   kernel A  = apply(previous chunk) + counter atomics(this chunk, pass 0 only)
+//   kernel B  = decide(this chunk), proposals by a 64-bit atomicMin keyed by the
+//               stream index.
+#include "block_scan.h"
 #include "common.h"
 
 namespace bgv {
@@ -98,14 +115,209 @@ __global__ void __launch_bounds__(kCdThreads) k_cd_decide(NodeState *__restrict_
 }
 
 // Counting stops after pass 0, so each record's counter is d(v), the true degree.
-__global__ void __launch_bounds__(kCdThreads) k_cd_finish(const NodeState *__restrict__ st, int32_t n,
+// Records are kRecInts int32 apart ({counter, label} first).
+template <int kRecInts>
+__global__ void __launch_bounds__(kCdThreads) k_cd_finish(const int32_t *__restrict__ st, int32_t n,
                                                            int32_t *__restrict__ labels, int32_t *__restrict__ degree,
                                                            unsigned long long *__restrict__ volume) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-        const int2 s = *reinterpret_cast<const int2 *>(&st[v]);
+        const int2 s = *reinterpret_cast<const int2 *>(st + kRecInts * v);
         labels[v] = s.y;
         degree[v] = s.x;
         if (volume && s.x) atomicAdd(&volume[s.y], (unsigned long long)s.x);
+    }
+}
+
+// ------------------------------------------------------------ bucketed path -------
+constexpr int kCdBucketBits = 12;
+constexpr int32_t kCdBucket = 1 << kCdBucketBits;  // node ids per bucket
+constexpr int32_t kCdMaxBuckets = 4096;             // bucket histogram held in LDS
+constexpr int kCdItems = 4;
+constexpr int32_t kCdTile = kCdThreads * kCdItems;  // edges per tile
+
+inline int32_t cd_buckets(int32_t n) { return (n + kCdBucket - 1) / kCdBucket; }
+inline bool cd_bucketed(int32_t n) { return cd_buckets(n) <= kCdMaxBuckets; }
+
+// Tile-local grouping by bucket: hist[0, nb) holds each bucket's entry count; turns it
+// into exclusive offsets in place, writes them (and the total at [nb]) to the tile's
+// table row, and returns the total.
+__device__ __forceinline__ uint32_t cd_offsets(uint32_t *hist, int32_t nb, uint32_t *__restrict__ row) {
+    const int32_t per = (nb + kCdThreads - 1) / kCdThreads;
+    const int32_t b0 = min(nb, (int32_t)threadIdx.x * per), b1 = min(nb, b0 + per);
+    uint32_t sum = 0;
+    for (int32_t b = b0; b < b1; ++b) sum += hist[b];
+    uint32_t total;
+    uint32_t run = block_excl_scan<uint32_t>(sum, &total);  // synchronises the block
+    for (int32_t b = b0; b < b1; ++b) {
+        const uint32_t c = hist[b];
+        hist[b] = run;
+        row[b] = run;
+        run += c;
+    }
+    if (threadIdx.x == 0) row[nb] = total;
+    __syncthreads();
+    return total;
+}
+
+__global__ void __launch_bounds__(kCdThreads) k_cd_init_b(int2 *st, int32_t n) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        st[v] = make_int2(0, (int32_t)v);
+}
+
+// Endpoints of the non-loop edges of tile blockIdx.x of chunk [cs, ce), grouped by
+// bucket: ends[tile * 2 * kCdTile + ...] holds their offsets within the bucket.
+__global__ void __launch_bounds__(kCdThreads) k_cd_group_ends(const int2 *__restrict__ edges, int64_t cs, int64_t ce,
+                                                               int32_t nb, uint16_t *__restrict__ ends,
+                                                               uint32_t *__restrict__ etab) {
+    __shared__ uint32_t hist[kCdMaxBuckets];
+    __shared__ uint16_t stage[2 * kCdTile];
+    for (int32_t b = threadIdx.x; b < nb; b += kCdThreads) hist[b] = 0;
+    __syncthreads();
+    const int64_t t0 = cs + (int64_t)blockIdx.x * kCdTile;
+    int32_t node[2 * kCdItems];
+    uint32_t rank[2 * kCdItems];
+#pragma unroll
+    for (int j = 0; j < kCdItems; ++j) {
+        const int64_t i = t0 + j * kCdThreads + threadIdx.x;
+        node[2 * j] = node[2 * j + 1] = -1;
+        if (i < ce) {
+            const int2 e = edges[i];
+            if (e.x != e.y) {
+                node[2 * j] = e.x;
+                node[2 * j + 1] = e.y;
+                rank[2 * j] = atomicAdd(&hist[e.x >> kCdBucketBits], 1u);
+                rank[2 * j + 1] = atomicAdd(&hist[e.y >> kCdBucketBits], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t total = cd_offsets(hist, nb, etab + (int64_t)blockIdx.x * (nb + 1));
+#pragma unroll
+    for (int q = 0; q < 2 * kCdItems; ++q)
+        if (node[q] >= 0)
+            stage[hist[node[q] >> kCdBucketBits] + rank[q]] = (uint16_t)(node[q] & (kCdBucket - 1));
+    __syncthreads();
+    uint16_t *out = ends + (int64_t)blockIdx.x * (2 * kCdTile);
+    for (uint32_t k = threadIdx.x; k < total; k += kCdThreads) out[k] = stage[k];
+}
+
+// Decide, tile blockIdx.x of chunk [cs, ce): the rule above on the records (counters
+// as in the atomic path's decide: pass-0 values stored per edge in c1 when more passes
+// follow, p * d(v) + c1 in later passes), each proposal (offset of the target in its
+// bucket, stream index, label) grouped by the target's bucket.
+template <int kMode>  // 0: only pass; 1: pass 0 of several; 2: a later pass
+__global__ void __launch_bounds__(kCdThreads) k_cd_decide_b(const int2 *__restrict__ st,
+                                                             const int2 *__restrict__ edges, int2 *__restrict__ c1,
+                                                             int64_t cs, int64_t ce, int32_t D, int32_t pass,
+                                                             int32_t nb, uint3 *__restrict__ props,
+                                                             uint32_t *__restrict__ ptab) {
+    __shared__ uint32_t hist[kCdMaxBuckets];
+    __shared__ uint3 stage[kCdTile];
+    for (int32_t b = threadIdx.x; b < nb; b += kCdThreads) hist[b] = 0;
+    __syncthreads();
+    const int64_t t0 = cs + (int64_t)blockIdx.x * kCdTile;
+    int32_t target[kCdItems], lab[kCdItems];
+    uint32_t rank[kCdItems];
+#pragma unroll
+    for (int j = 0; j < kCdItems; ++j) {
+        const int64_t i = t0 + j * kCdThreads + threadIdx.x;
+        target[j] = -1;
+        if (i < ce) {
+            const int2 e = edges[i];
+            if (e.x != e.y) {
+                const int2 su = st[e.x], sv = st[e.y];  // {counter, label}
+                int32_t cu = su.x, cv = sv.x;
+                if (kMode == 1) c1[i] = make_int2(cu, cv);
+                if (kMode == 2) {
+                    const int2 c = c1[i];
+                    cu = pass * su.x + c.x;
+                    cv = pass * sv.x + c.y;
+                }
+                if (cu <= D && cv <= D && cu != cv) {
+                    const bool u_low = cu < cv;
+                    target[j] = u_low ? e.x : e.y;
+                    lab[j] = u_low ? sv.y : su.y;
+                    rank[j] = atomicAdd(&hist[target[j] >> kCdBucketBits], 1u);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t total = cd_offsets(hist, nb, ptab + (int64_t)blockIdx.x * (nb + 1));
+#pragma unroll
+    for (int j = 0; j < kCdItems; ++j)
+        if (target[j] >= 0)
+            stage[hist[target[j] >> kCdBucketBits] + rank[j]] =
+                make_uint3((uint32_t)(target[j] & (kCdBucket - 1)),
+                           (uint32_t)(t0 + j * kCdThreads + threadIdx.x), (uint32_t)lab[j]);
+    __syncthreads();
+    uint3 *out = props + (int64_t)blockIdx.x * kCdTile;
+    for (uint32_t k = threadIdx.x; k < total; k += kCdThreads) out[k] = stage[k];
+}
+
+// Resolve, one workgroup per bucket: proposals from ptiles decide tiles and counter
+// increments from etiles grouped tiles.  The winner of a target is the smallest
+// (stream index, label) key (stream indices are distinct), found by LDS atomicMin;
+// then one sweep over the bucket's records writes the winners' labels and adds the
+// counts.  Only this workgroup writes the bucket's records.  One thread per tile (while
+// tiles <= kCdResolveThreads), each segment's entries loaded in batches before they are
+// applied, so a thread waits on few memory round trips.
+constexpr int kCdResolveThreads = 1024;
+
+__device__ __forceinline__ void cd_segment(const uint32_t *__restrict__ tab, int32_t nb, int32_t t, int32_t b,
+                                           uint32_t *q0, uint32_t *q1) {
+    const uint32_t *row = tab + (int64_t)t * (nb + 1);
+    *q0 = row[b];
+    *q1 = row[b + 1];
+}
+
+__global__ void __launch_bounds__(kCdResolveThreads) k_cd_resolve(int2 *__restrict__ st, int32_t n, int32_t nb,
+                                                                   const uint3 *__restrict__ props,
+                                                                   const uint32_t *__restrict__ ptab, int32_t ptiles,
+                                                                   const uint16_t *__restrict__ ends,
+                                                                   const uint32_t *__restrict__ etab, int32_t etiles) {
+    __shared__ unsigned long long win[kCdBucket];
+    __shared__ uint32_t inc[kCdBucket];
+    const int32_t b = blockIdx.x;
+    for (int32_t k = threadIdx.x; k < kCdBucket; k += kCdResolveThreads) {
+        win[k] = ~0ull;
+        inc[k] = 0u;
+    }
+    __syncthreads();
+    const int32_t tiles = max(ptiles, etiles);
+    for (int32_t t = threadIdx.x; t < tiles; t += kCdResolveThreads) {
+        uint32_t p0 = 0, p1 = 0, e0 = 0, e1 = 0;
+        if (t < ptiles) cd_segment(ptab, nb, t, b, &p0, &p1);
+        if (t < etiles) cd_segment(etab, nb, t, b, &e0, &e1);
+        const uint3 *ps = props + (int64_t)t * kCdTile;
+        for (uint32_t q = p0; q < p1; q += 4) {
+            uint3 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (q + u < p1) v[u] = ps[q + u];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (q + u < p1) atomicMin(&win[v[u].x], ((unsigned long long)v[u].y << 32) | v[u].z);
+        }
+        const uint16_t *es = ends + (int64_t)t * (2 * kCdTile);
+        for (uint32_t q = e0; q < e1; q += 8) {
+            uint32_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (q + u < e1) v[u] = es[q + u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (q + u < e1) atomicAdd(&inc[v[u]], 1u);
+        }
+    }
+    __syncthreads();
+    int2 *rec = st + ((int64_t)b << kCdBucketBits);
+    const int32_t span = min(kCdBucket, n - (b << kCdBucketBits));
+    for (int32_t k = threadIdx.x; k < span; k += kCdResolveThreads) {
+        const unsigned long long w = win[k];
+        const uint32_t c = inc[k];
+        if (w != ~0ull) rec[k].y = (int32_t)(uint32_t)w;
+        if (c) rec[k].x += (int32_t)c;
     }
 }
 
@@ -123,12 +335,33 @@ static bool cd_valid(int32_t n, int64_t m, const bgv_cd_params *p) {
            p->chunk >= 1 && p->reserved == 0;
 }
 
-static size_t cd_layout(Carver &c, int32_t n, int64_t m, const bgv_cd_params *p, NodeState **st, int32_t **prop,
-                        int2 **c1) {
-    *st = c.take<NodeState>((size_t)n);
+struct CdWs {
+    NodeState *st;      // atomic path
+    int32_t *prop;      // atomic path
+    int2 *st2;          // bucketed path
+    uint3 *props;       // bucketed: proposals grouped per tile
+    uint16_t *ends;     // bucketed: endpoints grouped per tile
+    uint32_t *ptab, *etab;
+    int2 *c1;
+};
+
+static size_t cd_layout(Carver &c, int32_t n, int64_t m, const bgv_cd_params *p, CdWs *w) {
     const int64_t b = p->chunk < m ? p->chunk : m;
-    *prop = c.take<int32_t>((size_t)(b > 0 ? b : 1));
-    *c1 = p->passes > 1 && m > 0 ? c.take<int2>((size_t)m) : nullptr;
+    const size_t bb = (size_t)(b > 0 ? b : 1);
+    *w = CdWs{};
+    if (cd_bucketed(n)) {
+        const size_t tiles = (bb + kCdTile - 1) / kCdTile;
+        const size_t nb = (size_t)cd_buckets(n);
+        w->st2 = c.take<int2>((size_t)n);
+        w->props = c.take<uint3>(tiles * kCdTile);
+        w->ends = c.take<uint16_t>(tiles * 2 * kCdTile);
+        w->ptab = c.take<uint32_t>(tiles * (nb + 1));
+        w->etab = c.take<uint32_t>(tiles * (nb + 1));
+    } else {
+        w->st = c.take<NodeState>((size_t)n);
+        w->prop = c.take<int32_t>(bb);
+    }
+    w->c1 = p->passes > 1 && m > 0 ? c.take<int2>((size_t)m) : nullptr;
     return c.size();
 }
 
@@ -139,10 +372,8 @@ using namespace bgv;
 extern "C" size_t bgv_community_workspace(int32_t n, int64_t m, const bgv_cd_params *p) {
     if (!cd_valid(n, m, p)) return 0;
     Carver c(nullptr);
-    NodeState *st;
-    int32_t *prop;
-    int2 *c1;
-    return cd_layout(c, n, m, p, &st, &prop, &c1);
+    CdWs w;
+    return cd_layout(c, n, m, p, &w);
 }
 
 extern "C" bgv_status bgv_community(int32_t n, int64_t m, const int32_t *edges, const bgv_cd_params *p,
@@ -160,17 +391,55 @@ extern "C" bgv_status bgv_community(int32_t n, int64_t m, const int32_t *edges, 
     BGV_TRY(check_ws(ws, ws_bytes, bgv_community_workspace(n, m, p)));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     Carver c(ws);
-    NodeState *st;
-    int32_t *prop;
-    int2 *c1;
-    cd_layout(c, n, m, p, &st, &prop, &c1);
+    CdWs w;
+    cd_layout(c, n, m, p, &w);
     const int2 *e2 = reinterpret_cast<const int2 *>(edges);
-
-    BGV_LAUNCH(k_cd_init, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, st, n);
     if (volume) BGV_TRY(fill<int64_t>(volume, 0, n, s));
-
     const int64_t B = p->chunk;
     const int64_t nchunk = (m + B - 1) / B;
+
+    if (cd_bucketed(n)) {
+        const int32_t nb = cd_buckets(n);
+        int2 *st2 = w.st2;
+        BGV_LAUNCH(k_cd_init_b, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, st2, n);
+        int32_t ptiles = 0;  // decide tiles whose proposals are not yet resolved
+        for (int32_t pass = 0; pass < p->passes && m > 0; ++pass) {
+            const int32_t D = pass_threshold(p->threshold, p->growth, pass);
+            for (int64_t k = 0; k < nchunk; ++k) {
+                const int64_t cs = k * B, ce = (cs + B < m) ? cs + B : m;
+                const int32_t tiles = (int32_t)((ce - cs + kCdTile - 1) / kCdTile);
+                // counters are incremented in pass 0 only (later passes use the closed form)
+                const int32_t etiles = pass == 0 ? tiles : 0;
+                if (etiles > 0)
+                    BGV_LAUNCH(k_cd_group_ends, dim3(etiles), dim3(kCdThreads), 0, s, e2, cs, ce, nb, w.ends, w.etab);
+                if (ptiles > 0 || etiles > 0)
+                    BGV_LAUNCH(k_cd_resolve, dim3(nb), dim3(kCdResolveThreads), 0, s, st2, n, nb, w.props, w.ptab, ptiles,
+                               w.ends, w.etab, etiles);
+                if (p->passes == 1)
+                    BGV_LAUNCH(k_cd_decide_b<0>, dim3(tiles), dim3(kCdThreads), 0, s, st2, e2, w.c1, cs, ce, D, pass,
+                               nb, w.props, w.ptab);
+                else if (pass == 0)
+                    BGV_LAUNCH(k_cd_decide_b<1>, dim3(tiles), dim3(kCdThreads), 0, s, st2, e2, w.c1, cs, ce, D, pass,
+                               nb, w.props, w.ptab);
+                else
+                    BGV_LAUNCH(k_cd_decide_b<2>, dim3(tiles), dim3(kCdThreads), 0, s, st2, e2, w.c1, cs, ce, D, pass,
+                               nb, w.props, w.ptab);
+                ptiles = tiles;
+            }
+        }
+        if (ptiles > 0)
+            BGV_LAUNCH(k_cd_resolve, dim3(nb), dim3(kCdResolveThreads), 0, s, st2, n, nb, w.props, w.ptab, ptiles, w.ends,
+                       w.etab, 0);
+        BGV_LAUNCH(k_cd_finish<2>, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s,
+                   reinterpret_cast<const int32_t *>(st2), n, labels, degree,
+                   reinterpret_cast<unsigned long long *>(volume));
+        return BGV_OK;
+    }
+
+    NodeState *st = w.st;
+    int32_t *prop = w.prop;
+    int2 *c1 = w.c1;
+    BGV_LAUNCH(k_cd_init, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, st, n);
     int64_t ps = 0, pe = 0;  // pending (not yet applied) chunk
     for (int32_t pass = 0; pass < p->passes && m > 0; ++pass) {
         const int32_t D = pass_threshold(p->threshold, p->growth, pass);
@@ -197,7 +466,8 @@ extern "C" bgv_status bgv_community(int32_t n, int64_t m, const int32_t *edges, 
         BGV_LAUNCH(k_cd_apply_hist, dim3(grid_for(pe - ps, kCdThreads * 4, 16384)), dim3(kCdThreads), 0, s,
                            st, e2, prop, ps, pe, (int64_t)0, (int64_t)0);
     }
-    BGV_LAUNCH(k_cd_finish, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, st, n, labels, degree,
+    BGV_LAUNCH(k_cd_finish<4>, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s,
+               reinterpret_cast<const int32_t *>(st), n, labels, degree,
                reinterpret_cast<unsigned long long *>(volume));
     return BGV_OK;
 }

@@ -36,11 +36,15 @@ def test_status_strings():
 
 
 def test_community_validation_and_workspace():
-    p = L.CdParams(16, 1, 2, 0, 256)
+    p = L.CdParams(16, 1, 2, 0, 4096)
     ws = L.bgv_community_workspace(2000, 10000, C.byref(p))
-    assert ws >= 2000 * 16 + 256 * 4
-    ws2 = L.bgv_community_workspace(2000, 100, C.byref(p))  # chunk clipped to m
+    assert ws >= 2000 * 8 + 4 * 1024 * 16  # records + four 1024-edge tiles of grouped entries
+    ws2 = L.bgv_community_workspace(2000, 100, C.byref(p))  # chunk clipped to m: one tile
     assert ws2 < ws
+    p3 = L.CdParams(16, 3, 2, 0, 4096)
+    assert L.bgv_community_workspace(2000, 10000, C.byref(p3)) >= ws + 8 * 10000  # pass-0 counters per edge
+    big = L.bgv_community_workspace((1 << 24) + 1, 100, C.byref(p))  # per-node atomic form
+    assert big >= ((1 << 24) + 1) * 16
     for bad in [L.CdParams(-1, 1, 2, 0, 1), L.CdParams(1, 0, 2, 0, 1), L.CdParams(1, 1, 0, 0, 1),
                 L.CdParams(1, 1, 2, 0, 0), L.CdParams(1, 1, 2, 7, 1)]:
         assert L.bgv_community_workspace(10, 10, C.byref(bad)) == 0

@@ -93,6 +93,32 @@ def test_community_tiny_and_degenerate(bgv):
         check_community(bgv, n, e, int(rng.integers(0, 20)), int(rng.integers(1, 4)), int(rng.integers(1, 4)), B)
 
 
+def test_community_bucket_boundaries(bgv):
+    """Several 4096-node buckets, chunks of several 1024-edge tiles with ragged tails,
+    a hub in every chunk (many proposals to and from one bucket) and self-loops."""
+    rng = np.random.default_rng(23)
+    n = 3 * 4096 + 17
+    m = 60_000
+    e = rng.integers(0, n, (m, 2)).astype(np.int32)
+    hub = rng.random(m) < 0.05
+    e[hub, 0] = 4095  # last id of bucket 0
+    e[rng.random(m) < 0.01, 1] = n - 1
+    loop = rng.random(m) < 0.02
+    e[loop, 1] = e[loop, 0]
+    for B, P in ((5000, 3), (1024, 2), (1025, 1), (m, 2)):
+        check_community(bgv, n, e, 6, P, 2, B)
+
+
+def test_community_above_bucket_limit(bgv):
+    """More than 4096 buckets of 4096 nodes: the per-node atomic form."""
+    rng = np.random.default_rng(29)
+    n = (1 << 24) + 4099
+    m = 40_000
+    ids = np.concatenate([rng.integers(0, 5000, 3000), rng.integers(n - 5000, n, 3000)])
+    e = ids[rng.integers(0, len(ids), (m, 2))].astype(np.int32)
+    check_community(bgv, n, e, 8, 2, 2, 3000)
+
+
 @pytest.fixture(scope="module")
 def planted():
     wl = graphgen.WORKLOADS["planted_2k"]
