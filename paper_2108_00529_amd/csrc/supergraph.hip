@@ -164,6 +164,116 @@ __global__ void k_sg_sketch_pairs(const int32_t *__restrict__ superedges, const 
     }
 }
 
+// Sketch 2 without global atomics, for sketches of at most kSkMaxBuckets buckets of
+// kSkBucket consecutive cells (cell = row * cols + column).  Each tile of kSkTile
+// distinct pairs writes its (cell offset in bucket, multiplicity) entries grouped by
+// bucket, one segment per (tile, bucket), offsets in a per-tile table row; then one
+// workgroup per bucket sums its segments from every tile in LDS and writes the
+// bucket's cells, all of them, so the sketch needs no clearing.  Same integer sums.
+constexpr int kSkBucketBits = 14;
+constexpr int32_t kSkBucket = 1 << kSkBucketBits;
+constexpr int32_t kSkMaxBuckets = 4096;
+constexpr int kSkItems = 4;
+constexpr int32_t kSkTile = kSgThreads * kSkItems;
+constexpr int kSkResolveThreads = 1024;
+
+inline int64_t sk_buckets(int64_t cells) { return (cells + kSkBucket - 1) / kSkBucket; }
+
+__global__ void __launch_bounds__(kSgThreads) k_sg_group_pairs(const int32_t *__restrict__ superedges,
+                                                                const uint32_t *__restrict__ run_start,
+                                                                const uint32_t *__restrict__ Ep, uint32_t nk,
+                                                                const int32_t *__restrict__ super_label, HashRows h,
+                                                                int32_t rows, uint32_t cols, int32_t nb,
+                                                                uint2 *__restrict__ ent, uint32_t *__restrict__ etab,
+                                                                uint32_t *__restrict__ se_count) {
+    __shared__ uint32_t hist[kSkMaxBuckets];
+    __shared__ uint2 stage[kSkTile * kMaxRows];
+    const int64_t E = *Ep;
+    const int64_t j0 = (int64_t)blockIdx.x * kSkTile;
+    if (j0 >= E) return;  // the grid covers the key count, an upper bound of E
+    for (int32_t b = threadIdx.x; b < nb; b += kSgThreads) hist[b] = 0;
+    __syncthreads();
+    uint32_t la[kSkItems], lb[kSkItems], cnt[kSkItems], rank[kSkItems][kMaxRows];
+#pragma unroll
+    for (int u = 0; u < kSkItems; ++u) {
+        const int64_t j = j0 + u * kSgThreads + threadIdx.x;
+        cnt[u] = 0;
+        if (j < E) {
+            cnt[u] = (j + 1 < E ? run_start[j + 1] : nk) - run_start[j];
+            la[u] = (uint32_t)super_label[superedges[2 * j]];
+            lb[u] = (uint32_t)super_label[superedges[2 * j + 1]];
+            if (se_count) se_count[j] = cnt[u];
+#pragma unroll
+            for (int r = 0; r < kMaxRows; ++r)
+                if (r < rows) {
+                    const uint32_t cell = (uint32_t)r * cols + col_pair(h.a[r], h.b[r], h.c[r], la[u], lb[u], cols);
+                    rank[u][r] = atomicAdd(&hist[cell >> kSkBucketBits], 1u);
+                }
+        }
+    }
+    __syncthreads();
+    // exclusive offsets of the tile's buckets, in place and into the table row
+    uint32_t *row = etab + (int64_t)blockIdx.x * (nb + 1);
+    const int32_t per = (nb + kSgThreads - 1) / kSgThreads;
+    const int32_t b0 = min(nb, (int32_t)threadIdx.x * per), b1 = min(nb, b0 + per);
+    uint32_t sum = 0;
+    for (int32_t b = b0; b < b1; ++b) sum += hist[b];
+    uint32_t total;
+    uint32_t run = block_excl_scan<uint32_t>(sum, &total);
+    for (int32_t b = b0; b < b1; ++b) {
+        const uint32_t c = hist[b];
+        hist[b] = run;
+        row[b] = run;
+        run += c;
+    }
+    if (threadIdx.x == 0) row[nb] = total;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kSkItems; ++u)
+        if (cnt[u]) {
+#pragma unroll
+            for (int r = 0; r < kMaxRows; ++r)
+                if (r < rows) {
+                    const uint32_t cell = (uint32_t)r * cols + col_pair(h.a[r], h.b[r], h.c[r], la[u], lb[u], cols);
+                    stage[hist[cell >> kSkBucketBits] + rank[u][r]] =
+                        make_uint2(cell & (kSkBucket - 1), cnt[u]);
+                }
+        }
+    __syncthreads();
+    uint2 *out = ent + (int64_t)blockIdx.x * (kSkTile * rows);  // a tile's region holds kSkTile * rows
+    for (uint32_t k = threadIdx.x; k < total; k += kSgThreads) out[k] = stage[k];
+}
+
+__global__ void __launch_bounds__(kSkResolveThreads) k_sg_sum_cells(const uint2 *__restrict__ ent,
+                                                                     const uint32_t *__restrict__ etab,
+                                                                     const uint32_t *__restrict__ Ep, int32_t rows,
+                                                                     int32_t nb, int64_t cells,
+                                                                     uint32_t *__restrict__ M2) {
+    __shared__ uint32_t acc[kSkBucket];
+    const int32_t b = blockIdx.x;
+    for (int32_t k = threadIdx.x; k < kSkBucket; k += kSkResolveThreads) acc[k] = 0u;
+    __syncthreads();
+    const int64_t tiles = ((int64_t)*Ep + kSkTile - 1) / kSkTile;
+    for (int64_t t = threadIdx.x; t < tiles; t += kSkResolveThreads) {
+        const uint32_t *row = etab + t * (nb + 1);
+        const uint32_t q0 = row[b], q1 = row[b + 1];
+        const uint2 *seg = ent + t * (kSkTile * rows);
+        for (uint32_t q = q0; q < q1; q += 8) {
+            uint2 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (q + u < q1) v[u] = seg[q + u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (q + u < q1) atomicAdd(&acc[v[u].x], v[u].y);
+        }
+    }
+    __syncthreads();
+    const int64_t base = (int64_t)b << kSkBucketBits;
+    const int32_t span = (int32_t)min((int64_t)kSkBucket, cells - base);
+    for (int32_t k = threadIdx.x; k < span; k += kSkResolveThreads) M2[base + k] = acc[k];
+}
+
 // Superedge weight = count-min estimate (minimum over the rows of sketch 2).
 __global__ void k_sg_pair_weights(const int32_t *__restrict__ superedges, const uint32_t *__restrict__ Ep,
                                   const int32_t *__restrict__ super_label, HashRows h, int32_t rows, uint32_t cols,
@@ -188,11 +298,15 @@ __global__ void k_sg_node_super(const int32_t *__restrict__ labels, const uint32
 struct SgWs {
     uint32_t *flag, *sid, *vol, *counters, *uflag, *upos, *run_start;
     uint64_t *keys, *keys_alt;
+    uint2 *ent;       // grouped sketch-2 entries (bucketed sketch only)
+    uint32_t *etab;   // their per-tile offset rows
     void *scan_scratch, *sort_scratch;
 };
 
-static size_t sg_layout(Carver &c, int32_t n, int64_t m, SgWs *w) {
+static size_t sg_layout(Carver &c, int32_t n, int64_t m, int32_t rows, int64_t cells, SgWs *w) {
     const int64_t mm = m > 0 ? m : 1;
+    w->ent = nullptr;
+    w->etab = nullptr;
     w->flag = c.take<uint32_t>((size_t)n);
     w->sid = c.take<uint32_t>((size_t)n);
     w->vol = c.take<uint32_t>((size_t)n);
@@ -205,6 +319,13 @@ static size_t sg_layout(Carver &c, int32_t n, int64_t m, SgWs *w) {
     const int64_t big = n > mm ? n : mm;
     w->scan_scratch = c.take<char>(scan_workspace(big));
     w->sort_scratch = c.take<char>(radix_workspace(mm));
+    const int64_t nb = sk_buckets(cells);
+    if (nb <= kSkMaxBuckets) {
+        // distinct pairs <= m: a tile bound, rows entries per pair
+        const size_t tiles = (size_t)((mm + kSkTile - 1) / kSkTile);
+        w->ent = c.take<uint2>(tiles * kSkTile * (size_t)rows);
+        w->etab = c.take<uint32_t>(tiles * (size_t)(nb + 1));
+    }
     return c.size();
 }
 
@@ -222,7 +343,7 @@ extern "C" size_t bgv_supergraph_workspace(int32_t n, int64_t m, const bgv_sketc
     if (!sg_valid(n, m, s)) return 0;
     Carver c(nullptr);
     SgWs w;
-    return sg_layout(c, n, m, &w);
+    return sg_layout(c, n, m, s->rows, (int64_t)s->rows * s->cols, &w);
 }
 
 extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges, const int32_t *labels,
@@ -245,7 +366,7 @@ extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges,
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     Carver c(ws);
     SgWs w;
-    sg_layout(c, n, m, &w);
+    sg_layout(c, n, m, sp->rows, (int64_t)sp->rows * sp->cols, &w);
     const int rows = sp->rows;
     const uint32_t cols = (uint32_t)sp->cols;
     const HashRows h1 = make_hash_rows(sp->coef1, rows), h2 = make_hash_rows(sp->coef2, rows);
@@ -270,7 +391,8 @@ extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges,
 
     // sketch 1 and sizes
     BGV_TRY(fill<uint32_t>(M1, 0u, cells, s));
-    BGV_TRY(fill<uint32_t>(M2, 0u, cells, s));
+    const bool grouped_sketch = w.ent != nullptr;  // sketch 2 written whole by k_sg_sum_cells
+    if (!grouped_sketch) BGV_TRY(fill<uint32_t>(M2, 0u, cells, s));
     if (lds_sketch) {
         BGV_LAUNCH(k_sg_sketch_nodes_lds, dim3(grid_for(n, kSgThreads * 16, 1024)), dim3(kSgThreads), 0, s,
                    labels, degree, n, h1, rows, cols, M1);
@@ -302,6 +424,7 @@ extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges,
     BGV_CHECK_HIP(hipMemcpyAsync(&nk, nkeys_d, sizeof nk, hipMemcpyDeviceToHost, s));
     BGV_CHECK_HIP(hipStreamSynchronize(s));
     int64_t E = 0;
+    if (nk == 0 && grouped_sketch) BGV_TRY(fill<uint32_t>(M2, 0u, cells, s));
     if (nk > 0) {
         uint64_t *sorted;
         BGV_TRY(radix_sort_u64(w.keys, w.keys_alt, nullptr, nullptr, (int64_t)nk, 2 * kbits, &sorted, nullptr,
@@ -311,8 +434,17 @@ extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges,
         BGV_TRY(exclusive_scan_u32(w.uflag, w.upos, (int64_t)nk, &w.counters[1], w.scan_scratch, s));
         BGV_LAUNCH(k_sg_unique_write, dim3(gk), dim3(kSgThreads), 0, s, sorted, (int64_t)nk, w.uflag, w.upos, kbits,
                    superedges, w.run_start);
-        BGV_LAUNCH(k_sg_sketch_pairs, dim3(gk), dim3(kSgThreads), 0, s, superedges, w.run_start, &w.counters[1],
-                   (uint32_t)nk, super_label, h2, rows, cols, M2, se_count);
+        if (grouped_sketch) {
+            const int32_t nb = (int32_t)sk_buckets(cells);
+            BGV_LAUNCH(k_sg_group_pairs, dim3((unsigned)((nk + kSkTile - 1) / kSkTile)), dim3(kSgThreads), 0, s,
+                       superedges, w.run_start, &w.counters[1], (uint32_t)nk, super_label, h2, rows, cols, nb, w.ent,
+                       w.etab, se_count);
+            BGV_LAUNCH(k_sg_sum_cells, dim3(nb), dim3(kSkResolveThreads), 0, s, w.ent, w.etab, &w.counters[1], rows,
+                       nb, cells, M2);
+        } else {
+            BGV_LAUNCH(k_sg_sketch_pairs, dim3(gk), dim3(kSgThreads), 0, s, superedges, w.run_start, &w.counters[1],
+                       (uint32_t)nk, super_label, h2, rows, cols, M2, se_count);
+        }
         BGV_LAUNCH(k_sg_pair_weights, dim3(gk), dim3(kSgThreads), 0, s, superedges, &w.counters[1], super_label, h2,
                    rows, cols, M2, se_weight);
         uint32_t Eh = 0;
