@@ -745,17 +745,8 @@ extern "C" bgv_status bgv_batched(int32_t G, int64_t n_total, int64_t m_total, c
     a.big = w.big;
     a.nbig = w.nbig;
 
-    // compute-unit count, queried once per device so that a captured launch makes no query
-    static int cu_count[64] = {0};
-    int dev = 0;
-    BGV_CHECK_HIP(hipGetDevice(&dev));
-    if (dev < 0 || dev >= 64) dev = 0;
-    if (cu_count[dev] == 0) {
-        int c = 0;
-        BGV_CHECK_HIP(hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev));
-        cu_count[dev] = c > 0 ? c : 1;
-    }
-    const int cus = cu_count[dev];
+    int cus = 1;
+    BGV_TRY(device_cu_count(&cus));
     const int per_cu = wg_threads == 1024 ? 1 : 2;
     const int grid = G < cus * per_cu ? G : cus * per_cu;
     BGV_TRY(fill<uint32_t>(w.queue, 0u, 1, s));

@@ -88,6 +88,22 @@ inline bgv_status check_ws(void *ws, size_t have, size_t need) {
     return BGV_OK;
 }
 
+// Compute units of the current device, queried once per device, so that a launch
+// sequence captured in a graph makes no query.
+inline bgv_status device_cu_count(int *out) {
+    static int cached[64] = {0};
+    int dev = 0;
+    BGV_CHECK_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) dev = 0;
+    if (cached[dev] == 0) {
+        int c = 0;
+        BGV_CHECK_HIP(hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev));
+        cached[dev] = c > 0 ? c : 1;
+    }
+    *out = cached[dev];
+    return BGV_OK;
+}
+
 inline unsigned grid_for(int64_t items, int per_block, unsigned cap = 1u << 20) {
     int64_t g = (items + per_block - 1) / per_block;
     if (g < 1) g = 1;

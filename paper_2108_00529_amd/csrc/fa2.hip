@@ -183,7 +183,52 @@ __global__ void __launch_bounds__(kFaThreads) k_attract(int32_t K, const float2 
     }
 }
 
+// The same with all K positions staged in LDS first (K <= kAttLdsMax): the gathers of
+// the neighbours' positions then read LDS instead of L2.  One workgroup of 16
+// wavefronts per compute unit, so each position array is loaded once per unit.
+constexpr int32_t kAttLdsMax = 19456;  // 152 KiB of float2
+constexpr int kAttLdsThreads = 1024;
+
+template <typename E>
+__global__ void __launch_bounds__(kAttLdsThreads) k_attract_lds(int32_t K, const float2 *__restrict__ pos,
+                                                                 const uint32_t *__restrict__ row,
+                                                                 const E *__restrict__ cw,
+                                                                 const uint32_t *__restrict__ item_of,
+                                                                 const uint32_t *__restrict__ item_row,
+                                                                 float2 *__restrict__ A) {
+    __shared__ float2 sp[kAttLdsMax];
+    for (int32_t i = threadIdx.x; i < K; i += kAttLdsThreads) sp[i] = pos[i];
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t nw = (int64_t)gridDim.x * (kAttLdsThreads / kWave);
+    const uint32_t T = item_of[K];
+    for (int64_t t = (blockIdx.x * (int64_t)kAttLdsThreads + threadIdx.x) / kWave; t < T; t += nw) {
+        const uint32_t r = item_row[t];
+        const uint32_t r1 = row[r + 1];
+        const uint32_t b0 = row[r] + ((uint32_t)t - item_of[r]) * kAttBlock;
+        const uint32_t b1 = r1 - b0 > kAttBlock ? b0 + kAttBlock : r1;
+        const float2 a = fa2_block_attraction(sp, cw, b0, b1, sp[r], lane);
+        if (lane == 0) A[t] = a;
+    }
+}
+
 bgv_status attraction(int32_t K, const float2 *pos, const CsrWs &csr, float2 *A, hipStream_t s) {
+    if (K <= kAttLdsMax) {
+        int cus = 1;
+        BGV_TRY(device_cu_count(&cus));
+        const unsigned wg = (unsigned)((csr.items_bound + kAttLdsThreads / kWave - 1) / (kAttLdsThreads / kWave));
+        const dim3 grid(wg < (unsigned)cus ? (wg > 0 ? wg : 1u) : (unsigned)cus);
+        if (csr.fmt == kCsrWeighted)
+            BGV_LAUNCH(k_attract_lds<int2>, grid, dim3(kAttLdsThreads), 0, s, K, pos, csr.row, csr.cw, csr.item_of,
+                       csr.item_row, A);
+        else if (csr.fmt == kCsrIds32)
+            BGV_LAUNCH(k_attract_lds<uint32_t>, grid, dim3(kAttLdsThreads), 0, s, K, pos, csr.row,
+                       reinterpret_cast<const uint32_t *>(csr.cw), csr.item_of, csr.item_row, A);
+        else
+            BGV_LAUNCH(k_attract_lds<uint16_t>, grid, dim3(kAttLdsThreads), 0, s, K, pos, csr.row,
+                       reinterpret_cast<const uint16_t *>(csr.cw), csr.item_of, csr.item_row, A);
+        return BGV_OK;
+    }
     // one wavefront per item; the item count is only known on the device, so the grid
     // covers the bound and the kernel reads the count
     const dim3 grid(grid_for(csr.items_bound, kFaThreads / kWave, 16384));
@@ -315,51 +360,62 @@ __device__ __forceinline__ uint32_t spread16(uint32_t v) {
     return v;
 }
 
-// Quantise on the 2^16 grid over the bounding square and Morton-encode (x even bits).
-__global__ void __launch_bounds__(kFaThreads) k_bh_codes(int32_t K, const float2 *__restrict__ pos,
-                                                          const float4 *__restrict__ part, int nparts,
-                                                          uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                                                          float *__restrict__ s0_out) {
+// The bounding square of the positions (from the per-block boxes): origin and side s0.
+// Every thread of the block gets the result; block 0 stores s0.
+__device__ __forceinline__ void bh_frame(const float4 *__restrict__ part, int nparts, float *xmin, float *ymin,
+                                         float *s0, float *__restrict__ s0_out) {
     float4 bb = make_float4(kInf, -kInf, kInf, -kInf);
     for (int q = threadIdx.x; q < nparts; q += kFaThreads) {
         const float4 r = part[q];
         bb = make_float4(fminf(bb.x, r.x), fmaxf(bb.y, r.y), fminf(bb.z, r.z), fmaxf(bb.w, r.w));
     }
     bb = block_bbox(bb);
-    const float xmin = bb.x, ymin = bb.z;
+    *xmin = bb.x;
+    *ymin = bb.z;
     const float ex = bb.y - bb.x, ey = bb.w - bb.z;
-    float s0 = ex > ey ? ex : ey;
-    if (!(s0 > 0.f)) s0 = 1.0f;
-    if (blockIdx.x == 0 && threadIdx.x == 0) *s0_out = s0;
+    float s = ex > ey ? ex : ey;
+    if (!(s > 0.f)) s = 1.0f;
+    *s0 = s;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *s0_out = s;
+}
+
+// Quantise on the 2^16 grid over the bounding square and Morton-encode (x even bits).
+__device__ __forceinline__ uint32_t bh_morton(float2 p, float xmin, float ymin, float s0) {
+    const float tx = __fdiv_rn(__fsub_rn(p.x, xmin), s0);
+    const float ty = __fdiv_rn(__fsub_rn(p.y, ymin), s0);
+    int32_t qx = (int32_t)__fmul_rn(tx, 65536.0f);
+    int32_t qy = (int32_t)__fmul_rn(ty, 65536.0f);
+    qx = qx > 65535 ? 65535 : qx;
+    qy = qy > 65535 ? 65535 : qy;
+    return spread16((uint32_t)qx) | (spread16((uint32_t)qy) << 1);
+}
+
+__global__ void __launch_bounds__(kFaThreads) k_bh_codes(int32_t K, const float2 *__restrict__ pos,
+                                                          const float4 *__restrict__ part, int nparts,
+                                                          uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                                                          float *__restrict__ s0_out) {
+    float xmin, ymin, s0;
+    bh_frame(part, nparts, &xmin, &ymin, &s0, s0_out);
     for (int32_t i = blockIdx.x * kFaThreads + threadIdx.x; i < K; i += gridDim.x * kFaThreads) {
-        const float2 p = pos[i];
-        const float tx = __fdiv_rn(__fsub_rn(p.x, xmin), s0);
-        const float ty = __fdiv_rn(__fsub_rn(p.y, ymin), s0);
-        int32_t qx = (int32_t)__fmul_rn(tx, 65536.0f);
-        int32_t qy = (int32_t)__fmul_rn(ty, 65536.0f);
-        qx = qx > 65535 ? 65535 : qx;
-        qy = qy > 65535 ? 65535 : qy;
-        keys[i] = (uint64_t)(spread16((uint32_t)qx) | (spread16((uint32_t)qy) << 1));
+        keys[i] = (uint64_t)bh_morton(pos[i], xmin, ymin, s0);
         vals[i] = (uint32_t)i;
     }
 }
 
-// Bodies in Morton order (one per thread, grid of ceil(K/kFaThreads) blocks) and the
-// block totals of the FP64 mass moments m, m*x, m*y.
-__global__ void __launch_bounds__(kFaThreads) k_bh_gather(int32_t K, const float2 *__restrict__ pos,
-                                                           const float *__restrict__ mass,
-                                                           const uint64_t *__restrict__ skeys,
-                                                           const uint32_t *__restrict__ order,
-                                                           float4 *__restrict__ body, uint32_t *__restrict__ code,
-                                                           double *__restrict__ part3) {
-    const int32_t k = blockIdx.x * kFaThreads + threadIdx.x;
+// Bodies [256 g, 256 g + 256) in Morton order (one per thread) and the group totals of
+// the FP64 mass moments m, m*x, m*y into part3[3 g ..].
+__device__ __forceinline__ void bh_gather_group(int32_t g, int32_t K, const float2 *__restrict__ pos,
+                                                const float *__restrict__ mass, const uint32_t *__restrict__ order,
+                                                uint32_t key_of_k, float4 *__restrict__ body,
+                                                uint32_t *__restrict__ code, double *__restrict__ part3) {
+    const int32_t k = g * kFaThreads + threadIdx.x;
     double m = 0.0, mx = 0.0, my = 0.0;
     if (k < K) {
         const uint32_t b = order[k];
         const float2 p = pos[b];
         const float mf = mass[b];
         body[k] = make_float4(p.x, p.y, mf, __int_as_float((int)b));
-        code[k] = (uint32_t)skeys[k];
+        code[k] = key_of_k;
         m = (double)mf;
         mx = m * (double)p.x;
         my = m * (double)p.y;
@@ -369,10 +425,20 @@ __global__ void __launch_bounds__(kFaThreads) k_bh_gather(int32_t K, const float
     block_excl_scan<double>(mx, &t1);
     block_excl_scan<double>(my, &t2);
     if (threadIdx.x == 0) {
-        part3[3 * blockIdx.x] = t0;
-        part3[3 * blockIdx.x + 1] = t1;
-        part3[3 * blockIdx.x + 2] = t2;
+        part3[3 * g] = t0;
+        part3[3 * g + 1] = t1;
+        part3[3 * g + 2] = t2;
     }
+}
+
+__global__ void __launch_bounds__(kFaThreads) k_bh_gather(int32_t K, const float2 *__restrict__ pos,
+                                                           const float *__restrict__ mass,
+                                                           const uint64_t *__restrict__ skeys,
+                                                           const uint32_t *__restrict__ order,
+                                                           float4 *__restrict__ body, uint32_t *__restrict__ code,
+                                                           double *__restrict__ part3) {
+    const int32_t k = blockIdx.x * kFaThreads + threadIdx.x;
+    bh_gather_group((int32_t)blockIdx.x, K, pos, mass, order, k < K ? (uint32_t)skeys[k] : 0u, body, code, part3);
 }
 
 // Exclusive FP64 prefix sums PM/PX/PY (K+1 entries) of the mass moments in Morton

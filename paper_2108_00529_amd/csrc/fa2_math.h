@@ -71,6 +71,17 @@ __device__ __forceinline__ float2 fa2_block_attraction(const float2 *__restrict_
                                                        uint32_t b0, uint32_t b1, float2 xi, int lane) {
     float ax = 0.f, ay = 0.f;
     uint32_t k = b0 + lane;
+    // every lane adds its entries in ascending k; the unrolled loads only overlap
+    for (; k + 7 * kWave < b1; k += 8 * kWave) {
+        E e[8];
+        float2 x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) e[u] = cw[k + u * kWave];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = pos[fa2_entry_id(e[u])];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) fa2_entry_add(e[u], x[u], xi, ax, ay);
+    }
     for (; k + 3 * kWave < b1; k += 4 * kWave) {
         const E e0 = cw[k], e1 = cw[k + kWave], e2 = cw[k + 2 * kWave], e3 = cw[k + 3 * kWave];
         const float2 x0 = pos[fa2_entry_id(e0)], x1 = pos[fa2_entry_id(e1)], x2 = pos[fa2_entry_id(e2)],

@@ -380,9 +380,11 @@ def test_bh_checkpoints_planted(bgv, planted_sg):
     assert worst <= TOL
 
 
-def test_bh_one_step_random(bgv):
+@pytest.mark.parametrize("K", [5000, 65536, 70000])
+def test_bh_one_step_random(bgv, K):
+    """Morton sorts at the largest size sorted in 1024-key tiles (64 of them) and just
+    above it (4096-key tiles)."""
     rng = np.random.default_rng(10)
-    K = 5000
     pos32 = (rng.standard_normal((K, 2)) * np.array([3.0, 1.0])).astype(np.float32)
     pos32[:20] = pos32[20]  # a multi-body cell
     se = np.array(sorted({(min(a, b), max(a, b)) for a, b in rng.integers(0, K, (9000, 2)).tolist() if a != b}),
