@@ -9,7 +9,7 @@
 //
 // Bucketed (n <= kCdMaxBuckets * kCdBucket): node records {counter, label} (8 bytes)
 // and no global atomics.  Nodes fall into buckets of kCdBucket consecutive ids.
-//   group (pass 0)  each 1024-edge tile of the chunk writes its endpoints grouped by
+//   group (pass 0)  each 1024-edge tile of a chunk writes its endpoints grouped by
 //                   bucket, one segment per (tile, bucket), offsets in a per-tile table
 //   decide          each 1024-edge tile writes its proposals (target, stream index,
 //                   label) grouped by the target's bucket in the same way
@@ -18,6 +18,8 @@
 //                   labels written, and in pass 0 the next chunk's counter increments
 //                   summed in LDS and added to the records, which no other workgroup
 //                   touches.
+// Per chunk: resolve(previous proposals, this chunk's increments), then one launch that
+// decides this chunk and, in pass 0, groups the next chunk's endpoints.
 // Device-scope atomics run at a small fraction of the LDS rate on this chip, and the
 // grouping costs two coalesced streams per chunk instead.
 //
@@ -25,6 +27,8 @@
 //   kernel A  = apply(previous chunk) + counter atomics(this chunk, pass 0 only)
 //   kernel B  = decide(this chunk), proposals by a 64-bit atomicMin keyed by the
 //               stream index.
+#include <algorithm>
+
 #include "block_scan.h"
 #include "common.h"
 
@@ -164,16 +168,14 @@ __global__ void __launch_bounds__(kCdThreads) k_cd_init_b(int2 *st, int32_t n) {
         st[v] = make_int2(0, (int32_t)v);
 }
 
-// Endpoints of the non-loop edges of tile blockIdx.x of chunk [cs, ce), grouped by
-// bucket: ends[tile * 2 * kCdTile + ...] holds their offsets within the bucket.
-__global__ void __launch_bounds__(kCdThreads) k_cd_group_ends(const int2 *__restrict__ edges, int64_t cs, int64_t ce,
-                                                               int32_t nb, uint16_t *__restrict__ ends,
-                                                               uint32_t *__restrict__ etab) {
-    __shared__ uint32_t hist[kCdMaxBuckets];
-    __shared__ uint16_t stage[2 * kCdTile];
+// Endpoints of the non-loop edges of tile `tile` of chunk [cs, ce), grouped by bucket:
+// ends[tile * 2 * kCdTile + ...] holds their offsets within the bucket.
+__device__ __forceinline__ void cd_group_tile(const int2 *__restrict__ edges, int64_t cs, int64_t ce, int32_t tile,
+                                              int32_t nb, uint16_t *__restrict__ ends, uint32_t *__restrict__ etab,
+                                              uint32_t *hist, uint16_t *stage) {
     for (int32_t b = threadIdx.x; b < nb; b += kCdThreads) hist[b] = 0;
     __syncthreads();
-    const int64_t t0 = cs + (int64_t)blockIdx.x * kCdTile;
+    const int64_t t0 = cs + (int64_t)tile * kCdTile;
     int32_t node[2 * kCdItems];
     uint32_t rank[2 * kCdItems];
 #pragma unroll
@@ -191,31 +193,28 @@ __global__ void __launch_bounds__(kCdThreads) k_cd_group_ends(const int2 *__rest
         }
     }
     __syncthreads();
-    const uint32_t total = cd_offsets(hist, nb, etab + (int64_t)blockIdx.x * (nb + 1));
+    const uint32_t total = cd_offsets(hist, nb, etab + (int64_t)tile * (nb + 1));
 #pragma unroll
     for (int q = 0; q < 2 * kCdItems; ++q)
         if (node[q] >= 0)
             stage[hist[node[q] >> kCdBucketBits] + rank[q]] = (uint16_t)(node[q] & (kCdBucket - 1));
     __syncthreads();
-    uint16_t *out = ends + (int64_t)blockIdx.x * (2 * kCdTile);
+    uint16_t *out = ends + (int64_t)tile * (2 * kCdTile);
     for (uint32_t k = threadIdx.x; k < total; k += kCdThreads) out[k] = stage[k];
 }
 
-// Decide, tile blockIdx.x of chunk [cs, ce): the rule above on the records (counters
-// as in the atomic path's decide: pass-0 values stored per edge in c1 when more passes
+// Decide, tile `tile` of chunk [cs, ce): the rule above on the records (counters as in
+// the atomic path's decide: pass-0 values stored per edge in c1 when more passes
 // follow, p * d(v) + c1 in later passes), each proposal (offset of the target in its
 // bucket, stream index, label) grouped by the target's bucket.
 template <int kMode>  // 0: only pass; 1: pass 0 of several; 2: a later pass
-__global__ void __launch_bounds__(kCdThreads) k_cd_decide_b(const int2 *__restrict__ st,
-                                                             const int2 *__restrict__ edges, int2 *__restrict__ c1,
-                                                             int64_t cs, int64_t ce, int32_t D, int32_t pass,
-                                                             int32_t nb, uint3 *__restrict__ props,
-                                                             uint32_t *__restrict__ ptab) {
-    __shared__ uint32_t hist[kCdMaxBuckets];
-    __shared__ uint3 stage[kCdTile];
+__device__ __forceinline__ void cd_decide_tile(const int2 *__restrict__ st, const int2 *__restrict__ edges,
+                                               int2 *__restrict__ c1, int64_t cs, int64_t ce, int32_t D,
+                                               int32_t pass, int32_t tile, int32_t nb, uint3 *__restrict__ props,
+                                               uint32_t *__restrict__ ptab, uint32_t *hist, uint3 *stage) {
     for (int32_t b = threadIdx.x; b < nb; b += kCdThreads) hist[b] = 0;
     __syncthreads();
-    const int64_t t0 = cs + (int64_t)blockIdx.x * kCdTile;
+    const int64_t t0 = cs + (int64_t)tile * kCdTile;
     int32_t target[kCdItems], lab[kCdItems];
     uint32_t rank[kCdItems];
 #pragma unroll
@@ -243,7 +242,7 @@ __global__ void __launch_bounds__(kCdThreads) k_cd_decide_b(const int2 *__restri
         }
     }
     __syncthreads();
-    const uint32_t total = cd_offsets(hist, nb, ptab + (int64_t)blockIdx.x * (nb + 1));
+    const uint32_t total = cd_offsets(hist, nb, ptab + (int64_t)tile * (nb + 1));
 #pragma unroll
     for (int j = 0; j < kCdItems; ++j)
         if (target[j] >= 0)
@@ -251,18 +250,47 @@ __global__ void __launch_bounds__(kCdThreads) k_cd_decide_b(const int2 *__restri
                 make_uint3((uint32_t)(target[j] & (kCdBucket - 1)),
                            (uint32_t)(t0 + j * kCdThreads + threadIdx.x), (uint32_t)lab[j]);
     __syncthreads();
-    uint3 *out = props + (int64_t)blockIdx.x * kCdTile;
+    uint3 *out = props + (int64_t)tile * kCdTile;
     for (uint32_t k = threadIdx.x; k < total; k += kCdThreads) out[k] = stage[k];
+}
+
+// One launch per chunk: decide chunk [cs, ce) (kMode >= 0) and, in pass 0, group the
+// endpoints of the next chunk [gs, ge) for the counter increments of the resolve that
+// follows; workgroup x takes tile x of each.
+template <int kMode>  // -1: grouping only
+__global__ void __launch_bounds__(kCdThreads) k_cd_step(const int2 *__restrict__ st, const int2 *__restrict__ edges,
+                                                         int2 *__restrict__ c1, int64_t cs, int64_t ce, int32_t D,
+                                                         int32_t pass, int32_t nb, uint3 *__restrict__ props,
+                                                         uint32_t *__restrict__ ptab, int64_t gs, int64_t ge,
+                                                         uint16_t *__restrict__ ends, uint32_t *__restrict__ etab) {
+    __shared__ uint32_t hist[kCdMaxBuckets];
+    __shared__ uint3 pstage[kCdTile];
+    __shared__ uint16_t estage[2 * kCdTile];
+    const int32_t tile = (int32_t)blockIdx.x;
+    if (kMode >= 0 && cs + (int64_t)tile * kCdTile < ce)  // uniform over the workgroup
+        cd_decide_tile<kMode < 0 ? 0 : kMode>(st, edges, c1, cs, ce, D, pass, tile, nb, props, ptab, hist, pstage);
+    if (gs + (int64_t)tile * kCdTile < ge) {
+        __syncthreads();  // hist is reused
+        cd_group_tile(edges, gs, ge, tile, nb, ends, etab, hist, estage);
+    }
 }
 
 // Resolve, one workgroup per bucket: proposals from ptiles decide tiles and counter
 // increments from etiles grouped tiles.  The winner of a target is the smallest
 // (stream index, label) key (stream indices are distinct), found by LDS atomicMin;
 // then one sweep over the bucket's records writes the winners' labels and adds the
-// counts.  Only this workgroup writes the bucket's records.  One thread per tile (while
-// tiles <= kCdResolveThreads), each segment's entries loaded in batches before they are
-// applied, so a thread waits on few memory round trips.
+// counts.  Only this workgroup writes the bucket's records.  Each tile's segment goes
+// to a group of `lanes` threads (a power of two: kCdResolveThreads / tiles, at least
+// 1), which load its entries in batches before applying them, so that few tiles with
+// long segments and many tiles with short ones both leave every thread few memory
+// round trips.
 constexpr int kCdResolveThreads = 1024;
+
+inline int32_t cd_resolve_lanes(int32_t tiles) {
+    int32_t g = 1;
+    while (g < kCdResolveThreads && (int64_t)g * 2 * (tiles > 0 ? tiles : 1) <= kCdResolveThreads) g *= 2;
+    return g;
+}
 
 __device__ __forceinline__ void cd_segment(const uint32_t *__restrict__ tab, int32_t nb, int32_t t, int32_t b,
                                            uint32_t *q0, uint32_t *q1) {
@@ -275,7 +303,8 @@ __global__ void __launch_bounds__(kCdResolveThreads) k_cd_resolve(int2 *__restri
                                                                    const uint3 *__restrict__ props,
                                                                    const uint32_t *__restrict__ ptab, int32_t ptiles,
                                                                    const uint16_t *__restrict__ ends,
-                                                                   const uint32_t *__restrict__ etab, int32_t etiles) {
+                                                                   const uint32_t *__restrict__ etab, int32_t etiles,
+                                                                   int32_t lanes) {
     __shared__ unsigned long long win[kCdBucket];
     __shared__ uint32_t inc[kCdBucket];
     const int32_t b = blockIdx.x;
@@ -285,29 +314,31 @@ __global__ void __launch_bounds__(kCdResolveThreads) k_cd_resolve(int2 *__restri
     }
     __syncthreads();
     const int32_t tiles = max(ptiles, etiles);
-    for (int32_t t = threadIdx.x; t < tiles; t += kCdResolveThreads) {
+    const int32_t groups = kCdResolveThreads / lanes;
+    const uint32_t sub = threadIdx.x % lanes, L = (uint32_t)lanes;
+    for (int32_t t = threadIdx.x / lanes; t < tiles; t += groups) {
         uint32_t p0 = 0, p1 = 0, e0 = 0, e1 = 0;
         if (t < ptiles) cd_segment(ptab, nb, t, b, &p0, &p1);
         if (t < etiles) cd_segment(etab, nb, t, b, &e0, &e1);
         const uint3 *ps = props + (int64_t)t * kCdTile;
-        for (uint32_t q = p0; q < p1; q += 4) {
+        for (uint32_t q = p0 + sub; q < p1; q += 4 * L) {
             uint3 v[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-                if (q + u < p1) v[u] = ps[q + u];
+                if (q + u * L < p1) v[u] = ps[q + u * L];
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-                if (q + u < p1) atomicMin(&win[v[u].x], ((unsigned long long)v[u].y << 32) | v[u].z);
+                if (q + u * L < p1) atomicMin(&win[v[u].x], ((unsigned long long)v[u].y << 32) | v[u].z);
         }
         const uint16_t *es = ends + (int64_t)t * (2 * kCdTile);
-        for (uint32_t q = e0; q < e1; q += 8) {
+        for (uint32_t q = e0 + sub; q < e1; q += 8 * L) {
             uint32_t v[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u)
-                if (q + u < e1) v[u] = es[q + u];
+                if (q + u * L < e1) v[u] = es[q + u * L];
 #pragma unroll
             for (int u = 0; u < 8; ++u)
-                if (q + u < e1) atomicAdd(&inc[v[u]], 1u);
+                if (q + u * L < e1) atomicAdd(&inc[v[u]], 1u);
         }
     }
     __syncthreads();
@@ -403,33 +434,48 @@ extern "C" bgv_status bgv_community(int32_t n, int64_t m, const int32_t *edges, 
         int2 *st2 = w.st2;
         BGV_LAUNCH(k_cd_init_b, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, st2, n);
         int32_t ptiles = 0;  // decide tiles whose proposals are not yet resolved
+        int32_t etiles = 0;  // grouped endpoint tiles whose increments are not yet added
+        auto tiles_of = [&](int64_t k) {
+            const int64_t len = (k + 1) * B < m ? B : m - k * B;
+            return (int32_t)((len + kCdTile - 1) / kCdTile);
+        };
+        if (nchunk > 0) {
+            // pass 0, chunk 0: its endpoints grouped before anything is decided
+            etiles = tiles_of(0);
+            BGV_LAUNCH(k_cd_step<-1>, dim3(etiles), dim3(kCdThreads), 0, s, st2, e2, w.c1, (int64_t)0, (int64_t)0,
+                       0, 0, nb, w.props, w.ptab, (int64_t)0, std::min<int64_t>(B, m), w.ends, w.etab);
+        }
         for (int32_t pass = 0; pass < p->passes && m > 0; ++pass) {
             const int32_t D = pass_threshold(p->threshold, p->growth, pass);
             for (int64_t k = 0; k < nchunk; ++k) {
                 const int64_t cs = k * B, ce = (cs + B < m) ? cs + B : m;
-                const int32_t tiles = (int32_t)((ce - cs + kCdTile - 1) / kCdTile);
-                // counters are incremented in pass 0 only (later passes use the closed form)
-                const int32_t etiles = pass == 0 ? tiles : 0;
-                if (etiles > 0)
-                    BGV_LAUNCH(k_cd_group_ends, dim3(etiles), dim3(kCdThreads), 0, s, e2, cs, ce, nb, w.ends, w.etab);
+                const int32_t tiles = tiles_of(k);
+                // proposals of the previous chunk and, in pass 0, this chunk's increments
                 if (ptiles > 0 || etiles > 0)
-                    BGV_LAUNCH(k_cd_resolve, dim3(nb), dim3(kCdResolveThreads), 0, s, st2, n, nb, w.props, w.ptab, ptiles,
-                               w.ends, w.etab, etiles);
+                    BGV_LAUNCH(k_cd_resolve, dim3(nb), dim3(kCdResolveThreads), 0, s, st2, n, nb, w.props, w.ptab,
+                               ptiles, w.ends, w.etab, etiles, cd_resolve_lanes(std::max(ptiles, etiles)));
+                // counters are incremented in pass 0 only (later passes use the closed form):
+                // the next chunk's endpoints are grouped by this launch in pass 0
+                const bool group_next = pass == 0 && k + 1 < nchunk;
+                const int64_t gs = group_next ? ce : 0, ge = group_next ? std::min<int64_t>(ce + B, m) : 0;
+                const int32_t gtiles = group_next ? tiles_of(k + 1) : 0;
+                const dim3 grid((unsigned)std::max(tiles, gtiles));
                 if (p->passes == 1)
-                    BGV_LAUNCH(k_cd_decide_b<0>, dim3(tiles), dim3(kCdThreads), 0, s, st2, e2, w.c1, cs, ce, D, pass,
-                               nb, w.props, w.ptab);
+                    BGV_LAUNCH(k_cd_step<0>, grid, dim3(kCdThreads), 0, s, st2, e2, w.c1, cs, ce, D, pass, nb,
+                               w.props, w.ptab, gs, ge, w.ends, w.etab);
                 else if (pass == 0)
-                    BGV_LAUNCH(k_cd_decide_b<1>, dim3(tiles), dim3(kCdThreads), 0, s, st2, e2, w.c1, cs, ce, D, pass,
-                               nb, w.props, w.ptab);
+                    BGV_LAUNCH(k_cd_step<1>, grid, dim3(kCdThreads), 0, s, st2, e2, w.c1, cs, ce, D, pass, nb,
+                               w.props, w.ptab, gs, ge, w.ends, w.etab);
                 else
-                    BGV_LAUNCH(k_cd_decide_b<2>, dim3(tiles), dim3(kCdThreads), 0, s, st2, e2, w.c1, cs, ce, D, pass,
-                               nb, w.props, w.ptab);
+                    BGV_LAUNCH(k_cd_step<2>, grid, dim3(kCdThreads), 0, s, st2, e2, w.c1, cs, ce, D, pass, nb,
+                               w.props, w.ptab, gs, ge, w.ends, w.etab);
                 ptiles = tiles;
+                etiles = gtiles;
             }
         }
         if (ptiles > 0)
             BGV_LAUNCH(k_cd_resolve, dim3(nb), dim3(kCdResolveThreads), 0, s, st2, n, nb, w.props, w.ptab, ptiles, w.ends,
-                       w.etab, 0);
+                       w.etab, 0, cd_resolve_lanes(ptiles));
         BGV_LAUNCH(k_cd_finish<2>, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s,
                    reinterpret_cast<const int32_t *>(st2), n, labels, degree,
                    reinterpret_cast<unsigned long long *>(volume));

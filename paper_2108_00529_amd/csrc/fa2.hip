@@ -183,10 +183,13 @@ __global__ void __launch_bounds__(kFaThreads) k_attract(int32_t K, const float2 
     }
 }
 
-// The same with all K positions staged in LDS first (K <= kAttLdsMax): the gathers of
-// the neighbours' positions then read LDS instead of L2.  One workgroup of 16
-// wavefronts per compute unit, so each position array is loaded once per unit.
-constexpr int32_t kAttLdsMax = 19456;  // 152 KiB of float2
+// The same with all K positions staged in LDS first (kAttLdsMin <= K <= kAttLdsMax):
+// the gathers of the neighbours' positions then read LDS instead of L2.  One workgroup
+// of 16 wavefronts per compute unit, so each position array is loaded once per unit.
+// Smaller supergraphs keep the plain kernel: their positions stay in L2 anyway and a
+// 1024-thread workgroup per unit only adds dispatch time to their short iterations.
+constexpr int32_t kAttLdsMin = 4096;
+constexpr int32_t kAttLdsMax = 19456;  // 152 KiB of float2 (dynamic LDS: K * 8 bytes)
 constexpr int kAttLdsThreads = 1024;
 
 template <typename E>
@@ -196,7 +199,7 @@ __global__ void __launch_bounds__(kAttLdsThreads) k_attract_lds(int32_t K, const
                                                                  const uint32_t *__restrict__ item_of,
                                                                  const uint32_t *__restrict__ item_row,
                                                                  float2 *__restrict__ A) {
-    __shared__ float2 sp[kAttLdsMax];
+    extern __shared__ float2 sp[];  // K entries
     for (int32_t i = threadIdx.x; i < K; i += kAttLdsThreads) sp[i] = pos[i];
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1);
@@ -213,19 +216,20 @@ __global__ void __launch_bounds__(kAttLdsThreads) k_attract_lds(int32_t K, const
 }
 
 bgv_status attraction(int32_t K, const float2 *pos, const CsrWs &csr, float2 *A, hipStream_t s) {
-    if (K <= kAttLdsMax) {
+    if (K >= kAttLdsMin && K <= kAttLdsMax) {
         int cus = 1;
         BGV_TRY(device_cu_count(&cus));
         const unsigned wg = (unsigned)((csr.items_bound + kAttLdsThreads / kWave - 1) / (kAttLdsThreads / kWave));
         const dim3 grid(wg < (unsigned)cus ? (wg > 0 ? wg : 1u) : (unsigned)cus);
+        const size_t lds = sizeof(float2) * (size_t)K;
         if (csr.fmt == kCsrWeighted)
-            BGV_LAUNCH(k_attract_lds<int2>, grid, dim3(kAttLdsThreads), 0, s, K, pos, csr.row, csr.cw, csr.item_of,
+            BGV_LAUNCH(k_attract_lds<int2>, grid, dim3(kAttLdsThreads), lds, s, K, pos, csr.row, csr.cw, csr.item_of,
                        csr.item_row, A);
         else if (csr.fmt == kCsrIds32)
-            BGV_LAUNCH(k_attract_lds<uint32_t>, grid, dim3(kAttLdsThreads), 0, s, K, pos, csr.row,
+            BGV_LAUNCH(k_attract_lds<uint32_t>, grid, dim3(kAttLdsThreads), lds, s, K, pos, csr.row,
                        reinterpret_cast<const uint32_t *>(csr.cw), csr.item_of, csr.item_row, A);
         else
-            BGV_LAUNCH(k_attract_lds<uint16_t>, grid, dim3(kAttLdsThreads), 0, s, K, pos, csr.row,
+            BGV_LAUNCH(k_attract_lds<uint16_t>, grid, dim3(kAttLdsThreads), lds, s, K, pos, csr.row,
                        reinterpret_cast<const uint16_t *>(csr.cw), csr.item_of, csr.item_row, A);
         return BGV_OK;
     }

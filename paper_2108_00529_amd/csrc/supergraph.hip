@@ -244,28 +244,39 @@ __global__ void __launch_bounds__(kSgThreads) k_sg_group_pairs(const int32_t *__
     for (uint32_t k = threadIdx.x; k < total; k += kSgThreads) out[k] = stage[k];
 }
 
+// Each tile's segment goes to a group of `lanes` threads (a power of two, about
+// kSkResolveThreads / tiles): few tiles with long segments and many tiles with short
+// ones both leave every thread few memory round trips.
+inline int32_t sk_sum_lanes(int64_t tiles) {
+    int32_t g = 1;
+    while (g < kSkResolveThreads && (int64_t)g * 2 * (tiles > 0 ? tiles : 1) <= kSkResolveThreads) g *= 2;
+    return g;
+}
+
 __global__ void __launch_bounds__(kSkResolveThreads) k_sg_sum_cells(const uint2 *__restrict__ ent,
                                                                      const uint32_t *__restrict__ etab,
                                                                      const uint32_t *__restrict__ Ep, int32_t rows,
-                                                                     int32_t nb, int64_t cells,
+                                                                     int32_t nb, int64_t cells, int32_t lanes,
                                                                      uint32_t *__restrict__ M2) {
     __shared__ uint32_t acc[kSkBucket];
     const int32_t b = blockIdx.x;
     for (int32_t k = threadIdx.x; k < kSkBucket; k += kSkResolveThreads) acc[k] = 0u;
     __syncthreads();
     const int64_t tiles = ((int64_t)*Ep + kSkTile - 1) / kSkTile;
-    for (int64_t t = threadIdx.x; t < tiles; t += kSkResolveThreads) {
+    const int64_t groups = kSkResolveThreads / lanes;
+    const uint32_t sub = threadIdx.x % lanes, L = (uint32_t)lanes;
+    for (int64_t t = threadIdx.x / lanes; t < tiles; t += groups) {
         const uint32_t *row = etab + t * (nb + 1);
         const uint32_t q0 = row[b], q1 = row[b + 1];
         const uint2 *seg = ent + t * (kSkTile * rows);
-        for (uint32_t q = q0; q < q1; q += 8) {
+        for (uint32_t q = q0 + sub; q < q1; q += 8 * L) {
             uint2 v[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u)
-                if (q + u < q1) v[u] = seg[q + u];
+                if (q + u * L < q1) v[u] = seg[q + u * L];
 #pragma unroll
             for (int u = 0; u < 8; ++u)
-                if (q + u < q1) atomicAdd(&acc[v[u].x], v[u].y);
+                if (q + u * L < q1) atomicAdd(&acc[v[u].x], v[u].y);
         }
     }
     __syncthreads();
@@ -439,8 +450,9 @@ extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges,
             BGV_LAUNCH(k_sg_group_pairs, dim3((unsigned)((nk + kSkTile - 1) / kSkTile)), dim3(kSgThreads), 0, s,
                        superedges, w.run_start, &w.counters[1], (uint32_t)nk, super_label, h2, rows, cols, nb, w.ent,
                        w.etab, se_count);
+            // the tile count is on the device; the key count bounds it
             BGV_LAUNCH(k_sg_sum_cells, dim3(nb), dim3(kSkResolveThreads), 0, s, w.ent, w.etab, &w.counters[1], rows,
-                       nb, cells, M2);
+                       nb, cells, sk_sum_lanes(((int64_t)nk + kSkTile - 1) / kSkTile), M2);
         } else {
             BGV_LAUNCH(k_sg_sketch_pairs, dim3(gk), dim3(kSgThreads), 0, s, superedges, w.run_start, &w.counters[1],
                        (uint32_t)nk, super_label, h2, rows, cols, M2, se_count);
