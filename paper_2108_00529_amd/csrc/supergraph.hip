@@ -92,9 +92,11 @@ __global__ void k_sg_super_size(const int32_t *__restrict__ super_label, const u
 // distinct key adds its multiplicity once (the same integer sums as one increment per
 // edge, without same-address contention on popular community pairs).
 constexpr int kKeyItems = 16;  // edges per thread; a block compacts kSgThreads*kKeyItems edges
+// nsid[v] = sid of node v's community: an edge is inter-community iff its endpoints'
+// sids differ, and since sids ascend with labels, (min, max) of the two sids is
+// (sid of the smaller label, sid of the larger).
 __global__ void __launch_bounds__(kSgThreads) k_sg_edge_keys(const int2 *__restrict__ edges, int64_t m,
-                                                              const int32_t *__restrict__ labels,
-                                                              const uint32_t *__restrict__ sid, int kbits,
+                                                              const uint32_t *__restrict__ nsid, int kbits,
                                                               uint64_t *__restrict__ keys,
                                                               unsigned long long *__restrict__ nkeys) {
     __shared__ unsigned long long s_base;
@@ -108,10 +110,9 @@ __global__ void __launch_bounds__(kSgThreads) k_sg_edge_keys(const int2 *__restr
         if (i < m) {
             const int2 e = edges[i];
             if (e.x != e.y) {
-                const int32_t a = labels[e.x], b = labels[e.y];
+                const uint32_t a = nsid[e.x], b = nsid[e.y];
                 if (a != b) {
-                    const uint32_t lo = (uint32_t)min(a, b), hi = (uint32_t)max(a, b);
-                    k[j] = ((uint64_t)sid[lo] << kbits) | (uint64_t)sid[hi];
+                    k[j] = ((uint64_t)min(a, b) << kbits) | (uint64_t)max(a, b);
                     flags |= 1u << j;
                     ++cnt;
                 }
@@ -300,14 +301,18 @@ __global__ void k_sg_pair_weights(const int32_t *__restrict__ superedges, const 
     }
 }
 
+// nsid[v] = sid of node v's community (and the caller's copy when asked for).
 __global__ void k_sg_node_super(const int32_t *__restrict__ labels, const uint32_t *__restrict__ sid, int32_t n,
-                                int32_t *__restrict__ node_super) {
-    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-        node_super[v] = (int32_t)sid[labels[v]];
+                                uint32_t *__restrict__ nsid, int32_t *__restrict__ node_super) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t x = sid[labels[v]];
+        nsid[v] = x;
+        if (node_super) node_super[v] = (int32_t)x;
+    }
 }
 
 struct SgWs {
-    uint32_t *flag, *sid, *vol, *counters, *uflag, *upos, *run_start;
+    uint32_t *flag, *sid, *vol, *nsid, *counters, *uflag, *upos, *run_start;
     uint64_t *keys, *keys_alt;
     uint2 *ent;       // grouped sketch-2 entries (bucketed sketch only)
     uint32_t *etab;   // their per-tile offset rows
@@ -319,6 +324,7 @@ static size_t sg_layout(Carver &c, int32_t n, int64_t m, int32_t rows, int64_t c
     w->ent = nullptr;
     w->etab = nullptr;
     w->flag = c.take<uint32_t>((size_t)n);
+    w->nsid = c.take<uint32_t>((size_t)n);
     w->sid = c.take<uint32_t>((size_t)n);
     w->vol = c.take<uint32_t>((size_t)n);
     w->counters = c.take<uint32_t>(8);  // [0] K, [1] E_S, [2..3] key count (u64, 8-byte aligned)
@@ -413,9 +419,7 @@ extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges,
     }
     BGV_LAUNCH(k_sg_super_size, dim3(gn), dim3(kSgThreads), 0, s, super_label, &w.counters[0], h1, rows, cols,
                        M1, super_size);
-    if (node_super) {
-        BGV_LAUNCH(k_sg_node_super, dim3(gn), dim3(kSgThreads), 0, s, labels, w.sid, n, node_super);
-    }
+    BGV_LAUNCH(k_sg_node_super, dim3(gn), dim3(kSgThreads), 0, s, labels, w.sid, n, w.nsid, node_super);
 
     // K is needed to size the packed superedge keys
     uint32_t Kh = 0;
@@ -428,8 +432,8 @@ extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges,
     // inter-community keys, sorted and made unique, then sketch 2 and the weights
     unsigned long long *nkeys_d = reinterpret_cast<unsigned long long *>(&w.counters[2]);
     if (m > 0) {
-        BGV_LAUNCH(k_sg_edge_keys, dim3((unsigned)((m + kSgThreads * kKeyItems - 1) / (kSgThreads * kKeyItems))), dim3(kSgThreads), 0, s, e2, m, labels,
-                   w.sid, kbits, w.keys, nkeys_d);
+        BGV_LAUNCH(k_sg_edge_keys, dim3((unsigned)((m + kSgThreads * kKeyItems - 1) / (kSgThreads * kKeyItems))), dim3(kSgThreads), 0, s, e2, m,
+                   w.nsid, kbits, w.keys, nkeys_d);
     }
     unsigned long long nk = 0;
     BGV_CHECK_HIP(hipMemcpyAsync(&nk, nkeys_d, sizeof nk, hipMemcpyDeviceToHost, s));
