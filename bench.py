@@ -442,7 +442,8 @@ def gradient_form(torch, bgv, graphgen, lrs=(3.0, 10.0, 30.0), max_steps=3000):
 # algorithmic work per unit: bytes (HBM-bound kernels) or flops (ALU-bound)
 EDGE_PASS_BYTES = 8            # one int32 (u,v) pair read per edge per pass
 BH_INTERACTION_FLOPS = 20      # body-node or body-body interaction, n-body convention
-CSR_ENTRY_BYTES = {"attract<uint16_t>": 2, "attract<uint32_t>": 4, "attract<int2>": 8}
+CSR_ENTRY_BYTES = {"attract<uint16_t>": 2, "attract<uint32_t>": 4, "attract<int2>": 8,
+                   "attract_lds<uint16_t>": 2, "attract_lds<uint32_t>": 4, "attract_lds<int2>": 8}
 
 
 def kernel_model(name, K, E, inter_per_launch=None):
