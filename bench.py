@@ -154,10 +154,11 @@ def main():
     prof.sample(1)
     kstats = prof.stats()
     inter = prof.counter("bh_interactions")
+    # the counter covers every force launch of the timed steps, timed or not
+    inter_per_launch = inter / (args.steps * wl["fa2_iters"]) if inter and not wl["exact"] else None
     for k in kstats:
-        if k.startswith("bh_force") and inter:
-            # the counter covers every launch of the timed steps, not only the sampled ones
-            kstats[k]["bh_interactions_per_launch"] = inter / (args.steps * wl["fa2_iters"])
+        if k.startswith("bh_force") and inter_per_launch:
+            kstats[k]["bh_interactions_per_launch"] = inter_per_launch
     print(f"[bench] timed {args.steps} steps in {t_total:.2f}s", file=sys.stderr, flush=True)
     # one more step with no kernel events at all: the layout rate without measurement
     step(record=True)
@@ -170,7 +171,11 @@ def main():
     K, E = sg["K"], sg["E"]
     value = m / (cd / 1000.0)
 
-    roofline, extra = roofline_report(kstats, kbreak, wl, n, m, K, E)
+    roofline, extra = roofline_report(kstats, kbreak, wl, n, m, K, E, inter_per_launch)
+    copy_gbs = measured_copy_gbs(torch)
+    for row in extra.get("roofline_edge_stream", {}).values():
+        row["measured_copy_peak_gbs"] = copy_gbs
+        row["frac_of_measured"] = row["achieved"] / copy_gbs
 
     out = {
         "metric": "edges/s through community pass+sketch; FA2 iters/s; batched/grad vs plain",
@@ -193,7 +198,15 @@ def main():
         "parts": {"community_sketch_ms": cd, "fa2_ms": fa,
                   "fa2_iters_per_s": wl["fa2_iters"] / (fa / 1000.0),
                   "fa2_iters_per_s_without_kernel_events": wl["fa2_iters"] / (fa_unprofiled / 1000.0),
-                  "pipeline_edges_per_s": m / ((cd + fa) / 1000.0)},
+                  "pipeline_edges_per_s": m / ((cd + fa) / 1000.0),
+                  # one community pass: device time of the community kernels over the passes
+                  "community_pass_edges_per_s": (m * wl["passes"] / (extra["roofline_edge_stream"]["community_passes"]
+                                                                     ["device_ms"] / 1000.0)
+                                                 if extra.get("roofline_edge_stream", {}).get("community_passes")
+                                                 else None),
+                  "bh_interactions_per_iteration": inter_per_launch,
+                  "bh_interactions_per_s": (inter_per_launch * wl["fa2_iters"] / (fa_unprofiled / 1000.0)
+                                            if inter_per_launch else None)},
         "roofline": roofline,
         **extra,
     }
@@ -479,7 +492,26 @@ def roofline_of(name, avg_s, K, E, inter_per_launch=None):
     return r
 
 
-def roofline_report(kstats, kbreak, wl, n, m, K, E):
+def measured_copy_gbs(torch, mib=1024, repeats=5):
+    """Device-to-device copy of `mib` MiB, best of `repeats`: bytes read + written per
+    second, the attainable stream rate beside the published 8 TB/s."""
+    src = torch.empty(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(repeats):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b))
+    del src, dst
+    return 2 * mib * (1 << 20) / (best / 1000.0) / 1e9
+
+
+def roofline_report(kstats, kbreak, wl, n, m, K, E, inter_per_launch=None):
     """Roofline of the dominant kernel, from the events recorded around it in the timed
     steps (kstats), plus the per-kernel breakdown of one untimed step with every launch timed
     (kbreak) with each layout kernel's roofline and the community passes' edge-stream
@@ -497,7 +529,7 @@ def roofline_report(kstats, kbreak, wl, n, m, K, E):
         rows["community_passes"] = dict(bound="hbm", achieved=EDGE_PASS_BYTES * m * wl["passes"] / (cd_ms / 1e3) / 1e9,
                                         peak=HBM_PEAK_GBS, unit="GB/s", device_ms=cd_ms)
     extra["roofline_edge_stream"] = {k: dict(v, frac=v["achieved"] / v["peak"]) for k, v in rows.items()}
-    inter = next((v.get("bh_interactions_per_launch") for k, v in kstats.items() if k.startswith("bh_force")), None)
+    inter = inter_per_launch
     layout = {}
     for name, st in kbreak.items():
         if kernel_model(name, K, E, inter) is not None:
