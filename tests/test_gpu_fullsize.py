@@ -3,9 +3,12 @@
 - lfr_3m (3.2M nodes, 34M edges, 3 passes, sketch 5 x 2^22): labels, degrees, volumes,
   both sketches and the supergraph bit-exact against the oracle; Barnes-Hut forces on the
   whole supergraph against the oracle's.
-- batched_512 (all 512 graphs in one launch, largest first, 1024-thread workgroups):
-  sampled graphs (the largest, the smallest and four seeded picks) bit-exact against the
-  oracle's integers, their last layout step against one oracle step.
+- batched_512 (all 512 graphs in one launch, largest first, in the launch shape the
+  benchmark's autotuner picks: 512-thread workgroups, supergraphs above 128 nodes laid
+  out by the multi-workgroup kernels): every graph bit-identical to the all-persistent
+  launch with 1024-thread workgroups; sampled graphs (the largest, the smallest and four
+  seeded picks) bit-exact against the oracle's integers, their last layout step against
+  one oracle step.
 - grad_50k (50,000 weighted supernodes from a 5M-node graph): the supergraph bit-exact,
   the gradient against FP64 central finite differences of the oracle's per-node energy
   on 500 seeded supernodes, and the energy against the oracle's.
@@ -64,8 +67,30 @@ def test_batched_512_full_size_sampled(bgv):
     for iters in (T - 1, T):
         pos = torch.from_numpy(np.concatenate(pos0)).to(d)
         runs[iters] = bgv.batched(edges, noff, eoff, int(noff_h[-1]), dict(wl, fa2_iters=iters), c1, c2, pos,
-                                  order=order, wg_threads=1024)
+                                  order=order, wg_threads=512, big_k=128)
         torch.cuda.synchronize()
+    # the same batch with every layout in the persistent launch: the same bits
+    pos = torch.from_numpy(np.concatenate(pos0)).to(d)
+    ref = bgv.batched(edges, noff, eoff, int(noff_h[-1]), wl, c1, c2, pos, order=order, wg_threads=1024, big_k=0)
+    torch.cuda.synchronize()
+    K_all = ref["K"].cpu().numpy()
+    say(f"  batched_512: {int(((K_all > 128) & (K_all <= 4096)).sum())} supergraphs laid out by the "
+        f"multi-workgroup kernels, largest K {int(K_all.max())}")
+    E_all = ref["E"].cpu().numpy()
+    # outputs beyond each graph's K (nodes) or E (edges) are not written: compare the rest
+    sup = np.zeros(int(noff_h[-1]), bool)
+    sedge = np.zeros(max(int(eoff_h[-1]), 1), bool)
+    for g in range(len(graphs)):
+        sup[noff_h[g]:noff_h[g] + K_all[g]] = True
+        sedge[eoff_h[g]:eoff_h[g] + E_all[g]] = True
+    sup_d, sedge_d = torch.from_numpy(sup).to(d), torch.from_numpy(sedge).to(d)
+    out = runs[T]
+    for key in ("labels", "degree", "K", "E", "pos", "fprev", "speed"):
+        assert torch.equal(out[key], ref[key]), key
+    for key in ("super_label", "super_size"):
+        assert torch.equal(out[key][: len(sup)][sup_d], ref[key][: len(sup)][sup_d]), key
+    for key in ("superedges", "se_weight"):
+        assert torch.equal(out[key][sedge_d], ref[key][sedge_d]), key
     sizes = np.diff(eoff_h)
     rng = np.random.default_rng(5)
     sample = [int(np.argmax(sizes)), int(np.argmin(sizes))] + [int(g) for g in rng.choice(len(graphs), 4, replace=False)]
