@@ -447,9 +447,9 @@ struct BtBig {
     const int32_t *big;
     const unsigned int *nbig;
     uint32_t *tile_off, *row_off;  // G+1 each: prefix sums of tiles / rows over the list
-    uint32_t *fitem_off;           // G+1: prefix sums of tiles x segments over the list
+    uint32_t *fitem_off;           // G+1: prefix sums of wave tiles x segments over the list
     uint32_t *tile_slot;           // list slot of every tile item
-    uint32_t *fitem_slot;          // list slot of every (tile, segment) item
+    uint32_t *fitem_slot;          // list slot of every (wave tile, segment) item
     uint4 *row_desc;               // per row item: CSR entries [x, y) in cw, node z, graph base w
     const uint32_t *row;
     const int2 *cw;
@@ -474,7 +474,7 @@ __global__ void __launch_bounds__(1024) k_bt_plan(BtBig b) {
             const int32_t g = b.big[sl];
             rows = (uint32_t)b.K[g];
             tiles = (rows + kFa2Tile - 1) / kFa2Tile;
-            fitems = tiles * (uint32_t)fa2_rep_segments((int32_t)rows);
+            fitems = ((rows + kWave - 1) / kWave) * (uint32_t)fa2_rep_segments((int32_t)rows);
             b.bspeed[2 * g] = b.speed[g];
         }
         uint32_t tt, tr, tf;
@@ -528,26 +528,59 @@ __global__ void __launch_bounds__(kFa2Tile) k_bt_maps(BtBig b) {
         b.fitem_slot[x] = bt_slot(b.fitem_off, nb, x);
 }
 
-// Repulsion of every (tile, segment) item into the segment sums, then attraction of the
-// listed graphs' rows, one wavefront per row as in the persistent kernel (the row
-// descriptor: absolute CSR range, node, graph base, in one load).  A graph of one
-// segment takes the same path: its one segment sum is its repulsion.
+// Repulsion of one (64-target wave tile, segment) item by one wavefront: the segment's
+// bodies pass through the wavefront's own LDS slice 64 at a time and every lane adds
+// them in ascending order, the same additions as the 256-target tiles of the plain path
+// (a target's sum does not depend on which targets share its tile), into the segment
+// sums seg[s * K + i].  Targets are grouped by 64 so that small supergraphs leave few
+// lanes idle.
+__device__ __forceinline__ void bt_wave_repulsion(int32_t wt, int32_t sgm, int32_t K, const float2 *__restrict__ pos,
+                                                  const float *__restrict__ mass, float2 *__restrict__ seg,
+                                                  float4 *slab) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int32_t i = wt * kWave + lane;
+    const bool live = i < K;
+    const float2 xi = live ? pos[i] : make_float2(0.f, 0.f);
+    const int32_t jb = sgm * kRepSegment, je = min(K, jb + kRepSegment);
+    float fx = 0.f, fy = 0.f;
+    for (int32_t t0 = jb; t0 < je; t0 += kWave) {
+        const int32_t j = t0 + lane;
+        if (j < je) {
+            const float2 xj = pos[j];
+            slab[lane] = make_float4(xj.x, xj.y, mass[j], 0.f);
+        }
+        __builtin_amdgcn_wave_barrier();
+        const int cnt = min(kWave, je - t0);
+        if (cnt == kWave) {
+            fa2_rep_run(xi, slab, kWave, fx, fy);
+        } else {
+            for (int q = 0; q < cnt; ++q) fa2_rep_term(xi, slab[q], fx, fy);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (live) seg[(int64_t)sgm * K + i] = make_float2(fx, fy);
+}
+
+// All (wave tile, segment) items, one per wavefront, then the attraction of the listed
+// graphs' rows, one wavefront per row as in the persistent kernel (the row descriptor:
+// absolute CSR range, node, graph base, in one load).  A graph of one segment takes the
+// same path: its one segment sum is its repulsion.
 __global__ void __launch_bounds__(kFa2Tile) k_bt_force(BtBig b) {
+    __shared__ float4 slab[kFa2Tile];
     const uint32_t nb = *b.nbig;
     const uint32_t FI = b.fitem_off[nb], R = b.row_off[nb];
-    for (uint32_t x = blockIdx.x; x < FI; x += gridDim.x) {
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const uint32_t nw = gridDim.x * (kFa2Tile / kWave);
+    for (uint32_t x = blockIdx.x * (kFa2Tile / kWave) + w; x < FI; x += nw) {
         const uint32_t sl = b.fitem_slot[x];
         const int32_t g = b.big[sl];
         const int64_t n0 = b.node_off[g];
-        const uint32_t ntiles = b.tile_off[sl + 1] - b.tile_off[sl];
+        const int32_t K = b.K[g];
+        const uint32_t wtiles = (uint32_t)((K + kWave - 1) / kWave);
         const uint32_t q = x - b.fitem_off[sl];
-        fa2_exact_force_tile<true>((int32_t)(q % ntiles), (int32_t)(q / ntiles), b.K[g], b.pos + n0, b.mass + n0,
-                                   nullptr, nullptr, b.kr, b.kg, nullptr, nullptr, nullptr,
-                                   b.seg + kBtMaxSeg * n0);
-        __syncthreads();  // the tile function's LDS is reused by the next item
+        bt_wave_repulsion((int32_t)(q % wtiles), (int32_t)(q / wtiles), K, b.pos + n0, b.mass + n0,
+                          b.seg + kBtMaxSeg * n0, slab + w * kWave);
     }
-    const int lane = threadIdx.x & (kWave - 1);
-    const uint32_t nw = gridDim.x * (kFa2Tile / kWave);
     for (uint32_t r = (blockIdx.x * kFa2Tile + threadIdx.x) / kWave; r < R; r += nw) {
         const uint4 d = b.row_desc[r];  // (first entry, end entry, node, graph's first node)
         const float2 *pos = b.pos + d.w;
@@ -636,7 +669,8 @@ static size_t bt_layout(Carver &c, int32_t G, int64_t n_total, int64_t m_total, 
     w->fitem_off = c.take<uint32_t>((size_t)G + 1);
     w->tile_slot = c.take<uint32_t>(n / kFa2Tile + (size_t)G + 1);
     // a listed graph has K <= kBtBigMax supernodes, at most kBtMaxSeg segments of them
-    w->fitem_slot = c.take<uint32_t>((size_t)kBtMaxSeg * (n / kFa2Tile + (size_t)G + 1));
+    // a listed graph has K <= kBtBigMax supernodes: at most kBtMaxSeg segments of K / 64 + 1 wave tiles
+    w->fitem_slot = c.take<uint32_t>((size_t)kBtMaxSeg * (n / kWave + (size_t)G + 1));
     w->row_desc = c.take<uint4>(n);
     w->seg = c.take<float2>((size_t)kBtMaxSeg * n);
     w->bspeed = c.take<float>(2 * (size_t)G);
@@ -792,6 +826,7 @@ extern "C" bgv_status bgv_batched(int32_t G, int64_t n_total, int64_t m_total, c
         // (measured: 512 workgroups looping over the items were 1.4x slower than 4096)
         const unsigned tiles_bound = (unsigned)(n_total / kFa2Tile + G);
         const unsigned gt = tiles_bound < 4096u ? (tiles_bound > 0 ? tiles_bound : 1u) : 4096u;
+        // force items are wavefronts: four per workgroup
         const unsigned gf = gt * (unsigned)kBtMaxSeg < 16384u ? gt * (unsigned)kBtMaxSeg : 16384u;
         BGV_LAUNCH(k_bt_plan, dim3(1), dim3(1024), 0, s, b);
         BGV_LAUNCH(k_bt_maps, dim3(grid_for(n_total > 0 ? n_total : 1, kFa2Tile, 4096)), dim3(kFa2Tile), 0, s, b);
