@@ -13,7 +13,7 @@ import torch
 from . import api
 
 WG_CANDIDATES = (256, 512, 1024)
-BIG_K_CANDIDATES = (0, 128, 256, 512)
+BIG_K_CANDIDATES = (0, 16, 32, 64, 128, 256)
 CANDIDATES = tuple((wg, bk) for wg in WG_CANDIDATES for bk in BIG_K_CANDIDATES)
 CACHE = os.path.join(os.path.expanduser("~"), ".cache", "bgv_autotune.json")
 

@@ -4,9 +4,9 @@
   both sketches and the supergraph bit-exact against the oracle; Barnes-Hut forces on the
   whole supergraph against the oracle's.
 - batched_512 (all 512 graphs in one launch, largest first, in the launch shape the
-  benchmark's autotuner picks: 512-thread workgroups, supergraphs above 128 nodes laid
-  out by the multi-workgroup kernels): every graph bit-identical to the all-persistent
-  launch with 1024-thread workgroups; sampled graphs (the largest, the smallest and four
+  benchmark's autotuner picks: workgroup size and the supergraph size above which the
+  multi-workgroup kernels lay a graph out): every graph bit-identical to the
+  all-persistent launch with 1024-thread workgroups; sampled graphs (the largest, the smallest and four
   seeded picks) bit-exact against the oracle's integers, their last layout step against
   one oracle step.
 - grad_50k (50,000 weighted supernodes from a 5M-node graph): the supergraph bit-exact,
@@ -63,19 +63,25 @@ def test_batched_512_full_size_sampled(bgv):
     edges, noff, eoff, noff_h, eoff_h = bgv.pack_graphs([(n, e) for n, e, _ in graphs], d)
     order = torch.from_numpy(np.argsort(-np.diff(eoff_h), kind="stable").astype(np.int32)).to(d)
     T = wl["fa2_iters"]
+    # the launch shape the benchmark times: the autotuner's pick
+    from paper_2108_00529_amd import autotune
+    (wg, bk), _ = autotune.tune_batched(edges, noff, eoff, int(noff_h[-1]), wl, c1, c2,
+                                        torch.from_numpy(np.concatenate(pos0)).to(d), order=order, repeats=1,
+                                        use_cache=False)
+    say(f"  batched_512: autotuned {wg}-thread workgroups, big_k {bk}")
     runs = {}
     for iters in (T - 1, T):
         pos = torch.from_numpy(np.concatenate(pos0)).to(d)
         runs[iters] = bgv.batched(edges, noff, eoff, int(noff_h[-1]), dict(wl, fa2_iters=iters), c1, c2, pos,
-                                  order=order, wg_threads=512, big_k=128)
+                                  order=order, wg_threads=wg, big_k=bk)
         torch.cuda.synchronize()
     # the same batch with every layout in the persistent launch: the same bits
     pos = torch.from_numpy(np.concatenate(pos0)).to(d)
     ref = bgv.batched(edges, noff, eoff, int(noff_h[-1]), wl, c1, c2, pos, order=order, wg_threads=1024, big_k=0)
     torch.cuda.synchronize()
     K_all = ref["K"].cpu().numpy()
-    say(f"  batched_512: {int(((K_all > 128) & (K_all <= 4096)).sum())} supergraphs laid out by the "
-        f"multi-workgroup kernels, largest K {int(K_all.max())}")
+    nbig = int(((K_all > bk) & (K_all <= 4096)).sum()) if bk > 0 else 0
+    say(f"  batched_512: {nbig} supergraphs laid out by the multi-workgroup kernels, largest K {int(K_all.max())}")
     E_all = ref["E"].cpu().numpy()
     # outputs beyond each graph's K (nodes) or E (edges) are not written: compare the rest
     sup = np.zeros(int(noff_h[-1]), bool)
