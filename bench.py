@@ -475,6 +475,8 @@ def kernel_model(name, K, E, inter_per_launch=None):
                 "update": 48}                       # position, force, previous force read; two written
     if name in per_body:
         return "hbm", per_body[name] * K, "byte"
+    if name == "bh_build_att":  # tree build and attraction in one launch (unweighted CSR ids)
+        return "hbm", 60 * K + (2 if K <= 65536 else 4) * 2 * E + 28 * K, "byte"
     return None
 
 

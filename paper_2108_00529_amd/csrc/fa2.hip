@@ -9,9 +9,10 @@
 //                           summed by k_force_combine when K is larger) + attraction +
 //                           gravity, swing/traction, FP64 block partials of the two sums
 //   BH:     k_bh_bbox -> k_bh_codes -> radix sort -> k_bh_gather -> FP64 prefix sums
-//           -> k_bh_build (binary radix tree; centre of mass of a node = difference of
-//           prefix sums over its body range, so no atomics) -> k_bh_force (traversal
-//           with a shared stack per body)
+//           -> k_bh_build_attract (binary radix tree: centre of mass of a node =
+//           difference of prefix sums over its body range, so no atomics; the
+//           attraction in the same launch) -> k_bh_force (traversal with a shared
+//           stack per body)
 //   both:   k_update        global speed from the partials (every block reduces them in
 //                           the same order), local speeds, displacement
 // No floating-point atomics anywhere: results are identical run to run.
@@ -164,16 +165,16 @@ __device__ __forceinline__ double2 block_sum2(double2 v) {
 // sums are combined by a fixed butterfly, so the result does not depend on timing.
 // Power-law supernode degrees (rows of thousands of entries next to rows of a few)
 // are why a row is not given to a single thread.
+// Attraction items wave0, wave0 + nwaves, ... (one per wavefront), positions from pos
+// (global memory or an LDS copy).
 template <typename E>
-__global__ void __launch_bounds__(kFaThreads) k_attract(int32_t K, const float2 *__restrict__ pos,
-                                                         const uint32_t *__restrict__ row, const E *__restrict__ cw,
-                                                         const uint32_t *__restrict__ item_of,
-                                                         const uint32_t *__restrict__ item_row,
-                                                         float2 *__restrict__ A) {
+__device__ __forceinline__ void att_items(int32_t K, const float2 *__restrict__ pos, const uint32_t *__restrict__ row,
+                                          const E *__restrict__ cw, const uint32_t *__restrict__ item_of,
+                                          const uint32_t *__restrict__ item_row, float2 *__restrict__ A,
+                                          int64_t wave0, int64_t nwaves) {
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t nw = (int64_t)gridDim.x * (kFaThreads / kWave);
     const uint32_t T = item_of[K];
-    for (int64_t t = (blockIdx.x * (int64_t)kFaThreads + threadIdx.x) / kWave; t < T; t += nw) {
+    for (int64_t t = wave0; t < T; t += nwaves) {
         const uint32_t r = item_row[t];
         const uint32_t r1 = row[r + 1];
         const uint32_t b0 = row[r] + ((uint32_t)t - item_of[r]) * kAttBlock;
@@ -181,6 +182,16 @@ __global__ void __launch_bounds__(kFaThreads) k_attract(int32_t K, const float2 
         const float2 a = fa2_block_attraction(pos, cw, b0, b1, pos[r], lane);
         if (lane == 0) A[t] = a;
     }
+}
+
+template <typename E>
+__global__ void __launch_bounds__(kFaThreads) k_attract(int32_t K, const float2 *__restrict__ pos,
+                                                         const uint32_t *__restrict__ row, const E *__restrict__ cw,
+                                                         const uint32_t *__restrict__ item_of,
+                                                         const uint32_t *__restrict__ item_row,
+                                                         float2 *__restrict__ A) {
+    att_items(K, pos, row, cw, item_of, item_row, A, (blockIdx.x * (int64_t)kFaThreads + threadIdx.x) / kWave,
+              (int64_t)gridDim.x * (kFaThreads / kWave));
 }
 
 // The same with all K positions staged in LDS first (kAttLdsMin <= K <= kAttLdsMax):
@@ -202,17 +213,8 @@ __global__ void __launch_bounds__(kAttLdsThreads) k_attract_lds(int32_t K, const
     extern __shared__ float2 sp[];  // K entries
     for (int32_t i = threadIdx.x; i < K; i += kAttLdsThreads) sp[i] = pos[i];
     __syncthreads();
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t nw = (int64_t)gridDim.x * (kAttLdsThreads / kWave);
-    const uint32_t T = item_of[K];
-    for (int64_t t = (blockIdx.x * (int64_t)kAttLdsThreads + threadIdx.x) / kWave; t < T; t += nw) {
-        const uint32_t r = item_row[t];
-        const uint32_t r1 = row[r + 1];
-        const uint32_t b0 = row[r] + ((uint32_t)t - item_of[r]) * kAttBlock;
-        const uint32_t b1 = r1 - b0 > kAttBlock ? b0 + kAttBlock : r1;
-        const float2 a = fa2_block_attraction(sp, cw, b0, b1, sp[r], lane);
-        if (lane == 0) A[t] = a;
-    }
+    att_items(K, sp, row, cw, item_of, item_row, A, (blockIdx.x * (int64_t)kAttLdsThreads + threadIdx.x) / kWave,
+              (int64_t)gridDim.x * (kAttLdsThreads / kWave));
 }
 
 bgv_status attraction(int32_t K, const float2 *pos, const CsrWs &csr, float2 *A, hipStream_t s) {
@@ -497,11 +499,13 @@ __device__ __forceinline__ int delta(const uint32_t *__restrict__ code, int32_t 
 // Internal node i of the binary radix tree over the sorted codes (Karras' parallel
 // construction).  Children: >= 0 internal node, < 0 leaf ~child.  nodeA = (centre of
 // mass, mass, size^2), size^2 < 0 for a node whose codes are all equal (a leaf cell).
-__global__ void k_bh_build(int32_t K, const uint32_t *__restrict__ code, const double *__restrict__ PM,
-                           const double *__restrict__ PX, const double *__restrict__ PY,
-                           const float *__restrict__ s0p, float4 *__restrict__ nodeA, int4 *__restrict__ nodeB) {
+__device__ __forceinline__ void bh_build_nodes(int32_t K, const uint32_t *__restrict__ code,
+                                               const double *__restrict__ PM, const double *__restrict__ PX,
+                                               const double *__restrict__ PY, const float *__restrict__ s0p,
+                                               float4 *__restrict__ nodeA, int4 *__restrict__ nodeB, int32_t i0,
+                                               int32_t stride) {
     const float s0 = *s0p;
-    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < K - 1; i += gridDim.x * blockDim.x) {
+    for (int32_t i = i0; i < K - 1; i += stride) {
         const int d = (delta(code, K, i, i + 1) - delta(code, K, i, i - 1)) >= 0 ? 1 : -1;
         const int dmin = delta(code, K, i, i - d);
         int lmax = 2;
@@ -536,6 +540,47 @@ __global__ void k_bh_build(int32_t K, const uint32_t *__restrict__ code, const d
         nodeB[i] = make_int4(left, right, first, last);
     }
 }
+
+__global__ void k_bh_build(int32_t K, const uint32_t *__restrict__ code, const double *__restrict__ PM,
+                           const double *__restrict__ PX, const double *__restrict__ PY,
+                           const float *__restrict__ s0p, float4 *__restrict__ nodeA, int4 *__restrict__ nodeB) {
+    bh_build_nodes(K, code, PM, PX, PY, s0p, nodeA, nodeB, blockIdx.x * blockDim.x + threadIdx.x,
+                   gridDim.x * blockDim.x);
+}
+
+// The tree build and the attraction in one launch: workgroups [0, build_blocks) build
+// the tree (a few dozen for a supergraph of some ten thousand bodies), the others take
+// the attraction items, which do not depend on the tree, so the two latency-bound jobs
+// overlap instead of following each other.  With kLds the attraction workgroups stage
+// the positions in (dynamic) LDS first, as k_attract_lds does.
+template <typename E, int NT, bool kLds>
+__global__ void __launch_bounds__(NT) k_bh_build_attract(int32_t K, const uint32_t *__restrict__ code,
+                                                          const double *__restrict__ PM,
+                                                          const double *__restrict__ PX,
+                                                          const double *__restrict__ PY,
+                                                          const float *__restrict__ s0p, float4 *__restrict__ nodeA,
+                                                          int4 *__restrict__ nodeB, int32_t build_blocks,
+                                                          const float2 *__restrict__ pos,
+                                                          const uint32_t *__restrict__ row, const E *__restrict__ cw,
+                                                          const uint32_t *__restrict__ item_of,
+                                                          const uint32_t *__restrict__ item_row,
+                                                          float2 *__restrict__ A) {
+    if ((int32_t)blockIdx.x < build_blocks) {  // uniform over the workgroup
+        bh_build_nodes(K, code, PM, PX, PY, s0p, nodeA, nodeB, blockIdx.x * NT + threadIdx.x, build_blocks * NT);
+        return;
+    }
+    const int64_t wave0 = ((int64_t)(blockIdx.x - build_blocks) * NT + threadIdx.x) / kWave;
+    const int64_t nwaves = (int64_t)(gridDim.x - build_blocks) * (NT / kWave);
+    if (kLds) {
+        extern __shared__ float2 sp[];  // K entries
+        for (int32_t i = threadIdx.x; i < K; i += NT) sp[i] = pos[i];
+        __syncthreads();
+        att_items(K, sp, row, cw, item_of, item_row, A, wave0, nwaves);
+    } else {
+        att_items(K, pos, row, cw, item_of, item_row, A, wave0, nwaves);
+    }
+}
+
 
 __device__ __forceinline__ void add_pair(float2 xi, float4 bj, float &fx, float &fy, uint32_t &ic) {
     ++ic;
@@ -759,6 +804,27 @@ static bool fa_valid(int32_t K, int64_t E, const bgv_fa2_params *p) {
 }
 
 // One Barnes-Hut repulsion + force evaluation into w.F / w.part.
+template <typename E, int NT, bool kLds>
+static bgv_status launch_build_attract(int32_t K, const BhWs &b, unsigned build_blocks, unsigned att_blocks,
+                                       size_t lds, const float2 *pos, const CsrWs &csr, float2 *A, hipStream_t s) {
+    const auto k_bh_build_att = k_bh_build_attract<E, NT, kLds>;  // one name for the profiler
+    BGV_LAUNCH(k_bh_build_att, dim3(build_blocks + att_blocks), dim3(NT), lds, s, K, b.code,
+               b.PM, b.PX, b.PY, b.s0, b.nodeA, b.nodeB, (int32_t)build_blocks, pos, csr.row,
+               reinterpret_cast<const E *>(csr.cw), csr.item_of, csr.item_row, A);
+    return BGV_OK;
+}
+
+template <int NT, bool kLds>
+static bgv_status build_attract(int32_t K, const BhWs &b, unsigned att_blocks, size_t lds, const float2 *pos,
+                                const CsrWs &csr, float2 *A, hipStream_t s) {
+    const unsigned build_blocks = grid_for(K - 1, NT, 65536);
+    if (csr.fmt == kCsrWeighted)
+        return launch_build_attract<int2, NT, kLds>(K, b, build_blocks, att_blocks, lds, pos, csr, A, s);
+    if (csr.fmt == kCsrIds32)
+        return launch_build_attract<uint32_t, NT, kLds>(K, b, build_blocks, att_blocks, lds, pos, csr, A, s);
+    return launch_build_attract<uint16_t, NT, kLds>(K, b, build_blocks, att_blocks, lds, pos, csr, A, s);
+}
+
 static bgv_status bh_forces(int32_t K, const float2 *pos, const float *mass, const CsrWs &csr, float theta, float kr,
                             float kg, const float2 *fprev, FaWs &w, hipStream_t s) {
     BhWs &b = w.bh;
@@ -772,9 +838,20 @@ static bgv_status bh_forces(int32_t K, const float2 *pos, const float *mass, con
     BGV_TRY(radix_sort_u64(b.keys, b.keys_alt, b.vals, b.vals_alt, K, 32, &sk, &sv, b.sort_scratch, s));
     BGV_LAUNCH(k_bh_gather, dim3(nb), dim3(kFaThreads), 0, s, K, pos, mass, sk, sv, b.body, b.code, b.part3);
     BGV_LAUNCH(k_bh_prefix, dim3(nb), dim3(kFaThreads), 0, s, K, b.body, b.part3, b.PM, b.PX, b.PY);
+    // the tree and the attraction (which the force kernel combines), in one launch
     if (K > 1) {
-        BGV_LAUNCH(k_bh_build, dim3(grid_for(K - 1, kFaThreads, 65536)), dim3(kFaThreads), 0, s, K, b.code,
-                           b.PM, b.PX, b.PY, b.s0, b.nodeA, b.nodeB);
+        if (K >= kAttLdsMin && K <= kAttLdsMax) {
+            int cus = 1;
+            BGV_TRY(device_cu_count(&cus));
+            const unsigned wg = (unsigned)((csr.items_bound + kAttLdsThreads / kWave - 1) / (kAttLdsThreads / kWave));
+            BGV_TRY((build_attract<kAttLdsThreads, true>(K, b, wg < (unsigned)cus ? (wg > 0 ? wg : 1u) : (unsigned)cus,
+                                                         sizeof(float2) * (size_t)K, pos, csr, w.A, s)));
+        } else {
+            BGV_TRY((build_attract<kFaThreads, false>(K, b, grid_for(csr.items_bound, kFaThreads / kWave, 16384), 0,
+                                                      pos, csr, w.A, s)));
+        }
+    } else {
+        BGV_TRY(attraction(K, pos, csr, w.A, s));
     }
     BGV_LAUNCH(k_bh_force<kBhLanes>, dim3(bh_force_blocks(K)), dim3(kBhThreads), 0, s, K, b.body, b.nodeA,
                b.nodeB, theta * theta, w.A, csr.item_of, kr, kg, fprev, w.F, w.part, b.overflow, b.icount);
@@ -823,11 +900,11 @@ extern "C" bgv_status bgv_fa2_layout(int32_t K, int64_t E, const int32_t *edges,
     float4 *bbox = p->exact ? nullptr : w.bh.bbox;
     if (bbox && p->iters > 0) BGV_LAUNCH(k_bh_bbox, dim3(nb), dim3(kFaThreads), 0, s, K, x, bbox);
     for (int32_t it = 0; it < p->iters; ++it) {
-        BGV_TRY(attraction(K, x, w.csr, w.A, s));
         if (p->exact) {
+            BGV_TRY(attraction(K, x, w.csr, w.A, s));
             BGV_TRY(exact_forces(K, x, m, w.A, w.csr.item_of, p->kr, p->kg, fp, w.F, w.part, w.seg, s));
         } else {
-            BGV_TRY(bh_forces(K, x, m, w.csr, p->theta, p->kr, p->kg, fp, w, s));
+            BGV_TRY(bh_forces(K, x, m, w.csr, p->theta, p->kr, p->kg, fp, w, s));  // attraction included
         }
         const int32_t nparts = p->exact ? nb : bh_force_blocks(K);
         BGV_LAUNCH(k_update, dim3(nb), dim3(kFaThreads), 0, s, K, x, fp, w.F, w.part, nparts, w.speed + (it & 1),
