@@ -469,6 +469,8 @@ def kernel_model(name, K, E, inter_per_launch=None):
     per_body = {"rs_downsweep<kRsItemsSmall>": 24,  # Morton sort pass: key and index read + written
                 "rs_upsweep<kRsItemsSmall>": 8,     # key read
                 "bh_codes": 20,                     # position read, key and index written
+                "bh_codes_count<4>": 20,            # the same, with the first digit count in LDS
+                "bh_codes_count<16>": 20,
                 "bh_gather": 44,                    # key, index, position, mass read; body and code written
                 "bh_prefix": 40,                    # body read; three FP64 prefix sums written
                 "bh_build": 60,                     # codes and prefix sums read; node written

@@ -130,6 +130,16 @@ bgv_status exclusive_scan(const T *in, T *out, int64_t n, T *total, void *scratc
 size_t radix_workspace(int64_t n);
 bgv_status radix_sort_u64(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, uint32_t *vals_alt,
                           int64_t n, int nbits, uint64_t **keys_out, uint32_t **vals_out,
-                          void *scratch, hipStream_t s);
+                          void *scratch, hipStream_t s, bool counted = false);
+
+// Sorts of at most kRsFewTiles tiles (n > 1) count pass 0's digits in one launch ahead
+// of the scatters.  A producer of the keys can do that count itself: for such an n,
+// radix_few_tiles gives the tile shape (tiles of 256 * items consecutive keys) and
+// radix_pass0_buffers where the counts go (counts0[digit * tiles + tile], the low 8
+// bits of each key) and a [256 * tiles] buffer to clear; radix_sort_u64 with
+// counted = true then skips its own count.
+constexpr int kRsFewTiles = 64;
+bool radix_few_tiles(int64_t n, int64_t *tiles, int *items);
+void radix_pass0_buffers(void *scratch, int64_t n, uint32_t **counts0, uint32_t **clear1);
 
 }  // namespace bgv

@@ -408,6 +408,39 @@ __global__ void __launch_bounds__(kFaThreads) k_bh_codes(int32_t K, const float2
     }
 }
 
+// The codes and the sort's first digit count in one launch (sorts on the few-tile
+// path): workgroup t encodes the bodies of sort tile t (256 * ITEMS consecutive ones),
+// counts their low 8 bits in LDS into counts0[digit * tiles + t] and clears its part of
+// the count buffer of the next pass.
+template <int ITEMS>
+__global__ void __launch_bounds__(kFaThreads) k_bh_codes_count(int32_t K, const float2 *__restrict__ pos,
+                                                                const float4 *__restrict__ part, int nparts,
+                                                                uint64_t *__restrict__ keys,
+                                                                uint32_t *__restrict__ vals,
+                                                                float *__restrict__ s0_out,
+                                                                uint32_t *__restrict__ counts0,
+                                                                uint32_t *__restrict__ clear1, int64_t tiles) {
+    __shared__ uint32_t hist[256];
+    float xmin, ymin, s0;
+    bh_frame(part, nparts, &xmin, &ymin, &s0, s0_out);
+    hist[threadIdx.x] = 0u;
+    clear1[(int64_t)blockIdx.x * 256 + threadIdx.x] = 0u;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * (kFaThreads * ITEMS);
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int64_t i = base + (int64_t)j * kFaThreads + threadIdx.x;
+        if (i < K) {
+            const uint32_t c = bh_morton(pos[i], xmin, ymin, s0);
+            keys[i] = (uint64_t)c;
+            vals[i] = (uint32_t)i;
+            atomicAdd(&hist[c & 255u], 1u);
+        }
+    }
+    __syncthreads();
+    counts0[(int64_t)threadIdx.x * tiles + blockIdx.x] = hist[threadIdx.x];
+}
+
 // Bodies [256 g, 256 g + 256) in Morton order (one per thread) and the group totals of
 // the FP64 mass moments m, m*x, m*y into part3[3 g ..].
 __device__ __forceinline__ void bh_gather_group(int32_t g, int32_t K, const float2 *__restrict__ pos,
@@ -831,11 +864,29 @@ static bgv_status bh_forces(int32_t K, const float2 *pos, const float *mass, con
     const unsigned nb = (unsigned)((K + kFaThreads - 1) / kFaThreads);
     // b.bbox holds one box per block of positions (written by k_bh_bbox before the first
     // iteration and by k_update after each one)
-    BGV_LAUNCH(k_bh_codes, dim3(grid_for(K, kFaThreads, 4096)), dim3(kFaThreads), 0, s, K, pos, b.bbox, (int)nb,
-               b.keys, b.vals, b.s0);
     uint64_t *sk;
     uint32_t *sv;
-    BGV_TRY(radix_sort_u64(b.keys, b.keys_alt, b.vals, b.vals_alt, K, 32, &sk, &sv, b.sort_scratch, s));
+    int64_t tiles;
+    int items;
+    if (radix_few_tiles(K, &tiles, &items)) {
+        uint32_t *counts0, *clear1;
+        radix_pass0_buffers(b.sort_scratch, K, &counts0, &clear1);
+        if (items == 4)
+            BGV_LAUNCH(k_bh_codes_count<4>, dim3((unsigned)tiles), dim3(kFaThreads), 0, s, K, pos, b.bbox, (int)nb,
+                       b.keys, b.vals, b.s0, counts0, clear1, tiles);
+        else if (items == 16)
+            BGV_LAUNCH(k_bh_codes_count<16>, dim3((unsigned)tiles), dim3(kFaThreads), 0, s, K, pos, b.bbox, (int)nb,
+                       b.keys, b.vals, b.s0, counts0, clear1, tiles);
+        else {
+            set_error("bh_forces: unexpected sort tile shape (%d keys per thread)", items);
+            return BGV_E_INVALID;
+        }
+        BGV_TRY(radix_sort_u64(b.keys, b.keys_alt, b.vals, b.vals_alt, K, 32, &sk, &sv, b.sort_scratch, s, true));
+    } else {
+        BGV_LAUNCH(k_bh_codes, dim3(grid_for(K, kFaThreads, 4096)), dim3(kFaThreads), 0, s, K, pos, b.bbox,
+                   (int)nb, b.keys, b.vals, b.s0);
+        BGV_TRY(radix_sort_u64(b.keys, b.keys_alt, b.vals, b.vals_alt, K, 32, &sk, &sv, b.sort_scratch, s));
+    }
     BGV_LAUNCH(k_bh_gather, dim3(nb), dim3(kFaThreads), 0, s, K, pos, mass, sk, sv, b.body, b.code, b.part3);
     BGV_LAUNCH(k_bh_prefix, dim3(nb), dim3(kFaThreads), 0, s, K, b.body, b.part3, b.PM, b.PX, b.PY);
     // the tree and the attraction (which the force kernel combines), in one launch

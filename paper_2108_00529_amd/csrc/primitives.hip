@@ -122,7 +122,7 @@ bgv_status exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint
 // ------------------------------------------------------------------ radix sort ---
 constexpr int kRsThreads = 256;
 constexpr int kRsWaves = kRsThreads / kWave;
-constexpr int kRsLocalOffsetTiles = 64;  // up to this many tiles the scatter kernel scans the counts itself
+constexpr int kRsLocalOffsetTiles = kRsFewTiles;  // up to this many tiles the scatter kernel scans the counts itself
 // Keys per thread: 16 for large sorts; 4 for sorts of at most kRsSmallN keys, so that
 // small sorts (the per-iteration Morton sort) spread over 4x more workgroups.
 constexpr int kRsItemsLarge = 16;
@@ -281,11 +281,43 @@ size_t radix_workspace(int64_t n) {
            align_up(3 * sizeof(uint32_t) * 256 * (size_t)kRsLocalOffsetTiles);
 }
 
+bool radix_few_tiles(int64_t n, int64_t *tiles, int *items) {
+    if (n <= 1) return false;
+    const int it = (int)rs_items(n);
+    const int64_t nb = (n + (int64_t)kRsThreads * it - 1) / ((int64_t)kRsThreads * it);
+    if (nb > kRsLocalOffsetTiles) return false;
+    *tiles = nb;
+    *items = it;
+    return true;
+}
+
+// The three rotating count buffers of the few-tile path sit after the per-tile counts
+// and the scan scratch.
+static uint32_t *rs_few_buffers(void *scratch, int64_t n) {
+    const size_t counts_bytes = align_up(sizeof(uint32_t) * 256 * (size_t)radix_tiles_bound(n));
+    return reinterpret_cast<uint32_t *>(static_cast<char *>(scratch) + counts_bytes +
+                                        scan_workspace(256 * radix_tiles_bound(n)));
+}
+
+void radix_pass0_buffers(void *scratch, int64_t n, uint32_t **counts0, uint32_t **clear1) {
+    uint32_t *cb = rs_few_buffers(scratch, n);
+    *counts0 = cb;
+    *clear1 = cb + 256 * kRsLocalOffsetTiles;
+}
+
 bgv_status radix_sort_u64(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, uint32_t *vals_alt,
                           int64_t n, int nbits, uint64_t **keys_out, uint32_t **vals_out,
-                          void *scratch, hipStream_t s) {
+                          void *scratch, hipStream_t s, bool counted) {
     uint64_t *src = keys, *dst = keys_alt;
     uint32_t *vsrc = vals, *vdst = vals_alt;
+    if (counted) {
+        int64_t t;
+        int it;
+        if (!radix_few_tiles(n, &t, &it)) {
+            set_error("radix_sort_u64: pass-0 counts given for a sort that is not on the few-tile path");
+            return BGV_E_INVALID;
+        }
+    }
     if (n > 1) {
         const bool small = rs_items(n) == kRsItemsSmall;
         const int64_t tile = kRsThreads * rs_items(n);
@@ -299,11 +331,12 @@ bgv_status radix_sort_u64(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, ui
             // the next pass's digits itself, so only pass 0 has a counting launch; three
             // count buffers rotate (read by pass i, filled during pass i-1, cleared two
             // passes ahead)
-            uint32_t *cb = reinterpret_cast<uint32_t *>(static_cast<char *>(scan_scratch) +
-                                                        scan_workspace(256 * radix_tiles_bound(n)));
+            uint32_t *cb = rs_few_buffers(scratch, n);
             uint32_t *buf[3] = {cb, cb + 256 * kRsLocalOffsetTiles, cb + 2 * 256 * kRsLocalOffsetTiles};
             uint32_t *zero1 = npass > 1 ? buf[1] : nullptr;
-            if (small)
+            if (counted) {
+                // the caller counted pass 0 into buf[0] and cleared buf[1]
+            } else if (small)
                 BGV_LAUNCH(k_rs_upsweep<kRsItemsSmall>, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, n, 0,
                            buf[0], nb, zero1);
             else

@@ -380,10 +380,11 @@ def test_bh_checkpoints_planted(bgv, planted_sg):
     assert worst <= TOL
 
 
-@pytest.mark.parametrize("K", [5000, 65536, 70000])
+@pytest.mark.parametrize("K", [5000, 65536, 70000, 270000])
 def test_bh_one_step_random(bgv, K):
-    """Morton sorts at the largest size sorted in 1024-key tiles (64 of them) and just
-    above it (4096-key tiles)."""
+    """Morton sorts at the largest size sorted in 1024-key tiles (64 of them), just above
+    it (4096-key tiles, codes counted by the encoding launch), and past 64 tiles (a
+    separate encoding launch, counts scanned device-wide)."""
     rng = np.random.default_rng(10)
     pos32 = (rng.standard_normal((K, 2)) * np.array([3.0, 1.0])).astype(np.float32)
     pos32[:20] = pos32[20]  # a multi-body cell
