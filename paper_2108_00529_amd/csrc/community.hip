@@ -7,7 +7,7 @@
 //
 // Two implementations give the same integers.
 //
-// Bucketed (n <= kCdMaxBuckets * kCdBucket): node records {counter, label} (8 bytes)
+// Bucketed (n <= kCdMaxBuckets * kCdBucket): counters and labels in two int32 arrays
 // and no global atomics.  Nodes fall into buckets of kCdBucket consecutive ids.
 //   group (pass 0)  each 1024-edge tile of a chunk writes its endpoints grouped by
 //                   bucket, one segment per (tile, bucket), offsets in a per-tile table
@@ -163,9 +163,25 @@ __device__ __forceinline__ uint32_t cd_offsets(uint32_t *hist, int32_t nb, uint3
     return total;
 }
 
-__global__ void __launch_bounds__(kCdThreads) k_cd_init_b(int2 *st, int32_t n) {
-    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-        st[v] = make_int2(0, (int32_t)v);
+__global__ void __launch_bounds__(kCdThreads) k_cd_init_b(int32_t *cnt, int32_t *lab, int32_t n) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        cnt[v] = 0;
+        lab[v] = (int32_t)v;
+    }
+}
+
+// Counting stops after pass 0, so each counter is d(v), the true degree.
+__global__ void __launch_bounds__(kCdThreads) k_cd_finish_b(const int32_t *__restrict__ cnt,
+                                                             const int32_t *__restrict__ lab, int32_t n,
+                                                             int32_t *__restrict__ labels,
+                                                             int32_t *__restrict__ degree,
+                                                             unsigned long long *__restrict__ volume) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t d = cnt[v], l = lab[v];
+        labels[v] = l;
+        degree[v] = d;
+        if (volume && d) atomicAdd(&volume[l], (unsigned long long)d);
+    }
 }
 
 // Endpoints of the non-loop edges of tile `tile` of chunk [cs, ce), grouped by bucket:
@@ -203,12 +219,15 @@ __device__ __forceinline__ void cd_group_tile(const int2 *__restrict__ edges, in
     for (uint32_t k = threadIdx.x; k < total; k += kCdThreads) out[k] = stage[k];
 }
 
-// Decide, tile `tile` of chunk [cs, ce): the rule above on the records (counters as in
-// the atomic path's decide: pass-0 values stored per edge in c1 when more passes
-// follow, p * d(v) + c1 in later passes), each proposal (offset of the target in its
-// bucket, stream index, label) grouped by the target's bucket.
+// Decide, tile `tile` of chunk [cs, ce): the rule above (counters as in the atomic
+// path's decide: pass-0 values stored per edge in c1 when more passes follow,
+// p * d(v) + c1 in later passes), each proposal (offset of the target in its bucket,
+// stream index, label) grouped by the target's bucket.  Counters and labels are
+// separate arrays: every edge gathers two 4-byte counters (at a million nodes the
+// counter array fits one XCD's L2), and only proposing edges gather a label.
 template <int kMode>  // 0: only pass; 1: pass 0 of several; 2: a later pass
-__device__ __forceinline__ void cd_decide_tile(const int2 *__restrict__ st, const int2 *__restrict__ edges,
+__device__ __forceinline__ void cd_decide_tile(const int32_t *__restrict__ cnt, const int32_t *__restrict__ labv,
+                                               const int2 *__restrict__ edges,
                                                int2 *__restrict__ c1, int64_t cs, int64_t ce, int32_t D,
                                                int32_t pass, int32_t tile, int32_t nb, uint3 *__restrict__ props,
                                                uint32_t *__restrict__ ptab, uint32_t *hist, uint3 *stage) {
@@ -224,18 +243,17 @@ __device__ __forceinline__ void cd_decide_tile(const int2 *__restrict__ st, cons
         if (i < ce) {
             const int2 e = edges[i];
             if (e.x != e.y) {
-                const int2 su = st[e.x], sv = st[e.y];  // {counter, label}
-                int32_t cu = su.x, cv = sv.x;
+                int32_t cu = cnt[e.x], cv = cnt[e.y];
                 if (kMode == 1) c1[i] = make_int2(cu, cv);
                 if (kMode == 2) {
                     const int2 c = c1[i];
-                    cu = pass * su.x + c.x;
-                    cv = pass * sv.x + c.y;
+                    cu = pass * cu + c.x;
+                    cv = pass * cv + c.y;
                 }
                 if (cu <= D && cv <= D && cu != cv) {
                     const bool u_low = cu < cv;
                     target[j] = u_low ? e.x : e.y;
-                    lab[j] = u_low ? sv.y : su.y;
+                    lab[j] = labv[u_low ? e.y : e.x];
                     rank[j] = atomicAdd(&hist[target[j] >> kCdBucketBits], 1u);
                 }
             }
@@ -258,7 +276,9 @@ __device__ __forceinline__ void cd_decide_tile(const int2 *__restrict__ st, cons
 // endpoints of the next chunk [gs, ge) for the counter increments of the resolve that
 // follows; workgroup x takes tile x of each.
 template <int kMode>  // -1: grouping only
-__global__ void __launch_bounds__(kCdThreads) k_cd_step(const int2 *__restrict__ st, const int2 *__restrict__ edges,
+__global__ void __launch_bounds__(kCdThreads) k_cd_step(const int32_t *__restrict__ cnt,
+                                                         const int32_t *__restrict__ labv,
+                                                         const int2 *__restrict__ edges,
                                                          int2 *__restrict__ c1, int64_t cs, int64_t ce, int32_t D,
                                                          int32_t pass, int32_t nb, uint3 *__restrict__ props,
                                                          uint32_t *__restrict__ ptab, int64_t gs, int64_t ge,
@@ -268,7 +288,8 @@ __global__ void __launch_bounds__(kCdThreads) k_cd_step(const int2 *__restrict__
     __shared__ uint16_t estage[2 * kCdTile];
     const int32_t tile = (int32_t)blockIdx.x;
     if (kMode >= 0 && cs + (int64_t)tile * kCdTile < ce)  // uniform over the workgroup
-        cd_decide_tile<kMode < 0 ? 0 : kMode>(st, edges, c1, cs, ce, D, pass, tile, nb, props, ptab, hist, pstage);
+        cd_decide_tile<kMode < 0 ? 0 : kMode>(cnt, labv, edges, c1, cs, ce, D, pass, tile, nb, props, ptab, hist,
+                                              pstage);
     if (gs + (int64_t)tile * kCdTile < ge) {
         __syncthreads();  // hist is reused
         cd_group_tile(edges, gs, ge, tile, nb, ends, etab, hist, estage);
@@ -299,7 +320,8 @@ __device__ __forceinline__ void cd_segment(const uint32_t *__restrict__ tab, int
     *q1 = row[b + 1];
 }
 
-__global__ void __launch_bounds__(kCdResolveThreads) k_cd_resolve(int2 *__restrict__ st, int32_t n, int32_t nb,
+__global__ void __launch_bounds__(kCdResolveThreads) k_cd_resolve(int32_t *__restrict__ cnt,
+                                                                   int32_t *__restrict__ lab, int32_t n, int32_t nb,
                                                                    const uint3 *__restrict__ props,
                                                                    const uint32_t *__restrict__ ptab, int32_t ptiles,
                                                                    const uint16_t *__restrict__ ends,
@@ -342,13 +364,13 @@ __global__ void __launch_bounds__(kCdResolveThreads) k_cd_resolve(int2 *__restri
         }
     }
     __syncthreads();
-    int2 *rec = st + ((int64_t)b << kCdBucketBits);
+    const int64_t base = (int64_t)b << kCdBucketBits;
     const int32_t span = min(kCdBucket, n - (b << kCdBucketBits));
     for (int32_t k = threadIdx.x; k < span; k += kCdResolveThreads) {
         const unsigned long long w = win[k];
         const uint32_t c = inc[k];
-        if (w != ~0ull) rec[k].y = (int32_t)(uint32_t)w;
-        if (c) rec[k].x += (int32_t)c;
+        if (w != ~0ull) lab[base + k] = (int32_t)(uint32_t)w;
+        if (c) cnt[base + k] += (int32_t)c;
     }
 }
 
@@ -369,7 +391,7 @@ static bool cd_valid(int32_t n, int64_t m, const bgv_cd_params *p) {
 struct CdWs {
     NodeState *st;      // atomic path
     int32_t *prop;      // atomic path
-    int2 *st2;          // bucketed path
+    int32_t *cnt, *lab; // bucketed path: counters and labels
     uint3 *props;       // bucketed: proposals grouped per tile
     uint16_t *ends;     // bucketed: endpoints grouped per tile
     uint32_t *ptab, *etab;
@@ -383,7 +405,8 @@ static size_t cd_layout(Carver &c, int32_t n, int64_t m, const bgv_cd_params *p,
     if (cd_bucketed(n)) {
         const size_t tiles = (bb + kCdTile - 1) / kCdTile;
         const size_t nb = (size_t)cd_buckets(n);
-        w->st2 = c.take<int2>((size_t)n);
+        w->cnt = c.take<int32_t>((size_t)n);
+        w->lab = c.take<int32_t>((size_t)n);
         w->props = c.take<uint3>(tiles * kCdTile);
         w->ends = c.take<uint16_t>(tiles * 2 * kCdTile);
         w->ptab = c.take<uint32_t>(tiles * (nb + 1));
@@ -431,8 +454,7 @@ extern "C" bgv_status bgv_community(int32_t n, int64_t m, const int32_t *edges, 
 
     if (cd_bucketed(n)) {
         const int32_t nb = cd_buckets(n);
-        int2 *st2 = w.st2;
-        BGV_LAUNCH(k_cd_init_b, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, st2, n);
+        BGV_LAUNCH(k_cd_init_b, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, w.cnt, w.lab, n);
         int32_t ptiles = 0;  // decide tiles whose proposals are not yet resolved
         int32_t etiles = 0;  // grouped endpoint tiles whose increments are not yet added
         auto tiles_of = [&](int64_t k) {
@@ -442,7 +464,7 @@ extern "C" bgv_status bgv_community(int32_t n, int64_t m, const int32_t *edges, 
         if (nchunk > 0) {
             // pass 0, chunk 0: its endpoints grouped before anything is decided
             etiles = tiles_of(0);
-            BGV_LAUNCH(k_cd_step<-1>, dim3(etiles), dim3(kCdThreads), 0, s, st2, e2, w.c1, (int64_t)0, (int64_t)0,
+            BGV_LAUNCH(k_cd_step<-1>, dim3(etiles), dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1, (int64_t)0, (int64_t)0,
                        0, 0, nb, w.props, w.ptab, (int64_t)0, std::min<int64_t>(B, m), w.ends, w.etab);
         }
         for (int32_t pass = 0; pass < p->passes && m > 0; ++pass) {
@@ -452,7 +474,7 @@ extern "C" bgv_status bgv_community(int32_t n, int64_t m, const int32_t *edges, 
                 const int32_t tiles = tiles_of(k);
                 // proposals of the previous chunk and, in pass 0, this chunk's increments
                 if (ptiles > 0 || etiles > 0)
-                    BGV_LAUNCH(k_cd_resolve, dim3(nb), dim3(kCdResolveThreads), 0, s, st2, n, nb, w.props, w.ptab,
+                    BGV_LAUNCH(k_cd_resolve, dim3(nb), dim3(kCdResolveThreads), 0, s, w.cnt, w.lab, n, nb, w.props, w.ptab,
                                ptiles, w.ends, w.etab, etiles, cd_resolve_lanes(std::max(ptiles, etiles)));
                 // counters are incremented in pass 0 only (later passes use the closed form):
                 // the next chunk's endpoints are grouped by this launch in pass 0
@@ -461,24 +483,23 @@ extern "C" bgv_status bgv_community(int32_t n, int64_t m, const int32_t *edges, 
                 const int32_t gtiles = group_next ? tiles_of(k + 1) : 0;
                 const dim3 grid((unsigned)std::max(tiles, gtiles));
                 if (p->passes == 1)
-                    BGV_LAUNCH(k_cd_step<0>, grid, dim3(kCdThreads), 0, s, st2, e2, w.c1, cs, ce, D, pass, nb,
+                    BGV_LAUNCH(k_cd_step<0>, grid, dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1, cs, ce, D, pass, nb,
                                w.props, w.ptab, gs, ge, w.ends, w.etab);
                 else if (pass == 0)
-                    BGV_LAUNCH(k_cd_step<1>, grid, dim3(kCdThreads), 0, s, st2, e2, w.c1, cs, ce, D, pass, nb,
+                    BGV_LAUNCH(k_cd_step<1>, grid, dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1, cs, ce, D, pass, nb,
                                w.props, w.ptab, gs, ge, w.ends, w.etab);
                 else
-                    BGV_LAUNCH(k_cd_step<2>, grid, dim3(kCdThreads), 0, s, st2, e2, w.c1, cs, ce, D, pass, nb,
+                    BGV_LAUNCH(k_cd_step<2>, grid, dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1, cs, ce, D, pass, nb,
                                w.props, w.ptab, gs, ge, w.ends, w.etab);
                 ptiles = tiles;
                 etiles = gtiles;
             }
         }
         if (ptiles > 0)
-            BGV_LAUNCH(k_cd_resolve, dim3(nb), dim3(kCdResolveThreads), 0, s, st2, n, nb, w.props, w.ptab, ptiles, w.ends,
+            BGV_LAUNCH(k_cd_resolve, dim3(nb), dim3(kCdResolveThreads), 0, s, w.cnt, w.lab, n, nb, w.props, w.ptab, ptiles, w.ends,
                        w.etab, 0, cd_resolve_lanes(ptiles));
-        BGV_LAUNCH(k_cd_finish<2>, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s,
-                   reinterpret_cast<const int32_t *>(st2), n, labels, degree,
-                   reinterpret_cast<unsigned long long *>(volume));
+        BGV_LAUNCH(k_cd_finish_b, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, w.cnt, w.lab, n,
+                   labels, degree, reinterpret_cast<unsigned long long *>(volume));
         return BGV_OK;
     }
 
