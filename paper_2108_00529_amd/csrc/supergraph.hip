@@ -129,23 +129,87 @@ __global__ void __launch_bounds__(kSgThreads) k_sg_edge_keys(const int2 *__restr
         if ((flags >> j) & 1u) keys[at++] = k[j];
 }
 
-__global__ void k_sg_unique_flag(const uint64_t *__restrict__ keys, int64_t nk, uint32_t *__restrict__ flag) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nk; i += (int64_t)gridDim.x * blockDim.x)
-        flag[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
+// Distinct sorted keys, in tiles of kUqTile: k_sg_unique_count counts each tile's run
+// starts (key differs from its predecessor), an exclusive scan of the tile counts gives
+// each tile's first superedge, and k_sg_unique_write numbers the run starts inside the
+// tile (a block scan in key order) and writes superedge j = (sid_lo, sid_hi) with the
+// position of its run.  Two reads of the keys instead of a device-wide scan of one flag
+// per key.
+constexpr int kUqItems = 16;
+constexpr int kUqTile = kSgThreads * kUqItems;
+constexpr int kUqWaves = kSgThreads / kWave;
+
+// The keys of wavefront w of a tile: kUqItems rounds of 64 consecutive keys from
+// tile * kUqTile + w * 64 * kUqItems, with the run-start flag of each (its key differs
+// from the one before it: the lane below, the last lane of the previous round, or for
+// the wavefront's first key the key before it in memory).
+__device__ __forceinline__ void uq_load(const uint64_t *__restrict__ keys, int64_t nk, int64_t wbase, int lane,
+                                        uint64_t *k, bool *start) {
+    uint64_t before = (lane == 0 && wbase > 0 && wbase - 1 < nk) ? keys[wbase - 1] : 0ull;
+#pragma unroll
+    for (int u = 0; u < kUqItems; ++u) {
+        const int64_t i = wbase + (int64_t)u * kWave + lane;
+        k[u] = i < nk ? keys[i] : 0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < kUqItems; ++u) {
+        const int64_t i = wbase + (int64_t)u * kWave + lane;
+        uint64_t prev = __shfl_up(k[u], 1, kWave);
+        const uint64_t last_prev_round = __shfl(u > 0 ? k[u > 0 ? u - 1 : 0] : before, kWave - 1, kWave);
+        if (lane == 0) prev = u > 0 ? last_prev_round : before;
+        start[u] = i < nk && (i == 0 || k[u] != prev);
+    }
 }
 
-// Distinct keys: superedge j = (sid_lo, sid_hi) and the position of its run.
-__global__ void k_sg_unique_write(const uint64_t *__restrict__ keys, int64_t nk, const uint32_t *__restrict__ flag,
-                                  const uint32_t *__restrict__ pos, int kbits, int32_t *__restrict__ superedges,
-                                  uint32_t *__restrict__ run_start) {
+__global__ void __launch_bounds__(kSgThreads) k_sg_unique_count(const uint64_t *__restrict__ keys, int64_t nk,
+                                                                 uint32_t *__restrict__ tile_count) {
+    __shared__ uint32_t ws[kUqWaves];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int64_t wbase = (int64_t)blockIdx.x * kUqTile + (int64_t)w * (kWave * kUqItems);
+    uint64_t k[kUqItems];
+    bool start[kUqItems];
+    uq_load(keys, nk, wbase, lane, k, start);
+    uint32_t c = 0;
+#pragma unroll
+    for (int u = 0; u < kUqItems; ++u) c += (uint32_t)__popcll(__ballot(start[u]));
+    if (lane == 0) ws[w] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int q = 0; q < kUqWaves; ++q) t += ws[q];
+        tile_count[blockIdx.x] = t;
+    }
+}
+
+__global__ void __launch_bounds__(kSgThreads) k_sg_unique_write(const uint64_t *__restrict__ keys, int64_t nk,
+                                                                 const uint32_t *__restrict__ tile_first, int kbits,
+                                                                 int32_t *__restrict__ superedges,
+                                                                 uint32_t *__restrict__ run_start) {
+    __shared__ uint32_t ws[kUqWaves];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int64_t wbase = (int64_t)blockIdx.x * kUqTile + (int64_t)w * (kWave * kUqItems);
+    uint64_t k[kUqItems];
+    bool start[kUqItems];
+    uq_load(keys, nk, wbase, lane, k, start);
+    uint32_t c = 0;
+#pragma unroll
+    for (int u = 0; u < kUqItems; ++u) c += (uint32_t)__popcll(__ballot(start[u]));
+    if (lane == 0) ws[w] = c;
+    __syncthreads();
+    uint32_t j = tile_first[blockIdx.x];
+    for (int q = 0; q < w; ++q) j += ws[q];  // the wavefronts before this one, in key order
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const uint64_t lowmask = (1ull << kbits) - 1ull;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nk; i += (int64_t)gridDim.x * blockDim.x) {
-        if (!flag[i]) continue;
-        const uint64_t k = keys[i];
-        const uint32_t j = pos[i];
-        superedges[2 * (int64_t)j] = (int32_t)(k >> kbits);
-        superedges[2 * (int64_t)j + 1] = (int32_t)(k & lowmask);
-        run_start[j] = (uint32_t)i;
+#pragma unroll
+    for (int u = 0; u < kUqItems; ++u) {
+        const uint64_t m = __ballot(start[u]);
+        if (start[u]) {
+            const uint32_t at = j + (uint32_t)__popcll(m & lt);
+            superedges[2 * (int64_t)at] = (int32_t)(k[u] >> kbits);
+            superedges[2 * (int64_t)at + 1] = (int32_t)(k[u] & lowmask);
+            run_start[at] = (uint32_t)(wbase + (int64_t)u * kWave + lane);
+        }
+        j += (uint32_t)__popcll(m);
     }
 }
 
@@ -312,7 +376,7 @@ __global__ void k_sg_node_super(const int32_t *__restrict__ labels, const uint32
 }
 
 struct SgWs {
-    uint32_t *flag, *sid, *vol, *nsid, *counters, *uflag, *upos, *run_start;
+    uint32_t *flag, *sid, *vol, *nsid, *counters, *utile, *run_start;
     uint64_t *keys, *keys_alt;
     uint2 *ent;       // grouped sketch-2 entries (bucketed sketch only)
     uint32_t *etab;   // their per-tile offset rows
@@ -330,8 +394,7 @@ static size_t sg_layout(Carver &c, int32_t n, int64_t m, int32_t rows, int64_t c
     w->counters = c.take<uint32_t>(8);  // [0] K, [1] E_S, [2..3] key count (u64, 8-byte aligned)
     w->keys = c.take<uint64_t>((size_t)mm);
     w->keys_alt = c.take<uint64_t>((size_t)mm);
-    w->uflag = c.take<uint32_t>((size_t)mm);
-    w->upos = c.take<uint32_t>((size_t)mm);
+    w->utile = c.take<uint32_t>((size_t)mm / kUqTile + 1);  // unique counts, then first superedge, per tile
     w->run_start = c.take<uint32_t>((size_t)mm);
     const int64_t big = n > mm ? n : mm;
     w->scan_scratch = c.take<char>(scan_workspace(big));
@@ -445,9 +508,10 @@ extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges,
         BGV_TRY(radix_sort_u64(w.keys, w.keys_alt, nullptr, nullptr, (int64_t)nk, 2 * kbits, &sorted, nullptr,
                                w.sort_scratch, s));
         const unsigned gk = grid_for((int64_t)nk, kSgThreads, 65536);
-        BGV_LAUNCH(k_sg_unique_flag, dim3(gk), dim3(kSgThreads), 0, s, sorted, (int64_t)nk, w.uflag);
-        BGV_TRY(exclusive_scan_u32(w.uflag, w.upos, (int64_t)nk, &w.counters[1], w.scan_scratch, s));
-        BGV_LAUNCH(k_sg_unique_write, dim3(gk), dim3(kSgThreads), 0, s, sorted, (int64_t)nk, w.uflag, w.upos, kbits,
+        const unsigned ut = (unsigned)(((int64_t)nk + kUqTile - 1) / kUqTile);
+        BGV_LAUNCH(k_sg_unique_count, dim3(ut), dim3(kSgThreads), 0, s, sorted, (int64_t)nk, w.utile);
+        BGV_TRY(exclusive_scan_u32(w.utile, w.utile, (int64_t)ut, &w.counters[1], w.scan_scratch, s));
+        BGV_LAUNCH(k_sg_unique_write, dim3(ut), dim3(kSgThreads), 0, s, sorted, (int64_t)nk, w.utile, kbits,
                    superedges, w.run_start);
         if (grouped_sketch) {
             const int32_t nb = (int32_t)sk_buckets(cells);
