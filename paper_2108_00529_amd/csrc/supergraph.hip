@@ -409,6 +409,22 @@ static size_t sg_layout(Carver &c, int32_t n, int64_t m, int32_t rows, int64_t c
     return c.size();
 }
 
+// A small pinned host buffer and an event per host thread, for device-to-host reads of
+// counts that run asynchronously while later work is already queued.
+struct SgReadback {
+    uint32_t *host = nullptr;
+    hipEvent_t ev = nullptr;
+};
+static bgv_status sg_readback(SgReadback **out) {
+    static thread_local SgReadback rb;
+    if (!rb.host) {
+        BGV_CHECK_HIP(hipHostMalloc(reinterpret_cast<void **>(&rb.host), 64, hipHostMallocDefault));
+        BGV_CHECK_HIP(hipEventCreateWithFlags(&rb.ev, hipEventDisableTiming));
+    }
+    *out = &rb;
+    return BGV_OK;
+}
+
 static bool sg_valid(int32_t n, int64_t m, const bgv_sketch_params *s) {
     return s && n >= 1 && m >= 0 && m <= INT32_MAX && s->rows >= 1 && s->rows <= kMaxRows && s->cols >= 1 &&
            s->coef1 && s->coef2;
@@ -468,6 +484,11 @@ extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges,
     }
     BGV_TRY(exclusive_scan_u32(w.flag, w.sid, n, &w.counters[0], w.scan_scratch, s));
     BGV_LAUNCH(k_sg_compact, dim3(gn), dim3(kSgThreads), 0, s, w.flag, w.sid, n, super_label);
+    // K sizes the packed superedge keys: read it back while the sketch-1 work below runs
+    SgReadback *rb;
+    BGV_TRY(sg_readback(&rb));
+    BGV_CHECK_HIP(hipMemcpyAsync(rb->host, &w.counters[0], sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    BGV_CHECK_HIP(hipEventRecord(rb->ev, s));
 
     // sketch 1 and sizes
     BGV_TRY(fill<uint32_t>(M1, 0u, cells, s));
@@ -484,10 +505,8 @@ extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges,
                        M1, super_size);
     BGV_LAUNCH(k_sg_node_super, dim3(gn), dim3(kSgThreads), 0, s, labels, w.sid, n, w.nsid, node_super);
 
-    // K is needed to size the packed superedge keys
-    uint32_t Kh = 0;
-    BGV_CHECK_HIP(hipMemcpyAsync(&Kh, &w.counters[0], sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    BGV_CHECK_HIP(hipStreamSynchronize(s));
+    BGV_CHECK_HIP(hipEventSynchronize(rb->ev));
+    const uint32_t Kh = rb->host[0];
     *K_out = (int32_t)Kh;
     int kbits = 1;
     while (kbits < 31 && (1u << kbits) < Kh) ++kbits;
@@ -498,9 +517,11 @@ extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges,
         BGV_LAUNCH(k_sg_edge_keys, dim3((unsigned)((m + kSgThreads * kKeyItems - 1) / (kSgThreads * kKeyItems))), dim3(kSgThreads), 0, s, e2, m,
                    w.nsid, kbits, w.keys, nkeys_d);
     }
-    unsigned long long nk = 0;
-    BGV_CHECK_HIP(hipMemcpyAsync(&nk, nkeys_d, sizeof nk, hipMemcpyDeviceToHost, s));
-    BGV_CHECK_HIP(hipStreamSynchronize(s));
+    unsigned long long *nk_host = reinterpret_cast<unsigned long long *>(rb->host + 2);
+    BGV_CHECK_HIP(hipMemcpyAsync(nk_host, nkeys_d, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    BGV_CHECK_HIP(hipEventRecord(rb->ev, s));
+    BGV_CHECK_HIP(hipEventSynchronize(rb->ev));
+    const unsigned long long nk = *nk_host;
     int64_t E = 0;
     if (nk == 0 && grouped_sketch) BGV_TRY(fill<uint32_t>(M2, 0u, cells, s));
     if (nk > 0) {
@@ -527,10 +548,9 @@ extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges,
         }
         BGV_LAUNCH(k_sg_pair_weights, dim3(gk), dim3(kSgThreads), 0, s, superedges, &w.counters[1], super_label, h2,
                    rows, cols, M2, se_weight);
-        uint32_t Eh = 0;
-        BGV_CHECK_HIP(hipMemcpyAsync(&Eh, &w.counters[1], sizeof Eh, hipMemcpyDeviceToHost, s));
+        BGV_CHECK_HIP(hipMemcpyAsync(rb->host + 4, &w.counters[1], sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         BGV_CHECK_HIP(hipStreamSynchronize(s));
-        E = Eh;
+        E = rb->host[4];
     }
     *E_out = E;
     return BGV_OK;
