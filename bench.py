@@ -466,8 +466,8 @@ def kernel_model(name, K, E, inter_per_launch=None):
         return "alu", BH_INTERACTION_FLOPS * inter_per_launch, "flop"
     if name in CSR_ENTRY_BYTES:  # CSR entries + row offsets, own and neighbour positions, result
         return "hbm", CSR_ENTRY_BYTES[name] * 2 * E + 28 * K, "byte"
-    per_body = {"rs_downsweep<kRsItemsSmall>": 24,  # Morton sort pass: key and index read + written
-                "rs_upsweep<kRsItemsSmall>": 8,     # key read
+    per_body = {"rs_downsweep_small": 16,          # Morton sort pass: 32-bit code and index read + written
+                "rs_upsweep_small": 4,              # code read
                 "bh_codes": 20,                     # position read, key and index written
                 "bh_codes_count<4>": 20,            # the same, with the first digit count in LDS
                 "bh_codes_count<16>": 20,

@@ -124,12 +124,16 @@ bgv_status exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint
 template <class T>  // instantiated for uint32_t and double
 bgv_status exclusive_scan(const T *in, T *out, int64_t n, T *total, void *scratch, hipStream_t s);
 
-// Stable LSD radix sort of 64-bit keys below 2^nbits, with an optional uint32 payload.
+// Stable LSD radix sort of keys below 2^nbits, with an optional uint32 payload.
 // keys/alt (and vals/vals_alt) are ping-pong buffers of n entries; the sorted result
 // ends in *keys_out/*vals_out (one of the two).  Scratch from radix_workspace(n).
 size_t radix_workspace(int64_t n);
 bgv_status radix_sort_u64(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, uint32_t *vals_alt,
                           int64_t n, int nbits, uint64_t **keys_out, uint32_t **vals_out,
+                          void *scratch, hipStream_t s, bool counted = false);
+// The same for keys below 2^nbits <= 2^32 held in 32 bits (half the traffic per pass).
+bgv_status radix_sort_u32(uint32_t *keys, uint32_t *keys_alt, uint32_t *vals, uint32_t *vals_alt,
+                          int64_t n, int nbits, uint32_t **keys_out, uint32_t **vals_out,
                           void *scratch, hipStream_t s, bool counted = false);
 
 // Sorts of at most kRsFewTiles tiles (n > 1) count pass 0's digits in one launch ahead

@@ -29,18 +29,20 @@ constexpr int kFaThreads = 256;
 static_assert(kFaThreads == kFa2Tile, "the layout kernels work on 256-node tiles");
 
 // ------------------------------------------------------------------------ CSR ----
-__global__ void k_csr_keys(const int2 *__restrict__ edges, int64_t E, int kb, uint64_t *__restrict__ keys,
+template <typename KT>  // 32-bit keys when 2 * kb <= 32
+__global__ void k_csr_keys(const int2 *__restrict__ edges, int64_t E, int kb, KT *__restrict__ keys,
                            uint32_t *__restrict__ vals) {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x) {
         const int2 p = edges[e];
-        keys[2 * e] = ((uint64_t)(uint32_t)p.x << kb) | (uint32_t)p.y;
-        keys[2 * e + 1] = ((uint64_t)(uint32_t)p.y << kb) | (uint32_t)p.x;
+        keys[2 * e] = ((KT)(uint32_t)p.x << kb) | (KT)(uint32_t)p.y;
+        keys[2 * e + 1] = ((KT)(uint32_t)p.y << kb) | (KT)(uint32_t)p.x;
         vals[2 * e] = (uint32_t)e;
         vals[2 * e + 1] = (uint32_t)e;
     }
 }
 
-__global__ void k_csr_fill(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals, int64_t nent,
+template <typename KT>
+__global__ void k_csr_fill(const KT *__restrict__ keys, const uint32_t *__restrict__ vals, int64_t nent,
                            int kb, int32_t K, const float *__restrict__ attr_w, int fmt, uint32_t *__restrict__ row,
                            int2 *__restrict__ cw) {
     const uint64_t mask = (1ull << kb) - 1ull;
@@ -116,13 +118,24 @@ bgv_status build_csr(int32_t K, int64_t E, const int32_t *edges, const float *at
         BGV_TRY(fill<uint32_t>(w.row, 0u, (int64_t)K + 1, s));
     } else {
         const int kb = bits_for(K);
-        BGV_LAUNCH(k_csr_keys, dim3(grid_for(E, kFaThreads, 65536)), dim3(kFaThreads), 0, s,
-                           reinterpret_cast<const int2 *>(edges), E, kb, w.keys, w.vals);
-        uint64_t *sk;
+        const int2 *e2 = reinterpret_cast<const int2 *>(edges);
+        const dim3 ge(grid_for(E, kFaThreads, 65536)), gf(grid_for(2 * E, kFaThreads, 65536));
         uint32_t *sv;
-        BGV_TRY(radix_sort_u64(w.keys, w.keys_alt, w.vals, w.vals_alt, 2 * E, 2 * kb, &sk, &sv, w.sort_scratch, s));
-        BGV_LAUNCH(k_csr_fill, dim3(grid_for(2 * E, kFaThreads, 65536)), dim3(kFaThreads), 0, s, sk, sv,
-                           2 * E, kb, K, attr_w, w.fmt, w.row, w.cw);
+        if (2 * kb <= 32) {  // keys in 32 bits: half the sort traffic
+            uint32_t *k32 = reinterpret_cast<uint32_t *>(w.keys), *k32_alt = reinterpret_cast<uint32_t *>(w.keys_alt);
+            uint32_t *sk;
+            BGV_LAUNCH(k_csr_keys<uint32_t>, ge, dim3(kFaThreads), 0, s, e2, E, kb, k32, w.vals);
+            BGV_TRY(radix_sort_u32(k32, k32_alt, w.vals, w.vals_alt, 2 * E, 2 * kb, &sk, &sv, w.sort_scratch, s));
+            BGV_LAUNCH(k_csr_fill<uint32_t>, gf, dim3(kFaThreads), 0, s, sk, sv, 2 * E, kb, K, attr_w, w.fmt, w.row,
+                       w.cw);
+        } else {
+            uint64_t *sk;
+            BGV_LAUNCH(k_csr_keys<uint64_t>, ge, dim3(kFaThreads), 0, s, e2, E, kb, w.keys, w.vals);
+            BGV_TRY(radix_sort_u64(w.keys, w.keys_alt, w.vals, w.vals_alt, 2 * E, 2 * kb, &sk, &sv, w.sort_scratch,
+                                   s));
+            BGV_LAUNCH(k_csr_fill<uint64_t>, gf, dim3(kFaThreads), 0, s, sk, sv, 2 * E, kb, K, attr_w, w.fmt, w.row,
+                       w.cw);
+        }
     }
     BGV_LAUNCH(k_att_item_counts, dim3(grid_for((int64_t)K + 1, kFaThreads, 65536)), dim3(kFaThreads), 0, s, w.row,
                K, w.item_of);
@@ -398,12 +411,12 @@ __device__ __forceinline__ uint32_t bh_morton(float2 p, float xmin, float ymin, 
 
 __global__ void __launch_bounds__(kFaThreads) k_bh_codes(int32_t K, const float2 *__restrict__ pos,
                                                           const float4 *__restrict__ part, int nparts,
-                                                          uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                                                          uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
                                                           float *__restrict__ s0_out) {
     float xmin, ymin, s0;
     bh_frame(part, nparts, &xmin, &ymin, &s0, s0_out);
     for (int32_t i = blockIdx.x * kFaThreads + threadIdx.x; i < K; i += gridDim.x * kFaThreads) {
-        keys[i] = (uint64_t)bh_morton(pos[i], xmin, ymin, s0);
+        keys[i] = bh_morton(pos[i], xmin, ymin, s0);
         vals[i] = (uint32_t)i;
     }
 }
@@ -415,7 +428,7 @@ __global__ void __launch_bounds__(kFaThreads) k_bh_codes(int32_t K, const float2
 template <int ITEMS>
 __global__ void __launch_bounds__(kFaThreads) k_bh_codes_count(int32_t K, const float2 *__restrict__ pos,
                                                                 const float4 *__restrict__ part, int nparts,
-                                                                uint64_t *__restrict__ keys,
+                                                                uint32_t *__restrict__ keys,
                                                                 uint32_t *__restrict__ vals,
                                                                 float *__restrict__ s0_out,
                                                                 uint32_t *__restrict__ counts0,
@@ -432,7 +445,7 @@ __global__ void __launch_bounds__(kFaThreads) k_bh_codes_count(int32_t K, const 
         const int64_t i = base + (int64_t)j * kFaThreads + threadIdx.x;
         if (i < K) {
             const uint32_t c = bh_morton(pos[i], xmin, ymin, s0);
-            keys[i] = (uint64_t)c;
+            keys[i] = c;
             vals[i] = (uint32_t)i;
             atomicAdd(&hist[c & 255u], 1u);
         }
@@ -472,12 +485,12 @@ __device__ __forceinline__ void bh_gather_group(int32_t g, int32_t K, const floa
 
 __global__ void __launch_bounds__(kFaThreads) k_bh_gather(int32_t K, const float2 *__restrict__ pos,
                                                            const float *__restrict__ mass,
-                                                           const uint64_t *__restrict__ skeys,
+                                                           const uint32_t *__restrict__ skeys,
                                                            const uint32_t *__restrict__ order,
                                                            float4 *__restrict__ body, uint32_t *__restrict__ code,
                                                            double *__restrict__ part3) {
     const int32_t k = blockIdx.x * kFaThreads + threadIdx.x;
-    bh_gather_group((int32_t)blockIdx.x, K, pos, mass, order, k < K ? (uint32_t)skeys[k] : 0u, body, code, part3);
+    bh_gather_group((int32_t)blockIdx.x, K, pos, mass, order, k < K ? skeys[k] : 0u, body, code, part3);
 }
 
 // Exclusive FP64 prefix sums PM/PX/PY (K+1 entries) of the mass moments in Morton
@@ -864,7 +877,9 @@ static bgv_status bh_forces(int32_t K, const float2 *pos, const float *mass, con
     const unsigned nb = (unsigned)((K + kFaThreads - 1) / kFaThreads);
     // b.bbox holds one box per block of positions (written by k_bh_bbox before the first
     // iteration and by k_update after each one)
-    uint64_t *sk;
+    // 32-bit Morton codes, sorted as 32-bit keys (the index buffers hold them)
+    uint32_t *keys = reinterpret_cast<uint32_t *>(b.keys), *keys_alt = reinterpret_cast<uint32_t *>(b.keys_alt);
+    uint32_t *sk;
     uint32_t *sv;
     int64_t tiles;
     int items;
@@ -873,19 +888,19 @@ static bgv_status bh_forces(int32_t K, const float2 *pos, const float *mass, con
         radix_pass0_buffers(b.sort_scratch, K, &counts0, &clear1);
         if (items == 4)
             BGV_LAUNCH(k_bh_codes_count<4>, dim3((unsigned)tiles), dim3(kFaThreads), 0, s, K, pos, b.bbox, (int)nb,
-                       b.keys, b.vals, b.s0, counts0, clear1, tiles);
+                       keys, b.vals, b.s0, counts0, clear1, tiles);
         else if (items == 16)
             BGV_LAUNCH(k_bh_codes_count<16>, dim3((unsigned)tiles), dim3(kFaThreads), 0, s, K, pos, b.bbox, (int)nb,
-                       b.keys, b.vals, b.s0, counts0, clear1, tiles);
+                       keys, b.vals, b.s0, counts0, clear1, tiles);
         else {
             set_error("bh_forces: unexpected sort tile shape (%d keys per thread)", items);
             return BGV_E_INVALID;
         }
-        BGV_TRY(radix_sort_u64(b.keys, b.keys_alt, b.vals, b.vals_alt, K, 32, &sk, &sv, b.sort_scratch, s, true));
+        BGV_TRY(radix_sort_u32(keys, keys_alt, b.vals, b.vals_alt, K, 32, &sk, &sv, b.sort_scratch, s, true));
     } else {
         BGV_LAUNCH(k_bh_codes, dim3(grid_for(K, kFaThreads, 4096)), dim3(kFaThreads), 0, s, K, pos, b.bbox,
-                   (int)nb, b.keys, b.vals, b.s0);
-        BGV_TRY(radix_sort_u64(b.keys, b.keys_alt, b.vals, b.vals_alt, K, 32, &sk, &sv, b.sort_scratch, s));
+                   (int)nb, keys, b.vals, b.s0);
+        BGV_TRY(radix_sort_u32(keys, keys_alt, b.vals, b.vals_alt, K, 32, &sk, &sv, b.sort_scratch, s));
     }
     BGV_LAUNCH(k_bh_gather, dim3(nb), dim3(kFaThreads), 0, s, K, pos, mass, sk, sv, b.body, b.code, b.part3);
     BGV_LAUNCH(k_bh_prefix, dim3(nb), dim3(kFaThreads), 0, s, K, b.body, b.part3, b.PM, b.PX, b.PY);

@@ -133,8 +133,8 @@ static int64_t rs_items(int64_t n) { return n <= kRsSmallN ? kRsItemsSmall : kRs
 
 // Per-tile digit counts (counts[digit * nb + tile]).  `zero` (or null): a 256 x nb count
 // buffer this launch clears for the next pass.
-template <int ITEMS>
-__global__ void __launch_bounds__(kRsThreads) k_rs_upsweep(const uint64_t *keys, int64_t n, int shift,
+template <int ITEMS, typename KT>
+__global__ void __launch_bounds__(kRsThreads) k_rs_upsweep(const KT *keys, int64_t n, int shift,
                                                             uint32_t *counts, int64_t nb, uint32_t *zero) {
     __shared__ uint32_t hist[256];
     hist[threadIdx.x] = 0;
@@ -161,8 +161,8 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_upsweep(const uint64_t *keys,
 // every key it writes into next[digit * nb + destination tile] (integer atomics, so the
 // counts do not depend on timing), which replaces the next pass's counting launch;
 // `zero` (or null) is a count buffer it clears for the pass after that.
-template <int ITEMS>
-__global__ void __launch_bounds__(kRsThreads) k_rs_downsweep(const uint64_t *keys, uint64_t *keys_out,
+template <int ITEMS, typename KT>
+__global__ void __launch_bounds__(kRsThreads) k_rs_downsweep(const KT *keys, KT *keys_out,
                                                               const uint32_t *vals, uint32_t *vals_out,
                                                               int64_t n, int shift, const uint32_t *offsets,
                                                               int64_t nb, int raw_counts, uint32_t *next,
@@ -171,7 +171,7 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_downsweep(const uint64_t *key
     __shared__ uint32_t running[256];  // where each digit of this tile starts in the output
     __shared__ uint32_t lstart[256];   // where each digit starts inside the tile
     __shared__ uint32_t hist[kRsWaves][256];
-    __shared__ uint64_t skey[kTile];
+    __shared__ KT skey[kTile];
     __shared__ uint32_t sval[kTile];
     const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
     if (raw_counts) {
@@ -202,12 +202,12 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_downsweep(const uint64_t *key
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int64_t base = (int64_t)blockIdx.x * kTile;
     const int64_t wbase = base + (int64_t)w * (kWave * ITEMS);
-    uint64_t key[ITEMS];
+    KT key[ITEMS];
     uint32_t val[ITEMS], rk[ITEMS];
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         const int64_t i = wbase + (int64_t)j * kWave + lane;
-        key[j] = i < n ? keys[i] : 0ull;
+        key[j] = i < n ? keys[i] : KT(0);
         val[j] = (i < n && vals) ? vals[i] : 0u;
     }
 #pragma unroll
@@ -253,7 +253,7 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_downsweep(const uint64_t *key
     __syncthreads();
     const int cnt = (int)((n - base) < kTile ? (n - base) : kTile);
     for (int p = t; p < cnt; p += kRsThreads) {
-        const uint64_t k = skey[p];
+        const KT k = skey[p];
         const uint32_t d = (uint32_t)(k >> shift) & 255u;
         const uint32_t dst = running[d] + ((uint32_t)p - lstart[d]);
         keys_out[dst] = k;
@@ -305,16 +305,21 @@ void radix_pass0_buffers(void *scratch, int64_t n, uint32_t **counts0, uint32_t 
     *clear1 = cb + 256 * kRsLocalOffsetTiles;
 }
 
-bgv_status radix_sort_u64(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, uint32_t *vals_alt,
-                          int64_t n, int nbits, uint64_t **keys_out, uint32_t **vals_out,
-                          void *scratch, hipStream_t s, bool counted) {
-    uint64_t *src = keys, *dst = keys_alt;
+template <typename KT>
+static bgv_status radix_sort(KT *keys, KT *keys_alt, uint32_t *vals, uint32_t *vals_alt, int64_t n, int nbits,
+                             KT **keys_out, uint32_t **vals_out, void *scratch, hipStream_t s, bool counted) {
+    // one name per kernel shape for the profiler (the key width is not part of it)
+    const auto k_rs_upsweep_small = k_rs_upsweep<kRsItemsSmall, KT>;
+    const auto k_rs_upsweep_large = k_rs_upsweep<kRsItemsLarge, KT>;
+    const auto k_rs_downsweep_small = k_rs_downsweep<kRsItemsSmall, KT>;
+    const auto k_rs_downsweep_large = k_rs_downsweep<kRsItemsLarge, KT>;
+    KT *src = keys, *dst = keys_alt;
     uint32_t *vsrc = vals, *vdst = vals_alt;
     if (counted) {
         int64_t t;
         int it;
         if (!radix_few_tiles(n, &t, &it)) {
-            set_error("radix_sort_u64: pass-0 counts given for a sort that is not on the few-tile path");
+            set_error("radix sort: pass-0 counts given for a sort that is not on the few-tile path");
             return BGV_E_INVALID;
         }
     }
@@ -337,33 +342,33 @@ bgv_status radix_sort_u64(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, ui
             if (counted) {
                 // the caller counted pass 0 into buf[0] and cleared buf[1]
             } else if (small)
-                BGV_LAUNCH(k_rs_upsweep<kRsItemsSmall>, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, n, 0,
+                BGV_LAUNCH(k_rs_upsweep_small, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, n, 0,
                            buf[0], nb, zero1);
             else
-                BGV_LAUNCH(k_rs_upsweep<kRsItemsLarge>, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, n, 0,
+                BGV_LAUNCH(k_rs_upsweep_large, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, n, 0,
                            buf[0], nb, zero1);
             for (int pass = 0; pass < npass; ++pass) {
                 const int shift = 8 * pass;
                 uint32_t *next = pass + 1 < npass ? buf[(pass + 1) % 3] : nullptr;
                 uint32_t *zero = pass + 2 < npass ? buf[(pass + 2) % 3] : nullptr;
                 if (small)
-                    BGV_LAUNCH(k_rs_downsweep<kRsItemsSmall>, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, dst,
+                    BGV_LAUNCH(k_rs_downsweep_small, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, dst,
                                vsrc, vdst, n, shift, buf[pass % 3], nb, 1, next, shift + 8, zero);
                 else
-                    BGV_LAUNCH(k_rs_downsweep<kRsItemsLarge>, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, dst,
+                    BGV_LAUNCH(k_rs_downsweep_large, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, dst,
                                vsrc, vdst, n, shift, buf[pass % 3], nb, 1, next, shift + 8, zero);
-                uint64_t *tk = src; src = dst; dst = tk;
+                KT *tk = src; src = dst; dst = tk;
                 uint32_t *tv = vsrc; vsrc = vdst; vdst = tv;
             }
         } else {
             for (int pass = 0; pass < npass; ++pass) {
                 const int shift = 8 * pass;
-                BGV_LAUNCH(k_rs_upsweep<kRsItemsLarge>, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, n, shift,
+                BGV_LAUNCH(k_rs_upsweep_large, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, n, shift,
                            counts, nb, (uint32_t *)nullptr);
                 BGV_TRY(exclusive_scan_u32(counts, counts, 256 * nb, nullptr, scan_scratch, s));
-                BGV_LAUNCH(k_rs_downsweep<kRsItemsLarge>, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, dst, vsrc,
+                BGV_LAUNCH(k_rs_downsweep_large, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, dst, vsrc,
                            vdst, n, shift, counts, nb, 0, (uint32_t *)nullptr, 0, (uint32_t *)nullptr);
-                uint64_t *tk = src; src = dst; dst = tk;
+                KT *tk = src; src = dst; dst = tk;
                 uint32_t *tv = vsrc; vsrc = vdst; vdst = tv;
             }
         }
@@ -371,6 +376,22 @@ bgv_status radix_sort_u64(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, ui
     *keys_out = src;
     if (vals_out) *vals_out = vsrc;
     return BGV_OK;
+}
+
+bgv_status radix_sort_u64(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, uint32_t *vals_alt, int64_t n,
+                          int nbits, uint64_t **keys_out, uint32_t **vals_out, void *scratch, hipStream_t s,
+                          bool counted) {
+    return radix_sort<uint64_t>(keys, keys_alt, vals, vals_alt, n, nbits, keys_out, vals_out, scratch, s, counted);
+}
+
+bgv_status radix_sort_u32(uint32_t *keys, uint32_t *keys_alt, uint32_t *vals, uint32_t *vals_alt, int64_t n,
+                          int nbits, uint32_t **keys_out, uint32_t **vals_out, void *scratch, hipStream_t s,
+                          bool counted) {
+    if (nbits > 32) {
+        set_error("radix_sort_u32: %d key bits", nbits);
+        return BGV_E_INVALID;
+    }
+    return radix_sort<uint32_t>(keys, keys_alt, vals, vals_alt, n, nbits, keys_out, vals_out, scratch, s, counted);
 }
 
 }  // namespace bgv

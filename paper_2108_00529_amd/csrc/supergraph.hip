@@ -95,13 +95,14 @@ constexpr int kKeyItems = 16;  // edges per thread; a block compacts kSgThreads*
 // nsid[v] = sid of node v's community: an edge is inter-community iff its endpoints'
 // sids differ, and since sids ascend with labels, (min, max) of the two sids is
 // (sid of the smaller label, sid of the larger).
+template <typename KT>  // 32-bit keys when 2 * kbits <= 32
 __global__ void __launch_bounds__(kSgThreads) k_sg_edge_keys(const int2 *__restrict__ edges, int64_t m,
                                                               const uint32_t *__restrict__ nsid, int kbits,
-                                                              uint64_t *__restrict__ keys,
+                                                              KT *__restrict__ keys,
                                                               unsigned long long *__restrict__ nkeys) {
     __shared__ unsigned long long s_base;
     const int64_t tile = (int64_t)blockIdx.x * (kSgThreads * kKeyItems);
-    uint64_t k[kKeyItems];
+    KT k[kKeyItems];
     uint32_t flags = 0, cnt = 0;
 #pragma unroll
     for (int j = 0; j < kKeyItems; ++j) {
@@ -112,7 +113,7 @@ __global__ void __launch_bounds__(kSgThreads) k_sg_edge_keys(const int2 *__restr
             if (e.x != e.y) {
                 const uint32_t a = nsid[e.x], b = nsid[e.y];
                 if (a != b) {
-                    k[j] = ((uint64_t)min(a, b) << kbits) | (uint64_t)max(a, b);
+                    k[j] = ((KT)min(a, b) << kbits) | (KT)max(a, b);
                     flags |= 1u << j;
                     ++cnt;
                 }
@@ -143,30 +144,32 @@ constexpr int kUqWaves = kSgThreads / kWave;
 // tile * kUqTile + w * 64 * kUqItems, with the run-start flag of each (its key differs
 // from the one before it: the lane below, the last lane of the previous round, or for
 // the wavefront's first key the key before it in memory).
-__device__ __forceinline__ void uq_load(const uint64_t *__restrict__ keys, int64_t nk, int64_t wbase, int lane,
-                                        uint64_t *k, bool *start) {
-    uint64_t before = (lane == 0 && wbase > 0 && wbase - 1 < nk) ? keys[wbase - 1] : 0ull;
+template <typename KT>
+__device__ __forceinline__ void uq_load(const KT *__restrict__ keys, int64_t nk, int64_t wbase, int lane, KT *k,
+                                        bool *start) {
+    KT before = (lane == 0 && wbase > 0 && wbase - 1 < nk) ? keys[wbase - 1] : KT(0);
 #pragma unroll
     for (int u = 0; u < kUqItems; ++u) {
         const int64_t i = wbase + (int64_t)u * kWave + lane;
-        k[u] = i < nk ? keys[i] : 0ull;
+        k[u] = i < nk ? keys[i] : KT(0);
     }
 #pragma unroll
     for (int u = 0; u < kUqItems; ++u) {
         const int64_t i = wbase + (int64_t)u * kWave + lane;
-        uint64_t prev = __shfl_up(k[u], 1, kWave);
-        const uint64_t last_prev_round = __shfl(u > 0 ? k[u > 0 ? u - 1 : 0] : before, kWave - 1, kWave);
+        KT prev = __shfl_up(k[u], 1, kWave);
+        const KT last_prev_round = __shfl(u > 0 ? k[u > 0 ? u - 1 : 0] : before, kWave - 1, kWave);
         if (lane == 0) prev = u > 0 ? last_prev_round : before;
         start[u] = i < nk && (i == 0 || k[u] != prev);
     }
 }
 
-__global__ void __launch_bounds__(kSgThreads) k_sg_unique_count(const uint64_t *__restrict__ keys, int64_t nk,
+template <typename KT>
+__global__ void __launch_bounds__(kSgThreads) k_sg_unique_count(const KT *__restrict__ keys, int64_t nk,
                                                                  uint32_t *__restrict__ tile_count) {
     __shared__ uint32_t ws[kUqWaves];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int64_t wbase = (int64_t)blockIdx.x * kUqTile + (int64_t)w * (kWave * kUqItems);
-    uint64_t k[kUqItems];
+    KT k[kUqItems];
     bool start[kUqItems];
     uq_load(keys, nk, wbase, lane, k, start);
     uint32_t c = 0;
@@ -181,14 +184,15 @@ __global__ void __launch_bounds__(kSgThreads) k_sg_unique_count(const uint64_t *
     }
 }
 
-__global__ void __launch_bounds__(kSgThreads) k_sg_unique_write(const uint64_t *__restrict__ keys, int64_t nk,
+template <typename KT>
+__global__ void __launch_bounds__(kSgThreads) k_sg_unique_write(const KT *__restrict__ keys, int64_t nk,
                                                                  const uint32_t *__restrict__ tile_first, int kbits,
                                                                  int32_t *__restrict__ superedges,
                                                                  uint32_t *__restrict__ run_start) {
     __shared__ uint32_t ws[kUqWaves];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int64_t wbase = (int64_t)blockIdx.x * kUqTile + (int64_t)w * (kWave * kUqItems);
-    uint64_t k[kUqItems];
+    KT k[kUqItems];
     bool start[kUqItems];
     uq_load(keys, nk, wbase, lane, k, start);
     uint32_t c = 0;
@@ -205,8 +209,8 @@ __global__ void __launch_bounds__(kSgThreads) k_sg_unique_write(const uint64_t *
         const uint64_t m = __ballot(start[u]);
         if (start[u]) {
             const uint32_t at = j + (uint32_t)__popcll(m & lt);
-            superedges[2 * (int64_t)at] = (int32_t)(k[u] >> kbits);
-            superedges[2 * (int64_t)at + 1] = (int32_t)(k[u] & lowmask);
+            superedges[2 * (int64_t)at] = (int32_t)((uint64_t)k[u] >> kbits);
+            superedges[2 * (int64_t)at + 1] = (int32_t)((uint64_t)k[u] & lowmask);
             run_start[at] = (uint32_t)(wbase + (int64_t)u * kWave + lane);
         }
         j += (uint32_t)__popcll(m);
@@ -513,9 +517,14 @@ extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges,
 
     // inter-community keys, sorted and made unique, then sketch 2 and the weights
     unsigned long long *nkeys_d = reinterpret_cast<unsigned long long *>(&w.counters[2]);
+    const bool k32 = 2 * kbits <= 32;  // keys in 32 bits: half the sort traffic
+    uint32_t *keys32 = reinterpret_cast<uint32_t *>(w.keys), *keys32_alt = reinterpret_cast<uint32_t *>(w.keys_alt);
     if (m > 0) {
-        BGV_LAUNCH(k_sg_edge_keys, dim3((unsigned)((m + kSgThreads * kKeyItems - 1) / (kSgThreads * kKeyItems))), dim3(kSgThreads), 0, s, e2, m,
-                   w.nsid, kbits, w.keys, nkeys_d);
+        const dim3 gkey((unsigned)((m + kSgThreads * kKeyItems - 1) / (kSgThreads * kKeyItems)));
+        if (k32)
+            BGV_LAUNCH(k_sg_edge_keys<uint32_t>, gkey, dim3(kSgThreads), 0, s, e2, m, w.nsid, kbits, keys32, nkeys_d);
+        else
+            BGV_LAUNCH(k_sg_edge_keys<uint64_t>, gkey, dim3(kSgThreads), 0, s, e2, m, w.nsid, kbits, w.keys, nkeys_d);
     }
     unsigned long long *nk_host = reinterpret_cast<unsigned long long *>(rb->host + 2);
     BGV_CHECK_HIP(hipMemcpyAsync(nk_host, nkeys_d, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
@@ -525,15 +534,27 @@ extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges,
     int64_t E = 0;
     if (nk == 0 && grouped_sketch) BGV_TRY(fill<uint32_t>(M2, 0u, cells, s));
     if (nk > 0) {
-        uint64_t *sorted;
-        BGV_TRY(radix_sort_u64(w.keys, w.keys_alt, nullptr, nullptr, (int64_t)nk, 2 * kbits, &sorted, nullptr,
-                               w.sort_scratch, s));
+        uint64_t *sorted = nullptr;
+        uint32_t *sorted32 = nullptr;
+        if (k32)
+            BGV_TRY(radix_sort_u32(keys32, keys32_alt, nullptr, nullptr, (int64_t)nk, 2 * kbits, &sorted32, nullptr,
+                                   w.sort_scratch, s));
+        else
+            BGV_TRY(radix_sort_u64(w.keys, w.keys_alt, nullptr, nullptr, (int64_t)nk, 2 * kbits, &sorted, nullptr,
+                                   w.sort_scratch, s));
         const unsigned gk = grid_for((int64_t)nk, kSgThreads, 65536);
         const unsigned ut = (unsigned)(((int64_t)nk + kUqTile - 1) / kUqTile);
-        BGV_LAUNCH(k_sg_unique_count, dim3(ut), dim3(kSgThreads), 0, s, sorted, (int64_t)nk, w.utile);
+        if (k32)
+            BGV_LAUNCH(k_sg_unique_count<uint32_t>, dim3(ut), dim3(kSgThreads), 0, s, sorted32, (int64_t)nk, w.utile);
+        else
+            BGV_LAUNCH(k_sg_unique_count<uint64_t>, dim3(ut), dim3(kSgThreads), 0, s, sorted, (int64_t)nk, w.utile);
         BGV_TRY(exclusive_scan_u32(w.utile, w.utile, (int64_t)ut, &w.counters[1], w.scan_scratch, s));
-        BGV_LAUNCH(k_sg_unique_write, dim3(ut), dim3(kSgThreads), 0, s, sorted, (int64_t)nk, w.utile, kbits,
-                   superedges, w.run_start);
+        if (k32)
+            BGV_LAUNCH(k_sg_unique_write<uint32_t>, dim3(ut), dim3(kSgThreads), 0, s, sorted32, (int64_t)nk, w.utile,
+                       kbits, superedges, w.run_start);
+        else
+            BGV_LAUNCH(k_sg_unique_write<uint64_t>, dim3(ut), dim3(kSgThreads), 0, s, sorted, (int64_t)nk, w.utile,
+                       kbits, superedges, w.run_start);
         if (grouped_sketch) {
             const int32_t nb = (int32_t)sk_buckets(cells);
             BGV_LAUNCH(k_sg_group_pairs, dim3((unsigned)((nk + kSkTile - 1) / kSkTile)), dim3(kSgThreads), 0, s,
