@@ -109,10 +109,11 @@ def test_community_bucket_boundaries(bgv):
         check_community(bgv, n, e, 6, P, 2, B)
 
 
-def test_community_above_bucket_limit(bgv):
-    """More than 4096 buckets of 4096 nodes: the per-node atomic form."""
+@pytest.mark.parametrize("n", [1 << 24, (1 << 24) + 4099])
+def test_community_at_and_above_bucket_limit(bgv, n):
+    """4096 buckets of 4096 nodes (the most the grouped form takes), and more: the
+    per-node atomic form."""
     rng = np.random.default_rng(29)
-    n = (1 << 24) + 4099
     m = 40_000
     ids = np.concatenate([rng.integers(0, 5000, 3000), rng.integers(n - 5000, n, 3000)])
     e = ids[rng.integers(0, len(ids), (m, 2))].astype(np.int32)
@@ -178,6 +179,22 @@ def test_supergraph_tiny_random(bgv):
         lab, cnt = oracle.bs_community(n, e, 5, 2, 2, 7)
         deg, _ = oracle.degree_volume(lab, cnt, 2)
         check_supergraph(bgv, n, e, lab, deg, int(rng.integers(1, 9)), int(rng.integers(1, 5000)), 100 + trial)
+
+
+@pytest.mark.parametrize("K", [65536, 65537])
+def test_supergraph_key_width_boundary(bgv, K):
+    """Every node its own community: K = 65,536 supernodes packs a superedge key into 32
+    bits (16 + 16), one more needs 34 and takes the 64-bit sort; a sketch of many
+    buckets (5 x 2^20 cells) and a small one (2 x 3000)."""
+    rng = np.random.default_rng(K)
+    m = 200_000
+    e = rng.integers(0, K, (m, 2)).astype(np.int32)
+    e[:50] = [K - 1, 0]  # the largest and smallest sids, repeated
+    lab = np.arange(K, dtype=np.int32)
+    deg = np.bincount(e[e[:, 0] != e[:, 1]].ravel(), minlength=K).astype(np.int32)
+    for rows, cols in ((5, 1 << 20), (2, 3000)):
+        sg, ref = check_supergraph(bgv, K, e, lab, deg, rows, cols, 7)
+        assert ref["K"] == K
 
 
 # ---------------------------------------------------------------- ForceAtlas2 ----
