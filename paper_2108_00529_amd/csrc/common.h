@@ -126,15 +126,19 @@ bgv_status exclusive_scan(const T *in, T *out, int64_t n, T *total, void *scratc
 
 // Stable LSD radix sort of keys below 2^nbits, with an optional uint32 payload.
 // keys/alt (and vals/vals_alt) are ping-pong buffers of n entries; the sorted result
-// ends in *keys_out/*vals_out (one of the two).  Scratch from radix_workspace(n).
+// ends in *keys_out/*vals_out (one of the two).  Scratch from radix_workspace(n).  With
+// n_dev the key count is read on the device (*n_dev <= n) and n is only its bound, so
+// the sort can be queued before the count is known on the host.
 size_t radix_workspace(int64_t n);
 bgv_status radix_sort_u64(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, uint32_t *vals_alt,
                           int64_t n, int nbits, uint64_t **keys_out, uint32_t **vals_out,
-                          void *scratch, hipStream_t s, bool counted = false);
+                          void *scratch, hipStream_t s, bool counted = false,
+                          const unsigned long long *n_dev = nullptr);
 // The same for keys below 2^nbits <= 2^32 held in 32 bits (half the traffic per pass).
 bgv_status radix_sort_u32(uint32_t *keys, uint32_t *keys_alt, uint32_t *vals, uint32_t *vals_alt,
                           int64_t n, int nbits, uint32_t **keys_out, uint32_t **vals_out,
-                          void *scratch, hipStream_t s, bool counted = false);
+                          void *scratch, hipStream_t s, bool counted = false,
+                          const unsigned long long *n_dev = nullptr);
 
 // Sorts of at most kRsFewTiles tiles (n > 1) count pass 0's digits in one launch ahead
 // of the scatters.  A producer of the keys can do that count itself: for such an n,

@@ -132,10 +132,13 @@ constexpr int64_t kRsSmallN = (int64_t)kRsLocalOffsetTiles * kRsThreads * kRsIte
 static int64_t rs_items(int64_t n) { return n <= kRsSmallN ? kRsItemsSmall : kRsItemsLarge; }
 
 // Per-tile digit counts (counts[digit * nb + tile]).  `zero` (or null): a 256 x nb count
-// buffer this launch clears for the next pass.
+// buffer this launch clears for the next pass.  With n_dev the key count is *n_dev and n
+// only bounds it (the grid covers n).
 template <int ITEMS, typename KT>
 __global__ void __launch_bounds__(kRsThreads) k_rs_upsweep(const KT *keys, int64_t n, int shift,
-                                                            uint32_t *counts, int64_t nb, uint32_t *zero) {
+                                                            uint32_t *counts, int64_t nb, uint32_t *zero,
+                                                            const unsigned long long *n_dev) {
+    if (n_dev) n = (int64_t)*n_dev;
     __shared__ uint32_t hist[256];
     hist[threadIdx.x] = 0;
     if (zero) zero[(int64_t)blockIdx.x * 256 + threadIdx.x] = 0u;
@@ -166,7 +169,9 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_downsweep(const KT *keys, KT 
                                                               const uint32_t *vals, uint32_t *vals_out,
                                                               int64_t n, int shift, const uint32_t *offsets,
                                                               int64_t nb, int raw_counts, uint32_t *next,
-                                                              int next_shift, uint32_t *zero) {
+                                                              int next_shift, uint32_t *zero,
+                                                              const unsigned long long *n_dev) {
+    if (n_dev) n = (int64_t)*n_dev;  // n bounds it
     constexpr int kTile = kRsThreads * ITEMS;
     __shared__ uint32_t running[256];  // where each digit of this tile starts in the output
     __shared__ uint32_t lstart[256];   // where each digit starts inside the tile
@@ -307,7 +312,8 @@ void radix_pass0_buffers(void *scratch, int64_t n, uint32_t **counts0, uint32_t 
 
 template <typename KT>
 static bgv_status radix_sort(KT *keys, KT *keys_alt, uint32_t *vals, uint32_t *vals_alt, int64_t n, int nbits,
-                             KT **keys_out, uint32_t **vals_out, void *scratch, hipStream_t s, bool counted) {
+                             KT **keys_out, uint32_t **vals_out, void *scratch, hipStream_t s, bool counted,
+                             const unsigned long long *n_dev) {
     // one name per kernel shape for the profiler (the key width is not part of it)
     const auto k_rs_upsweep_small = k_rs_upsweep<kRsItemsSmall, KT>;
     const auto k_rs_upsweep_large = k_rs_upsweep<kRsItemsLarge, KT>;
@@ -343,20 +349,20 @@ static bgv_status radix_sort(KT *keys, KT *keys_alt, uint32_t *vals, uint32_t *v
                 // the caller counted pass 0 into buf[0] and cleared buf[1]
             } else if (small)
                 BGV_LAUNCH(k_rs_upsweep_small, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, n, 0,
-                           buf[0], nb, zero1);
+                           buf[0], nb, zero1, n_dev);
             else
                 BGV_LAUNCH(k_rs_upsweep_large, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, n, 0,
-                           buf[0], nb, zero1);
+                           buf[0], nb, zero1, n_dev);
             for (int pass = 0; pass < npass; ++pass) {
                 const int shift = 8 * pass;
                 uint32_t *next = pass + 1 < npass ? buf[(pass + 1) % 3] : nullptr;
                 uint32_t *zero = pass + 2 < npass ? buf[(pass + 2) % 3] : nullptr;
                 if (small)
                     BGV_LAUNCH(k_rs_downsweep_small, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, dst,
-                               vsrc, vdst, n, shift, buf[pass % 3], nb, 1, next, shift + 8, zero);
+                               vsrc, vdst, n, shift, buf[pass % 3], nb, 1, next, shift + 8, zero, n_dev);
                 else
                     BGV_LAUNCH(k_rs_downsweep_large, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, dst,
-                               vsrc, vdst, n, shift, buf[pass % 3], nb, 1, next, shift + 8, zero);
+                               vsrc, vdst, n, shift, buf[pass % 3], nb, 1, next, shift + 8, zero, n_dev);
                 KT *tk = src; src = dst; dst = tk;
                 uint32_t *tv = vsrc; vsrc = vdst; vdst = tv;
             }
@@ -364,10 +370,10 @@ static bgv_status radix_sort(KT *keys, KT *keys_alt, uint32_t *vals, uint32_t *v
             for (int pass = 0; pass < npass; ++pass) {
                 const int shift = 8 * pass;
                 BGV_LAUNCH(k_rs_upsweep_large, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, n, shift,
-                           counts, nb, (uint32_t *)nullptr);
+                           counts, nb, (uint32_t *)nullptr, n_dev);
                 BGV_TRY(exclusive_scan_u32(counts, counts, 256 * nb, nullptr, scan_scratch, s));
                 BGV_LAUNCH(k_rs_downsweep_large, dim3((unsigned)nb), dim3(kRsThreads), 0, s, src, dst, vsrc,
-                           vdst, n, shift, counts, nb, 0, (uint32_t *)nullptr, 0, (uint32_t *)nullptr);
+                           vdst, n, shift, counts, nb, 0, (uint32_t *)nullptr, 0, (uint32_t *)nullptr, n_dev);
                 KT *tk = src; src = dst; dst = tk;
                 uint32_t *tv = vsrc; vsrc = vdst; vdst = tv;
             }
@@ -380,18 +386,20 @@ static bgv_status radix_sort(KT *keys, KT *keys_alt, uint32_t *vals, uint32_t *v
 
 bgv_status radix_sort_u64(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, uint32_t *vals_alt, int64_t n,
                           int nbits, uint64_t **keys_out, uint32_t **vals_out, void *scratch, hipStream_t s,
-                          bool counted) {
-    return radix_sort<uint64_t>(keys, keys_alt, vals, vals_alt, n, nbits, keys_out, vals_out, scratch, s, counted);
+                          bool counted, const unsigned long long *n_dev) {
+    return radix_sort<uint64_t>(keys, keys_alt, vals, vals_alt, n, nbits, keys_out, vals_out, scratch, s, counted,
+                                n_dev);
 }
 
 bgv_status radix_sort_u32(uint32_t *keys, uint32_t *keys_alt, uint32_t *vals, uint32_t *vals_alt, int64_t n,
                           int nbits, uint32_t **keys_out, uint32_t **vals_out, void *scratch, hipStream_t s,
-                          bool counted) {
+                          bool counted, const unsigned long long *n_dev) {
     if (nbits > 32) {
         set_error("radix_sort_u32: %d key bits", nbits);
         return BGV_E_INVALID;
     }
-    return radix_sort<uint32_t>(keys, keys_alt, vals, vals_alt, n, nbits, keys_out, vals_out, scratch, s, counted);
+    return radix_sort<uint32_t>(keys, keys_alt, vals, vals_alt, n, nbits, keys_out, vals_out, scratch, s, counted,
+                                n_dev);
 }
 
 }  // namespace bgv

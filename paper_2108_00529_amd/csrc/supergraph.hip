@@ -164,8 +164,10 @@ __device__ __forceinline__ void uq_load(const KT *__restrict__ keys, int64_t nk,
 }
 
 template <typename KT>
-__global__ void __launch_bounds__(kSgThreads) k_sg_unique_count(const KT *__restrict__ keys, int64_t nk,
+__global__ void __launch_bounds__(kSgThreads) k_sg_unique_count(const KT *__restrict__ keys,
+                                                                 const unsigned long long *__restrict__ nkp,
                                                                  uint32_t *__restrict__ tile_count) {
+    const int64_t nk = (int64_t)*nkp;  // the grid covers a bound of it
     __shared__ uint32_t ws[kUqWaves];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int64_t wbase = (int64_t)blockIdx.x * kUqTile + (int64_t)w * (kWave * kUqItems);
@@ -185,10 +187,12 @@ __global__ void __launch_bounds__(kSgThreads) k_sg_unique_count(const KT *__rest
 }
 
 template <typename KT>
-__global__ void __launch_bounds__(kSgThreads) k_sg_unique_write(const KT *__restrict__ keys, int64_t nk,
+__global__ void __launch_bounds__(kSgThreads) k_sg_unique_write(const KT *__restrict__ keys,
+                                                                 const unsigned long long *__restrict__ nkp,
                                                                  const uint32_t *__restrict__ tile_first, int kbits,
                                                                  int32_t *__restrict__ superedges,
                                                                  uint32_t *__restrict__ run_start) {
+    const int64_t nk = (int64_t)*nkp;  // the grid covers a bound of it
     __shared__ uint32_t ws[kUqWaves];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int64_t wbase = (int64_t)blockIdx.x * kUqTile + (int64_t)w * (kWave * kUqItems);
@@ -219,10 +223,12 @@ __global__ void __launch_bounds__(kSgThreads) k_sg_unique_write(const KT *__rest
 
 // Sketch 2: each distinct key adds its multiplicity (run length) at g_r(key).
 __global__ void k_sg_sketch_pairs(const int32_t *__restrict__ superedges, const uint32_t *__restrict__ run_start,
-                                  const uint32_t *__restrict__ Ep, uint32_t nk, const int32_t *__restrict__ super_label,
+                                  const uint32_t *__restrict__ Ep, const unsigned long long *__restrict__ nkp,
+                                  const int32_t *__restrict__ super_label,
                                   HashRows h, int32_t rows, uint32_t cols, uint32_t *__restrict__ M2,
                                   uint32_t *__restrict__ se_count) {
     const int64_t E = *Ep;
+    const uint32_t nk = (uint32_t)*nkp;
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < E; j += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t cnt = (j + 1 < E ? run_start[j + 1] : nk) - run_start[j];
         const uint32_t la = (uint32_t)super_label[superedges[2 * j]];
@@ -250,7 +256,8 @@ inline int64_t sk_buckets(int64_t cells) { return (cells + kSkBucket - 1) / kSkB
 
 __global__ void __launch_bounds__(kSgThreads) k_sg_group_pairs(const int32_t *__restrict__ superedges,
                                                                 const uint32_t *__restrict__ run_start,
-                                                                const uint32_t *__restrict__ Ep, uint32_t nk,
+                                                                const uint32_t *__restrict__ Ep,
+                                                                const unsigned long long *__restrict__ nkp,
                                                                 const int32_t *__restrict__ super_label, HashRows h,
                                                                 int32_t rows, uint32_t cols, int32_t nb,
                                                                 uint2 *__restrict__ ent, uint32_t *__restrict__ etab,
@@ -258,8 +265,9 @@ __global__ void __launch_bounds__(kSgThreads) k_sg_group_pairs(const int32_t *__
     __shared__ uint32_t hist[kSkMaxBuckets];
     __shared__ uint2 stage[kSkTile * kMaxRows];
     const int64_t E = *Ep;
+    const uint32_t nk = (uint32_t)*nkp;
     const int64_t j0 = (int64_t)blockIdx.x * kSkTile;
-    if (j0 >= E) return;  // the grid covers the key count, an upper bound of E
+    if (j0 >= E) return;  // the grid covers a bound of E
     for (int32_t b = threadIdx.x; b < nb; b += kSgThreads) hist[b] = 0;
     __syncthreads();
     uint32_t la[kSkItems], lb[kSkItems], cnt[kSkItems], rank[kSkItems][kMaxRows];
@@ -526,46 +534,43 @@ extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges,
         else
             BGV_LAUNCH(k_sg_edge_keys<uint64_t>, gkey, dim3(kSgThreads), 0, s, e2, m, w.nsid, kbits, w.keys, nkeys_d);
     }
-    unsigned long long *nk_host = reinterpret_cast<unsigned long long *>(rb->host + 2);
-    BGV_CHECK_HIP(hipMemcpyAsync(nk_host, nkeys_d, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-    BGV_CHECK_HIP(hipEventRecord(rb->ev, s));
-    BGV_CHECK_HIP(hipEventSynchronize(rb->ev));
-    const unsigned long long nk = *nk_host;
+    // the key count stays on the device: everything below is sized by the edge count m,
+    // which bounds it, and reads the count itself, so no host round trip is needed here
     int64_t E = 0;
-    if (nk == 0 && grouped_sketch) BGV_TRY(fill<uint32_t>(M2, 0u, cells, s));
-    if (nk > 0) {
+    if (m == 0 && grouped_sketch) BGV_TRY(fill<uint32_t>(M2, 0u, cells, s));
+    if (m > 0) {
         uint64_t *sorted = nullptr;
         uint32_t *sorted32 = nullptr;
         if (k32)
-            BGV_TRY(radix_sort_u32(keys32, keys32_alt, nullptr, nullptr, (int64_t)nk, 2 * kbits, &sorted32, nullptr,
-                                   w.sort_scratch, s));
+            BGV_TRY(radix_sort_u32(keys32, keys32_alt, nullptr, nullptr, m, 2 * kbits, &sorted32, nullptr,
+                                   w.sort_scratch, s, false, nkeys_d));
         else
-            BGV_TRY(radix_sort_u64(w.keys, w.keys_alt, nullptr, nullptr, (int64_t)nk, 2 * kbits, &sorted, nullptr,
-                                   w.sort_scratch, s));
-        const unsigned gk = grid_for((int64_t)nk, kSgThreads, 65536);
-        const unsigned ut = (unsigned)(((int64_t)nk + kUqTile - 1) / kUqTile);
+            BGV_TRY(radix_sort_u64(w.keys, w.keys_alt, nullptr, nullptr, m, 2 * kbits, &sorted, nullptr,
+                                   w.sort_scratch, s, false, nkeys_d));
+        const unsigned gk = grid_for(m, kSgThreads, 65536);
+        const unsigned ut = (unsigned)((m + kUqTile - 1) / kUqTile);
         if (k32)
-            BGV_LAUNCH(k_sg_unique_count<uint32_t>, dim3(ut), dim3(kSgThreads), 0, s, sorted32, (int64_t)nk, w.utile);
+            BGV_LAUNCH(k_sg_unique_count<uint32_t>, dim3(ut), dim3(kSgThreads), 0, s, sorted32, nkeys_d, w.utile);
         else
-            BGV_LAUNCH(k_sg_unique_count<uint64_t>, dim3(ut), dim3(kSgThreads), 0, s, sorted, (int64_t)nk, w.utile);
+            BGV_LAUNCH(k_sg_unique_count<uint64_t>, dim3(ut), dim3(kSgThreads), 0, s, sorted, nkeys_d, w.utile);
         BGV_TRY(exclusive_scan_u32(w.utile, w.utile, (int64_t)ut, &w.counters[1], w.scan_scratch, s));
         if (k32)
-            BGV_LAUNCH(k_sg_unique_write<uint32_t>, dim3(ut), dim3(kSgThreads), 0, s, sorted32, (int64_t)nk, w.utile,
+            BGV_LAUNCH(k_sg_unique_write<uint32_t>, dim3(ut), dim3(kSgThreads), 0, s, sorted32, nkeys_d, w.utile,
                        kbits, superedges, w.run_start);
         else
-            BGV_LAUNCH(k_sg_unique_write<uint64_t>, dim3(ut), dim3(kSgThreads), 0, s, sorted, (int64_t)nk, w.utile,
+            BGV_LAUNCH(k_sg_unique_write<uint64_t>, dim3(ut), dim3(kSgThreads), 0, s, sorted, nkeys_d, w.utile,
                        kbits, superedges, w.run_start);
         if (grouped_sketch) {
             const int32_t nb = (int32_t)sk_buckets(cells);
-            BGV_LAUNCH(k_sg_group_pairs, dim3((unsigned)((nk + kSkTile - 1) / kSkTile)), dim3(kSgThreads), 0, s,
-                       superedges, w.run_start, &w.counters[1], (uint32_t)nk, super_label, h2, rows, cols, nb, w.ent,
+            BGV_LAUNCH(k_sg_group_pairs, dim3((unsigned)((m + kSkTile - 1) / kSkTile)), dim3(kSgThreads), 0, s,
+                       superedges, w.run_start, &w.counters[1], nkeys_d, super_label, h2, rows, cols, nb, w.ent,
                        w.etab, se_count);
-            // the tile count is on the device; the key count bounds it
+            // the tile count is on the device; the edge count bounds it
             BGV_LAUNCH(k_sg_sum_cells, dim3(nb), dim3(kSkResolveThreads), 0, s, w.ent, w.etab, &w.counters[1], rows,
-                       nb, cells, sk_sum_lanes(((int64_t)nk + kSkTile - 1) / kSkTile), M2);
+                       nb, cells, sk_sum_lanes((m + kSkTile - 1) / kSkTile), M2);
         } else {
             BGV_LAUNCH(k_sg_sketch_pairs, dim3(gk), dim3(kSgThreads), 0, s, superedges, w.run_start, &w.counters[1],
-                       (uint32_t)nk, super_label, h2, rows, cols, M2, se_count);
+                       nkeys_d, super_label, h2, rows, cols, M2, se_count);
         }
         BGV_LAUNCH(k_sg_pair_weights, dim3(gk), dim3(kSgThreads), 0, s, superedges, &w.counters[1], super_label, h2,
                    rows, cols, M2, se_weight);
