@@ -30,6 +30,115 @@ __global__ void k_sg_flag_volume(const int32_t *__restrict__ labels, const int32
     }
 }
 
+// The same without device atomics (labels below kLbMaxBuckets * kLbBucket): each tile of
+// kLbTile nodes writes (label offset in bucket, degree) entries grouped by 4096-label
+// bucket, one segment per (tile, bucket), offsets in a per-tile row; one workgroup per
+// bucket then sums its segments from every tile in LDS and writes the bucket's flags and
+// volumes, all of them, so neither array needs clearing.  Same integers.
+constexpr int kLbBucketBits = 12;
+constexpr int32_t kLbBucket = 1 << kLbBucketBits;
+constexpr int32_t kLbMaxBuckets = 4096;
+constexpr int kLbItems = 4;
+constexpr int32_t kLbTile = kSgThreads * kLbItems;
+constexpr int kLbResolveThreads = 1024;
+
+inline int32_t lb_buckets(int32_t n) { return (n + kLbBucket - 1) / kLbBucket; }
+
+__global__ void __launch_bounds__(kSgThreads) k_sg_group_nodes(const int32_t *__restrict__ labels,
+                                                                const int32_t *__restrict__ degree, int32_t n,
+                                                                int32_t nb, uint2 *__restrict__ ent,
+                                                                uint32_t *__restrict__ etab) {
+    __shared__ uint32_t hist[kLbMaxBuckets];
+    __shared__ uint2 stage[kLbTile];
+    for (int32_t b = threadIdx.x; b < nb; b += kSgThreads) hist[b] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kLbTile;
+    int32_t lab[kLbItems];
+    uint32_t d[kLbItems], rank[kLbItems];
+#pragma unroll
+    for (int u = 0; u < kLbItems; ++u) {
+        const int64_t v = base + u * kSgThreads + threadIdx.x;
+        lab[u] = -1;
+        if (v < n) {
+            lab[u] = labels[v];
+            d[u] = (uint32_t)degree[v];
+            rank[u] = atomicAdd(&hist[lab[u] >> kLbBucketBits], 1u);
+        }
+    }
+    __syncthreads();
+    uint32_t *row = etab + (int64_t)blockIdx.x * (nb + 1);
+    const int32_t per = (nb + kSgThreads - 1) / kSgThreads;
+    const int32_t b0 = min(nb, (int32_t)threadIdx.x * per), b1 = min(nb, b0 + per);
+    uint32_t sum = 0;
+    for (int32_t b = b0; b < b1; ++b) sum += hist[b];
+    uint32_t total;
+    uint32_t run = block_excl_scan<uint32_t>(sum, &total);
+    for (int32_t b = b0; b < b1; ++b) {
+        const uint32_t c = hist[b];
+        hist[b] = run;
+        row[b] = run;
+        run += c;
+    }
+    if (threadIdx.x == 0) row[nb] = total;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kLbItems; ++u)
+        if (lab[u] >= 0)
+            stage[hist[lab[u] >> kLbBucketBits] + rank[u]] = make_uint2((uint32_t)(lab[u] & (kLbBucket - 1)), d[u]);
+    __syncthreads();
+    uint2 *out = ent + (int64_t)blockIdx.x * kLbTile;
+    for (uint32_t k = threadIdx.x; k < total; k += kSgThreads) out[k] = stage[k];
+}
+
+// One workgroup per label bucket; each tile's segment goes to a group of `lanes`
+// threads (a power of two sized by the tile count).
+__global__ void __launch_bounds__(kLbResolveThreads) k_sg_sum_labels(const uint2 *__restrict__ ent,
+                                                                      const uint32_t *__restrict__ etab, int32_t tiles,
+                                                                      int32_t nb, int32_t n, int32_t lanes,
+                                                                      uint32_t *__restrict__ flag,
+                                                                      uint32_t *__restrict__ vol) {
+    __shared__ uint32_t svol[kLbBucket];
+    __shared__ uint32_t sflag[kLbBucket];
+    const int32_t b = blockIdx.x;
+    for (int32_t k = threadIdx.x; k < kLbBucket; k += kLbResolveThreads) {
+        svol[k] = 0u;
+        sflag[k] = 0u;
+    }
+    __syncthreads();
+    const int32_t groups = kLbResolveThreads / lanes;
+    const uint32_t sub = threadIdx.x % lanes, L = (uint32_t)lanes;
+    for (int32_t t = threadIdx.x / lanes; t < tiles; t += groups) {
+        const uint32_t *row = etab + (int64_t)t * (nb + 1);
+        const uint32_t q0 = row[b], q1 = row[b + 1];
+        const uint2 *seg = ent + (int64_t)t * kLbTile;
+        for (uint32_t q = q0 + sub; q < q1; q += 4 * L) {
+            uint2 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (q + u * L < q1) v[u] = seg[q + u * L];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (q + u * L < q1) {
+                    atomicOr(&sflag[v[u].x], 1u);
+                    if (v[u].y) atomicAdd(&svol[v[u].x], v[u].y);
+                }
+        }
+    }
+    __syncthreads();
+    const int64_t base = (int64_t)b << kLbBucketBits;
+    const int32_t span = (int32_t)min((int64_t)kLbBucket, (int64_t)n - base);
+    for (int32_t k = threadIdx.x; k < span; k += kLbResolveThreads) {
+        flag[base + k] = sflag[k];
+        vol[base + k] = svol[k];
+    }
+}
+
+inline int32_t lb_lanes(int32_t tiles) {
+    int32_t g = 1;
+    while (g < kLbResolveThreads && (int64_t)g * 2 * (tiles > 0 ? tiles : 1) <= kLbResolveThreads) g *= 2;
+    return g;
+}
+
 // flag[] still holds the 0/1 flags; sid[] is its exclusive scan.
 __global__ void k_sg_compact(const uint32_t *__restrict__ flag, const uint32_t *__restrict__ sid, int32_t n,
                              int32_t *__restrict__ super_label) {
@@ -392,6 +501,8 @@ struct SgWs {
     uint64_t *keys, *keys_alt;
     uint2 *ent;       // grouped sketch-2 entries (bucketed sketch only)
     uint32_t *etab;   // their per-tile offset rows
+    uint2 *lent;      // grouped (label, degree) entries (volumes without atomics)
+    uint32_t *ltab;   // their per-tile offset rows
     void *scan_scratch, *sort_scratch;
 };
 
@@ -399,6 +510,8 @@ static size_t sg_layout(Carver &c, int32_t n, int64_t m, int32_t rows, int64_t c
     const int64_t mm = m > 0 ? m : 1;
     w->ent = nullptr;
     w->etab = nullptr;
+    w->lent = nullptr;
+    w->ltab = nullptr;
     w->flag = c.take<uint32_t>((size_t)n);
     w->nsid = c.take<uint32_t>((size_t)n);
     w->sid = c.take<uint32_t>((size_t)n);
@@ -411,6 +524,11 @@ static size_t sg_layout(Carver &c, int32_t n, int64_t m, int32_t rows, int64_t c
     const int64_t big = n > mm ? n : mm;
     w->scan_scratch = c.take<char>(scan_workspace(big));
     w->sort_scratch = c.take<char>(radix_workspace(mm));
+    if (cells > kLdsCounters && lb_buckets(n) <= kLbMaxBuckets) {
+        const size_t tiles = ((size_t)n + kLbTile - 1) / kLbTile;
+        w->lent = c.take<uint2>(tiles * kLbTile);
+        w->ltab = c.take<uint32_t>(tiles * (size_t)(lb_buckets(n) + 1));
+    }
     const int64_t nb = sk_buckets(cells);
     if (nb <= kSkMaxBuckets) {
         // distinct pairs <= m: a tile bound, rows entries per pair
@@ -486,11 +604,20 @@ extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges,
     // filled from the communities' volumes
     const int64_t cells = (int64_t)rows * cols;
     const bool lds_sketch = cells <= kLdsCounters;
-    BGV_TRY(fill<uint32_t>(w.flag, 0u, n, s));
     BGV_TRY(fill<uint32_t>(w.counters, 0u, 8, s));
     if (lds_sketch) {
+        BGV_TRY(fill<uint32_t>(w.flag, 0u, n, s));
         BGV_LAUNCH(k_sg_flag, dim3(gn), dim3(kSgThreads), 0, s, labels, n, w.flag);
+    } else if (w.lent) {
+        // flags and volumes grouped by label bucket, written whole
+        const int32_t lnb = lb_buckets(n);
+        const int32_t ltiles = (int32_t)(((int64_t)n + kLbTile - 1) / kLbTile);
+        BGV_LAUNCH(k_sg_group_nodes, dim3((unsigned)ltiles), dim3(kSgThreads), 0, s, labels, degree, n, lnb, w.lent,
+                   w.ltab);
+        BGV_LAUNCH(k_sg_sum_labels, dim3((unsigned)lnb), dim3(kLbResolveThreads), 0, s, w.lent, w.ltab, ltiles, lnb,
+                   n, lb_lanes(ltiles), w.flag, w.vol);
     } else {
+        BGV_TRY(fill<uint32_t>(w.flag, 0u, n, s));
         BGV_TRY(fill<uint32_t>(w.vol, 0u, n, s));
         BGV_LAUNCH(k_sg_flag_volume, dim3(gn), dim3(kSgThreads), 0, s, labels, degree, n, w.flag, w.vol);
     }
