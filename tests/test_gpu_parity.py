@@ -181,6 +181,23 @@ def test_supergraph_tiny_random(bgv):
         check_supergraph(bgv, n, e, lab, deg, int(rng.integers(1, 9)), int(rng.integers(1, 5000)), 100 + trial)
 
 
+def test_supergraph_degenerate_streams(bgv):
+    """One inter-community edge, one self-loop, only intra-community edges, and a single
+    node: the key count (kept on the device) is 1 or 0 while the sort and the pair
+    kernels are sized by the edge count."""
+    cases = [
+        (2, np.array([[0, 1]], np.int32), np.array([0, 1], np.int32)),
+        (3, np.array([[2, 2]], np.int32), np.array([0, 1, 2], np.int32)),
+        (6, np.array([[0, 1], [1, 2], [3, 4], [4, 5], [0, 2]], np.int32), np.array([0, 0, 0, 3, 3, 3], np.int32)),
+        (1, np.zeros((0, 2), np.int32), np.array([0], np.int32)),
+    ]
+    for n, e, lab in cases:
+        deg = np.bincount(e[e[:, 0] != e[:, 1]].ravel(), minlength=n).astype(np.int32) if len(e) else \
+            np.zeros(n, np.int32)
+        for rows, cols in ((4, 1024), (4, 1 << 20)):
+            check_supergraph(bgv, n, e, lab, deg, rows, cols, 3)
+
+
 @pytest.mark.parametrize("K", [65536, 65537])
 def test_supergraph_key_width_boundary(bgv, K):
     """Every node its own community: K = 65,536 supernodes packs a superedge key into 32
