@@ -3,6 +3,8 @@
 - lfr_3m (3.2M nodes, 34M edges, 3 passes, sketch 5 x 2^22): labels, degrees, volumes,
   both sketches and the supergraph bit-exact against the oracle; Barnes-Hut forces on the
   whole supergraph against the oracle's.
+- lfr_1m as a whole graph (1M nodes, 10M edges): Barnes-Hut forces of one layout step
+  against the oracle's, the layout the benchmark compares BigGraphVis with.
 - batched_512 (all 512 graphs in one launch, largest first, in the launch shape the
   benchmark's autotuner picks: workgroup size and the supergraph size above which the
   multi-workgroup kernels lay a graph out): every graph bit-identical to the
@@ -40,6 +42,18 @@ def test_lfr_3m_full_size(bgv):
     say(f"  lfr_3m supergraph: K={ref['K']} E={len(ref['superedges'])}")
     pos0 = graphgen.initial_positions(ref["K"], wl["pos_seed"])
     _, _, bad = bh_force_check(bgv, pos0, ref["superedges"], wl["theta"], "lfr_3m supergraph")
+    assert bad.mean() <= 1e-3
+
+
+def test_lfr_1m_whole_graph_bh_step(bgv):
+    """ForceAtlas2 on the whole original graph (the paper's comparison to BigGraphVis):
+    Barnes-Hut forces of one step on all 1M nodes and 10M edges against the oracle's."""
+    wl = graphgen.WORKLOADS["lfr_1m"]
+    say("  generating lfr_1m ...")
+    e, _ = graphgen.make_graph("lfr_1m")
+    e = np.ascontiguousarray(e[e[:, 0] != e[:, 1]])
+    pos0 = graphgen.initial_positions(wl["n"], wl["pos_seed"])
+    _, _, bad = bh_force_check(bgv, pos0, e, wl["theta"], "lfr_1m whole graph")
     assert bad.mean() <= 1e-3
 
 
