@@ -246,3 +246,30 @@ def pipeline(n, edges, wl, coef1, coef2, pos0):
                              tau=wl["tau"], ks=wl["ks"], ksmax=wl["ksmax"])
     return dict(labels=lab, counters=cnt, degree=deg, volume=vol, sg=sg, mass=mass, pos=pos,
                 Fprev=Fp, speed=sp)
+
+
+# -------------------------------------------------------------- drawing rules ---
+def draw_supernodes(super_size):
+    """Drawing attributes of the supernodes: the radius grows with the square root of
+    the size (Section 4.1), and 11 colour groups by size (Section 4.3).  Following
+    Section 4.3: alpha is the sum of all sizes; the communities are taken by size, small
+    first (equal sizes by supernode id); the smallest ones that together hold at most
+    half of alpha form group 0; the rest are cut into groups 1..10 holding equal shares
+    of the remaining half (the paper leaves the cut open; this reading is recorded with
+    the others), so a community whose running total (itself included) is P falls in
+    group ceil(10 * (2P - alpha) / alpha).  Integer arithmetic throughout.
+    Returns (group int32[K] in 0..10, radius float32[K] = correctly rounded sqrt of the
+    size converted to float32)."""
+    s = [int(v) for v in np.asarray(super_size, dtype=np.uint64)]
+    K = len(s)
+    order = sorted(range(K), key=lambda c: (s[c], c))
+    alpha = sum(s)
+    group = np.zeros(K, np.int32)
+    running = 0
+    for c in order:
+        running += s[c]
+        if 2 * running > alpha:
+            g = -(-10 * (2 * running - alpha) // alpha)  # ceiling division
+            group[c] = min(10, max(1, g))
+    radius = np.sqrt(np.asarray(super_size, dtype=np.uint32).astype(np.float32))
+    return group, radius

@@ -528,3 +528,56 @@ def test_fa2_trajectory_amplifies_rounding():
     b5 = oracle.fa2_layout(x1, sg["superedges"], iters=5)[0]
     assert dist(b1, a1) < 1e-4
     assert dist(b5, a5) > 1e-3
+
+
+# ------------------------------------------------------------- drawing rules ----
+def test_draw_groups_hand_worked():
+    """Section 4.3 applied by hand: sizes 6,1,1,1,1 (alpha = 10): the four size-1
+    communities hold 4 <= 5 = alpha/2, group 0; the size-6 one is the whole rest, group
+    10.  Twenty communities of size 1: ids 0..9 hold half, group 0; ids 10..19 take one
+    of the ten remaining groups each, in id order.  Two equal sizes: the lower id is the
+    smaller community (exactly half, group 0).  One community or all sizes 0."""
+    g, r = oracle.draw_supernodes([6, 1, 1, 1, 1])
+    assert g.tolist() == [10, 0, 0, 0, 0]
+    assert r.dtype == np.float32 and r[0] == np.float32(np.sqrt(np.float32(6))) and r[1] == 1.0
+    g, _ = oracle.draw_supernodes([1] * 20)
+    assert g.tolist() == [0] * 10 + list(range(1, 11))
+    assert oracle.draw_supernodes([3, 3])[0].tolist() == [0, 10]
+    assert oracle.draw_supernodes([5])[0].tolist() == [10]
+    g, r = oracle.draw_supernodes([0, 0, 0])
+    assert g.tolist() == [0, 0, 0] and r.tolist() == [0.0, 0.0, 0.0]
+    # radii: exact on squares, correctly rounded elsewhere
+    _, r = oracle.draw_supernodes([0, 1, 4, 9, 65536, 2**32 - 1])
+    assert r[:5].tolist() == [0.0, 1.0, 2.0, 3.0, 256.0]
+    assert r[5] == np.float32(65536.0)  # 2^32 - 1 rounds to 2^32 in float32
+
+
+def test_draw_groups_invariants():
+    """On random sizes: groups never decrease with size; group 0 holds at most half of
+    the total and adding the next community would exceed it; every group k >= 1 ends at
+    or before k/10 of the second half and the next one starts after (k-1)/10 of it; the
+    largest community is in group 10 whenever the total is positive."""
+    rng = np.random.default_rng(41)
+    for trial in range(30):
+        K = int(rng.integers(1, 400))
+        sizes = rng.integers(0, 1 + int(rng.choice([3, 100, 2**20])), K).astype(np.uint64)
+        if trial % 5 == 0:
+            sizes[rng.random(K) < 0.5] = 0
+        g, _ = oracle.draw_supernodes(sizes)
+        order = sorted(range(K), key=lambda c: (int(sizes[c]), c))
+        alpha = int(sizes.sum())
+        gs = [int(g[c]) for c in order]
+        assert gs == sorted(gs)
+        run = 0
+        for c in order:
+            run += int(sizes[c])
+            if g[c] == 0:
+                assert 2 * run <= alpha
+            else:
+                k = int(g[c])
+                assert 10 * (2 * run - alpha) <= k * alpha          # ends within group k's share
+                assert 10 * (2 * run - alpha) > (k - 1) * alpha     # and past group k-1's
+        if alpha > 0:
+            assert g[order[-1]] == 10
+        else:
+            assert (g == 0).all()
