@@ -246,6 +246,25 @@ bgv_status bgv_batched(int32_t G, int64_t n_total, int64_t m_total, const int64_
                        uint32_t *se_weight, float *pos, float *fprev, float *speed,
                        void *ws, size_t ws_bytes, bgv_stream_t stream);
 
+/* ---------------------------------------------------------------------------- */
+/* Drawing attributes of the supernodes                                          */
+/* ---------------------------------------------------------------------------- */
+/*
+ * Paper: Section 4.1 (a supernode is drawn with a radius proportional to the square
+ * root of its size) and Section 4.3 (eleven colour groups by community size).
+ * alpha = sum of the sizes; supernodes are ranked by size, small first (equal sizes by
+ * supernode id); one whose running total P (itself included) has 2P <= alpha is in
+ * group 0 (the smallest communities holding at most half of alpha), any other in group
+ * ceil(10 * (2P - alpha) / alpha), 1..10 (the remaining half cut into ten equal
+ * shares: the paper leaves the cut open).  All integer arithmetic.
+ * Inputs (dev): super_size uint32[K], e.g. the sketch-1 estimates from bgv_supergraph.
+ * Outputs (dev): group int32[K] in 0..10; radius float[K] = sqrt(size), correctly
+ * rounded (the caller scales it).  K >= 1; asynchronous on `stream`.
+ */
+size_t bgv_draw_workspace(int32_t K);
+bgv_status bgv_draw_supernodes(int32_t K, const uint32_t *super_size, int32_t *group, float *radius,
+                               void *ws, size_t ws_bytes, bgv_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -67,11 +67,15 @@ bgv_batched_workspace = _sig("bgv_batched_workspace", SZ, [i32, i64, i64])
 bgv_batched = _sig("bgv_batched", i32, [i32, i64, i64, P, P, P, P, C.POINTER(CdParams), C.POINTER(SketchParams),
                                         C.POINTER(Fa2Params), i32, i32, P, P, P, P, P, P, P, P, P, P, P, P, SZ, P])
 
+bgv_draw_workspace = _sig("bgv_draw_workspace", SZ, [i32])
+bgv_draw_supernodes = _sig("bgv_draw_supernodes", i32, [i32, P, P, P, P, SZ, P])
+
 EXPORTED = ["bgv_status_string", "bgv_last_error", "bgv_community_workspace", "bgv_community",
             "bgv_supergraph_workspace", "bgv_supergraph", "bgv_fa2_workspace", "bgv_fa2_layout",
             "bgv_fa2_energy_workspace", "bgv_fa2_energy", "bgv_fa2_grad",
             "bgv_profile_enable", "bgv_profile_filter", "bgv_profile_sample", "bgv_profile_reset", "bgv_profile_count", "bgv_profile_get",
-            "bgv_profile_counter", "bgv_batched_workspace", "bgv_batched"]
+            "bgv_profile_counter", "bgv_batched_workspace", "bgv_batched", "bgv_draw_workspace",
+            "bgv_draw_supernodes"]
 
 
 def check(status: int, what: str) -> None:

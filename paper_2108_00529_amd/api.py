@@ -205,6 +205,25 @@ def fa2_grad(superedges: torch.Tensor, pos: torch.Tensor, kr: float = 1.0, kg: f
     return g
 
 
+def draw_supernodes(super_size: torch.Tensor, ws=None, stream=None):
+    """Drawing attributes of the supernodes (Section 4.1 radius, Section 4.3 colour
+    groups): returns (group int32[K] in 0..10, radius float32[K] = sqrt(size))."""
+    K = super_size.shape[0]
+    if super_size.dtype not in (torch.int32, torch.uint32):
+        raise L.BgvError(f"super_size must be uint32 (or int32 bits), got {super_size.dtype}")
+    _need(super_size, super_size.dtype, "super_size", (K,))
+    need = L.bgv_draw_workspace(int(K))
+    if need == 0:
+        raise L.BgvError(f"invalid drawing arguments (K={K})")
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, super_size.device)
+    group = torch.empty(K, dtype=torch.int32, device=super_size.device)
+    radius = torch.empty(K, dtype=torch.float32, device=super_size.device)
+    L.check(L.bgv_draw_supernodes(int(K), _ptr(super_size), _ptr(group), _ptr(radius), _ptr(ws), ws.numel(),
+                                  _stream(stream)), "bgv_draw_supernodes")
+    return group, radius
+
+
 class FA2Energy(torch.autograd.Function):
     """Energy of a layout as an autograd function: forward = bgv_fa2_energy, backward =
     bgv_fa2_grad (the ForceAtlas2 force field, hand-written kernel)."""

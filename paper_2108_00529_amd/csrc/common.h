@@ -121,7 +121,7 @@ bgv_status fill(T *p, T value, int64_t count, hipStream_t s);
 size_t scan_workspace(int64_t n);
 bgv_status exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total,
                               void *scratch, hipStream_t s);
-template <class T>  // instantiated for uint32_t and double
+template <class T>  // instantiated for uint32_t, uint64_t and double
 bgv_status exclusive_scan(const T *in, T *out, int64_t n, T *total, void *scratch, hipStream_t s);
 
 // Stable LSD radix sort of keys below 2^nbits, with an optional uint32 payload.

@@ -113,6 +113,7 @@ bgv_status exclusive_scan(const T *in, T *out, int64_t n, T *total, void *scratc
 }
 template bgv_status exclusive_scan<uint32_t>(const uint32_t *, uint32_t *, int64_t, uint32_t *, void *, hipStream_t);
 template bgv_status exclusive_scan<double>(const double *, double *, int64_t, double *, void *, hipStream_t);
+template bgv_status exclusive_scan<uint64_t>(const uint64_t *, uint64_t *, int64_t, uint64_t *, void *, hipStream_t);
 
 bgv_status exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total, void *scratch,
                               hipStream_t s) {

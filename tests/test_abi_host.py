@@ -101,3 +101,14 @@ def test_fa2_validation():
     assert L.bgv_fa2_energy_workspace(10, 20) > 0
     assert L.bgv_fa2_energy(0, 0, None, None, None, one, 1.0, 1.0, one, one, 1 << 20, None) == -1
     assert L.bgv_fa2_grad(10, 0, None, None, None, one, 1.0, 1.0, None, None, one, 1 << 20, None) == -1
+
+
+def test_draw_validation():
+    assert L.bgv_draw_workspace(0) == 0 and L.bgv_draw_workspace(-5) == 0
+    assert L.bgv_draw_workspace(1000) > 4 * 8 * 1000
+    one = C.c_void_p(1)
+    assert L.bgv_draw_supernodes(0, one, one, one, None, 0, None) == -1
+    assert L.bgv_draw_supernodes(10, None, one, one, None, 0, None) == -1
+    assert L.bgv_draw_supernodes(10, one, None, one, None, 0, None) == -1
+    assert L.bgv_draw_supernodes(10, one, one, None, None, 0, None) == -1
+    assert L.bgv_draw_supernodes(10, one, one, one, None, 0, None) == -3  # no workspace, before any HIP call
