@@ -92,8 +92,22 @@ bgv_status bgv_community(int32_t n, int64_t m, const int32_t *edges, const bgv_c
                          int32_t *labels, int32_t *degree, int64_t *volume,
                          void *ws, size_t ws_bytes, bgv_stream_t stream);
 
+/*
+ * Paper: Section 3.2.1 (the passes of Algorithm 3, read as hierarchical community
+ * detection), Sections 5.3.3 and 5.3.5 (each pass's communities are kept as one level
+ * of the hierarchy, through which a supernode's members are reached).  Same arguments,
+ * workspace and outputs as bgv_community, plus pass_labels: dev int32[passes][n], row p = the labels after pass
+ * p (0-based), equal to the labels of bgv_community run with passes = p + 1; the last
+ * row equals `labels`.  pass_labels NULL is BGV_E_INVALID.  With m = 0 every row holds
+ * each node's own id.
+ */
+bgv_status bgv_community_passes(int32_t n, int64_t m, const int32_t *edges, const bgv_cd_params *p,
+                                int32_t *labels, int32_t *degree, int64_t *volume,
+                                int32_t *pass_labels, void *ws, size_t ws_bytes,
+                                bgv_stream_t stream);
+
 /* ---------------------------------------------------------------------------- */
-/* Count-min-sketch supergraph                                                   */
+/* Count-min-sketch supergraph                                                  */
 /* ---------------------------------------------------------------------------- */
 /*
  * Paper: Section 3.3 and Algorithm 2 (count-min sketch: r rows of c counters, one

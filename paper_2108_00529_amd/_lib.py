@@ -54,6 +54,7 @@ bgv_status_string = _sig("bgv_status_string", C.c_char_p, [i32])
 bgv_last_error = _sig("bgv_last_error", C.c_char_p, [])
 bgv_community_workspace = _sig("bgv_community_workspace", SZ, [i32, i64, C.POINTER(CdParams)])
 bgv_community = _sig("bgv_community", i32, [i32, i64, P, C.POINTER(CdParams), P, P, P, P, SZ, P])
+bgv_community_passes = _sig("bgv_community_passes", i32, [i32, i64, P, C.POINTER(CdParams), P, P, P, P, P, SZ, P])
 bgv_supergraph_workspace = _sig("bgv_supergraph_workspace", SZ, [i32, i64, C.POINTER(SketchParams)])
 bgv_supergraph = _sig("bgv_supergraph", i32, [i32, i64, P, P, P, C.POINTER(SketchParams), C.POINTER(i32),
                                               C.POINTER(i64), P, P, P, P, P, P, P, P, P, SZ, P])
@@ -71,6 +72,7 @@ bgv_draw_workspace = _sig("bgv_draw_workspace", SZ, [i32])
 bgv_draw_supernodes = _sig("bgv_draw_supernodes", i32, [i32, P, P, P, P, SZ, P])
 
 EXPORTED = ["bgv_status_string", "bgv_last_error", "bgv_community_workspace", "bgv_community",
+            "bgv_community_passes",
             "bgv_supergraph_workspace", "bgv_supergraph", "bgv_fa2_workspace", "bgv_fa2_layout",
             "bgv_fa2_energy_workspace", "bgv_fa2_energy", "bgv_fa2_grad",
             "bgv_profile_enable", "bgv_profile_filter", "bgv_profile_sample", "bgv_profile_reset", "bgv_profile_count", "bgv_profile_get",

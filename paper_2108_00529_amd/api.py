@@ -70,6 +70,28 @@ def community(edges: torch.Tensor, n: int, threshold: int, passes: int = 1, grow
     return labels, degree, vol
 
 
+def community_passes(edges: torch.Tensor, n: int, threshold: int, passes: int = 1, growth: int = 2,
+                     chunk: int = 1, volume: bool = False, ws: torch.Tensor | None = None, stream=None):
+    """community() that also keeps each pass's labels (the hierarchy of community sets).
+    Returns (labels, degree, volume or None, pass_labels int32[passes, n])."""
+    m = edges.shape[0] if edges.dim() == 2 else 0
+    _need(edges, torch.int32, "edges", (m, 2))
+    p = L.CdParams(int(threshold), int(passes), int(growth), 0, int(chunk))
+    need = L.bgv_community_workspace(int(n), m, C.byref(p))
+    if need == 0:
+        raise L.BgvError(f"invalid community arguments (n={n}, m={m}, {threshold}, {passes}, {growth}, {chunk})")
+    dev = edges.device
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, dev)
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
+    degree = torch.empty(n, dtype=torch.int32, device=dev)
+    vol = torch.empty(n, dtype=torch.int64, device=dev) if volume else None
+    rows = torch.empty((int(passes), n), dtype=torch.int32, device=dev)
+    L.check(L.bgv_community_passes(int(n), m, _ptr(edges), C.byref(p), _ptr(labels), _ptr(degree), _ptr(vol),
+                                   _ptr(rows), _ptr(ws), ws.numel(), _stream(stream)), "bgv_community_passes")
+    return labels, degree, vol, rows
+
+
 def community_workspace(edges: torch.Tensor, n: int, wl: dict) -> torch.Tensor:
     """A workspace tensor for community() on this graph and workload."""
     p = L.CdParams(int(wl["threshold"]), int(wl["passes"]), int(wl["growth"]), 0, int(wl["chunk"]))

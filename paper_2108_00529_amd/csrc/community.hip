@@ -430,16 +430,27 @@ extern "C" size_t bgv_community_workspace(int32_t n, int64_t m, const bgv_cd_par
     return cd_layout(c, n, m, p, &w);
 }
 
-extern "C" bgv_status bgv_community(int32_t n, int64_t m, const int32_t *edges, const bgv_cd_params *p,
-                                    int32_t *labels, int32_t *degree, int64_t *volume, void *ws,
-                                    size_t ws_bytes, bgv_stream_t stream) {
+namespace bgv {
+
+__global__ void k_cd_copy_labels(const int32_t *__restrict__ src, int32_t stride, int32_t n,
+                                 int32_t *__restrict__ dst) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        dst[v] = src[(int64_t)stride * v];
+}
+
+// The passes; with pass_labels, the labels after each pass are copied to row p (the
+// last chunk's proposals are then resolved at the end of its pass rather than with the
+// next pass's first chunk, which adds no counter increments, so nothing changes).
+static bgv_status cd_run(int32_t n, int64_t m, const int32_t *edges, const bgv_cd_params *p, int32_t *labels,
+                         int32_t *degree, int64_t *volume, int32_t *pass_labels, void *ws, size_t ws_bytes,
+                         bgv_stream_t stream, const char *who) {
     clear_error();
     if (!cd_valid(n, m, p)) {
-        set_error("bgv_community: invalid arguments (n=%d m=%lld)", n, (long long)m);
+        set_error("%s: invalid arguments (n=%d m=%lld)", who, n, (long long)m);
         return BGV_E_INVALID;
     }
     if ((m > 0 && !edges) || !labels || !degree) {
-        set_error("bgv_community: null pointer");
+        set_error("%s: null pointer", who);
         return BGV_E_INVALID;
     }
     BGV_TRY(check_ws(ws, ws_bytes, bgv_community_workspace(n, m, p)));
@@ -467,7 +478,7 @@ extern "C" bgv_status bgv_community(int32_t n, int64_t m, const int32_t *edges, 
             BGV_LAUNCH(k_cd_step<-1>, dim3(etiles), dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1, (int64_t)0, (int64_t)0,
                        0, 0, nb, w.props, w.ptab, (int64_t)0, std::min<int64_t>(B, m), w.ends, w.etab);
         }
-        for (int32_t pass = 0; pass < p->passes && m > 0; ++pass) {
+        for (int32_t pass = 0; pass < p->passes && (m > 0 || pass_labels); ++pass) {
             const int32_t D = pass_threshold(p->threshold, p->growth, pass);
             for (int64_t k = 0; k < nchunk; ++k) {
                 const int64_t cs = k * B, ce = (cs + B < m) ? cs + B : m;
@@ -494,6 +505,14 @@ extern "C" bgv_status bgv_community(int32_t n, int64_t m, const int32_t *edges, 
                 ptiles = tiles;
                 etiles = gtiles;
             }
+            if (pass_labels) {
+                if (ptiles > 0)
+                    BGV_LAUNCH(k_cd_resolve, dim3(nb), dim3(kCdResolveThreads), 0, s, w.cnt, w.lab, n, nb, w.props,
+                               w.ptab, ptiles, w.ends, w.etab, 0, cd_resolve_lanes(ptiles));
+                ptiles = 0;
+                BGV_LAUNCH(k_cd_copy_labels, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, w.lab, 1,
+                           n, pass_labels + (int64_t)pass * n);
+            }
         }
         if (ptiles > 0)
             BGV_LAUNCH(k_cd_resolve, dim3(nb), dim3(kCdResolveThreads), 0, s, w.cnt, w.lab, n, nb, w.props, w.ptab, ptiles, w.ends,
@@ -508,7 +527,7 @@ extern "C" bgv_status bgv_community(int32_t n, int64_t m, const int32_t *edges, 
     int2 *c1 = w.c1;
     BGV_LAUNCH(k_cd_init, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, st, n);
     int64_t ps = 0, pe = 0;  // pending (not yet applied) chunk
-    for (int32_t pass = 0; pass < p->passes && m > 0; ++pass) {
+    for (int32_t pass = 0; pass < p->passes && (m > 0 || pass_labels); ++pass) {
         const int32_t D = pass_threshold(p->threshold, p->growth, pass);
         for (int64_t k = 0; k < nchunk; ++k) {
             const int64_t cs = k * B, ce = (cs + B < m) ? cs + B : m;
@@ -528,6 +547,14 @@ extern "C" bgv_status bgv_community(int32_t n, int64_t m, const int32_t *edges, 
             ps = cs;
             pe = ce;
         }
+        if (pass_labels) {
+            if (pe > ps)
+                BGV_LAUNCH(k_cd_apply_hist, dim3(grid_for(pe - ps, kCdThreads * 4, 16384)), dim3(kCdThreads), 0, s,
+                           st, e2, prop, ps, pe, (int64_t)0, (int64_t)0);
+            ps = pe = 0;
+            BGV_LAUNCH(k_cd_copy_labels, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s,
+                       reinterpret_cast<const int32_t *>(st) + 1, 4, n, pass_labels + (int64_t)pass * n);
+        }
     }
     if (pe > ps) {
         BGV_LAUNCH(k_cd_apply_hist, dim3(grid_for(pe - ps, kCdThreads * 4, 16384)), dim3(kCdThreads), 0, s,
@@ -537,4 +564,25 @@ extern "C" bgv_status bgv_community(int32_t n, int64_t m, const int32_t *edges, 
                reinterpret_cast<const int32_t *>(st), n, labels, degree,
                reinterpret_cast<unsigned long long *>(volume));
     return BGV_OK;
+}
+
+}  // namespace bgv
+
+extern "C" bgv_status bgv_community(int32_t n, int64_t m, const int32_t *edges, const bgv_cd_params *p,
+                                    int32_t *labels, int32_t *degree, int64_t *volume, void *ws,
+                                    size_t ws_bytes, bgv_stream_t stream) {
+    return cd_run(n, m, edges, p, labels, degree, volume, nullptr, ws, ws_bytes, stream, "bgv_community");
+}
+
+extern "C" bgv_status bgv_community_passes(int32_t n, int64_t m, const int32_t *edges, const bgv_cd_params *p,
+                                           int32_t *labels, int32_t *degree, int64_t *volume,
+                                           int32_t *pass_labels, void *ws, size_t ws_bytes,
+                                           bgv_stream_t stream) {
+    if (!pass_labels) {
+        clear_error();
+        set_error("bgv_community_passes: null pointer");
+        return BGV_E_INVALID;
+    }
+    return cd_run(n, m, edges, p, labels, degree, volume, pass_labels, ws, ws_bytes, stream,
+                  "bgv_community_passes");
 }

@@ -65,6 +65,14 @@ def test_community_validation_and_workspace():
     assert L.bgv_community(10, 5, C.c_void_p(256), C.byref(p), C.c_void_p(256), C.c_void_p(256), None,
                            C.c_void_p(513), need, None) == -3
     assert b"workspace" in L.bgv_last_error()
+    # per-pass labels: same checks, and the rows buffer is required
+    assert L.bgv_community_passes(10, 5, C.c_void_p(256), C.byref(p), C.c_void_p(256), C.c_void_p(256), None,
+                                  None, C.c_void_p(512), need, None) == -1
+    assert b"bgv_community_passes" in L.bgv_last_error()
+    assert L.bgv_community_passes(0, 5, C.c_void_p(256), C.byref(p), C.c_void_p(256), C.c_void_p(256), None,
+                                  C.c_void_p(256), C.c_void_p(512), need, None) == -1
+    assert L.bgv_community_passes(10, 5, C.c_void_p(256), C.byref(p), C.c_void_p(256), C.c_void_p(256), None,
+                                  C.c_void_p(256), C.c_void_p(512), need - 1, None) == -3
 
 
 def test_supergraph_validation():

@@ -120,6 +120,47 @@ def test_community_at_and_above_bucket_limit(bgv, n):
     check_community(bgv, n, e, 8, 2, 2, 3000)
 
 
+def check_passes(bgv, n, e, D, P, f, B):
+    """Row p of the per-pass labels equals the labels of a (p+1)-pass run."""
+    say(f"  community passes n={n} m={len(e)} D={D} P={P} f={f} B={B}")
+    ed = dev(e.reshape(-1, 2).astype(np.int32))
+    lab, deg, vol, rows = bgv.community_passes(ed, n, D, P, f, B, volume=True)
+    torch.cuda.synchronize()
+    rows = host(rows)
+    assert rows.shape == (P, n)
+    for q in range(P):
+        lab_r, _ = oracle.bs_community(n, e, D, q + 1, f, B)
+        np.testing.assert_array_equal(rows[q], lab_r, err_msg=f"pass {q}")
+    lab_r, cnt_r = oracle.bs_community(n, e, D, P, f, B)
+    deg_r, vol_r = oracle.degree_volume(lab_r, cnt_r, P)
+    np.testing.assert_array_equal(host(lab), lab_r)
+    np.testing.assert_array_equal(host(deg), deg_r)
+    np.testing.assert_array_equal(host(vol), vol_r)
+
+
+def test_community_pass_labels(bgv):
+    """The labels after every pass (the hierarchy of community sets): small random
+    graphs, an empty stream, several buckets with ragged chunks, and the per-node atomic
+    form above 2^24 nodes."""
+    rng = np.random.default_rng(31)
+    check_passes(bgv, 7, np.zeros((0, 2), np.int32), 3, 3, 2, 4)
+    for trial in range(12):
+        n = int(rng.integers(1, 80))
+        m = int(rng.integers(1, 500))
+        e = graphgen.random_tiny_graph(rng, n, m)
+        B = int(rng.choice([1, 3, 17, 1000]))
+        check_passes(bgv, n, e, int(rng.integers(0, 12)), int(rng.integers(1, 5)), int(rng.integers(1, 4)), B)
+    n = 2 * 4096 + 5
+    e = rng.integers(0, n, (30_000, 2)).astype(np.int32)
+    e[rng.random(len(e)) < 0.05, 0] = 17
+    for B in (4000, 1024, len(e)):
+        check_passes(bgv, n, e, 5, 4, 2, B)
+    n = (1 << 24) + 77
+    ids = np.concatenate([rng.integers(0, 3000, 2000), rng.integers(n - 3000, n, 2000)])
+    e = ids[rng.integers(0, len(ids), (20_000, 2))].astype(np.int32)
+    check_passes(bgv, n, e, 6, 3, 2, 2500)
+
+
 @pytest.fixture(scope="module")
 def planted():
     wl = graphgen.WORKLOADS["planted_2k"]
