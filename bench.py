@@ -216,6 +216,7 @@ def main():
         del edges, pos0
         torch.cuda.empty_cache()
         out["forms"] = {"whole_graph_fa2": whole_graph_form(torch, bgv, edges_np, n, wl, cd + fa_unprofiled),
+                        "sequential_rule": sequential_rule_form(torch, bgv, edges_np, n, wl, not args.no_cpu),
                         "small_graph": small_graph_form(torch, bgv, graphgen),
                         "batched": batched_form(torch, bgv, graphgen),
                         "gradient": gradient_form(torch, bgv, graphgen),
@@ -416,6 +417,30 @@ def whole_graph_form(torch, bgv, edges_np, n, wl, bgv_ms):
     return {"nodes": n, "edges": int(e.shape[0]), "fa2_iterations": wl["fa2_iters"], "fa2_ms": ms,
             "fa2_iters_per_s": wl["fa2_iters"] / (ms / 1000.0), "biggraphvis_ms": bgv_ms,
             "time_reduction_pct": 100.0 * (1.0 - bgv_ms / ms)}
+
+
+def sequential_rule_form(torch, bgv, edges_np, n, wl, with_cpu):
+    """The community passes with chunk = 1 (the sequential rule, one chunk per edge) on
+    the same stream: back-pointer resolution (the automatic choice there), against the
+    oracle's sequential loop on one host thread as its CPU baseline."""
+    dev = torch.device("cuda:0")
+    ed = torch.from_numpy(np.ascontiguousarray(edges_np)).to(dev)
+    run = lambda: bgv.community(ed, n, wl["threshold"], wl["passes"], wl["growth"], 1)
+    run()
+    torch.cuda.synchronize()
+    ms = _timed(torch, run, repeats=3)
+    del ed
+    torch.cuda.empty_cache()
+    m = int(edges_np.shape[0])
+    out = {"chunk": 1, "passes": wl["passes"], "edges": m, "gpu_ms": ms,
+           "edges_per_s": m / (ms / 1000.0), "chunk_steps_avoided": wl["passes"] * m}
+    if with_cpu:
+        import oracle
+        t = time.perf_counter()
+        oracle.bs_community(n, edges_np, wl["threshold"], wl["passes"], wl["growth"], 1)
+        cpu_ms = (time.perf_counter() - t) * 1000.0
+        out.update(cpu_oracle_ms=cpu_ms, cpu_threads=1, speedup_vs_oracle=cpu_ms / ms)
+    return out
 
 
 def graphgen_initial(n, wl):

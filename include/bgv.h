@@ -63,12 +63,24 @@ const char *bgv_last_error(void);
  * chunk began; a node proposed to by several edges takes the label from the edge of
  * smallest stream index.  chunk = 1 is the sequential rule; `chunk` is part of the
  * result's definition, not a tuning knob.
+ *
+ * Two methods compute these same integers.  Chunk by chunk (method 1): two launches
+ * per chunk and pass.  Back-pointer resolution (method 2): decisions depend only on
+ * counters, which follow in closed form from the stream, so every pass's proposals are
+ * formed at once; a chunk's winner for a target is its proposal of smallest stream
+ * index, and the label it carries is the one its source got from its own latest winner
+ * in an earlier chunk; pointer jumping over those links resolves all labels in about
+ * 20 + log2(passes * chunks) launches, whatever the chunk size (chunk = 1 included).
+ * Method 2 needs m >= 1 and passes * m < 2^31 (method 2 otherwise: BGV_E_INVALID) and
+ * more workspace.  Method 0 picks 2 when it applies and the chunk-by-chunk form would
+ * take more than 16 + passes * m / 2^17 chunk steps, else 1.  Other values are
+ * BGV_E_INVALID.
  */
 typedef struct {
     int32_t threshold; /* D1 >= 0: threshold of the first pass                   */
     int32_t passes;    /* P >= 1                                                 */
     int32_t growth;    /* >= 1: threshold factor between passes                   */
-    int32_t reserved;  /* must be 0                                              */
+    int32_t method;    /* 0 automatic, 1 chunk by chunk, 2 back-pointer resolution */
     int64_t chunk;     /* >= 1: edges per synchronous chunk                        */
 } bgv_cd_params;
 
@@ -77,7 +89,8 @@ typedef struct {
  * endpoints plus two offset rows of 4 * (ceil(n / 4096) + 1) bytes.  Above: 16 bytes per
  * node and 4 per edge of a chunk.  With passes > 1 another 8 per edge (each edge's
  * pass-0 endpoint counters, from which later passes' counters follow without
- * increments). */
+ * increments).  Method 2: 48 bytes per edge, 8 per node and at most 56 per (pass, edge)
+ * proposal, plus radix-sort scratch. */
 size_t bgv_community_workspace(int32_t n, int64_t m, const bgv_cd_params *p);
 
 /*

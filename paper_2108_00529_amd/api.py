@@ -50,15 +50,18 @@ def validate_edges(edges: torch.Tensor, n: int) -> None:
 
 # ------------------------------------------------------------------- community --
 def community(edges: torch.Tensor, n: int, threshold: int, passes: int = 1, growth: int = 2,
-              chunk: int = 1, volume: bool = False, ws: torch.Tensor | None = None, stream=None):
+              chunk: int = 1, volume: bool = False, ws: torch.Tensor | None = None, stream=None,
+              method: int = 0):
     """Streaming community detection.  Returns (labels int32[n], degree int32[n],
-    volume int64[n] or None)."""
+    volume int64[n] or None).  method: 0 automatic, 1 chunk by chunk, 2 back-pointer
+    resolution (the same integers)."""
     m = edges.shape[0] if edges.dim() == 2 else 0
     _need(edges, torch.int32, "edges", (m, 2))
-    p = L.CdParams(int(threshold), int(passes), int(growth), 0, int(chunk))
+    p = L.CdParams(int(threshold), int(passes), int(growth), int(method), int(chunk))
     need = L.bgv_community_workspace(int(n), m, C.byref(p))
     if need == 0:
-        raise L.BgvError(f"invalid community arguments (n={n}, m={m}, {threshold}, {passes}, {growth}, {chunk})")
+        raise L.BgvError(f"invalid community arguments (n={n}, m={m}, {threshold}, {passes}, {growth}, {chunk}, "
+                         f"method {method})")
     dev = edges.device
     if ws is None or ws.numel() < need:
         ws = _workspace(need, dev)
@@ -71,15 +74,17 @@ def community(edges: torch.Tensor, n: int, threshold: int, passes: int = 1, grow
 
 
 def community_passes(edges: torch.Tensor, n: int, threshold: int, passes: int = 1, growth: int = 2,
-                     chunk: int = 1, volume: bool = False, ws: torch.Tensor | None = None, stream=None):
+                     chunk: int = 1, volume: bool = False, ws: torch.Tensor | None = None, stream=None,
+                     method: int = 0):
     """community() that also keeps each pass's labels (the hierarchy of community sets).
     Returns (labels, degree, volume or None, pass_labels int32[passes, n])."""
     m = edges.shape[0] if edges.dim() == 2 else 0
     _need(edges, torch.int32, "edges", (m, 2))
-    p = L.CdParams(int(threshold), int(passes), int(growth), 0, int(chunk))
+    p = L.CdParams(int(threshold), int(passes), int(growth), int(method), int(chunk))
     need = L.bgv_community_workspace(int(n), m, C.byref(p))
     if need == 0:
-        raise L.BgvError(f"invalid community arguments (n={n}, m={m}, {threshold}, {passes}, {growth}, {chunk})")
+        raise L.BgvError(f"invalid community arguments (n={n}, m={m}, {threshold}, {passes}, {growth}, {chunk}, "
+                         f"method {method})")
     dev = edges.device
     if ws is None or ws.numel() < need:
         ws = _workspace(need, dev)

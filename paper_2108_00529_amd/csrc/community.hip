@@ -5,7 +5,9 @@
 // the smaller counter join the other's community, and of the proposals to one node the
 // one from the smallest stream index wins.
 //
-// Two implementations give the same integers.
+// Three implementations give the same integers: the two chunk-by-chunk forms below
+// and, for many chunks, the back-pointer resolution of community_jump.hip (no barrier
+// per chunk; chosen by bgv_cd_params.method).
 //
 // Bucketed (n <= kCdMaxBuckets * kCdBucket): counters and labels in two int32 arrays
 // and no global atomics.  Nodes fall into buckets of kCdBucket consecutive ids.
@@ -31,6 +33,7 @@
 
 #include "block_scan.h"
 #include "common.h"
+#include "community_jump.h"
 
 namespace bgv {
 
@@ -384,8 +387,21 @@ static int32_t pass_threshold(int32_t D1, int32_t growth, int32_t p) {
 }
 
 static bool cd_valid(int32_t n, int64_t m, const bgv_cd_params *p) {
-    return p && n >= 1 && m >= 0 && m <= INT32_MAX && p->threshold >= 0 && p->passes >= 1 && p->growth >= 1 &&
-           p->chunk >= 1 && p->reserved == 0;
+    if (!(p && n >= 1 && m >= 0 && m <= INT32_MAX && p->threshold >= 0 && p->passes >= 1 && p->growth >= 1 &&
+          p->chunk >= 1 && p->method >= 0 && p->method <= 2))
+        return false;
+    return p->method != 2 || m == 0 || sq_fits(n, m, p);
+}
+
+// 1: chunk by chunk; 2: back-pointer resolution.  Automatic: measured on a 10M-edge
+// stream, a chunk step costs about 12 us and back-pointer resolution about 150 us plus
+// 0.09 ns more per (pass, edge) than the chunk steps' streaming, so the second wins past
+// about 16 + passes * m / 2^17 chunk steps (245 at 3 x 10M edges, 16 on small graphs).
+static int cd_method(int32_t n, int64_t m, const bgv_cd_params *p) {
+    if (m == 0) return 1;
+    if (p->method != 0) return p->method;
+    const int64_t steps = (int64_t)p->passes * ((m + p->chunk - 1) / p->chunk);
+    return steps > 16 + ((int64_t)p->passes * m >> 17) && sq_fits(n, m, p) ? 2 : 1;
 }
 
 struct CdWs {
@@ -426,6 +442,7 @@ using namespace bgv;
 extern "C" size_t bgv_community_workspace(int32_t n, int64_t m, const bgv_cd_params *p) {
     if (!cd_valid(n, m, p)) return 0;
     Carver c(nullptr);
+    if (cd_method(n, m, p) == 2) return sq_layout(c, n, m, p, nullptr);
     CdWs w;
     return cd_layout(c, n, m, p, &w);
 }
@@ -455,11 +472,12 @@ static bgv_status cd_run(int32_t n, int64_t m, const int32_t *edges, const bgv_c
     }
     BGV_TRY(check_ws(ws, ws_bytes, bgv_community_workspace(n, m, p)));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (volume) BGV_TRY(fill<int64_t>(volume, 0, n, s));
+    if (cd_method(n, m, p) == 2) return sq_run(n, m, edges, p, labels, degree, volume, pass_labels, ws, s);
     Carver c(ws);
     CdWs w;
     cd_layout(c, n, m, p, &w);
     const int2 *e2 = reinterpret_cast<const int2 *>(edges);
-    if (volume) BGV_TRY(fill<int64_t>(volume, 0, n, s));
     const int64_t B = p->chunk;
     const int64_t nchunk = (m + B - 1) / B;
 

@@ -1,0 +1,17 @@
+// Community detection by back-pointer resolution (community_jump.hip): the same
+// integers as the chunk-by-chunk form, in a fixed number of bulk launches.
+#pragma once
+#include "common.h"
+
+namespace bgv {
+
+// Whether the form applies: m >= 1 and passes * m < 2^31 (proposals indexed in 32 bits).
+bool sq_fits(int32_t n, int64_t m, const bgv_cd_params *p);
+// Workspace layout (out: the internal layout, or nullptr); returns the bytes used.
+size_t sq_layout(Carver &c, int32_t n, int64_t m, const bgv_cd_params *p, void *out);
+// The passes; arguments as bgv_community_passes (pass_labels may be null).  volume, if
+// given, must be zero-filled.
+bgv_status sq_run(int32_t n, int64_t m, const int32_t *edges, const bgv_cd_params *p, int32_t *labels,
+                  int32_t *degree, int64_t *volume, int32_t *pass_labels, void *ws, hipStream_t s);
+
+}  // namespace bgv

@@ -1,0 +1,397 @@
+// Streaming community detection without a barrier per chunk (the rule of Section 3.2,
+// the passes of Section 3.2.1 / Algorithm 3, batch-synchronous as in community.hip:
+// the same integers for every chunk size, chunk = 1 being the sequential rule).
+//
+// Under the degree rule an edge's decision in a pass (whether it proposes, and which
+// endpoint is the target) depends only on counters, and those follow in closed form
+// from the stream: in pass p at the end of chunk k the counter of x is p d(x) + c(x, k),
+// with c(x, k) the occurrences of x as an endpoint of a non-loop edge in chunks 0..k.
+// Labels enter only as the value a proposal carries (its source's label when the chunk
+// began).  So every pass's proposals are known up front; a target's winner in a chunk
+// is its proposal of smallest stream index; and the label a winner carries is the one
+// its source got from its own latest winner in an earlier chunk (the source's id if it
+// had none).  Those links point strictly back in time, and pointer jumping over them
+// labels every winner in O(log chunks) bulk steps:
+//   1. endpoint occurrences sorted by node (stable): d(x) = run length, c(x, k) of each
+//      occurrence by a binary search in its node's run;
+//   2. the proposals of every (pass, edge), compacted in stream order, sorted stably
+//      by (target, global chunk): the first of each run is the winner;
+//   3. winners compacted; each one's link = the last winner into its source with an
+//      earlier chunk (a binary search over the sorted winners);
+//   4. pointer jumping along the links; a node's label = its last winner's label.
+// About 20 launches whatever the number of chunks, against two per chunk and pass for
+// the chunk-by-chunk form: the choice for small chunks.
+#include <algorithm>
+
+#include "common.h"
+#include "community_jump.h"
+
+namespace bgv {
+
+constexpr int kSqThreads = 256;
+
+static int bits_for(uint64_t x) {  // bits needed to hold values 0..x
+    int b = 0;
+    while (b < 64 && (x >> b) != 0) ++b;
+    return b;
+}
+
+// D1 * growth^p, saturating at INT32_MAX (at most ~31 products before it saturates).
+__host__ __device__ inline int32_t sq_threshold(int32_t D1, int32_t growth, int32_t p) {
+    if (growth == 1 || D1 == 0) return D1;
+    int64_t D = D1;
+    for (int32_t k = 0; k < p; ++k) {
+        D *= growth;
+        if (D > INT32_MAX) return INT32_MAX;
+    }
+    return (int32_t)D;
+}
+
+bool sq_fits(int32_t n, int64_t m, const bgv_cd_params *p) {
+    if (m < 1) return false;
+    const int64_t nchunk = (m + p->chunk - 1) / p->chunk;
+    if ((int64_t)p->passes * m > INT32_MAX) return false;  // proposals indexed in 32 bits
+    const uint64_t G = (uint64_t)p->passes * (uint64_t)nchunk;
+    return bits_for((uint64_t)(n - 1)) + bits_for(G - 1) <= 64;
+}
+
+struct SqWs {
+    uint32_t *okey, *okey_alt, *oval, *oval_alt;  // endpoint occurrences [2m]
+    uint32_t *beg, *end;                          // run of each node in the sorted occurrences [n]
+    int4 *cd;                                     // per edge {c(e.x), c(e.y), d(e.x), d(e.y)}
+    uint32_t *flag;                               // [P m]: proposals, then winners
+    void *evk, *evk_alt;                          // proposal keys (target, chunk) [P m], 32 or 64 bits
+    uint32_t *evv, *evv_alt;                      // their edge indices
+    void *wk;                                     // winners' keys [P m]
+    uint32_t *wv;                                 // winners' edge indices
+    int32_t *nxt, *nxt2, *val, *val2;             // links and labels, ping-pong [P m]
+    uint32_t *tot;                                // [4]: proposals, winners
+    unsigned long long *tot64;                    // proposals, as the sort's device count
+    void *sort_scratch, *scan_scratch;
+};
+
+static bool sq_wide(int32_t n, int64_t m, const bgv_cd_params *p) {
+    const int64_t nchunk = (m + p->chunk - 1) / p->chunk;
+    return bits_for((uint64_t)(n - 1)) + bits_for((uint64_t)p->passes * (uint64_t)nchunk - 1) > 32;
+}
+
+size_t sq_layout(Carver &c, int32_t n, int64_t m, const bgv_cd_params *p, void *out) {
+    SqWs w{};
+    const size_t no = 2 * (size_t)m, pm = (size_t)p->passes * (size_t)m;
+    const size_t kw = sq_wide(n, m, p) ? sizeof(uint64_t) : sizeof(uint32_t);
+    w.okey = c.take<uint32_t>(no);
+    w.okey_alt = c.take<uint32_t>(no);
+    w.oval = c.take<uint32_t>(no);
+    w.oval_alt = c.take<uint32_t>(no);
+    w.beg = c.take<uint32_t>((size_t)n);
+    w.end = c.take<uint32_t>((size_t)n);
+    w.cd = c.take<int4>((size_t)m);
+    w.flag = c.take<uint32_t>(pm);
+    w.evk = c.take<char>(pm * kw);
+    w.evk_alt = c.take<char>(pm * kw);
+    w.evv = c.take<uint32_t>(pm);
+    w.evv_alt = c.take<uint32_t>(pm);
+    w.wk = c.take<char>(pm * kw);
+    w.wv = c.take<uint32_t>(pm);
+    w.nxt = c.take<int32_t>(pm);
+    w.nxt2 = c.take<int32_t>(pm);
+    w.val = c.take<int32_t>(pm);
+    w.val2 = c.take<int32_t>(pm);
+    w.tot = c.take<uint32_t>(4);
+    w.tot64 = c.take<unsigned long long>(2);
+    w.sort_scratch = c.take<char>(radix_workspace((int64_t)std::max(no, pm)));
+    w.scan_scratch = c.take<char>(scan_workspace((int64_t)pm));
+    if (out) *static_cast<SqWs *>(out) = w;
+    return c.size();
+}
+
+// ------------------------------------------------------------------ kernels ----
+#define SQ_LOOP(i, count) \
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (count); i += (int64_t)gridDim.x * blockDim.x)
+
+// Occurrence 2i + s is endpoint s of edge i, keyed by its node (self-loops by n, past
+// every node: they raise no counter).
+__global__ void __launch_bounds__(kSqThreads) k_sq_occ(const int2 *__restrict__ edges, int64_t m, int32_t n,
+                                                       uint32_t *__restrict__ okey, uint32_t *__restrict__ oval) {
+    SQ_LOOP(i, m) {
+        const int2 e = edges[i];
+        const bool loop = e.x == e.y;
+        okey[2 * i] = loop ? (uint32_t)n : (uint32_t)e.x;
+        okey[2 * i + 1] = loop ? (uint32_t)n : (uint32_t)e.y;
+        oval[2 * i] = (uint32_t)(2 * i);
+        oval[2 * i + 1] = (uint32_t)(2 * i + 1);
+    }
+}
+
+__global__ void __launch_bounds__(kSqThreads) k_sq_runs(const uint32_t *__restrict__ sk, int64_t no, int32_t n,
+                                                        uint32_t *__restrict__ beg, uint32_t *__restrict__ end) {
+    SQ_LOOP(j, no) {
+        const uint32_t x = sk[j];
+        if (x >= (uint32_t)n) continue;
+        if (j == 0 || sk[j - 1] != x) beg[x] = (uint32_t)j;
+        if (j + 1 == no || sk[j + 1] != x) end[x] = (uint32_t)(j + 1);
+    }
+}
+
+// c(x, k) of each occurrence: the occurrences of x before the end of its chunk, i.e.
+// the first place in x's run (occurrences in stream order) at or past that end.
+__global__ void __launch_bounds__(kSqThreads) k_sq_counts(const uint32_t *__restrict__ sk,
+                                                          const uint32_t *__restrict__ sv, int64_t no, int32_t n,
+                                                          const uint32_t *__restrict__ beg,
+                                                          const uint32_t *__restrict__ end, int64_t m, int64_t B,
+                                                          int4 *__restrict__ cd) {
+    SQ_LOOP(j, no) {
+        const uint32_t x = sk[j];
+        if (x >= (uint32_t)n) continue;
+        const uint32_t o = sv[j];
+        const int64_t i = o >> 1;
+        const int64_t ce = std::min<int64_t>((i / B + 1) * B, m);
+        const uint64_t lim = 2 * (uint64_t)ce;
+        uint32_t lo = (uint32_t)j + 1, hi = end[x];
+        while (lo < hi) {
+            const uint32_t mid = lo + (hi - lo) / 2;
+            if ((uint64_t)sv[mid] < lim) lo = mid + 1;
+            else hi = mid;
+        }
+        int32_t *rec = reinterpret_cast<int32_t *>(cd + i);
+        rec[o & 1u] = (int32_t)(lo - beg[x]);
+        rec[2 + (o & 1u)] = (int32_t)(end[x] - beg[x]);
+    }
+}
+
+// Target of edge e in pass p (threshold D), or -1: both counters at most D and unequal,
+// the endpoint with the smaller one is the target.
+__device__ __forceinline__ int32_t sq_target(int2 e, int4 c, int32_t p, int32_t D) {
+    if (e.x == e.y) return -1;
+    const int32_t cu = p * c.z + c.x, cv = p * c.w + c.y;
+    if (cu <= D && cv <= D && cu != cv) return cu < cv ? e.x : e.y;
+    return -1;
+}
+
+// flag[p m + i] = edge i proposes in pass p
+__global__ void __launch_bounds__(kSqThreads) k_sq_flags(const int2 *__restrict__ edges, const int4 *__restrict__ cd,
+                                                         int64_t m, int32_t P, int32_t D1, int32_t growth,
+                                                         uint32_t *__restrict__ flag) {
+    SQ_LOOP(t, (int64_t)P * m) {
+        const int32_t p = (int32_t)(t / m);
+        const int64_t i = t - (int64_t)p * m;
+        flag[t] = sq_target(edges[i], cd[i], p, sq_threshold(D1, growth, p)) >= 0 ? 1u : 0u;
+    }
+}
+
+// Proposal (p, i) at its place pos[p m + i]: key (target, global chunk), value i.
+template <class KT>
+__global__ void __launch_bounds__(kSqThreads) k_sq_emit(const int2 *__restrict__ edges, const int4 *__restrict__ cd,
+                                                        int64_t m, int32_t P, int32_t D1, int32_t growth, int64_t B,
+                                                        int64_t nchunk, int gbits, const uint32_t *__restrict__ pos,
+                                                        KT *__restrict__ key, uint32_t *__restrict__ val) {
+    SQ_LOOP(t, (int64_t)P * m) {
+        const int32_t p = (int32_t)(t / m);
+        const int64_t i = t - (int64_t)p * m;
+        const int32_t v = sq_target(edges[i], cd[i], p, sq_threshold(D1, growth, p));
+        if (v < 0) continue;
+        const uint64_t g = (uint64_t)p * (uint64_t)nchunk + (uint64_t)(i / B);
+        const uint32_t q = pos[t];
+        key[q] = (KT)(((uint64_t)v << gbits) | g);
+        val[q] = (uint32_t)i;
+    }
+}
+
+__global__ void __launch_bounds__(kSqThreads) k_sq_widen(const uint32_t *__restrict__ a, unsigned long long *b) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *b = *a;
+}
+
+// flag[q] = sorted proposal q is the first of its (target, chunk) run
+template <class KT>
+__global__ void __launch_bounds__(kSqThreads) k_sq_first(const KT *__restrict__ sk, int64_t bound,
+                                                         const uint32_t *__restrict__ count,
+                                                         uint32_t *__restrict__ flag) {
+    const int64_t E = *count;
+    SQ_LOOP(q, bound) flag[q] = (q < E && (q == 0 || sk[q - 1] != sk[q])) ? 1u : 0u;
+}
+
+template <class KT>
+__global__ void __launch_bounds__(kSqThreads) k_sq_compact(const KT *__restrict__ sk, const uint32_t *__restrict__ sv,
+                                                           const uint32_t *__restrict__ count,
+                                                           const uint32_t *__restrict__ pos, KT *__restrict__ wk,
+                                                           uint32_t *__restrict__ wv) {
+    const int64_t E = *count;
+    SQ_LOOP(q, E) {
+        if (q == 0 || sk[q - 1] != sk[q]) {
+            wk[pos[q]] = sk[q];
+            wv[pos[q]] = sv[q];
+        }
+    }
+}
+
+// Winner r's link: the last winner into its source with an earlier chunk, or -1; its
+// value: the source (the label it carries when the link is -1).
+template <class KT>
+__global__ void __launch_bounds__(kSqThreads) k_sq_links(const int2 *__restrict__ edges, const KT *__restrict__ wk,
+                                                         const uint32_t *__restrict__ wv,
+                                                         const uint32_t *__restrict__ wcount, int gbits,
+                                                         int32_t *__restrict__ nxt, int32_t *__restrict__ val) {
+    const int64_t W = *wcount;
+    SQ_LOOP(r, W) {
+        const uint64_t key = (uint64_t)wk[r];
+        const uint64_t gmask = gbits >= 64 ? ~0ull : ((1ull << gbits) - 1ull);
+        const int32_t v = (int32_t)(key >> gbits);
+        const int2 e = edges[wv[r]];
+        const int32_t u = e.x == v ? e.y : e.x;
+        const uint64_t want = ((uint64_t)u << gbits) | (key & gmask);
+        int64_t lo = 0, hi = W;  // first winner with key >= want
+        while (lo < hi) {
+            const int64_t mid = lo + (hi - lo) / 2;
+            if ((uint64_t)wk[mid] < want) lo = mid + 1;
+            else hi = mid;
+        }
+        const int64_t c = lo - 1;
+        nxt[r] = (c >= 0 && (int32_t)((uint64_t)wk[c] >> gbits) == u) ? (int32_t)c : -1;
+        val[r] = u;
+    }
+}
+
+// One pointer-jumping round: a winner whose link is resolved takes its label; any other
+// skips to its link's link.
+__global__ void __launch_bounds__(kSqThreads) k_sq_jump(const int32_t *__restrict__ nxt,
+                                                        const int32_t *__restrict__ val,
+                                                        const uint32_t *__restrict__ wcount,
+                                                        int32_t *__restrict__ nxt2, int32_t *__restrict__ val2) {
+    const int64_t W = *wcount;
+    SQ_LOOP(r, W) {
+        const int32_t a = nxt[r];
+        if (a < 0) {
+            nxt2[r] = -1;
+            val2[r] = val[r];
+        } else {
+            const int32_t b = nxt[a];
+            nxt2[r] = b < 0 ? -1 : b;
+            val2[r] = b < 0 ? val[a] : val[r];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kSqThreads) k_sq_init(int32_t n, int32_t rows, int32_t *__restrict__ labels,
+                                                        int32_t *__restrict__ pass_labels,
+                                                        const uint32_t *__restrict__ beg,
+                                                        const uint32_t *__restrict__ end,
+                                                        int32_t *__restrict__ degree) {
+    SQ_LOOP(v, n) {
+        labels[v] = (int32_t)v;
+        degree[v] = (int32_t)(end[v] - beg[v]);
+        for (int32_t p = 0; p < rows; ++p) pass_labels[(int64_t)p * n + v] = (int32_t)v;
+    }
+}
+
+// A node's label after pass p: the label of its last winner in a chunk of passes 0..p.
+template <class KT>
+__global__ void __launch_bounds__(kSqThreads) k_sq_labels(const KT *__restrict__ wk,
+                                                          const uint32_t *__restrict__ wcount, int gbits,
+                                                          int64_t nchunk, int32_t P, const int32_t *__restrict__ val,
+                                                          int32_t n, int32_t *__restrict__ labels,
+                                                          int32_t *__restrict__ pass_labels) {
+    const int64_t W = *wcount;
+    SQ_LOOP(r, W) {
+        const uint64_t key = (uint64_t)wk[r];
+        const uint64_t gmask = gbits >= 64 ? ~0ull : ((1ull << gbits) - 1ull);
+        const int32_t v = (int32_t)(key >> gbits);
+        const bool more = r + 1 < W && (int32_t)((uint64_t)wk[r + 1] >> gbits) == v;
+        if (!more) labels[v] = val[r];
+        if (pass_labels) {
+            const int32_t p0 = (int32_t)((key & gmask) / (uint64_t)nchunk);
+            const int32_t p1 = more ? (int32_t)(((uint64_t)wk[r + 1] & gmask) / (uint64_t)nchunk) : P;
+            for (int32_t p = p0; p < p1; ++p) pass_labels[(int64_t)p * n + v] = val[r];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kSqThreads) k_sq_volume(const int32_t *__restrict__ labels,
+                                                          const int32_t *__restrict__ degree, int32_t n,
+                                                          unsigned long long *__restrict__ volume) {
+    SQ_LOOP(v, n) {
+        const int32_t d = degree[v];
+        if (d) atomicAdd(&volume[labels[v]], (unsigned long long)d);
+    }
+}
+
+// ------------------------------------------------------------------- driver ----
+template <class KT>
+static bgv_status sq_sort_events(SqWs &w, int64_t pm, int nbits, KT **sk, uint32_t **sv, hipStream_t s);
+
+template <>
+bgv_status sq_sort_events<uint32_t>(SqWs &w, int64_t pm, int nbits, uint32_t **sk, uint32_t **sv, hipStream_t s) {
+    return radix_sort_u32(static_cast<uint32_t *>(w.evk), static_cast<uint32_t *>(w.evk_alt), w.evv, w.evv_alt, pm,
+                          nbits, sk, sv, w.sort_scratch, s, false, w.tot64);
+}
+
+template <>
+bgv_status sq_sort_events<uint64_t>(SqWs &w, int64_t pm, int nbits, uint64_t **sk, uint32_t **sv, hipStream_t s) {
+    return radix_sort_u64(static_cast<uint64_t *>(w.evk), static_cast<uint64_t *>(w.evk_alt), w.evv, w.evv_alt, pm,
+                          nbits, sk, sv, w.sort_scratch, s, false, w.tot64);
+}
+
+template <class KT>
+static bgv_status sq_events(const int2 *e2, int32_t n, int64_t m, const bgv_cd_params *p, SqWs &w, int32_t *labels,
+                            int32_t *pass_labels, hipStream_t s) {
+    const int32_t P = p->passes;
+    const int64_t B = p->chunk, nchunk = (m + B - 1) / B, pm = (int64_t)P * m;
+    const int gbits = bits_for((uint64_t)P * (uint64_t)nchunk - 1);
+    const int nbits = std::max(1, bits_for((uint64_t)(n - 1)) + gbits);
+    const unsigned grid = grid_for(pm, kSqThreads, 65536);
+    // proposals of every pass, in (pass, stream) order
+    BGV_LAUNCH(k_sq_flags, dim3(grid), dim3(kSqThreads), 0, s, e2, w.cd, m, P, p->threshold, p->growth, w.flag);
+    BGV_TRY(exclusive_scan_u32(w.flag, w.flag, pm, w.tot, w.scan_scratch, s));
+    BGV_LAUNCH(k_sq_emit<KT>, dim3(grid), dim3(kSqThreads), 0, s, e2, w.cd, m, P, p->threshold, p->growth, B, nchunk,
+               gbits, w.flag, static_cast<KT *>(w.evk), w.evv);
+    BGV_LAUNCH(k_sq_widen, dim3(1), dim3(kSqThreads), 0, s, w.tot, w.tot64);
+    KT *sk = nullptr;
+    uint32_t *sv = nullptr;
+    BGV_TRY(sq_sort_events<KT>(w, pm, nbits, &sk, &sv, s));
+    // winners: first of each (target, chunk) run
+    BGV_LAUNCH(k_sq_first<KT>, dim3(grid), dim3(kSqThreads), 0, s, sk, pm, w.tot, w.flag);
+    BGV_TRY(exclusive_scan_u32(w.flag, w.flag, pm, w.tot + 1, w.scan_scratch, s));
+    KT *wk = static_cast<KT *>(w.wk);
+    BGV_LAUNCH(k_sq_compact<KT>, dim3(grid), dim3(kSqThreads), 0, s, sk, sv, w.tot, w.flag, wk, w.wv);
+    BGV_LAUNCH(k_sq_links<KT>, dim3(grid), dim3(kSqThreads), 0, s, e2, wk, w.wv, w.tot + 1, gbits, w.nxt, w.val);
+    // a chain of links visits at most one winner per chunk: ceil(log2 chunks) + 1 rounds
+    const int rounds = bits_for((uint64_t)P * (uint64_t)nchunk) + 1;
+    int32_t *nx = w.nxt, *vl = w.val, *nx2 = w.nxt2, *vl2 = w.val2;
+    for (int r = 0; r < rounds; ++r) {
+        BGV_LAUNCH(k_sq_jump, dim3(grid), dim3(kSqThreads), 0, s, nx, vl, w.tot + 1, nx2, vl2);
+        std::swap(nx, nx2);
+        std::swap(vl, vl2);
+    }
+    BGV_LAUNCH(k_sq_labels<KT>, dim3(grid), dim3(kSqThreads), 0, s, wk, w.tot + 1, gbits, nchunk, P, vl, n, labels,
+               pass_labels);
+    return BGV_OK;
+}
+
+bgv_status sq_run(int32_t n, int64_t m, const int32_t *edges, const bgv_cd_params *p, int32_t *labels,
+                  int32_t *degree, int64_t *volume, int32_t *pass_labels, void *ws, hipStream_t s) {
+    Carver c(ws);
+    SqWs w;
+    sq_layout(c, n, m, p, &w);
+    const int2 *e2 = reinterpret_cast<const int2 *>(edges);
+    const int64_t no = 2 * m;
+    const unsigned go = grid_for(no, kSqThreads, 65536), gn = grid_for(n, kSqThreads, 65536);
+    BGV_LAUNCH(k_sq_occ, dim3(grid_for(m, kSqThreads, 65536)), dim3(kSqThreads), 0, s, e2, m, n, w.okey, w.oval);
+    uint32_t *sk = nullptr, *sv = nullptr;
+    BGV_TRY(radix_sort_u32(w.okey, w.okey_alt, w.oval, w.oval_alt, no, bits_for((uint64_t)n), &sk, &sv,
+                           w.sort_scratch, s));
+    BGV_TRY(fill<uint32_t>(w.beg, 0u, n, s));
+    BGV_TRY(fill<uint32_t>(w.end, 0u, n, s));
+    BGV_LAUNCH(k_sq_runs, dim3(go), dim3(kSqThreads), 0, s, sk, no, n, w.beg, w.end);
+    BGV_LAUNCH(k_sq_counts, dim3(go), dim3(kSqThreads), 0, s, sk, sv, no, n, w.beg, w.end, m, p->chunk, w.cd);
+    BGV_LAUNCH(k_sq_init, dim3(gn), dim3(kSqThreads), 0, s, n, pass_labels ? p->passes : 0, labels, pass_labels,
+               w.beg, w.end, degree);
+    if (sq_wide(n, m, p))
+        BGV_TRY(sq_events<uint64_t>(e2, n, m, p, w, labels, pass_labels, s));
+    else
+        BGV_TRY(sq_events<uint32_t>(e2, n, m, p, w, labels, pass_labels, s));
+    if (volume)
+        BGV_LAUNCH(k_sq_volume, dim3(gn), dim3(kSqThreads), 0, s, labels, degree, n,
+                   reinterpret_cast<unsigned long long *>(volume));
+    return BGV_OK;
+}
+
+}  // namespace bgv

@@ -45,8 +45,20 @@ def test_community_validation_and_workspace():
     assert L.bgv_community_workspace(2000, 10000, C.byref(p3)) >= ws + 8 * 10000  # pass-0 counters per edge
     big = L.bgv_community_workspace((1 << 24) + 1, 100, C.byref(p))  # per-node atomic form
     assert big >= ((1 << 24) + 1) * 16
+    # methods: back-pointer resolution needs more workspace; automatic picks it past 64 chunk steps
+    m1 = L.bgv_community_workspace(2000, 10000, C.byref(L.CdParams(16, 3, 2, 1, 100)))
+    m2 = L.bgv_community_workspace(2000, 10000, C.byref(L.CdParams(16, 3, 2, 2, 100)))
+    assert 0 < m1 < m2 and m2 >= 48 * 10000 + 3 * 10000 * 40
+    assert L.bgv_community_workspace(2000, 10000, C.byref(L.CdParams(16, 3, 2, 0, 100))) == m2   # 300 steps
+    assert L.bgv_community_workspace(2000, 10000, C.byref(L.CdParams(16, 3, 2, 0, 2000))) == \
+        L.bgv_community_workspace(2000, 10000, C.byref(L.CdParams(16, 3, 2, 1, 2000)))         # 15 steps
+    # passes * m must stay below 2^31 for method 2 (automatic then keeps method 1)
+    assert L.bgv_community_workspace(10, 2**30, C.byref(L.CdParams(4, 2, 2, 2, 1))) == 0
+    assert L.bgv_community_workspace(10, 2**30, C.byref(L.CdParams(4, 2, 2, 0, 1))) == \
+        L.bgv_community_workspace(10, 2**30, C.byref(L.CdParams(4, 2, 2, 1, 1)))
     for bad in [L.CdParams(-1, 1, 2, 0, 1), L.CdParams(1, 0, 2, 0, 1), L.CdParams(1, 1, 0, 0, 1),
-                L.CdParams(1, 1, 2, 0, 0), L.CdParams(1, 1, 2, 7, 1)]:
+                L.CdParams(1, 1, 2, 0, 0), L.CdParams(1, 1, 2, 7, 1), L.CdParams(1, 1, 2, 3, 1),
+                L.CdParams(1, 1, 2, -1, 1)]:
         assert L.bgv_community_workspace(10, 10, C.byref(bad)) == 0
         assert L.bgv_community(10, 10, C.c_void_p(1), C.byref(bad), C.c_void_p(1), C.c_void_p(1), None,
                                None, 0, None) == -1

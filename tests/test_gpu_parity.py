@@ -64,16 +64,21 @@ def sketch_coefs(rows, seed):
 
 
 # --------------------------------------------------------------- community -------
-def check_community(bgv, n, e, D, P, f, B):
-    say(f"  community n={n} m={len(e)} D={D} P={P} f={f} B={B}")
+def check_community(bgv, n, e, D, P, f, B, methods=(1, 2)):
+    """Both methods (chunk by chunk, back-pointer resolution) against the oracle; the
+    second needs at least one edge."""
     lab_r, cnt_r = oracle.bs_community(n, e, D, P, f, B)
     deg_r, vol_r = oracle.degree_volume(lab_r, cnt_r, P)
     ed = dev(e.reshape(-1, 2).astype(np.int32))
-    lab, deg, vol = bgv.community(ed, n, D, P, f, B, volume=True)
-    torch.cuda.synchronize()
-    np.testing.assert_array_equal(host(lab), lab_r)
-    np.testing.assert_array_equal(host(deg), deg_r)
-    np.testing.assert_array_equal(host(vol), vol_r)
+    for method in methods:
+        if method == 2 and len(e) == 0:
+            continue
+        say(f"  community n={n} m={len(e)} D={D} P={P} f={f} B={B} method={method}")
+        lab, deg, vol = bgv.community(ed, n, D, P, f, B, volume=True, method=method)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(host(lab), lab_r)
+        np.testing.assert_array_equal(host(deg), deg_r)
+        np.testing.assert_array_equal(host(vol), vol_r)
     return lab_r, deg_r
 
 
@@ -121,21 +126,24 @@ def test_community_at_and_above_bucket_limit(bgv, n):
 
 
 def check_passes(bgv, n, e, D, P, f, B):
-    """Row p of the per-pass labels equals the labels of a (p+1)-pass run."""
-    say(f"  community passes n={n} m={len(e)} D={D} P={P} f={f} B={B}")
+    """Row p of the per-pass labels equals the labels of a (p+1)-pass run (both methods)."""
     ed = dev(e.reshape(-1, 2).astype(np.int32))
-    lab, deg, vol, rows = bgv.community_passes(ed, n, D, P, f, B, volume=True)
-    torch.cuda.synchronize()
-    rows = host(rows)
-    assert rows.shape == (P, n)
-    for q in range(P):
-        lab_r, _ = oracle.bs_community(n, e, D, q + 1, f, B)
-        np.testing.assert_array_equal(rows[q], lab_r, err_msg=f"pass {q}")
+    ref_rows = [oracle.bs_community(n, e, D, q + 1, f, B)[0] for q in range(P)]
     lab_r, cnt_r = oracle.bs_community(n, e, D, P, f, B)
     deg_r, vol_r = oracle.degree_volume(lab_r, cnt_r, P)
-    np.testing.assert_array_equal(host(lab), lab_r)
-    np.testing.assert_array_equal(host(deg), deg_r)
-    np.testing.assert_array_equal(host(vol), vol_r)
+    for method in (1, 2):
+        if method == 2 and len(e) == 0:
+            continue
+        say(f"  community passes n={n} m={len(e)} D={D} P={P} f={f} B={B} method={method}")
+        lab, deg, vol, rows = bgv.community_passes(ed, n, D, P, f, B, volume=True, method=method)
+        torch.cuda.synchronize()
+        rows = host(rows)
+        assert rows.shape == (P, n)
+        for q in range(P):
+            np.testing.assert_array_equal(rows[q], ref_rows[q], err_msg=f"pass {q}")
+        np.testing.assert_array_equal(host(lab), lab_r)
+        np.testing.assert_array_equal(host(deg), deg_r)
+        np.testing.assert_array_equal(host(vol), vol_r)
 
 
 def test_community_pass_labels(bgv):
@@ -159,6 +167,21 @@ def test_community_pass_labels(bgv):
     ids = np.concatenate([rng.integers(0, 3000, 2000), rng.integers(n - 3000, n, 2000)])
     e = ids[rng.integers(0, len(ids), (20_000, 2))].astype(np.int32)
     check_passes(bgv, n, e, 6, 3, 2, 2500)
+
+
+def test_community_sequential_rule_by_back_pointers(bgv):
+    """chunk = 1 (the sequential rule: one chunk per edge) on streams of tens of
+    thousands of edges, which the back-pointer method resolves in a few dozen launches;
+    the automatic choice takes it there."""
+    rng = np.random.default_rng(37)
+    for n, m, P, D in ((3000, 40_000, 3, 8), (50_000, 120_000, 2, 4), (700, 30_000, 4, 30)):
+        e = rng.integers(0, n, (m, 2)).astype(np.int32)
+        hubs = rng.random(m) < 0.1
+        e[hubs, 0] = rng.integers(0, 16, int(hubs.sum()))
+        loop = rng.random(m) < 0.01
+        e[loop, 1] = e[loop, 0]
+        check_community(bgv, n, e, D, P, 2, 1, methods=(0,))
+        check_community(bgv, n, e, D, P, 2, 7, methods=(0,))
 
 
 @pytest.fixture(scope="module")
