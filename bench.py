@@ -217,6 +217,7 @@ def main():
         torch.cuda.empty_cache()
         out["forms"] = {"whole_graph_fa2": whole_graph_form(torch, bgv, edges_np, n, wl, cd + fa_unprofiled),
                         "sequential_rule": sequential_rule_form(torch, bgv, edges_np, n, wl, not args.no_cpu),
+                        "sweeps": sweeps_form(torch, bgv, graphgen, edges_np, n, wl),
                         "small_graph": small_graph_form(torch, bgv, graphgen),
                         "batched": batched_form(torch, bgv, graphgen),
                         "gradient": gradient_form(torch, bgv, graphgen),
@@ -441,6 +442,53 @@ def sequential_rule_form(torch, bgv, edges_np, n, wl, with_cpu):
         cpu_ms = (time.perf_counter() - t) * 1000.0
         out.update(cpu_oracle_ms=cpu_ms, cpu_threads=1, speedup_vs_oracle=cpu_ms / ms)
     return out
+
+
+def sweep_points(wl):
+    """The paper's sensitivity study on this workload: hash functions (sketch rows) 1-4,
+    rounds (passes) 2-4, threshold delta / 3 delta / 5 delta and sketch widths 5,000 and
+    15,000 beside the workload's own, one parameter changed at a time."""
+    d = wl["threshold"]
+    return ([("rows", r) for r in (1, 2, 3, 4)] + [("passes", p) for p in (2, 3, 4)] +
+            [("threshold", k * d) for k in (1, 3, 5)] + [("cols", c) for c in (5000, 15000, wl["cols"])])
+
+
+def sweeps_form(torch, bgv, graphgen, edges_np, n, wl):
+    """Time (community passes + supergraph + Barnes-Hut layout of the supergraph),
+    supernodes and superedges at each sweep point: the columns of the paper's
+    hash-function and rounds tables."""
+    dev = torch.device("cuda:0")
+    ed = torch.from_numpy(np.ascontiguousarray(edges_np)).to(dev)
+    pos0 = torch.from_numpy(graphgen_initial(n, wl)).to(dev)
+    rows = []
+    for key, value in sweep_points(wl):
+        w = dict(wl)
+        w[key] = value
+        c1 = graphgen.hash_coeffs(w["rows"], w["sketch_seed"])
+        c2 = graphgen.hash_coeffs(w["rows"], w["sketch_seed"] ^ 0x9E3779B97F4A7C15)
+        bgv.pipeline(ed, n, w, c1, c2, pos0)  # warm-up (workspaces, code paths)
+        torch.cuda.synchronize()
+        res = {}
+        ms = _timed(torch, lambda: res.update(bgv.pipeline(ed, n, w, c1, c2, pos0)))
+        row = {"param": key, "value": value, "ms": ms, "supernodes": int(res["sg"]["K"]),
+               "superedges": int(res["sg"]["E"])}
+        # what the sketch parameters change: the estimates' relative overestimate of the
+        # exact supernode sizes (community volumes) and superedge multiplicities (untimed)
+        lab, deg, vol = bgv.community(ed, n, w["threshold"], w["passes"], w["growth"], w["chunk"], volume=True)
+        sg = bgv.supergraph(ed, lab, deg, w["rows"], w["cols"], c1, c2, exact_counts=True)
+        size = sg["super_size"].to(torch.int64) & 0xFFFFFFFF
+        exact = vol[sg["super_label"].to(torch.int64)]
+        se_w = sg["se_weight"].to(torch.int64) & 0xFFFFFFFF
+        se_c = sg["se_count"].to(torch.int64) & 0xFFFFFFFF
+        rs = (size - exact).double() / exact.clamp(min=1).double()
+        rw = (se_w - se_c).double() / se_c.clamp(min=1).double()
+        row.update(size_overestimate_mean=float(rs.mean()), size_overestimate_max=float(rs.max()),
+                   weight_overestimate_mean=float(rw.mean()) if rw.numel() else 0.0,
+                   weight_overestimate_max=float(rw.max()) if rw.numel() else 0.0)
+        rows.append(row)
+    del ed, pos0
+    torch.cuda.empty_cache()
+    return rows
 
 
 def graphgen_initial(n, wl):

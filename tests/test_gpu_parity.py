@@ -184,6 +184,27 @@ def test_community_sequential_rule_by_back_pointers(bgv):
         check_community(bgv, n, e, D, P, 2, 7, methods=(0,))
 
 
+def test_parameter_sweeps_match_oracle(bgv):
+    """The bench's sweep points (sketch rows 1-4, passes 2-4, threshold x1/x3/x5, sketch
+    widths 5,000 / 15,000), on an LFR-style graph of 20,000 nodes and 200,000 edges: the
+    community and supergraph integers of every point bit-exact against the oracle."""
+    import bench
+    e, _ = graphgen.lfr_style(20_000, 200_000, 2.3, 1.5, 0.2, 77)
+    n = 20_000
+    wl = dict(graphgen.WORKLOADS["lfr_1m"], n=n, threshold=16, chunk=16_384, cols=1 << 14)
+    ed = dev(e)
+    for key, value in bench.sweep_points(wl):
+        w = dict(wl)
+        w[key] = value
+        say(f"  sweep {key}={value}")
+        lab_r, cnt_r = oracle.bs_community(n, e, w["threshold"], w["passes"], w["growth"], w["chunk"])
+        deg_r, _ = oracle.degree_volume(lab_r, cnt_r, w["passes"])
+        lab, deg, _ = bgv.community(ed, n, w["threshold"], w["passes"], w["growth"], w["chunk"])
+        np.testing.assert_array_equal(host(lab), lab_r)
+        np.testing.assert_array_equal(host(deg), deg_r)
+        check_supergraph(bgv, n, e, lab_r, deg_r, w["rows"], w["cols"], w["sketch_seed"])
+
+
 @pytest.fixture(scope="module")
 def planted():
     wl = graphgen.WORKLOADS["planted_2k"]
