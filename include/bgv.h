@@ -82,6 +82,9 @@ typedef struct {
     int32_t growth;    /* >= 1: threshold factor between passes                   */
     int32_t method;    /* 0 automatic, 1 chunk by chunk, 2 back-pointer resolution */
     int64_t chunk;     /* >= 1: edges per synchronous chunk                        */
+    int32_t tie;       /* 0: equal counters do nothing (Algorithm 3's nested tests);
+                          1: the edge's first endpoint joins the second's community  */
+    int32_t reserved;  /* must be 0                                              */
 } bgv_cd_params;
 
 /* Workspace bytes for bgv_community (0 only on invalid arguments).  Up to 2^24 nodes:

@@ -45,7 +45,8 @@ static int32_t orc_threshold(int32_t D1, int32_t growth, int32_t p)
  * Rule (Section 3.2): every streamed edge raises the degree of both endpoints; if
  * both degrees are at most the threshold, the endpoint of smaller degree joins the
  * community of the endpoint of larger degree; equal degrees do nothing (the nesting
- * of the conditions in Algorithm 3).  Degrees are never reset between passes
+ * of the conditions in Algorithm 3), or, with tie = 1 (the variant where the stream's
+ * first endpoint joins the second's community on a tie), the first endpoint joins.  Degrees are never reset between passes
  * (Algorithm 3 initialises them once, before the round loop).  Self-loops are ignored.
  *
  * Batch-synchronous reading: within each pass the stream is cut into chunks of
@@ -59,10 +60,10 @@ static int32_t orc_threshold(int32_t D1, int32_t growth, int32_t p)
  * Returns 0, or -1 on bad arguments.
  */
 int orc_bs_community(int32_t n, int64_t m, const int32_t *edges, int32_t D1,
-                     int32_t passes, int32_t growth, int64_t chunk,
+                     int32_t passes, int32_t growth, int64_t chunk, int32_t tie,
                      int32_t *label, int32_t *counter)
 {
-    if (n <= 0 || m < 0 || passes < 1 || growth < 1 || chunk < 1 || D1 < 0) return -1;
+    if (n <= 0 || m < 0 || passes < 1 || growth < 1 || chunk < 1 || D1 < 0 || tie < 0 || tie > 1) return -1;
     int64_t *prop_edge = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
     int32_t *prop_label = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
     int32_t *touched = (int32_t *)malloc(sizeof(int32_t) * (size_t)(chunk < m ? chunk : (m > 0 ? m : 1)));
@@ -86,9 +87,11 @@ int orc_bs_community(int32_t n, int64_t m, const int32_t *edges, int32_t D1,
                 const int32_t u = edges[2 * i], v = edges[2 * i + 1];
                 if (u == v) continue;
                 const int32_t du = counter[u], dv = counter[v];
-                if (du > D || dv > D || du == dv) continue;
-                const int32_t x = (du < dv) ? u : v;   /* lower degree joins ...  */
-                const int32_t y = (du < dv) ? v : u;   /* ... the higher's community */
+                if (du > D || dv > D) continue;
+                if (du == dv && !tie) continue;
+                /* lower degree joins the higher's community; on a tie (tie = 1) u joins v */
+                const int32_t x = (du <= dv) ? u : v;
+                const int32_t y = (du <= dv) ? v : u;
                 if (prop_edge[x] < 0) {                /* first (smallest) index wins */
                     prop_edge[x] = i;
                     prop_label[x] = label[y];

@@ -11,8 +11,10 @@ multiplies the threshold by a constant factor each round.  Self-loops are ignore
 from __future__ import annotations
 
 
-def seq_scoda(n, edges, threshold, passes=1, growth=2):
-    """Return (labels, counters) as Python lists.  counters[v] = passes * degree(v)."""
+def seq_scoda(n, edges, threshold, passes=1, growth=2, tie=False):
+    """Return (labels, counters) as Python lists.  counters[v] = passes * degree(v).
+    tie: the variant where, on equal degrees, the edge's first endpoint joins the
+    community of the second (instead of nothing happening)."""
     label = list(range(n))
     deg = [0] * n
     D = threshold
@@ -31,4 +33,6 @@ def seq_scoda(n, edges, threshold, passes=1, growth=2):
                     label[u] = label[v]
                 elif deg[v] < deg[u]:
                     label[v] = label[u]
+                elif tie:
+                    label[u] = label[v]
     return label, deg

@@ -27,7 +27,7 @@ struct BtArgs {
     const int64_t *node_off, *edge_off;  // device, G+1
     const int32_t *order;                // device, G, or null for 0..G-1
     const int2 *edges;                   // concatenated, local ids
-    int32_t threshold, passes, growth;
+    int32_t threshold, passes, growth, tie;
     int64_t chunk;
     int32_t rows;
     uint32_t cols;
@@ -196,8 +196,8 @@ __global__ void __launch_bounds__(NT) k_batched(BtArgs a) {
                     int32_t target = -1;
                     if (e.x != e.y) {
                         const int32_t du = cnt[e.x], dv = cnt[e.y];
-                        if (du <= D && dv <= D && du != dv) {
-                            const bool u_low = du < dv;
+                        if (du <= D && dv <= D && (du != dv || a.tie)) {
+                            const bool u_low = du <= dv;  // a tie (rule 1): the first endpoint joins
                             target = u_low ? e.x : e.y;
                             const int32_t l = u_low ? lab[e.y] : lab[e.x];
                             __hip_atomic_fetch_min(&win[target], ((unsigned long long)i << 32) | (uint32_t)l,
@@ -681,6 +681,7 @@ static bool bt_valid(int32_t G, int64_t n_total, int64_t m_total, const bgv_cd_p
                      const bgv_sketch_params *sk, const bgv_fa2_params *fa) {
     return G >= 1 && n_total >= 0 && n_total <= INT32_MAX && m_total >= 0 && m_total <= INT32_MAX && cd && sk &&
            fa && cd->threshold >= 0 && cd->passes >= 1 && cd->growth >= 1 && cd->chunk >= 1 && cd->method == 0 &&
+           (cd->tie == 0 || cd->tie == 1) && cd->reserved == 0 &&
            sk->rows >= 1 && sk->rows <= kMaxRows && sk->cols >= 1 && (int64_t)sk->rows * sk->cols <= kBtMaxCells &&
            sk->coef1 && sk->coef2 && fa->iters >= 0 && fa->exact == 1 && fa->tau > 0.f && fa->ks >= 0.f &&
            fa->ksmax > 0.f;
@@ -739,6 +740,7 @@ extern "C" bgv_status bgv_batched(int32_t G, int64_t n_total, int64_t m_total, c
     a.threshold = cd->threshold;
     a.passes = cd->passes;
     a.growth = cd->growth;
+    a.tie = cd->tie;
     a.chunk = cd->chunk;
     a.rows = sk->rows;
     a.cols = (uint32_t)sk->cols;

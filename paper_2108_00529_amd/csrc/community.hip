@@ -94,7 +94,8 @@ template <int kMode>  // 0: only pass; 1: pass 0 of several; 2: a later pass
 __global__ void __launch_bounds__(kCdThreads) k_cd_decide(NodeState *__restrict__ st,
                                                            const int2 *__restrict__ edges,
                                                            int32_t *__restrict__ prop, int2 *__restrict__ c1,
-                                                           int64_t cs, int64_t ce, int32_t D, int32_t pass) {
+                                                           int64_t cs, int64_t ce, int32_t D, int32_t pass,
+                                                           int32_t tie) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = cs + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ce; i += stride) {
         const int2 e = edges[i];
@@ -109,8 +110,8 @@ __global__ void __launch_bounds__(kCdThreads) k_cd_decide(NodeState *__restrict_
                 cu = pass * su.x + c.x;
                 cv = pass * sv.x + c.y;
             }
-            if (cu <= D && cv <= D && cu != cv) {
-                const bool u_low = cu < cv;
+            if (cu <= D && cv <= D && (cu != cv || tie)) {
+                const bool u_low = cu <= cv;  // a tie (rule 1): the first endpoint joins
                 target = u_low ? e.x : e.y;
                 const int32_t lab = u_low ? sv.y : su.y;
                 atomicMin(reinterpret_cast<unsigned long long *>(&st[target].win),
@@ -232,8 +233,9 @@ template <int kMode>  // 0: only pass; 1: pass 0 of several; 2: a later pass
 __device__ __forceinline__ void cd_decide_tile(const int32_t *__restrict__ cnt, const int32_t *__restrict__ labv,
                                                const int2 *__restrict__ edges,
                                                int2 *__restrict__ c1, int64_t cs, int64_t ce, int32_t D,
-                                               int32_t pass, int32_t tile, int32_t nb, uint3 *__restrict__ props,
-                                               uint32_t *__restrict__ ptab, uint32_t *hist, uint3 *stage) {
+                                               int32_t pass, int32_t tie, int32_t tile, int32_t nb,
+                                               uint3 *__restrict__ props, uint32_t *__restrict__ ptab,
+                                               uint32_t *hist, uint3 *stage) {
     for (int32_t b = threadIdx.x; b < nb; b += kCdThreads) hist[b] = 0;
     __syncthreads();
     const int64_t t0 = cs + (int64_t)tile * kCdTile;
@@ -253,8 +255,8 @@ __device__ __forceinline__ void cd_decide_tile(const int32_t *__restrict__ cnt, 
                     cu = pass * cu + c.x;
                     cv = pass * cv + c.y;
                 }
-                if (cu <= D && cv <= D && cu != cv) {
-                    const bool u_low = cu < cv;
+                if (cu <= D && cv <= D && (cu != cv || tie)) {
+                    const bool u_low = cu <= cv;  // a tie (rule 1): the first endpoint joins
                     target[j] = u_low ? e.x : e.y;
                     lab[j] = labv[u_low ? e.y : e.x];
                     rank[j] = atomicAdd(&hist[target[j] >> kCdBucketBits], 1u);
@@ -283,7 +285,8 @@ __global__ void __launch_bounds__(kCdThreads) k_cd_step(const int32_t *__restric
                                                          const int32_t *__restrict__ labv,
                                                          const int2 *__restrict__ edges,
                                                          int2 *__restrict__ c1, int64_t cs, int64_t ce, int32_t D,
-                                                         int32_t pass, int32_t nb, uint3 *__restrict__ props,
+                                                         int32_t pass, int32_t tie, int32_t nb,
+                                                         uint3 *__restrict__ props,
                                                          uint32_t *__restrict__ ptab, int64_t gs, int64_t ge,
                                                          uint16_t *__restrict__ ends, uint32_t *__restrict__ etab) {
     __shared__ uint32_t hist[kCdMaxBuckets];
@@ -291,8 +294,8 @@ __global__ void __launch_bounds__(kCdThreads) k_cd_step(const int32_t *__restric
     __shared__ uint16_t estage[2 * kCdTile];
     const int32_t tile = (int32_t)blockIdx.x;
     if (kMode >= 0 && cs + (int64_t)tile * kCdTile < ce)  // uniform over the workgroup
-        cd_decide_tile<kMode < 0 ? 0 : kMode>(cnt, labv, edges, c1, cs, ce, D, pass, tile, nb, props, ptab, hist,
-                                              pstage);
+        cd_decide_tile<kMode < 0 ? 0 : kMode>(cnt, labv, edges, c1, cs, ce, D, pass, tie, tile, nb, props, ptab,
+                                              hist, pstage);
     if (gs + (int64_t)tile * kCdTile < ge) {
         __syncthreads();  // hist is reused
         cd_group_tile(edges, gs, ge, tile, nb, ends, etab, hist, estage);
@@ -388,7 +391,7 @@ static int32_t pass_threshold(int32_t D1, int32_t growth, int32_t p) {
 
 static bool cd_valid(int32_t n, int64_t m, const bgv_cd_params *p) {
     if (!(p && n >= 1 && m >= 0 && m <= INT32_MAX && p->threshold >= 0 && p->passes >= 1 && p->growth >= 1 &&
-          p->chunk >= 1 && p->method >= 0 && p->method <= 2))
+          p->chunk >= 1 && p->method >= 0 && p->method <= 2 && (p->tie == 0 || p->tie == 1) && p->reserved == 0))
         return false;
     return p->method != 2 || m == 0 || sq_fits(n, m, p);
 }
@@ -494,7 +497,7 @@ static bgv_status cd_run(int32_t n, int64_t m, const int32_t *edges, const bgv_c
             // pass 0, chunk 0: its endpoints grouped before anything is decided
             etiles = tiles_of(0);
             BGV_LAUNCH(k_cd_step<-1>, dim3(etiles), dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1, (int64_t)0, (int64_t)0,
-                       0, 0, nb, w.props, w.ptab, (int64_t)0, std::min<int64_t>(B, m), w.ends, w.etab);
+                       0, 0, 0, nb, w.props, w.ptab, (int64_t)0, std::min<int64_t>(B, m), w.ends, w.etab);
         }
         for (int32_t pass = 0; pass < p->passes && (m > 0 || pass_labels); ++pass) {
             const int32_t D = pass_threshold(p->threshold, p->growth, pass);
@@ -512,13 +515,13 @@ static bgv_status cd_run(int32_t n, int64_t m, const int32_t *edges, const bgv_c
                 const int32_t gtiles = group_next ? tiles_of(k + 1) : 0;
                 const dim3 grid((unsigned)std::max(tiles, gtiles));
                 if (p->passes == 1)
-                    BGV_LAUNCH(k_cd_step<0>, grid, dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1, cs, ce, D, pass, nb,
+                    BGV_LAUNCH(k_cd_step<0>, grid, dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1, cs, ce, D, pass, p->tie, nb,
                                w.props, w.ptab, gs, ge, w.ends, w.etab);
                 else if (pass == 0)
-                    BGV_LAUNCH(k_cd_step<1>, grid, dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1, cs, ce, D, pass, nb,
+                    BGV_LAUNCH(k_cd_step<1>, grid, dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1, cs, ce, D, pass, p->tie, nb,
                                w.props, w.ptab, gs, ge, w.ends, w.etab);
                 else
-                    BGV_LAUNCH(k_cd_step<2>, grid, dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1, cs, ce, D, pass, nb,
+                    BGV_LAUNCH(k_cd_step<2>, grid, dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1, cs, ce, D, pass, p->tie, nb,
                                w.props, w.ptab, gs, ge, w.ends, w.etab);
                 ptiles = tiles;
                 etiles = gtiles;
@@ -557,11 +560,11 @@ static bgv_status cd_run(int32_t n, int64_t m, const int32_t *edges, const bgv_c
                            st, e2, prop, ps, pe, hs, he);
             const dim3 grid(grid_for(ce - cs, kCdThreads * 4, 16384));
             if (p->passes == 1)
-                BGV_LAUNCH(k_cd_decide<0>, grid, dim3(kCdThreads), 0, s, st, e2, prop, c1, cs, ce, D, pass);
+                BGV_LAUNCH(k_cd_decide<0>, grid, dim3(kCdThreads), 0, s, st, e2, prop, c1, cs, ce, D, pass, p->tie);
             else if (pass == 0)
-                BGV_LAUNCH(k_cd_decide<1>, grid, dim3(kCdThreads), 0, s, st, e2, prop, c1, cs, ce, D, pass);
+                BGV_LAUNCH(k_cd_decide<1>, grid, dim3(kCdThreads), 0, s, st, e2, prop, c1, cs, ce, D, pass, p->tie);
             else
-                BGV_LAUNCH(k_cd_decide<2>, grid, dim3(kCdThreads), 0, s, st, e2, prop, c1, cs, ce, D, pass);
+                BGV_LAUNCH(k_cd_decide<2>, grid, dim3(kCdThreads), 0, s, st, e2, prop, c1, cs, ce, D, pass, p->tie);
             ps = cs;
             pe = ce;
         }

@@ -160,35 +160,36 @@ __global__ void __launch_bounds__(kSqThreads) k_sq_counts(const uint32_t *__rest
 }
 
 // Target of edge e in pass p (threshold D), or -1: both counters at most D and unequal,
-// the endpoint with the smaller one is the target.
-__device__ __forceinline__ int32_t sq_target(int2 e, int4 c, int32_t p, int32_t D) {
+// the endpoint with the smaller one is the target; equal ones with tie rule 1: e.x.
+__device__ __forceinline__ int32_t sq_target(int2 e, int4 c, int32_t p, int32_t D, int32_t tie) {
     if (e.x == e.y) return -1;
     const int32_t cu = p * c.z + c.x, cv = p * c.w + c.y;
-    if (cu <= D && cv <= D && cu != cv) return cu < cv ? e.x : e.y;
+    if (cu <= D && cv <= D && (cu != cv || tie)) return cu <= cv ? e.x : e.y;
     return -1;
 }
 
 // flag[p m + i] = edge i proposes in pass p
 __global__ void __launch_bounds__(kSqThreads) k_sq_flags(const int2 *__restrict__ edges, const int4 *__restrict__ cd,
                                                          int64_t m, int32_t P, int32_t D1, int32_t growth,
-                                                         uint32_t *__restrict__ flag) {
+                                                         int32_t tie, uint32_t *__restrict__ flag) {
     SQ_LOOP(t, (int64_t)P * m) {
         const int32_t p = (int32_t)(t / m);
         const int64_t i = t - (int64_t)p * m;
-        flag[t] = sq_target(edges[i], cd[i], p, sq_threshold(D1, growth, p)) >= 0 ? 1u : 0u;
+        flag[t] = sq_target(edges[i], cd[i], p, sq_threshold(D1, growth, p), tie) >= 0 ? 1u : 0u;
     }
 }
 
 // Proposal (p, i) at its place pos[p m + i]: key (target, global chunk), value i.
 template <class KT>
 __global__ void __launch_bounds__(kSqThreads) k_sq_emit(const int2 *__restrict__ edges, const int4 *__restrict__ cd,
-                                                        int64_t m, int32_t P, int32_t D1, int32_t growth, int64_t B,
+                                                        int64_t m, int32_t P, int32_t D1, int32_t growth,
+                                                        int32_t tie, int64_t B,
                                                         int64_t nchunk, int gbits, const uint32_t *__restrict__ pos,
                                                         KT *__restrict__ key, uint32_t *__restrict__ val) {
     SQ_LOOP(t, (int64_t)P * m) {
         const int32_t p = (int32_t)(t / m);
         const int64_t i = t - (int64_t)p * m;
-        const int32_t v = sq_target(edges[i], cd[i], p, sq_threshold(D1, growth, p));
+        const int32_t v = sq_target(edges[i], cd[i], p, sq_threshold(D1, growth, p), tie);
         if (v < 0) continue;
         const uint64_t g = (uint64_t)p * (uint64_t)nchunk + (uint64_t)(i / B);
         const uint32_t q = pos[t];
@@ -339,9 +340,11 @@ static bgv_status sq_events(const int2 *e2, int32_t n, int64_t m, const bgv_cd_p
     const int nbits = std::max(1, bits_for((uint64_t)(n - 1)) + gbits);
     const unsigned grid = grid_for(pm, kSqThreads, 65536);
     // proposals of every pass, in (pass, stream) order
-    BGV_LAUNCH(k_sq_flags, dim3(grid), dim3(kSqThreads), 0, s, e2, w.cd, m, P, p->threshold, p->growth, w.flag);
+    BGV_LAUNCH(k_sq_flags, dim3(grid), dim3(kSqThreads), 0, s, e2, w.cd, m, P, p->threshold, p->growth, p->tie,
+               w.flag);
     BGV_TRY(exclusive_scan_u32(w.flag, w.flag, pm, w.tot, w.scan_scratch, s));
-    BGV_LAUNCH(k_sq_emit<KT>, dim3(grid), dim3(kSqThreads), 0, s, e2, w.cd, m, P, p->threshold, p->growth, B, nchunk,
+    BGV_LAUNCH(k_sq_emit<KT>, dim3(grid), dim3(kSqThreads), 0, s, e2, w.cd, m, P, p->threshold, p->growth, p->tie, B,
+               nchunk,
                gbits, w.flag, static_cast<KT *>(w.evk), w.evv);
     BGV_LAUNCH(k_sq_widen, dim3(1), dim3(kSqThreads), 0, s, w.tot, w.tot64);
     KT *sk = nullptr;

@@ -95,6 +95,24 @@ def test_batched_equals_plain_and_oracle(bgv, batch):
         assert np.array_equal(b["fprev"], host(f)) and b["speed"] == float(s)
 
 
+def test_batched_tie_rule(bgv, batch):
+    """The tie-rule variant in the batched form: every graph's labels and degrees equal
+    the oracle's with the same rule."""
+    wl, graphs, c1, c2, pos0 = batch
+    w = dict(wl, tie=1)
+    out, noff, eoff = run_batched(bgv, w, graphs, c1, c2, pos0, iters=2)
+    moved = 0
+    for g, (n, e, _) in enumerate(graphs):
+        r = per_graph(out, noff, eoff, g)
+        lab_r, cnt_r = oracle.bs_community(n, e, w["threshold"], w["passes"], w["growth"], w["chunk"], 1)
+        deg_r, _ = oracle.degree_volume(lab_r, cnt_r, w["passes"])
+        np.testing.assert_array_equal(r["labels"], lab_r)
+        np.testing.assert_array_equal(r["degree"], deg_r)
+        lab0, _ = oracle.bs_community(n, e, w["threshold"], w["passes"], w["growth"], w["chunk"], 0)
+        moved += int(not np.array_equal(lab0, lab_r))
+    assert moved > 0  # the rule changed some graph's communities
+
+
 def test_batched_last_step_matches_oracle(bgv, batch):
     wl, graphs, c1, c2, pos0 = batch
     T = wl["fa2_iters"]

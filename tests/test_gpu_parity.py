@@ -64,17 +64,17 @@ def sketch_coefs(rows, seed):
 
 
 # --------------------------------------------------------------- community -------
-def check_community(bgv, n, e, D, P, f, B, methods=(1, 2)):
+def check_community(bgv, n, e, D, P, f, B, methods=(1, 2), tie=0):
     """Both methods (chunk by chunk, back-pointer resolution) against the oracle; the
     second needs at least one edge."""
-    lab_r, cnt_r = oracle.bs_community(n, e, D, P, f, B)
+    lab_r, cnt_r = oracle.bs_community(n, e, D, P, f, B, tie)
     deg_r, vol_r = oracle.degree_volume(lab_r, cnt_r, P)
     ed = dev(e.reshape(-1, 2).astype(np.int32))
     for method in methods:
         if method == 2 and len(e) == 0:
             continue
-        say(f"  community n={n} m={len(e)} D={D} P={P} f={f} B={B} method={method}")
-        lab, deg, vol = bgv.community(ed, n, D, P, f, B, volume=True, method=method)
+        say(f"  community n={n} m={len(e)} D={D} P={P} f={f} B={B} method={method} tie={tie}")
+        lab, deg, vol = bgv.community(ed, n, D, P, f, B, volume=True, method=method, tie=tie)
         torch.cuda.synchronize()
         np.testing.assert_array_equal(host(lab), lab_r)
         np.testing.assert_array_equal(host(deg), deg_r)
@@ -125,17 +125,17 @@ def test_community_at_and_above_bucket_limit(bgv, n):
     check_community(bgv, n, e, 8, 2, 2, 3000)
 
 
-def check_passes(bgv, n, e, D, P, f, B):
+def check_passes(bgv, n, e, D, P, f, B, tie=0):
     """Row p of the per-pass labels equals the labels of a (p+1)-pass run (both methods)."""
     ed = dev(e.reshape(-1, 2).astype(np.int32))
-    ref_rows = [oracle.bs_community(n, e, D, q + 1, f, B)[0] for q in range(P)]
-    lab_r, cnt_r = oracle.bs_community(n, e, D, P, f, B)
+    ref_rows = [oracle.bs_community(n, e, D, q + 1, f, B, tie)[0] for q in range(P)]
+    lab_r, cnt_r = oracle.bs_community(n, e, D, P, f, B, tie)
     deg_r, vol_r = oracle.degree_volume(lab_r, cnt_r, P)
     for method in (1, 2):
         if method == 2 and len(e) == 0:
             continue
         say(f"  community passes n={n} m={len(e)} D={D} P={P} f={f} B={B} method={method}")
-        lab, deg, vol, rows = bgv.community_passes(ed, n, D, P, f, B, volume=True, method=method)
+        lab, deg, vol, rows = bgv.community_passes(ed, n, D, P, f, B, volume=True, method=method, tie=tie)
         torch.cuda.synchronize()
         rows = host(rows)
         assert rows.shape == (P, n)
@@ -167,6 +167,29 @@ def test_community_pass_labels(bgv):
     ids = np.concatenate([rng.integers(0, 3000, 2000), rng.integers(n - 3000, n, 2000)])
     e = ids[rng.integers(0, len(ids), (20_000, 2))].astype(np.int32)
     check_passes(bgv, n, e, 6, 3, 2, 2500)
+
+
+def test_community_tie_rule(bgv):
+    """The tie-rule variant (equal counters: the edge's first endpoint joins the
+    second's community) through every decision path: random small streams and several
+    buckets with both methods, per-pass labels, and the per-node atomic form."""
+    rng = np.random.default_rng(41)
+    for trial in range(16):
+        n = int(rng.integers(2, 60))
+        m = int(rng.integers(1, 400))
+        e = graphgen.random_tiny_graph(rng, n, m)
+        B = int(rng.choice([1, 3, 17, 1000]))
+        check_community(bgv, n, e, int(rng.integers(1, 20)), int(rng.integers(1, 4)), 2, B, tie=1)
+    n = 3 * 4096 + 17
+    e = rng.integers(0, n, (50_000, 2)).astype(np.int32)
+    e[rng.random(len(e)) < 0.05, 0] = 4095
+    for B, P in ((5000, 3), (len(e), 2)):
+        check_community(bgv, n, e, 6, P, 2, B, tie=1)
+    check_passes(bgv, 2000, rng.integers(0, 2000, (20_000, 2)).astype(np.int32), 5, 3, 2, 1500, tie=1)
+    n = (1 << 24) + 99
+    ids = np.concatenate([rng.integers(0, 3000, 2000), rng.integers(n - 3000, n, 2000)])
+    e = ids[rng.integers(0, len(ids), (20_000, 2))].astype(np.int32)
+    check_community(bgv, n, e, 6, 2, 2, 2500, tie=1)
 
 
 def test_community_sequential_rule_by_back_pointers(bgv):

@@ -68,6 +68,52 @@ def test_chunk_one_is_the_sequential_rule():
         assert cnt.tolist() == ref_c
 
 
+PATH = np.array([[0, 1], [2, 3], [1, 2]], dtype=np.int32)
+
+
+@pytest.mark.parametrize("row", _rows("tie_path.txt"))
+def test_tie_rule_hand_worked(row):
+    D, P, B, tie = (int(t) for t in row[:4])
+    expect = [int(t) for t in row[4:]]
+    lab, _ = oracle.bs_community(4, PATH, D, P, 2, B, tie)
+    assert lab.tolist() == expect
+    if B == 1:
+        assert oracle.seq_scoda(4, PATH.tolist(), D, P, 2, bool(tie))[0] == expect
+
+
+def test_tie_rule_chunk_one_is_the_sequential_rule():
+    """With the tie rule, chunk == 1 still reproduces the literal sequential loop."""
+    rng = np.random.default_rng(13)
+    for trial in range(300):
+        n = int(rng.integers(1, 25))
+        m = int(rng.integers(0, 80))
+        e = graphgen.random_tiny_graph(rng, n, m) if m else np.zeros((0, 2), np.int32)
+        D = int(rng.integers(0, 12))
+        P = int(rng.integers(1, 4))
+        f = int(rng.integers(1, 4))
+        ref_l, ref_c = oracle.seq_scoda(n, e.tolist(), D, P, f, tie=True)
+        lab, cnt = oracle.bs_community(n, e, D, P, f, 1, 1)
+        assert lab.tolist() == ref_l
+        assert cnt.tolist() == ref_c
+
+
+def test_tie_rule_needs_a_tie():
+    """Streams whose decisions never see equal counters give the same labels with and
+    without the tie rule; streams with ties differ somewhere."""
+    rng = np.random.default_rng(17)
+    differ = 0
+    for _ in range(100):
+        n = 30
+        e = graphgen.random_tiny_graph(rng, n, 60)
+        a, _ = oracle.bs_community(n, e, 0, 1, 2, 1, 1)   # D = 0: no edge is ever tested
+        b, _ = oracle.bs_community(n, e, 0, 1, 2, 1, 0)
+        assert np.array_equal(a, b)
+        c, _ = oracle.bs_community(n, e, 8, 2, 2, 1, 1)
+        d, _ = oracle.bs_community(n, e, 8, 2, 2, 1, 0)
+        differ += int(not np.array_equal(c, d))
+    assert differ > 50
+
+
 def test_self_loops_are_ignored():
     rng = np.random.default_rng(11)
     for _ in range(50):
