@@ -41,7 +41,7 @@ def _load():
         _lib = C.CDLL(_LIB)
         P = C.c_void_p
         i32, i64, f64, u32 = C.c_int32, C.c_int64, C.c_double, C.c_uint32
-        _lib.orc_bs_community.argtypes = [i32, i64, P, i32, i32, i32, i64, i32, P, P]
+        _lib.orc_bs_community.argtypes = [i32, i64, P, i32, i32, i32, i64, i32, i32, P, P]
         _lib.orc_bs_community.restype = C.c_int
         _lib.orc_degree_volume.argtypes = [i32, i32, P, P, P, P]
         _lib.orc_hash_key.argtypes = [P, u32, u32]
@@ -72,15 +72,17 @@ def _c(a, dtype):
 
 
 # ---------------------------------------------------------------- community ----
-def bs_community(n, edges, threshold, passes=1, growth=2, chunk=1, tie=0):
+def bs_community(n, edges, threshold, passes=1, growth=2, chunk=1, tie=0, rule=0):
     """Batch-synchronous streaming community detection (see bgv_oracle.c); tie = 1: on
-    equal counters the edge's first endpoint joins the second's community.
+    equal counters the edge's first endpoint joins the second's community; rule = 1:
+    the community-volume rule of SCoDA instead of the paper's degree rule.
     Returns (labels int32[n], counters int32[n])."""
     lib = _load()
     e = _c(edges, np.int32).reshape(-1, 2)
     lab = np.empty(n, np.int32)
     cnt = np.empty(n, np.int32)
-    rc = lib.orc_bs_community(n, e.shape[0], _p(e), threshold, passes, growth, chunk, int(tie), _p(lab), _p(cnt))
+    rc = lib.orc_bs_community(n, e.shape[0], _p(e), threshold, passes, growth, chunk, int(tie), int(rule), _p(lab),
+                              _p(cnt))
     if rc != 0:
         raise ValueError("orc_bs_community: bad arguments")
     return lab, cnt

@@ -56,18 +56,29 @@ static int32_t orc_threshold(int32_t D1, int32_t growth, int32_t p)
  * takes the label proposed by the edge of smallest index.  chunk == 1 is exactly the
  * sequential rule.
  *
+ * rule = 1: the community-volume rule of the SCoDA algorithm the paper adopts, in the
+ * same batch-synchronous form.  V[c] = sum of the counters of the nodes labelled c (a
+ * node's increments add to its community's V; a move carries its counter along).  An
+ * edge whose endpoints both have counters at most D and different chunk-start labels
+ * proposes: u joins v's community if V[label u] <= V[label v], else v joins u's (V and
+ * counters as at the end of the chunk's increments).  Endpoints already sharing a
+ * label make no proposal.  (tie must be 0 with rule 1.)
+ *
  * label[n] (out), counter[n] (out: degree counter after all passes = passes * d(v)).
  * Returns 0, or -1 on bad arguments.
  */
 int orc_bs_community(int32_t n, int64_t m, const int32_t *edges, int32_t D1,
-                     int32_t passes, int32_t growth, int64_t chunk, int32_t tie,
+                     int32_t passes, int32_t growth, int64_t chunk, int32_t tie, int32_t rule,
                      int32_t *label, int32_t *counter)
 {
     if (n <= 0 || m < 0 || passes < 1 || growth < 1 || chunk < 1 || D1 < 0 || tie < 0 || tie > 1) return -1;
+    if (rule < 0 || rule > 1 || (rule == 1 && tie)) return -1;
     int64_t *prop_edge = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
     int32_t *prop_label = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
     int32_t *touched = (int32_t *)malloc(sizeof(int32_t) * (size_t)(chunk < m ? chunk : (m > 0 ? m : 1)));
     if (!prop_edge || !prop_label || !touched) { free(prop_edge); free(prop_label); free(touched); return -1; }
+    int64_t *vol = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+    if (!vol) { free(prop_edge); free(prop_label); free(touched); return -1; }
     for (int32_t v = 0; v < n; ++v) { label[v] = v; counter[v] = 0; prop_edge[v] = -1; }
 
     for (int32_t p = 0; p < passes; ++p) {
@@ -80,6 +91,8 @@ int orc_bs_community(int32_t n, int64_t m, const int32_t *edges, int32_t D1,
                 if (u == v) continue;
                 counter[u] += 1;
                 counter[v] += 1;
+                vol[label[u]] += 1;
+                vol[label[v]] += 1;
             }
             /* (b) decisions on chunk-end degrees and chunk-start labels */
             int64_t nt = 0;
@@ -88,10 +101,18 @@ int orc_bs_community(int32_t n, int64_t m, const int32_t *edges, int32_t D1,
                 if (u == v) continue;
                 const int32_t du = counter[u], dv = counter[v];
                 if (du > D || dv > D) continue;
-                if (du == dv && !tie) continue;
-                /* lower degree joins the higher's community; on a tie (tie = 1) u joins v */
-                const int32_t x = (du <= dv) ? u : v;
-                const int32_t y = (du <= dv) ? v : u;
+                int32_t x, y;
+                if (rule == 0) {
+                    if (du == dv && !tie) continue;
+                    /* lower degree joins the higher's community; on a tie (tie = 1) u joins v */
+                    x = (du <= dv) ? u : v;
+                    y = (du <= dv) ? v : u;
+                } else {
+                    if (label[u] == label[v]) continue;
+                    /* the endpoint of the smaller (or equal) community volume moves */
+                    x = (vol[label[u]] <= vol[label[v]]) ? u : v;
+                    y = (x == u) ? v : u;
+                }
                 if (prop_edge[x] < 0) {                /* first (smallest) index wins */
                     prop_edge[x] = i;
                     prop_label[x] = label[y];
@@ -101,12 +122,14 @@ int orc_bs_community(int32_t n, int64_t m, const int32_t *edges, int32_t D1,
             /* (c) apply */
             for (int64_t t = 0; t < nt; ++t) {
                 const int32_t x = touched[t];
+                vol[label[x]] -= counter[x];   /* the move carries x's counter along */
+                vol[prop_label[x]] += counter[x];
                 label[x] = prop_label[x];
                 prop_edge[x] = -1;
             }
         }
     }
-    free(prop_edge); free(prop_label); free(touched);
+    free(prop_edge); free(prop_label); free(touched); free(vol);
     return 0;
 }
 

@@ -114,6 +114,42 @@ def test_tie_rule_needs_a_tie():
     assert differ > 50
 
 
+VSTREAM = np.array([[0, 1], [1, 2], [0, 2], [3, 2]], dtype=np.int32)
+
+
+@pytest.mark.parametrize("row", _rows("volume_rule.txt"))
+def test_volume_rule_hand_worked(row):
+    D, P, B, rule = (int(t) for t in row[:4])
+    expect = [int(t) for t in row[4:]]
+    lab, _ = oracle.bs_community(4, VSTREAM, D, P, 2, B, 0, rule)
+    assert lab.tolist() == expect
+    if B == 1:
+        assert oracle.seq_scoda(4, VSTREAM.tolist(), D, P, 2, volume_rule=bool(rule))[0] == expect
+
+
+def test_volume_rule_chunk_one_is_the_sequential_loop():
+    """With the volume rule, chunk == 1 reproduces the literal SCoDA loop."""
+    rng = np.random.default_rng(19)
+    for trial in range(300):
+        n = int(rng.integers(1, 25))
+        m = int(rng.integers(0, 80))
+        e = graphgen.random_tiny_graph(rng, n, m) if m else np.zeros((0, 2), np.int32)
+        if trial % 3 == 0 and m:
+            loop = rng.random(m) < 0.1
+            e[loop, 1] = e[loop, 0]
+        D = int(rng.integers(0, 12))
+        P = int(rng.integers(1, 4))
+        ref_l, ref_c = oracle.seq_scoda(n, e.tolist(), D, P, 2, volume_rule=True)
+        lab, cnt = oracle.bs_community(n, e, D, P, 2, 1, 0, 1)
+        assert lab.tolist() == ref_l
+        assert cnt.tolist() == ref_c
+
+
+def test_volume_rule_rejects_the_tie_flag():
+    with pytest.raises(ValueError):
+        oracle.bs_community(3, np.array([[0, 1]], np.int32), 4, 1, 2, 1, 1, 1)
+
+
 def test_self_loops_are_ignored():
     rng = np.random.default_rng(11)
     for _ in range(50):
