@@ -447,10 +447,12 @@ def sequential_rule_form(torch, bgv, edges_np, n, wl, with_cpu):
 def sweep_points(wl):
     """The paper's sensitivity study on this workload: hash functions (sketch rows) 1-4,
     rounds (passes) 2-4, threshold delta / 3 delta / 5 delta and sketch widths 5,000 and
-    15,000 beside the workload's own, one parameter changed at a time."""
+    15,000 beside the workload's own, one parameter changed at a time; then the rule
+    variants: equal counters join (tie 1) and SCoDA's community-volume rule (rule 1)."""
     d = wl["threshold"]
     return ([("rows", r) for r in (1, 2, 3, 4)] + [("passes", p) for p in (2, 3, 4)] +
-            [("threshold", k * d) for k in (1, 3, 5)] + [("cols", c) for c in (5000, 15000, wl["cols"])])
+            [("threshold", k * d) for k in (1, 3, 5)] + [("cols", c) for c in (5000, 15000, wl["cols"])] +
+            [("tie", 1), ("rule", 1)])
 
 
 def sweeps_form(torch, bgv, graphgen, edges_np, n, wl):
@@ -474,7 +476,8 @@ def sweeps_form(torch, bgv, graphgen, edges_np, n, wl):
                "superedges": int(res["sg"]["E"])}
         # what the sketch parameters change: the estimates' relative overestimate of the
         # exact supernode sizes (community volumes) and superedge multiplicities (untimed)
-        lab, deg, vol = bgv.community(ed, n, w["threshold"], w["passes"], w["growth"], w["chunk"], volume=True)
+        lab, deg, vol = bgv.community(ed, n, w["threshold"], w["passes"], w["growth"], w["chunk"], volume=True,
+                                      tie=w.get("tie", 0), rule=w.get("rule", 0))
         sg = bgv.supergraph(ed, lab, deg, w["rows"], w["cols"], c1, c2, exact_counts=True)
         size = sg["super_size"].to(torch.int64) & 0xFFFFFFFF
         exact = vol[sg["super_label"].to(torch.int64)]

@@ -72,7 +72,17 @@ const char *bgv_last_error(void);
  * in an earlier chunk; pointer jumping over those links resolves all labels in about
  * 20 + log2(passes * chunks) launches, whatever the chunk size (chunk = 1 included).
  * Method 2 needs m >= 1 and passes * m < 2^31 (method 2 otherwise: BGV_E_INVALID) and
- * more workspace.  Method 0 picks 2 when it applies and the chunk-by-chunk form would
+ * more workspace.
+ *
+ * rule = 1 (the volume rule of SCoDA, the streaming algorithm Section 3.2 adopts), in
+ * the same batch-synchronous form: V[c] = the sum of the counters of the nodes labelled
+ * c (increments raise the V of the chunk-start label; a move carries the node's counter
+ * from its old community's V to the new one's).  An edge whose counters are both at most
+ * the threshold and whose endpoints' chunk-start labels differ proposes: the endpoint
+ * whose community has the smaller or equal V joins the other's; endpoints that share a
+ * label propose nothing.  Decisions then depend on labels, so rule 1 runs chunk by chunk
+ * on per-node records with device atomics (method 0 or 1; tie must be 0); its
+ * workspace is 24 bytes per node and 4 per edge of a chunk.  Method 0 picks 2 when it applies and the chunk-by-chunk form would
  * take more than 16 + passes * m / 2^17 chunk steps, else 1.  Other values are
  * BGV_E_INVALID.
  */
@@ -84,7 +94,8 @@ typedef struct {
     int64_t chunk;     /* >= 1: edges per synchronous chunk                        */
     int32_t tie;       /* 0: equal counters do nothing (Algorithm 3's nested tests);
                           1: the edge's first endpoint joins the second's community  */
-    int32_t reserved;  /* must be 0                                              */
+    int32_t rule;      /* 0: the degree rule above (the paper);
+                          1: SCoDA's community-volume rule (see below)             */
 } bgv_cd_params;
 
 /* Workspace bytes for bgv_community (0 only on invalid arguments).  Up to 2^24 nodes:

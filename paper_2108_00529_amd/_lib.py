@@ -32,7 +32,7 @@ SZ = C.c_size_t
 
 class CdParams(C.Structure):
     _fields_ = [("threshold", i32), ("passes", i32), ("growth", i32), ("method", i32), ("chunk", i64),
-                ("tie", i32), ("reserved", i32)]
+                ("tie", i32), ("rule", i32)]
 
 
 class SketchParams(C.Structure):

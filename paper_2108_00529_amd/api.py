@@ -51,14 +51,15 @@ def validate_edges(edges: torch.Tensor, n: int) -> None:
 # ------------------------------------------------------------------- community --
 def community(edges: torch.Tensor, n: int, threshold: int, passes: int = 1, growth: int = 2,
               chunk: int = 1, volume: bool = False, ws: torch.Tensor | None = None, stream=None,
-              method: int = 0, tie: int = 0):
+              method: int = 0, tie: int = 0, rule: int = 0):
     """Streaming community detection.  Returns (labels int32[n], degree int32[n],
     volume int64[n] or None).  method: 0 automatic, 1 chunk by chunk, 2 back-pointer
     resolution (the same integers).  tie: 1 = on equal counters the edge's first
-    endpoint joins the second's community (0: nothing happens, as in Algorithm 3)."""
+    endpoint joins the second's community (0: nothing happens, as in Algorithm 3).
+    rule: 0 = the paper's degree rule, 1 = SCoDA's community-volume rule."""
     m = edges.shape[0] if edges.dim() == 2 else 0
     _need(edges, torch.int32, "edges", (m, 2))
-    p = L.CdParams(int(threshold), int(passes), int(growth), int(method), int(chunk), int(tie), 0)
+    p = L.CdParams(int(threshold), int(passes), int(growth), int(method), int(chunk), int(tie), int(rule))
     need = L.bgv_community_workspace(int(n), m, C.byref(p))
     if need == 0:
         raise L.BgvError(f"invalid community arguments (n={n}, m={m}, {threshold}, {passes}, {growth}, {chunk}, "
@@ -76,12 +77,12 @@ def community(edges: torch.Tensor, n: int, threshold: int, passes: int = 1, grow
 
 def community_passes(edges: torch.Tensor, n: int, threshold: int, passes: int = 1, growth: int = 2,
                      chunk: int = 1, volume: bool = False, ws: torch.Tensor | None = None, stream=None,
-                     method: int = 0, tie: int = 0):
+                     method: int = 0, tie: int = 0, rule: int = 0):
     """community() that also keeps each pass's labels (the hierarchy of community sets).
     Returns (labels, degree, volume or None, pass_labels int32[passes, n])."""
     m = edges.shape[0] if edges.dim() == 2 else 0
     _need(edges, torch.int32, "edges", (m, 2))
-    p = L.CdParams(int(threshold), int(passes), int(growth), int(method), int(chunk), int(tie), 0)
+    p = L.CdParams(int(threshold), int(passes), int(growth), int(method), int(chunk), int(tie), int(rule))
     need = L.bgv_community_workspace(int(n), m, C.byref(p))
     if need == 0:
         raise L.BgvError(f"invalid community arguments (n={n}, m={m}, {threshold}, {passes}, {growth}, {chunk}, "
@@ -101,7 +102,7 @@ def community_passes(edges: torch.Tensor, n: int, threshold: int, passes: int = 
 def community_workspace(edges: torch.Tensor, n: int, wl: dict) -> torch.Tensor:
     """A workspace tensor for community() on this graph and workload."""
     p = L.CdParams(int(wl["threshold"]), int(wl["passes"]), int(wl["growth"]), 0, int(wl["chunk"]),
-                   int(wl.get("tie", 0)), 0)
+                   int(wl.get("tie", 0)), int(wl.get("rule", 0)))
     need = L.bgv_community_workspace(int(n), int(edges.shape[0]), C.byref(p))
     return _workspace(need, edges.device)
 
@@ -279,7 +280,8 @@ def pipeline(edges: torch.Tensor, n: int, wl: dict, coef1: np.ndarray, coef2: np
     workload description ``wl`` (threshold, passes, growth, chunk, rows, cols,
     fa2_iters, exact, theta, kr, kg, tau, ks, ksmax).  pos0 (>= K rows) seeds the layout."""
     labels, degree, vol = community(edges, n, wl["threshold"], wl["passes"], wl["growth"], wl["chunk"],
-                                    volume=volume, stream=stream, tie=int(wl.get("tie", 0)))
+                                    volume=volume, stream=stream, tie=int(wl.get("tie", 0)),
+                                    rule=int(wl.get("rule", 0)))
     sg = supergraph(edges, labels, degree, wl["rows"], wl["cols"], coef1, coef2, stream=stream)
     pos = pos0[: sg["K"]].clone()
     pos, fprev, speed = fa2_layout(sg["superedges"], pos, wl["fa2_iters"], wl["exact"], wl["theta"], wl["kr"],
@@ -329,7 +331,7 @@ def batched(edges: torch.Tensor, node_off: torch.Tensor, edge_off: torch.Tensor,
     c1 = np.ascontiguousarray(coef1, dtype=np.uint64).reshape(rows, 3)
     c2 = np.ascontiguousarray(coef2, dtype=np.uint64).reshape(rows, 3)
     cd = L.CdParams(int(wl["threshold"]), int(wl["passes"]), int(wl["growth"]), 0, int(wl["chunk"]),
-                    int(wl.get("tie", 0)), 0)
+                    int(wl.get("tie", 0)), int(wl.get("rule", 0)))
     sp = L.SketchParams(rows, cols, c1.ctypes.data_as(C.c_void_p), c2.ctypes.data_as(C.c_void_p))
     fa = fa2_params(wl["fa2_iters"], True, wl.get("theta", 1.2), wl["kr"], wl["kg"], wl["tau"], wl["ks"],
                     wl["ksmax"])

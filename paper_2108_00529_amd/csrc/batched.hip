@@ -681,7 +681,7 @@ static bool bt_valid(int32_t G, int64_t n_total, int64_t m_total, const bgv_cd_p
                      const bgv_sketch_params *sk, const bgv_fa2_params *fa) {
     return G >= 1 && n_total >= 0 && n_total <= INT32_MAX && m_total >= 0 && m_total <= INT32_MAX && cd && sk &&
            fa && cd->threshold >= 0 && cd->passes >= 1 && cd->growth >= 1 && cd->chunk >= 1 && cd->method == 0 &&
-           (cd->tie == 0 || cd->tie == 1) && cd->reserved == 0 &&
+           (cd->tie == 0 || cd->tie == 1) && cd->rule == 0 &&
            sk->rows >= 1 && sk->rows <= kMaxRows && sk->cols >= 1 && (int64_t)sk->rows * sk->cols <= kBtMaxCells &&
            sk->coef1 && sk->coef2 && fa->iters >= 0 && fa->exact == 1 && fa->tau > 0.f && fa->ks >= 0.f &&
            fa->ksmax > 0.f;

@@ -391,8 +391,10 @@ static int32_t pass_threshold(int32_t D1, int32_t growth, int32_t p) {
 
 static bool cd_valid(int32_t n, int64_t m, const bgv_cd_params *p) {
     if (!(p && n >= 1 && m >= 0 && m <= INT32_MAX && p->threshold >= 0 && p->passes >= 1 && p->growth >= 1 &&
-          p->chunk >= 1 && p->method >= 0 && p->method <= 2 && (p->tie == 0 || p->tie == 1) && p->reserved == 0))
+          p->chunk >= 1 && p->method >= 0 && p->method <= 2 && (p->tie == 0 || p->tie == 1) &&
+          (p->rule == 0 || p->rule == 1)))
         return false;
+    if (p->rule == 1 && (p->tie != 0 || p->method == 2)) return false;
     return p->method != 2 || m == 0 || sq_fits(n, m, p);
 }
 
@@ -401,7 +403,7 @@ static bool cd_valid(int32_t n, int64_t m, const bgv_cd_params *p) {
 // 0.09 ns more per (pass, edge) than the chunk steps' streaming, so the second wins past
 // about 16 + passes * m / 2^17 chunk steps (245 at 3 x 10M edges, 16 on small graphs).
 static int cd_method(int32_t n, int64_t m, const bgv_cd_params *p) {
-    if (m == 0) return 1;
+    if (m == 0 || p->rule == 1) return 1;
     if (p->method != 0) return p->method;
     const int64_t steps = (int64_t)p->passes * ((m + p->chunk - 1) / p->chunk);
     return steps > 16 + ((int64_t)p->passes * m >> 17) && sq_fits(n, m, p) ? 2 : 1;
@@ -438,6 +440,96 @@ static size_t cd_layout(Carver &c, int32_t n, int64_t m, const bgv_cd_params *p,
     return c.size();
 }
 
+// ------------------------------------------------------------ volume rule ----
+// SCoDA's community-volume rule, batch-synchronous, on the per-node records plus
+// V[label] (64-bit): per chunk
+//   inc     counters and V of the chunk-start labels of both endpoints (atomics)
+//   decide  both counters at most D and labels different: the endpoint whose
+//           community has the smaller or equal V moves; proposals by a 64-bit
+//           atomicMin keyed by the stream index
+//   apply   winners take their label and carry their counter from the old V to the new
+// Integer atomics only, so the result does not depend on timing.  Counters are raised
+// in every pass (V needs the increments), so a counter ends at passes * d(v).
+__global__ void __launch_bounds__(kCdThreads) k_vr_inc(NodeState *__restrict__ st, unsigned long long *vol,
+                                                       const int2 *__restrict__ edges, int64_t cs, int64_t ce) {
+    for (int64_t i = cs + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ce; i += (int64_t)gridDim.x * blockDim.x) {
+        const int2 e = edges[i];
+        if (e.x == e.y) continue;
+        atomicAdd(&st[e.x].cnt, 1);
+        atomicAdd(&st[e.y].cnt, 1);
+        atomicAdd(&vol[st[e.x].label], 1ull);
+        atomicAdd(&vol[st[e.y].label], 1ull);
+    }
+}
+
+__global__ void __launch_bounds__(kCdThreads) k_vr_decide(NodeState *__restrict__ st,
+                                                          const unsigned long long *__restrict__ vol,
+                                                          const int2 *__restrict__ edges, int32_t *__restrict__ prop,
+                                                          int64_t cs, int64_t ce, int32_t D) {
+    for (int64_t i = cs + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ce; i += (int64_t)gridDim.x * blockDim.x) {
+        const int2 e = edges[i];
+        int32_t target = -1;
+        if (e.x != e.y) {
+            const int2 su = *reinterpret_cast<const int2 *>(&st[e.x]);  // {counter, label}
+            const int2 sv = *reinterpret_cast<const int2 *>(&st[e.y]);
+            if (su.x <= D && sv.x <= D && su.y != sv.y) {
+                const bool u_moves = vol[su.y] <= vol[sv.y];
+                target = u_moves ? e.x : e.y;
+                const int32_t lab = u_moves ? sv.y : su.y;
+                atomicMin(reinterpret_cast<unsigned long long *>(&st[target].win),
+                          (unsigned long long)(((uint64_t)i << 32) | (uint32_t)lab));
+            }
+        }
+        prop[i - cs] = target;
+    }
+}
+
+__global__ void __launch_bounds__(kCdThreads) k_vr_apply(NodeState *__restrict__ st, unsigned long long *vol,
+                                                         const int32_t *__restrict__ prop, int64_t cs, int64_t ce) {
+    for (int64_t i = cs + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ce; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t x = prop[i - cs];
+        if (x < 0) continue;
+        const uint64_t w = st[x].win;
+        if ((int64_t)(w >> 32) != i) continue;
+        const int32_t old = st[x].label, nw = (int32_t)(uint32_t)(w & 0xffffffffu);
+        const unsigned long long d = (unsigned long long)st[x].cnt;
+        st[x].label = nw;
+        st[x].win = kNoProposal;
+        atomicAdd(&vol[nw], d);
+        atomicAdd(&vol[old], 0ull - d);
+    }
+}
+
+__global__ void __launch_bounds__(kCdThreads) k_vr_finish(const NodeState *__restrict__ st, int32_t n, int32_t passes,
+                                                          int32_t *__restrict__ labels, int32_t *__restrict__ degree,
+                                                          unsigned long long *__restrict__ volume) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t d = st[v].cnt / passes, l = st[v].label;
+        labels[v] = l;
+        degree[v] = d;
+        if (volume && d) atomicAdd(&volume[l], (unsigned long long)d);
+    }
+}
+
+struct VrWs {
+    NodeState *st;
+    unsigned long long *vol;
+    int32_t *prop;
+};
+
+static size_t vr_layout(Carver &c, int32_t n, int64_t m, const bgv_cd_params *p, VrWs *w) {
+    const int64_t b = p->chunk < m ? p->chunk : m;
+    VrWs t;
+    t.st = c.take<NodeState>((size_t)n);
+    t.vol = c.take<unsigned long long>((size_t)n);
+    t.prop = c.take<int32_t>((size_t)(b > 0 ? b : 1));
+    if (w) *w = t;
+    return c.size();
+}
+
+static bgv_status vr_run(int32_t n, int64_t m, const int32_t *edges, const bgv_cd_params *p, int32_t *labels,
+                         int32_t *degree, int64_t *volume, int32_t *pass_labels, void *ws, hipStream_t s);
+
 }  // namespace bgv
 
 using namespace bgv;
@@ -446,6 +538,7 @@ extern "C" size_t bgv_community_workspace(int32_t n, int64_t m, const bgv_cd_par
     if (!cd_valid(n, m, p)) return 0;
     Carver c(nullptr);
     if (cd_method(n, m, p) == 2) return sq_layout(c, n, m, p, nullptr);
+    if (p->rule == 1) return vr_layout(c, n, m, p, nullptr);
     CdWs w;
     return cd_layout(c, n, m, p, &w);
 }
@@ -477,6 +570,7 @@ static bgv_status cd_run(int32_t n, int64_t m, const int32_t *edges, const bgv_c
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (volume) BGV_TRY(fill<int64_t>(volume, 0, n, s));
     if (cd_method(n, m, p) == 2) return sq_run(n, m, edges, p, labels, degree, volume, pass_labels, ws, s);
+    if (p->rule == 1) return vr_run(n, m, edges, p, labels, degree, volume, pass_labels, ws, s);
     Carver c(ws);
     CdWs w;
     cd_layout(c, n, m, p, &w);
@@ -583,6 +677,34 @@ static bgv_status cd_run(int32_t n, int64_t m, const int32_t *edges, const bgv_c
     }
     BGV_LAUNCH(k_cd_finish<4>, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s,
                reinterpret_cast<const int32_t *>(st), n, labels, degree,
+               reinterpret_cast<unsigned long long *>(volume));
+    return BGV_OK;
+}
+
+static bgv_status vr_run(int32_t n, int64_t m, const int32_t *edges, const bgv_cd_params *p, int32_t *labels,
+                         int32_t *degree, int64_t *volume, int32_t *pass_labels, void *ws, hipStream_t s) {
+    Carver c(ws);
+    VrWs w;
+    vr_layout(c, n, m, p, &w);
+    const int2 *e2 = reinterpret_cast<const int2 *>(edges);
+    const unsigned gn = grid_for(n, kCdThreads, 65536);
+    BGV_LAUNCH(k_cd_init, dim3(gn), dim3(kCdThreads), 0, s, w.st, n);
+    BGV_TRY(fill<uint64_t>(reinterpret_cast<uint64_t *>(w.vol), 0ull, n, s));
+    const int64_t B = p->chunk;
+    for (int32_t pass = 0; pass < p->passes; ++pass) {
+        const int32_t D = pass_threshold(p->threshold, p->growth, pass);
+        for (int64_t cs = 0; cs < m; cs += B) {
+            const int64_t ce = cs + B < m ? cs + B : m;
+            const dim3 grid(grid_for(ce - cs, kCdThreads * 4, 16384));
+            BGV_LAUNCH(k_vr_inc, grid, dim3(kCdThreads), 0, s, w.st, w.vol, e2, cs, ce);
+            BGV_LAUNCH(k_vr_decide, grid, dim3(kCdThreads), 0, s, w.st, w.vol, e2, w.prop, cs, ce, D);
+            BGV_LAUNCH(k_vr_apply, grid, dim3(kCdThreads), 0, s, w.st, w.vol, w.prop, cs, ce);
+        }
+        if (pass_labels)
+            BGV_LAUNCH(k_cd_copy_labels, dim3(gn), dim3(kCdThreads), 0, s, reinterpret_cast<const int32_t *>(w.st) + 1,
+                       4, n, pass_labels + (int64_t)pass * n);
+    }
+    BGV_LAUNCH(k_vr_finish, dim3(gn), dim3(kCdThreads), 0, s, w.st, n, p->passes, labels, degree,
                reinterpret_cast<unsigned long long *>(volume));
     return BGV_OK;
 }

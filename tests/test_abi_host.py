@@ -46,6 +46,10 @@ def test_community_validation_and_workspace():
     big = L.bgv_community_workspace((1 << 24) + 1, 100, C.byref(p))  # per-node atomic form
     assert big >= ((1 << 24) + 1) * 16
     assert L.bgv_community_workspace(10, 10, C.byref(L.CdParams(1, 1, 2, 0, 1, 1, 0))) > 0  # tie rule 1
+    # volume rule: per-node records, V and a chunk of proposals, whatever the method choice
+    vr = L.bgv_community_workspace(5000, 100000, C.byref(L.CdParams(8, 2, 2, 0, 1, 0, 1)))
+    assert vr == L.bgv_community_workspace(5000, 100000, C.byref(L.CdParams(8, 2, 2, 1, 1, 0, 1)))
+    assert 5000 * 24 <= vr <= 5000 * 24 + 4096
     # methods: back-pointer resolution needs more workspace; automatic picks it past 64 chunk steps
     m1 = L.bgv_community_workspace(2000, 10000, C.byref(L.CdParams(16, 3, 2, 1, 100)))
     m2 = L.bgv_community_workspace(2000, 10000, C.byref(L.CdParams(16, 3, 2, 2, 100)))
@@ -60,7 +64,8 @@ def test_community_validation_and_workspace():
     for bad in [L.CdParams(-1, 1, 2, 0, 1), L.CdParams(1, 0, 2, 0, 1), L.CdParams(1, 1, 0, 0, 1),
                 L.CdParams(1, 1, 2, 0, 0), L.CdParams(1, 1, 2, 7, 1), L.CdParams(1, 1, 2, 3, 1),
                 L.CdParams(1, 1, 2, -1, 1), L.CdParams(1, 1, 2, 0, 1, 2, 0), L.CdParams(1, 1, 2, 0, 1, -1, 0),
-                L.CdParams(1, 1, 2, 0, 1, 0, 5)]:
+                L.CdParams(1, 1, 2, 0, 1, 0, 5), L.CdParams(1, 1, 2, 0, 1, 0, 2),
+                L.CdParams(1, 1, 2, 0, 1, 1, 1), L.CdParams(1, 1, 2, 2, 1, 0, 1)]:
         assert L.bgv_community_workspace(10, 10, C.byref(bad)) == 0
         assert L.bgv_community(10, 10, C.c_void_p(1), C.byref(bad), C.c_void_p(1), C.c_void_p(1), None,
                                None, 0, None) == -1

@@ -64,17 +64,17 @@ def sketch_coefs(rows, seed):
 
 
 # --------------------------------------------------------------- community -------
-def check_community(bgv, n, e, D, P, f, B, methods=(1, 2), tie=0):
+def check_community(bgv, n, e, D, P, f, B, methods=(1, 2), tie=0, rule=0):
     """Both methods (chunk by chunk, back-pointer resolution) against the oracle; the
-    second needs at least one edge."""
-    lab_r, cnt_r = oracle.bs_community(n, e, D, P, f, B, tie)
+    second needs at least one edge and the degree rule."""
+    lab_r, cnt_r = oracle.bs_community(n, e, D, P, f, B, tie, rule)
     deg_r, vol_r = oracle.degree_volume(lab_r, cnt_r, P)
     ed = dev(e.reshape(-1, 2).astype(np.int32))
     for method in methods:
-        if method == 2 and len(e) == 0:
+        if method == 2 and (len(e) == 0 or rule == 1):
             continue
-        say(f"  community n={n} m={len(e)} D={D} P={P} f={f} B={B} method={method} tie={tie}")
-        lab, deg, vol = bgv.community(ed, n, D, P, f, B, volume=True, method=method, tie=tie)
+        say(f"  community n={n} m={len(e)} D={D} P={P} f={f} B={B} method={method} tie={tie} rule={rule}")
+        lab, deg, vol = bgv.community(ed, n, D, P, f, B, volume=True, method=method, tie=tie, rule=rule)
         torch.cuda.synchronize()
         np.testing.assert_array_equal(host(lab), lab_r)
         np.testing.assert_array_equal(host(deg), deg_r)
@@ -125,17 +125,18 @@ def test_community_at_and_above_bucket_limit(bgv, n):
     check_community(bgv, n, e, 8, 2, 2, 3000)
 
 
-def check_passes(bgv, n, e, D, P, f, B, tie=0):
+def check_passes(bgv, n, e, D, P, f, B, tie=0, rule=0):
     """Row p of the per-pass labels equals the labels of a (p+1)-pass run (both methods)."""
     ed = dev(e.reshape(-1, 2).astype(np.int32))
-    ref_rows = [oracle.bs_community(n, e, D, q + 1, f, B, tie)[0] for q in range(P)]
-    lab_r, cnt_r = oracle.bs_community(n, e, D, P, f, B, tie)
+    ref_rows = [oracle.bs_community(n, e, D, q + 1, f, B, tie, rule)[0] for q in range(P)]
+    lab_r, cnt_r = oracle.bs_community(n, e, D, P, f, B, tie, rule)
     deg_r, vol_r = oracle.degree_volume(lab_r, cnt_r, P)
     for method in (1, 2):
-        if method == 2 and len(e) == 0:
+        if method == 2 and (len(e) == 0 or rule == 1):
             continue
-        say(f"  community passes n={n} m={len(e)} D={D} P={P} f={f} B={B} method={method}")
-        lab, deg, vol, rows = bgv.community_passes(ed, n, D, P, f, B, volume=True, method=method, tie=tie)
+        say(f"  community passes n={n} m={len(e)} D={D} P={P} f={f} B={B} method={method} rule={rule}")
+        lab, deg, vol, rows = bgv.community_passes(ed, n, D, P, f, B, volume=True, method=method, tie=tie,
+                                                   rule=rule)
         torch.cuda.synchronize()
         rows = host(rows)
         assert rows.shape == (P, n)
@@ -192,6 +193,33 @@ def test_community_tie_rule(bgv):
     check_community(bgv, n, e, 6, 2, 2, 2500, tie=1)
 
 
+def test_community_volume_rule(bgv):
+    """SCoDA's community-volume rule: random small streams (chunk 1 = the literal SCoDA
+    loop, and larger chunks), an empty stream, several buckets with a hub, per-pass
+    labels and more than 2^24 nodes, bit-exact against the oracle with the same rule."""
+    rng = np.random.default_rng(43)
+    check_community(bgv, 5, np.zeros((0, 2), np.int32), 4, 2, 2, 3, rule=1)
+    for trial in range(20):
+        n = int(rng.integers(1, 60))
+        m = int(rng.integers(1, 400))
+        e = graphgen.random_tiny_graph(rng, n, m)
+        if trial % 4 == 0:
+            loop = rng.random(m) < 0.1
+            e[loop, 1] = e[loop, 0]
+        B = int(rng.choice([1, 2, 17, 1000]))
+        check_community(bgv, n, e, int(rng.integers(0, 20)), int(rng.integers(1, 4)), 2, B, rule=1)
+    n = 3 * 4096 + 17
+    e = rng.integers(0, n, (40_000, 2)).astype(np.int32)
+    e[rng.random(len(e)) < 0.05, 0] = 4095
+    for B, P in ((5000, 3), (len(e), 2), (1024, 1)):
+        check_community(bgv, n, e, 6, P, 2, B, rule=1)
+    check_passes(bgv, 2000, rng.integers(0, 2000, (20_000, 2)).astype(np.int32), 5, 3, 2, 1500, rule=1)
+    n = (1 << 24) + 5
+    ids = np.concatenate([rng.integers(0, 3000, 2000), rng.integers(n - 3000, n, 2000)])
+    e = ids[rng.integers(0, len(ids), (20_000, 2))].astype(np.int32)
+    check_community(bgv, n, e, 6, 2, 2, 2500, rule=1)
+
+
 def test_community_sequential_rule_by_back_pointers(bgv):
     """chunk = 1 (the sequential rule: one chunk per edge) on streams of tens of
     thousands of edges, which the back-pointer method resolves in a few dozen launches;
@@ -209,7 +237,7 @@ def test_community_sequential_rule_by_back_pointers(bgv):
 
 def test_parameter_sweeps_match_oracle(bgv):
     """The bench's sweep points (sketch rows 1-4, passes 2-4, threshold x1/x3/x5, sketch
-    widths 5,000 / 15,000), on an LFR-style graph of 20,000 nodes and 200,000 edges: the
+    widths 5,000 / 15,000, the tie and volume rules), on an LFR-style graph of 20,000 nodes and 200,000 edges: the
     community and supergraph integers of every point bit-exact against the oracle."""
     import bench
     e, _ = graphgen.lfr_style(20_000, 200_000, 2.3, 1.5, 0.2, 77)
@@ -220,9 +248,10 @@ def test_parameter_sweeps_match_oracle(bgv):
         w = dict(wl)
         w[key] = value
         say(f"  sweep {key}={value}")
-        lab_r, cnt_r = oracle.bs_community(n, e, w["threshold"], w["passes"], w["growth"], w["chunk"])
+        tie, rule = w.get("tie", 0), w.get("rule", 0)
+        lab_r, cnt_r = oracle.bs_community(n, e, w["threshold"], w["passes"], w["growth"], w["chunk"], tie, rule)
         deg_r, _ = oracle.degree_volume(lab_r, cnt_r, w["passes"])
-        lab, deg, _ = bgv.community(ed, n, w["threshold"], w["passes"], w["growth"], w["chunk"])
+        lab, deg, _ = bgv.community(ed, n, w["threshold"], w["passes"], w["growth"], w["chunk"], tie=tie, rule=rule)
         np.testing.assert_array_equal(host(lab), lab_r)
         np.testing.assert_array_equal(host(deg), deg_r)
         check_supergraph(bgv, n, e, lab_r, deg_r, w["rows"], w["cols"], w["sketch_seed"])
