@@ -450,15 +450,42 @@ static size_t cd_layout(Carver &c, int32_t n, int64_t m, const bgv_cd_params *p,
 //   apply   winners take their label and carry their counter from the old V to the new
 // Integer atomics only, so the result does not depend on timing.  Counters are raised
 // in every pass (V needs the increments), so a counter ends at passes * d(v).
+// Adds `v` to vol[key] for the active lanes of a wave with one atomic per distinct key
+// (a few giant communities would otherwise serialise most of a chunk's atomics on a
+// handful of addresses).  Called by every lane of the wave that is still running.
+__device__ __forceinline__ void vr_wave_add(unsigned long long *vol, int32_t key, unsigned long long v, bool active) {
+    const int lane = threadIdx.x & (kWave - 1);
+    uint64_t pending = __ballot(active);
+    while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int32_t k = __shfl(key, leader, kWave);
+        const uint64_t same = __ballot(active && key == k) & pending;
+        unsigned long long sum = (same >> lane) & 1ull ? v : 0ull;
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o, kWave);
+        if (lane == leader) atomicAdd(&vol[k], sum);
+        pending &= ~same;
+    }
+}
+
+// The grid-stride loops below advance whole workgroups together, so every lane of a
+// wave reaches the wave-wide steps.
 __global__ void __launch_bounds__(kCdThreads) k_vr_inc(NodeState *__restrict__ st, unsigned long long *vol,
                                                        const int2 *__restrict__ edges, int64_t cs, int64_t ce) {
-    for (int64_t i = cs + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ce; i += (int64_t)gridDim.x * blockDim.x) {
-        const int2 e = edges[i];
-        if (e.x == e.y) continue;
-        atomicAdd(&st[e.x].cnt, 1);
-        atomicAdd(&st[e.y].cnt, 1);
-        atomicAdd(&vol[st[e.x].label], 1ull);
-        atomicAdd(&vol[st[e.y].label], 1ull);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t b = cs + blockIdx.x * (int64_t)blockDim.x; b < ce; b += stride) {
+        const int64_t i = b + threadIdx.x;
+        const int2 e = i < ce ? edges[i] : make_int2(0, 0);
+        const bool act = i < ce && e.x != e.y;
+        int32_t lx = 0, ly = 0;
+        if (act) {
+            atomicAdd(&st[e.x].cnt, 1);
+            atomicAdd(&st[e.y].cnt, 1);
+            lx = st[e.x].label;
+            ly = st[e.y].label;
+        }
+        vr_wave_add(vol, lx, 1ull, act);
+        vr_wave_add(vol, ly, 1ull, act);
     }
 }
 
@@ -486,17 +513,26 @@ __global__ void __launch_bounds__(kCdThreads) k_vr_decide(NodeState *__restrict_
 
 __global__ void __launch_bounds__(kCdThreads) k_vr_apply(NodeState *__restrict__ st, unsigned long long *vol,
                                                          const int32_t *__restrict__ prop, int64_t cs, int64_t ce) {
-    for (int64_t i = cs + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ce; i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t x = prop[i - cs];
-        if (x < 0) continue;
-        const uint64_t w = st[x].win;
-        if ((int64_t)(w >> 32) != i) continue;
-        const int32_t old = st[x].label, nw = (int32_t)(uint32_t)(w & 0xffffffffu);
-        const unsigned long long d = (unsigned long long)st[x].cnt;
-        st[x].label = nw;
-        st[x].win = kNoProposal;
-        atomicAdd(&vol[nw], d);
-        atomicAdd(&vol[old], 0ull - d);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t b = cs + blockIdx.x * (int64_t)blockDim.x; b < ce; b += stride) {
+        const int64_t i = b + threadIdx.x;
+        const int32_t x = i < ce ? prop[i - cs] : -1;
+        bool won = false;
+        int32_t old = 0, nw = 0;
+        unsigned long long d = 0;
+        if (x >= 0) {
+            const uint64_t w = st[x].win;
+            if ((int64_t)(w >> 32) == i) {
+                won = true;
+                old = st[x].label;
+                nw = (int32_t)(uint32_t)(w & 0xffffffffu);
+                d = (unsigned long long)st[x].cnt;
+                st[x].label = nw;
+                st[x].win = kNoProposal;
+            }
+        }
+        vr_wave_add(vol, nw, d, won);
+        vr_wave_add(vol, old, 0ull - d, won);
     }
 }
 
