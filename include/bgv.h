@@ -103,7 +103,8 @@ typedef struct {
  * endpoints plus two offset rows of 4 * (ceil(n / 4096) + 1) bytes.  Above: 16 bytes per
  * node and 4 per edge of a chunk.  With passes > 1 another 8 per edge (each edge's
  * pass-0 endpoint counters, from which later passes' counters follow without
- * increments).  Method 2: 48 bytes per edge, 8 per node and at most 56 per (pass, edge)
+ * increments), and up to 2^24 nodes with passes > 2 one more byte per edge (passes 2-5
+ * decided once the degrees are known).  Method 2: 48 bytes per edge, 8 per node and at most 56 per (pass, edge)
  * proposal, plus radix-sort scratch. */
 size_t bgv_community_workspace(int32_t n, int64_t m, const bgv_cd_params *p);
 

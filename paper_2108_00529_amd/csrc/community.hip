@@ -229,10 +229,21 @@ __device__ __forceinline__ void cd_group_tile(const int2 *__restrict__ edges, in
 // stream index, label) grouped by the target's bucket.  Counters and labels are
 // separate arrays: every edge gathers two 4-byte counters (at a million nodes the
 // counter array fits one XCD's L2), and only proposing edges gather a label.
-template <int kMode>  // 0: only pass; 1: pass 0 of several; 2: a later pass
+// From pass 1 on every counter is known in closed form, so pass 1 (mode 2 with `mask`)
+// also settles passes 2 .. 1 + nlater (thresholds in `later`): mask[i] holds, per such
+// pass q, bit 2(q-2) = the edge proposes and bit 2(q-2)+1 = its first endpoint is the
+// target.  Those passes (mode 3) read that byte instead of the stored counters and
+// the two counter gathers.
+struct CdLater {
+    int32_t D[4];  // thresholds of passes 2..5
+    int32_t n;     // how many of them the mask covers
+};
+
+template <int kMode>  // 0: only pass; 1: pass 0 of several; 2: a later pass; 3: a pass in the mask
 __device__ __forceinline__ void cd_decide_tile(const int32_t *__restrict__ cnt, const int32_t *__restrict__ labv,
                                                const int2 *__restrict__ edges,
-                                               int2 *__restrict__ c1, int64_t cs, int64_t ce, int32_t D,
+                                               int2 *__restrict__ c1, uint8_t *__restrict__ mask, CdLater later,
+                                               int64_t cs, int64_t ce, int32_t D,
                                                int32_t pass, int32_t tie, int32_t tile, int32_t nb,
                                                uint3 *__restrict__ props, uint32_t *__restrict__ ptab,
                                                uint32_t *hist, uint3 *stage) {
@@ -248,15 +259,34 @@ __device__ __forceinline__ void cd_decide_tile(const int32_t *__restrict__ cnt, 
         if (i < ce) {
             const int2 e = edges[i];
             if (e.x != e.y) {
-                int32_t cu = cnt[e.x], cv = cnt[e.y];
-                if (kMode == 1) c1[i] = make_int2(cu, cv);
-                if (kMode == 2) {
-                    const int2 c = c1[i];
-                    cu = pass * cu + c.x;
-                    cv = pass * cv + c.y;
+                bool go, u_low;
+                if (kMode == 3) {
+                    const uint32_t mb = (uint32_t)mask[i] >> (2 * (pass - 2));
+                    go = mb & 1u;
+                    u_low = (mb >> 1) & 1u;
+                } else {
+                    const int32_t du = cnt[e.x], dv = cnt[e.y];
+                    int32_t cu = du, cv = dv;
+                    if (kMode == 1) c1[i] = make_int2(cu, cv);
+                    if (kMode == 2) {
+                        const int2 c = c1[i];
+                        cu = pass * du + c.x;
+                        cv = pass * dv + c.y;
+                        if (mask) {
+                            uint32_t mb = 0;
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) {
+                                const int32_t a = (q + 2) * du + c.x, b = (q + 2) * dv + c.y;
+                                if (q < later.n && a <= later.D[q] && b <= later.D[q] && (a != b || tie))
+                                    mb |= (a <= b ? 3u : 1u) << (2 * q);
+                            }
+                            mask[i] = (uint8_t)mb;
+                        }
+                    }
+                    go = cu <= D && cv <= D && (cu != cv || tie);
+                    u_low = cu <= cv;  // a tie (rule 1): the first endpoint joins
                 }
-                if (cu <= D && cv <= D && (cu != cv || tie)) {
-                    const bool u_low = cu <= cv;  // a tie (rule 1): the first endpoint joins
+                if (go) {
                     target[j] = u_low ? e.x : e.y;
                     lab[j] = labv[u_low ? e.y : e.x];
                     rank[j] = atomicAdd(&hist[target[j] >> kCdBucketBits], 1u);
@@ -284,7 +314,8 @@ template <int kMode>  // -1: grouping only
 __global__ void __launch_bounds__(kCdThreads) k_cd_step(const int32_t *__restrict__ cnt,
                                                          const int32_t *__restrict__ labv,
                                                          const int2 *__restrict__ edges,
-                                                         int2 *__restrict__ c1, int64_t cs, int64_t ce, int32_t D,
+                                                         int2 *__restrict__ c1, uint8_t *__restrict__ mask,
+                                                         CdLater later, int64_t cs, int64_t ce, int32_t D,
                                                          int32_t pass, int32_t tie, int32_t nb,
                                                          uint3 *__restrict__ props,
                                                          uint32_t *__restrict__ ptab, int64_t gs, int64_t ge,
@@ -294,8 +325,8 @@ __global__ void __launch_bounds__(kCdThreads) k_cd_step(const int32_t *__restric
     __shared__ uint16_t estage[2 * kCdTile];
     const int32_t tile = (int32_t)blockIdx.x;
     if (kMode >= 0 && cs + (int64_t)tile * kCdTile < ce)  // uniform over the workgroup
-        cd_decide_tile<kMode < 0 ? 0 : kMode>(cnt, labv, edges, c1, cs, ce, D, pass, tie, tile, nb, props, ptab,
-                                              hist, pstage);
+        cd_decide_tile<kMode < 0 ? 0 : kMode>(cnt, labv, edges, c1, mask, later, cs, ce, D, pass, tie, tile, nb,
+                                              props, ptab, hist, pstage);
     if (gs + (int64_t)tile * kCdTile < ge) {
         __syncthreads();  // hist is reused
         cd_group_tile(edges, gs, ge, tile, nb, ends, etab, hist, estage);
@@ -417,6 +448,7 @@ struct CdWs {
     uint16_t *ends;     // bucketed: endpoints grouped per tile
     uint32_t *ptab, *etab;
     int2 *c1;
+    uint8_t *mask;  // bucketed, passes > 2: decisions of passes 2..5 per edge
 };
 
 static size_t cd_layout(Carver &c, int32_t n, int64_t m, const bgv_cd_params *p, CdWs *w) {
@@ -437,6 +469,7 @@ static size_t cd_layout(Carver &c, int32_t n, int64_t m, const bgv_cd_params *p,
         w->prop = c.take<int32_t>(bb);
     }
     w->c1 = p->passes > 1 && m > 0 ? c.take<int2>((size_t)m) : nullptr;
+    w->mask = cd_bucketed(n) && p->passes > 2 && m > 0 ? c.take<uint8_t>((size_t)m) : nullptr;
     return c.size();
 }
 
@@ -626,9 +659,14 @@ static bgv_status cd_run(int32_t n, int64_t m, const int32_t *edges, const bgv_c
         if (nchunk > 0) {
             // pass 0, chunk 0: its endpoints grouped before anything is decided
             etiles = tiles_of(0);
-            BGV_LAUNCH(k_cd_step<-1>, dim3(etiles), dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1, (int64_t)0, (int64_t)0,
-                       0, 0, 0, nb, w.props, w.ptab, (int64_t)0, std::min<int64_t>(B, m), w.ends, w.etab);
+            BGV_LAUNCH(k_cd_step<-1>, dim3(etiles), dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1,
+                       (uint8_t *)nullptr, CdLater{}, (int64_t)0, (int64_t)0, 0, 0, 0, nb, w.props, w.ptab, (int64_t)0,
+                       std::min<int64_t>(B, m), w.ends, w.etab);
         }
+        // passes 2 .. 1 + later.n are decided in pass 1 (their counters are known there)
+        CdLater later{};
+        later.n = w.mask ? std::min(p->passes - 2, 4) : 0;
+        for (int q = 0; q < later.n; ++q) later.D[q] = pass_threshold(p->threshold, p->growth, q + 2);
         for (int32_t pass = 0; pass < p->passes && (m > 0 || pass_labels); ++pass) {
             const int32_t D = pass_threshold(p->threshold, p->growth, pass);
             for (int64_t k = 0; k < nchunk; ++k) {
@@ -645,14 +683,18 @@ static bgv_status cd_run(int32_t n, int64_t m, const int32_t *edges, const bgv_c
                 const int32_t gtiles = group_next ? tiles_of(k + 1) : 0;
                 const dim3 grid((unsigned)std::max(tiles, gtiles));
                 if (p->passes == 1)
-                    BGV_LAUNCH(k_cd_step<0>, grid, dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1, cs, ce, D, pass, p->tie, nb,
-                               w.props, w.ptab, gs, ge, w.ends, w.etab);
+                    BGV_LAUNCH(k_cd_step<0>, grid, dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1, (uint8_t *)nullptr,
+                               later, cs, ce, D, pass, p->tie, nb, w.props, w.ptab, gs, ge, w.ends, w.etab);
                 else if (pass == 0)
-                    BGV_LAUNCH(k_cd_step<1>, grid, dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1, cs, ce, D, pass, p->tie, nb,
-                               w.props, w.ptab, gs, ge, w.ends, w.etab);
+                    BGV_LAUNCH(k_cd_step<1>, grid, dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1, (uint8_t *)nullptr,
+                               later, cs, ce, D, pass, p->tie, nb, w.props, w.ptab, gs, ge, w.ends, w.etab);
+                else if (pass >= 2 && pass < 2 + later.n)
+                    BGV_LAUNCH(k_cd_step<3>, grid, dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1, w.mask, later, cs,
+                               ce, D, pass, p->tie, nb, w.props, w.ptab, gs, ge, w.ends, w.etab);
                 else
-                    BGV_LAUNCH(k_cd_step<2>, grid, dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1, cs, ce, D, pass, p->tie, nb,
-                               w.props, w.ptab, gs, ge, w.ends, w.etab);
+                    BGV_LAUNCH(k_cd_step<2>, grid, dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1,
+                               pass == 1 && later.n > 0 ? w.mask : (uint8_t *)nullptr, later, cs, ce, D, pass, p->tie,
+                               nb, w.props, w.ptab, gs, ge, w.ends, w.etab);
                 ptiles = tiles;
                 etiles = gtiles;
             }
