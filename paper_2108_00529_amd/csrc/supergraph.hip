@@ -204,9 +204,11 @@ constexpr int kKeyItems = 16;  // edges per thread; a block compacts kSgThreads*
 // nsid[v] = sid of node v's community: an edge is inter-community iff its endpoints'
 // sids differ, and since sids ascend with labels, (min, max) of the two sids is
 // (sid of the smaller label, sid of the larger).
-template <typename KT>  // 32-bit keys when 2 * kbits <= 32
+// 32-bit keys when 2 * kbits <= 32; then the supernode ids are gathered as 16-bit values
+// (half the footprint of the random gathers, which bound this kernel)
+template <typename KT, typename NT>
 __global__ void __launch_bounds__(kSgThreads) k_sg_edge_keys(const int2 *__restrict__ edges, int64_t m,
-                                                              const uint32_t *__restrict__ nsid, int kbits,
+                                                              const NT *__restrict__ nsid, int kbits,
                                                               KT *__restrict__ keys,
                                                               unsigned long long *__restrict__ nkeys) {
     __shared__ unsigned long long s_base;
@@ -220,7 +222,7 @@ __global__ void __launch_bounds__(kSgThreads) k_sg_edge_keys(const int2 *__restr
         if (i < m) {
             const int2 e = edges[i];
             if (e.x != e.y) {
-                const uint32_t a = nsid[e.x], b = nsid[e.y];
+                const uint32_t a = (uint32_t)nsid[e.x], b = (uint32_t)nsid[e.y];
                 if (a != b) {
                     k[j] = ((KT)min(a, b) << kbits) | (KT)max(a, b);
                     flags |= 1u << j;
@@ -487,17 +489,22 @@ __global__ void k_sg_pair_weights(const int32_t *__restrict__ superedges, const 
 }
 
 // nsid[v] = sid of node v's community (and the caller's copy when asked for).
+// nsid16: the same ids in 16 bits (saturated; exact whenever K <= 65536, the only case
+// that reads it), written before K is known on the host.
 __global__ void k_sg_node_super(const int32_t *__restrict__ labels, const uint32_t *__restrict__ sid, int32_t n,
-                                uint32_t *__restrict__ nsid, int32_t *__restrict__ node_super) {
+                                uint32_t *__restrict__ nsid, uint16_t *__restrict__ nsid16,
+                                int32_t *__restrict__ node_super) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t x = sid[labels[v]];
         nsid[v] = x;
+        nsid16[v] = (uint16_t)(x < 65535u ? x : 65535u);
         if (node_super) node_super[v] = (int32_t)x;
     }
 }
 
 struct SgWs {
     uint32_t *flag, *sid, *vol, *nsid, *counters, *utile, *run_start;
+    uint16_t *nsid16;
     uint64_t *keys, *keys_alt;
     uint2 *ent;       // grouped sketch-2 entries (bucketed sketch only)
     uint32_t *etab;   // their per-tile offset rows
@@ -514,6 +521,7 @@ static size_t sg_layout(Carver &c, int32_t n, int64_t m, int32_t rows, int64_t c
     w->ltab = nullptr;
     w->flag = c.take<uint32_t>((size_t)n);
     w->nsid = c.take<uint32_t>((size_t)n);
+    w->nsid16 = c.take<uint16_t>((size_t)n);
     w->sid = c.take<uint32_t>((size_t)n);
     w->vol = c.take<uint32_t>((size_t)n);
     w->counters = c.take<uint32_t>(8);  // [0] K, [1] E_S, [2..3] key count (u64, 8-byte aligned)
@@ -642,7 +650,7 @@ extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges,
     }
     BGV_LAUNCH(k_sg_super_size, dim3(gn), dim3(kSgThreads), 0, s, super_label, &w.counters[0], h1, rows, cols,
                        M1, super_size);
-    BGV_LAUNCH(k_sg_node_super, dim3(gn), dim3(kSgThreads), 0, s, labels, w.sid, n, w.nsid, node_super);
+    BGV_LAUNCH(k_sg_node_super, dim3(gn), dim3(kSgThreads), 0, s, labels, w.sid, n, w.nsid, w.nsid16, node_super);
 
     BGV_CHECK_HIP(hipEventSynchronize(rb->ev));
     const uint32_t Kh = rb->host[0];
@@ -652,14 +660,17 @@ extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges,
 
     // inter-community keys, sorted and made unique, then sketch 2 and the weights
     unsigned long long *nkeys_d = reinterpret_cast<unsigned long long *>(&w.counters[2]);
+    // one profiler name per key width
+    const auto k_sg_edge_keys_32 = k_sg_edge_keys<uint32_t, uint16_t>;
+    const auto k_sg_edge_keys_64 = k_sg_edge_keys<uint64_t, uint32_t>;
     const bool k32 = 2 * kbits <= 32;  // keys in 32 bits: half the sort traffic
     uint32_t *keys32 = reinterpret_cast<uint32_t *>(w.keys), *keys32_alt = reinterpret_cast<uint32_t *>(w.keys_alt);
     if (m > 0) {
         const dim3 gkey((unsigned)((m + kSgThreads * kKeyItems - 1) / (kSgThreads * kKeyItems)));
         if (k32)
-            BGV_LAUNCH(k_sg_edge_keys<uint32_t>, gkey, dim3(kSgThreads), 0, s, e2, m, w.nsid, kbits, keys32, nkeys_d);
+            BGV_LAUNCH(k_sg_edge_keys_32, gkey, dim3(kSgThreads), 0, s, e2, m, w.nsid16, kbits, keys32, nkeys_d);
         else
-            BGV_LAUNCH(k_sg_edge_keys<uint64_t>, gkey, dim3(kSgThreads), 0, s, e2, m, w.nsid, kbits, w.keys, nkeys_d);
+            BGV_LAUNCH(k_sg_edge_keys_64, gkey, dim3(kSgThreads), 0, s, e2, m, w.nsid, kbits, w.keys, nkeys_d);
     }
     // the key count stays on the device: everything below is sized by the edge count m,
     // which bounds it, and reads the count itself, so no host round trip is needed here
