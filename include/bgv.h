@@ -104,7 +104,7 @@ typedef struct {
  * node and 4 per edge of a chunk.  With passes > 1 another 8 per edge (each edge's
  * pass-0 endpoint counters, from which later passes' counters follow without
  * increments), and up to 2^24 nodes with passes > 2 one more byte per edge (passes 2-5
- * decided once the degrees are known).  Method 2: 48 bytes per edge, 8 per node and at most 56 per (pass, edge)
+ * decided once the degrees are known).  Method 2: 48 bytes per edge, 8 per node and at most 48 per (pass, edge)
  * proposal, plus radix-sort scratch. */
 size_t bgv_community_workspace(int32_t n, int64_t m, const bgv_cd_params *p);
 

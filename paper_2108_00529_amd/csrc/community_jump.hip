@@ -17,8 +17,10 @@
 //   2. the proposals of every (pass, edge), compacted in stream order, sorted stably
 //      by (target, global chunk): the first of each run is the winner;
 //   3. winners compacted; each one's link = the last winner into its source with an
-//      earlier chunk (a binary search over the sorted winners);
-//   4. pointer jumping along the links; a node's label = its last winner's label.
+//      earlier chunk (a binary search in the source's run of winners);
+//   4. pointer jumping along the links, in place on packed (link, label) words, each
+//      round skipped once a round has left nothing unresolved; a node's label = its
+//      last winner's label.
 // About 20 launches whatever the number of chunks, against two per chunk and pass for
 // the chunk-by-chunk form: the choice for small chunks.
 #include <algorithm>
@@ -29,6 +31,7 @@
 namespace bgv {
 
 constexpr int kSqThreads = 256;
+constexpr int kSqMaxRounds = 66;  // ceil(log2 chunks) + 1 <= 34 for 32-bit proposal indices
 
 static int bits_for(uint64_t x) {  // bits needed to hold values 0..x
     int b = 0;
@@ -58,13 +61,14 @@ bool sq_fits(int32_t n, int64_t m, const bgv_cd_params *p) {
 struct SqWs {
     uint32_t *okey, *okey_alt, *oval, *oval_alt;  // endpoint occurrences [2m]
     uint32_t *beg, *end;                          // run of each node in the sorted occurrences [n]
-    int4 *cd;                                     // per edge {c(e.x), c(e.y), d(e.x), d(e.y)}
+    int4 *cd;                                     // per edge {c(e.x), d(e.x), c(e.y), d(e.y)}
     uint32_t *flag;                               // [P m]: proposals, then winners
     void *evk, *evk_alt;                          // proposal keys (target, chunk) [P m], 32 or 64 bits
     uint32_t *evv, *evv_alt;                      // their edge indices
     void *wk;                                     // winners' keys [P m]
     uint32_t *wv;                                 // winners' edge indices
-    int32_t *nxt, *nxt2, *val, *val2;             // links and labels, ping-pong [P m]
+    unsigned long long *jv;                       // per winner: label << 32 | link (link ~0: resolved) [P m]
+    int32_t *go;                                  // [kSqMaxRounds + 1]: round r runs if go[r]
     uint32_t *tot;                                // [4]: proposals, winners
     unsigned long long *tot64;                    // proposals, as the sort's device count
     void *sort_scratch, *scan_scratch;
@@ -93,10 +97,8 @@ size_t sq_layout(Carver &c, int32_t n, int64_t m, const bgv_cd_params *p, void *
     w.evv_alt = c.take<uint32_t>(pm);
     w.wk = c.take<char>(pm * kw);
     w.wv = c.take<uint32_t>(pm);
-    w.nxt = c.take<int32_t>(pm);
-    w.nxt2 = c.take<int32_t>(pm);
-    w.val = c.take<int32_t>(pm);
-    w.val2 = c.take<int32_t>(pm);
+    w.jv = c.take<unsigned long long>(pm);
+    w.go = c.take<int32_t>(kSqMaxRounds + 1);
     w.tot = c.take<uint32_t>(4);
     w.tot64 = c.take<unsigned long long>(2);
     w.sort_scratch = c.take<char>(radix_workspace((int64_t)std::max(no, pm)));
@@ -147,15 +149,26 @@ __global__ void __launch_bounds__(kSqThreads) k_sq_counts(const uint32_t *__rest
         const int64_t i = o >> 1;
         const int64_t ce = std::min<int64_t>((i / B + 1) * B, m);
         const uint64_t lim = 2 * (uint64_t)ce;
-        uint32_t lo = (uint32_t)j + 1, hi = end[x];
+        // gallop from j (the chunk's run of x is usually short), then bisect
+        const uint32_t e = end[x];
+        uint32_t lo = (uint32_t)j + 1, hi = e;
+        uint64_t step = 1;
+        while (true) {
+            const uint64_t probe = (uint64_t)j + step;
+            if (probe >= e || (uint64_t)sv[probe] >= lim) {
+                hi = probe < e ? (uint32_t)probe : e;
+                break;
+            }
+            lo = (uint32_t)probe + 1;
+            step <<= 1;
+        }
         while (lo < hi) {
             const uint32_t mid = lo + (hi - lo) / 2;
             if ((uint64_t)sv[mid] < lim) lo = mid + 1;
             else hi = mid;
         }
-        int32_t *rec = reinterpret_cast<int32_t *>(cd + i);
-        rec[o & 1u] = (int32_t)(lo - beg[x]);
-        rec[2 + (o & 1u)] = (int32_t)(end[x] - beg[x]);
+        // one 8-byte store per occurrence: {c, d} of this endpoint
+        reinterpret_cast<int2 *>(cd + i)[o & 1u] = make_int2((int32_t)(lo - beg[x]), (int32_t)(e - beg[x]));
     }
 }
 
@@ -163,7 +176,7 @@ __global__ void __launch_bounds__(kSqThreads) k_sq_counts(const uint32_t *__rest
 // the endpoint with the smaller one is the target; equal ones with tie rule 1: e.x.
 __device__ __forceinline__ int32_t sq_target(int2 e, int4 c, int32_t p, int32_t D, int32_t tie) {
     if (e.x == e.y) return -1;
-    const int32_t cu = p * c.z + c.x, cv = p * c.w + c.y;
+    const int32_t cu = p * c.y + c.x, cv = p * c.w + c.z;
     if (cu <= D && cv <= D && (cu != cv || tie)) return cu <= cv ? e.x : e.y;
     return -1;
 }
@@ -225,13 +238,28 @@ __global__ void __launch_bounds__(kSqThreads) k_sq_compact(const KT *__restrict_
     }
 }
 
-// Winner r's link: the last winner into its source with an earlier chunk, or -1; its
-// value: the source (the label it carries when the link is -1).
+// The run of each node in the sorted winners (beg/end cleared before).
+template <class KT>
+__global__ void __launch_bounds__(kSqThreads) k_sq_wruns(const KT *__restrict__ wk,
+                                                         const uint32_t *__restrict__ wcount, int gbits,
+                                                         uint32_t *__restrict__ beg, uint32_t *__restrict__ end) {
+    const int64_t W = *wcount;
+    SQ_LOOP(r, W) {
+        const uint32_t v = (uint32_t)((uint64_t)wk[r] >> gbits);
+        if (r == 0 || (uint32_t)((uint64_t)wk[r - 1] >> gbits) != v) beg[v] = (uint32_t)r;
+        if (r + 1 == W || (uint32_t)((uint64_t)wk[r + 1] >> gbits) != v) end[v] = (uint32_t)(r + 1);
+    }
+}
+
+// Winner r's link: the last winner into its source with an earlier chunk, or none
+// (~0); packed with the source, the label it carries when it has no link.
 template <class KT>
 __global__ void __launch_bounds__(kSqThreads) k_sq_links(const int2 *__restrict__ edges, const KT *__restrict__ wk,
                                                          const uint32_t *__restrict__ wv,
                                                          const uint32_t *__restrict__ wcount, int gbits,
-                                                         int32_t *__restrict__ nxt, int32_t *__restrict__ val) {
+                                                         const uint32_t *__restrict__ beg,
+                                                         const uint32_t *__restrict__ end,
+                                                         unsigned long long *__restrict__ jv) {
     const int64_t W = *wcount;
     SQ_LOOP(r, W) {
         const uint64_t key = (uint64_t)wk[r];
@@ -240,36 +268,42 @@ __global__ void __launch_bounds__(kSqThreads) k_sq_links(const int2 *__restrict_
         const int2 e = edges[wv[r]];
         const int32_t u = e.x == v ? e.y : e.x;
         const uint64_t want = ((uint64_t)u << gbits) | (key & gmask);
-        int64_t lo = 0, hi = W;  // first winner with key >= want
+        const uint32_t b0 = beg[u];
+        uint32_t lo = b0, hi = end[u];  // u's winners (empty: beg = end = 0); first key >= want
         while (lo < hi) {
-            const int64_t mid = lo + (hi - lo) / 2;
+            const uint32_t mid = lo + (hi - lo) / 2;
             if ((uint64_t)wk[mid] < want) lo = mid + 1;
             else hi = mid;
         }
-        const int64_t c = lo - 1;
-        nxt[r] = (c >= 0 && (int32_t)((uint64_t)wk[c] >> gbits) == u) ? (int32_t)c : -1;
-        val[r] = u;
+        const uint32_t link = lo > b0 ? lo - 1 : 0xffffffffu;
+        jv[r] = ((unsigned long long)(uint32_t)u << 32) | link;
     }
 }
 
-// One pointer-jumping round: a winner whose link is resolved takes its label; any other
-// skips to its link's link.
-__global__ void __launch_bounds__(kSqThreads) k_sq_jump(const int32_t *__restrict__ nxt,
-                                                        const int32_t *__restrict__ val,
-                                                        const uint32_t *__restrict__ wcount,
-                                                        int32_t *__restrict__ nxt2, int32_t *__restrict__ val2) {
+// One pointer-jumping round, in place: a winner whose link is resolved takes its
+// label; any other skips to its link's link.  Each 8-byte word is read and written by
+// one instruction, so a concurrent reader sees a link and label that belong together
+// (older or newer, both true of the chain: its label is that of its link's), and the
+// final label is copied only from a resolved word; every word read is at least as new
+// as the round's start, so each round at least halves every remaining chain.  The
+// round does nothing if the previous one left nothing unresolved (*go_in == 0), and
+// sets *go_out when it did not resolve everything.
+__global__ void __launch_bounds__(kSqThreads) k_sq_jump(unsigned long long *jv, const uint32_t *__restrict__ wcount,
+                                                        const int32_t *go_in, int32_t *go_out) {
+    if (*go_in == 0) return;  // the same value for every thread of the grid
     const int64_t W = *wcount;
+    bool more = false;
     SQ_LOOP(r, W) {
-        const int32_t a = nxt[r];
-        if (a < 0) {
-            nxt2[r] = -1;
-            val2[r] = val[r];
-        } else {
-            const int32_t b = nxt[a];
-            nxt2[r] = b < 0 ? -1 : b;
-            val2[r] = b < 0 ? val[a] : val[r];
-        }
+        const unsigned long long w0 = __hip_atomic_load(&jv[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const uint32_t a = (uint32_t)w0;
+        if (a == 0xffffffffu) continue;
+        const unsigned long long wa = __hip_atomic_load(&jv[a], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const uint32_t b = (uint32_t)wa;
+        const unsigned long long nw = b == 0xffffffffu ? wa : ((w0 & 0xffffffff00000000ull) | b);
+        more |= b != 0xffffffffu;
+        __hip_atomic_store(&jv[r], nw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
+    if (__syncthreads_or(more) && threadIdx.x == 0) *go_out = 1;
 }
 
 __global__ void __launch_bounds__(kSqThreads) k_sq_init(int32_t n, int32_t rows, int32_t *__restrict__ labels,
@@ -288,7 +322,8 @@ __global__ void __launch_bounds__(kSqThreads) k_sq_init(int32_t n, int32_t rows,
 template <class KT>
 __global__ void __launch_bounds__(kSqThreads) k_sq_labels(const KT *__restrict__ wk,
                                                           const uint32_t *__restrict__ wcount, int gbits,
-                                                          int64_t nchunk, int32_t P, const int32_t *__restrict__ val,
+                                                          int64_t nchunk, int32_t P,
+                                                          const unsigned long long *__restrict__ jv,
                                                           int32_t n, int32_t *__restrict__ labels,
                                                           int32_t *__restrict__ pass_labels) {
     const int64_t W = *wcount;
@@ -297,11 +332,12 @@ __global__ void __launch_bounds__(kSqThreads) k_sq_labels(const KT *__restrict__
         const uint64_t gmask = gbits >= 64 ? ~0ull : ((1ull << gbits) - 1ull);
         const int32_t v = (int32_t)(key >> gbits);
         const bool more = r + 1 < W && (int32_t)((uint64_t)wk[r + 1] >> gbits) == v;
-        if (!more) labels[v] = val[r];
+        const int32_t lab = (int32_t)(jv[r] >> 32);
+        if (!more) labels[v] = lab;
         if (pass_labels) {
             const int32_t p0 = (int32_t)((key & gmask) / (uint64_t)nchunk);
             const int32_t p1 = more ? (int32_t)(((uint64_t)wk[r + 1] & gmask) / (uint64_t)nchunk) : P;
-            for (int32_t p = p0; p < p1; ++p) pass_labels[(int64_t)p * n + v] = val[r];
+            for (int32_t p = p0; p < p1; ++p) pass_labels[(int64_t)p * n + v] = lab;
         }
     }
 }
@@ -355,16 +391,20 @@ static bgv_status sq_events(const int2 *e2, int32_t n, int64_t m, const bgv_cd_p
     BGV_TRY(exclusive_scan_u32(w.flag, w.flag, pm, w.tot + 1, w.scan_scratch, s));
     KT *wk = static_cast<KT *>(w.wk);
     BGV_LAUNCH(k_sq_compact<KT>, dim3(grid), dim3(kSqThreads), 0, s, sk, sv, w.tot, w.flag, wk, w.wv);
-    BGV_LAUNCH(k_sq_links<KT>, dim3(grid), dim3(kSqThreads), 0, s, e2, wk, w.wv, w.tot + 1, gbits, w.nxt, w.val);
+    // each winner's link: a search in its source's run of winners (the occurrence runs'
+    // arrays, free by now, hold the winner runs)
+    BGV_TRY(fill<uint32_t>(w.beg, 0u, n, s));
+    BGV_TRY(fill<uint32_t>(w.end, 0u, n, s));
+    BGV_LAUNCH(k_sq_wruns<KT>, dim3(grid), dim3(kSqThreads), 0, s, wk, w.tot + 1, gbits, w.beg, w.end);
+    BGV_LAUNCH(k_sq_links<KT>, dim3(grid), dim3(kSqThreads), 0, s, e2, wk, w.wv, w.tot + 1, gbits, w.beg, w.end,
+               w.jv);
     // a chain of links visits at most one winner per chunk: ceil(log2 chunks) + 1 rounds
     const int rounds = bits_for((uint64_t)P * (uint64_t)nchunk) + 1;
-    int32_t *nx = w.nxt, *vl = w.val, *nx2 = w.nxt2, *vl2 = w.val2;
-    for (int r = 0; r < rounds; ++r) {
-        BGV_LAUNCH(k_sq_jump, dim3(grid), dim3(kSqThreads), 0, s, nx, vl, w.tot + 1, nx2, vl2);
-        std::swap(nx, nx2);
-        std::swap(vl, vl2);
-    }
-    BGV_LAUNCH(k_sq_labels<KT>, dim3(grid), dim3(kSqThreads), 0, s, wk, w.tot + 1, gbits, nchunk, P, vl, n, labels,
+    BGV_TRY(fill<int32_t>(w.go, 0, rounds + 1, s));
+    BGV_TRY(fill<int32_t>(w.go, 1, 1, s));
+    for (int r = 0; r < rounds; ++r)
+        BGV_LAUNCH(k_sq_jump, dim3(grid), dim3(kSqThreads), 0, s, w.jv, w.tot + 1, w.go + r, w.go + r + 1);
+    BGV_LAUNCH(k_sq_labels<KT>, dim3(grid), dim3(kSqThreads), 0, s, wk, w.tot + 1, gbits, nchunk, P, w.jv, n, labels,
                pass_labels);
     return BGV_OK;
 }
