@@ -183,16 +183,16 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_downsweep(const KT *keys, KT 
     if (raw_counts) {
         // few tiles: derive this tile's digit offsets from the raw per-tile counts here
         // instead of a separate device-wide scan
-        // eight independent loads at a time (a dependent chain of nb L2 round trips
-        // otherwise dominates small sorts)
+        // 32 independent loads at a time: one L2 round trip for up to 32 tiles (a
+        // dependent chain of round trips otherwise dominates small sorts)
         uint32_t tot = 0, pre = 0;
         const uint32_t *row = offsets + (int64_t)t * nb;
-        for (int64_t b0 = 0; b0 < nb; b0 += 8) {
-            uint32_t c[8];
+        for (int64_t b0 = 0; b0 < nb; b0 += 32) {
+            uint32_t c[32];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) c[u] = b0 + u < nb ? row[b0 + u] : 0u;
+            for (int u = 0; u < 32; ++u) c[u] = b0 + u < nb ? row[b0 + u] : 0u;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < 32; ++u) {
                 if (b0 + u < (int64_t)blockIdx.x) pre += c[u];
                 tot += c[u];
             }
