@@ -696,7 +696,19 @@ def cpu_baseline(edges_np, n, wl, c1, c2, pos0_np, fa2_iters):
             "sample": f"community passes + sketch supergraph over all {edges_np.shape[0]} edges "
                       f"({t_cd:.1f}s, 1 thread); FA2: {fa2_iters} Barnes-Hut iterations on the "
                       f"{K}-node supergraph in {t_fa:.1f}s with {threads} OpenMP threads",
-            "fa2_iters_per_s": fa2_iters / t_fa, "fa2_threads": threads}
+            "fa2_iters_per_s": fa2_iters / t_fa, "fa2_threads": threads,
+            "host_cpu": host_cpu_model(), "host_threads": os.cpu_count()}
+
+
+def host_cpu_model() -> str:
+    """The host CPU's model name (Linux /proc/cpuinfo), or "unknown"."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 if __name__ == "__main__":
