@@ -263,7 +263,8 @@ bgv_status bgv_fa2_grad(int32_t K, int64_t E, const int32_t *edges, const float 
  * of the concatenated arrays (node_off, edge_off: dev int64[G+1], non-decreasing,
  * node_off[G] = n_total, edge_off[G] = m_total); its edges use local ids in
  * [0, n_g).  Sketch shape: rows * cols <= 8192 (each graph's sketches live in LDS).
- * fa->exact must be 1.  wg_threads: 256, 512 or 1024 (0 = 512), a launch parameter that
+ * cd: the degree rule only (cd->rule 0; cd->tie 0 or 1), cd->method 0 (each workgroup
+ * runs its graph chunk by chunk).  fa->exact must be 1.  wg_threads: 256, 512 or 1024 (0 = 512), a launch parameter that
  * does not change any result.  big_k >= 0, another such parameter: a graph whose
  * supergraph has more than big_k nodes (and at most 4096) is laid out after the
  * persistent launch by kernels that spread each graph's tiles and repulsion segments

@@ -130,6 +130,35 @@ def test_fa2_validation():
     assert L.bgv_fa2_grad(10, 0, None, None, None, one, 1.0, 1.0, None, None, one, 1 << 20, None) == -1
 
 
+def test_batched_validation():
+    """Rejected on the host before any HIP call: community options the batched form
+    does not run (volume rule, back-pointer method, tie values other than 0/1), layout
+    and launch parameters, null outputs, and a small or misaligned workspace."""
+    import numpy as np
+    coef = np.zeros((4, 3), np.uint64)
+    sk = L.SketchParams(4, 1024, coef.ctypes.data_as(C.c_void_p), coef.ctypes.data_as(C.c_void_p))
+    fa = L.Fa2Params(10, 1, 1.2, 1.0, 1.0, 1.0, 0.1, 10.0)
+    G, n, m = 2, 20, 40
+    need = L.bgv_batched_workspace(G, n, m)
+    assert need > 0 and L.bgv_batched_workspace(0, n, m) == 0
+    one = C.c_void_p(256)
+
+    def call(cd=L.CdParams(16, 1, 2, 0, 256), sk=sk, fa=fa, wg=0, big_k=0, labels=one, ws=C.c_void_p(512), nbytes=need):
+        return L.bgv_batched(G, n, m, one, one, None, one, C.byref(cd), C.byref(sk), C.byref(fa), wg, big_k, labels,
+                             one, one, one, one, one, one, one, one, one, one, ws, nbytes, None)
+
+    for cd in [L.CdParams(16, 1, 2, 0, 256, 0, 1), L.CdParams(16, 1, 2, 2, 256), L.CdParams(16, 1, 2, 1, 256),
+               L.CdParams(16, 1, 2, 0, 256, 2, 0), L.CdParams(16, 0, 2, 0, 256)]:
+        assert call(cd=cd) == -1
+    assert call(fa=L.Fa2Params(10, 0, 1.2, 1.0, 1.0, 1.0, 0.1, 10.0)) == -1        # Barnes-Hut: not batched
+    assert call(sk=L.SketchParams(4, 4096, coef.ctypes.data_as(C.c_void_p), coef.ctypes.data_as(C.c_void_p))) == -1
+    assert call(wg=128) == -1 and call(big_k=-1) == -1
+    assert call(labels=None) == -1
+    assert b"null pointer" in L.bgv_last_error()
+    assert call(nbytes=need - 1) == -3 and call(ws=C.c_void_p(513)) == -3
+    assert call(cd=L.CdParams(16, 1, 2, 0, 256, 1, 0), nbytes=need - 1) == -3  # the tie rule is accepted
+
+
 def test_draw_validation():
     assert L.bgv_draw_workspace(0) == 0 and L.bgv_draw_workspace(-5) == 0
     assert L.bgv_draw_workspace(1000) > 4 * 8 * 1000
