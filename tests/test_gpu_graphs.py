@@ -51,3 +51,42 @@ def test_captured_community_replays_match_eager(bgv, method):
             assert torch.equal(a, b), (method, rep)
         junk = torch.randn(1 << 20, device=dev)  # unrelated eager work between replays
         (junk * 2).sum().item()
+
+
+@pytest.mark.parametrize("exact", [False, True])
+def test_captured_layout_replays_match_eager(bgv, exact):
+    """ForceAtlas2 iterations (Barnes-Hut and exact) captured in a HIP graph: each
+    replay restarts from the same positions and ends on the eager positions."""
+    rng = np.random.default_rng(93)
+    K = 6000
+    se = np.array(sorted({(min(a, b), max(a, b)) for a, b in rng.integers(0, K, (30_000, 2)).tolist() if a != b}),
+                  np.int32)
+    dev = torch.device("cuda")
+    sed = torch.from_numpy(se).to(dev)
+    pos0 = torch.from_numpy(graphgen.initial_positions(K, 7)).to(dev)
+    pos, fprev = pos0.clone(), torch.zeros_like(pos0)
+    speed = torch.ones(1, dtype=torch.float32, device=dev)
+
+    def run():
+        pos.copy_(pos0)
+        fprev.zero_()
+        speed.fill_(1.0)
+        bgv.fa2_layout(sed, pos, 30, exact=exact, theta=1.2, fprev=fprev, speed=speed)
+
+    run()
+    torch.cuda.synchronize()
+    eager = pos.clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        run()
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        run()
+    for rep in range(3):
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(pos, eager), (exact, rep)
+        junk = torch.randn(1 << 20, device=dev)
+        (junk * 2).sum().item()
