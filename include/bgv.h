@@ -99,7 +99,7 @@ typedef struct {
 } bgv_cd_params;
 
 /* Workspace bytes for bgv_community (0 only on invalid arguments).  Up to 2^24 nodes:
- * 8 bytes per node and, per 1024-edge tile of a chunk, 16 KiB of grouped proposals and
+ * 8 bytes per node and, per 2048-edge tile of a chunk, 32 KiB of grouped proposals and
  * endpoints plus two offset rows of 4 * (ceil(n / 4096) + 1) bytes.  Above: 16 bytes per
  * node and 4 per edge of a chunk.  With passes > 1 another 8 per edge (each edge's
  * pass-0 endpoint counters, from which later passes' counters follow without

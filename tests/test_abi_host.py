@@ -38,7 +38,7 @@ def test_status_strings():
 def test_community_validation_and_workspace():
     p = L.CdParams(16, 1, 2, 0, 4096)
     ws = L.bgv_community_workspace(2000, 10000, C.byref(p))
-    assert ws >= 2000 * 8 + 4 * 1024 * 16  # records + four 1024-edge tiles of grouped entries
+    assert ws >= 2000 * 8 + 4096 * 16  # records + a 4096-edge chunk of grouped entries (16 B per edge)
     ws2 = L.bgv_community_workspace(2000, 100, C.byref(p))  # chunk clipped to m: one tile
     assert ws2 < ws
     p3 = L.CdParams(16, 3, 2, 0, 4096)

@@ -99,7 +99,7 @@ def test_community_tiny_and_degenerate(bgv):
 
 
 def test_community_bucket_boundaries(bgv):
-    """Several 4096-node buckets, chunks of several 1024-edge tiles with ragged tails,
+    """Several 4096-node buckets, chunks of several 2048-edge tiles with ragged tails,
     a hub in every chunk (many proposals to and from one bucket) and self-loops."""
     rng = np.random.default_rng(23)
     n = 3 * 4096 + 17
@@ -110,7 +110,7 @@ def test_community_bucket_boundaries(bgv):
     e[rng.random(m) < 0.01, 1] = n - 1
     loop = rng.random(m) < 0.02
     e[loop, 1] = e[loop, 0]
-    for B, P in ((5000, 3), (1024, 2), (1025, 1), (m, 2)):
+    for B, P in ((5000, 3), (1024, 2), (1025, 1), (2048, 2), (2049, 1), (m, 2)):
         check_community(bgv, n, e, 6, P, 2, B)
 
 
