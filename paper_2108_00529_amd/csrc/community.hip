@@ -44,7 +44,7 @@ struct __align__(16) NodeState {
 };
 static_assert(sizeof(NodeState) == 16, "node record must be 16 bytes");
 
-constexpr int kCdThreads = 256;
+constexpr int kCdThreads = 1024;
 constexpr uint64_t kNoProposal = ~0ull;
 
 __global__ void __launch_bounds__(kCdThreads) k_cd_init(NodeState *st, int32_t n) {
@@ -140,7 +140,10 @@ __global__ void __launch_bounds__(kCdThreads) k_cd_finish(const int32_t *__restr
 constexpr int kCdBucketBits = 12;
 constexpr int32_t kCdBucket = 1 << kCdBucketBits;  // node ids per bucket
 constexpr int32_t kCdMaxBuckets = 4096;             // bucket histogram held in LDS
-constexpr int kCdItems = 8;  // 2048-edge tiles: fewer segments per resolve (1024: +4%, 4096: +14%)
+// 2048-edge tiles of 1024 threads x 2 edges: fewer segments per resolve than 1024-edge
+// tiles, and shorter per-thread chains in the decide than 256 x 8 or 512 x 4 (community
+// passes on a 10M-edge stream: 0.87 ms; 256 x 8: 0.94; 256 x 4: 0.98; 256 x 16: 1.06)
+constexpr int kCdItems = 2;
 constexpr int32_t kCdTile = kCdThreads * kCdItems;  // edges per tile
 
 inline int32_t cd_buckets(int32_t n) { return (n + kCdBucket - 1) / kCdBucket; }
