@@ -416,6 +416,21 @@ def test_first_iteration_global_speed():
         assert abs(sp - min(tau / 2, 1.5)) < 1e-12
 
 
+@pytest.mark.parametrize("row", _rows("fa2_first_step.txt"))
+def test_speed_and_displacement_by_hand(row):
+    """Two-body steps worked out from the closed forms (tests/golden/fa2_first_step.txt):
+    swing, traction, the global speed and its 1.5x cap, the local speed law, the
+    ksmax cap on the step and the mass weights of S and T, along two directions."""
+    t0, t1, m0, m1, kr, kg, tau, ks, ksmax, iters, cx, cy, e0, e1, es = row
+    u = np.array([cx, cy])
+    x0 = np.array([t0 * u, t1 * u])
+    se = np.array([[0, 1]], np.int32)
+    x, _, sp = oracle.fa2_layout(x0, se, np.array([m0, m1]), iters=int(iters), exact=True, kr=kr, kg=kg,
+                                 tau=tau, ks=ks, ksmax=ksmax)
+    assert np.allclose(x, np.array([e0 * u, e1 * u]), rtol=0, atol=1e-13)
+    assert abs(sp - es) < 1e-14
+
+
 def _rand_fa2(seed, K=40, E=80):
     rng = np.random.default_rng(seed)
     x = rng.uniform(-1, 1, size=(K, 2))
