@@ -58,8 +58,9 @@ def _load():
         _lib.orc_fa2_node_energy.argtypes = [i32, P, P, i64, P, P, f64, f64, i32]
         _lib.orc_fa2_node_energy.restype = f64
         _lib.orc_bh_codes.argtypes = [i32, P, P, P, P, P]
-        _lib.orc_bh_tree_export.argtypes = [i32, P, P, P, P, P]
+        _lib.orc_bh_tree_export.argtypes = [i32, P, P, P, P, P, P]
         _lib.orc_bh_tree_export.restype = i32
+        _lib.orc_bh_repulsion.argtypes = [i32, P, P, f64, f64, P, P]
     return _lib
 
 
@@ -225,16 +226,33 @@ def bh_codes(pos32):
 
 
 def bh_tree(pos, mass):
-    """Barnes-Hut tree: (order[K], nodes_i (N,4) lo,hi,left,right, nodes_d (N,4) size,mass,cx,cy)."""
+    """Barnes-Hut compressed quadtree: (order[K], nodes_i (N,5) lo,hi,child0,nchild,depth,
+    nodes_d (N,4) size,mass,cx,cy, child list).  Node 0 is the root; the children of
+    node k are child[child0 : child0 + nchild] (none for a leaf)."""
     lib = _load()
     x = _c(pos, np.float64).reshape(-1, 2)
     K = x.shape[0]
     ms = _c(mass, np.float64)
     order = np.empty(K, np.int32)
-    ni = np.empty((2 * K, 4), np.int32)
+    ni = np.empty((2 * K, 5), np.int32)
     nd = np.empty((2 * K, 4), np.float64)
-    nn = lib.orc_bh_tree_export(K, _p(x), _p(ms), _p(order), _p(ni), _p(nd))
-    return order, ni[:nn].copy(), nd[:nn].copy()
+    ch = np.empty(2 * K, np.int32)
+    nn = lib.orc_bh_tree_export(K, _p(x), _p(ms), _p(order), _p(ni), _p(nd), _p(ch))
+    nc = int(ni[:nn, 3].sum())
+    return order, ni[:nn].copy(), nd[:nn].copy(), ch[:nc].copy()
+
+
+def bh_repulsion(pos, mass, kr=1.0, theta=1.2):
+    """Barnes-Hut repulsion (K,2) FP64 and, per body, whether any of its opening
+    decisions is borderline (within single-precision rounding of theta)."""
+    lib = _load()
+    x = _c(pos, np.float64).reshape(-1, 2)
+    K = x.shape[0]
+    ms = _c(mass, np.float64)
+    F = np.zeros((K, 2), np.float64)
+    border = np.zeros(K, np.int32)
+    lib.orc_bh_repulsion(K, _p(x), _p(ms), kr, theta, _p(F), _p(border))
+    return F, border.astype(bool)
 
 
 # -------------------------------------------------------------- whole pipeline --

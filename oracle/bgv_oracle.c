@@ -315,30 +315,44 @@ static void orc_repulse_exact(int32_t K, const double *x, const double *mass, do
     }
 }
 
-/* ---- Barnes-Hut tree (Section 3.1 body repulsion) ----------------------------
- * Bodies are placed in the bounding square of their FP32 positions (side s0 = the
- * larger extent, 1 if zero), quantised to a 2^16 x 2^16 grid in FP32 arithmetic and
- * given 32-bit Morton codes (x bits at even positions, y bits at odd positions).
- * Bodies sorted by (code, index).  The tree recursively splits a code range at the
- * first bit (from the top) on which its first and last codes differ; a range whose
- * codes are all equal is a leaf (several bodies when they share a grid cell).  A
- * node whose codes share a prefix of P bits has cell size s0 / 2^floor(P/2).
- * Node mass = sum of body masses; centre of mass summed in sorted order. */
+/* ---- Barnes-Hut quadtree (Section 3.1 body repulsion) ---------------------------
+ * Section 3.1 approximates far groups of bodies through a hierarchical partition of
+ * the plane (the GPU quadtree of Burtscher and Pingali it cites).  The quadtree here:
+ * bodies are placed in the bounding square of their FP32 positions (side s0 = the
+ * larger extent, 1 if zero) and quantised to a 2^16 x 2^16 grid in FP32 arithmetic; a
+ * cell of depth d is a square of side s0 / 2^d, split into its four quadrants at
+ * depth d + 1.  The tree is the compressed quadtree: every node is the smallest cell
+ * that holds its bodies, so an internal node's bodies occupy at least two of its
+ * quadrants, and its children are the nodes of the occupied quadrants.  Bodies that
+ * share one grid point form a leaf (depth 16); so does a single body.  The node mass
+ * is the sum of the body masses and the centre of mass their weighted mean.
+ * (A chain of cells with one occupied quadrant has one body set and one centre of
+ * mass, and its smallest cell passes the opening test whenever a larger one does, so
+ * the uncompressed quadtree takes the same decisions.)
+ *
+ * Construction: bodies sorted by 32-bit Morton code of the grid point (x bits at the
+ * even positions), ties by body index; a cell is then a contiguous run of the sorted
+ * order, and the quadrant of a body at depth d + 1 is the two code bits below the
+ * cell's 2d-bit prefix. */
 typedef struct {
     int32_t lo, hi;        /* body range in sorted order */
-    int32_t left, right;   /* children (-1 for a leaf) */
+    int32_t child0;        /* first child in the child list, -1 for a leaf */
+    int32_t nchild;        /* 2..4 for an internal node, 0 for a leaf */
+    int32_t depth;         /* cell depth: side s0 / 2^depth */
     double size, mx, my, mass;
-} orc_bh_node;
+} orc_qt_node;
 
 typedef struct {
     int32_t K;
     int32_t *order;        /* sorted position -> body */
     int32_t *rank;         /* body -> sorted position */
     uint32_t *code;        /* code in sorted order */
-    orc_bh_node *nodes;
+    orc_qt_node *nodes;
     int32_t nnodes;
+    int32_t *child;        /* child lists */
+    int32_t nchildren;
     float s0;
-} orc_bh_tree;
+} orc_qt;
 
 static uint32_t orc_spread16(uint32_t v)
 {
@@ -381,36 +395,50 @@ static int orc_cmp_body(const void *pa, const void *pb)
     return (a > b) - (a < b);
 }
 
-static int32_t orc_bh_build_rec(orc_bh_tree *t, const double *x, const double *mass, int32_t lo, int32_t hi)
+/* The node of the smallest cell holding sorted bodies [lo, hi), and its subtree. */
+static int32_t orc_qt_build_rec(orc_qt *t, const double *x, const double *mass, int32_t lo, int32_t hi)
 {
     const int32_t id = t->nnodes++;
-    orc_bh_node *nd = &t->nodes[id];
-    nd->lo = lo; nd->hi = hi; nd->left = nd->right = -1;
     const uint32_t a = t->code[lo], b = t->code[hi - 1];
-    int prefix = 32;
+    int32_t depth = 16;
     if (a != b) {
-        prefix = 0;
+        int prefix = 0;   /* leading bits shared by all codes of the range (sorted: first and last) */
         while (((a ^ b) >> (31 - prefix) & 1u) == 0) ++prefix;
+        depth = prefix / 2;
     }
-    nd->size = (double)t->s0 / (double)(1u << (prefix / 2 > 16 ? 16 : prefix / 2));
-    if (a != b) {
-        int32_t split = lo;
-        while (((t->code[split] >> (31 - prefix)) & 1u) == 0) ++split;
-        int32_t l = orc_bh_build_rec(t, x, mass, lo, split);
-        int32_t r = orc_bh_build_rec(t, x, mass, split, hi);
-        nd = &t->nodes[id];
-        nd->left = l; nd->right = r;
-    }
+    orc_qt_node nd;
+    nd.lo = lo; nd.hi = hi; nd.depth = depth; nd.child0 = -1; nd.nchild = 0;
+    nd.size = (double)t->s0 / (double)(1u << depth);
     double M = 0.0, sx = 0.0, sy = 0.0;
     for (int32_t k = lo; k < hi; ++k) {
         const int32_t j = t->order[k];
         M += mass[j]; sx += mass[j] * x[2 * j]; sy += mass[j] * x[2 * j + 1];
     }
-    nd->mass = M; nd->mx = sx / M; nd->my = sy / M;
+    nd.mass = M; nd.mx = sx / M; nd.my = sy / M;
+    if (a != b) {
+        /* occupied quadrants at depth + 1: runs of equal 2-bit digit below the prefix */
+        const int shift = 30 - 2 * depth;
+        int32_t runs[5], nr = 0;
+        runs[nr++] = lo;
+        for (int32_t k = lo + 1; k < hi; ++k)
+            if (((t->code[k] >> shift) & 3u) != ((t->code[k - 1] >> shift) & 3u)) runs[nr++] = k;
+        runs[nr] = hi;
+        nd.child0 = t->nchildren;
+        nd.nchild = nr;
+        t->nchildren += nr;
+        for (int32_t q = 0; q < nr; ++q) t->child[nd.child0 + q] = -1;
+        t->nodes[id] = nd;
+        for (int32_t q = 0; q < nr; ++q) {
+            const int32_t c = orc_qt_build_rec(t, x, mass, runs[q], runs[q + 1]);
+            t->child[t->nodes[id].child0 + q] = c;
+        }
+    } else {
+        t->nodes[id] = nd;
+    }
     return id;
 }
 
-static void orc_bh_build(orc_bh_tree *t, int32_t K, const double *x, const double *mass)
+static void orc_qt_build(orc_qt *t, int32_t K, const double *x, const double *mass)
 {
     t->K = K;
     float *pf = (float *)malloc(sizeof(float) * 2 * (size_t)K);
@@ -418,8 +446,10 @@ static void orc_bh_build(orc_bh_tree *t, int32_t K, const double *x, const doubl
     t->order = (int32_t *)malloc(sizeof(int32_t) * (size_t)K);
     t->rank = (int32_t *)malloc(sizeof(int32_t) * (size_t)K);
     t->code = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)K);
-    t->nodes = (orc_bh_node *)malloc(sizeof(orc_bh_node) * (size_t)(2 * K));
+    t->nodes = (orc_qt_node *)malloc(sizeof(orc_qt_node) * (size_t)(2 * K));
+    t->child = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * K));
     t->nnodes = 0;
+    t->nchildren = 0;
     for (int32_t i = 0; i < 2 * K; ++i) pf[i] = (float)x[i];
     float xmin, ymin;
     orc_bh_codes(K, pf, codes, &t->s0, &xmin, &ymin);
@@ -427,25 +457,31 @@ static void orc_bh_build(orc_bh_tree *t, int32_t K, const double *x, const doubl
     orc_sort_codes = codes;
     qsort(t->order, (size_t)K, sizeof(int32_t), orc_cmp_body);
     for (int32_t k = 0; k < K; ++k) { t->code[k] = codes[t->order[k]]; t->rank[t->order[k]] = k; }
-    orc_bh_build_rec(t, x, mass, 0, K);
+    orc_qt_build_rec(t, x, mass, 0, K);
     free(pf); free(codes);
 }
 
-static void orc_bh_free(orc_bh_tree *t)
+static void orc_qt_free(orc_qt *t)
 {
-    free(t->order); free(t->rank); free(t->code); free(t->nodes);
+    free(t->order); free(t->rank); free(t->code); free(t->nodes); free(t->child);
 }
 
-/* Repulsion on body i: a node containing i is always opened; a leaf is summed body
- * by body (skipping i); otherwise a node is replaced by its centre of mass when
- * size^2 < theta^2 * dist^2 (dist > 0), else opened. */
-static void orc_bh_visit(const orc_bh_tree *t, const double *x, const double *mass, int32_t i,
-                         int32_t nid, double theta2, double kr, double *fx, double *fy)
+/* Repulsion on body i (Barnes-Hut): a node whose cell holds i is opened; a leaf is
+ * summed body by body (skipping i); any other node is replaced by its centre of mass
+ * when size / dist < theta (as size^2 < theta^2 dist^2, dist > 0), else opened.
+ *
+ * Borderline decisions: a single-precision implementation computes the distance from
+ * single-precision positions and a centre of mass rounded to single precision, so its
+ * test can fall the other way when size / dist lies within its rounding of theta.  A
+ * decision is flagged borderline when |size^2 - theta^2 dist^2| <= theta^2 dist^2 tol,
+ * tol = 1e-5 + 2 * eps32 * (|x_i| + |y_i| + |cx| + |cy|) * 4 / dist, eps32 = 2^-24:
+ * twice the relative change of dist from a rounding of every coordinate, with a
+ * factor 4 to spare. */
+static void orc_qt_visit(const orc_qt *t, const double *x, const double *mass, int32_t i,
+                         int32_t nid, double theta2, double kr, double *fx, double *fy, int32_t *border)
 {
-    const orc_bh_node *nd = &t->nodes[nid];
-    const int32_t ri = t->rank[i];
-    const int contains = (ri >= nd->lo && ri < nd->hi);
-    if (nd->left < 0) {
+    const orc_qt_node *nd = &t->nodes[nid];
+    if (nd->nchild == 0) {
         for (int32_t k = nd->lo; k < nd->hi; ++k) {
             const int32_t j = t->order[k];
             if (j == i) continue;
@@ -458,49 +494,69 @@ static void orc_bh_visit(const orc_bh_tree *t, const double *x, const double *ma
         }
         return;
     }
-    if (!contains) {
+    const int32_t ri = t->rank[i];
+    if (ri < nd->lo || ri >= nd->hi) {
         const double dx = x[2 * i] - nd->mx, dy = x[2 * i + 1] - nd->my;
         const double d2 = dx * dx + dy * dy;
+        if (border && d2 > 0.0) {
+            const double eps32 = 1.0 / 16777216.0;
+            const double tol = 1e-5 + 8.0 * eps32 * (fabs(x[2 * i]) + fabs(x[2 * i + 1]) + fabs(nd->mx) +
+                                                     fabs(nd->my)) / sqrt(d2);
+            if (fabs(nd->size * nd->size - theta2 * d2) <= theta2 * d2 * tol) *border = 1;
+        }
         if (d2 > 0.0 && nd->size * nd->size < theta2 * d2) {
             const double f = kr * mass[i] * nd->mass / d2;
             *fx += f * dx; *fy += f * dy;
             return;
         }
     }
-    orc_bh_visit(t, x, mass, i, nd->left, theta2, kr, fx, fy);
-    orc_bh_visit(t, x, mass, i, nd->right, theta2, kr, fx, fy);
+    for (int32_t q = 0; q < nd->nchild; ++q)
+        orc_qt_visit(t, x, mass, i, t->child[nd->child0 + q], theta2, kr, fx, fy, border);
 }
 
-static void orc_repulse_bh(int32_t K, const double *x, const double *mass, double kr, double theta, double *F)
+/* Barnes-Hut repulsion added into F; border (optional, K entries) receives 1 for the
+ * bodies with a borderline opening decision, else 0. */
+void orc_bh_repulsion(int32_t K, const double *x, const double *mass, double kr, double theta, double *F,
+                      int32_t *border)
 {
-    orc_bh_tree t;
-    orc_bh_build(&t, K, x, mass);
+    orc_qt t;
+    orc_qt_build(&t, K, x, mass);
     const double theta2 = theta * theta;
 #pragma omp parallel for schedule(dynamic, 64)
     for (int32_t i = 0; i < K; ++i) {
         double fx = 0.0, fy = 0.0;
-        orc_bh_visit(&t, x, mass, i, 0, theta2, kr, &fx, &fy);
+        int32_t b = 0;
+        orc_qt_visit(&t, x, mass, i, 0, theta2, kr, &fx, &fy, border ? &b : NULL);
         F[2 * i] += fx; F[2 * i + 1] += fy;
+        if (border) border[i] = b;
     }
-    orc_bh_free(&t);
+    orc_qt_free(&t);
 }
 
-/* Tree export for the structure tests: per node (lo, hi, left, right) and
- * (size, mass, cx, cy); order[K]; returns the node count (<= 2K-1). */
-int32_t orc_bh_tree_export(int32_t K, const double *x, const double *mass, int32_t *order,
-                           int32_t *node_i4, double *node_d4)
+static void orc_repulse_bh(int32_t K, const double *x, const double *mass, double kr, double theta, double *F)
 {
-    orc_bh_tree t;
-    orc_bh_build(&t, K, x, mass);
+    orc_bh_repulsion(K, x, mass, kr, theta, F, NULL);
+}
+
+/* Tree export for the structure tests: order[K]; per node (lo, hi, first child in
+ * child[], number of children, depth) and (size, mass, cx, cy); child[] (<= 2K
+ * entries).  Returns the node count (<= 2K - 1). */
+int32_t orc_bh_tree_export(int32_t K, const double *x, const double *mass, int32_t *order,
+                           int32_t *node_i5, double *node_d4, int32_t *child)
+{
+    orc_qt t;
+    orc_qt_build(&t, K, x, mass);
     for (int32_t k = 0; k < K; ++k) order[k] = t.order[k];
     for (int32_t n = 0; n < t.nnodes; ++n) {
-        node_i4[4 * n] = t.nodes[n].lo; node_i4[4 * n + 1] = t.nodes[n].hi;
-        node_i4[4 * n + 2] = t.nodes[n].left; node_i4[4 * n + 3] = t.nodes[n].right;
+        node_i5[5 * n] = t.nodes[n].lo; node_i5[5 * n + 1] = t.nodes[n].hi;
+        node_i5[5 * n + 2] = t.nodes[n].child0; node_i5[5 * n + 3] = t.nodes[n].nchild;
+        node_i5[5 * n + 4] = t.nodes[n].depth;
         node_d4[4 * n] = t.nodes[n].size; node_d4[4 * n + 1] = t.nodes[n].mass;
         node_d4[4 * n + 2] = t.nodes[n].mx; node_d4[4 * n + 3] = t.nodes[n].my;
     }
+    for (int32_t c = 0; c < t.nchildren; ++c) child[c] = t.child[c];
     int32_t nn = t.nnodes;
-    orc_bh_free(&t);
+    orc_qt_free(&t);
     return nn;
 }
 

@@ -526,57 +526,113 @@ def test_barnes_hut_error_shrinks_with_theta():
     assert errs[0] < 0.1 and errs[1] < errs[0] and errs[2] < errs[1]
 
 
-def test_barnes_hut_tree_against_geometric_cells():
-    """Every tree node holds exactly the bodies inside one grid cell of its size, the
-    children split it, and its mass / centre of mass are those of its bodies."""
-    rng = np.random.default_rng(12)
-    K = 300
-    x32 = rng.uniform(-3, 2, size=(K, 2)).astype(np.float32)
-    x32[:5] = x32[5]  # a multi-body leaf
-    x = x32.astype(np.float64)
-    mass = rng.integers(1, 6, K).astype(np.float64)
-    order, ni, nd = oracle.bh_tree(x, mass)
-    # independent FP32 quantisation
+def _quantise(x32):
+    """FP32 grid coordinates of the Barnes-Hut tree, computed here with numpy."""
     xmin, ymin = x32[:, 0].min(), x32[:, 1].min()
     s0 = max(x32[:, 0].max() - xmin, x32[:, 1].max() - ymin)
+    if not s0 > 0:
+        s0 = np.float32(1.0)
     qx = np.minimum(((x32[:, 0] - xmin) / np.float32(s0) * np.float32(65536)).astype(np.int64), 65535)
     qy = np.minimum(((x32[:, 1] - ymin) / np.float32(s0) * np.float32(65536)).astype(np.int64), 65535)
-    codes, s0o, _, _ = oracle.bh_codes(x32)
-    assert s0o == float(s0)
-    for i in range(K):
-        c = 0
-        for b in range(16):
-            c |= ((int(qx[i]) >> b) & 1) << (2 * b)
-            c |= ((int(qy[i]) >> b) & 1) << (2 * b + 1)
-        assert int(codes[i]) == c
-    assert sorted(order.tolist()) == list(range(K))
-    assert np.all(np.diff(codes[order].astype(np.int64)) >= 0)
-    assert ni[0, 0] == 0 and ni[0, 1] == K
-    for k in range(ni.shape[0]):
-        lo, hi, l, r = ni[k]
-        bodies = order[lo:hi]
-        size, M, cx, cy = nd[k]
-        assert abs(M - mass[bodies].sum()) < 1e-9
-        assert abs(cx - (mass[bodies] * x[bodies, 0]).sum() / M) < 1e-9
-        assert abs(cy - (mass[bodies] * x[bodies, 1]).sum() / M) < 1e-9
-        depth = int(round(math.log2(s0 / size)))
-        assert abs(size - s0 / 2**depth) < 1e-12 * s0
-        sh = 16 - depth
-        assert len({(int(qx[b]) >> sh, int(qy[b]) >> sh) for b in bodies}) == 1  # one cell
-        if l < 0:
-            assert len({int(codes[b]) for b in bodies}) == 1
-        else:
-            assert ni[l, 0] == lo and ni[l, 1] == ni[r, 0] and ni[r, 1] == hi
-            assert ni[l, 1] > lo and ni[r, 0] < hi
-            # the cell of a child is never larger than its parent's
-            assert nd[l, 0] <= size and nd[r, 0] <= size
-        # radix-tree node: exactly the bodies whose codes share its common prefix
-        a, b = int(codes[order[lo]]), int(codes[order[hi - 1]])
-        P = 32 if a == b else 32 - (a ^ b).bit_length()
-        members = [q for q in range(K) if (int(codes[q]) >> (32 - P)) == (a >> (32 - P))] if P < 32 else \
-                  [q for q in range(K) if int(codes[q]) == a]
-        assert sorted(members) == sorted(bodies.tolist())
-        assert depth == min(P // 2, 16)
+    return qx, qy, float(s0)
+
+
+def _quadtree_by_subdivision(qx, qy):
+    """Compressed quadtree by recursive subdivision of the grid, in plain Python: each
+    node is the smallest cell holding its bodies, its children the nodes of its
+    occupied quadrants.  Returns {(body set, depth): set of children's body sets}."""
+    out = {}
+
+    def node(bodies):
+        d = 0
+        while d < 16 and len({(int(qx[b]) >> (15 - d), int(qy[b]) >> (15 - d)) for b in bodies}) == 1:
+            d += 1
+        if d == 16 and len({(int(qx[b]), int(qy[b])) for b in bodies}) == 1:
+            out[(frozenset(bodies), 16)] = frozenset()
+            return frozenset(bodies)
+        groups = {}
+        for b in bodies:
+            groups.setdefault((int(qx[b]) >> (15 - d), int(qy[b]) >> (15 - d)), []).append(b)
+        out[(frozenset(bodies), d)] = frozenset(node(g) for g in groups.values())
+        return frozenset(bodies)
+
+    node(list(range(len(qx))))
+    return out
+
+
+def test_barnes_hut_tree_against_geometric_cells():
+    """The oracle's quadtree equals the one built by recursive subdivision of the grid
+    (node body sets, cell depths, children), its Morton codes are the grid points'
+    interleaved bits, and every node's mass and centre of mass are its bodies'."""
+    rng = np.random.default_rng(12)
+    for K, spread in ((300, 1.0), (400, 1e-3)):
+        x32 = rng.uniform(-3, 2, size=(K, 2)).astype(np.float32)
+        x32[K // 2:] = (x32[K // 2:] * np.float32(spread)).astype(np.float32)  # a dense cluster: deep cells
+        x32[:5] = x32[5]  # a multi-body leaf
+        x = x32.astype(np.float64)
+        mass = rng.integers(1, 6, K).astype(np.float64)
+        order, ni, nd, ch = oracle.bh_tree(x, mass)
+        qx, qy, s0 = _quantise(x32)
+        codes, s0o, _, _ = oracle.bh_codes(x32)
+        assert s0o == s0
+        for i in range(K):
+            c = 0
+            for b in range(16):
+                c |= ((int(qx[i]) >> b) & 1) << (2 * b)
+                c |= ((int(qy[i]) >> b) & 1) << (2 * b + 1)
+            assert int(codes[i]) == c
+        assert sorted(order.tolist()) == list(range(K))
+        assert np.all(np.diff(codes[order].astype(np.int64)) >= 0)
+        got = {}
+        for k in range(ni.shape[0]):
+            lo, hi, c0, nc, depth = ni[k]
+            bodies = order[lo:hi]
+            kids = frozenset(frozenset(order[ni[c, 0]:ni[c, 1]].tolist()) for c in ch[c0:c0 + nc]) if nc else frozenset()
+            got[(frozenset(bodies.tolist()), int(depth))] = kids
+            size, M, cx, cy = nd[k]
+            assert size == s0 / 2.0**depth
+            assert abs(M - mass[bodies].sum()) < 1e-9
+            assert abs(cx - (mass[bodies] * x[bodies, 0]).sum() / M) < 1e-9 * max(1.0, abs(cx))
+            assert abs(cy - (mass[bodies] * x[bodies, 1]).sum() / M) < 1e-9 * max(1.0, abs(cy))
+        assert ni[0, 0] == 0 and ni[0, 1] == K
+        ref = _quadtree_by_subdivision(qx, qy)
+        assert got == ref
+        assert max(d for _, d in ref) == 16 and any(len(v) == 2 for v in ref.values())
+
+
+def test_barnes_hut_opens_the_cell_holding_the_body():
+    """Body A at a corner of the square shares a quadrant (side 0.5) with a heavy body D;
+    that cell's centre of mass lies ~0.69 from A, so size / distance ~ 0.72 < theta =
+    1.2, yet the cell holds A and must be opened: A then meets D and E body by body,
+    and its repulsion is the exact pairwise sum."""
+    x = np.array([[0.0, 0.0], [0.49, 0.49], [1.0, 1.0]])
+    mass = np.array([1.0, 50.0, 2.0])
+    order, ni, nd, _ = oracle.bh_tree(x, mass)
+    cell = [k for k in range(ni.shape[0]) if sorted(order[ni[k, 0]:ni[k, 1]].tolist()) == [0, 1]][0]
+    size, _, cx, cy = nd[cell]
+    assert size == 0.5 and size / math.hypot(cx, cy) < 1.2
+    F, _ = oracle.bh_repulsion(x, mass, theta=1.2)
+    exact = sum(mass[0] * mass[j] * (x[0] - x[j]) / ((x[0] - x[j]) @ (x[0] - x[j])) for j in (1, 2))
+    assert np.allclose(F[0], exact, rtol=1e-14, atol=0)
+
+
+def test_barnes_hut_borderline_flags():
+    """A body is flagged exactly when one of its opening tests lies within the stated
+    single-precision margin of theta: with theta set to a cell's own size / distance
+    ratio the body that tests it is flagged; far from every ratio none is."""
+    x = np.array([[0.0, 0.0], [8.0, 0.0], [8.0, 0.25], [-7.0, 3.0]])
+    mass = np.array([1.0, 2.0, 3.0, 1.0])
+    order, ni, nd, ch = oracle.bh_tree(x, mass)
+    pair = [k for k in range(ni.shape[0]) if sorted(order[ni[k, 0]:ni[k, 1]].tolist()) == [1, 2]][0]
+    size, M, cx, cy = nd[pair]
+    ratio = size / math.hypot(cx, cy)
+    _, border = oracle.bh_repulsion(x, mass, theta=ratio)
+    assert border[0]
+    _, border = oracle.bh_repulsion(x, mass, theta=ratio * 1.01)
+    assert not border[0]
+    F, border = oracle.bh_repulsion(x, mass, theta=1e-3)  # every cell opened: no test is near theta
+    assert not border.any()
+    assert np.allclose(F, oracle.fa2_forces(x, np.zeros((0, 2), np.int32), mass, kg=0.0, exact=True), rtol=1e-12)
 
 
 def test_barnes_hut_opening_criterion_by_hand():
@@ -586,7 +642,7 @@ def test_barnes_hut_opening_criterion_by_hand():
     x = np.array([[0.0, 0.0], [8.0, 0.0], [8.0, 0.25]])
     mass = np.array([1.0, 2.0, 3.0])
     se = np.zeros((0, 2), np.int32)
-    order, ni, nd = oracle.bh_tree(x, mass)
+    order, ni, nd, _ = oracle.bh_tree(x, mass)
     pair = [k for k in range(ni.shape[0]) if sorted(order[ni[k, 0]:ni[k, 1]].tolist()) == [1, 2]]
     assert len(pair) == 1
     size, M, cx, cy = nd[pair[0]]
