@@ -102,8 +102,8 @@ def main():
         if record:
             ev["a"].record(stream)
         labels, degree, _ = bgv.community(edges, n, wl["threshold"], wl["passes"], wl["growth"], wl["chunk"],
-                                          ws=ws_cd)
-        sg = bgv.supergraph(edges, labels, degree, wl["rows"], wl["cols"], c1, c2, ws=ws_sg)
+                                          ws=ws_cd, check=False)
+        sg = bgv.supergraph(edges, labels, degree, wl["rows"], wl["cols"], c1, c2, ws=ws_sg, check=False)
         if record:
             ev["b"].record(stream)
         pos = pos0[: sg["K"]].clone()
@@ -293,7 +293,7 @@ def batched_form(torch, bgv, graphgen):
     t = time.perf_counter()
     K_p = []
     for g, (n, _, _) in enumerate(graphs):
-        o = bgv.pipeline(edges_g[g], n, wl, c1, c2, pos0_d[g])
+        o = bgv.pipeline(edges_g[g], n, wl, c1, c2, pos0_d[g], check=False)
         K_p.append(o["sg"]["K"])
     torch.cuda.synchronize()
     seq_ms = 1000.0 * (time.perf_counter() - t)
@@ -320,7 +320,7 @@ def small_graph_form(torch, bgv, graphgen, repeats=5):
     edges_b, noff, eoff, noff_h, _ = bgv.pack_graphs([(n, e)], dev)
 
     def plain():
-        return bgv.pipeline(ed, n, wl, c1, c2, pos0)
+        return bgv.pipeline(ed, n, wl, c1, c2, pos0, check=False)
 
     def batched():
         return bgv.batched(edges_b, noff, eoff, n, wl, c1, c2, pos0.clone(), wg_threads=1024)
@@ -368,8 +368,9 @@ def largest_graph_form(torch, bgv, graphgen, cpu_fa2_iters=10):
     ws_sg = bgv.api.supergraph_workspace(ed, n, wl)
 
     def run():
-        labels, degree, _ = bgv.community(ed, n, wl["threshold"], wl["passes"], wl["growth"], wl["chunk"], ws=ws_cd)
-        sg = bgv.supergraph(ed, labels, degree, wl["rows"], wl["cols"], c1, c2, ws=ws_sg)
+        labels, degree, _ = bgv.community(ed, n, wl["threshold"], wl["passes"], wl["growth"], wl["chunk"], ws=ws_cd,
+                                          check=False)
+        sg = bgv.supergraph(ed, labels, degree, wl["rows"], wl["cols"], c1, c2, ws=ws_sg, check=False)
         pos = pos_d[: sg["K"]].clone()
         bgv.fa2_layout(sg["superedges"], pos, wl["fa2_iters"], exact=False, theta=wl["theta"], kr=wl["kr"],
                        kg=wl["kg"], tau=wl["tau"], ks=wl["ks"], ksmax=wl["ksmax"])
@@ -426,7 +427,7 @@ def sequential_rule_form(torch, bgv, edges_np, n, wl, with_cpu):
     oracle's sequential loop on one host thread as its CPU baseline."""
     dev = torch.device("cuda:0")
     ed = torch.from_numpy(np.ascontiguousarray(edges_np)).to(dev)
-    run = lambda: bgv.community(ed, n, wl["threshold"], wl["passes"], wl["growth"], 1)
+    run = lambda: bgv.community(ed, n, wl["threshold"], wl["passes"], wl["growth"], 1, check=False)
     run()
     torch.cuda.synchronize()
     ms = _timed(torch, run, repeats=3)
@@ -468,10 +469,10 @@ def sweeps_form(torch, bgv, graphgen, edges_np, n, wl):
         w[key] = value
         c1 = graphgen.hash_coeffs(w["rows"], w["sketch_seed"])
         c2 = graphgen.hash_coeffs(w["rows"], w["sketch_seed"] ^ 0x9E3779B97F4A7C15)
-        bgv.pipeline(ed, n, w, c1, c2, pos0)  # warm-up (workspaces, code paths)
+        bgv.pipeline(ed, n, w, c1, c2, pos0, check=False)  # warm-up (workspaces, code paths)
         torch.cuda.synchronize()
         res = {}
-        ms = _timed(torch, lambda: res.update(bgv.pipeline(ed, n, w, c1, c2, pos0)))
+        ms = _timed(torch, lambda: res.update(bgv.pipeline(ed, n, w, c1, c2, pos0, check=False)))
         row = {"param": key, "value": value, "ms": ms, "supernodes": int(res["sg"]["K"]),
                "superedges": int(res["sg"]["E"])}
         # what the sketch parameters change: the estimates' relative overestimate of the

@@ -21,6 +21,13 @@
  *     results are identical run to run (fixed reduction orders, no FP atomics).
  *   - Edge lists are int32 (m, 2) row-major: edge i is (edges[2i], edges[2i+1]), and
  *     i is its position in the stream.  Node ids must lie in [0, n).
+ *   - Ids are not checked on the device by default: an id outside its range makes the
+ *     kernels read and write outside the caller's arrays.  With the environment
+ *     variable BGV_CHECK=1, every entry point that takes ids first scans them with a
+ *     read-only kernel (edges, and labels for bgv_supergraph; superedge ids against K;
+ *     the batched form's offsets, local ids and order), synchronises its stream, and
+ *     returns BGV_E_RANGE before any kernel indexes by them.  bgv_validate_edges runs
+ *     the same scan on request.
  */
 #ifndef BGV_H
 #define BGV_H
@@ -37,6 +44,7 @@ typedef struct ihipStream_t *bgv_stream_t; /* a hipStream_t; NULL = the null str
 typedef int32_t bgv_status;
 #define BGV_OK 0
 #define BGV_E_INVALID (-1)     /* an argument is out of its documented range      */
+#define BGV_E_RANGE (-2)       /* an id lies outside its range (device check)     */
 #define BGV_E_WORKSPACE (-3)   /* ws is NULL, misaligned or smaller than required */
 #define BGV_E_HIP (-4)         /* a HIP call failed; see bgv_last_error()          */
 
@@ -114,7 +122,7 @@ size_t bgv_community_workspace(int32_t n, int64_t m, const bgv_cd_params *p);
  * if it never joined), degree int32[n] (true degree: occurrences as an endpoint of a
  * non-loop edge), volume int64[n] or NULL (volume[c] = sum of degree over nodes with
  * label c; the exact weight the sketch estimates).  Ids outside [0, n) are undefined
- * behaviour (not checked on the device).
+ * behaviour unless BGV_CHECK=1 (then BGV_E_RANGE, see the conventions above).
  */
 bgv_status bgv_community(int32_t n, int64_t m, const int32_t *edges, const bgv_cd_params *p,
                          int32_t *labels, int32_t *degree, int64_t *volume,
@@ -197,11 +205,13 @@ bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges, const int3
  * s = min(tau * sum m_i traction_i / sum m_i swing_i, 1.5 s) when the swing sum is
  * positive; s_i = ks s / (1 + s sqrt(swing_i)), at most ksmax / |F_i|;
  * x_i += s_i F_i; F' = F.
- * Barnes-Hut (exact = 0): bodies are quantised in FP32 to a 2^16 x 2^16 grid over
- * their bounding square and Morton-sorted; the tree splits a code range at its first
- * differing bit; a range of equal codes is one leaf; a node with a P-bit common
- * prefix has cell size s0 / 2^floor(P/2).  A node not containing i is replaced by
- * its centre of mass when size^2 < theta^2 * dist^2; leaves are summed directly.
+ * Barnes-Hut (exact = 0), Section 3.1's hierarchical partition: bodies are quantised
+ * in FP32 to a 2^16 x 2^16 grid over their bounding square (side s0 = the larger
+ * extent, 1 if zero); the tree is the compressed quadtree of the grid points: each
+ * node is the smallest cell (side s0 / 2^depth) that holds its bodies, whose bodies
+ * occupy at least two of its quadrants; bodies on one grid point form one leaf.  A
+ * node not containing i is replaced by its centre of mass when
+ * size^2 < theta^2 * dist^2, else opened; leaves are summed body by body.
  */
 typedef struct {
     int32_t iters; /* >= 0                                                        */
@@ -307,6 +317,39 @@ bgv_status bgv_batched(int32_t G, int64_t n_total, int64_t m_total, const int64_
 size_t bgv_draw_workspace(int32_t K);
 bgv_status bgv_draw_supernodes(int32_t K, const uint32_t *super_size, int32_t *group, float *radius,
                                void *ws, size_t ws_bytes, bgv_stream_t stream);
+
+/* ---------------------------------------------------------------------------- */
+/* Checks and diagnostics                                                        */
+/* ---------------------------------------------------------------------------- */
+/*
+ * The id range check of the conventions above, on request: scans the m edges (dev
+ * int32 (m,2)) for an id outside [0, n), with flag (dev int32[1], caller-owned) as
+ * its device result (1 if any, else 0).  Synchronises `stream`; returns BGV_E_RANGE
+ * if an id is out of range, BGV_OK if none, BGV_E_INVALID for n < 1, m < 0 or
+ * m >= 2^31 or a null pointer.  Reads the edges only.
+ */
+bgv_status bgv_validate_edges(int32_t n, int64_t m, const int32_t *edges, int32_t *flag, bgv_stream_t stream);
+
+/*
+ * The Barnes-Hut tree that one ForceAtlas2 iteration builds for positions pos
+ * (dev float (K,2)) and masses mass (dev float[K]), copied out for inspection.  The
+ * device form is the binary radix tree of the sorted codes, which refines the
+ * compressed quadtree above: its internal node j (0 <= j < K-1) covers sorted bodies
+ * [first, last]; a node whose codes share a 2d-bit prefix (and differ in the next bit)
+ * is the quadtree node of depth d; a node with a (2d+1)-bit prefix is one too unless
+ * its parent has the 2d-bit prefix, in which case it is half of the parent's cell and
+ * is always opened.  Outputs (dev): codes uint32[K] (Morton codes in sorted order: x
+ * bits at even positions, ties by body index), body float (K,4) (x, y, mass, body
+ * index as int32 bits, sorted), s0 float[1] (side of the root square), and for K > 1
+ * nodeA float (K-1,4) (centre of mass x, y, mass, size^2; size^2 < 0 for a node whose
+ * codes are all equal, a leaf summed body by body; +inf for a half cell) and nodeB
+ * int32 (K-1,4) (left, right, first, last; a child c < 0 is the single body at sorted
+ * position ~c).  Workspace from bgv_bh_tree_workspace(K).  K >= 1; asynchronous.
+ */
+size_t bgv_bh_tree_workspace(int32_t K);
+bgv_status bgv_bh_tree(int32_t K, const float *pos, const float *mass, uint32_t *codes, float *body,
+                       float *nodeA, int32_t *nodeB, float *s0, void *ws, size_t ws_bytes,
+                       bgv_stream_t stream);
 
 #ifdef __cplusplus
 }

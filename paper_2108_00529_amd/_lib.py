@@ -72,13 +72,20 @@ bgv_batched = _sig("bgv_batched", i32, [i32, i64, i64, P, P, P, P, C.POINTER(CdP
 bgv_draw_workspace = _sig("bgv_draw_workspace", SZ, [i32])
 bgv_draw_supernodes = _sig("bgv_draw_supernodes", i32, [i32, P, P, P, P, SZ, P])
 
+bgv_validate_edges = _sig("bgv_validate_edges", i32, [i32, i64, P, P, P])
+bgv_bh_tree_workspace = _sig("bgv_bh_tree_workspace", SZ, [i32])
+bgv_bh_tree = _sig("bgv_bh_tree", i32, [i32, P, P, P, P, P, P, P, P, SZ, P])
+
 EXPORTED = ["bgv_status_string", "bgv_last_error", "bgv_community_workspace", "bgv_community",
             "bgv_community_passes",
             "bgv_supergraph_workspace", "bgv_supergraph", "bgv_fa2_workspace", "bgv_fa2_layout",
             "bgv_fa2_energy_workspace", "bgv_fa2_energy", "bgv_fa2_grad",
             "bgv_profile_enable", "bgv_profile_filter", "bgv_profile_sample", "bgv_profile_reset", "bgv_profile_count", "bgv_profile_get",
             "bgv_profile_counter", "bgv_batched_workspace", "bgv_batched", "bgv_draw_workspace",
-            "bgv_draw_supernodes"]
+            "bgv_draw_supernodes", "bgv_validate_edges", "bgv_bh_tree_workspace", "bgv_bh_tree"]
+
+
+BGV_E_RANGE = -2
 
 
 def check(status: int, what: str) -> None:

@@ -34,31 +34,59 @@ def _need(t, dtype, name, shape=None):
         raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
 
 
+class _range_check:
+    """Sets BGV_CHECK=1 (the library's opt-in device id checks) for one call."""
+
+    def __init__(self, on: bool):
+        self.on = on
+
+    def __enter__(self):
+        import os
+        if self.on:
+            self.prev = os.environ.get("BGV_CHECK")
+            os.environ["BGV_CHECK"] = "1"
+
+    def __exit__(self, *exc):
+        import os
+        if self.on:
+            if self.prev is None:
+                os.environ.pop("BGV_CHECK", None)
+            else:
+                os.environ["BGV_CHECK"] = self.prev
+
+
 def _workspace(nbytes: int, device) -> torch.Tensor:
     ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
     assert ws.data_ptr() % 256 == 0
     return ws
 
 
-def validate_edges(edges: torch.Tensor, n: int) -> None:
-    """Host-side guard used before launches on untrusted input: ids in [0, n)."""
-    if edges.numel():
-        lo, hi = int(edges.min()), int(edges.max())
-        if lo < 0 or hi >= n:
-            raise ValueError(f"edge ids must lie in [0, {n}), got [{lo}, {hi}]")
+def validate_edges(edges: torch.Tensor, n: int, stream=None) -> None:
+    """Device scan of the edge ids (bgv_validate_edges): raises ValueError if an id lies
+    outside [0, n).  Synchronises the stream."""
+    m = edges.shape[0] if edges.dim() == 2 else 0
+    _need(edges, torch.int32, "edges", (m, 2))
+    flag = torch.empty(1, dtype=torch.int32, device=edges.device)
+    st = L.bgv_validate_edges(int(n), int(m), _ptr(edges), _ptr(flag), _stream(stream))
+    if st == L.BGV_E_RANGE:
+        raise ValueError(f"edge ids must lie in [0, {n})")
+    L.check(st, "bgv_validate_edges")
 
 
 # ------------------------------------------------------------------- community --
 def community(edges: torch.Tensor, n: int, threshold: int, passes: int = 1, growth: int = 2,
               chunk: int = 1, volume: bool = False, ws: torch.Tensor | None = None, stream=None,
-              method: int = 0, tie: int = 0, rule: int = 0):
+              method: int = 0, tie: int = 0, rule: int = 0, check: bool = True):
     """Streaming community detection.  Returns (labels int32[n], degree int32[n],
     volume int64[n] or None).  method: 0 automatic, 1 chunk by chunk, 2 back-pointer
     resolution (the same integers).  tie: 1 = on equal counters the edge's first
     endpoint joins the second's community (0: nothing happens, as in Algorithm 3).
-    rule: 0 = the paper's degree rule, 1 = SCoDA's community-volume rule."""
+    rule: 0 = the paper's degree rule, 1 = SCoDA's community-volume rule.  check: scan
+    the edge ids on the device first (validate_edges; synchronises the stream)."""
     m = edges.shape[0] if edges.dim() == 2 else 0
     _need(edges, torch.int32, "edges", (m, 2))
+    if check:
+        validate_edges(edges, n, stream)
     p = L.CdParams(int(threshold), int(passes), int(growth), int(method), int(chunk), int(tie), int(rule))
     need = L.bgv_community_workspace(int(n), m, C.byref(p))
     if need == 0:
@@ -77,11 +105,13 @@ def community(edges: torch.Tensor, n: int, threshold: int, passes: int = 1, grow
 
 def community_passes(edges: torch.Tensor, n: int, threshold: int, passes: int = 1, growth: int = 2,
                      chunk: int = 1, volume: bool = False, ws: torch.Tensor | None = None, stream=None,
-                     method: int = 0, tie: int = 0, rule: int = 0):
+                     method: int = 0, tie: int = 0, rule: int = 0, check: bool = True):
     """community() that also keeps each pass's labels (the hierarchy of community sets).
     Returns (labels, degree, volume or None, pass_labels int32[passes, n])."""
     m = edges.shape[0] if edges.dim() == 2 else 0
     _need(edges, torch.int32, "edges", (m, 2))
+    if check:
+        validate_edges(edges, n, stream)
     p = L.CdParams(int(threshold), int(passes), int(growth), int(method), int(chunk), int(tie), int(rule))
     need = L.bgv_community_workspace(int(n), m, C.byref(p))
     if need == 0:
@@ -118,13 +148,15 @@ def supergraph_workspace(edges: torch.Tensor, n: int, wl: dict) -> torch.Tensor:
 # ------------------------------------------------------------------ supergraph --
 def supergraph(edges: torch.Tensor, labels: torch.Tensor, degree: torch.Tensor, rows: int, cols: int,
                coef1: np.ndarray, coef2: np.ndarray, ws: torch.Tensor | None = None, stream=None,
-               exact_counts: bool = False):
+               exact_counts: bool = False, check: bool = True):
     """Count-min-sketch supergraph.  Synchronises the stream.  Returns a dict with K,
     super_label, super_size, node_super, superedges (E,2), se_weight, se_count (exact
-    multiplicities, if asked for), M1, M2."""
+    multiplicities, if asked for), M1, M2.  check: scan the edge ids on the device first."""
     n = labels.shape[0]
     m = edges.shape[0]
     _need(edges, torch.int32, "edges", (m, 2))
+    if check:
+        validate_edges(edges, n, stream)
     _need(labels, torch.int32, "labels", (n,))
     _need(degree, torch.int32, "degree", (n,))
     c1 = np.ascontiguousarray(coef1, dtype=np.uint64).reshape(rows, 3)
@@ -235,6 +267,31 @@ def fa2_grad(superedges: torch.Tensor, pos: torch.Tensor, kr: float = 1.0, kg: f
     return g
 
 
+def bh_tree(pos: torch.Tensor, mass: torch.Tensor, ws=None, stream=None):
+    """The Barnes-Hut tree one layout iteration builds (bgv_bh_tree), for inspection:
+    dict of device tensors codes (K,) int32 (uint32 bits), body (K,4) float32 (x, y,
+    mass, index bits), s0 (1,), nodeA (K-1,4) float32, nodeB (K-1,4) int32."""
+    K = pos.shape[0]
+    _need(pos, torch.float32, "pos", (K, 2))
+    _need(mass, torch.float32, "mass", (K,))
+    need = L.bgv_bh_tree_workspace(int(K))
+    if need == 0:
+        raise L.BgvError(f"invalid tree arguments (K={K})")
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, pos.device)
+    dev = pos.device
+    out = dict(codes=torch.empty(K, dtype=torch.int32, device=dev),
+               body=torch.empty((K, 4), dtype=torch.float32, device=dev),
+               s0=torch.empty(1, dtype=torch.float32, device=dev),
+               nodeA=torch.empty((max(K - 1, 1), 4), dtype=torch.float32, device=dev),
+               nodeB=torch.empty((max(K - 1, 1), 4), dtype=torch.int32, device=dev))
+    L.check(L.bgv_bh_tree(int(K), _ptr(pos), _ptr(mass), _ptr(out["codes"]), _ptr(out["body"]), _ptr(out["nodeA"]),
+                          _ptr(out["nodeB"]), _ptr(out["s0"]), _ptr(ws), ws.numel(), _stream(stream)), "bgv_bh_tree")
+    out["nodeA"] = out["nodeA"][: K - 1]
+    out["nodeB"] = out["nodeB"][: K - 1]
+    return out
+
+
 def draw_supernodes(super_size: torch.Tensor, ws=None, stream=None):
     """Drawing attributes of the supernodes (Section 4.1 radius, Section 4.3 colour
     groups): returns (group int32[K] in 0..10, radius float32[K] = sqrt(size))."""
@@ -275,14 +332,15 @@ class FA2Energy(torch.autograd.Function):
 
 # ------------------------------------------------------------------ whole path --
 def pipeline(edges: torch.Tensor, n: int, wl: dict, coef1: np.ndarray, coef2: np.ndarray, pos0: torch.Tensor,
-             volume: bool = False, stream=None):
+             volume: bool = False, stream=None, check: bool = True):
     """Community passes + supergraph + ForceAtlas2 layout of the supergraph for one
     workload description ``wl`` (threshold, passes, growth, chunk, rows, cols,
-    fa2_iters, exact, theta, kr, kg, tau, ks, ksmax).  pos0 (>= K rows) seeds the layout."""
+    fa2_iters, exact, theta, kr, kg, tau, ks, ksmax).  pos0 (>= K rows) seeds the layout.
+    check: scan the edge ids on the device first."""
     labels, degree, vol = community(edges, n, wl["threshold"], wl["passes"], wl["growth"], wl["chunk"],
                                     volume=volume, stream=stream, tie=int(wl.get("tie", 0)),
-                                    rule=int(wl.get("rule", 0)))
-    sg = supergraph(edges, labels, degree, wl["rows"], wl["cols"], coef1, coef2, stream=stream)
+                                    rule=int(wl.get("rule", 0)), check=check)
+    sg = supergraph(edges, labels, degree, wl["rows"], wl["cols"], coef1, coef2, stream=stream, check=False)
     pos = pos0[: sg["K"]].clone()
     pos, fprev, speed = fa2_layout(sg["superedges"], pos, wl["fa2_iters"], wl["exact"], wl["theta"], wl["kr"],
                                    wl["kg"], wl["tau"], wl["ks"], wl["ksmax"], stream=stream)
@@ -307,11 +365,13 @@ def pack_graphs(graphs, device):
 def batched(edges: torch.Tensor, node_off: torch.Tensor, edge_off: torch.Tensor, n_total: int, wl: dict,
             coef1: np.ndarray, coef2: np.ndarray, pos: torch.Tensor, order: torch.Tensor | None = None,
             fprev: torch.Tensor | None = None, speed: torch.Tensor | None = None, wg_threads: int = 0,
-            big_k: int = 0, ws: torch.Tensor | None = None, stream=None):
+            big_k: int = 0, ws: torch.Tensor | None = None, stream=None, check: bool = False):
     """The whole path for G graphs in one persistent launch (include/bgv.h,
     bgv_batched); with big_k > 0, supergraphs larger than big_k nodes are laid out by
     multi-workgroup kernels after it.  pos (n_total, 2) float32 holds each graph's
-    initial positions and is updated in place.  Returns a dict of device tensors."""
+    initial positions and is updated in place.  Returns a dict of device tensors.
+    check: run the library's device id and offset checks first (BGV_CHECK=1 for this
+    call; synchronises the stream, raises ValueError on BGV_E_RANGE)."""
     G = node_off.shape[0] - 1
     m_total = edges.shape[0]
     dev = edges.device
@@ -348,12 +408,16 @@ def batched(edges: torch.Tensor, node_off: torch.Tensor, edge_off: torch.Tensor,
                super_size=torch.empty(nn, dtype=torch.int32, device=dev),
                superedges=torch.empty((mm, 2), dtype=torch.int32, device=dev),
                se_weight=torch.empty(mm, dtype=torch.int32, device=dev))
-    L.check(L.bgv_batched(int(G), int(n_total), int(m_total), _ptr(node_off), _ptr(edge_off), _ptr(order),
-                          _ptr(edges), C.byref(cd), C.byref(sp), C.byref(fa), int(wg_threads), int(big_k),
-                          _ptr(out["labels"]),
-                          _ptr(out["degree"]), _ptr(out["K"]), _ptr(out["E"]), _ptr(out["super_label"]),
-                          _ptr(out["super_size"]), _ptr(out["superedges"]), _ptr(out["se_weight"]), _ptr(pos),
-                          _ptr(fprev), _ptr(speed), _ptr(ws), ws.numel(), _stream(stream)), "bgv_batched")
+    with _range_check(check):
+        st = L.bgv_batched(int(G), int(n_total), int(m_total), _ptr(node_off), _ptr(edge_off), _ptr(order),
+                           _ptr(edges), C.byref(cd), C.byref(sp), C.byref(fa), int(wg_threads), int(big_k),
+                           _ptr(out["labels"]),
+                           _ptr(out["degree"]), _ptr(out["K"]), _ptr(out["E"]), _ptr(out["super_label"]),
+                           _ptr(out["super_size"]), _ptr(out["superedges"]), _ptr(out["se_weight"]), _ptr(pos),
+                           _ptr(fprev), _ptr(speed), _ptr(ws), ws.numel(), _stream(stream))
+    if st == L.BGV_E_RANGE:
+        raise ValueError("batched graphs: offsets inconsistent or local ids out of range")
+    L.check(st, "bgv_batched")
     out.update(pos=pos, fprev=fprev, speed=speed)
     return out
 

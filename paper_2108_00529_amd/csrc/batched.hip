@@ -727,6 +727,10 @@ extern "C" bgv_status bgv_batched(int32_t G, int64_t n_total, int64_t m_total, c
     }
     BGV_TRY(check_ws(ws, ws_bytes, bgv_batched_workspace(G, n_total, m_total)));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (range_check_on()) {  // K[0] holds the flag; it is written below
+        BGV_TRY(check_batched_ids(G, n_total, m_total, node_off, edge_off, edges, K, s));
+        if (order) BGV_TRY(check_id_list(G, order, G, K, s));
+    }
     Carver c(ws);
     BtWs w;
     bt_layout(c, G, n_total, m_total, &w);

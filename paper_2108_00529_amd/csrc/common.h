@@ -111,6 +111,16 @@ inline unsigned grid_for(int64_t items, int per_block, unsigned cap = 1u << 20) 
     return static_cast<unsigned>(g);
 }
 
+// ------------------------------------------------------------- id range checks ----
+// Opt-in device checks (BGV_CHECK=1 in the environment): a read-only scan of the ids
+// raises a device flag (one int32 the caller's call is about to overwrite), read back
+// on the host; BGV_E_RANGE when set.  They synchronise the stream.
+bool range_check_on();
+bgv_status check_edge_ids(int32_t n, int64_t m, const int32_t *edges, int32_t *flag, hipStream_t s);
+bgv_status check_id_list(int64_t count, const int32_t *id, int32_t bound, int32_t *flag, hipStream_t s);
+bgv_status check_batched_ids(int32_t G, int64_t n_total, int64_t m_total, const int64_t *node_off,
+                             const int64_t *edge_off, const int32_t *edges, int32_t *flag, hipStream_t s);
+
 // ---------------------------------------------------------------- primitives ----
 // Device-wide fill (a kernel, so it is safe inside captured graphs).
 template <class T>

@@ -640,6 +640,7 @@ static bgv_status cd_run(int32_t n, int64_t m, const int32_t *edges, const bgv_c
     }
     BGV_TRY(check_ws(ws, ws_bytes, bgv_community_workspace(n, m, p)));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (range_check_on()) BGV_TRY(check_edge_ids(n, m, edges, labels, s));  // labels[0]: overwritten below
     if (volume) BGV_TRY(fill<int64_t>(volume, 0, n, s));
     if (cd_method(n, m, p) == 2) return sq_run(n, m, edges, p, labels, degree, volume, pass_labels, ws, s);
     if (p->rule == 1) return vr_run(n, m, edges, p, labels, degree, volume, pass_labels, ws, s);

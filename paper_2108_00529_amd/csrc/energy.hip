@@ -255,6 +255,7 @@ extern "C" bgv_status bgv_fa2_energy(int32_t K, int64_t E, const int32_t *edges,
     }
     BGV_TRY(check_ws(ws, ws_bytes, bgv_fa2_energy_workspace(K, E)));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (range_check_on()) BGV_TRY(check_edge_ids(K, E, edges, reinterpret_cast<int32_t *>(energy), s));
     Carver c(ws);
     EnWs w;
     en_layout(c, K, E, &w);
@@ -282,6 +283,7 @@ extern "C" bgv_status bgv_fa2_grad(int32_t K, int64_t E, const int32_t *edges, c
     }
     BGV_TRY(check_ws(ws, ws_bytes, bgv_fa2_energy_workspace(K, E)));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (range_check_on()) BGV_TRY(check_edge_ids(K, E, edges, reinterpret_cast<int32_t *>(grad), s));
     Carver c(ws);
     EnWs w;
     en_layout(c, K, E, &w);

@@ -545,6 +545,17 @@ __device__ __forceinline__ int delta(const uint32_t *__restrict__ code, int32_t 
 // Internal node i of the binary radix tree over the sorted codes (Karras' parallel
 // construction).  Children: >= 0 internal node, < 0 leaf ~child.  nodeA = (centre of
 // mass, mass, size^2), size^2 < 0 for a node whose codes are all equal (a leaf cell).
+//
+// The radix tree refines the compressed quadtree of Section 3.1's hierarchical
+// partition: a node whose codes share a 2d-bit prefix and differ in the next bit is
+// the quadtree cell of depth d (side s0 / 2^d) whose bodies occupy quadrants in both
+// of its y halves; a node with a (2d+1)-bit prefix holds bodies in two quadrants of one
+// y half.  When its parent has the 2d-bit prefix, that node is only half of the
+// parent's cell, not a quadtree cell: it gets size^2 = +inf, so the traversal always
+// opens it and reaches the quadrant nodes below it.  Every other node is a quadtree
+// cell with its own side, so the opening decisions are those of the quadtree.  The
+// parent of the node over [first, last] has the longer of the prefixes shared across
+// the range's two ends (Karras' tree: the parent extends the range on that side).
 __device__ __forceinline__ void bh_build_nodes(int32_t K, const uint32_t *__restrict__ code,
                                                const double *__restrict__ PM, const double *__restrict__ PX,
                                                const double *__restrict__ PY, const float *__restrict__ s0p,
@@ -577,6 +588,9 @@ __device__ __forceinline__ void bh_build_nodes(int32_t K, const uint32_t *__rest
         float size2;
         if (dnode >= 32) {
             size2 = -1.0f;
+        } else if ((dnode & 1) &&
+                   max(delta(code, K, first - 1, first), delta(code, K, last, last + 1)) == dnode - 1) {
+            size2 = __builtin_inff();  // half of the parent's cell: always opened
         } else {
             const int lev = min(dnode >> 1, 16);
             const float sz = s0 / (float)(1u << lev);
@@ -646,8 +660,10 @@ constexpr int kBhLanes = 8;  // lanes per body (16 and 32 measured slower on the
 // indices (>= 0) or bodies (~j).  Children are pushed in reverse lane order, so the
 // deepest entries stay on top and the stack is sorted by depth; a step that pops an
 // entry of depth d then pops every deeper entry, so at most 2G entries of any one
-// depth are ever on the stack, and 2G per level of the tree bounds it.  The order of
-// the additions depends only on G and the tree: results are identical run to run.
+// depth are ever on the stack, and 2G per level of the tree bounds it: a node's prefix
+// is longer than its parent's, so the tree has at most 34 levels (root, 32 prefix
+// lengths, bodies) and the stack never exceeds kDepth.  The order of the additions
+// depends only on G and the tree: results are identical run to run.
 constexpr int kBhTreeLevels = 34;  // 32-bit Morton codes: root, 32 prefix lengths, equal-code cells
 
 template <int G>
@@ -657,7 +673,7 @@ __global__ void __launch_bounds__(kBhThreads) k_bh_force(int32_t K, const float4
                                                           const float2 *__restrict__ att,
                                                           const uint32_t *__restrict__ item_of, float kr, float kg,
                                                           const float2 *__restrict__ fprev, float2 *__restrict__ F,
-                                                          double2 *__restrict__ part, int *__restrict__ overflow,
+                                                          double2 *__restrict__ part,
                                                           uint32_t *__restrict__ icount) {
     static_assert(G >= 2 && G <= kWave && (G & (G - 1)) == 0, "lanes per body: power of two in [2, 64]");
     constexpr int kGroups = kBhThreads / G;
@@ -726,16 +742,11 @@ __global__ void __launch_bounds__(kBhThreads) k_bh_force(int32_t K, const float4
         }
         const int total = __shfl(incl, 0, G);
         if (np) {
-            const int at = size + incl - np;  // this lane's two slots: at, at + 1
-            if (at + 1 < kDepth) {
-                st_g[at] = c_right;
-                st_g[at + 1] = c_left;  // left on top: popped first
-            } else {
-                *overflow = 1;
-            }
+            const int at = size + incl - np;  // this lane's two slots: at, at + 1 (< kDepth, see above)
+            st_g[at] = c_right;
+            st_g[at + 1] = c_left;  // left on top: popped first
         }
         size += total;
-        if (size > kDepth) size = kDepth;
     }
 #pragma unroll
     for (int o = G / 2; o > 0; o >>= 1) {
@@ -798,7 +809,6 @@ struct BhWs {
     double *part3, *PM, *PX, *PY;
     float4 *nodeA;
     int4 *nodeB;
-    int *overflow;
     uint32_t *icount;  // interactions per force workgroup, summed over the call's iterations
     void *sort_scratch;
 };
@@ -809,6 +819,7 @@ struct FaWs {
     float2 *seg;  // exact repulsion: per-segment sums [segments][K] when K spans several segments
     double2 *part;
     float *speed;  // [2] ping-pong
+    int32_t *flag;  // id range check
     BhWs bh;
 };
 
@@ -819,6 +830,7 @@ static size_t fa_layout(Carver &c, int32_t K, int64_t E, const bgv_fa2_params *p
     w->A = c.take<float2>((size_t)w->csr.items_bound);
     w->part = c.take<double2>((size_t)(nb > bh_force_blocks(K) ? nb : bh_force_blocks(K)));
     w->speed = c.take<float>(2);
+    w->flag = c.take<int32_t>(1);
     w->seg = nullptr;
     if (p->exact && fa2_rep_segments(K) > 1) w->seg = c.take<float2>((size_t)fa2_rep_segments(K) * (size_t)K);
     if (!p->exact) {
@@ -837,7 +849,6 @@ static size_t fa_layout(Carver &c, int32_t K, int64_t E, const bgv_fa2_params *p
         b.PY = c.take<double>((size_t)K + 1);
         b.nodeA = c.take<float4>((size_t)K);
         b.nodeB = c.take<int4>((size_t)K);
-        b.overflow = c.take<int>(1);
         b.icount = c.take<uint32_t>((size_t)bh_force_blocks(K));
         b.sort_scratch = c.take<char>(radix_workspace(K));
     }
@@ -871,9 +882,9 @@ static bgv_status build_attract(int32_t K, const BhWs &b, unsigned att_blocks, s
     return launch_build_attract<uint16_t, NT, kLds>(K, b, build_blocks, att_blocks, lds, pos, csr, A, s);
 }
 
-static bgv_status bh_forces(int32_t K, const float2 *pos, const float *mass, const CsrWs &csr, float theta, float kr,
-                            float kg, const float2 *fprev, FaWs &w, hipStream_t s) {
-    BhWs &b = w.bh;
+// Morton codes of the positions, sorted, the bodies gathered in Morton order and the
+// FP64 prefix sums of their mass moments: everything the node build reads.
+static bgv_status bh_sorted_bodies(int32_t K, const float2 *pos, const float *mass, BhWs &b, hipStream_t s) {
     const unsigned nb = (unsigned)((K + kFaThreads - 1) / kFaThreads);
     // b.bbox holds one box per block of positions (written by k_bh_bbox before the first
     // iteration and by k_update after each one)
@@ -904,6 +915,13 @@ static bgv_status bh_forces(int32_t K, const float2 *pos, const float *mass, con
     }
     BGV_LAUNCH(k_bh_gather, dim3(nb), dim3(kFaThreads), 0, s, K, pos, mass, sk, sv, b.body, b.code, b.part3);
     BGV_LAUNCH(k_bh_prefix, dim3(nb), dim3(kFaThreads), 0, s, K, b.body, b.part3, b.PM, b.PX, b.PY);
+    return BGV_OK;
+}
+
+static bgv_status bh_forces(int32_t K, const float2 *pos, const float *mass, const CsrWs &csr, float theta, float kr,
+                            float kg, const float2 *fprev, FaWs &w, hipStream_t s) {
+    BhWs &b = w.bh;
+    BGV_TRY(bh_sorted_bodies(K, pos, mass, b, s));
     // the tree and the attraction (which the force kernel combines), in one launch
     if (K > 1) {
         if (K >= kAttLdsMin && K <= kAttLdsMax) {
@@ -920,7 +938,7 @@ static bgv_status bh_forces(int32_t K, const float2 *pos, const float *mass, con
         BGV_TRY(attraction(K, pos, csr, w.A, s));
     }
     BGV_LAUNCH(k_bh_force<kBhLanes>, dim3(bh_force_blocks(K)), dim3(kBhThreads), 0, s, K, b.body, b.nodeA,
-               b.nodeB, theta * theta, w.A, csr.item_of, kr, kg, fprev, w.F, w.part, b.overflow, b.icount);
+               b.nodeB, theta * theta, w.A, csr.item_of, kr, kg, fprev, w.F, w.part, b.icount);
     return BGV_OK;
 }
 
@@ -952,10 +970,10 @@ extern "C" bgv_status bgv_fa2_layout(int32_t K, int64_t E, const int32_t *edges,
     Carver c(ws);
     FaWs w;
     fa_layout(c, K, E, p, &w);
+    if (range_check_on()) BGV_TRY(check_edge_ids(K, E, edges, w.flag, s));
     const float *m = nullptr;
     BGV_TRY(build_csr(K, E, edges, attr_w, mass, w.csr, s, &m));
     if (!p->exact) {
-        BGV_TRY(fill<int>(w.bh.overflow, 0, 1, s));
         BGV_TRY(fill<uint32_t>(w.bh.icount, 0u, bh_force_blocks(K), s));
     }
 
@@ -979,5 +997,49 @@ extern "C" bgv_status bgv_fa2_layout(int32_t K, int64_t E, const int32_t *edges,
     BGV_LAUNCH(k_copy_f32, dim3(1), dim3(1), 0, s, w.speed + (p->iters & 1), speed);
     if (!p->exact && p->iters > 0 && prof_on())
         BGV_LAUNCH(k_count_total, dim3(1), dim3(kFaThreads), 0, s, w.bh.icount, bh_force_blocks(K));
+    return BGV_OK;
+}
+
+// Diagnostics: the Barnes-Hut tree of one set of positions (the tree an iteration builds).
+extern "C" size_t bgv_bh_tree_workspace(int32_t K) {
+    if (K < 1) return 0;
+    bgv_fa2_params p{};
+    p.exact = 0;
+    p.theta = 1.f;
+    p.tau = 1.f;
+    p.ksmax = 1.f;
+    return bgv_fa2_workspace(K, 0, &p);
+}
+
+extern "C" bgv_status bgv_bh_tree(int32_t K, const float *pos, const float *mass, uint32_t *codes, float *body,
+                                  float *nodeA, int32_t *nodeB, float *s0, void *ws, size_t ws_bytes,
+                                  bgv_stream_t stream) {
+    clear_error();
+    if (K < 1 || !pos || !mass || !codes || !body || !s0 || (K > 1 && (!nodeA || !nodeB))) {
+        set_error("bgv_bh_tree: invalid arguments (K=%d)", K);
+        return BGV_E_INVALID;
+    }
+    BGV_TRY(check_ws(ws, ws_bytes, bgv_bh_tree_workspace(K)));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    bgv_fa2_params p{};
+    p.exact = 0;
+    Carver c(ws);
+    FaWs w;
+    fa_layout(c, K, 0, &p, &w);
+    BhWs &b = w.bh;
+    const float2 *x = reinterpret_cast<const float2 *>(pos);
+    const unsigned nb = (unsigned)((K + kFaThreads - 1) / kFaThreads);
+    BGV_LAUNCH(k_bh_bbox, dim3(nb), dim3(kFaThreads), 0, s, K, x, b.bbox);
+    BGV_TRY(bh_sorted_bodies(K, x, mass, b, s));
+    if (K > 1)
+        BGV_LAUNCH(k_bh_build, dim3(grid_for(K - 1, kFaThreads, 65536)), dim3(kFaThreads), 0, s, K, b.code, b.PM,
+                   b.PX, b.PY, b.s0, b.nodeA, b.nodeB);
+    BGV_CHECK_HIP(hipMemcpyAsync(codes, b.code, sizeof(uint32_t) * (size_t)K, hipMemcpyDeviceToDevice, s));
+    BGV_CHECK_HIP(hipMemcpyAsync(body, b.body, sizeof(float4) * (size_t)K, hipMemcpyDeviceToDevice, s));
+    BGV_CHECK_HIP(hipMemcpyAsync(s0, b.s0, sizeof(float), hipMemcpyDeviceToDevice, s));
+    if (K > 1) {
+        BGV_CHECK_HIP(hipMemcpyAsync(nodeA, b.nodeA, sizeof(float4) * (size_t)(K - 1), hipMemcpyDeviceToDevice, s));
+        BGV_CHECK_HIP(hipMemcpyAsync(nodeB, b.nodeB, sizeof(int4) * (size_t)(K - 1), hipMemcpyDeviceToDevice, s));
+    }
     return BGV_OK;
 }

@@ -409,6 +409,7 @@ extern "C" const char *bgv_status_string(bgv_status s) {
     switch (s) {
         case BGV_OK: return "BGV_OK";
         case BGV_E_INVALID: return "BGV_E_INVALID";
+        case BGV_E_RANGE: return "BGV_E_RANGE";
         case BGV_E_WORKSPACE: return "BGV_E_WORKSPACE";
         case BGV_E_HIP: return "BGV_E_HIP";
         default: return "BGV_E_UNKNOWN";

@@ -598,6 +598,10 @@ extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges,
     }
     BGV_TRY(check_ws(ws, ws_bytes, bgv_supergraph_workspace(n, m, sp)));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (range_check_on()) {  // super_label[0] holds the flag; it is written below
+        BGV_TRY(check_edge_ids(n, m, edges, super_label, s));
+        BGV_TRY(check_id_list(n, labels, n, super_label, s));
+    }
     Carver c(ws);
     SgWs w;
     sg_layout(c, n, m, sp->rows, (int64_t)sp->rows * sp->cols, &w);

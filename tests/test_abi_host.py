@@ -168,3 +168,25 @@ def test_draw_validation():
     assert L.bgv_draw_supernodes(10, one, None, one, None, 0, None) == -1
     assert L.bgv_draw_supernodes(10, one, one, None, None, 0, None) == -1
     assert L.bgv_draw_supernodes(10, one, one, one, None, 0, None) == -3  # no workspace, before any HIP call
+
+
+def test_checks_and_tree_export_validation():
+    """The id check and the tree export reject bad arguments before any HIP call."""
+    one = C.c_void_p(256)
+    assert L.bgv_status_string(-2) == b"BGV_E_RANGE"
+    assert L.bgv_validate_edges(0, 5, one, one, None) == -1
+    assert L.bgv_validate_edges(10, -1, one, one, None) == -1
+    assert L.bgv_validate_edges(10, 2**31, one, one, None) == -1
+    assert L.bgv_validate_edges(10, 5, None, one, None) == -1
+    assert L.bgv_validate_edges(10, 5, one, None, None) == -1
+    assert L.bgv_bh_tree_workspace(0) == 0
+    assert L.bgv_bh_tree_workspace(1000) > L.bgv_bh_tree_workspace(10) > 0
+    need = L.bgv_bh_tree_workspace(100)
+    args = [one] * 7  # pos, mass, codes, body, nodeA, nodeB, s0
+    assert L.bgv_bh_tree(0, *args, one, need, None) == -1
+    for k in range(7):
+        a = list(args)
+        a[k] = None
+        assert L.bgv_bh_tree(100, *a, one, need, None) == -1
+    assert L.bgv_bh_tree(100, *args, one, need - 1, None) == -3
+    assert L.bgv_bh_tree(100, *args, C.c_void_p(257), need, None) == -3
