@@ -534,7 +534,8 @@ __global__ void __launch_bounds__(kFaThreads) k_bh_prefix(int32_t K, const float
 }
 
 // Common-prefix length of sorted positions i and j; index bits break ties between
-// equal codes (values >= 32 mean equal codes); -1 outside [0, K).
+// equal codes (values >= 32 mean equal codes); -1 when j is outside [0, K) (only j is
+// checked: i must be a valid position).
 __device__ __forceinline__ int delta(const uint32_t *__restrict__ code, int32_t K, int32_t i, int32_t j) {
     if (j < 0 || j >= K) return -1;
     const uint32_t a = code[i], b = code[j];
@@ -589,7 +590,7 @@ __device__ __forceinline__ void bh_build_nodes(int32_t K, const uint32_t *__rest
         if (dnode >= 32) {
             size2 = -1.0f;
         } else if ((dnode & 1) &&
-                   max(delta(code, K, first - 1, first), delta(code, K, last, last + 1)) == dnode - 1) {
+                   max(delta(code, K, first, first - 1), delta(code, K, last, last + 1)) == dnode - 1) {
             size2 = __builtin_inff();  // half of the parent's cell: always opened
         } else {
             const int lev = min(dnode >> 1, 16);
