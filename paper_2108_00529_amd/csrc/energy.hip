@@ -4,6 +4,8 @@
 // Pair terms are evaluated in FP32 on LDS-staged 256x256 tiles; per-block partial
 // sums are combined in FP64 in a fixed order.  The gradient splits the j range over
 // several blocks per i tile and sums the splits in order, so no FP atomics are used.
+#include <algorithm>
+
 #include "common.h"
 #include "fa2_internal.h"
 #include "fa2_math.h"
@@ -58,20 +60,25 @@ __device__ __forceinline__ float en_log_term(float2 xi, float4 p) {
     return d2 > 0.f ? p.z * l : 0.f;
 }
 
-__global__ void __launch_bounds__(kEnThreads) k_energy_pairs(int32_t K, int T, const float2 *__restrict__ pos,
+// Block x takes tile pairs x, x + grid, ... (one pair per block up to kEnPairBlocks
+// pairs, i.e. up to about 740k supernodes; a fixed assignment and order either way).
+__global__ void __launch_bounds__(kEnThreads) k_energy_pairs(int32_t K, int T, int64_t ntri,
+                                                              const float2 *__restrict__ pos,
                                                               const float *__restrict__ mass,
                                                               double *__restrict__ part) {
     __shared__ float4 tile[kEnThreads];
+    double acc = 0.0;
+    for (int64_t pb = blockIdx.x; pb < ntri; pb += gridDim.x) {  // uniform over the workgroup
     int I, J;
-    tri_index(blockIdx.x, T, I, J);
+    tri_index(pb, T, I, J);
     const int32_t i = I * kEnThreads + threadIdx.x;
     const int32_t j0 = J * kEnThreads;
+    if (pb != blockIdx.x) __syncthreads();  // the previous pair's reads of the tile are done
     if (j0 + (int)threadIdx.x < K) {
         const float2 p = pos[j0 + threadIdx.x];
         tile[threadIdx.x] = make_float4(p.x, p.y, mass[j0 + threadIdx.x], 0.f);
     }
     __syncthreads();
-    double acc = 0.0;
     if (i < K) {
         const float2 xi = pos[i];
         const int cnt = min(kEnThreads, K - j0);
@@ -91,7 +98,8 @@ __global__ void __launch_bounds__(kEnThreads) k_energy_pairs(int32_t K, int T, c
                 s += j0 + q > i ? v : 0.f;
             }
         }
-        acc = 0.5 * kLn2 * (double)mass[i] * (double)s;
+        acc += 0.5 * kLn2 * (double)mass[i] * (double)s;
+    }
     }
     acc = block_sum(acc);
     if (threadIdx.x == 0) part[blockIdx.x] = acc;
@@ -208,10 +216,14 @@ struct EnWs {
 };
 
 static int en_tiles(int32_t K) { return (K + kEnThreads - 1) / kEnThreads; }
-static int64_t en_tri_blocks(int32_t K) {
+static int64_t en_tri_pairs(int32_t K) {
     const int64_t T = en_tiles(K);
     return T * (T + 1) / 2;
 }
+// larger supergraphs share their tile pairs out over this grid (4M workgroups of 256:
+// under the 2^32 work-items a launch may have)
+constexpr int64_t kEnPairBlocks = (int64_t)1 << 22;
+static int64_t en_tri_blocks(int32_t K) { return std::min(en_tri_pairs(K), kEnPairBlocks); }
 static int en_edge_blocks(int64_t E) { return (int)grid_for(E, kEnThreads * 8, 2048); }
 static int en_grav_blocks(int32_t K) { return (int)grid_for(K, kEnThreads * 8, 2048); }
 static int en_splits(int32_t K) {
@@ -263,7 +275,8 @@ extern "C" bgv_status bgv_fa2_energy(int32_t K, int64_t E, const int32_t *edges,
     if (!m) BGV_TRY(build_csr(K, E, edges, attr_w, nullptr, w.csr, s, &m));
     const float2 *x = reinterpret_cast<const float2 *>(pos);
     const int64_t ntri = en_tri_blocks(K);
-    BGV_LAUNCH(k_energy_pairs, dim3((unsigned)ntri), dim3(kEnThreads), 0, s, K, en_tiles(K), x, m, w.prep);
+    BGV_LAUNCH(k_energy_pairs, dim3((unsigned)ntri), dim3(kEnThreads), 0, s, K, en_tiles(K), en_tri_pairs(K), x, m,
+               w.prep);
     const int ne = en_edge_blocks(E), ng = en_grav_blocks(K);
     BGV_LAUNCH(k_energy_edges, dim3(ne), dim3(kEnThreads), 0, s, E, reinterpret_cast<const int2 *>(edges),
                        attr_w, x, w.patt);

@@ -91,3 +91,33 @@ def test_energy_run_to_run_identical(bgv):
     ga = bgv.fa2_grad(dev(se), dev(pos))
     gb = bgv.fa2_grad(dev(se), dev(pos))
     assert torch.equal(ga, gb)
+
+
+def _lattice_repulsion(a, b):
+    """sum over pairs of ln |x_i - x_j| for the a x b integer lattice, by offsets: the
+    offset (dx, dy) joins (a - |dx|)(b - |dy|) pairs (each unordered pair counted once
+    over the half-plane of offsets).  FP64, O(a b) terms."""
+    dx = np.arange(-(a - 1), a)[:, None]
+    dy = np.arange(-(b - 1), b)[None, :]
+    cnt = (a - np.abs(dx)) * (b - np.abs(dy)).astype(np.float64)
+    d2 = (dx * dx + dy * dy).astype(np.float64)
+    with np.errstate(divide="ignore"):
+        t = np.where(d2 > 0, cnt * 0.5 * np.log(d2), 0.0)
+    return 0.5 * t.sum()  # every unordered pair appears at +offset and -offset
+
+
+@pytest.mark.parametrize("a,b", [(40, 30), (1000, 800)])
+def test_energy_lattice_closed_form(bgv, a, b):
+    """Repulsion energy of unit masses on an integer lattice against its closed form by
+    offsets.  800,000 bodies give 1.25M tile pairs more than one workgroup each can take,
+    so the pairs are shared out over a capped grid."""
+    xs, ys = np.meshgrid(np.arange(a), np.arange(b), indexing="ij")
+    pos = np.stack([xs.ravel(), ys.ravel()], 1).astype(np.float32)
+    K = len(pos)
+    se = np.zeros((0, 2), np.int32)
+    mass = dev(np.ones(K, np.float32))
+    e = float(bgv.fa2_energy(dev(se), dev(pos), kr=1.0, kg=0.0, mass=mass))
+    ref = -_lattice_repulsion(a, b)
+    print(f"  lattice {a}x{b}: K={K} energy {e:.10e} closed form {ref:.10e} rel {abs(e - ref) / abs(ref):.2e}",
+          flush=True)
+    assert abs(e - ref) <= 1e-5 * abs(ref)
