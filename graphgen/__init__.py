@@ -13,7 +13,12 @@ Every generator is deterministic in its seed (numpy PCG64).
 """
 from __future__ import annotations
 
+import concurrent.futures as _futures
+import os
+
 import numpy as np
+
+_THREADS = max(1, min(16, os.cpu_count() or 1))
 
 __all__ = [
     "planted_partition",
@@ -105,12 +110,20 @@ def planted_fixed_m(n: int, blocks: int, m: int, frac_intra: float, seed: int):
 
 def _sorted_search(table: np.ndarray, t: np.ndarray) -> np.ndarray:
     """np.searchsorted(table, t, side='right'), faster for large unsorted t (the
-    queries are visited in sorted order, which keeps the table walk cache-friendly)."""
+    queries are visited in sorted order, which keeps the table walk cache-friendly),
+    in slices on several threads (numpy's sort releases the interpreter lock)."""
     if t.shape[0] < 65536:
         return np.searchsorted(table, t, side="right")
-    idx = np.argsort(t, kind="stable")
     out = np.empty(t.shape[0], dtype=np.int64)
-    out[idx] = np.searchsorted(table, t[idx], side="right")
+
+    def part(lo, hi):
+        tc = t[lo:hi]
+        idx = np.argsort(tc, kind="stable")
+        out[lo + idx] = np.searchsorted(table, tc[idx], side="right")
+
+    bounds = np.linspace(0, t.shape[0], _THREADS + 1).astype(np.int64)
+    with _futures.ThreadPoolExecutor(_THREADS) as ex:
+        list(ex.map(part, bounds[:-1], bounds[1:]))
     return out
 
 
