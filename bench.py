@@ -2,11 +2,13 @@
 
 One step = the whole path over one synthetic graph already resident in HBM:
 streaming community passes -> count-min-sketch supergraph -> Barnes-Hut ForceAtlas2
-layout of the supergraph.  Default workload: the LFR-style power-law graph with 1M
-nodes and 10M edges (degree exponent 2.3, community sizes exponent 1.5, mixing 0.2),
-threshold 64, 3 passes, 2^20-edge chunks, sketch 4 x 2^20, 500 iterations at theta 1.2.
+layout of the supergraph.  Default workload: the largest single graph, an LFR-style
+power-law graph with 3.2M nodes and 34M edges (degree exponent 2.1, community sizes
+exponent 1.5, mixing 0.3), threshold 128, 3 passes, 2^22-edge chunks, sketch
+5 x 2^22, 1,000 Barnes-Hut iterations at theta 1.2 (the analogue of the paper's
+largest Table 1 row).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload lfr_1m] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload lfr_3m] [--no-cpu]
 
 Prints one JSON line.  `value` is edges/s through the community passes + sketch
 supergraph; FA2 iterations/s and the whole-step rate are reported beside it.
@@ -35,16 +37,20 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="lfr_1m")
+    ap.add_argument("--workload", default="lfr_3m")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    ap.add_argument("--cpu-fa2-iters", type=int, default=500,
-                    help="layout iterations the CPU oracle runs for the baseline (the workload has 500)")
+    ap.add_argument("--cpu-fa2-iters", type=int, default=10,
+                    help="Barnes-Hut layout iterations the CPU oracle runs for its FA2 rate (a sample: the "
+                         "workload has 1,000)")
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the batched, gradient and largest-graph comparisons")
+                    help="skip the whole-graph, sequential-rule, sweep, small-graph, batched, gradient and lfr_1m "
+                         "comparisons")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="do not time launches with HIP events (for hardware-counter runs)")
     ap.add_argument("--profile-sample", type=int, default=PROFILE_SAMPLE, metavar="N",
                     help="time one in N launches of the dominant kernel in the timed steps")
+    ap.add_argument("--form", default=None, choices=sorted(FORMS),
+                    help="run only this comparison and print its JSON (for profiling runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (5 times), to scale HBM counters")
     return ap.parse_args()
@@ -78,7 +84,11 @@ def main():
     import paper_2108_00529_amd as bgv
     from paper_2108_00529_amd import profile as prof
 
-    wl = graphgen.WORKLOADS[args.workload]
+    if args.form:
+        print(json.dumps({"form": args.form, **FORMS[args.form](torch, bgv, graphgen)}))
+        return
+
+    wl = dict(graphgen.WORKLOADS[args.workload], name=args.workload)
     n = wl["n"]
     t0 = time.time()
     edges_np, _ = graphgen.make_graph(args.workload)
@@ -221,7 +231,7 @@ def main():
                         "small_graph": small_graph_form(torch, bgv, graphgen),
                         "batched": batched_form(torch, bgv, graphgen),
                         "gradient": gradient_form(torch, bgv, graphgen),
-                        "largest_graph": largest_graph_form(torch, bgv, graphgen)}
+                        "lfr_1m": lfr_1m_form(torch, bgv, graphgen)}
     print(json.dumps(out))
 
 
@@ -346,59 +356,44 @@ def small_graph_form(torch, bgv, graphgen, repeats=5):
             "fa2_iters_per_s_in_batch": wl["fa2_iters"] / (batch_ms / 1000.0), "same_positions": same}
 
 
-def largest_graph_form(torch, bgv, graphgen, cpu_fa2_iters=10):
-    """The lfr_3m workload (3.2M nodes, 34M edges) end to end on the GPU (community
-    passes, supergraph, 1,000 Barnes-Hut iterations) against the oracle on the host:
-    the oracle runs the community passes and supergraph in full (one thread) and
-    `cpu_fa2_iters` layout iterations (all OpenMP threads), scaled to the workload's
-    iteration count."""
-    import oracle
-    wl = graphgen.WORKLOADS["lfr_3m"]
+def lfr_1m_form(torch, bgv, graphgen, repeats=3):
+    """The 1M-node / 10M-edge LFR-style workload (3 passes with 2^20-edge chunks,
+    sketch 4 x 2^20, 500 Barnes-Hut iterations): community passes + sketch supergraph
+    edges/s and layout iterations/s, best of `repeats` steps after a warm-up one."""
+    wl = graphgen.WORKLOADS["lfr_1m"]
     t0 = time.time()
-    e, _ = graphgen.make_graph("lfr_3m")
-    print(f"[bench] largest graph: generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    e, _ = graphgen.make_graph("lfr_1m")
+    print(f"[bench] lfr_1m: generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     n, m = wl["n"], e.shape[0]
     c1 = graphgen.hash_coeffs(wl["rows"], wl["sketch_seed"])
     c2 = graphgen.hash_coeffs(wl["rows"], wl["sketch_seed"] ^ 0x9E3779B97F4A7C15)
-    pos_all = graphgen.initial_positions(n, wl["pos_seed"])
     dev = torch.device("cuda:0")
     ed = torch.from_numpy(e).to(dev)
-    pos_d = torch.from_numpy(pos_all).to(dev)
+    pos_d = torch.from_numpy(graphgen.initial_positions(n, wl["pos_seed"])).to(dev)
     ws_cd = bgv.api.community_workspace(ed, n, wl)
     ws_sg = bgv.api.supergraph_workspace(ed, n, wl)
-
-    def run():
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    best_cd, best_fa, sg = float("inf"), float("inf"), None
+    for r in range(repeats + 1):
+        ev[0].record()
         labels, degree, _ = bgv.community(ed, n, wl["threshold"], wl["passes"], wl["growth"], wl["chunk"], ws=ws_cd,
                                           check=False)
         sg = bgv.supergraph(ed, labels, degree, wl["rows"], wl["cols"], c1, c2, ws=ws_sg, check=False)
+        ev[1].record()
         pos = pos_d[: sg["K"]].clone()
         bgv.fa2_layout(sg["superedges"], pos, wl["fa2_iters"], exact=False, theta=wl["theta"], kr=wl["kr"],
                        kg=wl["kg"], tau=wl["tau"], ks=wl["ks"], ksmax=wl["ksmax"])
-        return sg
-
-    run()
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    sg = run()
-    torch.cuda.synchronize()
-    gpu_ms = 1000.0 * (time.perf_counter() - t)
-    del ed, pos_d
+        ev[2].record()
+        ev[2].synchronize()
+        if r > 0:
+            best_cd = min(best_cd, ev[0].elapsed_time(ev[1]))
+            best_fa = min(best_fa, ev[1].elapsed_time(ev[2]))
+    del ed, pos_d, ws_cd, ws_sg
     torch.cuda.empty_cache()
-    t = time.perf_counter()
-    lab, cnt = oracle.bs_community(n, e, wl["threshold"], wl["passes"], wl["growth"], wl["chunk"])
-    deg, _ = oracle.degree_volume(lab, cnt, wl["passes"])
-    ref = oracle.supergraph(n, e, lab, deg, wl["rows"], wl["cols"], c1, c2)
-    cpu_cd_s = time.perf_counter() - t
-    t = time.perf_counter()
-    oracle.fa2_layout(pos_all[: ref["K"]], ref["superedges"], iters=cpu_fa2_iters, exact=False, theta=wl["theta"])
-    cpu_fa_s = (time.perf_counter() - t) * wl["fa2_iters"] / cpu_fa2_iters
-    cpu_ms = 1000.0 * (cpu_cd_s + cpu_fa_s)
     return {"nodes": n, "edges": m, "supernodes": sg["K"], "superedges": sg["E"],
-            "supernodes_equal_oracle": bool(sg["K"] == ref["K"]), "fa2_iterations": wl["fa2_iters"],
-            "gpu_end_to_end_ms": gpu_ms, "oracle_end_to_end_ms": cpu_ms,
-            "oracle_sample": f"community + supergraph in full on 1 thread ({cpu_cd_s:.1f}s); {cpu_fa2_iters} "
-                             f"Barnes-Hut iterations scaled to {wl['fa2_iters']}",
-            "speedup_vs_oracle": cpu_ms / gpu_ms}
+            "community_sketch_ms": best_cd, "community_sketch_edges_per_s": m / (best_cd / 1000.0),
+            "fa2_iterations": wl["fa2_iters"], "fa2_ms": best_fa,
+            "fa2_iters_per_s": wl["fa2_iters"] / (best_fa / 1000.0)}
 
 
 def whole_graph_form(torch, bgv, edges_np, n, wl, bgv_ms):
@@ -504,7 +499,8 @@ def gradient_form(torch, bgv, graphgen, lrs=(3.0, 10.0, 30.0), max_steps=3000):
     """The grad_50k workload: weighted supergraph of 50,000 supernodes (planted
     communities of a 5M-node LFR-style graph; weights from a 5 x 2^22 sketch).  Exact FA2
     with its adaptive speeds for the workload's iterations vs Adam on the FA2 energy
-    (autograd function with the hand-written gradient) until it reaches the same energy."""
+    (autograd function with the hand-written gradient) until it reaches the same energy.
+    With lrs empty only the exact layout runs (its pair rate: K^2 pairs per iteration)."""
     wl = graphgen.WORKLOADS["grad_50k"]
     t0 = time.time()
     e, comm = graphgen.make_graph("grad_50k")
@@ -526,6 +522,8 @@ def gradient_form(torch, bgv, graphgen, lrs=(3.0, 10.0, 30.0), max_steps=3000):
     fa2_iters = wl["fa2_iters"]
     p = pos0.clone()
     ms_fa2 = _timed(torch, lambda: bgv.fa2_layout(se, p, fa2_iters, exact=True, attr_w=w))
+    print(f"[bench] gradient form: {fa2_iters} exact iterations on K={K} in {ms_fa2:.1f} ms", file=sys.stderr,
+          flush=True)
     e_fa2 = float(bgv.fa2_energy(se, p, attr_w=w))
     e_start = float(bgv.fa2_energy(se, pos0, attr_w=w))
     adam = {}
@@ -551,8 +549,31 @@ def gradient_form(torch, bgv, graphgen, lrs=(3.0, 10.0, 30.0), max_steps=3000):
                          "energy": energy}
     ok = [v for v in adam.values() if v["reached_fa2_energy"]]
     return {"supernodes": K, "superedges": E, "fa2_iterations": fa2_iters, "fa2_ms": ms_fa2,
+            "fa2_pairs_per_s": float(K) * K * fa2_iters / (ms_fa2 / 1000.0),
             "energy_start": e_start, "energy_fa2": e_fa2, "adam": adam,
             "adam_best_ms_to_fa2_energy": min(v["ms"] for v in ok) if ok else None}
+
+
+def _forms():
+    """The comparisons `--form` can run alone."""
+    def needs_bench_graph(fn):
+        def run(torch, bgv, graphgen, name="lfr_3m"):
+            wl = dict(graphgen.WORKLOADS[name], name=name)
+            e, _ = graphgen.make_graph(name)
+            return fn(torch, bgv, e, wl)
+        return run
+    return {"gradient": gradient_form,
+            "gradient_fa2": lambda torch, bgv, graphgen: gradient_form(torch, bgv, graphgen, lrs=()),
+            "batched": batched_form,
+            "small_graph": small_graph_form,
+            "lfr_1m": lfr_1m_form,
+            "whole_graph_fa2": needs_bench_graph(lambda torch, bgv, e, wl: whole_graph_form(torch, bgv, e, wl["n"], wl,
+                                                                                             float("nan"))),
+            "sequential_rule": needs_bench_graph(lambda torch, bgv, e, wl: sequential_rule_form(torch, bgv, e, wl["n"],
+                                                                                                 wl, False))}
+
+
+FORMS = _forms()
 
 
 # algorithmic work per unit: bytes (HBM-bound kernels) or flops (ALU-bound)
@@ -647,7 +668,8 @@ def roofline_report(kstats, kbreak, wl, n, m, K, E, inter_per_launch=None):
     r = roofline_of(top, avg_s, K, E, st.get("bh_interactions_per_launch"))
     if st.get("bh_interactions_per_launch"):
         r["interactions_per_launch"] = st["bh_interactions_per_launch"]
-    r = dict(r, kernel=top, avg_ms=avg_s * 1000.0, launches_sampled=st["launches"], traffic=measured_traffic(top))
+    r = dict(r, kernel=top, avg_ms=avg_s * 1000.0, launches_sampled=st["launches"],
+             traffic=measured_traffic(top, wl["name"]))
     return r, extra
 
 
@@ -662,12 +684,12 @@ def csrc_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
-    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when it has no entry or the
-    kernel sources have changed since the counters were taken."""
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary of
+    the workload (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when it has no entry
+    or the kernel sources have changed since the counters were taken."""
     import re
-    summary = os.path.join(ROOT, "profiles", "hbm_traffic_lfr_1m.md")
+    summary = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
     try:
         text = open(summary).read()
     except OSError:
@@ -681,7 +703,8 @@ def measured_traffic(kernel: str):
 
 def cpu_baseline(edges_np, n, wl, c1, c2, pos0_np, fa2_iters):
     """The oracle, untuned, on this host: community passes + supergraph on the whole
-    graph (single thread) and a few Barnes-Hut FA2 iterations (OpenMP)."""
+    graph (single thread; `value` in edges/s like the GPU's) and a sample of
+    `fa2_iters` Barnes-Hut FA2 iterations on the supergraph (OpenMP over all threads)."""
     import oracle
     t = time.perf_counter()
     lab, cnt = oracle.bs_community(n, edges_np, wl["threshold"], wl["passes"], wl["growth"], wl["chunk"])
@@ -695,8 +718,9 @@ def cpu_baseline(edges_np, n, wl, c1, c2, pos0_np, fa2_iters):
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": edges_np.shape[0] / t_cd, "unit": "edges/s", "cores": 1, "kind": "oracle",
             "sample": f"community passes + sketch supergraph over all {edges_np.shape[0]} edges "
-                      f"({t_cd:.1f}s, 1 thread); FA2: {fa2_iters} Barnes-Hut iterations on the "
-                      f"{K}-node supergraph in {t_fa:.1f}s with {threads} OpenMP threads",
+                      f"({t_cd:.1f}s, 1 thread); FA2: {fa2_iters} of the workload's {wl['fa2_iters']} "
+                      f"Barnes-Hut iterations on the {K}-node supergraph in {t_fa:.1f}s with {threads} "
+                      f"OpenMP threads (not scaled up)",
             "fa2_iters_per_s": fa2_iters / t_fa, "fa2_threads": threads,
             "host_cpu": host_cpu_model(), "host_threads": os.cpu_count()}
 
