@@ -142,6 +142,24 @@ bgv_status bgv_community_passes(int32_t n, int64_t m, const int32_t *edges, cons
                                 int32_t *pass_labels, void *ws, size_t ws_bytes,
                                 bgv_stream_t stream);
 
+/*
+ * Paper: Section 3.2.1 and Algorithm 3 (the rounds share one state: each node's label
+ * and degree counter, initialised once before the first round).  Continues a run of
+ * bgv_community that stopped after `done` passes, 1 <= done < p->passes: same n, m,
+ * edges and parameters; labels_in (dev int32[n], ids in [0, n)) holds that run's labels
+ * after its `done` passes (e.g. row done-1 of bgv_community_passes, or the labels of
+ * bgv_community with passes = done).  Runs passes done .. passes-1 and returns exactly
+ * what bgv_community with p->passes returns (labels, degree, volume).  The counters at
+ * that point are done * d(v) and d(v) follows from the stream, so labels and `done`
+ * are the whole state; the degrees are recounted from the edges (one counting sweep).
+ * labels_in must not overlap labels.  Workspace: bgv_community_workspace(n, m, p).
+ * Invalid done, a null or aliased labels_in: BGV_E_INVALID.  With BGV_CHECK=1,
+ * labels_in is range-checked too (BGV_E_RANGE).
+ */
+bgv_status bgv_community_resume(int32_t n, int64_t m, const int32_t *edges, const bgv_cd_params *p,
+                                int32_t done, const int32_t *labels_in, int32_t *labels, int32_t *degree,
+                                int64_t *volume, void *ws, size_t ws_bytes, bgv_stream_t stream);
+
 /* ---------------------------------------------------------------------------- */
 /* Count-min-sketch supergraph                                                  */
 /* ---------------------------------------------------------------------------- */

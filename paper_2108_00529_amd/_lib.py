@@ -56,6 +56,8 @@ bgv_last_error = _sig("bgv_last_error", C.c_char_p, [])
 bgv_community_workspace = _sig("bgv_community_workspace", SZ, [i32, i64, C.POINTER(CdParams)])
 bgv_community = _sig("bgv_community", i32, [i32, i64, P, C.POINTER(CdParams), P, P, P, P, SZ, P])
 bgv_community_passes = _sig("bgv_community_passes", i32, [i32, i64, P, C.POINTER(CdParams), P, P, P, P, P, SZ, P])
+bgv_community_resume = _sig("bgv_community_resume", i32, [i32, i64, P, C.POINTER(CdParams), i32, P, P, P, P, P,
+                                                          SZ, P])
 bgv_supergraph_workspace = _sig("bgv_supergraph_workspace", SZ, [i32, i64, C.POINTER(SketchParams)])
 bgv_supergraph = _sig("bgv_supergraph", i32, [i32, i64, P, P, P, C.POINTER(SketchParams), C.POINTER(i32),
                                               C.POINTER(i64), P, P, P, P, P, P, P, P, P, SZ, P])
@@ -77,7 +79,7 @@ bgv_bh_tree_workspace = _sig("bgv_bh_tree_workspace", SZ, [i32])
 bgv_bh_tree = _sig("bgv_bh_tree", i32, [i32, P, P, P, P, P, P, P, P, SZ, P])
 
 EXPORTED = ["bgv_status_string", "bgv_last_error", "bgv_community_workspace", "bgv_community",
-            "bgv_community_passes",
+            "bgv_community_passes", "bgv_community_resume",
             "bgv_supergraph_workspace", "bgv_supergraph", "bgv_fa2_workspace", "bgv_fa2_layout",
             "bgv_fa2_energy_workspace", "bgv_fa2_energy", "bgv_fa2_grad",
             "bgv_profile_enable", "bgv_profile_filter", "bgv_profile_sample", "bgv_profile_reset", "bgv_profile_count", "bgv_profile_get",

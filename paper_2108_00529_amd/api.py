@@ -129,6 +129,36 @@ def community_passes(edges: torch.Tensor, n: int, threshold: int, passes: int = 
     return labels, degree, vol, rows
 
 
+def community_resume(edges: torch.Tensor, n: int, labels_in: torch.Tensor, done: int, threshold: int,
+                     passes: int, growth: int = 2, chunk: int = 1, volume: bool = False,
+                     ws: torch.Tensor | None = None, stream=None, method: int = 0, tie: int = 0, rule: int = 0,
+                     check: bool = True):
+    """Continue a community() run that stopped after `done` passes from its labels then
+    (labels_in int32[n]): passes done .. passes-1, with the same results as community()
+    with `passes` passes.  Returns (labels, degree, volume or None)."""
+    m = edges.shape[0] if edges.dim() == 2 else 0
+    _need(edges, torch.int32, "edges", (m, 2))
+    _need(labels_in, torch.int32, "labels_in", (n,))
+    if check:
+        validate_edges(edges, n, stream)
+    p = L.CdParams(int(threshold), int(passes), int(growth), int(method), int(chunk), int(tie), int(rule))
+    need = L.bgv_community_workspace(int(n), m, C.byref(p))
+    if need == 0:
+        raise L.BgvError(f"invalid community arguments (n={n}, m={m}, {threshold}, {passes}, {growth}, {chunk}, "
+                         f"method {method})")
+    dev = edges.device
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, dev)
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
+    degree = torch.empty(n, dtype=torch.int32, device=dev)
+    vol = torch.empty(n, dtype=torch.int64, device=dev) if volume else None
+    with _range_check(check):
+        L.check(L.bgv_community_resume(int(n), m, _ptr(edges), C.byref(p), int(done), _ptr(labels_in), _ptr(labels),
+                                       _ptr(degree), _ptr(vol), _ptr(ws), ws.numel(), _stream(stream)),
+                "bgv_community_resume")
+    return labels, degree, vol
+
+
 def community_workspace(edges: torch.Tensor, n: int, wl: dict) -> torch.Tensor:
     """A workspace tensor for community() on this graph and workload."""
     p = L.CdParams(int(wl["threshold"]), int(wl["passes"]), int(wl["growth"]), 0, int(wl["chunk"]),
@@ -227,6 +257,7 @@ def fa2_layout(superedges: torch.Tensor, pos: torch.Tensor, iters: int, exact: b
     L.check(L.bgv_fa2_layout(int(K), int(E), _ptr(superedges), _ptr(attr_w), _ptr(mass), _ptr(pos), _ptr(fprev),
                              _ptr(speed), C.byref(p), _ptr(ws), ws.numel(), _stream(stream)), "bgv_fa2_layout")
     return pos, fprev, speed
+
 
 
 def fa2_energy(superedges: torch.Tensor, pos: torch.Tensor, kr: float = 1.0, kg: float = 1.0,

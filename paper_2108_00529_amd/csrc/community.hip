@@ -47,11 +47,12 @@ static_assert(sizeof(NodeState) == 16, "node record must be 16 bytes");
 constexpr int kCdThreads = 1024;
 constexpr uint64_t kNoProposal = ~0ull;
 
-__global__ void __launch_bounds__(kCdThreads) k_cd_init(NodeState *st, int32_t n) {
+// Records: counter 0, label lab0[v] (a resumed run's labels) or v, no proposal.
+__global__ void __launch_bounds__(kCdThreads) k_cd_init(NodeState *st, int32_t n, const int32_t *__restrict__ lab0) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         NodeState s;
         s.cnt = 0;
-        s.label = (int32_t)v;
+        s.label = lab0 ? lab0[v] : (int32_t)v;
         s.win = kNoProposal;
         st[v] = s;
     }
@@ -170,10 +171,11 @@ __device__ __forceinline__ uint32_t cd_offsets(uint32_t *hist, int32_t nb, uint3
     return total;
 }
 
-__global__ void __launch_bounds__(kCdThreads) k_cd_init_b(int32_t *cnt, int32_t *lab, int32_t n) {
+__global__ void __launch_bounds__(kCdThreads) k_cd_init_b(int32_t *cnt, int32_t *lab, int32_t n,
+                                                           const int32_t *__restrict__ lab0) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         cnt[v] = 0;
-        lab[v] = (int32_t)v;
+        lab[v] = lab0 ? lab0[v] : (int32_t)v;
     }
 }
 
@@ -600,7 +602,8 @@ static size_t vr_layout(Carver &c, int32_t n, int64_t m, const bgv_cd_params *p,
 }
 
 static bgv_status vr_run(int32_t n, int64_t m, const int32_t *edges, const bgv_cd_params *p, int32_t *labels,
-                         int32_t *degree, int64_t *volume, int32_t *pass_labels, void *ws, hipStream_t s);
+                         int32_t *degree, int64_t *volume, int32_t *pass_labels, int32_t first,
+                         const int32_t *lab0, void *ws, hipStream_t s);
 
 }  // namespace bgv
 
@@ -627,8 +630,8 @@ __global__ void k_cd_copy_labels(const int32_t *__restrict__ src, int32_t stride
 // last chunk's proposals are then resolved at the end of its pass rather than with the
 // next pass's first chunk, which adds no counter increments, so nothing changes).
 static bgv_status cd_run(int32_t n, int64_t m, const int32_t *edges, const bgv_cd_params *p, int32_t *labels,
-                         int32_t *degree, int64_t *volume, int32_t *pass_labels, void *ws, size_t ws_bytes,
-                         bgv_stream_t stream, const char *who) {
+                         int32_t *degree, int64_t *volume, int32_t *pass_labels, int32_t first,
+                         const int32_t *lab0, void *ws, size_t ws_bytes, bgv_stream_t stream, const char *who) {
     clear_error();
     if (!cd_valid(n, m, p)) {
         set_error("%s: invalid arguments (n=%d m=%lld)", who, n, (long long)m);
@@ -640,10 +643,14 @@ static bgv_status cd_run(int32_t n, int64_t m, const int32_t *edges, const bgv_c
     }
     BGV_TRY(check_ws(ws, ws_bytes, bgv_community_workspace(n, m, p)));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    if (range_check_on()) BGV_TRY(check_edge_ids(n, m, edges, labels, s));  // labels[0]: overwritten below
+    if (range_check_on()) {
+        BGV_TRY(check_edge_ids(n, m, edges, labels, s));  // labels[0]: overwritten below
+        if (lab0) BGV_TRY(check_id_list(n, lab0, n, labels, s));
+    }
     if (volume) BGV_TRY(fill<int64_t>(volume, 0, n, s));
-    if (cd_method(n, m, p) == 2) return sq_run(n, m, edges, p, labels, degree, volume, pass_labels, ws, s);
-    if (p->rule == 1) return vr_run(n, m, edges, p, labels, degree, volume, pass_labels, ws, s);
+    if (cd_method(n, m, p) == 2)
+        return sq_run(n, m, edges, p, labels, degree, volume, pass_labels, first, lab0, ws, s);
+    if (p->rule == 1) return vr_run(n, m, edges, p, labels, degree, volume, pass_labels, first, lab0, ws, s);
     Carver c(ws);
     CdWs w;
     cd_layout(c, n, m, p, &w);
@@ -653,7 +660,7 @@ static bgv_status cd_run(int32_t n, int64_t m, const int32_t *edges, const bgv_c
 
     if (cd_bucketed(n)) {
         const int32_t nb = cd_buckets(n);
-        BGV_LAUNCH(k_cd_init_b, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, w.cnt, w.lab, n);
+        BGV_LAUNCH(k_cd_init_b, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, w.cnt, w.lab, n, lab0);
         int32_t ptiles = 0;  // decide tiles whose proposals are not yet resolved
         int32_t etiles = 0;  // grouped endpoint tiles whose increments are not yet added
         auto tiles_of = [&](int64_t k) {
@@ -667,12 +674,17 @@ static bgv_status cd_run(int32_t n, int64_t m, const int32_t *edges, const bgv_c
                        (uint8_t *)nullptr, CdLater{}, (int64_t)0, (int64_t)0, 0, 0, 0, nb, w.props, w.ptab, (int64_t)0,
                        std::min<int64_t>(B, m), w.ends, w.etab);
         }
-        // passes 2 .. 1 + later.n are decided in pass 1 (their counters are known there)
+        // passes 2 .. 1 + later.n are decided in pass 1 (their counters are known there);
+        // a run resumed after two or more passes has no pass 1 and decides each pass itself
         CdLater later{};
-        later.n = w.mask ? std::min(p->passes - 2, 4) : 0;
+        later.n = w.mask && first <= 1 ? std::min(p->passes - 2, 4) : 0;
         for (int q = 0; q < later.n; ++q) later.D[q] = pass_threshold(p->threshold, p->growth, q + 2);
         for (int32_t pass = 0; pass < p->passes && (m > 0 || pass_labels); ++pass) {
-            const int32_t D = pass_threshold(p->threshold, p->growth, pass);
+            // resumed after `first` passes: pass 0 only counts (threshold -1: no edge
+            // proposes), which yields the degrees and the per-edge pass-0 counters of the
+            // closed form; passes 1 .. first-1 are skipped
+            if (pass > 0 && pass < first) continue;
+            const int32_t D = pass == 0 && first > 0 ? -1 : pass_threshold(p->threshold, p->growth, pass);
             for (int64_t k = 0; k < nchunk; ++k) {
                 const int64_t cs = k * B, ce = (cs + B < m) ? cs + B : m;
                 const int32_t tiles = tiles_of(k);
@@ -722,10 +734,11 @@ static bgv_status cd_run(int32_t n, int64_t m, const int32_t *edges, const bgv_c
     NodeState *st = w.st;
     int32_t *prop = w.prop;
     int2 *c1 = w.c1;
-    BGV_LAUNCH(k_cd_init, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, st, n);
+    BGV_LAUNCH(k_cd_init, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, st, n, lab0);
     int64_t ps = 0, pe = 0;  // pending (not yet applied) chunk
     for (int32_t pass = 0; pass < p->passes && (m > 0 || pass_labels); ++pass) {
-        const int32_t D = pass_threshold(p->threshold, p->growth, pass);
+        if (pass > 0 && pass < first) continue;  // resumed: as in the bucketed form above
+        const int32_t D = pass == 0 && first > 0 ? -1 : pass_threshold(p->threshold, p->growth, pass);
         for (int64_t k = 0; k < nchunk; ++k) {
             const int64_t cs = k * B, ce = (cs + B < m) ? cs + B : m;
             // counters are incremented in pass 0 only (later passes use the closed form)
@@ -764,16 +777,23 @@ static bgv_status cd_run(int32_t n, int64_t m, const int32_t *edges, const bgv_c
 }
 
 static bgv_status vr_run(int32_t n, int64_t m, const int32_t *edges, const bgv_cd_params *p, int32_t *labels,
-                         int32_t *degree, int64_t *volume, int32_t *pass_labels, void *ws, hipStream_t s) {
+                         int32_t *degree, int64_t *volume, int32_t *pass_labels, int32_t first,
+                         const int32_t *lab0, void *ws, hipStream_t s) {
     Carver c(ws);
     VrWs w;
     vr_layout(c, n, m, p, &w);
     const int2 *e2 = reinterpret_cast<const int2 *>(edges);
     const unsigned gn = grid_for(n, kCdThreads, 65536);
-    BGV_LAUNCH(k_cd_init, dim3(gn), dim3(kCdThreads), 0, s, w.st, n);
+    BGV_LAUNCH(k_cd_init, dim3(gn), dim3(kCdThreads), 0, s, w.st, n, lab0);
     BGV_TRY(fill<uint64_t>(reinterpret_cast<uint64_t *>(w.vol), 0ull, n, s));
     const int64_t B = p->chunk;
-    for (int32_t pass = 0; pass < p->passes; ++pass) {
+    // a resumed run: after `first` passes every counter is first * d(v) and V[c] the sum
+    // of the counters labelled c; the increments of `first` sweeps over the stream with
+    // the labels held at lab0 build exactly that
+    for (int32_t q = 0; q < first && m > 0; ++q)
+        BGV_LAUNCH(k_vr_inc, dim3(grid_for(m, kCdThreads * 4, 16384)), dim3(kCdThreads), 0, s, w.st, w.vol, e2,
+                   (int64_t)0, m);
+    for (int32_t pass = first; pass < p->passes; ++pass) {
         const int32_t D = pass_threshold(p->threshold, p->growth, pass);
         for (int64_t cs = 0; cs < m; cs += B) {
             const int64_t ce = cs + B < m ? cs + B : m;
@@ -796,7 +816,21 @@ static bgv_status vr_run(int32_t n, int64_t m, const int32_t *edges, const bgv_c
 extern "C" bgv_status bgv_community(int32_t n, int64_t m, const int32_t *edges, const bgv_cd_params *p,
                                     int32_t *labels, int32_t *degree, int64_t *volume, void *ws,
                                     size_t ws_bytes, bgv_stream_t stream) {
-    return cd_run(n, m, edges, p, labels, degree, volume, nullptr, ws, ws_bytes, stream, "bgv_community");
+    return cd_run(n, m, edges, p, labels, degree, volume, nullptr, 0, nullptr, ws, ws_bytes, stream, "bgv_community");
+}
+
+extern "C" bgv_status bgv_community_resume(int32_t n, int64_t m, const int32_t *edges, const bgv_cd_params *p,
+                                           int32_t done, const int32_t *labels_in, int32_t *labels,
+                                           int32_t *degree, int64_t *volume, void *ws, size_t ws_bytes,
+                                           bgv_stream_t stream) {
+    if (!p || done < 1 || done >= p->passes || !labels_in || labels_in == labels) {
+        clear_error();
+        set_error("bgv_community_resume: invalid arguments (done=%d, passes=%d, labels_in %p, labels %p)", done,
+                  p ? p->passes : 0, (const void *)labels_in, (void *)labels);
+        return BGV_E_INVALID;
+    }
+    return cd_run(n, m, edges, p, labels, degree, volume, nullptr, done, labels_in, ws, ws_bytes, stream,
+                  "bgv_community_resume");
 }
 
 extern "C" bgv_status bgv_community_passes(int32_t n, int64_t m, const int32_t *edges, const bgv_cd_params *p,
@@ -808,6 +842,6 @@ extern "C" bgv_status bgv_community_passes(int32_t n, int64_t m, const int32_t *
         set_error("bgv_community_passes: null pointer");
         return BGV_E_INVALID;
     }
-    return cd_run(n, m, edges, p, labels, degree, volume, pass_labels, ws, ws_bytes, stream,
+    return cd_run(n, m, edges, p, labels, degree, volume, pass_labels, 0, nullptr, ws, ws_bytes, stream,
                   "bgv_community_passes");
 }

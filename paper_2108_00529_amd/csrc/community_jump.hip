@@ -181,14 +181,14 @@ __device__ __forceinline__ int32_t sq_target(int2 e, int4 c, int32_t p, int32_t 
     return -1;
 }
 
-// flag[p m + i] = edge i proposes in pass p
+// flag[p m + i] = edge i proposes in pass p (passes before `first` propose nothing)
 __global__ void __launch_bounds__(kSqThreads) k_sq_flags(const int2 *__restrict__ edges, const int4 *__restrict__ cd,
                                                          int64_t m, int32_t P, int32_t D1, int32_t growth,
-                                                         int32_t tie, uint32_t *__restrict__ flag) {
+                                                         int32_t tie, int32_t first, uint32_t *__restrict__ flag) {
     SQ_LOOP(t, (int64_t)P * m) {
         const int32_t p = (int32_t)(t / m);
         const int64_t i = t - (int64_t)p * m;
-        flag[t] = sq_target(edges[i], cd[i], p, sq_threshold(D1, growth, p), tie) >= 0 ? 1u : 0u;
+        flag[t] = p >= first && sq_target(edges[i], cd[i], p, sq_threshold(D1, growth, p), tie) >= 0 ? 1u : 0u;
     }
 }
 
@@ -196,12 +196,13 @@ __global__ void __launch_bounds__(kSqThreads) k_sq_flags(const int2 *__restrict_
 template <class KT>
 __global__ void __launch_bounds__(kSqThreads) k_sq_emit(const int2 *__restrict__ edges, const int4 *__restrict__ cd,
                                                         int64_t m, int32_t P, int32_t D1, int32_t growth,
-                                                        int32_t tie, int64_t B,
+                                                        int32_t tie, int32_t first, int64_t B,
                                                         int64_t nchunk, int gbits, const uint32_t *__restrict__ pos,
                                                         KT *__restrict__ key, uint32_t *__restrict__ val) {
     SQ_LOOP(t, (int64_t)P * m) {
         const int32_t p = (int32_t)(t / m);
         const int64_t i = t - (int64_t)p * m;
+        if (p < first) continue;
         const int32_t v = sq_target(edges[i], cd[i], p, sq_threshold(D1, growth, p), tie);
         if (v < 0) continue;
         const uint64_t g = (uint64_t)p * (uint64_t)nchunk + (uint64_t)(i / B);
@@ -252,13 +253,15 @@ __global__ void __launch_bounds__(kSqThreads) k_sq_wruns(const KT *__restrict__ 
 }
 
 // Winner r's link: the last winner into its source with an earlier chunk, or none
-// (~0); packed with the source, the label it carries when it has no link.
+// (~0); packed with the label it carries when it has no link: the source's starting
+// label (its id, or lab0 of a resumed run).
 template <class KT>
 __global__ void __launch_bounds__(kSqThreads) k_sq_links(const int2 *__restrict__ edges, const KT *__restrict__ wk,
                                                          const uint32_t *__restrict__ wv,
                                                          const uint32_t *__restrict__ wcount, int gbits,
                                                          const uint32_t *__restrict__ beg,
                                                          const uint32_t *__restrict__ end,
+                                                         const int32_t *__restrict__ lab0,
                                                          unsigned long long *__restrict__ jv) {
     const int64_t W = *wcount;
     SQ_LOOP(r, W) {
@@ -276,7 +279,8 @@ __global__ void __launch_bounds__(kSqThreads) k_sq_links(const int2 *__restrict_
             else hi = mid;
         }
         const uint32_t link = lo > b0 ? lo - 1 : 0xffffffffu;
-        jv[r] = ((unsigned long long)(uint32_t)u << 32) | link;
+        const int32_t l0 = lab0 ? lab0[u] : u;
+        jv[r] = ((unsigned long long)(uint32_t)l0 << 32) | link;
     }
 }
 
@@ -310,9 +314,10 @@ __global__ void __launch_bounds__(kSqThreads) k_sq_init(int32_t n, int32_t rows,
                                                         int32_t *__restrict__ pass_labels,
                                                         const uint32_t *__restrict__ beg,
                                                         const uint32_t *__restrict__ end,
+                                                        const int32_t *__restrict__ lab0,
                                                         int32_t *__restrict__ degree) {
     SQ_LOOP(v, n) {
-        labels[v] = (int32_t)v;
+        labels[v] = lab0 ? lab0[v] : (int32_t)v;
         degree[v] = (int32_t)(end[v] - beg[v]);
         for (int32_t p = 0; p < rows; ++p) pass_labels[(int64_t)p * n + v] = (int32_t)v;
     }
@@ -369,7 +374,7 @@ bgv_status sq_sort_events<uint64_t>(SqWs &w, int64_t pm, int nbits, uint64_t **s
 
 template <class KT>
 static bgv_status sq_events(const int2 *e2, int32_t n, int64_t m, const bgv_cd_params *p, SqWs &w, int32_t *labels,
-                            int32_t *pass_labels, hipStream_t s) {
+                            int32_t *pass_labels, int32_t first, const int32_t *lab0, hipStream_t s) {
     const int32_t P = p->passes;
     const int64_t B = p->chunk, nchunk = (m + B - 1) / B, pm = (int64_t)P * m;
     const int gbits = bits_for((uint64_t)P * (uint64_t)nchunk - 1);
@@ -377,10 +382,10 @@ static bgv_status sq_events(const int2 *e2, int32_t n, int64_t m, const bgv_cd_p
     const unsigned grid = grid_for(pm, kSqThreads, 65536);
     // proposals of every pass, in (pass, stream) order
     BGV_LAUNCH(k_sq_flags, dim3(grid), dim3(kSqThreads), 0, s, e2, w.cd, m, P, p->threshold, p->growth, p->tie,
-               w.flag);
+               first, w.flag);
     BGV_TRY(exclusive_scan_u32(w.flag, w.flag, pm, w.tot, w.scan_scratch, s));
-    BGV_LAUNCH(k_sq_emit<KT>, dim3(grid), dim3(kSqThreads), 0, s, e2, w.cd, m, P, p->threshold, p->growth, p->tie, B,
-               nchunk,
+    BGV_LAUNCH(k_sq_emit<KT>, dim3(grid), dim3(kSqThreads), 0, s, e2, w.cd, m, P, p->threshold, p->growth, p->tie,
+               first, B, nchunk,
                gbits, w.flag, static_cast<KT *>(w.evk), w.evv);
     BGV_LAUNCH(k_sq_widen, dim3(1), dim3(kSqThreads), 0, s, w.tot, w.tot64);
     KT *sk = nullptr;
@@ -397,7 +402,7 @@ static bgv_status sq_events(const int2 *e2, int32_t n, int64_t m, const bgv_cd_p
     BGV_TRY(fill<uint32_t>(w.end, 0u, n, s));
     BGV_LAUNCH(k_sq_wruns<KT>, dim3(grid), dim3(kSqThreads), 0, s, wk, w.tot + 1, gbits, w.beg, w.end);
     BGV_LAUNCH(k_sq_links<KT>, dim3(grid), dim3(kSqThreads), 0, s, e2, wk, w.wv, w.tot + 1, gbits, w.beg, w.end,
-               w.jv);
+               lab0, w.jv);
     // a chain of links visits at most one winner per chunk: ceil(log2 chunks) + 1 rounds
     const int rounds = bits_for((uint64_t)P * (uint64_t)nchunk) + 1;
     BGV_TRY(fill<int32_t>(w.go, 0, rounds + 1, s));
@@ -410,7 +415,8 @@ static bgv_status sq_events(const int2 *e2, int32_t n, int64_t m, const bgv_cd_p
 }
 
 bgv_status sq_run(int32_t n, int64_t m, const int32_t *edges, const bgv_cd_params *p, int32_t *labels,
-                  int32_t *degree, int64_t *volume, int32_t *pass_labels, void *ws, hipStream_t s) {
+                  int32_t *degree, int64_t *volume, int32_t *pass_labels, int32_t first, const int32_t *lab0,
+                  void *ws, hipStream_t s) {
     Carver c(ws);
     SqWs w;
     sq_layout(c, n, m, p, &w);
@@ -426,11 +432,11 @@ bgv_status sq_run(int32_t n, int64_t m, const int32_t *edges, const bgv_cd_param
     BGV_LAUNCH(k_sq_runs, dim3(go), dim3(kSqThreads), 0, s, sk, no, n, w.beg, w.end);
     BGV_LAUNCH(k_sq_counts, dim3(go), dim3(kSqThreads), 0, s, sk, sv, no, n, w.beg, w.end, m, p->chunk, w.cd);
     BGV_LAUNCH(k_sq_init, dim3(gn), dim3(kSqThreads), 0, s, n, pass_labels ? p->passes : 0, labels, pass_labels,
-               w.beg, w.end, degree);
+               w.beg, w.end, lab0, degree);
     if (sq_wide(n, m, p))
-        BGV_TRY(sq_events<uint64_t>(e2, n, m, p, w, labels, pass_labels, s));
+        BGV_TRY(sq_events<uint64_t>(e2, n, m, p, w, labels, pass_labels, first, lab0, s));
     else
-        BGV_TRY(sq_events<uint32_t>(e2, n, m, p, w, labels, pass_labels, s));
+        BGV_TRY(sq_events<uint32_t>(e2, n, m, p, w, labels, pass_labels, first, lab0, s));
     if (volume)
         BGV_LAUNCH(k_sq_volume, dim3(gn), dim3(kSqThreads), 0, s, labels, degree, n,
                    reinterpret_cast<unsigned long long *>(volume));

@@ -94,6 +94,25 @@ def test_community_validation_and_workspace():
                                   C.c_void_p(256), C.c_void_p(512), need - 1, None) == -3
 
 
+def test_community_resume_validation():
+    """Rejected before any HIP call: a pass count outside [1, passes), a null or aliased
+    saved state, and the arguments bgv_community rejects."""
+    p = L.CdParams(16, 3, 2, 0, 4096)
+    one, two = C.c_void_p(256), C.c_void_p(512)
+    ws = 1 << 30
+    for done in (0, 3, -2):
+        assert L.bgv_community_resume(10, 5, one, C.byref(p), done, one, two, one, None, one, ws, None) == -1
+    assert L.bgv_community_resume(10, 5, one, C.byref(p), 1, None, two, one, None, one, ws, None) == -1
+    assert L.bgv_community_resume(10, 5, one, C.byref(p), 1, two, two, one, None, one, ws, None) == -1  # aliased
+    assert L.bgv_community_resume(0, 5, one, C.byref(p), 1, one, two, one, None, one, ws, None) == -1
+    assert L.bgv_community_resume(10, 5, one, None, 1, one, two, one, None, one, ws, None) == -1
+    one_pass = L.CdParams(16, 1, 2, 0, 4096)  # nothing to resume
+    assert L.bgv_community_resume(10, 5, one, C.byref(one_pass), 1, one, two, one, None, one, ws, None) == -1
+    # the workspace is bgv_community's
+    need = L.bgv_community_workspace(10, 5, C.byref(p))
+    assert L.bgv_community_resume(10, 5, one, C.byref(p), 1, one, two, one, None, one, need - 1, None) == -3
+
+
 def test_supergraph_validation():
     import numpy as np
     coef = np.zeros((8, 3), np.uint64)

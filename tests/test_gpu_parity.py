@@ -493,11 +493,12 @@ def test_fa2_weights_and_masses(bgv, planted_sg):
     assert worst <= TOL
 
 
-@pytest.mark.parametrize("K", [512, 513, 1300, 9000])
+@pytest.mark.parametrize("K", [512, 513, 1300, 9000, 50_000])
 def test_fa2_exact_segmented_repulsion(bgv, K):
     """Bodies beyond one repulsion segment (512): the sum is split over workgroups and
     recombined in segment order; one step must still match the oracle, and the result
-    must not depend on anything but the inputs (two runs, same bits)."""
+    must not depend on anything but the inputs (two runs, same bits).  50,000 bodies is
+    the size of the gradient workload's supergraph (98 segments)."""
     rng = np.random.default_rng(K)
     pos0 = rng.uniform(-10, 10, (K, 2)).astype(np.float32)
     pos0[7] = pos0[3]  # coincident bodies
