@@ -11,7 +11,8 @@
  *     data_ptr()); pointers marked "host" are host memory.  Every buffer is owned by
  *     the caller and is never freed or reallocated by the library.
  *   - Scratch memory comes only from the caller's workspace `ws` (dev), at least the
- *     size returned by the matching *_workspace() query, 256-byte aligned.  The
+ *     size returned by the matching *_workspace() query, 256-byte aligned, except for
+ *     bgv_fa2_layout_static, which uses a fixed device array of the library.  The
  *     library itself never calls hipMalloc.
  *   - Work is enqueued on `stream` and is asynchronous, except where an entry point
  *     says it synchronises.  Calls on distinct streams need distinct workspaces.
@@ -255,6 +256,26 @@ size_t bgv_fa2_workspace(int32_t K, int64_t E, const bgv_fa2_params *p);
 bgv_status bgv_fa2_layout(int32_t K, int64_t E, const int32_t *edges, const float *attr_w,
                           const float *mass, float *pos, float *fprev, float *speed,
                           const bgv_fa2_params *p, void *ws, size_t ws_bytes, bgv_stream_t stream);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, hosts that forbid hipMalloc): bgv_fa2_layout with the same arguments
+ * (less the workspace), kernels and results.  Scratch comes from a device array of
+ * BGV_FA2_STATIC_SCRATCH_BYTES (64 MiB) inside the library, one copy per GPU, held
+ * until the process ends; the call itself allocates nothing.  A call whose
+ * bgv_fa2_workspace(K, E, p) exceeds that size returns BGV_E_INVALID and touches no
+ * device memory (Barnes-Hut: K = 65,536 fits up to about 890,000 edges, K = 131,072 up
+ * to about 750,000; exact: K = 16,384 up to about 960,000 edges, K = 65,536 never).
+ * Every call on one GPU shares that GPU's array: calls that overlap in time on one GPU
+ * (different streams, or host threads without an order between them) race and give
+ * undefined results; calls queued on one stream are ordered.  The array keeps the last
+ * call's contents; each call initialises what it reads.  The first call on each device
+ * looks up the array's address (hipGetSymbolAddress, not a stream operation).
+ */
+#define BGV_FA2_STATIC_SCRATCH_BYTES (64u << 20)
+bgv_status bgv_fa2_layout_static(int32_t K, int64_t E, const int32_t *edges, const float *attr_w,
+                                 const float *mass, float *pos, float *fprev, float *speed,
+                                 const bgv_fa2_params *p, bgv_stream_t stream);
 
 /*
  * ForceAtlas2 energy, whose negative gradient is the force field above (exact

@@ -63,6 +63,8 @@ bgv_supergraph = _sig("bgv_supergraph", i32, [i32, i64, P, P, P, C.POINTER(Sketc
                                               C.POINTER(i64), P, P, P, P, P, P, P, P, P, SZ, P])
 bgv_fa2_workspace = _sig("bgv_fa2_workspace", SZ, [i32, i64, C.POINTER(Fa2Params)])
 bgv_fa2_layout = _sig("bgv_fa2_layout", i32, [i32, i64, P, P, P, P, P, P, C.POINTER(Fa2Params), P, SZ, P])
+bgv_fa2_layout_static = _sig("bgv_fa2_layout_static", i32, [i32, i64, P, P, P, P, P, P, C.POINTER(Fa2Params), P])
+BGV_FA2_STATIC_SCRATCH_BYTES = 64 << 20
 bgv_fa2_energy_workspace = _sig("bgv_fa2_energy_workspace", SZ, [i32, i64])
 bgv_fa2_energy = _sig("bgv_fa2_energy", i32, [i32, i64, P, P, P, P, f32, f32, P, P, SZ, P])
 bgv_fa2_grad = _sig("bgv_fa2_grad", i32, [i32, i64, P, P, P, P, f32, f32, P, P, P, SZ, P])
@@ -80,7 +82,7 @@ bgv_bh_tree = _sig("bgv_bh_tree", i32, [i32, P, P, P, P, P, P, P, P, SZ, P])
 
 EXPORTED = ["bgv_status_string", "bgv_last_error", "bgv_community_workspace", "bgv_community",
             "bgv_community_passes", "bgv_community_resume",
-            "bgv_supergraph_workspace", "bgv_supergraph", "bgv_fa2_workspace", "bgv_fa2_layout",
+            "bgv_supergraph_workspace", "bgv_supergraph", "bgv_fa2_workspace", "bgv_fa2_layout", "bgv_fa2_layout_static",
             "bgv_fa2_energy_workspace", "bgv_fa2_energy", "bgv_fa2_grad",
             "bgv_profile_enable", "bgv_profile_filter", "bgv_profile_sample", "bgv_profile_reset", "bgv_profile_count", "bgv_profile_get",
             "bgv_profile_counter", "bgv_batched_workspace", "bgv_batched", "bgv_draw_workspace",

@@ -259,6 +259,28 @@ def fa2_layout(superedges: torch.Tensor, pos: torch.Tensor, iters: int, exact: b
     return pos, fprev, speed
 
 
+def fa2_layout_static(superedges: torch.Tensor, pos: torch.Tensor, fprev: torch.Tensor, speed: torch.Tensor,
+                      iters: int, exact: bool = True, theta: float = 1.2, kr: float = 1.0, kg: float = 1.0,
+                      tau: float = 1.0, ks: float = 0.1, ksmax: float = 10.0,
+                      attr_w: torch.Tensor | None = None, mass: torch.Tensor | None = None, stream=None):
+    """fa2_layout without a workspace and without allocating: the library's fixed
+    per-device scratch array serves instead (bgv_fa2_layout_static).  pos, fprev and
+    speed are updated in place; calls that overlap on one GPU race."""
+    K = pos.shape[0]
+    E = superedges.shape[0]
+    _need(pos, torch.float32, "pos", (K, 2))
+    _need(superedges, torch.int32, "superedges", (E, 2))
+    _need(fprev, torch.float32, "fprev", (K, 2))
+    _need(speed, torch.float32, "speed", (1,))
+    if attr_w is not None:
+        _need(attr_w, torch.float32, "attr_w", (E,))
+    if mass is not None:
+        _need(mass, torch.float32, "mass", (K,))
+    p = fa2_params(iters, exact, theta, kr, kg, tau, ks, ksmax)
+    L.check(L.bgv_fa2_layout_static(int(K), int(E), _ptr(superedges), _ptr(attr_w), _ptr(mass), _ptr(pos),
+                                    _ptr(fprev), _ptr(speed), C.byref(p), _stream(stream)), "bgv_fa2_layout_static")
+    return pos, fprev, speed
+
 
 def fa2_energy(superedges: torch.Tensor, pos: torch.Tensor, kr: float = 1.0, kg: float = 1.0,
                attr_w: torch.Tensor | None = None, mass: torch.Tensor | None = None, ws=None, stream=None):

@@ -17,7 +17,7 @@ LIB = os.path.join(PKG, "libbgv.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
 SOURCES = ["primitives.hip", "profile.hip", "community.hip", "supergraph.hip", "fa2.hip", "energy.hip",
-           "batched.hip", "draw.hip", "community_jump.hip", "check.hip"]
+           "batched.hip", "draw.hip", "community_jump.hip", "check.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -149,6 +149,23 @@ def test_fa2_validation():
     assert L.bgv_fa2_grad(10, 0, None, None, None, one, 1.0, 1.0, None, None, one, 1 << 20, None) == -1
 
 
+def test_fa2_layout_static_validation():
+    """The allocation-free layout rejects, before any HIP call, what bgv_fa2_layout
+    rejects and any size whose workspace would exceed its fixed scratch array."""
+    ok = L.Fa2Params(10, 0, 1.2, 1.0, 1.0, 1.0, 0.1, 10.0)
+    one = C.c_void_p(256)
+    assert L.bgv_fa2_layout_static(0, 3, one, None, None, one, one, one, C.byref(ok), None) == -1
+    assert L.bgv_fa2_layout_static(10, 3, one, None, None, None, one, one, C.byref(ok), None) == -1
+    assert L.bgv_fa2_layout_static(10, 3, None, None, None, one, one, one, C.byref(ok), None) == -1
+    bad = L.Fa2Params(10, 2, 1.2, 1.0, 1.0, 1.0, 0.1, 10.0)
+    assert L.bgv_fa2_layout_static(10, 3, one, None, None, one, one, one, C.byref(bad), None) == -1
+    K, E = 65_536, 2_000_000
+    assert L.bgv_fa2_workspace(K, E, C.byref(ok)) > L.BGV_FA2_STATIC_SCRATCH_BYTES
+    assert L.bgv_fa2_layout_static(K, E, one, None, None, one, one, one, C.byref(ok), None) == -1
+    assert b"more than" in L.bgv_last_error()
+    assert L.bgv_fa2_workspace(65_536, 800_000, C.byref(ok)) <= L.BGV_FA2_STATIC_SCRATCH_BYTES
+
+
 def test_batched_validation():
     """Rejected on the host before any HIP call: community options the batched form
     does not run (volume rule, back-pointer method, tie values other than 0/1), layout
