@@ -47,6 +47,9 @@ def parse():
                          "comparisons")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="do not time launches with HIP events (for hardware-counter runs)")
+    ap.add_argument("--fa2-iters", type=int, default=None, metavar="N",
+                    help="lay the supergraph out for N iterations instead of the workload's (hardware-counter runs "
+                         "only: the per-launch counters need a few iterations; the line then names N)")
     ap.add_argument("--profile-sample", type=int, default=PROFILE_SAMPLE, metavar="N",
                     help="time one in N launches of the dominant kernel in the timed steps")
     ap.add_argument("--form", default=None, choices=sorted(FORMS),
@@ -89,6 +92,8 @@ def main():
         return
 
     wl = dict(graphgen.WORKLOADS[args.workload], name=args.workload)
+    if args.fa2_iters is not None:
+        wl["fa2_iters"] = args.fa2_iters
     n = wl["n"]
     t0 = time.time()
     edges_np, _ = graphgen.make_graph(args.workload)
@@ -164,6 +169,7 @@ def main():
     prof.sample(1)
     kstats = prof.stats()
     inter = prof.counter("bh_interactions")
+    redo = prof.counter("bh_redo_blocks")
     # the counter covers every force launch of the timed steps, timed or not
     inter_per_launch = inter / (args.steps * wl["fa2_iters"]) if inter and not wl["exact"] else None
     for k in kstats:
@@ -215,6 +221,8 @@ def main():
                                                  if extra.get("roofline_edge_stream", {}).get("community_passes")
                                                  else None),
                   "bh_interactions_per_iteration": inter_per_launch,
+                  "bh_force_blocks_redone_per_iteration": (redo / (args.steps * wl["fa2_iters"])
+                                                           if redo is not None and not wl["exact"] else None),
                   "bh_interactions_per_s": (inter_per_launch * wl["fa2_iters"] / (fa_unprofiled / 1000.0)
                                             if inter_per_launch else None)},
         "roofline": roofline,
@@ -590,15 +598,17 @@ def kernel_model(name, K, E, inter_per_launch=None):
         return "alu", BH_INTERACTION_FLOPS * inter_per_launch, "flop"
     if name in CSR_ENTRY_BYTES:  # CSR entries + row offsets, own and neighbour positions, result
         return "hbm", CSR_ENTRY_BYTES[name] * 2 * E + 28 * K, "byte"
-    per_body = {"rs_downsweep_small": 16,          # Morton sort pass: 32-bit code and index read + written
-                "rs_upsweep_small": 4,              # code read
+    per_body = {"os_pass<4>": 16,                  # Morton sort pass: 32-bit code and index read + written
+                "os_pass<16>": 16,
+                "rs_downsweep_small": 16,
                 "bh_codes": 20,                     # position read, key and index written
-                "bh_codes_count<4>": 20,            # the same, with the first digit count in LDS
-                "bh_codes_count<16>": 20,
+                "bh_codes_os<4>": 20,               # the same, with the sort's digit counts in LDS
+                "bh_codes_os<16>": 20,
                 "bh_gather": 44,                    # key, index, position, mass read; body and code written
                 "bh_prefix": 40,                    # body read; three FP64 prefix sums written
                 "bh_build": 60,                     # codes and prefix sums read; node written
-                "update": 48}                       # position, force, previous force read; two written
+                "bh_update": 40,                    # position, force, previous force read; two written
+                "update": 48}                       # the same plus the block partials (exact path)
     if name in per_body:
         return "hbm", per_body[name] * K, "byte"
     if name == "bh_build_att":  # tree build and attraction in one launch (unweighted CSR ids)

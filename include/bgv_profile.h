@@ -38,7 +38,9 @@ int bgv_profile_get(int idx, const char **name, int64_t *launches, double *total
 /* Device-side work counters accumulated while profiling is enabled (reset by
  * bgv_profile_reset).  "bh_interactions": number of Barnes-Hut force terms summed
  * (body-body pairs plus body-cell centre-of-mass terms) over all layout iterations.
- * Synchronises the device.  Returns 0, or -1 for an unknown name or a HIP error. */
+ * "bh_redo_blocks": Barnes-Hut force workgroups (8 bodies each) whose walk outgrew
+ * the short per-body stack of the first launch and were redone with the full one
+ * (counted whether or not profiling is enabled).  Synchronises the device.  Returns 0, or -1 for an unknown name or a HIP error. */
 int bgv_profile_counter(const char *name, uint64_t *value);
 
 #ifdef __cplusplus

@@ -349,6 +349,17 @@ __global__ void __launch_bounds__(kCdThreads) k_cd_step(const int32_t *__restric
 // round trips.
 constexpr int kCdResolveThreads = 1024;
 
+// Workgroups are dealt to the chip's eight XCDs (each with its own L2) in turn, so
+// workgroup x runs on XCD x mod 8.  Neighbouring buckets share cache lines of the
+// offset rows and of the grouped segments (a tile writes its buckets' segments one
+// after another), so the resolve gives each XCD a contiguous range of buckets: every
+// line is then fetched into one L2 instead of into all eight.
+constexpr int32_t kXcds = 8;
+inline int32_t cd_resolve_grid(int32_t nb) { return (nb + kXcds - 1) / kXcds * kXcds; }
+__device__ __forceinline__ int32_t cd_resolve_bucket(int32_t x, int32_t nb) {
+    return (x % kXcds) * ((nb + kXcds - 1) / kXcds) + x / kXcds;
+}
+
 inline int32_t cd_resolve_lanes(int32_t tiles) {
     int32_t g = 1;
     while (g < kCdResolveThreads && (int64_t)g * 2 * (tiles > 0 ? tiles : 1) <= kCdResolveThreads) g *= 2;
@@ -371,7 +382,8 @@ __global__ void __launch_bounds__(kCdResolveThreads) k_cd_resolve(int32_t *__res
                                                                    int32_t lanes) {
     __shared__ unsigned long long win[kCdBucket];
     __shared__ uint32_t inc[kCdBucket];
-    const int32_t b = blockIdx.x;
+    const int32_t b = cd_resolve_bucket((int32_t)blockIdx.x, nb);
+    if (b >= nb) return;  // the grid is rounded up to a multiple of the XCD count
     for (int32_t k = threadIdx.x; k < kCdBucket; k += kCdResolveThreads) {
         win[k] = ~0ull;
         inc[k] = 0u;
@@ -690,7 +702,7 @@ static bgv_status cd_run(int32_t n, int64_t m, const int32_t *edges, const bgv_c
                 const int32_t tiles = tiles_of(k);
                 // proposals of the previous chunk and, in pass 0, this chunk's increments
                 if (ptiles > 0 || etiles > 0)
-                    BGV_LAUNCH(k_cd_resolve, dim3(nb), dim3(kCdResolveThreads), 0, s, w.cnt, w.lab, n, nb, w.props, w.ptab,
+                    BGV_LAUNCH(k_cd_resolve, dim3(cd_resolve_grid(nb)), dim3(kCdResolveThreads), 0, s, w.cnt, w.lab, n, nb, w.props, w.ptab,
                                ptiles, w.ends, w.etab, etiles, cd_resolve_lanes(std::max(ptiles, etiles)));
                 // counters are incremented in pass 0 only (later passes use the closed form):
                 // the next chunk's endpoints are grouped by this launch in pass 0
@@ -716,7 +728,7 @@ static bgv_status cd_run(int32_t n, int64_t m, const int32_t *edges, const bgv_c
             }
             if (pass_labels) {
                 if (ptiles > 0)
-                    BGV_LAUNCH(k_cd_resolve, dim3(nb), dim3(kCdResolveThreads), 0, s, w.cnt, w.lab, n, nb, w.props,
+                    BGV_LAUNCH(k_cd_resolve, dim3(cd_resolve_grid(nb)), dim3(kCdResolveThreads), 0, s, w.cnt, w.lab, n, nb, w.props,
                                w.ptab, ptiles, w.ends, w.etab, 0, cd_resolve_lanes(ptiles));
                 ptiles = 0;
                 BGV_LAUNCH(k_cd_copy_labels, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, w.lab, 1,
@@ -724,7 +736,7 @@ static bgv_status cd_run(int32_t n, int64_t m, const int32_t *edges, const bgv_c
             }
         }
         if (ptiles > 0)
-            BGV_LAUNCH(k_cd_resolve, dim3(nb), dim3(kCdResolveThreads), 0, s, w.cnt, w.lab, n, nb, w.props, w.ptab, ptiles, w.ends,
+            BGV_LAUNCH(k_cd_resolve, dim3(cd_resolve_grid(nb)), dim3(kCdResolveThreads), 0, s, w.cnt, w.lab, n, nb, w.props, w.ptab, ptiles, w.ends,
                        w.etab, 0, cd_resolve_lanes(ptiles));
         BGV_LAUNCH(k_cd_finish_b, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, w.cnt, w.lab, n,
                    labels, degree, reinterpret_cast<unsigned long long *>(volume));

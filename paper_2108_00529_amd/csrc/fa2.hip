@@ -13,8 +13,10 @@
 //           difference of prefix sums over its body range, so no atomics; the
 //           attraction in the same launch) -> k_bh_force (traversal with a shared
 //           stack per body)
-//   both:   k_update        global speed from the partials (every block reduces them in
+//   exact:  k_update        global speed from the partials (every block reduces them in
 //                           the same order), local speeds, displacement
+//   BH:     k_bh_speed      global speed from the partials (one per 8 bodies) in one block
+//           k_bh_update     local speeds, displacement, bounding-box partials
 // No floating-point atomics anywhere: results are identical run to run.
 #include <cstring>
 
@@ -357,6 +359,66 @@ __global__ void __launch_bounds__(kFaThreads) k_update(int32_t K, float2 *__rest
 
 __global__ void k_copy_f32(const float *__restrict__ a, float *__restrict__ b) { *b = *a; }
 
+// Barnes-Hut iterations have one force partial per 8 bodies, too many for every update
+// block to reduce: one 1024-thread block reduces them (each thread its strided share in
+// ascending order, eight loads in flight; then the waves in order) ...
+constexpr int kBhSpeedThreads = 1024;
+
+// Also clears the force launch's redo count for the next iteration (adding it to a
+// running tally that the profiler can read).
+__device__ unsigned long long g_bh_redo_blocks;
+
+__global__ void __launch_bounds__(kBhSpeedThreads) k_bh_speed(const double2 *__restrict__ part, int32_t nparts,
+                                                               const float *__restrict__ speed_in,
+                                                               float *__restrict__ speed_out, float tau,
+                                                               uint32_t *__restrict__ redo) {
+    __shared__ double2 ws[kBhSpeedThreads / kWave];
+    double2 acc = make_double2(0.0, 0.0);
+    int32_t p = threadIdx.x;
+    for (; p + 7 * kBhSpeedThreads < nparts; p += 8 * kBhSpeedThreads) {
+        double2 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = part[p + u * kBhSpeedThreads];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            acc.x += v[u].x;
+            acc.y += v[u].y;
+        }
+    }
+    for (; p < nparts; p += kBhSpeedThreads) {
+        acc.x += part[p].x;
+        acc.y += part[p].y;
+    }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        acc.x += __shfl_down(acc.x, o, kWave);
+        acc.y += __shfl_down(acc.y, o, kWave);
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) ws[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double2 r = ws[0];
+        for (int q = 1; q < kBhSpeedThreads / kWave; ++q) {
+            r.x += ws[q].x;
+            r.y += ws[q].y;
+        }
+        *speed_out = fa2_global_speed(r.x, r.y, *speed_in, tau);
+        g_bh_redo_blocks += redo[0];
+        redo[0] = 0u;
+    }
+}
+
+// ... and the update blocks read the result; each writes the bounding box of the
+// positions it moved.
+__global__ void __launch_bounds__(kFaThreads) k_bh_update(int32_t K, float2 *__restrict__ pos,
+                                                           float2 *__restrict__ fprev, const float2 *__restrict__ F,
+                                                           const float *__restrict__ speed, float ks, float ksmax,
+                                                           float4 *__restrict__ bbox_part) {
+    float4 bb = fa2_move_tile((int32_t)blockIdx.x, (int32_t)gridDim.x, K, pos, fprev, F, *speed, ks, ksmax);
+    bb = block_bbox(bb);
+    if (threadIdx.x == 0) bbox_part[blockIdx.x] = bb;
+}
+
 // ------------------------------------------------------------------ Barnes-Hut --
 // One bounding-box partial per block of kFaThreads positions (same grid as k_update).
 __global__ void __launch_bounds__(kFaThreads) k_bh_bbox(int32_t K, const float2 *__restrict__ pos,
@@ -421,23 +483,25 @@ __global__ void __launch_bounds__(kFaThreads) k_bh_codes(int32_t K, const float2
     }
 }
 
-// The codes and the sort's first digit count in one launch (sorts on the few-tile
-// path): workgroup t encodes the bodies of sort tile t (256 * ITEMS consecutive ones),
-// counts their low 8 bits in LDS into counts0[digit * tiles + t] and clears its part of
-// the count buffer of the next pass.
+// The codes and the one-sweep sort's counts in one launch: workgroup t encodes the
+// bodies of sort tile t (256 * ITEMS consecutive ones), counts the four 8-bit digits
+// of their codes in LDS into counts[t*1024 + pass*256 + d], and clears its share
+// of the sort's look-back words.
 template <int ITEMS>
-__global__ void __launch_bounds__(kFaThreads) k_bh_codes_count(int32_t K, const float2 *__restrict__ pos,
-                                                                const float4 *__restrict__ part, int nparts,
-                                                                uint32_t *__restrict__ keys,
-                                                                uint32_t *__restrict__ vals,
-                                                                float *__restrict__ s0_out,
-                                                                uint32_t *__restrict__ counts0,
-                                                                uint32_t *__restrict__ clear1, int64_t tiles) {
-    __shared__ uint32_t hist[256];
+__global__ void __launch_bounds__(kFaThreads) k_bh_codes_os(int32_t K, const float2 *__restrict__ pos,
+                                                             const float4 *__restrict__ part, int nparts,
+                                                             uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                                                             float *__restrict__ s0_out,
+                                                             uint32_t *__restrict__ counts,
+                                                             uint32_t *__restrict__ status, int64_t status_words) {
+    __shared__ uint32_t hist[4][256];
     float xmin, ymin, s0;
     bh_frame(part, nparts, &xmin, &ymin, &s0, s0_out);
-    hist[threadIdx.x] = 0u;
-    clear1[(int64_t)blockIdx.x * 256 + threadIdx.x] = 0u;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) hist[q][threadIdx.x] = 0u;
+    for (int64_t i = (int64_t)blockIdx.x * kFaThreads + threadIdx.x; i < status_words;
+         i += (int64_t)gridDim.x * kFaThreads)
+        status[i] = 0u;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * (kFaThreads * ITEMS);
 #pragma unroll
@@ -447,11 +511,13 @@ __global__ void __launch_bounds__(kFaThreads) k_bh_codes_count(int32_t K, const 
             const uint32_t c = bh_morton(pos[i], xmin, ymin, s0);
             keys[i] = c;
             vals[i] = (uint32_t)i;
-            atomicAdd(&hist[c & 255u], 1u);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) atomicAdd(&hist[q][(c >> (8 * q)) & 255u], 1u);
         }
     }
     __syncthreads();
-    counts0[(int64_t)threadIdx.x * tiles + blockIdx.x] = hist[threadIdx.x];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) counts[(int64_t)blockIdx.x * 1024 + q * 256 + threadIdx.x] = hist[q][threadIdx.x];
 }
 
 // Bodies [256 g, 256 g + 256) in Morton order (one per thread) and the group totals of
@@ -667,20 +733,21 @@ constexpr int kBhLanes = 8;  // lanes per body (16 and 32 measured slower on the
 // depends only on G and the tree: results are identical run to run.
 constexpr int kBhTreeLevels = 34;  // 32-bit Morton codes: root, 32 prefix lengths, equal-code cells
 
-template <int G>
-__global__ void __launch_bounds__(kBhThreads) k_bh_force(int32_t K, const float4 *__restrict__ body,
-                                                          const float4 *__restrict__ nodeA,
-                                                          const int4 *__restrict__ nodeB, float theta2,
-                                                          const float2 *__restrict__ att,
-                                                          const uint32_t *__restrict__ item_of, float kr, float kg,
-                                                          const float2 *__restrict__ fprev, float2 *__restrict__ F,
-                                                          double2 *__restrict__ part,
-                                                          uint32_t *__restrict__ icount) {
+// One force workgroup's bodies (block `blk`) with a stack of C entries per body.  A step
+// whose pushes would not fit stops the body's walk and returns true (the caller then
+// redoes the whole workgroup with the full stack); otherwise the forces, the
+// workgroup's speed partial and its interaction tally are written and false returned.
+template <int G, int C>
+__device__ __forceinline__ bool bh_force_block(int32_t blk, int32_t K, const float4 *__restrict__ body,
+                                               const float4 *__restrict__ nodeA, const int4 *__restrict__ nodeB,
+                                               float theta2, const float2 *__restrict__ att,
+                                               const uint32_t *__restrict__ item_of, float kr, float kg,
+                                               const float2 *__restrict__ fprev, float2 *__restrict__ F,
+                                               double2 *__restrict__ part, uint32_t *__restrict__ icount) {
     static_assert(G >= 2 && G <= kWave && (G & (G - 1)) == 0, "lanes per body: power of two in [2, 64]");
     constexpr int kGroups = kBhThreads / G;
-    constexpr int kDepth = 2 * G * kBhTreeLevels;
-    __shared__ int stk[kGroups][kDepth];
-    const int64_t tid = (int64_t)blockIdx.x * kBhThreads + threadIdx.x;
+    __shared__ int stk[kGroups][C];
+    const int64_t tid = (int64_t)blk * kBhThreads + threadIdx.x;
     const int32_t r = (int32_t)(tid / G);
     const int L = (int)(tid % G);
     int *st_g = stk[threadIdx.x / G];
@@ -689,6 +756,7 @@ __global__ void __launch_bounds__(kBhThreads) k_bh_force(int32_t K, const float4
     uint32_t ic = 0;
     float4 me = make_float4(0.f, 0.f, 0.f, 0.f);
     int size = 0;
+    bool overflow = false;
     if (r < K) {
         me = body[r];
         if (K > 1) size = 1;
@@ -742,13 +810,19 @@ __global__ void __launch_bounds__(kBhThreads) k_bh_force(int32_t K, const float4
             if (L + o < G) incl += v;
         }
         const int total = __shfl(incl, 0, G);
-        if (np) {
-            const int at = size + incl - np;  // this lane's two slots: at, at + 1 (< kDepth, see above)
-            st_g[at] = c_right;
-            st_g[at + 1] = c_left;  // left on top: popped first
+        if (size + total > C) {  // uniform over the body's lanes
+            overflow = true;
+            size = 0;
+        } else {
+            if (np) {
+                const int at = size + incl - np;  // this lane's two slots: at, at + 1
+                st_g[at] = c_right;
+                st_g[at + 1] = c_left;  // left on top: popped first
+            }
+            size += total;
         }
-        size += total;
     }
+    if (__any(overflow)) return true;  // uniform: the workgroup is one wavefront
 #pragma unroll
     for (int o = G / 2; o > 0; o >>= 1) {
         fx += __shfl_xor(fx, o, kWave);
@@ -765,9 +839,52 @@ __global__ void __launch_bounds__(kBhThreads) k_bh_force(int32_t K, const float4
     for (int o = kWave / 2; o > 0; o >>= 1) ic += __shfl_xor(ic, o, kWave);
     st = block_sum2(st);
     if (threadIdx.x == 0) {
-        part[blockIdx.x] = st;
-        icount[blockIdx.x] += ic;
+        part[blk] = st;
+        icount[blk] += ic;
     }
+    return false;
+}
+
+// The full stack: at most 2G entries of one depth (see above) on at most kBhTreeLevels
+// depths.  The fast launch gives each body kBhFastStack entries, so that several times
+// more wavefronts fit a compute unit's LDS; a workgroup whose walk would not fit
+// appends itself to a list, and k_bh_force_full redoes it with the full stack (the same
+// steps, so the same bits: results never depend on the capacity).
+template <int G>
+struct BhStack {
+    static constexpr int kFull = 2 * G * kBhTreeLevels;
+    static constexpr int kFast = 160;
+};
+
+template <int G>
+__global__ void __launch_bounds__(kBhThreads) k_bh_force(int32_t K, const float4 *__restrict__ body,
+                                                          const float4 *__restrict__ nodeA,
+                                                          const int4 *__restrict__ nodeB, float theta2,
+                                                          const float2 *__restrict__ att,
+                                                          const uint32_t *__restrict__ item_of, float kr, float kg,
+                                                          const float2 *__restrict__ fprev, float2 *__restrict__ F,
+                                                          double2 *__restrict__ part, uint32_t *__restrict__ icount,
+                                                          uint32_t *__restrict__ redo) {
+    const bool ovf = bh_force_block<G, BhStack<G>::kFast>((int32_t)blockIdx.x, K, body, nodeA, nodeB, theta2, att,
+                                                           item_of, kr, kg, fprev, F, part, icount);
+    if (ovf && threadIdx.x == 0) redo[1 + atomicAdd(&redo[0], 1u)] = blockIdx.x;
+}
+
+// The listed workgroups again with the full stack; redo[0] counts them.
+template <int G>
+__global__ void __launch_bounds__(kBhThreads) k_bh_force_full(int32_t K, const float4 *__restrict__ body,
+                                                               const float4 *__restrict__ nodeA,
+                                                               const int4 *__restrict__ nodeB, float theta2,
+                                                               const float2 *__restrict__ att,
+                                                               const uint32_t *__restrict__ item_of, float kr,
+                                                               float kg, const float2 *__restrict__ fprev,
+                                                               float2 *__restrict__ F, double2 *__restrict__ part,
+                                                               uint32_t *__restrict__ icount,
+                                                               const uint32_t *__restrict__ redo) {
+    const uint32_t n = redo[0];
+    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x)
+        bh_force_block<G, BhStack<G>::kFull>((int32_t)redo[1 + i], K, body, nodeA, nodeB, theta2, att, item_of, kr,
+                                             kg, fprev, F, part, icount);
 }
 
 static_assert(kBhThreads == kWave, "the interaction tally reduces over one wavefront per workgroup");
@@ -784,9 +901,14 @@ __global__ void __launch_bounds__(kFaThreads) k_count_total(const uint32_t *__re
 }
 
 int prof_read_counter(const char *name, uint64_t *value) {
-    if (std::strcmp(name, "bh_interactions") != 0) return -1;
     unsigned long long v = 0;
-    if (hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_bh_interactions), sizeof v) != hipSuccess) return -1;
+    if (std::strcmp(name, "bh_interactions") == 0) {
+        if (hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_bh_interactions), sizeof v) != hipSuccess) return -1;
+    } else if (std::strcmp(name, "bh_redo_blocks") == 0) {
+        if (hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_bh_redo_blocks), sizeof v) != hipSuccess) return -1;
+    } else {
+        return -1;
+    }
     *value = v;
     return 0;
 }
@@ -794,10 +916,20 @@ int prof_read_counter(const char *name, uint64_t *value) {
 void prof_reset_counters() {
     const unsigned long long z = 0;
     (void)hipMemcpyToSymbol(HIP_SYMBOL(g_bh_interactions), &z, sizeof z);
+    (void)hipMemcpyToSymbol(HIP_SYMBOL(g_bh_redo_blocks), &z, sizeof z);
 }
 
 static int32_t bh_force_blocks(int32_t K) {
     return (int32_t)(((int64_t)K * kBhLanes + kBhThreads - 1) / kBhThreads);
+}
+constexpr int kBhFullBlocks = 64;  // workgroups of the full-stack redo launch (grid-stride over its list)
+
+// Blocks of the Barnes-Hut update, and so the number of bounding-box partials the next
+// tree build reduces (min/max, so any count gives the same box).
+constexpr int32_t kBhUpdateMaxBlocks = 256;
+static int32_t bh_update_blocks(int32_t K) {
+    const int32_t nb = (K + kFaThreads - 1) / kFaThreads;
+    return nb < kBhUpdateMaxBlocks ? nb : kBhUpdateMaxBlocks;
 }
 
 struct BhWs {
@@ -811,6 +943,7 @@ struct BhWs {
     float4 *nodeA;
     int4 *nodeB;
     uint32_t *icount;  // interactions per force workgroup, summed over the call's iterations
+    uint32_t *redo;    // [0]: force workgroups to redo with the full stack, [1..]: their ids
     void *sort_scratch;
 };
 
@@ -851,7 +984,8 @@ static size_t fa_layout(Carver &c, int32_t K, int64_t E, const bgv_fa2_params *p
         b.nodeA = c.take<float4>((size_t)K);
         b.nodeB = c.take<int4>((size_t)K);
         b.icount = c.take<uint32_t>((size_t)bh_force_blocks(K));
-        b.sort_scratch = c.take<char>(radix_workspace(K));
+        b.redo = c.take<uint32_t>((size_t)bh_force_blocks(K) + 1);
+        b.sort_scratch = c.take<char>(onesweep_workspace(K));
     }
     return c.size();
 }
@@ -887,32 +1021,26 @@ static bgv_status build_attract(int32_t K, const BhWs &b, unsigned att_blocks, s
 // FP64 prefix sums of their mass moments: everything the node build reads.
 static bgv_status bh_sorted_bodies(int32_t K, const float2 *pos, const float *mass, BhWs &b, hipStream_t s) {
     const unsigned nb = (unsigned)((K + kFaThreads - 1) / kFaThreads);
-    // b.bbox holds one box per block of positions (written by k_bh_bbox before the first
-    // iteration and by k_update after each one)
+    // b.bbox holds one box per update block (written by k_bh_bbox before the first
+    // iteration and by k_bh_update after each one)
+    const int nbox = bh_update_blocks(K);
     // 32-bit Morton codes, sorted as 32-bit keys (the index buffers hold them)
     uint32_t *keys = reinterpret_cast<uint32_t *>(b.keys), *keys_alt = reinterpret_cast<uint32_t *>(b.keys_alt);
-    uint32_t *sk;
-    uint32_t *sv;
-    int64_t tiles;
-    int items;
-    if (radix_few_tiles(K, &tiles, &items)) {
-        uint32_t *counts0, *clear1;
-        radix_pass0_buffers(b.sort_scratch, K, &counts0, &clear1);
-        if (items == 4)
-            BGV_LAUNCH(k_bh_codes_count<4>, dim3((unsigned)tiles), dim3(kFaThreads), 0, s, K, pos, b.bbox, (int)nb,
-                       keys, b.vals, b.s0, counts0, clear1, tiles);
-        else if (items == 16)
-            BGV_LAUNCH(k_bh_codes_count<16>, dim3((unsigned)tiles), dim3(kFaThreads), 0, s, K, pos, b.bbox, (int)nb,
-                       keys, b.vals, b.s0, counts0, clear1, tiles);
-        else {
-            set_error("bh_forces: unexpected sort tile shape (%d keys per thread)", items);
-            return BGV_E_INVALID;
-        }
-        BGV_TRY(radix_sort_u32(keys, keys_alt, b.vals, b.vals_alt, K, 32, &sk, &sv, b.sort_scratch, s, true));
+    uint32_t *sk = keys;
+    uint32_t *sv = b.vals;
+    if (K > 1) {
+        // codes and the sort's digit counts in one launch, then the one-sweep passes
+        OsBuffers ob;
+        onesweep_layout(b.sort_scratch, K, os_items(K), &ob);
+        if (ob.items == 4)
+            BGV_LAUNCH(k_bh_codes_os<4>, dim3((unsigned)ob.tiles), dim3(kFaThreads), 0, s, K, pos, b.bbox, nbox, keys,
+                       b.vals, b.s0, ob.counts, ob.status, ob.status_words);
+        else
+            BGV_LAUNCH(k_bh_codes_os<16>, dim3((unsigned)ob.tiles), dim3(kFaThreads), 0, s, K, pos, b.bbox, nbox, keys,
+                       b.vals, b.s0, ob.counts, ob.status, ob.status_words);
+        BGV_TRY(onesweep_sort_u32(keys, keys_alt, b.vals, b.vals_alt, K, &sk, &sv, b.sort_scratch, s, true));
     } else {
-        BGV_LAUNCH(k_bh_codes, dim3(grid_for(K, kFaThreads, 4096)), dim3(kFaThreads), 0, s, K, pos, b.bbox,
-                   (int)nb, keys, b.vals, b.s0);
-        BGV_TRY(radix_sort_u32(keys, keys_alt, b.vals, b.vals_alt, K, 32, &sk, &sv, b.sort_scratch, s));
+        BGV_LAUNCH(k_bh_codes, dim3(1), dim3(kFaThreads), 0, s, K, pos, b.bbox, nbox, keys, b.vals, b.s0);
     }
     BGV_LAUNCH(k_bh_gather, dim3(nb), dim3(kFaThreads), 0, s, K, pos, mass, sk, sv, b.body, b.code, b.part3);
     BGV_LAUNCH(k_bh_prefix, dim3(nb), dim3(kFaThreads), 0, s, K, b.body, b.part3, b.PM, b.PX, b.PY);
@@ -939,7 +1067,9 @@ static bgv_status bh_forces(int32_t K, const float2 *pos, const float *mass, con
         BGV_TRY(attraction(K, pos, csr, w.A, s));
     }
     BGV_LAUNCH(k_bh_force<kBhLanes>, dim3(bh_force_blocks(K)), dim3(kBhThreads), 0, s, K, b.body, b.nodeA,
-               b.nodeB, theta * theta, w.A, csr.item_of, kr, kg, fprev, w.F, w.part, b.icount);
+               b.nodeB, theta * theta, w.A, csr.item_of, kr, kg, fprev, w.F, w.part, b.icount, b.redo);
+    BGV_LAUNCH(k_bh_force_full<kBhLanes>, dim3(kBhFullBlocks), dim3(kBhThreads), 0, s, K, b.body, b.nodeA, b.nodeB,
+               theta * theta, w.A, csr.item_of, kr, kg, fprev, w.F, w.part, b.icount, b.redo);
     return BGV_OK;
 }
 
@@ -976,6 +1106,7 @@ extern "C" bgv_status bgv_fa2_layout(int32_t K, int64_t E, const int32_t *edges,
     BGV_TRY(build_csr(K, E, edges, attr_w, mass, w.csr, s, &m));
     if (!p->exact) {
         BGV_TRY(fill<uint32_t>(w.bh.icount, 0u, bh_force_blocks(K), s));
+        BGV_TRY(fill<uint32_t>(w.bh.redo, 0u, 1, s));
     }
 
     float2 *x = reinterpret_cast<float2 *>(pos);
@@ -983,7 +1114,8 @@ extern "C" bgv_status bgv_fa2_layout(int32_t K, int64_t E, const int32_t *edges,
     const int32_t nb = (K + kFaThreads - 1) / kFaThreads;
     BGV_LAUNCH(k_copy_f32, dim3(1), dim3(1), 0, s, speed, w.speed);
     float4 *bbox = p->exact ? nullptr : w.bh.bbox;
-    if (bbox && p->iters > 0) BGV_LAUNCH(k_bh_bbox, dim3(nb), dim3(kFaThreads), 0, s, K, x, bbox);
+    if (bbox && p->iters > 0)
+        BGV_LAUNCH(k_bh_bbox, dim3(bh_update_blocks(K)), dim3(kFaThreads), 0, s, K, x, bbox);
     for (int32_t it = 0; it < p->iters; ++it) {
         if (p->exact) {
             BGV_TRY(attraction(K, x, w.csr, w.A, s));
@@ -992,8 +1124,15 @@ extern "C" bgv_status bgv_fa2_layout(int32_t K, int64_t E, const int32_t *edges,
             BGV_TRY(bh_forces(K, x, m, w.csr, p->theta, p->kr, p->kg, fp, w, s));  // attraction included
         }
         const int32_t nparts = p->exact ? nb : bh_force_blocks(K);
-        BGV_LAUNCH(k_update, dim3(nb), dim3(kFaThreads), 0, s, K, x, fp, w.F, w.part, nparts, w.speed + (it & 1),
-                   w.speed + ((it + 1) & 1), p->tau, p->ks, p->ksmax, bbox);
+        if (p->exact) {
+            BGV_LAUNCH(k_update, dim3(nb), dim3(kFaThreads), 0, s, K, x, fp, w.F, w.part, nparts, w.speed + (it & 1),
+                       w.speed + ((it + 1) & 1), p->tau, p->ks, p->ksmax, (float4 *)nullptr);
+        } else {
+            BGV_LAUNCH(k_bh_speed, dim3(1), dim3(kBhSpeedThreads), 0, s, w.part, nparts, w.speed + (it & 1),
+                       w.speed + ((it + 1) & 1), p->tau, w.bh.redo);
+            BGV_LAUNCH(k_bh_update, dim3(bh_update_blocks(K)), dim3(kFaThreads), 0, s, K, x, fp, w.F,
+                       w.speed + ((it + 1) & 1), p->ks, p->ksmax, bbox);
+        }
     }
     BGV_LAUNCH(k_copy_f32, dim3(1), dim3(1), 0, s, w.speed + (p->iters & 1), speed);
     if (!p->exact && p->iters > 0 && prof_on())
@@ -1030,7 +1169,7 @@ extern "C" bgv_status bgv_bh_tree(int32_t K, const float *pos, const float *mass
     BhWs &b = w.bh;
     const float2 *x = reinterpret_cast<const float2 *>(pos);
     const unsigned nb = (unsigned)((K + kFaThreads - 1) / kFaThreads);
-    BGV_LAUNCH(k_bh_bbox, dim3(nb), dim3(kFaThreads), 0, s, K, x, b.bbox);
+    BGV_LAUNCH(k_bh_bbox, dim3(bh_update_blocks(K)), dim3(kFaThreads), 0, s, K, x, b.bbox);
     BGV_TRY(bh_sorted_bodies(K, x, mass, b, s));
     if (K > 1)
         BGV_LAUNCH(k_bh_build, dim3(grid_for(K - 1, kFaThreads, 65536)), dim3(kFaThreads), 0, s, K, b.code, b.PM,

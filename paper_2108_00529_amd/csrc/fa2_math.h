@@ -285,11 +285,10 @@ __device__ __forceinline__ void fa2_combine_tile(int32_t bx, int32_t K, int32_t 
 // Global speed from part[0, nparts) (every tile reduces them in the same order; tile 0
 // stores it), then local speeds and displacement of the nodes bx*256 + t + q*stride.
 // Returns the thread's bounding box (xmin, xmax, ymin, ymax) of the moved positions.
-__device__ __forceinline__ float4 fa2_update_tile(int32_t bx, int32_t stride, int32_t K, float2 *__restrict__ pos,
-                                                  float2 *__restrict__ fprev, const float2 *__restrict__ F,
-                                                  const double2 *__restrict__ part, int32_t nparts,
-                                                  const float *__restrict__ speed_in, float *__restrict__ speed_out,
-                                                  float tau, float ks, float ksmax) {
+// The global speed from part[0, nparts) by one 256-thread block (fixed order); every
+// thread gets it.
+__device__ __forceinline__ float fa2_speed_of_parts(const double2 *__restrict__ part, int32_t nparts,
+                                                    const float *__restrict__ speed_in, float tau) {
     __shared__ float s_speed;
     __shared__ double2 ws[kFa2Tile / kWave];
     double2 acc = make_double2(0.0, 0.0);
@@ -298,13 +297,16 @@ __device__ __forceinline__ float4 fa2_update_tile(int32_t bx, int32_t stride, in
         acc.y += part[p].y;
     }
     acc = fa2_sum256(acc, ws);
-    if (threadIdx.x == 0) {
-        const float s = fa2_global_speed(acc.x, acc.y, *speed_in, tau);
-        s_speed = s;
-        if (bx == 0) *speed_out = s;
-    }
+    if (threadIdx.x == 0) s_speed = fa2_global_speed(acc.x, acc.y, *speed_in, tau);
     __syncthreads();
-    const float s = s_speed;
+    return s_speed;
+}
+
+// Local speeds and displacement, at global speed s, of the nodes bx*256 + t + q*stride;
+// returns the thread's bounding box (xmin, xmax, ymin, ymax) of the moved positions.
+__device__ __forceinline__ float4 fa2_move_tile(int32_t bx, int32_t stride, int32_t K, float2 *__restrict__ pos,
+                                                float2 *__restrict__ fprev, const float2 *__restrict__ F, float s,
+                                                float ks, float ksmax) {
     const float inf = __builtin_huge_valf();
     float4 bb = make_float4(inf, -inf, inf, -inf);
     for (int32_t i = bx * kFa2Tile + threadIdx.x; i < K; i += stride * kFa2Tile) {
@@ -315,6 +317,16 @@ __device__ __forceinline__ float4 fa2_update_tile(int32_t bx, int32_t stride, in
         bb = make_float4(fminf(bb.x, p.x), fmaxf(bb.y, p.x), fminf(bb.z, p.y), fmaxf(bb.w, p.y));
     }
     return bb;
+}
+
+__device__ __forceinline__ float4 fa2_update_tile(int32_t bx, int32_t stride, int32_t K, float2 *__restrict__ pos,
+                                                  float2 *__restrict__ fprev, const float2 *__restrict__ F,
+                                                  const double2 *__restrict__ part, int32_t nparts,
+                                                  const float *__restrict__ speed_in, float *__restrict__ speed_out,
+                                                  float tau, float ks, float ksmax) {
+    const float s = fa2_speed_of_parts(part, nparts, speed_in, tau);
+    if (bx == 0 && threadIdx.x == 0) *speed_out = s;
+    return fa2_move_tile(bx, stride, K, pos, fprev, F, s, ks, ksmax);
 }
 
 }  // namespace bgv

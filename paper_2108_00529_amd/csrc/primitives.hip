@@ -403,6 +403,233 @@ bgv_status radix_sort_u32(uint32_t *keys, uint32_t *keys_alt, uint32_t *vals, ui
                                 n_dev);
 }
 
+// ----------------------------------------------------------- one-sweep radix sort ---
+// Stable LSD sort of 32-bit keys (with 32-bit values) in four 8-bit passes, one launch
+// per pass and no per-key device atomics.  Before the passes, every key's four digits
+// are counted per tile (os_count, or a producer of the keys doing the same) and the
+// digit bases over all keys are summed from those counts (k_os_bases).  In a pass each
+// tile takes its index in launch order from a counter (so every earlier tile has
+// started), ranks its keys by digit as the scatter above does, publishes its digit
+// counts, and finds how many keys of each digit precede it by walking back over the
+// published words of earlier tiles: a word holds either that tile's own count
+// (kOsAgg) or its inclusive prefix (kOsInc), so the walk adds counts until it meets an
+// inclusive prefix (decoupled look-back).  Tile 0 publishes its counts as inclusive, so
+// every walk ends; no tile waits on a later one.  The words and counters are cleared
+// by the counting launch.
+constexpr uint32_t kOsAgg = 1u << 30;
+constexpr uint32_t kOsInc = 2u << 30;
+constexpr uint32_t kOsCountMask = (1u << 30) - 1;
+constexpr int kOsPasses = 4;
+// A walk step waits for a word that an earlier, already started tile publishes right
+// after ranking its keys; the bound only keeps a broken invariant from hanging the GPU
+// (the sort's output is then wrong, which the callers' tests would show).
+constexpr uint32_t kOsMaxSpins = 1u << 20;
+
+__device__ __forceinline__ void os_publish(uint32_t *w, uint32_t v) {
+    __hip_atomic_store(w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t os_peek(const uint32_t *w) {
+    return __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+static int64_t os_tiles(int64_t n, int items) { return (n + kRsThreads * items - 1) / (kRsThreads * items); }
+
+void onesweep_layout(void *scratch, int64_t n, int items, OsBuffers *b) {
+    const int64_t tiles = os_tiles(n, items);
+    char *p = static_cast<char *>(scratch);
+    b->tiles = tiles;
+    b->items = items;
+    b->counts = reinterpret_cast<uint32_t *>(p);
+    p += align_up(sizeof(uint32_t) * kOsPasses * 256 * (size_t)tiles);
+    b->gbase = reinterpret_cast<uint32_t *>(p);
+    p += align_up(sizeof(uint32_t) * kOsPasses * 256);
+    b->status = reinterpret_cast<uint32_t *>(p);  // passes x tiles x 256 words, then the pass counters
+    b->status_words = (int64_t)kOsPasses * tiles * 256 + kOsPasses;
+}
+
+size_t onesweep_workspace(int64_t n) {
+    const int64_t tiles = os_tiles(n > 0 ? n : 1, os_items(n));
+    return align_up(sizeof(uint32_t) * kOsPasses * 256 * (size_t)tiles) + align_up(sizeof(uint32_t) * kOsPasses * 256) +
+           align_up(sizeof(uint32_t) * ((size_t)kOsPasses * tiles * 256 + kOsPasses));
+}
+
+// Digit counts of one tile's keys for all four passes (counts[tile*1024 + pass*256 + d],
+// one contiguous row per tile) and, spread over the grid, the clearing of the
+// look-back words.
+template <int ITEMS>
+__global__ void __launch_bounds__(kRsThreads) k_os_count(const uint32_t *__restrict__ keys, int64_t n,
+                                                          uint32_t *__restrict__ counts,
+                                                          uint32_t *__restrict__ status, int64_t status_words) {
+    __shared__ uint32_t hist[kOsPasses][256];
+#pragma unroll
+    for (int q = 0; q < kOsPasses; ++q) hist[q][threadIdx.x] = 0u;
+    for (int64_t i = (int64_t)blockIdx.x * kRsThreads + threadIdx.x; i < status_words;
+         i += (int64_t)gridDim.x * kRsThreads)
+        status[i] = 0u;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * (kRsThreads * ITEMS);
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int64_t i = base + (int64_t)j * kRsThreads + threadIdx.x;
+        if (i < n) {
+            const uint32_t k = keys[i];
+#pragma unroll
+            for (int q = 0; q < kOsPasses; ++q) atomicAdd(&hist[q][(k >> (8 * q)) & 255u], 1u);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kOsPasses; ++q)
+        counts[(int64_t)blockIdx.x * (kOsPasses * 256) + q * 256 + threadIdx.x] = hist[q][threadIdx.x];
+}
+
+// gbase[pass*256 + d] = keys whose digit in that pass is below d: one block, thread
+// pass*256 + d sums its digit's tile counts (one coalesced row per tile); a block scan
+// over all 1024 totals gives pass*n + the pass's own exclusive prefix.
+__global__ void __launch_bounds__(kOsPasses * 256) k_os_bases(const uint32_t *__restrict__ counts, int64_t tiles,
+                                                              int64_t n, uint32_t *__restrict__ gbase) {
+    const int t = threadIdx.x;
+    uint32_t tot = 0;
+    for (int64_t j0 = 0; j0 < tiles; j0 += 48) {  // 48 loads in flight per round trip
+        uint32_t c[48];
+#pragma unroll
+        for (int u = 0; u < 48; ++u) c[u] = j0 + u < tiles ? counts[(j0 + u) * (kOsPasses * 256) + t] : 0u;
+#pragma unroll
+        for (int u = 0; u < 48; ++u) tot += c[u];
+    }
+    uint64_t all;
+    const uint64_t ex = block_excl_scan<uint64_t>((uint64_t)tot, &all);
+    gbase[t] = (uint32_t)(ex - (uint64_t)(t / 256) * (uint64_t)n);
+}
+
+template <int ITEMS>
+__global__ void __launch_bounds__(kRsThreads) k_os_pass(const uint32_t *__restrict__ keys, uint32_t *__restrict__ keys_out,
+                                                         const uint32_t *__restrict__ vals,
+                                                         uint32_t *__restrict__ vals_out, int64_t n, int64_t tiles,
+                                                         int shift, const uint32_t *__restrict__ gbase,
+                                                         uint32_t *status, uint32_t *counter) {
+    constexpr int kTile = kRsThreads * ITEMS;
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t running[256];
+    __shared__ uint32_t lstart[256];
+    __shared__ uint32_t hist[kRsWaves][256];
+    __shared__ uint32_t skey[kTile];
+    __shared__ uint32_t sval[kTile];
+    const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
+    if (t == 0) s_tile = atomicAdd(counter, 1u);
+#pragma unroll
+    for (int q = 0; q < kRsWaves; ++q) hist[q][t] = 0;
+    __syncthreads();
+    const int64_t tile = s_tile;
+    if (tile >= tiles) return;  // only if the counter was not cleared (uniform)
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t base = tile * kTile;
+    const int64_t wbase = base + (int64_t)w * (kWave * ITEMS);
+    uint32_t key[ITEMS], val[ITEMS], rk[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int64_t i = wbase + (int64_t)j * kWave + lane;
+        key[j] = i < n ? keys[i] : 0u;
+        val[j] = i < n ? vals[i] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const bool valid = wbase + (int64_t)j * kWave + lane < n;
+        const uint32_t d = (key[j] >> shift) & 255u;
+        uint64_t match = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            match &= bit ? bb : ~bb;
+        }
+        const uint32_t below = (uint32_t)__popcll(match & lt_mask);
+        const uint32_t before = hist[w][d];
+        rk[j] = before + below;
+        if (valid && below == 0) hist[w][d] = before + (uint32_t)__popcll(match);
+    }
+    __syncthreads();
+    uint32_t cnt_d = 0;  // this tile's keys of digit t
+#pragma unroll
+    for (int q = 0; q < kRsWaves; ++q) {
+        const uint32_t c = hist[q][t];
+        hist[q][t] = cnt_d;
+        cnt_d += c;
+    }
+    os_publish(&status[tile * 256 + t], (tile == 0 ? kOsInc : kOsAgg) | cnt_d);
+    uint32_t all;
+    lstart[t] = block_excl_scan<uint32_t>(cnt_d, &all);
+    uint32_t excl = 0;
+    if (tile > 0) {
+        uint32_t spins = 0;
+        for (int64_t j = tile - 1; j >= 0; --j) {
+            uint32_t v;
+            do {
+                v = os_peek(&status[j * 256 + t]);
+            } while ((v & ~kOsCountMask) == 0u && ++spins < kOsMaxSpins);
+            excl += v & kOsCountMask;
+            if (v & kOsInc) break;
+        }
+        os_publish(&status[tile * 256 + t], kOsInc | (excl + cnt_d));
+    }
+    running[t] = gbase[t] + excl;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        if (wbase + (int64_t)j * kWave + lane < n) {
+            const uint32_t d = (key[j] >> shift) & 255u;
+            const uint32_t lp = lstart[d] + hist[w][d] + rk[j];
+            skey[lp] = key[j];
+            sval[lp] = val[j];
+        }
+    }
+    __syncthreads();
+    const int cnt = (int)((n - base) < kTile ? (n - base) : kTile);
+    for (int p = t; p < cnt; p += kRsThreads) {
+        const uint32_t k = skey[p];
+        const uint32_t d = (k >> shift) & 255u;
+        const uint32_t dst = running[d] + ((uint32_t)p - lstart[d]);
+        keys_out[dst] = k;
+        vals_out[dst] = sval[p];
+    }
+}
+
+int os_items(int64_t n) { return n <= (int64_t)(1 << 20) ? 4 : 16; }
+
+bgv_status onesweep_sort_u32(uint32_t *keys, uint32_t *keys_alt, uint32_t *vals, uint32_t *vals_alt, int64_t n,
+                             uint32_t **keys_out, uint32_t **vals_out, void *scratch, hipStream_t s, bool counted) {
+    OsBuffers b;
+    onesweep_layout(scratch, n, os_items(n), &b);
+    uint32_t *src = keys, *dst = keys_alt, *vsrc = vals, *vdst = vals_alt;
+    if (n > 1) {
+        const unsigned tiles = (unsigned)b.tiles;
+        if (!counted) {
+            if (b.items == 4)
+                BGV_LAUNCH(k_os_count<4>, dim3(tiles), dim3(kRsThreads), 0, s, src, n, b.counts, b.status,
+                           b.status_words);
+            else
+                BGV_LAUNCH(k_os_count<16>, dim3(tiles), dim3(kRsThreads), 0, s, src, n, b.counts, b.status,
+                           b.status_words);
+        }
+        BGV_LAUNCH(k_os_bases, dim3(1), dim3(kOsPasses * 256), 0, s, b.counts, b.tiles, n, b.gbase);
+        uint32_t *counters = b.status + (int64_t)kOsPasses * b.tiles * 256;
+        for (int pass = 0; pass < kOsPasses; ++pass) {
+            uint32_t *st = b.status + (int64_t)pass * b.tiles * 256;
+            if (b.items == 4)
+                BGV_LAUNCH(k_os_pass<4>, dim3(tiles), dim3(kRsThreads), 0, s, src, dst, vsrc, vdst, n, b.tiles,
+                           8 * pass, b.gbase + 256 * pass, st, counters + pass);
+            else
+                BGV_LAUNCH(k_os_pass<16>, dim3(tiles), dim3(kRsThreads), 0, s, src, dst, vsrc, vdst, n, b.tiles,
+                           8 * pass, b.gbase + 256 * pass, st, counters + pass);
+            uint32_t *tk = src; src = dst; dst = tk;
+            uint32_t *tv = vsrc; vsrc = vdst; vdst = tv;
+        }
+    }
+    *keys_out = src;
+    *vals_out = vsrc;
+    return BGV_OK;
+}
+
 }  // namespace bgv
 
 extern "C" const char *bgv_status_string(bgv_status s) {

@@ -423,8 +423,11 @@ __global__ void __launch_bounds__(kSgThreads) k_sg_group_pairs(const int32_t *__
             for (int r = 0; r < kMaxRows; ++r)
                 if (r < rows) {
                     const uint32_t cell = (uint32_t)r * cols + col_pair(h.a[r], h.b[r], h.c[r], la[u], lb[u], cols);
+                    // (pair within the tile, cell within the bucket), the pair's multiplicity
                     stage[hist[cell >> kSkBucketBits] + rank[u][r]] =
-                        make_uint2(cell & (kSkBucket - 1), cnt[u]);
+                        make_uint2(((uint32_t)(u * kSgThreads + threadIdx.x) << kSkBucketBits) |
+                                       (cell & (kSkBucket - 1)),
+                                   cnt[u]);
                 }
         }
     __syncthreads();
@@ -441,18 +444,29 @@ inline int32_t sk_sum_lanes(int64_t tiles) {
     return g;
 }
 
-__global__ void __launch_bounds__(kSkResolveThreads) k_sg_sum_cells(const uint2 *__restrict__ ent,
+// One workgroup per bucket of sketch-2 cells: the bucket's entries from every tile are
+// summed into its cells in LDS and the cells written whole; then every entry's count
+// is replaced in place by its cell's final value, so that each tile finds its pairs'
+// row estimates in its own region (k_sg_pair_min) instead of gathering them from the
+// sketch.  Buckets are dealt to the XCDs in contiguous ranges (as in the community
+// resolve): neighbouring buckets' segments share cache lines.
+constexpr int32_t kSgXcds = 8;
+
+__global__ void __launch_bounds__(kSkResolveThreads) k_sg_sum_cells(uint2 *__restrict__ ent,
                                                                      const uint32_t *__restrict__ etab,
                                                                      const uint32_t *__restrict__ Ep, int32_t rows,
                                                                      int32_t nb, int64_t cells, int32_t lanes,
                                                                      uint32_t *__restrict__ M2) {
     __shared__ uint32_t acc[kSkBucket];
-    const int32_t b = blockIdx.x;
+    const int32_t x = (int32_t)blockIdx.x;
+    const int32_t b = (x % kSgXcds) * ((nb + kSgXcds - 1) / kSgXcds) + x / kSgXcds;
+    if (b >= nb) return;  // the grid is rounded up to a multiple of the XCD count
     for (int32_t k = threadIdx.x; k < kSkBucket; k += kSkResolveThreads) acc[k] = 0u;
     __syncthreads();
     const int64_t tiles = ((int64_t)*Ep + kSkTile - 1) / kSkTile;
     const int64_t groups = kSkResolveThreads / lanes;
     const uint32_t sub = threadIdx.x % lanes, L = (uint32_t)lanes;
+    constexpr uint32_t kCell = kSkBucket - 1;
     for (int64_t t = threadIdx.x / lanes; t < tiles; t += groups) {
         const uint32_t *row = etab + t * (nb + 1);
         const uint32_t q0 = row[b], q1 = row[b + 1];
@@ -464,13 +478,52 @@ __global__ void __launch_bounds__(kSkResolveThreads) k_sg_sum_cells(const uint2 
                 if (q + u * L < q1) v[u] = seg[q + u * L];
 #pragma unroll
             for (int u = 0; u < 8; ++u)
-                if (q + u * L < q1) atomicAdd(&acc[v[u].x], v[u].y);
+                if (q + u * L < q1) atomicAdd(&acc[v[u].x & kCell], v[u].y);
         }
     }
     __syncthreads();
     const int64_t base = (int64_t)b << kSkBucketBits;
     const int32_t span = (int32_t)min((int64_t)kSkBucket, cells - base);
     for (int32_t k = threadIdx.x; k < span; k += kSkResolveThreads) M2[base + k] = acc[k];
+    for (int64_t t = threadIdx.x / lanes; t < tiles; t += groups) {
+        const uint32_t *row = etab + t * (nb + 1);
+        const uint32_t q0 = row[b], q1 = row[b + 1];
+        uint2 *seg = ent + t * (kSkTile * rows);
+        for (uint32_t q = q0 + sub; q < q1; q += 8 * L) {
+            uint32_t c[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (q + u * L < q1) c[u] = seg[q + u * L].x;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (q + u * L < q1) seg[q + u * L].y = acc[c[u] & kCell];
+        }
+    }
+}
+
+inline unsigned sg_sum_grid(int32_t nb) { return (unsigned)((nb + kSgXcds - 1) / kSgXcds * kSgXcds); }
+
+// Superedge weight = count-min estimate, the minimum over the rows of the final cell
+// values k_sg_sum_cells left in the tile's entries (one per pair and row).
+__global__ void __launch_bounds__(kSgThreads) k_sg_pair_min(const uint2 *__restrict__ ent,
+                                                             const uint32_t *__restrict__ etab,
+                                                             const uint32_t *__restrict__ Ep, int32_t rows, int32_t nb,
+                                                             uint32_t *__restrict__ se_weight) {
+    __shared__ uint32_t best[kSkTile];
+    const int64_t E = *Ep;
+    const int64_t j0 = (int64_t)blockIdx.x * kSkTile;
+    if (j0 >= E) return;  // the grid covers a bound of E
+    for (int k = threadIdx.x; k < kSkTile; k += kSgThreads) best[k] = 0xffffffffu;
+    __syncthreads();
+    const uint32_t total = etab[(int64_t)blockIdx.x * (nb + 1) + nb];
+    const uint2 *seg = ent + (int64_t)blockIdx.x * (kSkTile * rows);
+    for (uint32_t k = threadIdx.x; k < total; k += kSgThreads) {
+        const uint2 v = seg[k];
+        atomicMin(&best[v.x >> kSkBucketBits], v.y);
+    }
+    __syncthreads();
+    const int32_t cnt = (int32_t)min((int64_t)kSkTile, E - j0);
+    for (int k = threadIdx.x; k < cnt; k += kSgThreads) se_weight[j0 + k] = best[k];
 }
 
 // Superedge weight = count-min estimate (minimum over the rows of sketch 2).
@@ -708,14 +761,16 @@ extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges,
                        superedges, w.run_start, &w.counters[1], nkeys_d, super_label, h2, rows, cols, nb, w.ent,
                        w.etab, se_count);
             // the tile count is on the device; the edge count bounds it
-            BGV_LAUNCH(k_sg_sum_cells, dim3(nb), dim3(kSkResolveThreads), 0, s, w.ent, w.etab, &w.counters[1], rows,
-                       nb, cells, sk_sum_lanes((m + kSkTile - 1) / kSkTile), M2);
+            BGV_LAUNCH(k_sg_sum_cells, dim3(sg_sum_grid(nb)), dim3(kSkResolveThreads), 0, s, w.ent, w.etab,
+                       &w.counters[1], rows, nb, cells, sk_sum_lanes((m + kSkTile - 1) / kSkTile), M2);
+            BGV_LAUNCH(k_sg_pair_min, dim3((unsigned)((m + kSkTile - 1) / kSkTile)), dim3(kSgThreads), 0, s, w.ent,
+                       w.etab, &w.counters[1], rows, nb, se_weight);
         } else {
             BGV_LAUNCH(k_sg_sketch_pairs, dim3(gk), dim3(kSgThreads), 0, s, superedges, w.run_start, &w.counters[1],
                        nkeys_d, super_label, h2, rows, cols, M2, se_count);
+            BGV_LAUNCH(k_sg_pair_weights, dim3(gk), dim3(kSgThreads), 0, s, superedges, &w.counters[1], super_label,
+                       h2, rows, cols, M2, se_weight);
         }
-        BGV_LAUNCH(k_sg_pair_weights, dim3(gk), dim3(kSgThreads), 0, s, superedges, &w.counters[1], super_label, h2,
-                   rows, cols, M2, se_weight);
         BGV_CHECK_HIP(hipMemcpyAsync(rb->host + 4, &w.counters[1], sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         BGV_CHECK_HIP(hipStreamSynchronize(s));
         E = rb->host[4];

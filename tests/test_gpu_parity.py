@@ -635,6 +635,30 @@ def test_bh_theta_zero_equals_exact_oracle(bgv):
     assert np.abs(host(fprev) - F_ex).max() <= TOL * np.abs(F_ex).max()
 
 
+def test_bh_short_stack_redo(bgv):
+    """The force launch gives each body a short stack and redoes any workgroup whose walk
+    outgrows it with the full stack.  Small opening angles on a deep tree (clusters
+    nested down to the grid) make many walks outgrow it: the forces must still match
+    the oracle by the opening-decision protocol, the redo count must be positive, and
+    two runs must give the same bits."""
+    from paper_2108_00529_amd import profile as prof
+    rng = np.random.default_rng(23)
+    K = 6000
+    c = rng.uniform(-1, 1, (K, 2)) * (0.5 ** rng.integers(0, 14, (K, 1)))  # scales 1 .. 2^-13
+    pos32 = c.astype(np.float32)
+    se = np.array(sorted({(min(a, b), max(a, b)) for a, b in rng.integers(0, K, (2 * K, 2)).tolist() if a != b}),
+                  np.int32)
+    for theta in (0.05, 0.3):
+        prof.reset()
+        F, F_ref, _ = bh_force_check(bgv, pos32, se, theta, f"deep tree theta={theta}")
+        redone = prof.counter("bh_redo_blocks")
+        say(f"  theta={theta}: {redone} of {(K + 7) // 8} force workgroups redone with the full stack")
+        if theta == 0.05:
+            assert redone > 0
+        _, f2, _ = bgv.fa2_layout(dev(se), dev(pos32), 1, exact=False, theta=theta)
+        assert np.array_equal(host(f2), F.astype(np.float32))
+
+
 def test_bh_checkpoints_planted(bgv, planted_sg):
     wl, sg, pos0 = planted_sg
     worst = step_parity(bgv, sg["superedges"], pos0, 200, [0, 1, 10, 100, 199], exact=False, theta=1.2,
