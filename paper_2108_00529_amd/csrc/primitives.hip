@@ -483,23 +483,22 @@ __global__ void __launch_bounds__(kRsThreads) k_os_count(const uint32_t *__restr
         counts[(int64_t)blockIdx.x * (kOsPasses * 256) + q * 256 + threadIdx.x] = hist[q][threadIdx.x];
 }
 
-// gbase[pass*256 + d] = keys whose digit in that pass is below d: one block, thread
-// pass*256 + d sums its digit's tile counts (one coalesced row per tile); a block scan
-// over all 1024 totals gives pass*n + the pass's own exclusive prefix.
-__global__ void __launch_bounds__(kOsPasses * 256) k_os_bases(const uint32_t *__restrict__ counts, int64_t tiles,
-                                                              int64_t n, uint32_t *__restrict__ gbase) {
-    const int t = threadIdx.x;
+// gbase[pass*256 + d] = keys whose digit in that pass is below d: one block per pass,
+// thread d sums its digit's tile counts (one coalesced row per tile), then a block scan.
+__global__ void __launch_bounds__(256) k_os_bases(const uint32_t *__restrict__ counts, int64_t tiles,
+                                                  uint32_t *__restrict__ gbase) {
+    const int t = threadIdx.x, pass = blockIdx.x;
+    const uint32_t *col = counts + pass * 256 + t;
     uint32_t tot = 0;
-    for (int64_t j0 = 0; j0 < tiles; j0 += 48) {  // 48 loads in flight per round trip
-        uint32_t c[48];
+    for (int64_t j0 = 0; j0 < tiles; j0 += 32) {  // 32 loads in flight per round trip
+        uint32_t c[32];
 #pragma unroll
-        for (int u = 0; u < 48; ++u) c[u] = j0 + u < tiles ? counts[(j0 + u) * (kOsPasses * 256) + t] : 0u;
+        for (int u = 0; u < 32; ++u) c[u] = j0 + u < tiles ? col[(j0 + u) * (kOsPasses * 256)] : 0u;
 #pragma unroll
-        for (int u = 0; u < 48; ++u) tot += c[u];
+        for (int u = 0; u < 32; ++u) tot += c[u];
     }
-    uint64_t all;
-    const uint64_t ex = block_excl_scan<uint64_t>((uint64_t)tot, &all);
-    gbase[t] = (uint32_t)(ex - (uint64_t)(t / 256) * (uint64_t)n);
+    uint32_t all;
+    gbase[pass * 256 + t] = block_excl_scan<uint32_t>(tot, &all);
 }
 
 template <int ITEMS>
@@ -611,7 +610,7 @@ bgv_status onesweep_sort_u32(uint32_t *keys, uint32_t *keys_alt, uint32_t *vals,
                 BGV_LAUNCH(k_os_count<16>, dim3(tiles), dim3(kRsThreads), 0, s, src, n, b.counts, b.status,
                            b.status_words);
         }
-        BGV_LAUNCH(k_os_bases, dim3(1), dim3(kOsPasses * 256), 0, s, b.counts, b.tiles, n, b.gbase);
+        BGV_LAUNCH(k_os_bases, dim3(kOsPasses), dim3(256), 0, s, b.counts, b.tiles, b.gbase);
         uint32_t *counters = b.status + (int64_t)kOsPasses * b.tiles * 256;
         for (int pass = 0; pass < kOsPasses; ++pass) {
             uint32_t *st = b.status + (int64_t)pass * b.tiles * 256;
