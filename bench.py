@@ -43,7 +43,7 @@ def parse():
                     help="Barnes-Hut layout iterations the CPU oracle runs for its FA2 rate (a sample: the "
                          "workload has 1,000)")
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the whole-graph, sequential-rule, sweep, small-graph, batched, gradient and lfr_1m "
+                    help="skip the whole-graph, sequential-rule, atomics, sweep, small-graph, batched, gradient and lfr_1m "
                          "comparisons")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="do not time launches with HIP events (for hardware-counter runs)")
@@ -235,6 +235,7 @@ def main():
         torch.cuda.empty_cache()
         out["forms"] = {"whole_graph_fa2": whole_graph_form(torch, bgv, edges_np, n, wl, cd + fa_unprofiled),
                         "sequential_rule": sequential_rule_form(torch, bgv, edges_np, n, wl, not args.no_cpu),
+                        "atomics": atomic_forms(torch, bgv, edges_np, n, wl),
                         "sweeps": sweeps_form(torch, bgv, graphgen, edges_np, n, wl),
                         "small_graph": small_graph_form(torch, bgv, graphgen),
                         "batched": batched_form(torch, bgv, graphgen),
@@ -578,7 +579,8 @@ def _forms():
             "whole_graph_fa2": needs_bench_graph(lambda torch, bgv, e, wl: whole_graph_form(torch, bgv, e, wl["n"], wl,
                                                                                              float("nan"))),
             "sequential_rule": needs_bench_graph(lambda torch, bgv, e, wl: sequential_rule_form(torch, bgv, e, wl["n"],
-                                                                                                 wl, False))}
+                                                                                                 wl, False)),
+            "atomics": needs_bench_graph(lambda torch, bgv, e, wl: atomic_forms(torch, bgv, e, wl["n"], wl))}
 
 
 FORMS = _forms()
@@ -647,6 +649,55 @@ def measured_copy_gbs(torch, mib=1024, repeats=5):
         best = min(best, a.elapsed_time(b))
     del src, dst
     return 2 * mib * (1 << 20) / (best / 1000.0) / 1e9
+
+
+def measured_atomic_rate(torch, n_ops=1 << 26, n_addr=1 << 24, repeats=3):
+    """Random device atomics per second: torch's index_add_ on int32 (one atomic add per
+    source element) of n_ops ones at uniformly random places of an n_addr-entry array,
+    best of `repeats`: the practical rate of scattered device-scope integer atomics,
+    beside which the library's atomic forms (the volume rule, the per-node form above
+    2^24 nodes) are read."""
+    g = torch.Generator(device="cuda").manual_seed(5)
+    idx = torch.randint(0, n_addr, (n_ops,), device="cuda", generator=g)
+    src = torch.ones(n_ops, dtype=torch.int32, device="cuda")
+    x = torch.zeros(n_addr, dtype=torch.int32, device="cuda")
+    x.index_add_(0, idx, src)
+    best = float("inf")
+    for _ in range(repeats):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        x.index_add_(0, idx, src)
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b))
+    ok = int(x.sum().item()) == (repeats + 1) * n_ops
+    del idx, src, x
+    return n_ops / (best / 1000.0), ok
+
+
+def atomic_forms(torch, bgv, edges_np, n, wl):
+    """The community passes under SCoDA's volume rule (the library's form built on device
+    atomics: two counter increments per non-loop edge and pass, plus the V updates
+    combined per wave and label) on the bench graph, against the measured random-atomic
+    rate."""
+    rate, ok = measured_atomic_rate(torch)
+    dev = torch.device("cuda:0")
+    ed = torch.from_numpy(np.ascontiguousarray(edges_np)).to(dev)
+    run = lambda: bgv.community(ed, n, wl["threshold"], wl["passes"], wl["growth"], wl["chunk"], rule=1, check=False)
+    run()
+    torch.cuda.synchronize()
+    ms = _timed(torch, run, repeats=2)
+    loops = int((edges_np[:, 0] == edges_np[:, 1]).sum())
+    min_atomics = 2 * (int(edges_np.shape[0]) - loops) * wl["passes"]
+    del ed
+    torch.cuda.empty_cache()
+    return {"measured_random_atomic_adds_per_s": rate, "measured_with": "torch index_add_ int32, 2^26 adds at "
+                                                                       "random places of a 2^24-entry array",
+            "measured_sum_checked": ok, "volume_rule_community_ms": ms,
+            "volume_rule_counter_atomics": min_atomics,
+            "volume_rule_counter_atomics_per_s": min_atomics / (ms / 1000.0),
+            "volume_rule_frac_of_measured_atomic_rate": min_atomics / (ms / 1000.0) / rate}
 
 
 def roofline_report(kstats, kbreak, wl, n, m, K, E, inter_per_launch=None):
