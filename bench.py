@@ -590,7 +590,8 @@ FORMS = _forms()
 EDGE_PASS_BYTES = 8            # one int32 (u,v) pair read per edge per pass
 BH_INTERACTION_FLOPS = 20      # body-node or body-body interaction, n-body convention
 CSR_ENTRY_BYTES = {"attract<uint16_t>": 2, "attract<uint32_t>": 4, "attract<int2>": 8,
-                   "attract_lds<uint16_t>": 2, "attract_lds<uint32_t>": 4, "attract_lds<int2>": 8}
+                   "attract_lds<uint16_t>": 2, "attract_lds<uint32_t>": 4, "attract_lds<int2>": 8,
+                   "attract_cols<uint16_t>": 2, "attract_cols<int2>": 8}
 
 
 def kernel_model(name, K, E, inter_per_launch=None):

@@ -18,6 +18,9 @@
 //   BH:     k_bh_speed      global speed from the partials (one per 8 bodies) in one block
 //           k_bh_update     local speeds, displacement, bounding-box partials
 // No floating-point atomics anywhere: results are identical run to run.
+#include <algorithm>
+#include <climits>
+#include <cstddef>
 #include <cstring>
 
 #include "block_scan.h"
@@ -29,6 +32,18 @@ namespace bgv {
 
 constexpr int kFaThreads = 256;
 static_assert(kFaThreads == kFa2Tile, "the layout kernels work on 256-node tiles");
+
+// Column-blocked attraction (att_cols(K)): blocks of kAttCol consecutive neighbour ids,
+// whose positions fill 128 KiB of LDS; items of at most kAttCap entries of one row in
+// one block, summed by kAttColLanes lanes each.
+constexpr int kAttColBits = 14;
+constexpr int32_t kAttCol = 1 << kAttColBits;
+constexpr uint32_t kAttCap = 256;
+constexpr int kAttLenBits = 9;  // kAttCap - length, in the low bits of an item's sort key
+static_assert(kAttCap < (1u << kAttLenBits), "item lengths must fit the key field");
+constexpr int kAttColLanes = 8;
+constexpr int kAttColThreads = 1024;
+inline int32_t att_col_blocks(int32_t K) { return (K + kAttCol - 1) / kAttCol; }
 
 // ------------------------------------------------------------------------ CSR ----
 template <typename KT>  // 32-bit keys when 2 * kb <= 32
@@ -76,7 +91,13 @@ static int bits_for(int64_t K) {
     return kb;
 }
 
-int64_t att_items_cap(int32_t K, int64_t E) { return (int64_t)K + (2 * E) / kAttBlock + 1; }
+int64_t att_items_cap(int32_t K, int64_t E) {
+    if (!att_cols(K)) return (int64_t)K + (2 * E) / kAttBlock + 1;
+    // every row one item, every further block run one more, every kAttCap entries of a
+    // run one more
+    const int64_t runs = std::min<int64_t>(2 * E, (int64_t)K * att_col_blocks(K));
+    return (int64_t)K + runs + (2 * E) / kAttCap + 1;
+}
 
 size_t csr_layout(Carver &c, int32_t K, int64_t E, CsrWs *w) {
     const int64_t nent = 2 * E > 0 ? 2 * E : 1;
@@ -86,12 +107,53 @@ size_t csr_layout(Carver &c, int32_t K, int64_t E, CsrWs *w) {
     w->items_bound = att_items_cap(K, E);
     w->item_of = c.take<uint32_t>((size_t)K + 1);
     w->item_row = c.take<uint32_t>((size_t)w->items_bound);
-    w->keys = c.take<uint64_t>((size_t)nent);
-    w->keys_alt = c.take<uint64_t>((size_t)nent);
-    w->vals = c.take<uint32_t>((size_t)nent);
-    w->vals_alt = c.take<uint32_t>((size_t)nent);
-    const size_t rs = radix_workspace(nent), sc = scan_workspace((int64_t)K + 1);
-    w->sort_scratch = c.take<char>(rs > sc ? rs : sc);
+    const bool cols = att_cols(K);
+    const int64_t nblk = cols ? att_col_blocks(K) : 0;
+    // column-blocked entries: nent plus the padding of each block's groups, at most one
+    // group's worth per block (lengths fall within a block, so a group's padding is at
+    // most the previous group's entries)
+    const int64_t cwb_slots = nent + nblk * kWave * (int64_t)kAttCap;
+    w->keys = c.take<uint64_t>((size_t)std::max<int64_t>(nent, cols ? cwb_slots : 0));
+    size_t scratch = std::max(radix_workspace(nent), scan_workspace((int64_t)K + 1));
+    w->it = w->ir = w->cstart = w->gfirst = w->gbase = w->wg_first = nullptr;
+    w->il = nullptr;
+    w->item_beg = w->ikeys = w->ikeys_alt = w->ivals = w->ivals_alt = w->ilen = nullptr;
+    w->cwb = nullptr;
+    w->nitems = nullptr;
+    const int64_t T = w->items_bound;
+    const int64_t ngroups = T / kWave + nblk + 1;  // bound on the groups of 64
+    if (cols) {
+        w->it = c.take<uint32_t>((size_t)T);
+        w->ir = c.take<uint32_t>((size_t)T);
+        w->il = c.take<uint16_t>((size_t)T);
+        w->cstart = c.take<uint32_t>((size_t)nblk + 1);
+        w->gfirst = c.take<uint32_t>((size_t)nblk + 1);
+        w->gbase = c.take<uint32_t>((size_t)ngroups + 1);
+        w->wg_first = c.take<uint32_t>((size_t)nblk + 1);
+        w->nitems = c.take<unsigned long long>(1);
+        w->cwb = w->keys;  // free once the CSR is filled
+    }
+    // the CSR sort's other buffers and the item setup's are both dead once the CSR is
+    // built, so they share one region
+    char *const r0 = c.base ? c.base + c.size() : nullptr;
+    Carver a(r0);
+    w->keys_alt = a.take<uint64_t>((size_t)nent);
+    w->vals = a.take<uint32_t>((size_t)nent);
+    w->vals_alt = a.take<uint32_t>((size_t)nent);
+    size_t region = a.size();
+    if (cols) {
+        Carver b(r0);
+        w->item_beg = b.take<uint32_t>((size_t)T + 1);
+        w->ikeys = b.take<uint32_t>((size_t)T);
+        w->ikeys_alt = b.take<uint32_t>((size_t)T);
+        w->ivals = b.take<uint32_t>((size_t)T);
+        w->ivals_alt = b.take<uint32_t>((size_t)T);
+        w->ilen = b.take<uint32_t>((size_t)std::max<int64_t>(T, ngroups + 1));
+        region = std::max(region, b.size());
+        scratch = std::max(scratch, std::max(radix_workspace(T), scan_workspace(std::max<int64_t>(T, ngroups + 1))));
+    }
+    c.take<char>(region);
+    w->sort_scratch = c.take<char>(scratch);
     return c.size();
 }
 
@@ -111,6 +173,242 @@ __global__ void k_att_item_counts(const uint32_t *__restrict__ row, int32_t K, u
 __global__ void k_att_item_rows(const uint32_t *__restrict__ item_of, int32_t K, uint32_t *__restrict__ item_row) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < K; i += (int64_t)gridDim.x * blockDim.x)
         for (uint32_t t = item_of[i]; t < item_of[i + 1]; ++t) item_row[t] = (uint32_t)i;
+}
+
+// --------------------------------------------------- column-blocked item setup ----
+// Item starts of row r (entries [r0, r1), neighbours ascending, so a row's column
+// blocks come in runs in ascending order), one wavefront per row: entry k starts an
+// item when it opens a block run or lies a multiple of kAttCap entries after the start
+// of its run.  f(k, j) is called by the lane holding each start, j = the start's rank
+// in the row.  Returns the number of starts.
+template <typename E, typename F>
+__device__ __forceinline__ uint32_t attc_walk(const E *__restrict__ cw, uint32_t r0, uint32_t r1, int lane, F f) {
+    uint32_t run = r0, count = 0;
+    int32_t prev_blk = -1;
+    for (uint32_t c0 = r0; c0 < r1; c0 += kWave) {
+        const uint32_t k = c0 + (uint32_t)lane;
+        const bool in = k < r1;
+        const int32_t blk = in ? (fa2_entry_id(cw[k]) >> kAttColBits) : INT_MAX;
+        int32_t before = __shfl_up(blk, 1, kWave);
+        if (lane == 0) before = prev_blk;
+        // latest run start at or before each lane: an inclusive max-scan
+        uint32_t rs = (in && blk != before) ? k : run;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const uint32_t v = __shfl_up(rs, o, kWave);
+            if (lane >= o) rs = max(rs, v);
+        }
+        const bool start = in && ((k - rs) & (kAttCap - 1)) == 0;
+        const uint64_t m = __ballot(start);
+        if (start) f(k, count + (uint32_t)__popcll(m & ((1ull << lane) - 1ull)));
+        count += (uint32_t)__popcll(m);
+        run = __shfl(rs, kWave - 1, kWave);
+        prev_blk = __shfl(blk, kWave - 1, kWave);
+    }
+    return count;
+}
+
+// item_of[r] = items of row r (at least one: an empty row has one empty item);
+// item_of[K] = 0 for the scan that follows.
+template <typename E>
+__global__ void __launch_bounds__(kFaThreads) k_attc_count(const uint32_t *__restrict__ row, const E *__restrict__ cw,
+                                                            int32_t K, uint32_t *__restrict__ item_of) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t nw = (int64_t)gridDim.x * (kFaThreads / kWave);
+    for (int64_t r = (blockIdx.x * (int64_t)kFaThreads + threadIdx.x) / kWave; r <= K; r += nw) {
+        if (r == K) {
+            if (lane == 0) item_of[K] = 0u;
+            continue;
+        }
+        const uint32_t n = attc_walk(cw, row[r], row[r + 1], lane, [](uint32_t, uint32_t) {});
+        if (lane == 0) item_of[r] = n ? n : 1u;
+    }
+}
+
+// item_row and item_beg of every item (item_of now holds first-item offsets), the item
+// count in *nitems and item_beg[count] = nent.
+template <typename E>
+__global__ void __launch_bounds__(kFaThreads) k_attc_fill(const uint32_t *__restrict__ row, const E *__restrict__ cw,
+                                                           int32_t K, const uint32_t *__restrict__ item_of,
+                                                           uint32_t nent, uint32_t *__restrict__ item_row,
+                                                           uint32_t *__restrict__ item_beg,
+                                                           unsigned long long *__restrict__ nitems) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t nw = (int64_t)gridDim.x * (kFaThreads / kWave);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        item_beg[item_of[K]] = nent;
+        *nitems = item_of[K];
+    }
+    for (int64_t r = (blockIdx.x * (int64_t)kFaThreads + threadIdx.x) / kWave; r < K; r += nw) {
+        const uint32_t r0 = row[r], r1 = row[r + 1], base = item_of[r];
+        if (r0 == r1) {
+            if (lane == 0) {
+                item_row[base] = (uint32_t)r;
+                item_beg[base] = r0;
+            }
+            continue;
+        }
+        attc_walk(cw, r0, r1, lane, [&](uint32_t k, uint32_t j) {
+            item_row[base + j] = (uint32_t)r;
+            item_beg[base + j] = k;
+        });
+    }
+}
+
+// Sort keys of the items: column block above, kAttCap - length below (so each block's
+// items come longest first); an empty item goes with block 0.
+template <typename E>
+__global__ void k_attc_keys(const E *__restrict__ cw, const uint32_t *__restrict__ item_beg,
+                            const unsigned long long *__restrict__ nitems, uint32_t *__restrict__ keys,
+                            uint32_t *__restrict__ vals) {
+    const uint32_t T = (uint32_t)*nitems;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < T; t += gridDim.x * blockDim.x) {
+        const uint32_t b = item_beg[t], len = item_beg[t + 1] - b;
+        const uint32_t blk = len ? (uint32_t)fa2_entry_id(cw[b]) >> kAttColBits : 0u;
+        keys[t] = (blk << kAttLenBits) | (kAttCap - len);
+        vals[t] = t;
+    }
+}
+
+// The first schedule position of every column block (items sorted by their keys).
+__global__ void k_attc_order(const uint32_t *__restrict__ skeys, const unsigned long long *__restrict__ nitems,
+                             int32_t nblk, uint32_t *__restrict__ cstart) {
+    const uint32_t T = (uint32_t)*nitems;
+    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < T; q += gridDim.x * blockDim.x) {
+        const int32_t c = (int32_t)(skeys[q] >> kAttLenBits);
+        const int32_t before = q ? (int32_t)(skeys[q - 1] >> kAttLenBits) : -1;
+        for (int32_t x = before + 1; x <= c; ++x) cstart[x] = q;
+        if (q == T - 1)
+            for (int32_t x = c + 1; x <= nblk; ++x) cstart[x] = T;
+    }
+}
+
+// gfirst[c] = first group of block c (groups of kWave consecutive items of a block).
+__global__ void k_attc_gfirst(int32_t nblk, const uint32_t *__restrict__ cstart, uint32_t *__restrict__ gfirst) {
+    if (threadIdx.x != 0) return;
+    uint32_t g = 0;
+    for (int32_t c = 0; c < nblk; ++c) {
+        gfirst[c] = g;
+        g += (cstart[c + 1] - cstart[c] + kWave - 1) / kWave;
+    }
+    gfirst[nblk] = g;
+}
+
+__device__ __forceinline__ int32_t attc_block_of(const uint32_t *__restrict__ first, int32_t nblk, uint32_t x) {
+    int32_t lo = 0, hi = nblk - 1;  // the last c with first[c] <= x
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// gsize[gi] = kWave * (length of the group's first item, its longest); 0 past the groups.
+__global__ void k_attc_gsize(const uint32_t *__restrict__ svals, const uint32_t *__restrict__ item_beg,
+                             int32_t nblk, const uint32_t *__restrict__ cstart, const uint32_t *__restrict__ gfirst,
+                             int64_t bound, uint32_t *__restrict__ gsize) {
+    const uint32_t NG = gfirst[nblk];
+    for (int64_t gi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; gi < bound; gi += (int64_t)gridDim.x * blockDim.x) {
+        if (gi >= NG) {
+            gsize[gi] = 0u;
+            continue;
+        }
+        const int32_t c = attc_block_of(gfirst, nblk, (uint32_t)gi);
+        const uint32_t q0 = cstart[c] + ((uint32_t)gi - gfirst[c]) * kWave;
+        const uint32_t t = svals[q0];
+        gsize[gi] = kWave * (item_beg[t + 1] - item_beg[t]);
+    }
+}
+
+// The schedule arrays and the entries, copied transposed per group (gbase = exclusive
+// sums of gsize), neighbour ids replaced by their offsets in the block; kAttColLanes
+// lanes per item.
+__device__ __forceinline__ uint16_t attc_local(uint32_t e, int32_t base) { return (uint16_t)((int32_t)e - base); }
+__device__ __forceinline__ uint16_t attc_local(uint16_t e, int32_t base) { return (uint16_t)((int32_t)e - base); }
+__device__ __forceinline__ int2 attc_local(int2 e, int32_t base) { return make_int2(e.x - base, e.y); }
+
+template <typename E, typename EC>
+__global__ void k_attc_copy(const E *__restrict__ cw, const uint32_t *__restrict__ skeys,
+                            const uint32_t *__restrict__ svals, const unsigned long long *__restrict__ nitems,
+                            const uint32_t *__restrict__ item_beg, const uint32_t *__restrict__ item_row,
+                            const uint32_t *__restrict__ cstart, const uint32_t *__restrict__ gfirst,
+                            const uint32_t *__restrict__ gbase, uint32_t *__restrict__ it, uint32_t *__restrict__ ir,
+                            uint16_t *__restrict__ il, EC *__restrict__ cwb) {
+    const uint32_t T = (uint32_t)*nitems;
+    const uint32_t L = threadIdx.x % kAttColLanes;
+    const int64_t groups = (int64_t)gridDim.x * (blockDim.x / kAttColLanes);
+    for (int64_t q = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kAttColLanes; q < T; q += groups) {
+        const int32_t c = (int32_t)(skeys[q] >> kAttLenBits);
+        const uint32_t off = (uint32_t)q - cstart[c];
+        const uint32_t lane = off % kWave;
+        const uint32_t eb = gbase[gfirst[c] + off / kWave];
+        const uint32_t t = svals[q], b = item_beg[t], len = item_beg[t + 1] - b;
+        const int32_t base = c << kAttColBits;
+        for (uint32_t k = L; k < len; k += kAttColLanes) cwb[eb + k * kWave + lane] = attc_local(cw[b + k], base);
+        if (L == 0) {
+            it[q] = t;
+            ir[q] = item_row[t];
+            il[q] = (uint16_t)len;
+        }
+    }
+}
+
+// Workgroups of the column-blocked attraction per block: one each, and the other
+// G - nblk shared out in proportion to the block's work (the longest entry of each of
+// its groups, plus 8 per group), so that the blocks finish together.
+__global__ void k_attc_plan(int32_t nblk, int32_t G, const uint32_t *__restrict__ gfirst,
+                            const uint32_t *__restrict__ gbase, uint32_t *__restrict__ wg_first) {
+    if (threadIdx.x != 0) return;
+    uint64_t total = 0;
+    for (int32_t c = 0; c < nblk; ++c)
+        total += (gbase[gfirst[c + 1]] - gbase[gfirst[c]]) / kWave + 8ull * (gfirst[c + 1] - gfirst[c]);
+    const uint64_t spare = (uint64_t)(G - nblk);
+    uint64_t run = 0;
+    for (int32_t c = 0; c < nblk; ++c) {
+        wg_first[c] = (uint32_t)c + (uint32_t)(total ? spare * run / total : 0);
+        run += (gbase[gfirst[c + 1]] - gbase[gfirst[c]]) / kWave + 8ull * (gfirst[c + 1] - gfirst[c]);
+    }
+    wg_first[nblk] = (uint32_t)G;
+}
+
+static bgv_status att_col_grid(int32_t K, int32_t *G) {
+    int cus = 1;
+    BGV_TRY(device_cu_count(&cus));
+    *G = std::max(cus, att_col_blocks(K));
+    return BGV_OK;
+}
+
+template <typename E, typename EC>
+static bgv_status attc_setup(int32_t K, int64_t nent, CsrWs &w, hipStream_t s) {
+    const E *cw = reinterpret_cast<const E *>(w.cw);
+    const int64_t T = w.items_bound;
+    const int32_t nblk = att_col_blocks(K);
+    const int64_t ngroups = T / kWave + nblk + 1;
+    const dim3 gr(grid_for((int64_t)K + 1, kFaThreads / kWave, 65536));
+    BGV_LAUNCH(k_attc_count<E>, gr, dim3(kFaThreads), 0, s, w.row, cw, K, w.item_of);
+    BGV_TRY(exclusive_scan_u32(w.item_of, w.item_of, (int64_t)K + 1, nullptr, w.sort_scratch, s));
+    BGV_LAUNCH(k_attc_fill<E>, gr, dim3(kFaThreads), 0, s, w.row, cw, K, w.item_of, (uint32_t)nent, w.item_row,
+               w.item_beg, w.nitems);
+    const dim3 gt(grid_for(T, kFaThreads, 65536));
+    BGV_LAUNCH(k_attc_keys<E>, gt, dim3(kFaThreads), 0, s, cw, w.item_beg, w.nitems, w.ikeys, w.ivals);
+    int kbits = kAttLenBits + 1;
+    while ((1ll << (kbits - kAttLenBits)) < nblk) ++kbits;
+    uint32_t *sk, *sv;
+    BGV_TRY(radix_sort_u32(w.ikeys, w.ikeys_alt, w.ivals, w.ivals_alt, T, kbits, &sk, &sv, w.sort_scratch, s, false,
+                           w.nitems));
+    BGV_LAUNCH(k_attc_order, gt, dim3(kFaThreads), 0, s, sk, w.nitems, nblk, w.cstart);
+    BGV_LAUNCH(k_attc_gfirst, dim3(1), dim3(64), 0, s, nblk, w.cstart, w.gfirst);
+    BGV_LAUNCH(k_attc_gsize, dim3(grid_for(ngroups + 1, kFaThreads, 65536)), dim3(kFaThreads), 0, s, sv, w.item_beg,
+               nblk, w.cstart, w.gfirst, ngroups + 1, w.ilen);
+    BGV_TRY(exclusive_scan_u32(w.ilen, w.gbase, ngroups + 1, nullptr, w.sort_scratch, s));
+    const auto k_attc_copy_ = k_attc_copy<E, EC>;
+    BGV_LAUNCH(k_attc_copy_, dim3(grid_for(T, kFaThreads / kAttColLanes, 65536)), dim3(kFaThreads), 0, s, cw, sk, sv,
+               w.nitems, w.item_beg, w.item_row, w.cstart, w.gfirst, w.gbase, w.it, w.ir, w.il,
+               reinterpret_cast<EC *>(w.cwb));
+    int32_t G = 1;
+    BGV_TRY(att_col_grid(K, &G));
+    BGV_LAUNCH(k_attc_plan, dim3(1), dim3(64), 0, s, nblk, G, w.gfirst, w.gbase, w.wg_first);
+    return BGV_OK;
 }
 
 bgv_status build_csr(int32_t K, int64_t E, const int32_t *edges, const float *attr_w, const float *mass_in,
@@ -139,11 +437,20 @@ bgv_status build_csr(int32_t K, int64_t E, const int32_t *edges, const float *at
                        w.cw);
         }
     }
-    BGV_LAUNCH(k_att_item_counts, dim3(grid_for((int64_t)K + 1, kFaThreads, 65536)), dim3(kFaThreads), 0, s, w.row,
-               K, w.item_of);
-    BGV_TRY(exclusive_scan_u32(w.item_of, w.item_of, (int64_t)K + 1, nullptr, w.sort_scratch, s));
-    BGV_LAUNCH(k_att_item_rows, dim3(grid_for(K, kFaThreads, 65536)), dim3(kFaThreads), 0, s, w.item_of, K,
-               w.item_row);
+    if (att_cols(K)) {
+        if (w.fmt == kCsrWeighted)
+            BGV_TRY((attc_setup<int2, int2>(K, 2 * E, w, s)));
+        else if (w.fmt == kCsrIds32)
+            BGV_TRY((attc_setup<uint32_t, uint16_t>(K, 2 * E, w, s)));
+        else
+            BGV_TRY((attc_setup<uint16_t, uint16_t>(K, 2 * E, w, s)));
+    } else {
+        BGV_LAUNCH(k_att_item_counts, dim3(grid_for((int64_t)K + 1, kFaThreads, 65536)), dim3(kFaThreads), 0, s,
+                   w.row, K, w.item_of);
+        BGV_TRY(exclusive_scan_u32(w.item_of, w.item_of, (int64_t)K + 1, nullptr, w.sort_scratch, s));
+        BGV_LAUNCH(k_att_item_rows, dim3(grid_for(K, kFaThreads, 65536)), dim3(kFaThreads), 0, s, w.item_of, K,
+                   w.item_row);
+    }
     if (mass_in) {
         *mass_out = mass_in;
     } else {
@@ -214,8 +521,7 @@ __global__ void __launch_bounds__(kFaThreads) k_attract(int32_t K, const float2 
 // of 16 wavefronts per compute unit, so each position array is loaded once per unit.
 // Smaller supergraphs keep the plain kernel: their positions stay in L2 anyway and a
 // 1024-thread workgroup per unit only adds dispatch time to their short iterations.
-constexpr int32_t kAttLdsMin = 4096;
-constexpr int32_t kAttLdsMax = 19456;  // 152 KiB of float2 (dynamic LDS: K * 8 bytes)
+constexpr int32_t kAttLdsMin = 4096;  // up to kAttLdsMax: dynamic LDS of K * 8 bytes
 constexpr int kAttLdsThreads = 1024;
 
 template <typename E>
@@ -232,7 +538,78 @@ __global__ void __launch_bounds__(kAttLdsThreads) k_attract_lds(int32_t K, const
               (int64_t)gridDim.x * (kAttLdsThreads / kWave));
 }
 
+// Column-blocked attraction: the workgroups [wg_first[c], wg_first[c + 1]) of column
+// block c (one per compute unit: the block's positions take 128 KiB of LDS) stage the
+// block's positions, then their wavefronts take the block's groups in turn, one item
+// per lane: the lane adds its item's entries in order, reading them from the group's
+// transposed run (coalesced) and the positions from LDS.  Every item sum, and so
+// every node's attraction, is identical run to run.
+template <typename EC>
+__global__ void __launch_bounds__(kAttColThreads) k_attract_cols(int32_t K, int32_t nblk,
+                                                                  const uint32_t *__restrict__ wg_first,
+                                                                  const float2 *__restrict__ pos,
+                                                                  const uint32_t *__restrict__ it,
+                                                                  const uint32_t *__restrict__ ir,
+                                                                  const uint16_t *__restrict__ il,
+                                                                  const uint32_t *__restrict__ cstart,
+                                                                  const uint32_t *__restrict__ gfirst,
+                                                                  const uint32_t *__restrict__ gbase,
+                                                                  const EC *__restrict__ cwb, float2 *__restrict__ A) {
+    extern __shared__ float2 sp[];  // kAttCol entries
+    const uint32_t x = blockIdx.x;
+    const int32_t c = attc_block_of(wg_first, nblk, x);
+    const uint32_t g = x - wg_first[c], wpb = wg_first[c + 1] - wg_first[c];
+    const int32_t base = c << kAttColBits;
+    const int32_t nb = min(kAttCol, K - base);
+    for (int32_t i = threadIdx.x; i < nb; i += kAttColThreads) sp[i] = pos[base + i];
+    __syncthreads();
+    constexpr uint32_t kWaves = kAttColThreads / kWave;
+    const uint32_t lane = threadIdx.x % kWave;
+    const uint32_t g0 = gfirst[c], g1 = gfirst[c + 1], qs = cstart[c], qe = cstart[c + 1];
+    for (uint32_t gi = g0 + g * kWaves + threadIdx.x / kWave; gi < g1; gi += wpb * kWaves) {
+        const uint32_t q = qs + (gi - g0) * kWave + lane;
+        if (q >= qe) continue;
+        const uint32_t t = it[q], len = il[q];
+        const float2 xi = pos[ir[q]];
+        const EC *e = cwb + gbase[gi] + lane;
+        float ax = 0.f, ay = 0.f;
+        uint32_t k = 0;
+        for (; k + 4 <= len; k += 4) {
+            EC v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = e[(k + u) * kWave];
+            float2 xv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) xv[u] = sp[fa2_entry_id(v[u])];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) fa2_entry_add(v[u], xv[u], xi, ax, ay);
+        }
+        for (; k < len; ++k) {
+            const EC v = e[k * kWave];
+            fa2_entry_add(v, sp[fa2_entry_id(v)], xi, ax, ay);
+        }
+        A[t] = make_float2(ax, ay);
+    }
+}
+
+static bgv_status attraction_cols(int32_t K, const float2 *pos, const CsrWs &csr, float2 *A, hipStream_t s) {
+    int32_t G = 1;
+    BGV_TRY(att_col_grid(K, &G));
+    const int32_t nblk = att_col_blocks(K);
+    const size_t lds = sizeof(float2) * (size_t)kAttCol;
+    if (csr.fmt == kCsrWeighted)
+        BGV_LAUNCH(k_attract_cols<int2>, dim3((unsigned)G), dim3(kAttColThreads), lds, s, K, nblk, csr.wg_first, pos,
+                   csr.it, csr.ir, csr.il, csr.cstart, csr.gfirst, csr.gbase, reinterpret_cast<const int2 *>(csr.cwb),
+                   A);
+    else
+        BGV_LAUNCH(k_attract_cols<uint16_t>, dim3((unsigned)G), dim3(kAttColThreads), lds, s, K, nblk, csr.wg_first,
+                   pos, csr.it, csr.ir, csr.il, csr.cstart, csr.gfirst, csr.gbase,
+                   reinterpret_cast<const uint16_t *>(csr.cwb), A);
+    return BGV_OK;
+}
+
 bgv_status attraction(int32_t K, const float2 *pos, const CsrWs &csr, float2 *A, hipStream_t s) {
+    if (att_cols(K)) return attraction_cols(K, pos, csr, A, s);
     if (K >= kAttLdsMin && K <= kAttLdsMax) {
         int cus = 1;
         BGV_TRY(device_cu_count(&cus));
@@ -610,8 +987,8 @@ __device__ __forceinline__ int delta(const uint32_t *__restrict__ code, int32_t 
 }
 
 // Internal node i of the binary radix tree over the sorted codes (Karras' parallel
-// construction).  Children: >= 0 internal node, < 0 leaf ~child.  nodeA = (centre of
-// mass, mass, size^2), size^2 < 0 for a node whose codes are all equal (a leaf cell).
+// construction).  Children: >= 0 internal node, < 0 leaf ~child.  Record half a = (centre
+// of mass, mass, size^2), size^2 < 0 for a node whose codes are all equal (a leaf cell).
 //
 // The radix tree refines the compressed quadtree of Section 3.1's hierarchical
 // partition: a node whose codes share a 2d-bit prefix and differ in the next bit is
@@ -623,11 +1000,17 @@ __device__ __forceinline__ int delta(const uint32_t *__restrict__ code, int32_t 
 // cell with its own side, so the opening decisions are those of the quadtree.  The
 // parent of the node over [first, last] has the longer of the prefixes shared across
 // the range's two ends (Karras' tree: the parent extends the range on that side).
+// A node's record: (centre of mass, mass, size^2) and (left, right, first, last) in 32
+// bytes, so a traversal step that reads a node touches one cache line.
+struct __align__(32) BhNode {
+    float4 a;
+    int4 b;
+};
+
 __device__ __forceinline__ void bh_build_nodes(int32_t K, const uint32_t *__restrict__ code,
                                                const double *__restrict__ PM, const double *__restrict__ PX,
                                                const double *__restrict__ PY, const float *__restrict__ s0p,
-                                               float4 *__restrict__ nodeA, int4 *__restrict__ nodeB, int32_t i0,
-                                               int32_t stride) {
+                                               BhNode *__restrict__ node, int32_t i0, int32_t stride) {
     const float s0 = *s0p;
     for (int32_t i = i0; i < K - 1; i += stride) {
         const int d = (delta(code, K, i, i + 1) - delta(code, K, i, i - 1)) >= 0 ? 1 : -1;
@@ -663,15 +1046,17 @@ __device__ __forceinline__ void bh_build_nodes(int32_t K, const uint32_t *__rest
             const float sz = s0 / (float)(1u << lev);
             size2 = sz * sz;
         }
-        nodeA[i] = make_float4((float)cx, (float)cy, (float)M, size2);
-        nodeB[i] = make_int4(left, right, first, last);
+        BhNode nd;
+        nd.a = make_float4((float)cx, (float)cy, (float)M, size2);
+        nd.b = make_int4(left, right, first, last);
+        node[i] = nd;
     }
 }
 
 __global__ void k_bh_build(int32_t K, const uint32_t *__restrict__ code, const double *__restrict__ PM,
                            const double *__restrict__ PX, const double *__restrict__ PY,
-                           const float *__restrict__ s0p, float4 *__restrict__ nodeA, int4 *__restrict__ nodeB) {
-    bh_build_nodes(K, code, PM, PX, PY, s0p, nodeA, nodeB, blockIdx.x * blockDim.x + threadIdx.x,
+                           const float *__restrict__ s0p, BhNode *__restrict__ node) {
+    bh_build_nodes(K, code, PM, PX, PY, s0p, node, blockIdx.x * blockDim.x + threadIdx.x,
                    gridDim.x * blockDim.x);
 }
 
@@ -685,15 +1070,15 @@ __global__ void __launch_bounds__(NT) k_bh_build_attract(int32_t K, const uint32
                                                           const double *__restrict__ PM,
                                                           const double *__restrict__ PX,
                                                           const double *__restrict__ PY,
-                                                          const float *__restrict__ s0p, float4 *__restrict__ nodeA,
-                                                          int4 *__restrict__ nodeB, int32_t build_blocks,
+                                                          const float *__restrict__ s0p, BhNode *__restrict__ node,
+                                                          int32_t build_blocks,
                                                           const float2 *__restrict__ pos,
                                                           const uint32_t *__restrict__ row, const E *__restrict__ cw,
                                                           const uint32_t *__restrict__ item_of,
                                                           const uint32_t *__restrict__ item_row,
                                                           float2 *__restrict__ A) {
     if ((int32_t)blockIdx.x < build_blocks) {  // uniform over the workgroup
-        bh_build_nodes(K, code, PM, PX, PY, s0p, nodeA, nodeB, blockIdx.x * NT + threadIdx.x, build_blocks * NT);
+        bh_build_nodes(K, code, PM, PX, PY, s0p, node, blockIdx.x * NT + threadIdx.x, build_blocks * NT);
         return;
     }
     const int64_t wave0 = ((int64_t)(blockIdx.x - build_blocks) * NT + threadIdx.x) / kWave;
@@ -715,7 +1100,11 @@ __device__ __forceinline__ void add_pair(float2 xi, float4 bj, float &fx, float 
 }
 
 constexpr int kBhThreads = 64;
-constexpr int kBhLanes = 8;  // lanes per body (16 and 32 measured slower on the 17.7k-body bench supergraph)
+// Lanes per body: few, so that few lanes idle when a body's stack is short, but enough
+// that the bodies' wavefronts fill the chip.  Measured on the 171,724-body lfr_3m
+// supergraph: 8 lanes 93 us per launch, 4 lanes 72, 2 lanes 71; on the 17,724-body
+// lfr_1m supergraph 8 lanes beat 16 and 32.
+static int bh_lanes(int32_t K) { return K >= 131072 ? 2 : K >= 65536 ? 4 : 8; }
 
 // Barnes-Hut repulsion.  Bodies are taken in Morton order, so the bodies of a wavefront
 // walk similar paths.  Each body has a shared stack and G lanes: they pop the top
@@ -739,8 +1128,7 @@ constexpr int kBhTreeLevels = 34;  // 32-bit Morton codes: root, 32 prefix lengt
 // workgroup's speed partial and its interaction tally are written and false returned.
 template <int G, int C>
 __device__ __forceinline__ bool bh_force_block(int32_t blk, int32_t K, const float4 *__restrict__ body,
-                                               const float4 *__restrict__ nodeA, const int4 *__restrict__ nodeB,
-                                               float theta2, const float2 *__restrict__ att,
+                                               const BhNode *__restrict__ node, float theta2, const float2 *__restrict__ att,
                                                const uint32_t *__restrict__ item_of, float kr, float kg,
                                                const float2 *__restrict__ fprev, float2 *__restrict__ F,
                                                double2 *__restrict__ part, uint32_t *__restrict__ icount) {
@@ -774,8 +1162,9 @@ __device__ __forceinline__ bool bh_force_block(int32_t blk, int32_t K, const flo
                 const int j = ~e;
                 if (j != r) add_pair(xi, body[j], fx, fy, ic);
             } else {
-                const float4 A = nodeA[e];
-                const int4 Bn = nodeB[e];
+                const BhNode nd = node[e];
+                const float4 A = nd.a;
+                const int4 Bn = nd.b;
                 if (A.w < 0.f) {  // a cell of equal codes: direct sum
                     for (int k = Bn.z; k <= Bn.w; ++k)
                         if (k != r) add_pair(xi, body[k], fx, fy, ic);
@@ -846,26 +1235,26 @@ __device__ __forceinline__ bool bh_force_block(int32_t blk, int32_t K, const flo
 }
 
 // The full stack: at most 2G entries of one depth (see above) on at most kBhTreeLevels
-// depths.  The fast launch gives each body kBhFastStack entries, so that several times
-// more wavefronts fit a compute unit's LDS; a workgroup whose walk would not fit
+// depths.  The fast launch gives each body 20 entries per lane (5 KiB of LDS per
+// wavefront whatever G is), so that several times more wavefronts fit a compute unit's
+// LDS than with the full stack; a workgroup whose walk would not fit
 // appends itself to a list, and k_bh_force_full redoes it with the full stack (the same
 // steps, so the same bits: results never depend on the capacity).
 template <int G>
 struct BhStack {
     static constexpr int kFull = 2 * G * kBhTreeLevels;
-    static constexpr int kFast = 160;
+    static constexpr int kFast = 20 * G;
 };
 
 template <int G>
 __global__ void __launch_bounds__(kBhThreads) k_bh_force(int32_t K, const float4 *__restrict__ body,
-                                                          const float4 *__restrict__ nodeA,
-                                                          const int4 *__restrict__ nodeB, float theta2,
+                                                          const BhNode *__restrict__ node, float theta2,
                                                           const float2 *__restrict__ att,
                                                           const uint32_t *__restrict__ item_of, float kr, float kg,
                                                           const float2 *__restrict__ fprev, float2 *__restrict__ F,
                                                           double2 *__restrict__ part, uint32_t *__restrict__ icount,
                                                           uint32_t *__restrict__ redo) {
-    const bool ovf = bh_force_block<G, BhStack<G>::kFast>((int32_t)blockIdx.x, K, body, nodeA, nodeB, theta2, att,
+    const bool ovf = bh_force_block<G, BhStack<G>::kFast>((int32_t)blockIdx.x, K, body, node, theta2, att,
                                                            item_of, kr, kg, fprev, F, part, icount);
     if (ovf && threadIdx.x == 0) redo[1 + atomicAdd(&redo[0], 1u)] = blockIdx.x;
 }
@@ -873,8 +1262,7 @@ __global__ void __launch_bounds__(kBhThreads) k_bh_force(int32_t K, const float4
 // The listed workgroups again with the full stack; redo[0] counts them.
 template <int G>
 __global__ void __launch_bounds__(kBhThreads) k_bh_force_full(int32_t K, const float4 *__restrict__ body,
-                                                               const float4 *__restrict__ nodeA,
-                                                               const int4 *__restrict__ nodeB, float theta2,
+                                                               const BhNode *__restrict__ node, float theta2,
                                                                const float2 *__restrict__ att,
                                                                const uint32_t *__restrict__ item_of, float kr,
                                                                float kg, const float2 *__restrict__ fprev,
@@ -883,7 +1271,7 @@ __global__ void __launch_bounds__(kBhThreads) k_bh_force_full(int32_t K, const f
                                                                const uint32_t *__restrict__ redo) {
     const uint32_t n = redo[0];
     for (uint32_t i = blockIdx.x; i < n; i += gridDim.x)
-        bh_force_block<G, BhStack<G>::kFull>((int32_t)redo[1 + i], K, body, nodeA, nodeB, theta2, att, item_of, kr,
+        bh_force_block<G, BhStack<G>::kFull>((int32_t)redo[1 + i], K, body, node, theta2, att, item_of, kr,
                                              kg, fprev, F, part, icount);
 }
 
@@ -920,7 +1308,7 @@ void prof_reset_counters() {
 }
 
 static int32_t bh_force_blocks(int32_t K) {
-    return (int32_t)(((int64_t)K * kBhLanes + kBhThreads - 1) / kBhThreads);
+    return (int32_t)(((int64_t)K * bh_lanes(K) + kBhThreads - 1) / kBhThreads);
 }
 constexpr int kBhFullBlocks = 64;  // workgroups of the full-stack redo launch (grid-stride over its list)
 
@@ -940,8 +1328,7 @@ struct BhWs {
     float4 *body;
     uint32_t *code;
     double *part3, *PM, *PX, *PY;
-    float4 *nodeA;
-    int4 *nodeB;
+    BhNode *node;
     uint32_t *icount;  // interactions per force workgroup, summed over the call's iterations
     uint32_t *redo;    // [0]: force workgroups to redo with the full stack, [1..]: their ids
     void *sort_scratch;
@@ -981,8 +1368,7 @@ static size_t fa_layout(Carver &c, int32_t K, int64_t E, const bgv_fa2_params *p
         b.PM = c.take<double>((size_t)K + 1);
         b.PX = c.take<double>((size_t)K + 1);
         b.PY = c.take<double>((size_t)K + 1);
-        b.nodeA = c.take<float4>((size_t)K);
-        b.nodeB = c.take<int4>((size_t)K);
+        b.node = c.take<BhNode>((size_t)K);
         b.icount = c.take<uint32_t>((size_t)bh_force_blocks(K));
         b.redo = c.take<uint32_t>((size_t)bh_force_blocks(K) + 1);
         b.sort_scratch = c.take<char>(onesweep_workspace(K));
@@ -1001,7 +1387,7 @@ static bgv_status launch_build_attract(int32_t K, const BhWs &b, unsigned build_
                                        size_t lds, const float2 *pos, const CsrWs &csr, float2 *A, hipStream_t s) {
     const auto k_bh_build_att = k_bh_build_attract<E, NT, kLds>;  // one name for the profiler
     BGV_LAUNCH(k_bh_build_att, dim3(build_blocks + att_blocks), dim3(NT), lds, s, K, b.code,
-               b.PM, b.PX, b.PY, b.s0, b.nodeA, b.nodeB, (int32_t)build_blocks, pos, csr.row,
+               b.PM, b.PX, b.PY, b.s0, b.node, (int32_t)build_blocks, pos, csr.row,
                reinterpret_cast<const E *>(csr.cw), csr.item_of, csr.item_row, A);
     return BGV_OK;
 }
@@ -1047,13 +1433,32 @@ static bgv_status bh_sorted_bodies(int32_t K, const float2 *pos, const float *ma
     return BGV_OK;
 }
 
+// The force launch and the redo of the workgroups whose walk outgrew the fast stack.
+template <int G>
+static bgv_status bh_force_launch(int32_t K, const BhWs &b, float theta, float kr, float kg, const float2 *fprev,
+                                  const CsrWs &csr, FaWs &w, hipStream_t s) {
+    const auto k_bh_force_g = k_bh_force<G>;  // one profiler name for every lane count
+    const auto k_bh_force_full_g = k_bh_force_full<G>;
+    BGV_LAUNCH(k_bh_force_g, dim3(bh_force_blocks(K)), dim3(kBhThreads), 0, s, K, b.body, b.node, theta * theta, w.A,
+               csr.item_of, kr, kg, fprev, w.F, w.part, b.icount, b.redo);
+    BGV_LAUNCH(k_bh_force_full_g, dim3(kBhFullBlocks), dim3(kBhThreads), 0, s, K, b.body, b.node, theta * theta, w.A,
+               csr.item_of, kr, kg, fprev, w.F, w.part, b.icount, b.redo);
+    return BGV_OK;
+}
+
 static bgv_status bh_forces(int32_t K, const float2 *pos, const float *mass, const CsrWs &csr, float theta, float kr,
                             float kg, const float2 *fprev, FaWs &w, hipStream_t s) {
     BhWs &b = w.bh;
     BGV_TRY(bh_sorted_bodies(K, pos, mass, b, s));
     // the tree and the attraction (which the force kernel combines), in one launch
     if (K > 1) {
-        if (K >= kAttLdsMin && K <= kAttLdsMax) {
+        if (att_cols(K)) {
+            // the tree, then the column-blocked attraction (a launch of its own: its
+            // workgroups take all of a compute unit's LDS)
+            BGV_LAUNCH(k_bh_build, dim3(grid_for(K - 1, kFaThreads, 65536)), dim3(kFaThreads), 0, s, K, b.code, b.PM,
+                       b.PX, b.PY, b.s0, b.node);
+            BGV_TRY(attraction_cols(K, pos, csr, w.A, s));
+        } else if (K >= kAttLdsMin && K <= kAttLdsMax) {
             int cus = 1;
             BGV_TRY(device_cu_count(&cus));
             const unsigned wg = (unsigned)((csr.items_bound + kAttLdsThreads / kWave - 1) / (kAttLdsThreads / kWave));
@@ -1066,11 +1471,11 @@ static bgv_status bh_forces(int32_t K, const float2 *pos, const float *mass, con
     } else {
         BGV_TRY(attraction(K, pos, csr, w.A, s));
     }
-    BGV_LAUNCH(k_bh_force<kBhLanes>, dim3(bh_force_blocks(K)), dim3(kBhThreads), 0, s, K, b.body, b.nodeA,
-               b.nodeB, theta * theta, w.A, csr.item_of, kr, kg, fprev, w.F, w.part, b.icount, b.redo);
-    BGV_LAUNCH(k_bh_force_full<kBhLanes>, dim3(kBhFullBlocks), dim3(kBhThreads), 0, s, K, b.body, b.nodeA, b.nodeB,
-               theta * theta, w.A, csr.item_of, kr, kg, fprev, w.F, w.part, b.icount, b.redo);
-    return BGV_OK;
+    switch (bh_lanes(K)) {
+        case 2: return bh_force_launch<2>(K, b, theta, kr, kg, fprev, csr, w, s);
+        case 4: return bh_force_launch<4>(K, b, theta, kr, kg, fprev, csr, w, s);
+        default: return bh_force_launch<8>(K, b, theta, kr, kg, fprev, csr, w, s);
+    }
 }
 
 }  // namespace bgv
@@ -1173,13 +1578,16 @@ extern "C" bgv_status bgv_bh_tree(int32_t K, const float *pos, const float *mass
     BGV_TRY(bh_sorted_bodies(K, x, mass, b, s));
     if (K > 1)
         BGV_LAUNCH(k_bh_build, dim3(grid_for(K - 1, kFaThreads, 65536)), dim3(kFaThreads), 0, s, K, b.code, b.PM,
-                   b.PX, b.PY, b.s0, b.nodeA, b.nodeB);
+                   b.PX, b.PY, b.s0, b.node);
     BGV_CHECK_HIP(hipMemcpyAsync(codes, b.code, sizeof(uint32_t) * (size_t)K, hipMemcpyDeviceToDevice, s));
     BGV_CHECK_HIP(hipMemcpyAsync(body, b.body, sizeof(float4) * (size_t)K, hipMemcpyDeviceToDevice, s));
     BGV_CHECK_HIP(hipMemcpyAsync(s0, b.s0, sizeof(float), hipMemcpyDeviceToDevice, s));
     if (K > 1) {
-        BGV_CHECK_HIP(hipMemcpyAsync(nodeA, b.nodeA, sizeof(float4) * (size_t)(K - 1), hipMemcpyDeviceToDevice, s));
-        BGV_CHECK_HIP(hipMemcpyAsync(nodeB, b.nodeB, sizeof(int4) * (size_t)(K - 1), hipMemcpyDeviceToDevice, s));
+        // the two halves of the node records, each to its own packed array
+        BGV_CHECK_HIP(hipMemcpy2DAsync(nodeA, sizeof(float4), reinterpret_cast<const char *>(b.node) + offsetof(BhNode, a), sizeof(BhNode), sizeof(float4),
+                                       (size_t)(K - 1), hipMemcpyDeviceToDevice, s));
+        BGV_CHECK_HIP(hipMemcpy2DAsync(nodeB, sizeof(int4), reinterpret_cast<const char *>(b.node) + offsetof(BhNode, b), sizeof(BhNode), sizeof(int4),
+                                       (size_t)(K - 1), hipMemcpyDeviceToDevice, s));
     }
     return BGV_OK;
 }
