@@ -22,6 +22,7 @@
 #include <climits>
 #include <cstddef>
 #include <cstring>
+#include <mutex>
 
 #include "block_scan.h"
 #include "common.h"
@@ -1446,18 +1447,39 @@ static bgv_status bh_force_launch(int32_t K, const BhWs &b, float theta, float k
     return BGV_OK;
 }
 
+// Streams of one layout call: the caller's, and (when the call may use it) a second one
+// on which the column-blocked attraction of an iteration runs beside that iteration's
+// sort and tree build, which leave most compute units idle; fork and join are two
+// events of the call.
+struct FaStreams {
+    hipStream_t s;
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+
 static bgv_status bh_forces(int32_t K, const float2 *pos, const float *mass, const CsrWs &csr, float theta, float kr,
-                            float kg, const float2 *fprev, FaWs &w, hipStream_t s) {
+                            float kg, const float2 *fprev, FaWs &w, const FaStreams &st) {
+    hipStream_t s = st.s;
     BhWs &b = w.bh;
+    const bool side = st.side && att_cols(K) && K > 1;
+    if (side) {  // the attraction reads only the positions: it can start at once
+        BGV_CHECK_HIP(hipEventRecord(st.fork, s));
+        BGV_CHECK_HIP(hipStreamWaitEvent(st.side, st.fork, 0));
+        BGV_TRY(attraction_cols(K, pos, csr, w.A, st.side));
+        BGV_CHECK_HIP(hipEventRecord(st.join, st.side));
+    }
     BGV_TRY(bh_sorted_bodies(K, pos, mass, b, s));
     // the tree and the attraction (which the force kernel combines), in one launch
     if (K > 1) {
         if (att_cols(K)) {
-            // the tree, then the column-blocked attraction (a launch of its own: its
-            // workgroups take all of a compute unit's LDS)
+            // the tree, and the column-blocked attraction in a launch of its own (its
+            // workgroups take most of a compute unit's LDS)
             BGV_LAUNCH(k_bh_build, dim3(grid_for(K - 1, kFaThreads, 65536)), dim3(kFaThreads), 0, s, K, b.code, b.PM,
                        b.PX, b.PY, b.s0, b.node);
-            BGV_TRY(attraction_cols(K, pos, csr, w.A, s));
+            if (side)
+                BGV_CHECK_HIP(hipStreamWaitEvent(s, st.join, 0));
+            else
+                BGV_TRY(attraction_cols(K, pos, csr, w.A, s));
         } else if (K >= kAttLdsMin && K <= kAttLdsMax) {
             int cus = 1;
             BGV_TRY(device_cu_count(&cus));
@@ -1489,9 +1511,69 @@ extern "C" size_t bgv_fa2_workspace(int32_t K, int64_t E, const bgv_fa2_params *
     return fa_layout(c, K, E, p, &w);
 }
 
+namespace bgv {
+
+// The second stream of each device (see FaStreams), created on first use outside graph
+// capture, at the default priority, kept until the process ends.  nullptr when it
+// cannot be had: the call then runs on the caller's stream alone, with the same results.
+static hipStream_t side_stream(hipStream_t main) {
+    static std::mutex mu;
+    static hipStream_t side[64] = {};
+    static bool tried[64] = {};
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(main, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return nullptr;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!tried[dev]) {
+        tried[dev] = true;
+        hipStream_t q = nullptr;
+        if (hipStreamCreateWithFlags(&q, hipStreamNonBlocking) == hipSuccess) side[dev] = q;
+    }
+    return side[dev];
+}
+
+// The iterations of one layout call (the loop of Algorithm 1).
+static bgv_status fa2_iterations(int32_t K, float2 *x, float2 *fp, const float *m, const bgv_fa2_params *p, FaWs &w,
+                                 int32_t nb, const FaStreams &st) {
+    hipStream_t s = st.s;
+    float4 *bbox = p->exact ? nullptr : w.bh.bbox;
+    if (bbox && p->iters > 0)
+        BGV_LAUNCH(k_bh_bbox, dim3(bh_update_blocks(K)), dim3(kFaThreads), 0, s, K, x, bbox);
+    for (int32_t it = 0; it < p->iters; ++it) {
+        if (p->exact) {
+            BGV_TRY(attraction(K, x, w.csr, w.A, s));
+            BGV_TRY(exact_forces(K, x, m, w.A, w.csr.item_of, p->kr, p->kg, fp, w.F, w.part, w.seg, s));
+        } else {
+            BGV_TRY(bh_forces(K, x, m, w.csr, p->theta, p->kr, p->kg, fp, w, st));  // attraction included
+        }
+        const int32_t nparts = p->exact ? nb : bh_force_blocks(K);
+        if (p->exact) {
+            BGV_LAUNCH(k_update, dim3(nb), dim3(kFaThreads), 0, s, K, x, fp, w.F, w.part, nparts, w.speed + (it & 1),
+                       w.speed + ((it + 1) & 1), p->tau, p->ks, p->ksmax, (float4 *)nullptr);
+        } else {
+            BGV_LAUNCH(k_bh_speed, dim3(1), dim3(kBhSpeedThreads), 0, s, w.part, nparts, w.speed + (it & 1),
+                       w.speed + ((it + 1) & 1), p->tau, w.bh.redo);
+            BGV_LAUNCH(k_bh_update, dim3(bh_update_blocks(K)), dim3(kFaThreads), 0, s, K, x, fp, w.F,
+                       w.speed + ((it + 1) & 1), p->ks, p->ksmax, bbox);
+        }
+    }
+    return BGV_OK;
+}
+
+}  // namespace bgv
+
 extern "C" bgv_status bgv_fa2_layout(int32_t K, int64_t E, const int32_t *edges, const float *attr_w,
                                      const float *mass, float *pos, float *fprev, float *speed,
                                      const bgv_fa2_params *p, void *ws, size_t ws_bytes, bgv_stream_t stream) {
+    return fa2_layout_run(K, E, edges, attr_w, mass, pos, fprev, speed, p, ws, ws_bytes, stream, true);
+}
+
+// One layout call; with may_fork the column-blocked attraction may run on the device's
+// second stream (the allocation-free entry point passes false: it creates nothing).
+bgv_status bgv::fa2_layout_run(int32_t K, int64_t E, const int32_t *edges, const float *attr_w, const float *mass,
+                               float *pos, float *fprev, float *speed, const bgv_fa2_params *p, void *ws,
+                               size_t ws_bytes, bgv_stream_t stream, bool may_fork) {
     clear_error();
     if (!fa_valid(K, E, p)) {
         set_error("bgv_fa2_layout: invalid arguments (K=%d E=%lld)", K, (long long)E);
@@ -1518,27 +1600,21 @@ extern "C" bgv_status bgv_fa2_layout(int32_t K, int64_t E, const int32_t *edges,
     float2 *fp = reinterpret_cast<float2 *>(fprev);
     const int32_t nb = (K + kFaThreads - 1) / kFaThreads;
     BGV_LAUNCH(k_copy_f32, dim3(1), dim3(1), 0, s, speed, w.speed);
-    float4 *bbox = p->exact ? nullptr : w.bh.bbox;
-    if (bbox && p->iters > 0)
-        BGV_LAUNCH(k_bh_bbox, dim3(bh_update_blocks(K)), dim3(kFaThreads), 0, s, K, x, bbox);
-    for (int32_t it = 0; it < p->iters; ++it) {
-        if (p->exact) {
-            BGV_TRY(attraction(K, x, w.csr, w.A, s));
-            BGV_TRY(exact_forces(K, x, m, w.A, w.csr.item_of, p->kr, p->kg, fp, w.F, w.part, w.seg, s));
-        } else {
-            BGV_TRY(bh_forces(K, x, m, w.csr, p->theta, p->kr, p->kg, fp, w, s));  // attraction included
-        }
-        const int32_t nparts = p->exact ? nb : bh_force_blocks(K);
-        if (p->exact) {
-            BGV_LAUNCH(k_update, dim3(nb), dim3(kFaThreads), 0, s, K, x, fp, w.F, w.part, nparts, w.speed + (it & 1),
-                       w.speed + ((it + 1) & 1), p->tau, p->ks, p->ksmax, (float4 *)nullptr);
-        } else {
-            BGV_LAUNCH(k_bh_speed, dim3(1), dim3(kBhSpeedThreads), 0, s, w.part, nparts, w.speed + (it & 1),
-                       w.speed + ((it + 1) & 1), p->tau, w.bh.redo);
-            BGV_LAUNCH(k_bh_update, dim3(bh_update_blocks(K)), dim3(kFaThreads), 0, s, K, x, fp, w.F,
-                       w.speed + ((it + 1) & 1), p->ks, p->ksmax, bbox);
+    FaStreams st;
+    st.s = s;
+    if (may_fork && !p->exact && att_cols(K) && K > 1 && p->iters > 0) {
+        st.side = side_stream(s);
+        if (st.side && (hipEventCreateWithFlags(&st.fork, hipEventDisableTiming) != hipSuccess ||
+                        hipEventCreateWithFlags(&st.join, hipEventDisableTiming) != hipSuccess)) {
+            if (st.fork) (void)hipEventDestroy(st.fork);
+            st = FaStreams{};
+            st.s = s;
         }
     }
+    const bgv_status rc = fa2_iterations(K, x, fp, m, p, w, nb, st);
+    if (st.fork) (void)hipEventDestroy(st.fork);
+    if (st.join) (void)hipEventDestroy(st.join);
+    BGV_TRY(rc);
     BGV_LAUNCH(k_copy_f32, dim3(1), dim3(1), 0, s, w.speed + (p->iters & 1), speed);
     if (!p->exact && p->iters > 0 && prof_on())
         BGV_LAUNCH(k_count_total, dim3(1), dim3(kFaThreads), 0, s, w.bh.icount, bh_force_blocks(K));

@@ -56,4 +56,11 @@ bgv_status attraction(int32_t K, const float2 *pos, const CsrWs &csr, float2 *A,
 bgv_status build_csr(int32_t K, int64_t E, const int32_t *edges, const float *attr_w, const float *mass_in,
                      CsrWs &w, hipStream_t s, const float **mass_out);
 
+// bgv_fa2_layout; may_fork lets the call run part of each iteration on a second stream
+// of the device (created once, on first use outside graph capture); results do not
+// depend on it.
+bgv_status fa2_layout_run(int32_t K, int64_t E, const int32_t *edges, const float *attr_w, const float *mass,
+                          float *pos, float *fprev, float *speed, const bgv_fa2_params *p, void *ws, size_t ws_bytes,
+                          bgv_stream_t stream, bool may_fork);
+
 }  // namespace bgv

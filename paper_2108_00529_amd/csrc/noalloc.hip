@@ -11,6 +11,7 @@
 #include <mutex>
 
 #include "common.h"
+#include "fa2_internal.h"
 
 namespace bgv {
 namespace {
@@ -70,6 +71,7 @@ extern "C" bgv_status bgv_fa2_layout_static(int32_t K, int64_t E, const int32_t 
     }
     void *ws = nullptr;
     BGV_TRY(scratch_address(&ws));
-    return bgv_fa2_layout(K, E, edges, attr_w, mass, pos, fprev, speed, p, ws, (size_t)BGV_FA2_STATIC_SCRATCH_BYTES,
-                          stream);
+    // on the caller's stream alone: no second stream or events are created
+    return fa2_layout_run(K, E, edges, attr_w, mass, pos, fprev, speed, p, ws, (size_t)BGV_FA2_STATIC_SCRATCH_BYTES,
+                          stream, false);
 }
