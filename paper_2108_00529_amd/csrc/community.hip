@@ -9,8 +9,8 @@
 // and, for many chunks, the back-pointer resolution of community_jump.hip (no barrier
 // per chunk; chosen by bgv_cd_params.method).
 //
-// Bucketed (n <= kCdMaxBuckets * kCdBucket): counters and labels in two int32 arrays
-// and no global atomics.  Nodes fall into buckets of kCdBucket consecutive ids.
+// Bucketed (n <= 2^24): counters and labels in two int32 arrays and no global atomics.
+// Nodes fall into buckets of 2^kB consecutive ids (kB = cd_bucket_bits(n)).
 //   group (pass 0)  each 2048-edge tile of a chunk writes its endpoints grouped by
 //                   bucket, one segment per (tile, bucket), offsets in a per-tile table
 //   decide          each 2048-edge tile writes its proposals (target, stream index,
@@ -138,17 +138,21 @@ __global__ void __launch_bounds__(kCdThreads) k_cd_finish(const int32_t *__restr
 }
 
 // ------------------------------------------------------------ bucketed path -------
-constexpr int kCdBucketBits = 12;
-constexpr int32_t kCdBucket = 1 << kCdBucketBits;  // node ids per bucket
-constexpr int32_t kCdMaxBuckets = 4096;             // bucket histogram held in LDS
+// Buckets of 2^12 consecutive node ids, or 2^13 from 2^21 nodes on: larger buckets halve
+// the (tile, bucket) segments each resolve walks but leave half as many resolve
+// workgroups (measured over the community passes and sketch: 3.2M nodes and 34M edges,
+// 13 bits 0.33 ms faster; 1M nodes and 10M edges, 12 bits 0.13 ms faster).
+constexpr int32_t kCdMaxNodes = 1 << 24;           // bucketed path up to here
+constexpr int32_t kCdMaxBuckets = kCdMaxNodes >> 12;  // bucket histogram held in LDS
+inline int cd_bucket_bits(int32_t n) { return n >= (1 << 21) ? 13 : 12; }
 // 2048-edge tiles of 1024 threads x 2 edges: fewer segments per resolve than 1024-edge
 // tiles, and shorter per-thread chains in the decide than 256 x 8 or 512 x 4 (community
 // passes on a 10M-edge stream: 0.87 ms; 256 x 8: 0.94; 256 x 4: 0.98; 256 x 16: 1.06)
 constexpr int kCdItems = 2;
 constexpr int32_t kCdTile = kCdThreads * kCdItems;  // edges per tile
 
-inline int32_t cd_buckets(int32_t n) { return (n + kCdBucket - 1) / kCdBucket; }
-inline bool cd_bucketed(int32_t n) { return cd_buckets(n) <= kCdMaxBuckets; }
+inline int32_t cd_buckets(int32_t n, int bits) { return (int32_t)(((int64_t)n + (1 << bits) - 1) >> bits); }
+inline bool cd_bucketed(int32_t n) { return n <= kCdMaxNodes; }
 
 // Tile-local grouping by bucket: hist[0, nb) holds each bucket's entry count; turns it
 // into exclusive offsets in place, writes them (and the total at [nb]) to the tile's
@@ -195,6 +199,7 @@ __global__ void __launch_bounds__(kCdThreads) k_cd_finish_b(const int32_t *__res
 
 // Endpoints of the non-loop edges of tile `tile` of chunk [cs, ce), grouped by bucket:
 // ends[tile * 2 * kCdTile + ...] holds their offsets within the bucket.
+template <int kB>
 __device__ __forceinline__ void cd_group_tile(const int2 *__restrict__ edges, int64_t cs, int64_t ce, int32_t tile,
                                               int32_t nb, uint16_t *__restrict__ ends, uint32_t *__restrict__ etab,
                                               uint32_t *hist, uint16_t *stage) {
@@ -212,8 +217,8 @@ __device__ __forceinline__ void cd_group_tile(const int2 *__restrict__ edges, in
             if (e.x != e.y) {
                 node[2 * j] = e.x;
                 node[2 * j + 1] = e.y;
-                rank[2 * j] = atomicAdd(&hist[e.x >> kCdBucketBits], 1u);
-                rank[2 * j + 1] = atomicAdd(&hist[e.y >> kCdBucketBits], 1u);
+                rank[2 * j] = atomicAdd(&hist[e.x >> kB], 1u);
+                rank[2 * j + 1] = atomicAdd(&hist[e.y >> kB], 1u);
             }
         }
     }
@@ -222,7 +227,7 @@ __device__ __forceinline__ void cd_group_tile(const int2 *__restrict__ edges, in
 #pragma unroll
     for (int q = 0; q < 2 * kCdItems; ++q)
         if (node[q] >= 0)
-            stage[hist[node[q] >> kCdBucketBits] + rank[q]] = (uint16_t)(node[q] & (kCdBucket - 1));
+            stage[hist[node[q] >> kB] + rank[q]] = (uint16_t)(node[q] & ((1 << kB) - 1));
     __syncthreads();
     uint16_t *out = ends + (int64_t)tile * (2 * kCdTile);
     for (uint32_t k = threadIdx.x; k < total; k += kCdThreads) out[k] = stage[k];
@@ -244,7 +249,7 @@ struct CdLater {
     int32_t n;     // how many of them the mask covers
 };
 
-template <int kMode>  // 0: only pass; 1: pass 0 of several; 2: a later pass; 3: a pass in the mask
+template <int kMode, int kB>  // kMode 0: only pass; 1: pass 0 of several; 2: a later pass; 3: a pass in the mask
 __device__ __forceinline__ void cd_decide_tile(const int32_t *__restrict__ cnt, const int32_t *__restrict__ labv,
                                                const int2 *__restrict__ edges,
                                                int2 *__restrict__ c1, uint8_t *__restrict__ mask, CdLater later,
@@ -294,7 +299,7 @@ __device__ __forceinline__ void cd_decide_tile(const int32_t *__restrict__ cnt, 
                 if (go) {
                     target[j] = u_low ? e.x : e.y;
                     lab[j] = labv[u_low ? e.y : e.x];
-                    rank[j] = atomicAdd(&hist[target[j] >> kCdBucketBits], 1u);
+                    rank[j] = atomicAdd(&hist[target[j] >> kB], 1u);
                 }
             }
         }
@@ -304,8 +309,8 @@ __device__ __forceinline__ void cd_decide_tile(const int32_t *__restrict__ cnt, 
 #pragma unroll
     for (int j = 0; j < kCdItems; ++j)
         if (target[j] >= 0)
-            stage[hist[target[j] >> kCdBucketBits] + rank[j]] =
-                make_uint3((uint32_t)(target[j] & (kCdBucket - 1)),
+            stage[hist[target[j] >> kB] + rank[j]] =
+                make_uint3((uint32_t)(target[j] & ((1 << kB) - 1)),
                            (uint32_t)(t0 + j * kCdThreads + threadIdx.x), (uint32_t)lab[j]);
     __syncthreads();
     uint3 *out = props + (int64_t)tile * kCdTile;
@@ -315,7 +320,7 @@ __device__ __forceinline__ void cd_decide_tile(const int32_t *__restrict__ cnt, 
 // One launch per chunk: decide chunk [cs, ce) (kMode >= 0) and, in pass 0, group the
 // endpoints of the next chunk [gs, ge) for the counter increments of the resolve that
 // follows; workgroup x takes tile x of each.
-template <int kMode>  // -1: grouping only
+template <int kMode, int kB>  // kMode -1: grouping only
 __global__ void __launch_bounds__(kCdThreads) k_cd_step(const int32_t *__restrict__ cnt,
                                                          const int32_t *__restrict__ labv,
                                                          const int2 *__restrict__ edges,
@@ -330,11 +335,11 @@ __global__ void __launch_bounds__(kCdThreads) k_cd_step(const int32_t *__restric
     __shared__ uint16_t estage[2 * kCdTile];
     const int32_t tile = (int32_t)blockIdx.x;
     if (kMode >= 0 && cs + (int64_t)tile * kCdTile < ce)  // uniform over the workgroup
-        cd_decide_tile<kMode < 0 ? 0 : kMode>(cnt, labv, edges, c1, mask, later, cs, ce, D, pass, tie, tile, nb,
-                                              props, ptab, hist, pstage);
+        cd_decide_tile<kMode < 0 ? 0 : kMode, kB>(cnt, labv, edges, c1, mask, later, cs, ce, D, pass, tie, tile,
+                                                  nb, props, ptab, hist, pstage);
     if (gs + (int64_t)tile * kCdTile < ge) {
         __syncthreads();  // hist is reused
-        cd_group_tile(edges, gs, ge, tile, nb, ends, etab, hist, estage);
+        cd_group_tile<kB>(edges, gs, ge, tile, nb, ends, etab, hist, estage);
     }
 }
 
@@ -373,6 +378,7 @@ __device__ __forceinline__ void cd_segment(const uint32_t *__restrict__ tab, int
     *q1 = row[b + 1];
 }
 
+template <int kB>
 __global__ void __launch_bounds__(kCdResolveThreads) k_cd_resolve(int32_t *__restrict__ cnt,
                                                                    int32_t *__restrict__ lab, int32_t n, int32_t nb,
                                                                    const uint3 *__restrict__ props,
@@ -380,11 +386,11 @@ __global__ void __launch_bounds__(kCdResolveThreads) k_cd_resolve(int32_t *__res
                                                                    const uint16_t *__restrict__ ends,
                                                                    const uint32_t *__restrict__ etab, int32_t etiles,
                                                                    int32_t lanes) {
-    __shared__ unsigned long long win[kCdBucket];
-    __shared__ uint32_t inc[kCdBucket];
+    __shared__ unsigned long long win[1 << kB];
+    __shared__ uint32_t inc[1 << kB];
     const int32_t b = cd_resolve_bucket((int32_t)blockIdx.x, nb);
     if (b >= nb) return;  // the grid is rounded up to a multiple of the XCD count
-    for (int32_t k = threadIdx.x; k < kCdBucket; k += kCdResolveThreads) {
+    for (int32_t k = threadIdx.x; k < (1 << kB); k += kCdResolveThreads) {
         win[k] = ~0ull;
         inc[k] = 0u;
     }
@@ -418,8 +424,8 @@ __global__ void __launch_bounds__(kCdResolveThreads) k_cd_resolve(int32_t *__res
         }
     }
     __syncthreads();
-    const int64_t base = (int64_t)b << kCdBucketBits;
-    const int32_t span = min(kCdBucket, n - (b << kCdBucketBits));
+    const int64_t base = (int64_t)b << kB;
+    const int32_t span = min(1 << kB, n - (b << kB));
     for (int32_t k = threadIdx.x; k < span; k += kCdResolveThreads) {
         const unsigned long long w = win[k];
         const uint32_t c = inc[k];
@@ -474,7 +480,7 @@ static size_t cd_layout(Carver &c, int32_t n, int64_t m, const bgv_cd_params *p,
     *w = CdWs{};
     if (cd_bucketed(n)) {
         const size_t tiles = (bb + kCdTile - 1) / kCdTile;
-        const size_t nb = (size_t)cd_buckets(n);
+        const size_t nb = (size_t)cd_buckets(n, 12);  // the larger of the two bucket counts
         w->cnt = c.take<int32_t>((size_t)n);
         w->lab = c.take<int32_t>((size_t)n);
         w->props = c.take<uint3>(tiles * kCdTile);
@@ -638,6 +644,92 @@ __global__ void k_cd_copy_labels(const int32_t *__restrict__ src, int32_t stride
         dst[v] = src[(int64_t)stride * v];
 }
 
+// The bucketed form, buckets of 2^kB node ids.
+template <int kB>
+static bgv_status cd_run_bucketed(int32_t n, int64_t m, const int2 *e2, const bgv_cd_params *p, const CdWs &w,
+                                  int32_t first, const int32_t *lab0, int32_t *labels, int32_t *degree,
+                                  int64_t *volume, int32_t *pass_labels, hipStream_t s) {
+    const int64_t B = p->chunk;
+    const int64_t nchunk = (m + B - 1) / B;
+    const int32_t nb = cd_buckets(n, kB);
+    // one profiler name per kernel, whatever the bucket size
+    const auto k_cd_resolve = bgv::k_cd_resolve<kB>;
+    const auto k_cd_group = k_cd_step<-1, kB>;
+    const auto k_cd_step0 = k_cd_step<0, kB>;
+    const auto k_cd_step1 = k_cd_step<1, kB>;
+    const auto k_cd_step2 = k_cd_step<2, kB>;
+    const auto k_cd_step3 = k_cd_step<3, kB>;
+    BGV_LAUNCH(k_cd_init_b, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, w.cnt, w.lab, n, lab0);
+    int32_t ptiles = 0;  // decide tiles whose proposals are not yet resolved
+    int32_t etiles = 0;  // grouped endpoint tiles whose increments are not yet added
+    auto tiles_of = [&](int64_t k) {
+        const int64_t len = (k + 1) * B < m ? B : m - k * B;
+        return (int32_t)((len + kCdTile - 1) / kCdTile);
+    };
+    if (nchunk > 0) {
+        // pass 0, chunk 0: its endpoints grouped before anything is decided
+        etiles = tiles_of(0);
+        BGV_LAUNCH(k_cd_group, dim3(etiles), dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1,
+                   (uint8_t *)nullptr, CdLater{}, (int64_t)0, (int64_t)0, 0, 0, 0, nb, w.props, w.ptab, (int64_t)0,
+                   std::min<int64_t>(B, m), w.ends, w.etab);
+    }
+    // passes 2 .. 1 + later.n are decided in pass 1 (their counters are known there);
+    // a run resumed after two or more passes has no pass 1 and decides each pass itself
+    CdLater later{};
+    later.n = w.mask && first <= 1 ? std::min(p->passes - 2, 4) : 0;
+    for (int q = 0; q < later.n; ++q) later.D[q] = pass_threshold(p->threshold, p->growth, q + 2);
+    for (int32_t pass = 0; pass < p->passes && (m > 0 || pass_labels); ++pass) {
+        // resumed after `first` passes: pass 0 only counts (threshold -1: no edge
+        // proposes), which yields the degrees and the per-edge pass-0 counters of the
+        // closed form; passes 1 .. first-1 are skipped
+        if (pass > 0 && pass < first) continue;
+        const int32_t D = pass == 0 && first > 0 ? -1 : pass_threshold(p->threshold, p->growth, pass);
+        for (int64_t k = 0; k < nchunk; ++k) {
+            const int64_t cs = k * B, ce = (cs + B < m) ? cs + B : m;
+            const int32_t tiles = tiles_of(k);
+            // proposals of the previous chunk and, in pass 0, this chunk's increments
+            if (ptiles > 0 || etiles > 0)
+                BGV_LAUNCH(k_cd_resolve, dim3(cd_resolve_grid(nb)), dim3(kCdResolveThreads), 0, s, w.cnt, w.lab, n, nb, w.props, w.ptab,
+                           ptiles, w.ends, w.etab, etiles, cd_resolve_lanes(std::max(ptiles, etiles)));
+            // counters are incremented in pass 0 only (later passes use the closed form):
+            // the next chunk's endpoints are grouped by this launch in pass 0
+            const bool group_next = pass == 0 && k + 1 < nchunk;
+            const int64_t gs = group_next ? ce : 0, ge = group_next ? std::min<int64_t>(ce + B, m) : 0;
+            const int32_t gtiles = group_next ? tiles_of(k + 1) : 0;
+            const dim3 grid((unsigned)std::max(tiles, gtiles));
+            if (p->passes == 1)
+                BGV_LAUNCH(k_cd_step0, grid, dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1, (uint8_t *)nullptr,
+                           later, cs, ce, D, pass, p->tie, nb, w.props, w.ptab, gs, ge, w.ends, w.etab);
+            else if (pass == 0)
+                BGV_LAUNCH(k_cd_step1, grid, dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1, (uint8_t *)nullptr,
+                           later, cs, ce, D, pass, p->tie, nb, w.props, w.ptab, gs, ge, w.ends, w.etab);
+            else if (pass >= 2 && pass < 2 + later.n)
+                BGV_LAUNCH(k_cd_step3, grid, dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1, w.mask, later, cs,
+                           ce, D, pass, p->tie, nb, w.props, w.ptab, gs, ge, w.ends, w.etab);
+            else
+                BGV_LAUNCH(k_cd_step2, grid, dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1,
+                           pass == 1 && later.n > 0 ? w.mask : (uint8_t *)nullptr, later, cs, ce, D, pass, p->tie,
+                           nb, w.props, w.ptab, gs, ge, w.ends, w.etab);
+            ptiles = tiles;
+            etiles = gtiles;
+        }
+        if (pass_labels) {
+            if (ptiles > 0)
+                BGV_LAUNCH(k_cd_resolve, dim3(cd_resolve_grid(nb)), dim3(kCdResolveThreads), 0, s, w.cnt, w.lab, n, nb, w.props,
+                           w.ptab, ptiles, w.ends, w.etab, 0, cd_resolve_lanes(ptiles));
+            ptiles = 0;
+            BGV_LAUNCH(k_cd_copy_labels, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, w.lab, 1,
+                       n, pass_labels + (int64_t)pass * n);
+        }
+    }
+    if (ptiles > 0)
+        BGV_LAUNCH(k_cd_resolve, dim3(cd_resolve_grid(nb)), dim3(kCdResolveThreads), 0, s, w.cnt, w.lab, n, nb, w.props, w.ptab, ptiles, w.ends,
+                   w.etab, 0, cd_resolve_lanes(ptiles));
+    BGV_LAUNCH(k_cd_finish_b, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, w.cnt, w.lab, n,
+               labels, degree, reinterpret_cast<unsigned long long *>(volume));
+    return BGV_OK;
+}
+
 // The passes; with pass_labels, the labels after each pass are copied to row p (the
 // last chunk's proposals are then resolved at the end of its pass rather than with the
 // next pass's first chunk, which adds no counter increments, so nothing changes).
@@ -671,76 +763,9 @@ static bgv_status cd_run(int32_t n, int64_t m, const int32_t *edges, const bgv_c
     const int64_t nchunk = (m + B - 1) / B;
 
     if (cd_bucketed(n)) {
-        const int32_t nb = cd_buckets(n);
-        BGV_LAUNCH(k_cd_init_b, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, w.cnt, w.lab, n, lab0);
-        int32_t ptiles = 0;  // decide tiles whose proposals are not yet resolved
-        int32_t etiles = 0;  // grouped endpoint tiles whose increments are not yet added
-        auto tiles_of = [&](int64_t k) {
-            const int64_t len = (k + 1) * B < m ? B : m - k * B;
-            return (int32_t)((len + kCdTile - 1) / kCdTile);
-        };
-        if (nchunk > 0) {
-            // pass 0, chunk 0: its endpoints grouped before anything is decided
-            etiles = tiles_of(0);
-            BGV_LAUNCH(k_cd_step<-1>, dim3(etiles), dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1,
-                       (uint8_t *)nullptr, CdLater{}, (int64_t)0, (int64_t)0, 0, 0, 0, nb, w.props, w.ptab, (int64_t)0,
-                       std::min<int64_t>(B, m), w.ends, w.etab);
-        }
-        // passes 2 .. 1 + later.n are decided in pass 1 (their counters are known there);
-        // a run resumed after two or more passes has no pass 1 and decides each pass itself
-        CdLater later{};
-        later.n = w.mask && first <= 1 ? std::min(p->passes - 2, 4) : 0;
-        for (int q = 0; q < later.n; ++q) later.D[q] = pass_threshold(p->threshold, p->growth, q + 2);
-        for (int32_t pass = 0; pass < p->passes && (m > 0 || pass_labels); ++pass) {
-            // resumed after `first` passes: pass 0 only counts (threshold -1: no edge
-            // proposes), which yields the degrees and the per-edge pass-0 counters of the
-            // closed form; passes 1 .. first-1 are skipped
-            if (pass > 0 && pass < first) continue;
-            const int32_t D = pass == 0 && first > 0 ? -1 : pass_threshold(p->threshold, p->growth, pass);
-            for (int64_t k = 0; k < nchunk; ++k) {
-                const int64_t cs = k * B, ce = (cs + B < m) ? cs + B : m;
-                const int32_t tiles = tiles_of(k);
-                // proposals of the previous chunk and, in pass 0, this chunk's increments
-                if (ptiles > 0 || etiles > 0)
-                    BGV_LAUNCH(k_cd_resolve, dim3(cd_resolve_grid(nb)), dim3(kCdResolveThreads), 0, s, w.cnt, w.lab, n, nb, w.props, w.ptab,
-                               ptiles, w.ends, w.etab, etiles, cd_resolve_lanes(std::max(ptiles, etiles)));
-                // counters are incremented in pass 0 only (later passes use the closed form):
-                // the next chunk's endpoints are grouped by this launch in pass 0
-                const bool group_next = pass == 0 && k + 1 < nchunk;
-                const int64_t gs = group_next ? ce : 0, ge = group_next ? std::min<int64_t>(ce + B, m) : 0;
-                const int32_t gtiles = group_next ? tiles_of(k + 1) : 0;
-                const dim3 grid((unsigned)std::max(tiles, gtiles));
-                if (p->passes == 1)
-                    BGV_LAUNCH(k_cd_step<0>, grid, dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1, (uint8_t *)nullptr,
-                               later, cs, ce, D, pass, p->tie, nb, w.props, w.ptab, gs, ge, w.ends, w.etab);
-                else if (pass == 0)
-                    BGV_LAUNCH(k_cd_step<1>, grid, dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1, (uint8_t *)nullptr,
-                               later, cs, ce, D, pass, p->tie, nb, w.props, w.ptab, gs, ge, w.ends, w.etab);
-                else if (pass >= 2 && pass < 2 + later.n)
-                    BGV_LAUNCH(k_cd_step<3>, grid, dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1, w.mask, later, cs,
-                               ce, D, pass, p->tie, nb, w.props, w.ptab, gs, ge, w.ends, w.etab);
-                else
-                    BGV_LAUNCH(k_cd_step<2>, grid, dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1,
-                               pass == 1 && later.n > 0 ? w.mask : (uint8_t *)nullptr, later, cs, ce, D, pass, p->tie,
-                               nb, w.props, w.ptab, gs, ge, w.ends, w.etab);
-                ptiles = tiles;
-                etiles = gtiles;
-            }
-            if (pass_labels) {
-                if (ptiles > 0)
-                    BGV_LAUNCH(k_cd_resolve, dim3(cd_resolve_grid(nb)), dim3(kCdResolveThreads), 0, s, w.cnt, w.lab, n, nb, w.props,
-                               w.ptab, ptiles, w.ends, w.etab, 0, cd_resolve_lanes(ptiles));
-                ptiles = 0;
-                BGV_LAUNCH(k_cd_copy_labels, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, w.lab, 1,
-                           n, pass_labels + (int64_t)pass * n);
-            }
-        }
-        if (ptiles > 0)
-            BGV_LAUNCH(k_cd_resolve, dim3(cd_resolve_grid(nb)), dim3(kCdResolveThreads), 0, s, w.cnt, w.lab, n, nb, w.props, w.ptab, ptiles, w.ends,
-                       w.etab, 0, cd_resolve_lanes(ptiles));
-        BGV_LAUNCH(k_cd_finish_b, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, w.cnt, w.lab, n,
-                   labels, degree, reinterpret_cast<unsigned long long *>(volume));
-        return BGV_OK;
+        if (cd_bucket_bits(n) == 13)
+            return cd_run_bucketed<13>(n, m, e2, p, w, first, lab0, labels, degree, volume, pass_labels, s);
+        return cd_run_bucketed<12>(n, m, e2, p, w, first, lab0, labels, degree, volume, pass_labels, s);
     }
 
     NodeState *st = w.st;

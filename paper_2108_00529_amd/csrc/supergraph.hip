@@ -350,21 +350,25 @@ __global__ void k_sg_sketch_pairs(const int32_t *__restrict__ superedges, const 
     }
 }
 
-// Sketch 2 without global atomics, for sketches of at most kSkMaxBuckets buckets of
-// kSkBucket consecutive cells (cell = row * cols + column).  Each tile of kSkTile
+// Sketch 2 without global atomics, for sketches of at most kSkMaxCells cells, in buckets
+// of 2^kB consecutive cells (cell = row * cols + column).  Each tile of kSkTile
 // distinct pairs writes its (cell offset in bucket, multiplicity) entries grouped by
 // bucket, one segment per (tile, bucket), offsets in a per-tile table row; then one
 // workgroup per bucket sums its segments from every tile in LDS and writes the
 // bucket's cells, all of them, so the sketch needs no clearing.  Same integer sums.
-constexpr int kSkBucketBits = 14;
-constexpr int32_t kSkBucket = 1 << kSkBucketBits;
-constexpr int32_t kSkMaxBuckets = 4096;
+// Buckets of 2^14 cells, or 2^15 from 2^23 cells on (the 128 KiB of LDS counters leave
+// one resolve workgroup per compute unit, but halve the (tile, bucket) segments and the
+// grouping's per-tile bucket table; measured with the community buckets above).
+constexpr int32_t kSkMaxCells = 1 << 26;             // grouped sketch 2 up to here
+constexpr int32_t kSkMaxBuckets = kSkMaxCells >> 14;  // bucket histogram held in LDS
+inline int sk_bucket_bits(int64_t cells) { return cells >= (1 << 23) ? 15 : 14; }
 constexpr int kSkItems = 4;
 constexpr int32_t kSkTile = kSgThreads * kSkItems;
 constexpr int kSkResolveThreads = 1024;
 
-inline int64_t sk_buckets(int64_t cells) { return (cells + kSkBucket - 1) / kSkBucket; }
+inline int64_t sk_buckets(int64_t cells, int bits) { return (cells + (1ll << bits) - 1) >> bits; }
 
+template <int kB>
 __global__ void __launch_bounds__(kSgThreads) k_sg_group_pairs(const int32_t *__restrict__ superedges,
                                                                 const uint32_t *__restrict__ run_start,
                                                                 const uint32_t *__restrict__ Ep,
@@ -395,7 +399,7 @@ __global__ void __launch_bounds__(kSgThreads) k_sg_group_pairs(const int32_t *__
             for (int r = 0; r < kMaxRows; ++r)
                 if (r < rows) {
                     const uint32_t cell = (uint32_t)r * cols + col_pair(h.a[r], h.b[r], h.c[r], la[u], lb[u], cols);
-                    rank[u][r] = atomicAdd(&hist[cell >> kSkBucketBits], 1u);
+                    rank[u][r] = atomicAdd(&hist[cell >> kB], 1u);
                 }
         }
     }
@@ -424,9 +428,9 @@ __global__ void __launch_bounds__(kSgThreads) k_sg_group_pairs(const int32_t *__
                 if (r < rows) {
                     const uint32_t cell = (uint32_t)r * cols + col_pair(h.a[r], h.b[r], h.c[r], la[u], lb[u], cols);
                     // (pair within the tile, cell within the bucket), the pair's multiplicity
-                    stage[hist[cell >> kSkBucketBits] + rank[u][r]] =
-                        make_uint2(((uint32_t)(u * kSgThreads + threadIdx.x) << kSkBucketBits) |
-                                       (cell & (kSkBucket - 1)),
+                    stage[hist[cell >> kB] + rank[u][r]] =
+                        make_uint2(((uint32_t)(u * kSgThreads + threadIdx.x) << kB) |
+                                       (cell & ((1 << kB) - 1)),
                                    cnt[u]);
                 }
         }
@@ -452,21 +456,22 @@ inline int32_t sk_sum_lanes(int64_t tiles) {
 // resolve): neighbouring buckets' segments share cache lines.
 constexpr int32_t kSgXcds = 8;
 
+template <int kB>
 __global__ void __launch_bounds__(kSkResolveThreads) k_sg_sum_cells(uint2 *__restrict__ ent,
                                                                      const uint32_t *__restrict__ etab,
                                                                      const uint32_t *__restrict__ Ep, int32_t rows,
                                                                      int32_t nb, int64_t cells, int32_t lanes,
                                                                      uint32_t *__restrict__ M2) {
-    __shared__ uint32_t acc[kSkBucket];
+    __shared__ uint32_t acc[1 << kB];
     const int32_t x = (int32_t)blockIdx.x;
     const int32_t b = (x % kSgXcds) * ((nb + kSgXcds - 1) / kSgXcds) + x / kSgXcds;
     if (b >= nb) return;  // the grid is rounded up to a multiple of the XCD count
-    for (int32_t k = threadIdx.x; k < kSkBucket; k += kSkResolveThreads) acc[k] = 0u;
+    for (int32_t k = threadIdx.x; k < (1 << kB); k += kSkResolveThreads) acc[k] = 0u;
     __syncthreads();
     const int64_t tiles = ((int64_t)*Ep + kSkTile - 1) / kSkTile;
     const int64_t groups = kSkResolveThreads / lanes;
     const uint32_t sub = threadIdx.x % lanes, L = (uint32_t)lanes;
-    constexpr uint32_t kCell = kSkBucket - 1;
+    constexpr uint32_t kCell = (1u << kB) - 1;
     for (int64_t t = threadIdx.x / lanes; t < tiles; t += groups) {
         const uint32_t *row = etab + t * (nb + 1);
         const uint32_t q0 = row[b], q1 = row[b + 1];
@@ -482,8 +487,8 @@ __global__ void __launch_bounds__(kSkResolveThreads) k_sg_sum_cells(uint2 *__res
         }
     }
     __syncthreads();
-    const int64_t base = (int64_t)b << kSkBucketBits;
-    const int32_t span = (int32_t)min((int64_t)kSkBucket, cells - base);
+    const int64_t base = (int64_t)b << kB;
+    const int32_t span = (int32_t)min((int64_t)1 << kB, cells - base);
     for (int32_t k = threadIdx.x; k < span; k += kSkResolveThreads) M2[base + k] = acc[k];
     for (int64_t t = threadIdx.x / lanes; t < tiles; t += groups) {
         const uint32_t *row = etab + t * (nb + 1);
@@ -505,6 +510,7 @@ inline unsigned sg_sum_grid(int32_t nb) { return (unsigned)((nb + kSgXcds - 1) /
 
 // Superedge weight = count-min estimate, the minimum over the rows of the final cell
 // values k_sg_sum_cells left in the tile's entries (one per pair and row).
+template <int kB>
 __global__ void __launch_bounds__(kSgThreads) k_sg_pair_min(const uint2 *__restrict__ ent,
                                                              const uint32_t *__restrict__ etab,
                                                              const uint32_t *__restrict__ Ep, int32_t rows, int32_t nb,
@@ -519,7 +525,7 @@ __global__ void __launch_bounds__(kSgThreads) k_sg_pair_min(const uint2 *__restr
     const uint2 *seg = ent + (int64_t)blockIdx.x * (kSkTile * rows);
     for (uint32_t k = threadIdx.x; k < total; k += kSgThreads) {
         const uint2 v = seg[k];
-        atomicMin(&best[v.x >> kSkBucketBits], v.y);
+        atomicMin(&best[v.x >> kB], v.y);
     }
     __syncthreads();
     const int32_t cnt = (int32_t)min((int64_t)kSkTile, E - j0);
@@ -590,8 +596,8 @@ static size_t sg_layout(Carver &c, int32_t n, int64_t m, int32_t rows, int64_t c
         w->lent = c.take<uint2>(tiles * kLbTile);
         w->ltab = c.take<uint32_t>(tiles * (size_t)(lb_buckets(n) + 1));
     }
-    const int64_t nb = sk_buckets(cells);
-    if (nb <= kSkMaxBuckets) {
+    const int64_t nb = sk_buckets(cells, 14);  // the larger of the two bucket counts
+    if (cells <= kSkMaxCells) {
         // distinct pairs <= m: a tile bound, rows entries per pair
         const size_t tiles = (size_t)((mm + kSkTile - 1) / kSkTile);
         w->ent = c.take<uint2>(tiles * kSkTile * (size_t)rows);
@@ -613,6 +619,26 @@ static bgv_status sg_readback(SgReadback **out) {
         BGV_CHECK_HIP(hipEventCreateWithFlags(&rb.ev, hipEventDisableTiming));
     }
     *out = &rb;
+    return BGV_OK;
+}
+
+// Sketch 2 by grouped entries (buckets of 2^kB cells) and the superedge weights.
+template <int kB>
+static bgv_status sg_sketch2_grouped(int64_t m, const SgWs &w, const int32_t *superedges,
+                                     const unsigned long long *nkeys_d, const int32_t *super_label, HashRows h2,
+                                     int32_t rows, uint32_t cols, int64_t cells, uint32_t *se_count, uint32_t *M2,
+                                     uint32_t *se_weight, hipStream_t s) {
+    const int32_t nb = (int32_t)sk_buckets(cells, kB);
+    const unsigned tiles = (unsigned)((m + kSkTile - 1) / kSkTile);  // a bound: the pair count is on the device
+    const auto k_sg_group_pairs = bgv::k_sg_group_pairs<kB>;  // one profiler name per kernel
+    const auto k_sg_sum_cells = bgv::k_sg_sum_cells<kB>;
+    const auto k_sg_pair_min = bgv::k_sg_pair_min<kB>;
+    BGV_LAUNCH(k_sg_group_pairs, dim3(tiles), dim3(kSgThreads), 0, s, superedges, w.run_start, &w.counters[1],
+               nkeys_d, super_label, h2, rows, cols, nb, w.ent, w.etab, se_count);
+    BGV_LAUNCH(k_sg_sum_cells, dim3(sg_sum_grid(nb)), dim3(kSkResolveThreads), 0, s, w.ent, w.etab, &w.counters[1],
+               rows, nb, cells, sk_sum_lanes(tiles), M2);
+    BGV_LAUNCH(k_sg_pair_min, dim3(tiles), dim3(kSgThreads), 0, s, w.ent, w.etab, &w.counters[1], rows, nb,
+               se_weight);
     return BGV_OK;
 }
 
@@ -756,15 +782,12 @@ extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges,
             BGV_LAUNCH(k_sg_unique_write<uint64_t>, dim3(ut), dim3(kSgThreads), 0, s, sorted, nkeys_d, w.utile,
                        kbits, superedges, w.run_start);
         if (grouped_sketch) {
-            const int32_t nb = (int32_t)sk_buckets(cells);
-            BGV_LAUNCH(k_sg_group_pairs, dim3((unsigned)((m + kSkTile - 1) / kSkTile)), dim3(kSgThreads), 0, s,
-                       superedges, w.run_start, &w.counters[1], nkeys_d, super_label, h2, rows, cols, nb, w.ent,
-                       w.etab, se_count);
-            // the tile count is on the device; the edge count bounds it
-            BGV_LAUNCH(k_sg_sum_cells, dim3(sg_sum_grid(nb)), dim3(kSkResolveThreads), 0, s, w.ent, w.etab,
-                       &w.counters[1], rows, nb, cells, sk_sum_lanes((m + kSkTile - 1) / kSkTile), M2);
-            BGV_LAUNCH(k_sg_pair_min, dim3((unsigned)((m + kSkTile - 1) / kSkTile)), dim3(kSgThreads), 0, s, w.ent,
-                       w.etab, &w.counters[1], rows, nb, se_weight);
+            if (sk_bucket_bits(cells) == 15)
+                BGV_TRY(sg_sketch2_grouped<15>(m, w, superedges, nkeys_d, super_label, h2, rows, cols, cells, se_count,
+                                               M2, se_weight, s));
+            else
+                BGV_TRY(sg_sketch2_grouped<14>(m, w, superedges, nkeys_d, super_label, h2, rows, cols, cells, se_count,
+                                               M2, se_weight, s));
         } else {
             BGV_LAUNCH(k_sg_sketch_pairs, dim3(gk), dim3(kSgThreads), 0, s, superedges, w.run_start, &w.counters[1],
                        nkeys_d, super_label, h2, rows, cols, M2, se_count);
