@@ -1247,6 +1247,8 @@ struct BhStack {
     static constexpr int kFast = 20 * G;
 };
 
+constexpr int32_t kBhXcds = 8;
+
 template <int G>
 __global__ void __launch_bounds__(kBhThreads) k_bh_force(int32_t K, const float4 *__restrict__ body,
                                                           const BhNode *__restrict__ node, float theta2,
@@ -1255,9 +1257,16 @@ __global__ void __launch_bounds__(kBhThreads) k_bh_force(int32_t K, const float4
                                                           const float2 *__restrict__ fprev, float2 *__restrict__ F,
                                                           double2 *__restrict__ part, uint32_t *__restrict__ icount,
                                                           uint32_t *__restrict__ redo) {
-    const bool ovf = bh_force_block<G, BhStack<G>::kFast>((int32_t)blockIdx.x, K, body, node, theta2, att,
-                                                           item_of, kr, kg, fprev, F, part, icount);
-    if (ovf && threadIdx.x == 0) redo[1 + atomicAdd(&redo[0], 1u)] = blockIdx.x;
+    // workgroups are dealt to the eight XCDs in turn; each XCD takes a contiguous eighth
+    // of the bodies (in Morton order: a region of the plane), so its L2 holds the nodes
+    // that region's walks visit rather than the whole tree
+    const int32_t nblk = (int32_t)((K * (int64_t)G + kBhThreads - 1) / kBhThreads);
+    const int32_t per = (nblk + kBhXcds - 1) / kBhXcds;
+    const int32_t blk = ((int32_t)blockIdx.x % kBhXcds) * per + (int32_t)blockIdx.x / kBhXcds;
+    if (blk >= nblk) return;  // the grid is rounded up to a multiple of the XCD count
+    const bool ovf = bh_force_block<G, BhStack<G>::kFast>(blk, K, body, node, theta2, att, item_of, kr, kg, fprev,
+                                                           F, part, icount);
+    if (ovf && threadIdx.x == 0) redo[1 + atomicAdd(&redo[0], 1u)] = (uint32_t)blk;
 }
 
 // The listed workgroups again with the full stack; redo[0] counts them.
@@ -1440,7 +1449,8 @@ static bgv_status bh_force_launch(int32_t K, const BhWs &b, float theta, float k
                                   const CsrWs &csr, FaWs &w, hipStream_t s) {
     const auto k_bh_force_g = k_bh_force<G>;  // one profiler name for every lane count
     const auto k_bh_force_full_g = k_bh_force_full<G>;
-    BGV_LAUNCH(k_bh_force_g, dim3(bh_force_blocks(K)), dim3(kBhThreads), 0, s, K, b.body, b.node, theta * theta, w.A,
+    const unsigned grid = (unsigned)((bh_force_blocks(K) + kBhXcds - 1) / kBhXcds * kBhXcds);
+    BGV_LAUNCH(k_bh_force_g, dim3(grid), dim3(kBhThreads), 0, s, K, b.body, b.node, theta * theta, w.A,
                csr.item_of, kr, kg, fprev, w.F, w.part, b.icount, b.redo);
     BGV_LAUNCH(k_bh_force_full_g, dim3(kBhFullBlocks), dim3(kBhThreads), 0, s, K, b.body, b.node, theta * theta, w.A,
                csr.item_of, kr, kg, fprev, w.F, w.part, b.icount, b.redo);
