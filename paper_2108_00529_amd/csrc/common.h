@@ -161,21 +161,21 @@ bool radix_few_tiles(int64_t n, int64_t *tiles, int *items);
 void radix_pass0_buffers(void *scratch, int64_t n, uint32_t **counts0, uint32_t **clear1);
 
 // One-sweep sort of 32-bit keys with 32-bit values (all 32 bits, four 8-bit passes, one
-// launch per pass after a counting launch and a bases launch; see primitives.hip).
-// keys/alt and vals/vals_alt are ping-pong buffers of n entries; after the four passes
-// the result is back in keys/vals.  Scratch from onesweep_workspace(n).  With counted =
-// true a producer of the keys has already written what the counting launch would:
-// for tiles of 256 * os_items(n) consecutive keys, the four digits' counts per tile
-// (OsBuffers::counts[tile*1024 + pass*256 + d]) and zeros over OsBuffers::status
-// (status_words words).
+// launch per pass after a counting launch; see primitives.hip).  keys/alt and
+// vals/vals_alt are ping-pong buffers of n entries; after the four passes the result is
+// back in keys/vals.  Scratch from onesweep_workspace(n).  With counted = true a
+// producer of the keys has already done what the counting launch would, for tiles of
+// 256 * os_items(n) consecutive keys: added each tile's digit counts of all four passes
+// into OsBuffers::totals[pass*256 + d] (which the caller had cleared before, in an
+// earlier launch) and written zeros over OsBuffers::status (status_words words).
 struct OsBuffers {
     int64_t tiles;
     int items;
-    uint32_t *counts;
-    uint32_t *gbase;
+    uint32_t *totals;  // kOsTotals words: keys per (pass, digit)
     uint32_t *status;
     int64_t status_words;
 };
+constexpr int kOsTotals = 4 * 256;
 int os_items(int64_t n);
 size_t onesweep_workspace(int64_t n);
 void onesweep_layout(void *scratch, int64_t n, int items, OsBuffers *b);

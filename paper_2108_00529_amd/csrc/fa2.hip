@@ -788,19 +788,29 @@ __global__ void __launch_bounds__(kBhSpeedThreads) k_bh_speed(const double2 *__r
 
 // ... and the update blocks read the result; each writes the bounding box of the
 // positions it moved.
+// The Morton sort's digit totals, which the next encoding launch adds into, cleared by
+// the launch before it (the bounding box before the first iteration, the update after
+// each one).
+__device__ __forceinline__ void bh_clear_totals(uint32_t *__restrict__ totals) {
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < kOsTotals; i += blockDim.x) totals[i] = 0u;
+}
+
 __global__ void __launch_bounds__(kFaThreads) k_bh_update(int32_t K, float2 *__restrict__ pos,
                                                            float2 *__restrict__ fprev, const float2 *__restrict__ F,
                                                            const float *__restrict__ speed, float ks, float ksmax,
-                                                           float4 *__restrict__ bbox_part) {
+                                                           float4 *__restrict__ bbox_part, uint32_t *__restrict__ totals) {
     float4 bb = fa2_move_tile((int32_t)blockIdx.x, (int32_t)gridDim.x, K, pos, fprev, F, *speed, ks, ksmax);
     bb = block_bbox(bb);
     if (threadIdx.x == 0) bbox_part[blockIdx.x] = bb;
+    bh_clear_totals(totals);
 }
 
 // ------------------------------------------------------------------ Barnes-Hut --
 // One bounding-box partial per block of kFaThreads positions (same grid as k_update).
 __global__ void __launch_bounds__(kFaThreads) k_bh_bbox(int32_t K, const float2 *__restrict__ pos,
-                                                         float4 *__restrict__ part) {
+                                                         float4 *__restrict__ part, uint32_t *__restrict__ totals) {
+    bh_clear_totals(totals);
     float4 bb = make_float4(kInf, -kInf, kInf, -kInf);
     for (int32_t i = blockIdx.x * kFaThreads + threadIdx.x; i < K; i += gridDim.x * kFaThreads) {
         const float2 p = pos[i];
@@ -870,7 +880,7 @@ __global__ void __launch_bounds__(kFaThreads) k_bh_codes_os(int32_t K, const flo
                                                              const float4 *__restrict__ part, int nparts,
                                                              uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
                                                              float *__restrict__ s0_out,
-                                                             uint32_t *__restrict__ counts,
+                                                             uint32_t *__restrict__ totals,
                                                              uint32_t *__restrict__ status, int64_t status_words) {
     __shared__ uint32_t hist[4][256];
     float xmin, ymin, s0;
@@ -895,7 +905,8 @@ __global__ void __launch_bounds__(kFaThreads) k_bh_codes_os(int32_t K, const flo
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 4; ++q) counts[(int64_t)blockIdx.x * 1024 + q * 256 + threadIdx.x] = hist[q][threadIdx.x];
+    for (int q = 0; q < 4; ++q)
+        if (hist[q][threadIdx.x]) atomicAdd(&totals[q * 256 + threadIdx.x], hist[q][threadIdx.x]);
 }
 
 // Bodies [256 g, 256 g + 256) in Morton order (one per thread) and the group totals of
@@ -1413,6 +1424,13 @@ static bgv_status build_attract(int32_t K, const BhWs &b, unsigned att_blocks, s
     return launch_build_attract<uint16_t, NT, kLds>(K, b, build_blocks, att_blocks, lds, pos, csr, A, s);
 }
 
+// The Morton sort's digit totals in the layout's sort scratch.
+static uint32_t *bh_sort_totals(const BhWs &b, int32_t K) {
+    OsBuffers ob;
+    onesweep_layout(b.sort_scratch, K, os_items(K), &ob);
+    return ob.totals;
+}
+
 // Morton codes of the positions, sorted, the bodies gathered in Morton order and the
 // FP64 prefix sums of their mass moments: everything the node build reads.
 static bgv_status bh_sorted_bodies(int32_t K, const float2 *pos, const float *mass, BhWs &b, hipStream_t s) {
@@ -1430,10 +1448,10 @@ static bgv_status bh_sorted_bodies(int32_t K, const float2 *pos, const float *ma
         onesweep_layout(b.sort_scratch, K, os_items(K), &ob);
         if (ob.items == 4)
             BGV_LAUNCH(k_bh_codes_os<4>, dim3((unsigned)ob.tiles), dim3(kFaThreads), 0, s, K, pos, b.bbox, nbox, keys,
-                       b.vals, b.s0, ob.counts, ob.status, ob.status_words);
+                       b.vals, b.s0, ob.totals, ob.status, ob.status_words);
         else
             BGV_LAUNCH(k_bh_codes_os<16>, dim3((unsigned)ob.tiles), dim3(kFaThreads), 0, s, K, pos, b.bbox, nbox, keys,
-                       b.vals, b.s0, ob.counts, ob.status, ob.status_words);
+                       b.vals, b.s0, ob.totals, ob.status, ob.status_words);
         BGV_TRY(onesweep_sort_u32(keys, keys_alt, b.vals, b.vals_alt, K, &sk, &sv, b.sort_scratch, s, true));
     } else {
         BGV_LAUNCH(k_bh_codes, dim3(1), dim3(kFaThreads), 0, s, K, pos, b.bbox, nbox, keys, b.vals, b.s0);
@@ -1549,7 +1567,7 @@ static bgv_status fa2_iterations(int32_t K, float2 *x, float2 *fp, const float *
     hipStream_t s = st.s;
     float4 *bbox = p->exact ? nullptr : w.bh.bbox;
     if (bbox && p->iters > 0)
-        BGV_LAUNCH(k_bh_bbox, dim3(bh_update_blocks(K)), dim3(kFaThreads), 0, s, K, x, bbox);
+        BGV_LAUNCH(k_bh_bbox, dim3(bh_update_blocks(K)), dim3(kFaThreads), 0, s, K, x, bbox, bh_sort_totals(w.bh, K));
     for (int32_t it = 0; it < p->iters; ++it) {
         if (p->exact) {
             BGV_TRY(attraction(K, x, w.csr, w.A, s));
@@ -1565,7 +1583,7 @@ static bgv_status fa2_iterations(int32_t K, float2 *x, float2 *fp, const float *
             BGV_LAUNCH(k_bh_speed, dim3(1), dim3(kBhSpeedThreads), 0, s, w.part, nparts, w.speed + (it & 1),
                        w.speed + ((it + 1) & 1), p->tau, w.bh.redo);
             BGV_LAUNCH(k_bh_update, dim3(bh_update_blocks(K)), dim3(kFaThreads), 0, s, K, x, fp, w.F,
-                       w.speed + ((it + 1) & 1), p->ks, p->ksmax, bbox);
+                       w.speed + ((it + 1) & 1), p->ks, p->ksmax, bbox, bh_sort_totals(w.bh, K));
         }
     }
     return BGV_OK;
@@ -1660,7 +1678,7 @@ extern "C" bgv_status bgv_bh_tree(int32_t K, const float *pos, const float *mass
     BhWs &b = w.bh;
     const float2 *x = reinterpret_cast<const float2 *>(pos);
     const unsigned nb = (unsigned)((K + kFaThreads - 1) / kFaThreads);
-    BGV_LAUNCH(k_bh_bbox, dim3(bh_update_blocks(K)), dim3(kFaThreads), 0, s, K, x, b.bbox);
+    BGV_LAUNCH(k_bh_bbox, dim3(bh_update_blocks(K)), dim3(kFaThreads), 0, s, K, x, b.bbox, bh_sort_totals(b, K));
     BGV_TRY(bh_sorted_bodies(K, x, mass, b, s));
     if (K > 1)
         BGV_LAUNCH(k_bh_build, dim3(grid_for(K - 1, kFaThreads, 65536)), dim3(kFaThreads), 0, s, K, b.code, b.PM,

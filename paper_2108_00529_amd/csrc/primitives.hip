@@ -406,8 +406,9 @@ bgv_status radix_sort_u32(uint32_t *keys, uint32_t *keys_alt, uint32_t *vals, ui
 // ----------------------------------------------------------- one-sweep radix sort ---
 // Stable LSD sort of 32-bit keys (with 32-bit values) in four 8-bit passes, one launch
 // per pass and no per-key device atomics.  Before the passes, every key's four digits
-// are counted per tile (os_count, or a producer of the keys doing the same) and the
-// digit bases over all keys are summed from those counts (k_os_bases).  In a pass each
+// are counted per tile and each tile adds its counts into the totals per (pass, digit)
+// (os_count, or a producer of the keys doing the same: one device atomic per tile and
+// digit); a pass's tiles scan the 256 totals of their pass for the digit bases.  In a pass each
 // tile takes its index in launch order from a counter (so every earlier tile has
 // started), ranks its keys by digit as the scatter above does, publishes its digit
 // counts, and finds how many keys of each digit precede it by walking back over the
@@ -439,26 +440,23 @@ void onesweep_layout(void *scratch, int64_t n, int items, OsBuffers *b) {
     char *p = static_cast<char *>(scratch);
     b->tiles = tiles;
     b->items = items;
-    b->counts = reinterpret_cast<uint32_t *>(p);
-    p += align_up(sizeof(uint32_t) * kOsPasses * 256 * (size_t)tiles);
-    b->gbase = reinterpret_cast<uint32_t *>(p);
-    p += align_up(sizeof(uint32_t) * kOsPasses * 256);
+    b->totals = reinterpret_cast<uint32_t *>(p);
+    p += align_up(sizeof(uint32_t) * kOsTotals);
     b->status = reinterpret_cast<uint32_t *>(p);  // passes x tiles x 256 words, then the pass counters
     b->status_words = (int64_t)kOsPasses * tiles * 256 + kOsPasses;
 }
 
 size_t onesweep_workspace(int64_t n) {
     const int64_t tiles = os_tiles(n > 0 ? n : 1, os_items(n));
-    return align_up(sizeof(uint32_t) * kOsPasses * 256 * (size_t)tiles) + align_up(sizeof(uint32_t) * kOsPasses * 256) +
+    return align_up(sizeof(uint32_t) * kOsTotals) +
            align_up(sizeof(uint32_t) * ((size_t)kOsPasses * tiles * 256 + kOsPasses));
 }
 
-// Digit counts of one tile's keys for all four passes (counts[tile*1024 + pass*256 + d],
-// one contiguous row per tile) and, spread over the grid, the clearing of the
-// look-back words.
+// Digit counts of one tile's keys for all four passes, added into the totals, and,
+// spread over the grid, the clearing of the look-back words.
 template <int ITEMS>
 __global__ void __launch_bounds__(kRsThreads) k_os_count(const uint32_t *__restrict__ keys, int64_t n,
-                                                          uint32_t *__restrict__ counts,
+                                                          uint32_t *__restrict__ totals,
                                                           uint32_t *__restrict__ status, int64_t status_words) {
     __shared__ uint32_t hist[kOsPasses][256];
 #pragma unroll
@@ -480,32 +478,14 @@ __global__ void __launch_bounds__(kRsThreads) k_os_count(const uint32_t *__restr
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < kOsPasses; ++q)
-        counts[(int64_t)blockIdx.x * (kOsPasses * 256) + q * 256 + threadIdx.x] = hist[q][threadIdx.x];
-}
-
-// gbase[pass*256 + d] = keys whose digit in that pass is below d: one block per pass,
-// thread d sums its digit's tile counts (one coalesced row per tile), then a block scan.
-__global__ void __launch_bounds__(256) k_os_bases(const uint32_t *__restrict__ counts, int64_t tiles,
-                                                  uint32_t *__restrict__ gbase) {
-    const int t = threadIdx.x, pass = blockIdx.x;
-    const uint32_t *col = counts + pass * 256 + t;
-    uint32_t tot = 0;
-    for (int64_t j0 = 0; j0 < tiles; j0 += 32) {  // 32 loads in flight per round trip
-        uint32_t c[32];
-#pragma unroll
-        for (int u = 0; u < 32; ++u) c[u] = j0 + u < tiles ? col[(j0 + u) * (kOsPasses * 256)] : 0u;
-#pragma unroll
-        for (int u = 0; u < 32; ++u) tot += c[u];
-    }
-    uint32_t all;
-    gbase[pass * 256 + t] = block_excl_scan<uint32_t>(tot, &all);
+        if (hist[q][threadIdx.x]) atomicAdd(&totals[q * 256 + threadIdx.x], hist[q][threadIdx.x]);
 }
 
 template <int ITEMS>
 __global__ void __launch_bounds__(kRsThreads) k_os_pass(const uint32_t *__restrict__ keys, uint32_t *__restrict__ keys_out,
                                                          const uint32_t *__restrict__ vals,
                                                          uint32_t *__restrict__ vals_out, int64_t n, int64_t tiles,
-                                                         int shift, const uint32_t *__restrict__ gbase,
+                                                         int shift, const uint32_t *__restrict__ totals,
                                                          uint32_t *status, uint32_t *counter) {
     constexpr int kTile = kRsThreads * ITEMS;
     __shared__ uint32_t s_tile;
@@ -516,6 +496,7 @@ __global__ void __launch_bounds__(kRsThreads) k_os_pass(const uint32_t *__restri
     __shared__ uint32_t sval[kTile];
     const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
     if (t == 0) s_tile = atomicAdd(counter, 1u);
+    const uint32_t tot = totals[t];  // keys of digit t in this pass
 #pragma unroll
     for (int q = 0; q < kRsWaves; ++q) hist[q][t] = 0;
     __syncthreads();
@@ -571,7 +552,8 @@ __global__ void __launch_bounds__(kRsThreads) k_os_pass(const uint32_t *__restri
         }
         os_publish(&status[tile * 256 + t], kOsInc | (excl + cnt_d));
     }
-    running[t] = gbase[t] + excl;
+    uint32_t all_keys;
+    running[t] = block_excl_scan<uint32_t>(tot, &all_keys) + excl;  // keys of lower digits, then earlier tiles
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
@@ -603,23 +585,23 @@ bgv_status onesweep_sort_u32(uint32_t *keys, uint32_t *keys_alt, uint32_t *vals,
     if (n > 1) {
         const unsigned tiles = (unsigned)b.tiles;
         if (!counted) {
+            BGV_TRY(fill<uint32_t>(b.totals, 0u, kOsTotals, s));
             if (b.items == 4)
-                BGV_LAUNCH(k_os_count<4>, dim3(tiles), dim3(kRsThreads), 0, s, src, n, b.counts, b.status,
+                BGV_LAUNCH(k_os_count<4>, dim3(tiles), dim3(kRsThreads), 0, s, src, n, b.totals, b.status,
                            b.status_words);
             else
-                BGV_LAUNCH(k_os_count<16>, dim3(tiles), dim3(kRsThreads), 0, s, src, n, b.counts, b.status,
+                BGV_LAUNCH(k_os_count<16>, dim3(tiles), dim3(kRsThreads), 0, s, src, n, b.totals, b.status,
                            b.status_words);
         }
-        BGV_LAUNCH(k_os_bases, dim3(kOsPasses), dim3(256), 0, s, b.counts, b.tiles, b.gbase);
         uint32_t *counters = b.status + (int64_t)kOsPasses * b.tiles * 256;
         for (int pass = 0; pass < kOsPasses; ++pass) {
             uint32_t *st = b.status + (int64_t)pass * b.tiles * 256;
             if (b.items == 4)
                 BGV_LAUNCH(k_os_pass<4>, dim3(tiles), dim3(kRsThreads), 0, s, src, dst, vsrc, vdst, n, b.tiles,
-                           8 * pass, b.gbase + 256 * pass, st, counters + pass);
+                           8 * pass, b.totals + 256 * pass, st, counters + pass);
             else
                 BGV_LAUNCH(k_os_pass<16>, dim3(tiles), dim3(kRsThreads), 0, s, src, dst, vsrc, vdst, n, b.tiles,
-                           8 * pass, b.gbase + 256 * pass, st, counters + pass);
+                           8 * pass, b.totals + 256 * pass, st, counters + pass);
             uint32_t *tk = src; src = dst; dst = tk;
             uint32_t *tv = vsrc; vsrc = vdst; vdst = tv;
         }
