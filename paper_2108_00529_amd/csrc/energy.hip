@@ -235,7 +235,7 @@ static int en_splits(int32_t K) {
 }
 
 static size_t en_layout(Carver &c, int32_t K, int64_t E, EnWs *w) {
-    csr_layout(c, K, E, &w->csr);
+    csr_layout(c, K, E, &w->csr, false);  // one evaluation per call: no column-blocked setup
     w->prep = c.take<double>((size_t)en_tri_blocks(K));
     w->patt = c.take<double>((size_t)en_edge_blocks(E));
     w->pgrav = c.take<double>((size_t)en_grav_blocks(K));

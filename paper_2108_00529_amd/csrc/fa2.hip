@@ -34,7 +34,7 @@ namespace bgv {
 constexpr int kFaThreads = 256;
 static_assert(kFaThreads == kFa2Tile, "the layout kernels work on 256-node tiles");
 
-// Column-blocked attraction (att_cols(K)): blocks of kAttCol consecutive neighbour ids,
+// Column-blocked attraction (CsrWs::cols): blocks of kAttCol consecutive neighbour ids,
 // whose positions fill 128 KiB of LDS; items of at most kAttCap entries of one row in
 // one block, summed by kAttColLanes lanes each.
 constexpr int kAttColBits = 14;
@@ -92,23 +92,24 @@ static int bits_for(int64_t K) {
     return kb;
 }
 
-int64_t att_items_cap(int32_t K, int64_t E) {
-    if (!att_cols(K)) return (int64_t)K + (2 * E) / kAttBlock + 1;
+int64_t att_items_cap(int32_t K, int64_t E, bool cols) {
+    if (!cols) return (int64_t)K + (2 * E) / kAttBlock + 1;
     // every row one item, every further block run one more, every kAttCap entries of a
     // run one more
     const int64_t runs = std::min<int64_t>(2 * E, (int64_t)K * att_col_blocks(K));
     return (int64_t)K + runs + (2 * E) / kAttCap + 1;
 }
 
-size_t csr_layout(Carver &c, int32_t K, int64_t E, CsrWs *w) {
+size_t csr_layout(Carver &c, int32_t K, int64_t E, CsrWs *w, bool allow_cols) {
     const int64_t nent = 2 * E > 0 ? 2 * E : 1;
     w->row = c.take<uint32_t>((size_t)K + 1);
     w->cw = c.take<int2>((size_t)nent);
     w->mass = c.take<float>((size_t)K);
-    w->items_bound = att_items_cap(K, E);
+    w->cols = allow_cols && att_cols(K);
+    w->items_bound = att_items_cap(K, E, w->cols);
     w->item_of = c.take<uint32_t>((size_t)K + 1);
     w->item_row = c.take<uint32_t>((size_t)w->items_bound);
-    const bool cols = att_cols(K);
+    const bool cols = w->cols;
     const int64_t nblk = cols ? att_col_blocks(K) : 0;
     // column-blocked entries: nent plus the padding of each block's groups, at most one
     // group's worth per block (lengths fall within a block, so a group's padding is at
@@ -438,7 +439,7 @@ bgv_status build_csr(int32_t K, int64_t E, const int32_t *edges, const float *at
                        w.cw);
         }
     }
-    if (att_cols(K)) {
+    if (w.cols) {
         if (w.fmt == kCsrWeighted)
             BGV_TRY((attc_setup<int2, int2>(K, 2 * E, w, s)));
         else if (w.fmt == kCsrIds32)
@@ -610,7 +611,7 @@ static bgv_status attraction_cols(int32_t K, const float2 *pos, const CsrWs &csr
 }
 
 bgv_status attraction(int32_t K, const float2 *pos, const CsrWs &csr, float2 *A, hipStream_t s) {
-    if (att_cols(K)) return attraction_cols(K, pos, csr, A, s);
+    if (csr.cols) return attraction_cols(K, pos, csr, A, s);
     if (K >= kAttLdsMin && K <= kAttLdsMax) {
         int cus = 1;
         BGV_TRY(device_cu_count(&cus));
@@ -1366,7 +1367,7 @@ struct FaWs {
 };
 
 static size_t fa_layout(Carver &c, int32_t K, int64_t E, const bgv_fa2_params *p, FaWs *w) {
-    csr_layout(c, K, E, &w->csr);
+    csr_layout(c, K, E, &w->csr, true);
     const int64_t nb = (K + kFaThreads - 1) / kFaThreads;
     w->F = c.take<float2>((size_t)K);
     w->A = c.take<float2>((size_t)w->csr.items_bound);
@@ -1489,7 +1490,7 @@ static bgv_status bh_forces(int32_t K, const float2 *pos, const float *mass, con
                             float kg, const float2 *fprev, FaWs &w, const FaStreams &st) {
     hipStream_t s = st.s;
     BhWs &b = w.bh;
-    const bool side = st.side && att_cols(K) && K > 1;
+    const bool side = st.side && csr.cols && K > 1;
     if (side) {  // the attraction reads only the positions: it can start at once
         BGV_CHECK_HIP(hipEventRecord(st.fork, s));
         BGV_CHECK_HIP(hipStreamWaitEvent(st.side, st.fork, 0));
@@ -1499,7 +1500,7 @@ static bgv_status bh_forces(int32_t K, const float2 *pos, const float *mass, con
     BGV_TRY(bh_sorted_bodies(K, pos, mass, b, s));
     // the tree and the attraction (which the force kernel combines), in one launch
     if (K > 1) {
-        if (att_cols(K)) {
+        if (csr.cols) {
             // the tree, and the column-blocked attraction in a launch of its own (its
             // workgroups take most of a compute unit's LDS)
             BGV_LAUNCH(k_bh_build, dim3(grid_for(K - 1, kFaThreads, 65536)), dim3(kFaThreads), 0, s, K, b.code, b.PM,
@@ -1630,7 +1631,7 @@ bgv_status bgv::fa2_layout_run(int32_t K, int64_t E, const int32_t *edges, const
     BGV_LAUNCH(k_copy_f32, dim3(1), dim3(1), 0, s, speed, w.speed);
     FaStreams st;
     st.s = s;
-    if (may_fork && !p->exact && att_cols(K) && K > 1 && p->iters > 0) {
+    if (may_fork && !p->exact && w.csr.cols && K > 1 && p->iters > 0) {
         st.side = side_stream(s);
         if (st.side && (hipEventCreateWithFlags(&st.fork, hipEventDisableTiming) != hipSuccess ||
                         hipEventCreateWithFlags(&st.join, hipEventDisableTiming) != hipSuccess)) {

@@ -19,14 +19,16 @@ struct CsrWs {
     // (at least one block per row); item_of[i] = first item of row i (K+1 entries,
     // item_of[K] = number of items), item_row[t] = row of item t
     uint32_t *item_of, *item_row;
-    int64_t items_bound;  // att_items_cap(K, E)
-    // Above kAttLdsMax rows (att_cols(K)) items are cut by column block too (see
+    int64_t items_bound;  // att_items_cap(K, E, cols)
+    // With cols (chosen by csr_layout: above kAttLdsMax rows, for callers that run many
+    // iterations on one CSR) items are cut by column block too (see
     // attraction).  Schedule order q: block by block, each block's items longest first,
     // in groups of 64 (one wavefront; group gi of block c at gfirst[c] + j holds the
     // block's items cstart[c] + 64 j ..).  it/ir/il[q] = item, row and length; cwb holds
     // each group's entries transposed from gbase[gi] (entry k of the group's lane l at
     // gbase[gi] + 64 k + l) as in-block offsets (uint16, or (offset, weight bits) when
     // weighted), in the sort keys' buffer, free once the CSR is built.
+    bool cols;
     uint32_t *it, *ir;
     uint16_t *il;
     uint32_t *cstart, *gfirst, *gbase;
@@ -43,12 +45,14 @@ struct CsrWs {
 
 // Upper bound on the number of attraction work items (block sums) of K rows holding 2E
 // entries.
-int64_t att_items_cap(int32_t K, int64_t E);
+int64_t att_items_cap(int32_t K, int64_t E, bool cols);
 // Rows above which the attraction's positions no longer fit in LDS and its items are
 // cut by column block as well.
 constexpr int32_t kAttLdsMax = 19456;  // 152 KiB of float2
 inline bool att_cols(int32_t K) { return K > kAttLdsMax; }
-size_t csr_layout(Carver &c, int32_t K, int64_t E, CsrWs *w);
+// allow_cols: the column-blocked items may be used (their setup costs about as much as
+// a few iterations, so callers that evaluate the attraction once pass false).
+size_t csr_layout(Carver &c, int32_t K, int64_t E, CsrWs *w, bool allow_cols);
 // A[t] = attraction block sum of work item t (att_items_cap(K, E) entries), one
 // wavefront per item; node i's attraction is fa2_att_combine(A, csr.item_of, i).
 bgv_status attraction(int32_t K, const float2 *pos, const CsrWs &csr, float2 *A, hipStream_t s);
