@@ -30,6 +30,7 @@
 //   kernel B  = decide(this chunk), proposals by a 64-bit atomicMin keyed by the
 //               stream index.
 #include <algorithm>
+#include <type_traits>
 
 #include "block_scan.h"
 #include "common.h"
@@ -176,9 +177,12 @@ __device__ __forceinline__ uint32_t cd_offsets(uint32_t *hist, int32_t nb, uint3
 }
 
 __global__ void __launch_bounds__(kCdThreads) k_cd_init_b(int32_t *cnt, int32_t *lab, int32_t n,
-                                                           const int32_t *__restrict__ lab0) {
+                                                           const int32_t *__restrict__ lab0, uint8_t *cnt8,
+                                                           uint16_t *cnt16) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         cnt[v] = 0;
+        if (cnt8) cnt8[v] = 0;
+        if (cnt16) cnt16[v] = 0;
         lab[v] = lab0 ? lab0[v] : (int32_t)v;
     }
 }
@@ -249,8 +253,8 @@ struct CdLater {
     int32_t n;     // how many of them the mask covers
 };
 
-template <int kMode, int kB>  // kMode 0: only pass; 1: pass 0 of several; 2: a later pass; 3: a pass in the mask
-__device__ __forceinline__ void cd_decide_tile(const int32_t *__restrict__ cnt, const int32_t *__restrict__ labv,
+template <int kMode, int kB, typename CT>  // kMode 0: only pass; 1: pass 0 of several; 2: a later pass; 3: a pass in the mask
+__device__ __forceinline__ void cd_decide_tile(const CT *__restrict__ cnt, const int32_t *__restrict__ labv,
                                                const int2 *__restrict__ edges,
                                                int2 *__restrict__ c1, uint8_t *__restrict__ mask, CdLater later,
                                                int64_t cs, int64_t ce, int32_t D,
@@ -275,7 +279,7 @@ __device__ __forceinline__ void cd_decide_tile(const int32_t *__restrict__ cnt, 
                     go = mb & 1u;
                     u_low = (mb >> 1) & 1u;
                 } else {
-                    const int32_t du = cnt[e.x], dv = cnt[e.y];
+                    const int32_t du = (int32_t)cnt[e.x], dv = (int32_t)cnt[e.y];
                     int32_t cu = du, cv = dv;
                     if (kMode == 1) c1[i] = make_int2(cu, cv);
                     if (kMode == 2) {
@@ -320,8 +324,8 @@ __device__ __forceinline__ void cd_decide_tile(const int32_t *__restrict__ cnt, 
 // One launch per chunk: decide chunk [cs, ce) (kMode >= 0) and, in pass 0, group the
 // endpoints of the next chunk [gs, ge) for the counter increments of the resolve that
 // follows; workgroup x takes tile x of each.
-template <int kMode, int kB>  // kMode -1: grouping only
-__global__ void __launch_bounds__(kCdThreads) k_cd_step(const int32_t *__restrict__ cnt,
+template <int kMode, int kB, typename CT>  // kMode -1: grouping only
+__global__ void __launch_bounds__(kCdThreads) k_cd_step(const CT *__restrict__ cnt,
                                                          const int32_t *__restrict__ labv,
                                                          const int2 *__restrict__ edges,
                                                          int2 *__restrict__ c1, uint8_t *__restrict__ mask,
@@ -335,8 +339,8 @@ __global__ void __launch_bounds__(kCdThreads) k_cd_step(const int32_t *__restric
     __shared__ uint16_t estage[2 * kCdTile];
     const int32_t tile = (int32_t)blockIdx.x;
     if (kMode >= 0 && cs + (int64_t)tile * kCdTile < ce)  // uniform over the workgroup
-        cd_decide_tile<kMode < 0 ? 0 : kMode, kB>(cnt, labv, edges, c1, mask, later, cs, ce, D, pass, tie, tile,
-                                                  nb, props, ptab, hist, pstage);
+        cd_decide_tile<kMode < 0 ? 0 : kMode, kB, CT>(cnt, labv, edges, c1, mask, later, cs, ce, D, pass, tie,
+                                                      tile, nb, props, ptab, hist, pstage);
     if (gs + (int64_t)tile * kCdTile < ge) {
         __syncthreads();  // hist is reused
         cd_group_tile<kB>(edges, gs, ge, tile, nb, ends, etab, hist, estage);
@@ -385,7 +389,8 @@ __global__ void __launch_bounds__(kCdResolveThreads) k_cd_resolve(int32_t *__res
                                                                    const uint32_t *__restrict__ ptab, int32_t ptiles,
                                                                    const uint16_t *__restrict__ ends,
                                                                    const uint32_t *__restrict__ etab, int32_t etiles,
-                                                                   int32_t lanes) {
+                                                                   int32_t lanes, uint8_t *__restrict__ cnt8,
+                                                                   uint16_t *__restrict__ cnt16) {
     __shared__ unsigned long long win[1 << kB];
     __shared__ uint32_t inc[1 << kB];
     const int32_t b = cd_resolve_bucket((int32_t)blockIdx.x, nb);
@@ -430,7 +435,12 @@ __global__ void __launch_bounds__(kCdResolveThreads) k_cd_resolve(int32_t *__res
         const unsigned long long w = win[k];
         const uint32_t c = inc[k];
         if (w != ~0ull) lab[base + k] = (int32_t)(uint32_t)w;
-        if (c) cnt[base + k] += (int32_t)c;
+        if (c) {
+            const int32_t v = cnt[base + k] + (int32_t)c;
+            cnt[base + k] = v;
+            if (cnt8) cnt8[base + k] = (uint8_t)min(v, 255);
+            if (cnt16) cnt16[base + k] = (uint16_t)min(v, 65535);
+        }
     }
 }
 
@@ -467,6 +477,8 @@ struct CdWs {
     NodeState *st;      // atomic path
     int32_t *prop;      // atomic path
     int32_t *cnt, *lab; // bucketed path: counters and labels
+    uint8_t *cnt8;      // bucketed path: saturated copies of the counters (see cd_counter_widths)
+    uint16_t *cnt16;
     uint3 *props;       // bucketed: proposals grouped per tile
     uint16_t *ends;     // bucketed: endpoints grouped per tile
     uint32_t *ptab, *etab;
@@ -482,6 +494,8 @@ static size_t cd_layout(Carver &c, int32_t n, int64_t m, const bgv_cd_params *p,
         const size_t tiles = (bb + kCdTile - 1) / kCdTile;
         const size_t nb = (size_t)cd_buckets(n, 12);  // the larger of the two bucket counts
         w->cnt = c.take<int32_t>((size_t)n);
+        w->cnt8 = c.take<uint8_t>((size_t)n);
+        w->cnt16 = c.take<uint16_t>((size_t)n);
         w->lab = c.take<int32_t>((size_t)n);
         w->props = c.take<uint3>(tiles * kCdTile);
         w->ends = c.take<uint16_t>(tiles * 2 * kCdTile);
@@ -644,8 +658,29 @@ __global__ void k_cd_copy_labels(const int32_t *__restrict__ src, int32_t stride
         dst[v] = src[(int64_t)stride * v];
 }
 
-// The bucketed form, buckets of 2^kB node ids.
-template <int kB>
+// Width of the counter copies the decisions gather.  A decision only compares counters
+// with the pass threshold and with each other when both are within it, so a copy that
+// saturates above every threshold decides the same: 16 bits when every threshold is
+// below 65,535.  Pass 0 may use 8 bits when its own threshold is below 255 and no later
+// pass p can accept an edge whose stored pass-0 counter c1 saturated: there the
+// counter p*d(v) + c1 >= (p + 1) * c1 (c1 <= d(v)), so every threshold must be below
+// (p + 1) * 255.  Later passes gather degrees in 16 bits (8 would not hold d(v) up to
+// the thresholds).  Returns 8 (pass 0 in 8 bits, later ones in 16), 16 or 32.
+static int cd_counter_widths(const bgv_cd_params *p, int32_t first) {
+    const int64_t D0 = first > 0 ? -1 : p->threshold;
+    bool w8 = D0 < 255, w16 = true;
+    int64_t D = p->threshold;
+    for (int32_t q = 0; q < p->passes; ++q) {
+        if (q > 0) D = std::min<int64_t>(D * p->growth, INT32_MAX);
+        if (D >= 65535) w16 = false;
+        if (q > 0 && D >= (int64_t)(q + 1) * 255) w8 = false;
+    }
+    return w16 ? (w8 ? 8 : 16) : 32;
+}
+
+// The bucketed form, buckets of 2^kB node ids; the decisions of pass 0 gather counters
+// of type C0 and those of later passes degrees of type C1 (see cd_counter_widths).
+template <int kB, typename C0, typename C1>
 static bgv_status cd_run_bucketed(int32_t n, int64_t m, const int2 *e2, const bgv_cd_params *p, const CdWs &w,
                                   int32_t first, const int32_t *lab0, int32_t *labels, int32_t *degree,
                                   int64_t *volume, int32_t *pass_labels, hipStream_t s) {
@@ -654,12 +689,22 @@ static bgv_status cd_run_bucketed(int32_t n, int64_t m, const int2 *e2, const bg
     const int32_t nb = cd_buckets(n, kB);
     // one profiler name per kernel, whatever the bucket size
     const auto k_cd_resolve = bgv::k_cd_resolve<kB>;
-    const auto k_cd_group = k_cd_step<-1, kB>;
-    const auto k_cd_step0 = k_cd_step<0, kB>;
-    const auto k_cd_step1 = k_cd_step<1, kB>;
-    const auto k_cd_step2 = k_cd_step<2, kB>;
-    const auto k_cd_step3 = k_cd_step<3, kB>;
-    BGV_LAUNCH(k_cd_init_b, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, w.cnt, w.lab, n, lab0);
+    const auto k_cd_group = k_cd_step<-1, kB, int32_t>;
+    const auto k_cd_step0 = k_cd_step<0, kB, C0>;
+    const auto k_cd_step1 = k_cd_step<1, kB, C0>;
+    const auto k_cd_step2 = k_cd_step<2, kB, C1>;
+    const auto k_cd_step3 = k_cd_step<3, kB, int32_t>;
+    // the counter arrays the decisions gather: the exact one, or a saturated copy that
+    // the resolve keeps beside it
+    uint8_t *const cnt8 = std::is_same<C0, uint8_t>::value ? w.cnt8 : nullptr;
+    uint16_t *const cnt16 = std::is_same<C0, uint16_t>::value || std::is_same<C1, uint16_t>::value ? w.cnt16 : nullptr;
+    const C0 *const g0 = std::is_same<C0, uint8_t>::value    ? reinterpret_cast<const C0 *>(w.cnt8)
+                         : std::is_same<C0, uint16_t>::value ? reinterpret_cast<const C0 *>(w.cnt16)
+                                                             : reinterpret_cast<const C0 *>(w.cnt);
+    const C1 *const g1 = std::is_same<C1, uint16_t>::value ? reinterpret_cast<const C1 *>(w.cnt16)
+                                                           : reinterpret_cast<const C1 *>(w.cnt);
+    BGV_LAUNCH(k_cd_init_b, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, w.cnt, w.lab, n, lab0,
+               cnt8, cnt16);
     int32_t ptiles = 0;  // decide tiles whose proposals are not yet resolved
     int32_t etiles = 0;  // grouped endpoint tiles whose increments are not yet added
     auto tiles_of = [&](int64_t k) {
@@ -690,7 +735,7 @@ static bgv_status cd_run_bucketed(int32_t n, int64_t m, const int2 *e2, const bg
             // proposals of the previous chunk and, in pass 0, this chunk's increments
             if (ptiles > 0 || etiles > 0)
                 BGV_LAUNCH(k_cd_resolve, dim3(cd_resolve_grid(nb)), dim3(kCdResolveThreads), 0, s, w.cnt, w.lab, n, nb, w.props, w.ptab,
-                           ptiles, w.ends, w.etab, etiles, cd_resolve_lanes(std::max(ptiles, etiles)));
+                           ptiles, w.ends, w.etab, etiles, cd_resolve_lanes(std::max(ptiles, etiles)), cnt8, cnt16);
             // counters are incremented in pass 0 only (later passes use the closed form):
             // the next chunk's endpoints are grouped by this launch in pass 0
             const bool group_next = pass == 0 && k + 1 < nchunk;
@@ -698,16 +743,16 @@ static bgv_status cd_run_bucketed(int32_t n, int64_t m, const int2 *e2, const bg
             const int32_t gtiles = group_next ? tiles_of(k + 1) : 0;
             const dim3 grid((unsigned)std::max(tiles, gtiles));
             if (p->passes == 1)
-                BGV_LAUNCH(k_cd_step0, grid, dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1, (uint8_t *)nullptr,
+                BGV_LAUNCH(k_cd_step0, grid, dim3(kCdThreads), 0, s, g0, w.lab, e2, w.c1, (uint8_t *)nullptr,
                            later, cs, ce, D, pass, p->tie, nb, w.props, w.ptab, gs, ge, w.ends, w.etab);
             else if (pass == 0)
-                BGV_LAUNCH(k_cd_step1, grid, dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1, (uint8_t *)nullptr,
+                BGV_LAUNCH(k_cd_step1, grid, dim3(kCdThreads), 0, s, g0, w.lab, e2, w.c1, (uint8_t *)nullptr,
                            later, cs, ce, D, pass, p->tie, nb, w.props, w.ptab, gs, ge, w.ends, w.etab);
             else if (pass >= 2 && pass < 2 + later.n)
                 BGV_LAUNCH(k_cd_step3, grid, dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1, w.mask, later, cs,
                            ce, D, pass, p->tie, nb, w.props, w.ptab, gs, ge, w.ends, w.etab);
             else
-                BGV_LAUNCH(k_cd_step2, grid, dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1,
+                BGV_LAUNCH(k_cd_step2, grid, dim3(kCdThreads), 0, s, g1, w.lab, e2, w.c1,
                            pass == 1 && later.n > 0 ? w.mask : (uint8_t *)nullptr, later, cs, ce, D, pass, p->tie,
                            nb, w.props, w.ptab, gs, ge, w.ends, w.etab);
             ptiles = tiles;
@@ -716,7 +761,7 @@ static bgv_status cd_run_bucketed(int32_t n, int64_t m, const int2 *e2, const bg
         if (pass_labels) {
             if (ptiles > 0)
                 BGV_LAUNCH(k_cd_resolve, dim3(cd_resolve_grid(nb)), dim3(kCdResolveThreads), 0, s, w.cnt, w.lab, n, nb, w.props,
-                           w.ptab, ptiles, w.ends, w.etab, 0, cd_resolve_lanes(ptiles));
+                           w.ptab, ptiles, w.ends, w.etab, 0, cd_resolve_lanes(ptiles), cnt8, cnt16);
             ptiles = 0;
             BGV_LAUNCH(k_cd_copy_labels, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, w.lab, 1,
                        n, pass_labels + (int64_t)pass * n);
@@ -724,7 +769,7 @@ static bgv_status cd_run_bucketed(int32_t n, int64_t m, const int2 *e2, const bg
     }
     if (ptiles > 0)
         BGV_LAUNCH(k_cd_resolve, dim3(cd_resolve_grid(nb)), dim3(kCdResolveThreads), 0, s, w.cnt, w.lab, n, nb, w.props, w.ptab, ptiles, w.ends,
-                   w.etab, 0, cd_resolve_lanes(ptiles));
+                   w.etab, 0, cd_resolve_lanes(ptiles), cnt8, cnt16);
     BGV_LAUNCH(k_cd_finish_b, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, w.cnt, w.lab, n,
                labels, degree, reinterpret_cast<unsigned long long *>(volume));
     return BGV_OK;
@@ -763,9 +808,25 @@ static bgv_status cd_run(int32_t n, int64_t m, const int32_t *edges, const bgv_c
     const int64_t nchunk = (m + B - 1) / B;
 
     if (cd_bucketed(n)) {
-        if (cd_bucket_bits(n) == 13)
-            return cd_run_bucketed<13>(n, m, e2, p, w, first, lab0, labels, degree, volume, pass_labels, s);
-        return cd_run_bucketed<12>(n, m, e2, p, w, first, lab0, labels, degree, volume, pass_labels, s);
+        const int wd = cd_counter_widths(p, first);
+        if (cd_bucket_bits(n) == 13) {
+            if (wd == 8)
+                return cd_run_bucketed<13, uint8_t, uint16_t>(n, m, e2, p, w, first, lab0, labels, degree, volume,
+                                                              pass_labels, s);
+            if (wd == 16)
+                return cd_run_bucketed<13, uint16_t, uint16_t>(n, m, e2, p, w, first, lab0, labels, degree, volume,
+                                                               pass_labels, s);
+            return cd_run_bucketed<13, int32_t, int32_t>(n, m, e2, p, w, first, lab0, labels, degree, volume,
+                                                         pass_labels, s);
+        }
+        if (wd == 8)
+            return cd_run_bucketed<12, uint8_t, uint16_t>(n, m, e2, p, w, first, lab0, labels, degree, volume,
+                                                          pass_labels, s);
+        if (wd == 16)
+            return cd_run_bucketed<12, uint16_t, uint16_t>(n, m, e2, p, w, first, lab0, labels, degree, volume,
+                                                           pass_labels, s);
+        return cd_run_bucketed<12, int32_t, int32_t>(n, m, e2, p, w, first, lab0, labels, degree, volume,
+                                                     pass_labels, s);
     }
 
     NodeState *st = w.st;

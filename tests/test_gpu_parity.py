@@ -174,6 +174,38 @@ def test_community_pass_labels(bgv):
     check_passes(bgv, n, e, 6, 3, 2, 2500)
 
 
+def test_community_counter_widths(bgv):
+    """The decisions gather saturated 8- or 16-bit copies of the counters when every
+    threshold allows it (pass 0 below 255 and pass p below (p+1)*255: 8 bits; all below
+    65,535: 16 bits) and the exact counters otherwise.  Thresholds on both sides of each
+    limit, with hubs whose counters pass 255 and 65,535 within one pass, the tie rule and
+    a resumed run, against the oracle."""
+    rng = np.random.default_rng(77)
+    n = 3 * 4096 + 5
+    m = 200_000
+    e = rng.integers(0, n, (m, 2)).astype(np.int32)
+    e[rng.random(m) < 0.36, 0] = 11       # a hub of degree > 65,535
+    e[rng.random(m) < 0.002, 1] = 4097    # a hub of degree ~ 400 (past 255)
+    e[rng.random(m) < 0.0007, 1] = 9000   # ~140: below 255 in pass 0
+    for D, P, f in ((120, 3, 2),     # 8 bits (120, 240 < 510, 480 < 765)
+                    (254, 2, 2),     # 8 bits at the pass-0 limit (508 < 510)
+                    (255, 2, 2),     # 16 bits: pass 0 at 255
+                    (200, 3, 3),     # 16 bits: pass 1 at 600 >= 510
+                    (65534, 1, 2),   # 16 bits at the limit
+                    (65535, 2, 2),   # exact counters
+                    (40000, 3, 2)):  # exact counters from pass 1 on (80,000)
+        check_community(bgv, n, e, D, P, f, 7001, methods=(1,))
+    check_community(bgv, n, e, 200, 3, 2, 7001, methods=(1,), tie=1)
+    ed = dev(e)
+    lab_r, cnt_r = oracle.bs_community(n, e, 120, 3, 2, 7001)
+    deg_r, _ = oracle.degree_volume(lab_r, cnt_r, 3)
+    _, _, _, rows = bgv.community_passes(ed, n, 120, 3, 2, 7001, method=1)
+    lab, deg, _ = bgv.community_resume(ed, n, rows[0].clone(), 1, 120, 3, 2, 7001, volume=True, method=1)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(host(lab), lab_r)
+    np.testing.assert_array_equal(host(deg), deg_r)
+
+
 def test_community_tie_rule(bgv):
     """The tie-rule variant (equal counters: the edge's first endpoint joins the
     second's community) through every decision path: random small streams and several
