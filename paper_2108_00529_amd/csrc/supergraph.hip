@@ -351,62 +351,71 @@ __global__ void k_sg_sketch_pairs(const int32_t *__restrict__ superedges, const 
 }
 
 // Sketch 2 without global atomics, for sketches of at most kSkMaxCells cells, in buckets
-// of 2^kB consecutive cells (cell = row * cols + column).  Each tile of kSkTile
-// distinct pairs writes its (cell offset in bucket, multiplicity) entries grouped by
-// bucket, one segment per (tile, bucket), offsets in a per-tile table row; then one
-// workgroup per bucket sums its segments from every tile in LDS and writes the
-// bucket's cells, all of them, so the sketch needs no clearing.  Same integer sums.
+// of 2^kB consecutive cells (cell = row * cols + column).  Each tile of distinct pairs
+// (4,096 of them, 2,048 with more than five rows) writes one 4-byte entry per (pair,
+// row) grouped by bucket, one segment per (tile, bucket), offsets in a per-tile table
+// row; then one workgroup per bucket sums its segments from every tile in LDS and
+// writes the bucket's cells, all of them, so the sketch needs no clearing.  Same
+// integer sums.  An entry packs the cell's offset in its bucket (kB bits), the pair's
+// multiplicity when below 31 (5 bits; 31: look it up in the tile's count row) and the
+// pair's index in its tile (12 bits).
 // Buckets of 2^14 cells, or 2^15 from 2^23 cells on (the 128 KiB of LDS counters leave
 // one resolve workgroup per compute unit, but halve the (tile, bucket) segments and the
-// grouping's per-tile bucket table; measured with the community buckets above).
+// grouping's per-tile bucket table).
 constexpr int32_t kSkMaxCells = 1 << 26;             // grouped sketch 2 up to here
 constexpr int32_t kSkMaxBuckets = kSkMaxCells >> 14;  // bucket histogram held in LDS
 inline int sk_bucket_bits(int64_t cells) { return cells >= (1 << 23) ? 15 : 14; }
-constexpr int kSkItems = 4;
-constexpr int32_t kSkTile = kSgThreads * kSkItems;
+constexpr int kSkThreads = 1024;                      // grouping workgroup
+constexpr int32_t kSkStage = 20480;                   // entries a tile stages in LDS
+inline int32_t sk_tile_pairs(int32_t rows) { return rows <= 5 ? 4096 : 2048; }
+constexpr int kSkCodeBits = 5;
+constexpr uint32_t kSkEscape = (1u << kSkCodeBits) - 1;
 constexpr int kSkResolveThreads = 1024;
 
 inline int64_t sk_buckets(int64_t cells, int bits) { return (cells + (1ll << bits) - 1) >> bits; }
 
 template <int kB>
-__global__ void __launch_bounds__(kSgThreads) k_sg_group_pairs(const int32_t *__restrict__ superedges,
+__global__ void __launch_bounds__(kSkThreads) k_sg_group_pairs(const int32_t *__restrict__ superedges,
                                                                 const uint32_t *__restrict__ run_start,
                                                                 const uint32_t *__restrict__ Ep,
                                                                 const unsigned long long *__restrict__ nkp,
                                                                 const int32_t *__restrict__ super_label, HashRows h,
-                                                                int32_t rows, uint32_t cols, int32_t nb,
-                                                                uint2 *__restrict__ ent, uint32_t *__restrict__ etab,
+                                                                int32_t rows, uint32_t cols, int32_t nb, int32_t tp,
+                                                                uint32_t *__restrict__ ent, uint32_t *__restrict__ etab,
+                                                                uint32_t *__restrict__ pcnt,
                                                                 uint32_t *__restrict__ se_count) {
+    static_assert(kB + kSkCodeBits + 12 <= 32, "entry fields must fit 32 bits");
+    constexpr int kItems = 4096 / kSkThreads;  // pairs per thread at most
     __shared__ uint32_t hist[kSkMaxBuckets];
-    __shared__ uint2 stage[kSkTile * kMaxRows];
+    __shared__ uint32_t stage[kSkStage];
     const int64_t E = *Ep;
     const uint32_t nk = (uint32_t)*nkp;
-    const int64_t j0 = (int64_t)blockIdx.x * kSkTile;
+    const int64_t j0 = (int64_t)blockIdx.x * tp;
     if (j0 >= E) return;  // the grid covers a bound of E
-    for (int32_t b = threadIdx.x; b < nb; b += kSgThreads) hist[b] = 0;
+    for (int32_t b = threadIdx.x; b < nb; b += kSkThreads) hist[b] = 0;
     __syncthreads();
-    uint32_t la[kSkItems], lb[kSkItems], cnt[kSkItems], rank[kSkItems][kMaxRows];
+    const int items = tp / kSkThreads;
+    uint32_t la[kItems], lb[kItems], cnt[kItems];
 #pragma unroll
-    for (int u = 0; u < kSkItems; ++u) {
-        const int64_t j = j0 + u * kSgThreads + threadIdx.x;
+    for (int u = 0; u < kItems; ++u) {
+        const int64_t j = j0 + u * kSkThreads + threadIdx.x;
         cnt[u] = 0;
-        if (j < E) {
+        if (u < items && j < E) {
             cnt[u] = (j + 1 < E ? run_start[j + 1] : nk) - run_start[j];
             la[u] = (uint32_t)super_label[superedges[2 * j]];
             lb[u] = (uint32_t)super_label[superedges[2 * j + 1]];
+            pcnt[j] = cnt[u];
             if (se_count) se_count[j] = cnt[u];
-#pragma unroll
-            for (int r = 0; r < kMaxRows; ++r)
-                if (r < rows) {
-                    const uint32_t cell = (uint32_t)r * cols + col_pair(h.a[r], h.b[r], h.c[r], la[u], lb[u], cols);
-                    rank[u][r] = atomicAdd(&hist[cell >> kB], 1u);
-                }
+            for (int r = 0; r < rows; ++r) {
+                const uint32_t cell = (uint32_t)r * cols + col_pair(h.a[r], h.b[r], h.c[r], la[u], lb[u], cols);
+                atomicAdd(&hist[cell >> kB], 1u);
+            }
         }
     }
     __syncthreads();
     // exclusive offsets of the tile's buckets, in place and into the table row
     uint32_t *row = etab + (int64_t)blockIdx.x * (nb + 1);
-    const int32_t per = (nb + kSgThreads - 1) / kSgThreads;
+    const int32_t per = (nb + kSkThreads - 1) / kSkThreads;
     const int32_t b0 = min(nb, (int32_t)threadIdx.x * per), b1 = min(nb, b0 + per);
     uint32_t sum = 0;
     for (int32_t b = b0; b < b1; ++b) sum += hist[b];
@@ -420,23 +429,22 @@ __global__ void __launch_bounds__(kSgThreads) k_sg_group_pairs(const int32_t *__
     }
     if (threadIdx.x == 0) row[nb] = total;
     __syncthreads();
+    // the entries placed in their buckets' segments (the order inside a segment does not
+    // matter: sums and minima)
 #pragma unroll
-    for (int u = 0; u < kSkItems; ++u)
+    for (int u = 0; u < kItems; ++u)
         if (cnt[u]) {
-#pragma unroll
-            for (int r = 0; r < kMaxRows; ++r)
-                if (r < rows) {
-                    const uint32_t cell = (uint32_t)r * cols + col_pair(h.a[r], h.b[r], h.c[r], la[u], lb[u], cols);
-                    // (pair within the tile, cell within the bucket), the pair's multiplicity
-                    stage[hist[cell >> kB] + rank[u][r]] =
-                        make_uint2(((uint32_t)(u * kSgThreads + threadIdx.x) << kB) |
-                                       (cell & ((1 << kB) - 1)),
-                                   cnt[u]);
-                }
+            const uint32_t pair = (uint32_t)(u * kSkThreads + threadIdx.x);
+            const uint32_t code = cnt[u] < kSkEscape ? cnt[u] : kSkEscape;
+            for (int r = 0; r < rows; ++r) {
+                const uint32_t cell = (uint32_t)r * cols + col_pair(h.a[r], h.b[r], h.c[r], la[u], lb[u], cols);
+                const uint32_t at = atomicAdd(&hist[cell >> kB], 1u);
+                stage[at] = (pair << (kB + kSkCodeBits)) | (code << kB) | (cell & ((1u << kB) - 1));
+            }
         }
     __syncthreads();
-    uint2 *out = ent + (int64_t)blockIdx.x * (kSkTile * rows);  // a tile's region holds kSkTile * rows
-    for (uint32_t k = threadIdx.x; k < total; k += kSgThreads) out[k] = stage[k];
+    uint32_t *out = ent + (int64_t)blockIdx.x * ((int64_t)tp * rows);  // a tile's region holds tp * rows
+    for (uint32_t k = threadIdx.x; k < total; k += kSkThreads) out[k] = stage[k];
 }
 
 // Each tile's segment goes to a group of `lanes` threads (a power of two, about
@@ -449,41 +457,48 @@ inline int32_t sk_sum_lanes(int64_t tiles) {
 }
 
 // One workgroup per bucket of sketch-2 cells: the bucket's entries from every tile are
-// summed into its cells in LDS and the cells written whole; then every entry's count
-// is replaced in place by its cell's final value, so that each tile finds its pairs'
-// row estimates in its own region (k_sg_pair_min) instead of gathering them from the
-// sketch.  Buckets are dealt to the XCDs in contiguous ranges (as in the community
+// summed into its cells in LDS and the cells written whole; then every entry's cell
+// value is written beside it (est, the same position), so that each tile finds its
+// pairs' row estimates in its own region (k_sg_pair_min) instead of gathering them from
+// the sketch.  Buckets are dealt to the XCDs in contiguous ranges (as in the community
 // resolve): neighbouring buckets' segments share cache lines.
 constexpr int32_t kSgXcds = 8;
 
 template <int kB>
-__global__ void __launch_bounds__(kSkResolveThreads) k_sg_sum_cells(uint2 *__restrict__ ent,
+__global__ void __launch_bounds__(kSkResolveThreads) k_sg_sum_cells(const uint32_t *__restrict__ ent,
+                                                                     uint32_t *__restrict__ est,
                                                                      const uint32_t *__restrict__ etab,
+                                                                     const uint32_t *__restrict__ pcnt,
                                                                      const uint32_t *__restrict__ Ep, int32_t rows,
-                                                                     int32_t nb, int64_t cells, int32_t lanes,
-                                                                     uint32_t *__restrict__ M2) {
+                                                                     int32_t nb, int32_t tp, int64_t cells,
+                                                                     int32_t lanes, uint32_t *__restrict__ M2) {
     __shared__ uint32_t acc[1 << kB];
     const int32_t x = (int32_t)blockIdx.x;
     const int32_t b = (x % kSgXcds) * ((nb + kSgXcds - 1) / kSgXcds) + x / kSgXcds;
     if (b >= nb) return;  // the grid is rounded up to a multiple of the XCD count
     for (int32_t k = threadIdx.x; k < (1 << kB); k += kSkResolveThreads) acc[k] = 0u;
     __syncthreads();
-    const int64_t tiles = ((int64_t)*Ep + kSkTile - 1) / kSkTile;
+    const int64_t tiles = ((int64_t)*Ep + tp - 1) / tp;
     const int64_t groups = kSkResolveThreads / lanes;
     const uint32_t sub = threadIdx.x % lanes, L = (uint32_t)lanes;
     constexpr uint32_t kCell = (1u << kB) - 1;
+    const int64_t region = (int64_t)tp * rows;
     for (int64_t t = threadIdx.x / lanes; t < tiles; t += groups) {
         const uint32_t *row = etab + t * (nb + 1);
         const uint32_t q0 = row[b], q1 = row[b + 1];
-        const uint2 *seg = ent + t * (kSkTile * rows);
+        const uint32_t *seg = ent + t * region;
         for (uint32_t q = q0 + sub; q < q1; q += 8 * L) {
-            uint2 v[8];
+            uint32_t v[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u)
                 if (q + u * L < q1) v[u] = seg[q + u * L];
 #pragma unroll
             for (int u = 0; u < 8; ++u)
-                if (q + u * L < q1) atomicAdd(&acc[v[u].x & kCell], v[u].y);
+                if (q + u * L < q1) {
+                    uint32_t c = (v[u] >> kB) & kSkEscape;
+                    if (c == kSkEscape) c = pcnt[t * tp + (v[u] >> (kB + kSkCodeBits))];
+                    atomicAdd(&acc[v[u] & kCell], c);
+                }
         }
     }
     __syncthreads();
@@ -493,15 +508,16 @@ __global__ void __launch_bounds__(kSkResolveThreads) k_sg_sum_cells(uint2 *__res
     for (int64_t t = threadIdx.x / lanes; t < tiles; t += groups) {
         const uint32_t *row = etab + t * (nb + 1);
         const uint32_t q0 = row[b], q1 = row[b + 1];
-        uint2 *seg = ent + t * (kSkTile * rows);
+        const uint32_t *seg = ent + t * region;
+        uint32_t *eseg = est + t * region;
         for (uint32_t q = q0 + sub; q < q1; q += 8 * L) {
             uint32_t c[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u)
-                if (q + u * L < q1) c[u] = seg[q + u * L].x;
+                if (q + u * L < q1) c[u] = seg[q + u * L];
 #pragma unroll
             for (int u = 0; u < 8; ++u)
-                if (q + u * L < q1) seg[q + u * L].y = acc[c[u] & kCell];
+                if (q + u * L < q1) eseg[q + u * L] = acc[c[u] & kCell];
         }
     }
 }
@@ -509,26 +525,25 @@ __global__ void __launch_bounds__(kSkResolveThreads) k_sg_sum_cells(uint2 *__res
 inline unsigned sg_sum_grid(int32_t nb) { return (unsigned)((nb + kSgXcds - 1) / kSgXcds * kSgXcds); }
 
 // Superedge weight = count-min estimate, the minimum over the rows of the final cell
-// values k_sg_sum_cells left in the tile's entries (one per pair and row).
+// values k_sg_sum_cells left beside the tile's entries (one per pair and row).
 template <int kB>
-__global__ void __launch_bounds__(kSgThreads) k_sg_pair_min(const uint2 *__restrict__ ent,
+__global__ void __launch_bounds__(kSgThreads) k_sg_pair_min(const uint32_t *__restrict__ ent,
+                                                             const uint32_t *__restrict__ est,
                                                              const uint32_t *__restrict__ etab,
                                                              const uint32_t *__restrict__ Ep, int32_t rows, int32_t nb,
-                                                             uint32_t *__restrict__ se_weight) {
-    __shared__ uint32_t best[kSkTile];
+                                                             int32_t tp, uint32_t *__restrict__ se_weight) {
+    __shared__ uint32_t best[4096];
     const int64_t E = *Ep;
-    const int64_t j0 = (int64_t)blockIdx.x * kSkTile;
+    const int64_t j0 = (int64_t)blockIdx.x * tp;
     if (j0 >= E) return;  // the grid covers a bound of E
-    for (int k = threadIdx.x; k < kSkTile; k += kSgThreads) best[k] = 0xffffffffu;
+    for (int k = threadIdx.x; k < tp; k += kSgThreads) best[k] = 0xffffffffu;
     __syncthreads();
     const uint32_t total = etab[(int64_t)blockIdx.x * (nb + 1) + nb];
-    const uint2 *seg = ent + (int64_t)blockIdx.x * (kSkTile * rows);
-    for (uint32_t k = threadIdx.x; k < total; k += kSgThreads) {
-        const uint2 v = seg[k];
-        atomicMin(&best[v.x >> kB], v.y);
-    }
+    const int64_t region = (int64_t)blockIdx.x * ((int64_t)tp * rows);
+    for (uint32_t k = threadIdx.x; k < total; k += kSgThreads)
+        atomicMin(&best[ent[region + k] >> (kB + kSkCodeBits)], est[region + k]);
     __syncthreads();
-    const int32_t cnt = (int32_t)min((int64_t)kSkTile, E - j0);
+    const int32_t cnt = (int32_t)min((int64_t)tp, E - j0);
     for (int k = threadIdx.x; k < cnt; k += kSgThreads) se_weight[j0 + k] = best[k];
 }
 
@@ -565,7 +580,9 @@ struct SgWs {
     uint32_t *flag, *sid, *vol, *nsid, *counters, *utile, *run_start;
     uint16_t *nsid16;
     uint64_t *keys, *keys_alt;
-    uint2 *ent;       // grouped sketch-2 entries (bucketed sketch only)
+    uint32_t *ent;    // grouped sketch-2 entries (bucketed sketch only)
+    uint32_t *est;    // beside each entry, its cell's final value
+    uint32_t *pcnt;   // multiplicity of each distinct pair
     uint32_t *etab;   // their per-tile offset rows
     uint2 *lent;      // grouped (label, degree) entries (volumes without atomics)
     uint32_t *ltab;   // their per-tile offset rows
@@ -574,7 +591,7 @@ struct SgWs {
 
 static size_t sg_layout(Carver &c, int32_t n, int64_t m, int32_t rows, int64_t cells, SgWs *w) {
     const int64_t mm = m > 0 ? m : 1;
-    w->ent = nullptr;
+    w->ent = w->est = w->pcnt = nullptr;
     w->etab = nullptr;
     w->lent = nullptr;
     w->ltab = nullptr;
@@ -599,8 +616,11 @@ static size_t sg_layout(Carver &c, int32_t n, int64_t m, int32_t rows, int64_t c
     const int64_t nb = sk_buckets(cells, 14);  // the larger of the two bucket counts
     if (cells <= kSkMaxCells) {
         // distinct pairs <= m: a tile bound, rows entries per pair
-        const size_t tiles = (size_t)((mm + kSkTile - 1) / kSkTile);
-        w->ent = c.take<uint2>(tiles * kSkTile * (size_t)rows);
+        const size_t tp = (size_t)sk_tile_pairs(rows);
+        const size_t tiles = ((size_t)mm + tp - 1) / tp;
+        w->ent = c.take<uint32_t>(tiles * tp * (size_t)rows);
+        w->est = c.take<uint32_t>(tiles * tp * (size_t)rows);
+        w->pcnt = c.take<uint32_t>(tiles * tp);
         w->etab = c.take<uint32_t>(tiles * (size_t)(nb + 1));
     }
     return c.size();
@@ -629,16 +649,17 @@ static bgv_status sg_sketch2_grouped(int64_t m, const SgWs &w, const int32_t *su
                                      int32_t rows, uint32_t cols, int64_t cells, uint32_t *se_count, uint32_t *M2,
                                      uint32_t *se_weight, hipStream_t s) {
     const int32_t nb = (int32_t)sk_buckets(cells, kB);
-    const unsigned tiles = (unsigned)((m + kSkTile - 1) / kSkTile);  // a bound: the pair count is on the device
+    const int32_t tp = sk_tile_pairs(rows);
+    const unsigned tiles = (unsigned)((m + tp - 1) / tp);  // a bound: the pair count is on the device
     const auto k_sg_group_pairs = bgv::k_sg_group_pairs<kB>;  // one profiler name per kernel
     const auto k_sg_sum_cells = bgv::k_sg_sum_cells<kB>;
     const auto k_sg_pair_min = bgv::k_sg_pair_min<kB>;
-    BGV_LAUNCH(k_sg_group_pairs, dim3(tiles), dim3(kSgThreads), 0, s, superedges, w.run_start, &w.counters[1],
-               nkeys_d, super_label, h2, rows, cols, nb, w.ent, w.etab, se_count);
-    BGV_LAUNCH(k_sg_sum_cells, dim3(sg_sum_grid(nb)), dim3(kSkResolveThreads), 0, s, w.ent, w.etab, &w.counters[1],
-               rows, nb, cells, sk_sum_lanes(tiles), M2);
-    BGV_LAUNCH(k_sg_pair_min, dim3(tiles), dim3(kSgThreads), 0, s, w.ent, w.etab, &w.counters[1], rows, nb,
-               se_weight);
+    BGV_LAUNCH(k_sg_group_pairs, dim3(tiles), dim3(kSkThreads), 0, s, superedges, w.run_start, &w.counters[1],
+               nkeys_d, super_label, h2, rows, cols, nb, tp, w.ent, w.etab, w.pcnt, se_count);
+    BGV_LAUNCH(k_sg_sum_cells, dim3(sg_sum_grid(nb)), dim3(kSkResolveThreads), 0, s, w.ent, w.est, w.etab, w.pcnt,
+               &w.counters[1], rows, nb, tp, cells, sk_sum_lanes(tiles), M2);
+    BGV_LAUNCH(k_sg_pair_min, dim3(tiles), dim3(kSgThreads), 0, s, w.ent, w.est, w.etab, &w.counters[1], rows, nb,
+               tp, se_weight);
     return BGV_OK;
 }
 
