@@ -447,11 +447,15 @@ __global__ void __launch_bounds__(kSkThreads) k_sg_group_pairs(const int32_t *__
     for (uint32_t k = threadIdx.x; k < total; k += kSkThreads) out[k] = stage[k];
 }
 
-// Each tile's segment goes to a group of `lanes` threads (a power of two, about
-// kSkResolveThreads / tiles): few tiles with long segments and many tiles with short
-// ones both leave every thread few memory round trips.
-inline int32_t sk_sum_lanes(int64_t tiles) {
+// Each tile's segment goes to a group of `lanes` threads (a power of two): enough that
+// a segment of average length takes one batch of eight loads per lane, and at least
+// about kSkResolveThreads / tiles, so that few tiles with long segments still spread
+// over the workgroup.  (3.2M-node bench graph, 32-entry segments: 4 lanes 348 us per
+// resolve, 16 lanes 393, 1 lane 968.)
+inline int32_t sk_sum_lanes(int64_t tiles, int32_t tp, int32_t rows, int32_t nb) {
+    const int64_t seg = (int64_t)tp * rows / (nb > 0 ? nb : 1);  // entries per (tile, bucket) on average
     int32_t g = 1;
+    while (g < 64 && (int64_t)g * 8 < seg) g *= 2;
     while (g < kSkResolveThreads && (int64_t)g * 2 * (tiles > 0 ? tiles : 1) <= kSkResolveThreads) g *= 2;
     return g;
 }
@@ -657,7 +661,7 @@ static bgv_status sg_sketch2_grouped(int64_t m, const SgWs &w, const int32_t *su
     BGV_LAUNCH(k_sg_group_pairs, dim3(tiles), dim3(kSkThreads), 0, s, superedges, w.run_start, &w.counters[1],
                nkeys_d, super_label, h2, rows, cols, nb, tp, w.ent, w.etab, w.pcnt, se_count);
     BGV_LAUNCH(k_sg_sum_cells, dim3(sg_sum_grid(nb)), dim3(kSkResolveThreads), 0, s, w.ent, w.est, w.etab, w.pcnt,
-               &w.counters[1], rows, nb, tp, cells, sk_sum_lanes(tiles), M2);
+               &w.counters[1], rows, nb, tp, cells, sk_sum_lanes(tiles, tp, rows, nb), M2);
     BGV_LAUNCH(k_sg_pair_min, dim3(tiles), dim3(kSgThreads), 0, s, w.ent, w.est, w.etab, &w.counters[1], rows, nb,
                tp, se_weight);
     return BGV_OK;
