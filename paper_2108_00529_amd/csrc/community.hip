@@ -369,8 +369,12 @@ __device__ __forceinline__ int32_t cd_resolve_bucket(int32_t x, int32_t nb) {
     return (x % kXcds) * ((nb + kXcds - 1) / kXcds) + x / kXcds;
 }
 
-inline int32_t cd_resolve_lanes(int32_t tiles) {
+inline int32_t cd_resolve_lanes(int32_t tiles, int32_t nb) {
+    // an average endpoint segment (2 * kCdTile / nb entries) in one batch of eight loads
+    // per lane, and at least about kCdResolveThreads / tiles lanes
+    const int64_t seg = 2 * (int64_t)kCdTile / (nb > 0 ? nb : 1);
     int32_t g = 1;
+    while (g < 64 && (int64_t)g * 8 < seg) g *= 2;
     while (g < kCdResolveThreads && (int64_t)g * 2 * (tiles > 0 ? tiles : 1) <= kCdResolveThreads) g *= 2;
     return g;
 }
@@ -735,7 +739,7 @@ static bgv_status cd_run_bucketed(int32_t n, int64_t m, const int2 *e2, const bg
             // proposals of the previous chunk and, in pass 0, this chunk's increments
             if (ptiles > 0 || etiles > 0)
                 BGV_LAUNCH(k_cd_resolve, dim3(cd_resolve_grid(nb)), dim3(kCdResolveThreads), 0, s, w.cnt, w.lab, n, nb, w.props, w.ptab,
-                           ptiles, w.ends, w.etab, etiles, cd_resolve_lanes(std::max(ptiles, etiles)), cnt8, cnt16);
+                           ptiles, w.ends, w.etab, etiles, cd_resolve_lanes(std::max(ptiles, etiles), nb), cnt8, cnt16);
             // counters are incremented in pass 0 only (later passes use the closed form):
             // the next chunk's endpoints are grouped by this launch in pass 0
             const bool group_next = pass == 0 && k + 1 < nchunk;
@@ -761,7 +765,7 @@ static bgv_status cd_run_bucketed(int32_t n, int64_t m, const int2 *e2, const bg
         if (pass_labels) {
             if (ptiles > 0)
                 BGV_LAUNCH(k_cd_resolve, dim3(cd_resolve_grid(nb)), dim3(kCdResolveThreads), 0, s, w.cnt, w.lab, n, nb, w.props,
-                           w.ptab, ptiles, w.ends, w.etab, 0, cd_resolve_lanes(ptiles), cnt8, cnt16);
+                           w.ptab, ptiles, w.ends, w.etab, 0, cd_resolve_lanes(ptiles, nb), cnt8, cnt16);
             ptiles = 0;
             BGV_LAUNCH(k_cd_copy_labels, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, w.lab, 1,
                        n, pass_labels + (int64_t)pass * n);
@@ -769,7 +773,7 @@ static bgv_status cd_run_bucketed(int32_t n, int64_t m, const int2 *e2, const bg
     }
     if (ptiles > 0)
         BGV_LAUNCH(k_cd_resolve, dim3(cd_resolve_grid(nb)), dim3(kCdResolveThreads), 0, s, w.cnt, w.lab, n, nb, w.props, w.ptab, ptiles, w.ends,
-                   w.etab, 0, cd_resolve_lanes(ptiles), cnt8, cnt16);
+                   w.etab, 0, cd_resolve_lanes(ptiles, nb), cnt8, cnt16);
     BGV_LAUNCH(k_cd_finish_b, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, w.cnt, w.lab, n,
                labels, degree, reinterpret_cast<unsigned long long *>(volume));
     return BGV_OK;
