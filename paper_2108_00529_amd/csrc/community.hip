@@ -253,8 +253,21 @@ struct CdLater {
     int32_t n;     // how many of them the mask covers
 };
 
+// Whether a node whose degree is at least dlow (stored pass-0 counter c) could still
+// pass the threshold of pass `pass` or of one of the passes the mask decides.
+__device__ __forceinline__ bool cd_may_pass(int32_t dlow, int32_t c, int32_t pass, int32_t D, const CdLater &later,
+                                            bool masked) {
+    if (pass * dlow + c <= D) return true;
+    if (masked)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (q < later.n && (q + 2) * dlow + c <= later.D[q]) return true;
+    return false;
+}
+
 template <int kMode, int kB, typename CT>  // kMode 0: only pass; 1: pass 0 of several; 2: a later pass; 3: a pass in the mask
-__device__ __forceinline__ void cd_decide_tile(const CT *__restrict__ cnt, const int32_t *__restrict__ labv,
+__device__ __forceinline__ void cd_decide_tile(const CT *__restrict__ cnt, const int32_t *__restrict__ exact,
+                                               const int32_t *__restrict__ labv,
                                                const int2 *__restrict__ edges,
                                                int2 *__restrict__ c1, uint8_t *__restrict__ mask, CdLater later,
                                                int64_t cs, int64_t ce, int32_t D,
@@ -279,11 +292,18 @@ __device__ __forceinline__ void cd_decide_tile(const CT *__restrict__ cnt, const
                     go = mb & 1u;
                     u_low = (mb >> 1) & 1u;
                 } else {
-                    const int32_t du = (int32_t)cnt[e.x], dv = (int32_t)cnt[e.y];
+                    int32_t du = (int32_t)cnt[e.x], dv = (int32_t)cnt[e.y];
+                    int2 c = make_int2(0, 0);
+                    if (kMode == 2) c = c1[i];
+                    if (kMode == 2 && sizeof(CT) == 1) {
+                        // 255 stands for a degree of 255 or more: the exact degree is read
+                        // only where such a degree could still pass a threshold
+                        if (du == 255 && cd_may_pass(255, c.x, pass, D, later, mask != nullptr)) du = exact[e.x];
+                        if (dv == 255 && cd_may_pass(255, c.y, pass, D, later, mask != nullptr)) dv = exact[e.y];
+                    }
                     int32_t cu = du, cv = dv;
                     if (kMode == 1) c1[i] = make_int2(cu, cv);
                     if (kMode == 2) {
-                        const int2 c = c1[i];
                         cu = pass * du + c.x;
                         cv = pass * dv + c.y;
                         if (mask) {
@@ -326,6 +346,7 @@ __device__ __forceinline__ void cd_decide_tile(const CT *__restrict__ cnt, const
 // follows; workgroup x takes tile x of each.
 template <int kMode, int kB, typename CT>  // kMode -1: grouping only
 __global__ void __launch_bounds__(kCdThreads) k_cd_step(const CT *__restrict__ cnt,
+                                                         const int32_t *__restrict__ exact,
                                                          const int32_t *__restrict__ labv,
                                                          const int2 *__restrict__ edges,
                                                          int2 *__restrict__ c1, uint8_t *__restrict__ mask,
@@ -339,7 +360,7 @@ __global__ void __launch_bounds__(kCdThreads) k_cd_step(const CT *__restrict__ c
     __shared__ uint16_t estage[2 * kCdTile];
     const int32_t tile = (int32_t)blockIdx.x;
     if (kMode >= 0 && cs + (int64_t)tile * kCdTile < ce)  // uniform over the workgroup
-        cd_decide_tile<kMode < 0 ? 0 : kMode, kB, CT>(cnt, labv, edges, c1, mask, later, cs, ce, D, pass, tie,
+        cd_decide_tile<kMode < 0 ? 0 : kMode, kB, CT>(cnt, exact, labv, edges, c1, mask, later, cs, ce, D, pass, tie,
                                                       tile, nb, props, ptab, hist, pstage);
     if (gs + (int64_t)tile * kCdTile < ge) {
         __syncthreads();  // hist is reused
@@ -668,8 +689,9 @@ __global__ void k_cd_copy_labels(const int32_t *__restrict__ src, int32_t stride
 // below 65,535.  Pass 0 may use 8 bits when its own threshold is below 255 and no later
 // pass p can accept an edge whose stored pass-0 counter c1 saturated: there the
 // counter p*d(v) + c1 >= (p + 1) * c1 (c1 <= d(v)), so every threshold must be below
-// (p + 1) * 255.  Later passes gather degrees in 16 bits (8 would not hold d(v) up to
-// the thresholds).  Returns 8 (pass 0 in 8 bits, later ones in 16), 16 or 32.
+// (p + 1) * 255.  Later passes gather the 8-bit copy of the degrees and read the exact
+// degree only where a saturated one (255 or more) could still pass a threshold
+// (cd_may_pass).  Returns 8 (pass 0 in 8 bits), 16 or 32 (exact counters throughout).
 static int cd_counter_widths(const bgv_cd_params *p, int32_t first) {
     const int64_t D0 = first > 0 ? -1 : p->threshold;
     bool w8 = D0 < 255, w16 = true;
@@ -683,7 +705,8 @@ static int cd_counter_widths(const bgv_cd_params *p, int32_t first) {
 }
 
 // The bucketed form, buckets of 2^kB node ids; the decisions of pass 0 gather counters
-// of type C0 and those of later passes degrees of type C1 (see cd_counter_widths).
+// of type C0 and those of later passes degrees of type C1 (uint8_t: the saturated copy
+// with the exact degree read where needed; see cd_counter_widths).
 template <int kB, typename C0, typename C1>
 static bgv_status cd_run_bucketed(int32_t n, int64_t m, const int2 *e2, const bgv_cd_params *p, const CdWs &w,
                                   int32_t first, const int32_t *lab0, int32_t *labels, int32_t *degree,
@@ -700,13 +723,13 @@ static bgv_status cd_run_bucketed(int32_t n, int64_t m, const int2 *e2, const bg
     const auto k_cd_step3 = k_cd_step<3, kB, int32_t>;
     // the counter arrays the decisions gather: the exact one, or a saturated copy that
     // the resolve keeps beside it
-    uint8_t *const cnt8 = std::is_same<C0, uint8_t>::value ? w.cnt8 : nullptr;
-    uint16_t *const cnt16 = std::is_same<C0, uint16_t>::value || std::is_same<C1, uint16_t>::value ? w.cnt16 : nullptr;
+    uint8_t *const cnt8 = std::is_same<C0, uint8_t>::value || std::is_same<C1, uint8_t>::value ? w.cnt8 : nullptr;
+    uint16_t *const cnt16 = std::is_same<C0, uint16_t>::value ? w.cnt16 : nullptr;
     const C0 *const g0 = std::is_same<C0, uint8_t>::value    ? reinterpret_cast<const C0 *>(w.cnt8)
                          : std::is_same<C0, uint16_t>::value ? reinterpret_cast<const C0 *>(w.cnt16)
                                                              : reinterpret_cast<const C0 *>(w.cnt);
-    const C1 *const g1 = std::is_same<C1, uint16_t>::value ? reinterpret_cast<const C1 *>(w.cnt16)
-                                                           : reinterpret_cast<const C1 *>(w.cnt);
+    const C1 *const g1 = std::is_same<C1, uint8_t>::value ? reinterpret_cast<const C1 *>(w.cnt8)
+                                                          : reinterpret_cast<const C1 *>(w.cnt);
     BGV_LAUNCH(k_cd_init_b, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, w.cnt, w.lab, n, lab0,
                cnt8, cnt16);
     int32_t ptiles = 0;  // decide tiles whose proposals are not yet resolved
@@ -718,7 +741,7 @@ static bgv_status cd_run_bucketed(int32_t n, int64_t m, const int2 *e2, const bg
     if (nchunk > 0) {
         // pass 0, chunk 0: its endpoints grouped before anything is decided
         etiles = tiles_of(0);
-        BGV_LAUNCH(k_cd_group, dim3(etiles), dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1,
+        BGV_LAUNCH(k_cd_group, dim3(etiles), dim3(kCdThreads), 0, s, w.cnt, w.cnt, w.lab, e2, w.c1,
                    (uint8_t *)nullptr, CdLater{}, (int64_t)0, (int64_t)0, 0, 0, 0, nb, w.props, w.ptab, (int64_t)0,
                    std::min<int64_t>(B, m), w.ends, w.etab);
     }
@@ -747,16 +770,16 @@ static bgv_status cd_run_bucketed(int32_t n, int64_t m, const int2 *e2, const bg
             const int32_t gtiles = group_next ? tiles_of(k + 1) : 0;
             const dim3 grid((unsigned)std::max(tiles, gtiles));
             if (p->passes == 1)
-                BGV_LAUNCH(k_cd_step0, grid, dim3(kCdThreads), 0, s, g0, w.lab, e2, w.c1, (uint8_t *)nullptr,
+                BGV_LAUNCH(k_cd_step0, grid, dim3(kCdThreads), 0, s, g0, w.cnt, w.lab, e2, w.c1, (uint8_t *)nullptr,
                            later, cs, ce, D, pass, p->tie, nb, w.props, w.ptab, gs, ge, w.ends, w.etab);
             else if (pass == 0)
-                BGV_LAUNCH(k_cd_step1, grid, dim3(kCdThreads), 0, s, g0, w.lab, e2, w.c1, (uint8_t *)nullptr,
+                BGV_LAUNCH(k_cd_step1, grid, dim3(kCdThreads), 0, s, g0, w.cnt, w.lab, e2, w.c1, (uint8_t *)nullptr,
                            later, cs, ce, D, pass, p->tie, nb, w.props, w.ptab, gs, ge, w.ends, w.etab);
             else if (pass >= 2 && pass < 2 + later.n)
-                BGV_LAUNCH(k_cd_step3, grid, dim3(kCdThreads), 0, s, w.cnt, w.lab, e2, w.c1, w.mask, later, cs,
+                BGV_LAUNCH(k_cd_step3, grid, dim3(kCdThreads), 0, s, w.cnt, w.cnt, w.lab, e2, w.c1, w.mask, later, cs,
                            ce, D, pass, p->tie, nb, w.props, w.ptab, gs, ge, w.ends, w.etab);
             else
-                BGV_LAUNCH(k_cd_step2, grid, dim3(kCdThreads), 0, s, g1, w.lab, e2, w.c1,
+                BGV_LAUNCH(k_cd_step2, grid, dim3(kCdThreads), 0, s, g1, w.cnt, w.lab, e2, w.c1,
                            pass == 1 && later.n > 0 ? w.mask : (uint8_t *)nullptr, later, cs, ce, D, pass, p->tie,
                            nb, w.props, w.ptab, gs, ge, w.ends, w.etab);
             ptiles = tiles;
@@ -815,19 +838,19 @@ static bgv_status cd_run(int32_t n, int64_t m, const int32_t *edges, const bgv_c
         const int wd = cd_counter_widths(p, first);
         if (cd_bucket_bits(n) == 13) {
             if (wd == 8)
-                return cd_run_bucketed<13, uint8_t, uint16_t>(n, m, e2, p, w, first, lab0, labels, degree, volume,
+                return cd_run_bucketed<13, uint8_t, uint8_t>(n, m, e2, p, w, first, lab0, labels, degree, volume,
                                                               pass_labels, s);
             if (wd == 16)
-                return cd_run_bucketed<13, uint16_t, uint16_t>(n, m, e2, p, w, first, lab0, labels, degree, volume,
+                return cd_run_bucketed<13, uint16_t, uint8_t>(n, m, e2, p, w, first, lab0, labels, degree, volume,
                                                                pass_labels, s);
             return cd_run_bucketed<13, int32_t, int32_t>(n, m, e2, p, w, first, lab0, labels, degree, volume,
                                                          pass_labels, s);
         }
         if (wd == 8)
-            return cd_run_bucketed<12, uint8_t, uint16_t>(n, m, e2, p, w, first, lab0, labels, degree, volume,
+            return cd_run_bucketed<12, uint8_t, uint8_t>(n, m, e2, p, w, first, lab0, labels, degree, volume,
                                                           pass_labels, s);
         if (wd == 16)
-            return cd_run_bucketed<12, uint16_t, uint16_t>(n, m, e2, p, w, first, lab0, labels, degree, volume,
+            return cd_run_bucketed<12, uint16_t, uint8_t>(n, m, e2, p, w, first, lab0, labels, degree, volume,
                                                            pass_labels, s);
         return cd_run_bucketed<12, int32_t, int32_t>(n, m, e2, p, w, first, lab0, labels, degree, volume,
                                                      pass_labels, s);
