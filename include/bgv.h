@@ -264,8 +264,8 @@ bgv_status bgv_fa2_layout(int32_t K, int64_t E, const int32_t *edges, const floa
  * BGV_FA2_STATIC_SCRATCH_BYTES (64 MiB) inside the library, one copy per GPU, held
  * until the process ends; the call itself allocates nothing.  A call whose
  * bgv_fa2_workspace(K, E, p) exceeds that size returns BGV_E_INVALID and touches no
- * device memory (Barnes-Hut: K = 16,384 fits up to about 1,000,000 edges, K = 65,536 up
- * to about 780,000, K = 131,072 up to about 340,000; exact: K = 16,384 up to about
+ * device memory (Barnes-Hut: K = 16,384 fits up to about 980,000 edges, K = 65,536 up
+ * to about 720,000, K = 131,072 up to about 280,000; exact: K = 16,384 up to about
  * 960,000 edges, K = 65,536 never).
  * Every call on one GPU shares that GPU's array: calls that overlap in time on one GPU
  * (different streams, or host threads without an order between them) race and give

@@ -999,9 +999,26 @@ __device__ __forceinline__ int delta(const uint32_t *__restrict__ code, int32_t 
     return 32 + __clz((uint32_t)i ^ (uint32_t)j);
 }
 
-// Internal node i of the binary radix tree over the sorted codes (Karras' parallel
-// construction).  Children: >= 0 internal node, < 0 leaf ~child.  Record half a = (centre
-// of mass, mass, size^2), size^2 < 0 for a node whose codes are all equal (a leaf cell).
+// A node's own record: (centre of mass, mass, size^2) and (left, right, first, last) in
+// 32 bytes (the tree export reads these).
+struct __align__(32) BhNode {
+    float4 a;
+    int4 b;
+};
+
+// What a traversal step needs about the two children of an opened node, so that the
+// step that pops the node decides both children without loading their own records:
+// per child its (centre of mass, mass, size^2) — a body's (x, y, m, unused) —, its
+// body range and its index (>= 0 internal node, < 0 leaf ~body).  64 bytes: one line.
+struct __align__(64) BhKids {
+    float4 a[2];
+    int4 range;  // first and last body of the left child, then of the right one
+    int2 idx;    // left, right
+    int2 pad;
+};
+
+// (centre of mass, mass, size^2) of the internal node over bodies [first, last]
+// (first < last); size^2 < 0 for a node whose codes are all equal (a leaf cell).
 //
 // The radix tree refines the compressed quadtree of Section 3.1's hierarchical
 // partition: a node whose codes share a 2d-bit prefix and differ in the next bit is
@@ -1013,17 +1030,35 @@ __device__ __forceinline__ int delta(const uint32_t *__restrict__ code, int32_t 
 // cell with its own side, so the opening decisions are those of the quadtree.  The
 // parent of the node over [first, last] has the longer of the prefixes shared across
 // the range's two ends (Karras' tree: the parent extends the range on that side).
-// A node's record: (centre of mass, mass, size^2) and (left, right, first, last) in 32
-// bytes, so a traversal step that reads a node touches one cache line.
-struct __align__(32) BhNode {
-    float4 a;
-    int4 b;
-};
+__device__ __forceinline__ float4 bh_range_data(int32_t K, const uint32_t *__restrict__ code,
+                                                const double *__restrict__ PM, const double *__restrict__ PX,
+                                                const double *__restrict__ PY, float s0, int first, int last) {
+    const int dnode = delta(code, K, first, last);
+    const double M = PM[last + 1] - PM[first];
+    const double cx = (PX[last + 1] - PX[first]) / M;
+    const double cy = (PY[last + 1] - PY[first]) / M;
+    float size2;
+    if (dnode >= 32) {
+        size2 = -1.0f;
+    } else if ((dnode & 1) && max(delta(code, K, first, first - 1), delta(code, K, last, last + 1)) == dnode - 1) {
+        size2 = __builtin_inff();  // half of the parent's cell: always opened
+    } else {
+        const int lev = min(dnode >> 1, 16);
+        const float sz = s0 / (float)(1u << lev);
+        size2 = sz * sz;
+    }
+    return make_float4((float)cx, (float)cy, (float)M, size2);
+}
 
+// Internal node i of the binary radix tree over the sorted codes (Karras' parallel
+// construction): the record of its two children that the traversal reads and, when
+// `node` is given (the tree export), its own record (children >= 0 internal node, < 0
+// leaf ~child).
 __device__ __forceinline__ void bh_build_nodes(int32_t K, const uint32_t *__restrict__ code,
                                                const double *__restrict__ PM, const double *__restrict__ PX,
                                                const double *__restrict__ PY, const float *__restrict__ s0p,
-                                               BhNode *__restrict__ node, int32_t i0, int32_t stride) {
+                                               const float4 *__restrict__ body, BhNode *__restrict__ node,
+                                               BhKids *__restrict__ kids, int32_t i0, int32_t stride) {
     const float s0 = *s0p;
     for (int32_t i = i0; i < K - 1; i += stride) {
         const int d = (delta(code, K, i, i + 1) - delta(code, K, i, i - 1)) >= 0 ? 1 : -1;
@@ -1045,31 +1080,27 @@ __device__ __forceinline__ void bh_build_nodes(int32_t K, const uint32_t *__rest
         const int first = min(i, j), last = max(i, j);
         const int left = (first == gamma) ? ~gamma : gamma;
         const int right = (last == gamma + 1) ? ~(gamma + 1) : gamma + 1;
-        const double M = PM[last + 1] - PM[first];
-        const double cx = (PX[last + 1] - PX[first]) / M;
-        const double cy = (PY[last + 1] - PY[first]) / M;
-        float size2;
-        if (dnode >= 32) {
-            size2 = -1.0f;
-        } else if ((dnode & 1) &&
-                   max(delta(code, K, first, first - 1), delta(code, K, last, last + 1)) == dnode - 1) {
-            size2 = __builtin_inff();  // half of the parent's cell: always opened
-        } else {
-            const int lev = min(dnode >> 1, 16);
-            const float sz = s0 / (float)(1u << lev);
-            size2 = sz * sz;
+        if (node) {  // the tree export only: the traversal reads the children records
+            BhNode nd;
+            nd.a = bh_range_data(K, code, PM, PX, PY, s0, first, last);
+            nd.b = make_int4(left, right, first, last);
+            node[i] = nd;
         }
-        BhNode nd;
-        nd.a = make_float4((float)cx, (float)cy, (float)M, size2);
-        nd.b = make_int4(left, right, first, last);
-        node[i] = nd;
+        BhKids kd;
+        kd.a[0] = left < 0 ? body[first] : bh_range_data(K, code, PM, PX, PY, s0, first, gamma);
+        kd.a[1] = right < 0 ? body[last] : bh_range_data(K, code, PM, PX, PY, s0, gamma + 1, last);
+        kd.range = make_int4(first, gamma, gamma + 1, last);
+        kd.idx = make_int2(left, right);
+        kd.pad = make_int2(0, 0);
+        kids[i] = kd;
     }
 }
 
 __global__ void k_bh_build(int32_t K, const uint32_t *__restrict__ code, const double *__restrict__ PM,
                            const double *__restrict__ PX, const double *__restrict__ PY,
-                           const float *__restrict__ s0p, BhNode *__restrict__ node) {
-    bh_build_nodes(K, code, PM, PX, PY, s0p, node, blockIdx.x * blockDim.x + threadIdx.x,
+                           const float *__restrict__ s0p, const float4 *__restrict__ body,
+                           BhNode *__restrict__ node, BhKids *__restrict__ kids) {
+    bh_build_nodes(K, code, PM, PX, PY, s0p, body, node, kids, blockIdx.x * blockDim.x + threadIdx.x,
                    gridDim.x * blockDim.x);
 }
 
@@ -1083,15 +1114,17 @@ __global__ void __launch_bounds__(NT) k_bh_build_attract(int32_t K, const uint32
                                                           const double *__restrict__ PM,
                                                           const double *__restrict__ PX,
                                                           const double *__restrict__ PY,
-                                                          const float *__restrict__ s0p, BhNode *__restrict__ node,
-                                                          int32_t build_blocks,
+                                                          const float *__restrict__ s0p,
+                                                          const float4 *__restrict__ body, BhNode *__restrict__ node,
+                                                          BhKids *__restrict__ kids, int32_t build_blocks,
                                                           const float2 *__restrict__ pos,
                                                           const uint32_t *__restrict__ row, const E *__restrict__ cw,
                                                           const uint32_t *__restrict__ item_of,
                                                           const uint32_t *__restrict__ item_row,
                                                           float2 *__restrict__ A) {
     if ((int32_t)blockIdx.x < build_blocks) {  // uniform over the workgroup
-        bh_build_nodes(K, code, PM, PX, PY, s0p, node, blockIdx.x * NT + threadIdx.x, build_blocks * NT);
+        bh_build_nodes(K, code, PM, PX, PY, s0p, body, node, kids, blockIdx.x * NT + threadIdx.x,
+                       build_blocks * NT);
         return;
     }
     const int64_t wave0 = ((int64_t)(blockIdx.x - build_blocks) * NT + threadIdx.x) / kWave;
@@ -1120,19 +1153,20 @@ constexpr int kBhThreads = 64;
 static int bh_lanes(int32_t K) { return K >= 131072 ? 2 : K >= 65536 ? 4 : 8; }
 
 // Barnes-Hut repulsion.  Bodies are taken in Morton order, so the bodies of a wavefront
-// walk similar paths.  Each body has a shared stack and G lanes: they pop the top
-// (up to) G entries of the body's LDS stack together, decide each exactly as a single
-// traversal would (a cell of equal codes or a body is summed directly, a node far
-// enough away by its centre of mass, any other node is opened) and push the children
-// of the opened nodes.  Work is shared out afresh every step, so no lane waits on
-// another's subtree; each step costs one dependent load per lane.  Entries are node
-// indices (>= 0) or bodies (~j).  Children are pushed in reverse lane order, so the
-// deepest entries stay on top and the stack is sorted by depth; a step that pops an
-// entry of depth d then pops every deeper entry, so at most 2G entries of any one
-// depth are ever on the stack, and 2G per level of the tree bounds it: a node's prefix
-// is longer than its parent's, so the tree has at most 34 levels (root, 32 prefix
-// lengths, bodies) and the stack never exceeds kDepth.  The order of the additions
-// depends only on G and the tree: results are identical run to run.
+// walk similar paths.  Each body has a shared stack of opened nodes and G lanes: they
+// pop the top (up to) G nodes of the body's LDS stack together, and each lane decides
+// both children of its node from the node's children record, exactly as a single
+// traversal would (a body or a cell of equal codes is summed directly, a node far
+// enough away by its centre of mass, any other node is opened and pushed).  So a
+// step costs one dependent load per lane and settles two entries: the accepted
+// nodes and the bodies are never loaded on their own.  Work is shared out afresh every
+// step, so no lane waits on another's subtree.  Children are pushed in reverse lane
+// order, so the deepest entries stay on top and the stack is sorted by depth; a step
+// that pops an entry of depth d then pops every deeper entry, so at most 2G entries of
+// any one depth are ever on the stack, and 2G per level of the tree bounds it: a
+// node's prefix is longer than its parent's, so the tree has at most 34 levels (root,
+// 32 prefix lengths, bodies) and the stack never exceeds that.  The order of the
+// additions depends only on G and the tree: results are identical run to run.
 constexpr int kBhTreeLevels = 34;  // 32-bit Morton codes: root, 32 prefix lengths, equal-code cells
 
 // One force workgroup's bodies (block `blk`) with a stack of C entries per body.  A step
@@ -1141,7 +1175,7 @@ constexpr int kBhTreeLevels = 34;  // 32-bit Morton codes: root, 32 prefix lengt
 // workgroup's speed partial and its interaction tally are written and false returned.
 template <int G, int C>
 __device__ __forceinline__ bool bh_force_block(int32_t blk, int32_t K, const float4 *__restrict__ body,
-                                               const BhNode *__restrict__ node, float theta2, const float2 *__restrict__ att,
+                                               const BhKids *__restrict__ kids, float theta2, const float2 *__restrict__ att,
                                                const uint32_t *__restrict__ item_of, float kr, float kg,
                                                const float2 *__restrict__ fprev, float2 *__restrict__ F,
                                                double2 *__restrict__ part, uint32_t *__restrict__ icount) {
@@ -1171,36 +1205,43 @@ __device__ __forceinline__ bool bh_force_block(int32_t blk, int32_t K, const flo
         size -= take;
         int c_left = 0, c_right = 0, np = 0;
         if (has) {
-            if (e < 0) {
-                const int j = ~e;
-                if (j != r) add_pair(xi, body[j], fx, fy, ic);
-            } else {
-                const BhNode nd = node[e];
-                const float4 A = nd.a;
-                const int4 Bn = nd.b;
-                if (A.w < 0.f) {  // a cell of equal codes: direct sum
-                    for (int k = Bn.z; k <= Bn.w; ++k)
+            // an opened node: decide both children from its children's record
+            const BhKids kd = kids[e];
+            bool open[2] = {false, false};
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const float4 A = kd.a[q];
+                const int c = q ? kd.idx.y : kd.idx.x;
+                const int f = q ? kd.range.z : kd.range.x, l = q ? kd.range.w : kd.range.y;
+                if (c < 0) {
+                    if (~c != r) add_pair(xi, A, fx, fy, ic);  // a body
+                } else if (A.w < 0.f) {  // a cell of equal codes: direct sum
+                    for (int k = f; k <= l; ++k)
                         if (k != r) add_pair(xi, body[k], fx, fy, ic);
                 } else {
-                    bool open = r >= Bn.z && r <= Bn.w;
-                    if (!open) {
+                    bool o = r >= f && r <= l;
+                    if (!o) {
                         const float dx = xi.x - A.x, dy = xi.y - A.y;
                         const float d2 = dx * dx + dy * dy;
                         if (d2 > 0.f && A.w < theta2 * d2) {
-                            const float f = A.z * __builtin_amdgcn_rcpf(d2);
-                            fx += f * dx;
-                            fy += f * dy;
+                            const float fr = A.z * __builtin_amdgcn_rcpf(d2);
+                            fx += fr * dx;
+                            fy += fr * dy;
                             ++ic;
                         } else {
-                            open = true;
+                            o = true;
                         }
                     }
-                    if (open) {
-                        c_left = Bn.x;
-                        c_right = Bn.y;
-                        np = 2;
-                    }
+                    open[q] = o;
                 }
+            }
+            if (open[0] && open[1]) {
+                c_left = kd.idx.x;
+                c_right = kd.idx.y;
+                np = 2;
+            } else if (open[0] || open[1]) {
+                c_left = open[0] ? kd.idx.x : kd.idx.y;
+                np = 1;
             }
         }
         // inclusive scan of the pushes from the highest lane down, so lane 0 (the
@@ -1216,10 +1257,12 @@ __device__ __forceinline__ bool bh_force_block(int32_t blk, int32_t K, const flo
             overflow = true;
             size = 0;
         } else {
-            if (np) {
+            if (np == 2) {
                 const int at = size + incl - np;  // this lane's two slots: at, at + 1
                 st_g[at] = c_right;
                 st_g[at + 1] = c_left;  // left on top: popped first
+            } else if (np == 1) {
+                st_g[size + incl - 1] = c_left;
             }
             size += total;
         }
@@ -1263,7 +1306,7 @@ constexpr int32_t kBhXcds = 8;
 
 template <int G>
 __global__ void __launch_bounds__(kBhThreads) k_bh_force(int32_t K, const float4 *__restrict__ body,
-                                                          const BhNode *__restrict__ node, float theta2,
+                                                          const BhKids *__restrict__ kids, float theta2,
                                                           const float2 *__restrict__ att,
                                                           const uint32_t *__restrict__ item_of, float kr, float kg,
                                                           const float2 *__restrict__ fprev, float2 *__restrict__ F,
@@ -1276,7 +1319,7 @@ __global__ void __launch_bounds__(kBhThreads) k_bh_force(int32_t K, const float4
     const int32_t per = (nblk + kBhXcds - 1) / kBhXcds;
     const int32_t blk = ((int32_t)blockIdx.x % kBhXcds) * per + (int32_t)blockIdx.x / kBhXcds;
     if (blk >= nblk) return;  // the grid is rounded up to a multiple of the XCD count
-    const bool ovf = bh_force_block<G, BhStack<G>::kFast>(blk, K, body, node, theta2, att, item_of, kr, kg, fprev,
+    const bool ovf = bh_force_block<G, BhStack<G>::kFast>(blk, K, body, kids, theta2, att, item_of, kr, kg, fprev,
                                                            F, part, icount);
     if (ovf && threadIdx.x == 0) redo[1 + atomicAdd(&redo[0], 1u)] = (uint32_t)blk;
 }
@@ -1284,7 +1327,7 @@ __global__ void __launch_bounds__(kBhThreads) k_bh_force(int32_t K, const float4
 // The listed workgroups again with the full stack; redo[0] counts them.
 template <int G>
 __global__ void __launch_bounds__(kBhThreads) k_bh_force_full(int32_t K, const float4 *__restrict__ body,
-                                                               const BhNode *__restrict__ node, float theta2,
+                                                               const BhKids *__restrict__ kids, float theta2,
                                                                const float2 *__restrict__ att,
                                                                const uint32_t *__restrict__ item_of, float kr,
                                                                float kg, const float2 *__restrict__ fprev,
@@ -1293,7 +1336,7 @@ __global__ void __launch_bounds__(kBhThreads) k_bh_force_full(int32_t K, const f
                                                                const uint32_t *__restrict__ redo) {
     const uint32_t n = redo[0];
     for (uint32_t i = blockIdx.x; i < n; i += gridDim.x)
-        bh_force_block<G, BhStack<G>::kFull>((int32_t)redo[1 + i], K, body, node, theta2, att, item_of, kr,
+        bh_force_block<G, BhStack<G>::kFull>((int32_t)redo[1 + i], K, body, kids, theta2, att, item_of, kr,
                                              kg, fprev, F, part, icount);
 }
 
@@ -1351,6 +1394,7 @@ struct BhWs {
     uint32_t *code;
     double *part3, *PM, *PX, *PY;
     BhNode *node;
+    BhKids *kids;      // the children's records of each internal node (what the traversal reads)
     uint32_t *icount;  // interactions per force workgroup, summed over the call's iterations
     uint32_t *redo;    // [0]: force workgroups to redo with the full stack, [1..]: their ids
     void *sort_scratch;
@@ -1391,6 +1435,7 @@ static size_t fa_layout(Carver &c, int32_t K, int64_t E, const bgv_fa2_params *p
         b.PX = c.take<double>((size_t)K + 1);
         b.PY = c.take<double>((size_t)K + 1);
         b.node = c.take<BhNode>((size_t)K);
+        b.kids = c.take<BhKids>((size_t)K);
         b.icount = c.take<uint32_t>((size_t)bh_force_blocks(K));
         b.redo = c.take<uint32_t>((size_t)bh_force_blocks(K) + 1);
         b.sort_scratch = c.take<char>(onesweep_workspace(K));
@@ -1409,7 +1454,7 @@ static bgv_status launch_build_attract(int32_t K, const BhWs &b, unsigned build_
                                        size_t lds, const float2 *pos, const CsrWs &csr, float2 *A, hipStream_t s) {
     const auto k_bh_build_att = k_bh_build_attract<E, NT, kLds>;  // one name for the profiler
     BGV_LAUNCH(k_bh_build_att, dim3(build_blocks + att_blocks), dim3(NT), lds, s, K, b.code,
-               b.PM, b.PX, b.PY, b.s0, b.node, (int32_t)build_blocks, pos, csr.row,
+               b.PM, b.PX, b.PY, b.s0, b.body, (BhNode *)nullptr, b.kids, (int32_t)build_blocks, pos, csr.row,
                reinterpret_cast<const E *>(csr.cw), csr.item_of, csr.item_row, A);
     return BGV_OK;
 }
@@ -1469,9 +1514,9 @@ static bgv_status bh_force_launch(int32_t K, const BhWs &b, float theta, float k
     const auto k_bh_force_g = k_bh_force<G>;  // one profiler name for every lane count
     const auto k_bh_force_full_g = k_bh_force_full<G>;
     const unsigned grid = (unsigned)((bh_force_blocks(K) + kBhXcds - 1) / kBhXcds * kBhXcds);
-    BGV_LAUNCH(k_bh_force_g, dim3(grid), dim3(kBhThreads), 0, s, K, b.body, b.node, theta * theta, w.A,
+    BGV_LAUNCH(k_bh_force_g, dim3(grid), dim3(kBhThreads), 0, s, K, b.body, b.kids, theta * theta, w.A,
                csr.item_of, kr, kg, fprev, w.F, w.part, b.icount, b.redo);
-    BGV_LAUNCH(k_bh_force_full_g, dim3(kBhFullBlocks), dim3(kBhThreads), 0, s, K, b.body, b.node, theta * theta, w.A,
+    BGV_LAUNCH(k_bh_force_full_g, dim3(kBhFullBlocks), dim3(kBhThreads), 0, s, K, b.body, b.kids, theta * theta, w.A,
                csr.item_of, kr, kg, fprev, w.F, w.part, b.icount, b.redo);
     return BGV_OK;
 }
@@ -1504,7 +1549,7 @@ static bgv_status bh_forces(int32_t K, const float2 *pos, const float *mass, con
             // the tree, and the column-blocked attraction in a launch of its own (its
             // workgroups take most of a compute unit's LDS)
             BGV_LAUNCH(k_bh_build, dim3(grid_for(K - 1, kFaThreads, 65536)), dim3(kFaThreads), 0, s, K, b.code, b.PM,
-                       b.PX, b.PY, b.s0, b.node);
+                       b.PX, b.PY, b.s0, b.body, (BhNode *)nullptr, b.kids);
             if (side)
                 BGV_CHECK_HIP(hipStreamWaitEvent(s, st.join, 0));
             else
@@ -1683,7 +1728,7 @@ extern "C" bgv_status bgv_bh_tree(int32_t K, const float *pos, const float *mass
     BGV_TRY(bh_sorted_bodies(K, x, mass, b, s));
     if (K > 1)
         BGV_LAUNCH(k_bh_build, dim3(grid_for(K - 1, kFaThreads, 65536)), dim3(kFaThreads), 0, s, K, b.code, b.PM,
-                   b.PX, b.PY, b.s0, b.node);
+                   b.PX, b.PY, b.s0, b.body, b.node, b.kids);
     BGV_CHECK_HIP(hipMemcpyAsync(codes, b.code, sizeof(uint32_t) * (size_t)K, hipMemcpyDeviceToDevice, s));
     BGV_CHECK_HIP(hipMemcpyAsync(body, b.body, sizeof(float4) * (size_t)K, hipMemcpyDeviceToDevice, s));
     BGV_CHECK_HIP(hipMemcpyAsync(s0, b.s0, sizeof(float), hipMemcpyDeviceToDevice, s));

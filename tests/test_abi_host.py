@@ -163,8 +163,8 @@ def test_fa2_layout_static_validation():
     assert L.bgv_fa2_workspace(K, E, C.byref(ok)) > L.BGV_FA2_STATIC_SCRATCH_BYTES
     assert L.bgv_fa2_layout_static(K, E, one, None, None, one, one, one, C.byref(ok), None) == -1
     assert b"more than" in L.bgv_last_error()
-    assert L.bgv_fa2_workspace(65_536, 780_000, C.byref(ok)) <= L.BGV_FA2_STATIC_SCRATCH_BYTES
-    assert L.bgv_fa2_workspace(131_072, 340_000, C.byref(ok)) <= L.BGV_FA2_STATIC_SCRATCH_BYTES
+    assert L.bgv_fa2_workspace(65_536, 720_000, C.byref(ok)) <= L.BGV_FA2_STATIC_SCRATCH_BYTES
+    assert L.bgv_fa2_workspace(131_072, 280_000, C.byref(ok)) <= L.BGV_FA2_STATIC_SCRATCH_BYTES
 
 
 def test_batched_validation():
