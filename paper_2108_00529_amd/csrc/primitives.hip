@@ -425,6 +425,7 @@ constexpr int kOsPasses = 4;
 // after ranking its keys; the bound only keeps a broken invariant from hanging the GPU
 // (the sort's output is then wrong, which the callers' tests would show).
 constexpr uint32_t kOsMaxSpins = 1u << 20;
+constexpr int kOsWindow = 8;  // earlier tiles' words read at once by a walk step
 
 __device__ __forceinline__ void os_publish(uint32_t *w, uint32_t v) {
     __hip_atomic_store(w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -541,14 +542,23 @@ __global__ void __launch_bounds__(kRsThreads) k_os_pass(const uint32_t *__restri
     lstart[t] = block_excl_scan<uint32_t>(cnt_d, &all);
     uint32_t excl = 0;
     if (tile > 0) {
+        // the walk reads the words of kOsWindow earlier tiles at once (independent loads),
+        // then adds them nearest first up to the first inclusive prefix; below tile 0 a
+        // word reads as an inclusive zero and is not loaded
         uint32_t spins = 0;
-        for (int64_t j = tile - 1; j >= 0; --j) {
-            uint32_t v;
-            do {
-                v = os_peek(&status[j * 256 + t]);
-            } while ((v & ~kOsCountMask) == 0u && ++spins < kOsMaxSpins);
-            excl += v & kOsCountMask;
-            if (v & kOsInc) break;
+        bool done = false;
+        for (int64_t j = tile - 1; !done; j -= kOsWindow) {
+            uint32_t v[kOsWindow];
+#pragma unroll
+            for (int q = 0; q < kOsWindow; ++q) v[q] = j - q >= 0 ? os_peek(&status[(j - q) * 256 + t]) : kOsInc;
+#pragma unroll
+            for (int q = 0; q < kOsWindow; ++q) {
+                if (done) break;
+                uint32_t x = v[q];
+                while ((x & ~kOsCountMask) == 0u && ++spins < kOsMaxSpins) x = os_peek(&status[(j - q) * 256 + t]);
+                excl += x & kOsCountMask;
+                if (x & kOsInc) done = true;
+            }
         }
         os_publish(&status[tile * 256 + t], kOsInc | (excl + cnt_d));
     }

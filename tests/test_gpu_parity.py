@@ -371,11 +371,12 @@ def test_supergraph_degenerate_streams(bgv):
             check_supergraph(bgv, n, e, lab, deg, rows, cols, 3)
 
 
-@pytest.mark.parametrize("K", [65536, 65537])
+@pytest.mark.parametrize("K", [65536, 65537, 262144, 262145, 1048577])
 def test_supergraph_key_width_boundary(bgv, K):
     """Every node its own community: K = 65,536 supernodes packs a superedge key into 32
-    bits (16 + 16), one more needs 34 and takes the 64-bit sort; a sketch of many
-    buckets (5 x 2^20 cells) and a small one (2 x 3000)."""
+    bits (16 + 16), one more needs 34 and takes the 64-bit sort (36 to 42-bit keys at
+    2^18 and 2^20 supernodes and just past them); a sketch of many buckets (5 x 2^20
+    cells) and a small one (2 x 3000)."""
     rng = np.random.default_rng(K)
     m = 200_000
     e = rng.integers(0, K, (m, 2)).astype(np.int32)
