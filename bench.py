@@ -602,10 +602,12 @@ def kernel_model(name, K, E, inter_per_launch=None):
     if name in CSR_ENTRY_BYTES:  # CSR entries + row offsets, own and neighbour positions, result
         return "hbm", CSR_ENTRY_BYTES[name] * 2 * E + 28 * K, "byte"
     per_body = {"os_pass<4>": 16,                  # Morton sort pass: 32-bit code and index read + written
+                "os_pass<8>": 16,
                 "os_pass<16>": 16,
                 "rs_downsweep_small": 16,
                 "bh_codes": 20,                     # position read, key and index written
                 "bh_codes_os<4>": 20,               # the same, with the sort's digit counts in LDS
+                "bh_codes_os<8>": 20,
                 "bh_codes_os<16>": 20,
                 "bh_gather": 44,                    # key, index, position, mass read; body and code written
                 "bh_prefix": 40,                    # body read; three FP64 prefix sums written

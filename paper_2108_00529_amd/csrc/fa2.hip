@@ -1495,6 +1495,9 @@ static bgv_status bh_sorted_bodies(int32_t K, const float2 *pos, const float *ma
         if (ob.items == 4)
             BGV_LAUNCH(k_bh_codes_os<4>, dim3((unsigned)ob.tiles), dim3(kFaThreads), 0, s, K, pos, b.bbox, nbox, keys,
                        b.vals, b.s0, ob.totals, ob.status, ob.status_words);
+        else if (ob.items == 8)
+            BGV_LAUNCH(k_bh_codes_os<8>, dim3((unsigned)ob.tiles), dim3(kFaThreads), 0, s, K, pos, b.bbox, nbox, keys,
+                       b.vals, b.s0, ob.totals, ob.status, ob.status_words);
         else
             BGV_LAUNCH(k_bh_codes_os<16>, dim3((unsigned)ob.tiles), dim3(kFaThreads), 0, s, K, pos, b.bbox, nbox, keys,
                        b.vals, b.s0, ob.totals, ob.status, ob.status_words);

@@ -585,7 +585,7 @@ __global__ void __launch_bounds__(kRsThreads) k_os_pass(const uint32_t *__restri
     }
 }
 
-int os_items(int64_t n) { return n <= (int64_t)(1 << 20) ? 4 : 16; }
+int os_items(int64_t n) { return n <= (int64_t)(1 << 16) ? 4 : n <= (int64_t)(1 << 20) ? 8 : 16; }
 
 bgv_status onesweep_sort_u32(uint32_t *keys, uint32_t *keys_alt, uint32_t *vals, uint32_t *vals_alt, int64_t n,
                              uint32_t **keys_out, uint32_t **vals_out, void *scratch, hipStream_t s, bool counted) {
@@ -599,6 +599,9 @@ bgv_status onesweep_sort_u32(uint32_t *keys, uint32_t *keys_alt, uint32_t *vals,
             if (b.items == 4)
                 BGV_LAUNCH(k_os_count<4>, dim3(tiles), dim3(kRsThreads), 0, s, src, n, b.totals, b.status,
                            b.status_words);
+            else if (b.items == 8)
+                BGV_LAUNCH(k_os_count<8>, dim3(tiles), dim3(kRsThreads), 0, s, src, n, b.totals, b.status,
+                           b.status_words);
             else
                 BGV_LAUNCH(k_os_count<16>, dim3(tiles), dim3(kRsThreads), 0, s, src, n, b.totals, b.status,
                            b.status_words);
@@ -608,6 +611,9 @@ bgv_status onesweep_sort_u32(uint32_t *keys, uint32_t *keys_alt, uint32_t *vals,
             uint32_t *st = b.status + (int64_t)pass * b.tiles * 256;
             if (b.items == 4)
                 BGV_LAUNCH(k_os_pass<4>, dim3(tiles), dim3(kRsThreads), 0, s, src, dst, vsrc, vdst, n, b.tiles,
+                           8 * pass, b.totals + 256 * pass, st, counters + pass);
+            else if (b.items == 8)
+                BGV_LAUNCH(k_os_pass<8>, dim3(tiles), dim3(kRsThreads), 0, s, src, dst, vsrc, vdst, n, b.tiles,
                            8 * pass, b.totals + 256 * pass, st, counters + pass);
             else
                 BGV_LAUNCH(k_os_pass<16>, dim3(tiles), dim3(kRsThreads), 0, s, src, dst, vsrc, vdst, n, b.tiles,
