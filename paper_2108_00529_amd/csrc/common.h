@@ -182,4 +182,15 @@ void onesweep_layout(void *scratch, int64_t n, int items, OsBuffers *b);
 bgv_status onesweep_sort_u32(uint32_t *keys, uint32_t *keys_alt, uint32_t *vals, uint32_t *vals_alt, int64_t n,
                              uint32_t **keys_out, uint32_t **vals_out, void *scratch, hipStream_t s, bool counted);
 
+// One-sweep sort of keys alone (uint32_t or uint64_t; the low nbits significant,
+// ceil(nbits / 8) <= sizeof(KT) passes; stable, so equal keys keep their order).
+// keys/keys_alt are ping-pong buffers of n entries; the sorted keys end in *keys_out
+// (one of the two).  With n_dev the key count is read on the device (*n_dev <= n) and
+// n is only its bound, so the sort can be queued before the count is known on the
+// host.  Scratch from onesweep_keys_workspace(n, nbits); n < 2^30.
+size_t onesweep_keys_workspace(int64_t n, int nbits);
+template <class KT>
+bgv_status onesweep_sort_keys(KT *keys, KT *keys_alt, int64_t n, const unsigned long long *n_dev, int nbits,
+                              KT **keys_out, void *scratch, hipStream_t s);
+
 }  // namespace bgv

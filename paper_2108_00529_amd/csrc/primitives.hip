@@ -585,6 +585,210 @@ __global__ void __launch_bounds__(kRsThreads) k_os_pass(const uint32_t *__restri
     }
 }
 
+// ------------------------------------------------ one-sweep sort of keys alone ---
+// The same passes for keys without values (32 or 64 bits, the low nbits significant:
+// ceil(nbits / 8) passes), whose count may be known only on the device (*n_dev <= the
+// bound n): every launch is sized by the bound and reads the count itself.  One
+// counting launch first reads the keys once, adds the digit counts of every pass into
+// the totals and clears the look-back words and tile counters; then each pass is one
+// launch that reads and writes every key once.
+constexpr int kOs64Items = 16;  // keys per thread for 64-bit keys
+template <typename KT>
+struct OsKeyShape {
+    static constexpr int kItems = sizeof(KT) == 8 ? kOs64Items : 16;  // keys per thread
+    static constexpr int kTile = kRsThreads * kItems;
+};
+constexpr int kOsMaxPasses = 8;
+constexpr unsigned kOsCountBlocks = 1024;
+constexpr int kOsCountLoads = 8;
+
+static int os_key_passes(int nbits) { return nbits <= 0 ? 1 : (nbits + 7) / 8; }
+template <typename KT>
+static int64_t os_key_tiles(int64_t n) {
+    return (n + OsKeyShape<KT>::kTile - 1) / OsKeyShape<KT>::kTile;
+}
+
+size_t onesweep_keys_workspace(int64_t n, int nbits) {
+    const int64_t t32 = os_key_tiles<uint32_t>(n > 0 ? n : 1), t64 = os_key_tiles<uint64_t>(n > 0 ? n : 1);
+    const int64_t tiles = t32 > t64 ? t32 : t64;
+    const int passes = os_key_passes(nbits);
+    return align_up(sizeof(uint32_t) * kOsMaxPasses * 256) +
+           align_up(sizeof(uint32_t) * ((size_t)passes * tiles * 256 + passes));
+}
+
+__device__ __forceinline__ int64_t os_key_count(const unsigned long long *n_dev, int64_t n) {
+    if (!n_dev) return n;
+    const int64_t c = (int64_t)*n_dev;
+    return c < n ? c : n;
+}
+
+template <typename KT>
+__global__ void __launch_bounds__(kRsThreads) k_os_count_keys(const KT *__restrict__ keys,
+                                                               const unsigned long long *__restrict__ n_dev,
+                                                               int64_t n_bound, int passes,
+                                                               uint32_t *__restrict__ totals,
+                                                               uint32_t *__restrict__ status, int64_t status_words) {
+    __shared__ uint32_t hist[kOsMaxPasses][256];
+    for (int q = 0; q < passes; ++q) hist[q][threadIdx.x] = 0u;
+    for (int64_t i = (int64_t)blockIdx.x * kRsThreads + threadIdx.x; i < status_words;
+         i += (int64_t)gridDim.x * kRsThreads)
+        status[i] = 0u;
+    __syncthreads();
+    const int64_t n = os_key_count(n_dev, n_bound);
+    // kOsCountLoads keys per thread and round, all loaded before any is counted
+    const int64_t stride = (int64_t)gridDim.x * kRsThreads;
+    for (int64_t i0 = (int64_t)blockIdx.x * kRsThreads + threadIdx.x; i0 < n; i0 += stride * kOsCountLoads) {
+        KT k[kOsCountLoads];
+#pragma unroll
+        for (int u = 0; u < kOsCountLoads; ++u) {
+            const int64_t i = i0 + u * stride;
+            k[u] = i < n ? keys[i] : (KT)0;
+        }
+#pragma unroll
+        for (int u = 0; u < kOsCountLoads; ++u)
+            if (i0 + u * stride < n)
+                for (int q = 0; q < passes; ++q) atomicAdd(&hist[q][(uint32_t)(k[u] >> (8 * q)) & 255u], 1u);
+    }
+    __syncthreads();
+    for (int q = 0; q < passes; ++q)
+        if (hist[q][threadIdx.x]) atomicAdd(&totals[q * 256 + threadIdx.x], hist[q][threadIdx.x]);
+}
+
+template <typename KT>
+__global__ void __launch_bounds__(kRsThreads) k_os_pass_keys(const KT *__restrict__ keys, KT *__restrict__ keys_out,
+                                                              const unsigned long long *__restrict__ n_dev,
+                                                              int64_t n_bound, int shift,
+                                                              const uint32_t *__restrict__ totals, uint32_t *status,
+                                                              uint32_t *counter) {
+    constexpr int ITEMS = OsKeyShape<KT>::kItems;
+    constexpr int kTile = OsKeyShape<KT>::kTile;
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t running[256];
+    __shared__ uint32_t lstart[256];
+    __shared__ uint32_t hist[kRsWaves][256];
+    __shared__ KT skey[kTile];
+    const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
+    if (t == 0) s_tile = atomicAdd(counter, 1u);
+    const uint32_t tot = totals[t];  // keys of digit t in this pass
+#pragma unroll
+    for (int q = 0; q < kRsWaves; ++q) hist[q][t] = 0;
+    __syncthreads();
+    const int64_t n = os_key_count(n_dev, n_bound);
+    const int64_t tiles = (n + kTile - 1) / kTile;
+    const int64_t tile = s_tile;
+    if (tile >= tiles) return;  // uniform: tiles past the count take no part
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t base = tile * kTile;
+    const int64_t wbase = base + (int64_t)w * (kWave * ITEMS);
+    KT key[ITEMS];
+    uint32_t rk[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int64_t i = wbase + (int64_t)j * kWave + lane;
+        key[j] = i < n ? keys[i] : (KT)0;
+    }
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const bool valid = wbase + (int64_t)j * kWave + lane < n;
+        const uint32_t d = (uint32_t)(key[j] >> shift) & 255u;
+        uint64_t match = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            match &= bit ? bb : ~bb;
+        }
+        const uint32_t below = (uint32_t)__popcll(match & lt_mask);
+        const uint32_t before = hist[w][d];
+        rk[j] = before + below;
+        if (valid && below == 0) hist[w][d] = before + (uint32_t)__popcll(match);
+    }
+    __syncthreads();
+    uint32_t cnt_d = 0;  // this tile's keys of digit t
+#pragma unroll
+    for (int q = 0; q < kRsWaves; ++q) {
+        const uint32_t c = hist[q][t];
+        hist[q][t] = cnt_d;
+        cnt_d += c;
+    }
+    os_publish(&status[tile * 256 + t], (tile == 0 ? kOsInc : kOsAgg) | cnt_d);
+    uint32_t all;
+    lstart[t] = block_excl_scan<uint32_t>(cnt_d, &all);
+    uint32_t excl = 0;
+    if (tile > 0) {
+        uint32_t spins = 0;
+        bool done = false;
+        for (int64_t j = tile - 1; !done; j -= kOsWindow) {
+            uint32_t v[kOsWindow];
+#pragma unroll
+            for (int q = 0; q < kOsWindow; ++q) v[q] = j - q >= 0 ? os_peek(&status[(j - q) * 256 + t]) : kOsInc;
+#pragma unroll
+            for (int q = 0; q < kOsWindow; ++q) {
+                if (done) break;
+                uint32_t x = v[q];
+                while ((x & ~kOsCountMask) == 0u && ++spins < kOsMaxSpins) x = os_peek(&status[(j - q) * 256 + t]);
+                excl += x & kOsCountMask;
+                if (x & kOsInc) done = true;
+            }
+        }
+        os_publish(&status[tile * 256 + t], kOsInc | (excl + cnt_d));
+    }
+    uint32_t all_keys;
+    running[t] = block_excl_scan<uint32_t>(tot, &all_keys) + excl;  // keys of lower digits, then earlier tiles
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        if (wbase + (int64_t)j * kWave + lane < n) {
+            const uint32_t d = (uint32_t)(key[j] >> shift) & 255u;
+            skey[lstart[d] + hist[w][d] + rk[j]] = key[j];
+        }
+    }
+    __syncthreads();
+    const int cnt = (int)((n - base) < kTile ? (n - base) : kTile);
+    for (int p = t; p < cnt; p += kRsThreads) {
+        const KT k = skey[p];
+        const uint32_t d = (uint32_t)(k >> shift) & 255u;
+        keys_out[running[d] + ((uint32_t)p - lstart[d])] = k;
+    }
+}
+
+template <typename KT>
+bgv_status onesweep_sort_keys(KT *keys, KT *keys_alt, int64_t n, const unsigned long long *n_dev, int nbits,
+                              KT **keys_out, void *scratch, hipStream_t s) {
+    const int passes = os_key_passes(nbits);
+    if (passes > (int)sizeof(KT) || n > (int64_t)kOsCountMask) {
+        set_error("onesweep_sort_keys: %d key bits, %lld keys", nbits, (long long)n);
+        return BGV_E_INVALID;
+    }
+    KT *src = keys, *dst = keys_alt;
+    if (n > 0) {
+        const int64_t tiles = os_key_tiles<KT>(n);
+        char *p = static_cast<char *>(scratch);
+        uint32_t *totals = reinterpret_cast<uint32_t *>(p);
+        p += align_up(sizeof(uint32_t) * kOsMaxPasses * 256);
+        uint32_t *status = reinterpret_cast<uint32_t *>(p);
+        const int64_t status_words = (int64_t)passes * tiles * 256 + passes;
+        uint32_t *counters = status + (int64_t)passes * tiles * 256;
+        BGV_TRY(fill<uint32_t>(totals, 0u, passes * 256, s));
+        const unsigned gc = grid_for(n, kRsThreads * 16, kOsCountBlocks);
+        BGV_LAUNCH(k_os_count_keys<KT>, dim3(gc), dim3(kRsThreads), 0, s, keys, n_dev, n, passes, totals, status,
+                   status_words);
+        for (int pass = 0; pass < passes; ++pass) {
+            BGV_LAUNCH(k_os_pass_keys<KT>, dim3((unsigned)tiles), dim3(kRsThreads), 0, s, src, dst, n_dev, n,
+                       8 * pass, totals + 256 * pass, status + (int64_t)pass * tiles * 256, counters + pass);
+            KT *tk = src;
+            src = dst;
+            dst = tk;
+        }
+    }
+    *keys_out = src;
+    return BGV_OK;
+}
+template bgv_status onesweep_sort_keys<uint32_t>(uint32_t *, uint32_t *, int64_t, const unsigned long long *, int,
+                                                 uint32_t **, void *, hipStream_t);
+template bgv_status onesweep_sort_keys<uint64_t>(uint64_t *, uint64_t *, int64_t, const unsigned long long *, int,
+                                                 uint64_t **, void *, hipStream_t);
+
 int os_items(int64_t n) { return n <= (int64_t)(1 << 16) ? 4 : n <= (int64_t)(1 << 20) ? 8 : 16; }
 
 bgv_status onesweep_sort_u32(uint32_t *keys, uint32_t *keys_alt, uint32_t *vals, uint32_t *vals_alt, int64_t n,

@@ -593,6 +593,11 @@ struct SgWs {
     void *scan_scratch, *sort_scratch;
 };
 
+// The inter-community keys are sorted by the one-sweep sort of keys alone (one read and
+// one write of the keys per 8-bit pass, after one counting read), below 2^30 edges;
+// beyond, by the reduce-then-scan radix sort.
+static bool sg_onesweep(int64_t m) { return m < ((int64_t)1 << 30) - 1; }
+
 static size_t sg_layout(Carver &c, int32_t n, int64_t m, int32_t rows, int64_t cells, SgWs *w) {
     const int64_t mm = m > 0 ? m : 1;
     w->ent = w->est = w->pcnt = nullptr;
@@ -611,7 +616,7 @@ static size_t sg_layout(Carver &c, int32_t n, int64_t m, int32_t rows, int64_t c
     w->run_start = c.take<uint32_t>((size_t)mm);
     const int64_t big = n > mm ? n : mm;
     w->scan_scratch = c.take<char>(scan_workspace(big));
-    w->sort_scratch = c.take<char>(radix_workspace(mm));
+    w->sort_scratch = c.take<char>(sg_onesweep(mm) ? onesweep_keys_workspace(mm, 64) : radix_workspace(mm));
     if (cells > kLdsCounters && lb_buckets(n) <= kLbMaxBuckets) {
         const size_t tiles = ((size_t)n + kLbTile - 1) / kLbTile;
         w->lent = c.take<uint2>(tiles * kLbTile);
@@ -787,12 +792,20 @@ extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges,
     if (m > 0) {
         uint64_t *sorted = nullptr;
         uint32_t *sorted32 = nullptr;
-        if (k32)
+        if (sg_onesweep(m)) {
+            if (k32)
+                BGV_TRY(onesweep_sort_keys<uint32_t>(keys32, keys32_alt, m, nkeys_d, 2 * kbits, &sorted32,
+                                                     w.sort_scratch, s));
+            else
+                BGV_TRY(onesweep_sort_keys<uint64_t>(w.keys, w.keys_alt, m, nkeys_d, 2 * kbits, &sorted,
+                                                     w.sort_scratch, s));
+        } else if (k32) {
             BGV_TRY(radix_sort_u32(keys32, keys32_alt, nullptr, nullptr, m, 2 * kbits, &sorted32, nullptr,
                                    w.sort_scratch, s, false, nkeys_d));
-        else
+        } else {
             BGV_TRY(radix_sort_u64(w.keys, w.keys_alt, nullptr, nullptr, m, 2 * kbits, &sorted, nullptr,
                                    w.sort_scratch, s, false, nkeys_d));
+        }
         const unsigned gk = grid_for(m, kSgThreads, 65536);
         const unsigned ut = (unsigned)((m + kUqTile - 1) / kUqTile);
         if (k32)
