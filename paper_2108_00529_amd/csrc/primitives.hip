@@ -601,6 +601,7 @@ struct OsKeyShape {
 constexpr int kOsMaxPasses = 8;
 constexpr unsigned kOsCountBlocks = 1024;
 constexpr int kOsCountLoads = 8;
+constexpr int kOsKeyWindow = 8;  // earlier tiles' words read at once by a look-back step
 
 static int os_key_passes(int nbits) { return nbits <= 0 ? 1 : (nbits + 7) / 8; }
 template <typename KT>
@@ -714,16 +715,27 @@ __global__ void __launch_bounds__(kRsThreads) k_os_pass_keys(const KT *__restric
     os_publish(&status[tile * 256 + t], (tile == 0 ? kOsInc : kOsAgg) | cnt_d);
     uint32_t all;
     lstart[t] = block_excl_scan<uint32_t>(cnt_d, &all);
+    __syncthreads();
+    // the tile's keys in digit order in LDS before the look-back, so that no key is held
+    // in registers while it waits
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        if (wbase + (int64_t)j * kWave + lane < n) {
+            const uint32_t d = (uint32_t)(key[j] >> shift) & 255u;
+            skey[lstart[d] + hist[w][d] + rk[j]] = key[j];
+        }
+    }
     uint32_t excl = 0;
     if (tile > 0) {
         uint32_t spins = 0;
         bool done = false;
-        for (int64_t j = tile - 1; !done; j -= kOsWindow) {
-            uint32_t v[kOsWindow];
+        for (int64_t j = tile - 1; !done; j -= kOsKeyWindow) {
+            uint32_t v[kOsKeyWindow];
 #pragma unroll
-            for (int q = 0; q < kOsWindow; ++q) v[q] = j - q >= 0 ? os_peek(&status[(j - q) * 256 + t]) : kOsInc;
+            for (int q = 0; q < kOsKeyWindow; ++q)
+                v[q] = j - q >= 0 ? os_peek(&status[(j - q) * 256 + t]) : kOsInc;
 #pragma unroll
-            for (int q = 0; q < kOsWindow; ++q) {
+            for (int q = 0; q < kOsKeyWindow; ++q) {
                 if (done) break;
                 uint32_t x = v[q];
                 while ((x & ~kOsCountMask) == 0u && ++spins < kOsMaxSpins) x = os_peek(&status[(j - q) * 256 + t]);
@@ -735,14 +747,6 @@ __global__ void __launch_bounds__(kRsThreads) k_os_pass_keys(const KT *__restric
     }
     uint32_t all_keys;
     running[t] = block_excl_scan<uint32_t>(tot, &all_keys) + excl;  // keys of lower digits, then earlier tiles
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        if (wbase + (int64_t)j * kWave + lane < n) {
-            const uint32_t d = (uint32_t)(key[j] >> shift) & 255u;
-            skey[lstart[d] + hist[w][d] + rk[j]] = key[j];
-        }
-    }
     __syncthreads();
     const int cnt = (int)((n - base) < kTile ? (n - base) : kTile);
     for (int p = t; p < cnt; p += kRsThreads) {
