@@ -651,6 +651,20 @@ static bgv_status sg_readback(SgReadback **out) {
     return BGV_OK;
 }
 
+// Waits for the readback event by polling it: the two readbacks wait on work this call
+// has just queued (well under a millisecond for K), and a blocking wait would add the
+// host thread's wake-up time to each.
+static bgv_status sg_wait(hipEvent_t ev) {
+    for (;;) {
+        const hipError_t e = hipEventQuery(ev);
+        if (e == hipSuccess) return BGV_OK;
+        if (e != hipErrorNotReady) {
+            set_error("hipEventQuery failed: %s", hipGetErrorString(e));
+            return BGV_E_HIP;
+        }
+    }
+}
+
 // Sketch 2 by grouped entries (buckets of 2^kB cells) and the superedge weights.
 template <int kB>
 static bgv_status sg_sketch2_grouped(int64_t m, const SgWs &w, const int32_t *superedges,
@@ -765,7 +779,7 @@ extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges,
                        M1, super_size);
     BGV_LAUNCH(k_sg_node_super, dim3(gn), dim3(kSgThreads), 0, s, labels, w.sid, n, w.nsid, w.nsid16, node_super);
 
-    BGV_CHECK_HIP(hipEventSynchronize(rb->ev));
+    BGV_TRY(sg_wait(rb->ev));
     const uint32_t Kh = rb->host[0];
     *K_out = (int32_t)Kh;
     int kbits = 1;
@@ -833,7 +847,8 @@ extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges,
                        h2, rows, cols, M2, se_weight);
         }
         BGV_CHECK_HIP(hipMemcpyAsync(rb->host + 4, &w.counters[1], sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        BGV_CHECK_HIP(hipStreamSynchronize(s));
+        BGV_CHECK_HIP(hipEventRecord(rb->ev, s));
+        BGV_TRY(sg_wait(rb->ev));
         E = rb->host[4];
     }
     *E_out = E;
