@@ -656,7 +656,7 @@ __global__ void __launch_bounds__(kRsThreads) k_os_count_keys(const KT *__restri
 }
 
 template <typename KT>
-__global__ void __launch_bounds__(kRsThreads) k_os_pass_keys(const KT *__restrict__ keys, KT *__restrict__ keys_out,
+__global__ void __launch_bounds__(kRsThreads, 4) k_os_pass_keys(const KT *__restrict__ keys, KT *__restrict__ keys_out,
                                                               const unsigned long long *__restrict__ n_dev,
                                                               int64_t n_bound, int shift,
                                                               const uint32_t *__restrict__ totals, uint32_t *status,
