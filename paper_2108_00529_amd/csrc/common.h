@@ -188,9 +188,16 @@ bgv_status onesweep_sort_u32(uint32_t *keys, uint32_t *keys_alt, uint32_t *vals,
 // (one of the two).  With n_dev the key count is read on the device (*n_dev <= n) and
 // n is only its bound, so the sort can be queued before the count is known on the
 // host.  Scratch from onesweep_keys_workspace(n, nbits); n < 2^30.
+// With counted = true a producer of the keys has done the counting launch's work: it
+// wrote the digit counts of its blocks' keys (bcnt[block * passes * 256 + pass * 256 +
+// d], passes = onesweep_key_passes(nbits)) and onesweep_keys_counted summed them into
+// the scratch's totals and cleared its look-back words (wide: 64-bit keys).
 size_t onesweep_keys_workspace(int64_t n, int nbits);
+int onesweep_key_passes(int nbits);
+bgv_status onesweep_keys_counted(const uint32_t *bcnt, int64_t nblocks, int64_t n, int nbits, bool wide,
+                                 void *scratch, hipStream_t s);
 template <class KT>
 bgv_status onesweep_sort_keys(KT *keys, KT *keys_alt, int64_t n, const unsigned long long *n_dev, int nbits,
-                              KT **keys_out, void *scratch, hipStream_t s);
+                              KT **keys_out, void *scratch, hipStream_t s, bool counted = false);
 
 }  // namespace bgv

@@ -756,9 +756,49 @@ __global__ void __launch_bounds__(kRsThreads, 4) k_os_pass_keys(const KT *__rest
     }
 }
 
+// The totals from per-block digit counts that a producer of the keys wrote
+// (bcnt[block * passes * 256 + pass * 256 + d]), and the clearing of the look-back
+// words: workgroup (c, q) sums the counts of digit threadIdx.x in pass q over its share
+// of the blocks.
+constexpr int kOsSumRows = 16;
+__global__ void __launch_bounds__(kRsThreads) k_os_sum_block_counts(const uint32_t *__restrict__ bcnt, int64_t nblocks,
+                                                                     int passes, uint32_t *__restrict__ totals,
+                                                                     uint32_t *__restrict__ status, int64_t status_words) {
+    const int q = blockIdx.y;
+    const int64_t b0 = (int64_t)blockIdx.x * kOsSumRows;
+    uint32_t acc = 0;
+#pragma unroll 8
+    for (int r = 0; r < kOsSumRows; ++r) {
+        const int64_t b = b0 + r;
+        if (b < nblocks) acc += bcnt[(b * passes + q) * 256 + threadIdx.x];
+    }
+    if (acc) atomicAdd(&totals[q * 256 + threadIdx.x], acc);
+    const int64_t nthreads = (int64_t)gridDim.x * gridDim.y * kRsThreads;
+    for (int64_t i = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * kRsThreads + threadIdx.x; i < status_words;
+         i += nthreads)
+        status[i] = 0u;
+}
+
+int onesweep_key_passes(int nbits) { return os_key_passes(nbits); }
+
+bgv_status onesweep_keys_counted(const uint32_t *bcnt, int64_t nblocks, int64_t n, int nbits, bool wide,
+                                 void *scratch, hipStream_t s) {
+    const int passes = os_key_passes(nbits);
+    const int64_t tiles = wide ? os_key_tiles<uint64_t>(n) : os_key_tiles<uint32_t>(n);
+    uint32_t *totals = static_cast<uint32_t *>(scratch);
+    uint32_t *status = reinterpret_cast<uint32_t *>(static_cast<char *>(scratch) +
+                                                    align_up(sizeof(uint32_t) * kOsMaxPasses * 256));
+    const int64_t status_words = (int64_t)passes * tiles * 256 + passes;
+    BGV_TRY(fill<uint32_t>(totals, 0u, passes * 256, s));
+    const dim3 grid((unsigned)((nblocks + kOsSumRows - 1) / kOsSumRows), (unsigned)passes);
+    BGV_LAUNCH(k_os_sum_block_counts, grid, dim3(kRsThreads), 0, s, bcnt, nblocks, passes, totals, status,
+               status_words);
+    return BGV_OK;
+}
+
 template <typename KT>
 bgv_status onesweep_sort_keys(KT *keys, KT *keys_alt, int64_t n, const unsigned long long *n_dev, int nbits,
-                              KT **keys_out, void *scratch, hipStream_t s) {
+                              KT **keys_out, void *scratch, hipStream_t s, bool counted) {
     const int passes = os_key_passes(nbits);
     if (passes > (int)sizeof(KT) || n > (int64_t)kOsCountMask) {
         set_error("onesweep_sort_keys: %d key bits, %lld keys", nbits, (long long)n);
@@ -773,10 +813,12 @@ bgv_status onesweep_sort_keys(KT *keys, KT *keys_alt, int64_t n, const unsigned 
         uint32_t *status = reinterpret_cast<uint32_t *>(p);
         const int64_t status_words = (int64_t)passes * tiles * 256 + passes;
         uint32_t *counters = status + (int64_t)passes * tiles * 256;
-        BGV_TRY(fill<uint32_t>(totals, 0u, passes * 256, s));
-        const unsigned gc = grid_for(n, kRsThreads * 16, kOsCountBlocks);
-        BGV_LAUNCH(k_os_count_keys<KT>, dim3(gc), dim3(kRsThreads), 0, s, keys, n_dev, n, passes, totals, status,
-                   status_words);
+        if (!counted) {
+            BGV_TRY(fill<uint32_t>(totals, 0u, passes * 256, s));
+            const unsigned gc = grid_for(n, kRsThreads * 16, kOsCountBlocks);
+            BGV_LAUNCH(k_os_count_keys<KT>, dim3(gc), dim3(kRsThreads), 0, s, keys, n_dev, n, passes, totals, status,
+                       status_words);
+        }
         for (int pass = 0; pass < passes; ++pass) {
             BGV_LAUNCH(k_os_pass_keys<KT>, dim3((unsigned)tiles), dim3(kRsThreads), 0, s, src, dst, n_dev, n,
                        8 * pass, totals + 256 * pass, status + (int64_t)pass * tiles * 256, counters + pass);
@@ -789,9 +831,9 @@ bgv_status onesweep_sort_keys(KT *keys, KT *keys_alt, int64_t n, const unsigned 
     return BGV_OK;
 }
 template bgv_status onesweep_sort_keys<uint32_t>(uint32_t *, uint32_t *, int64_t, const unsigned long long *, int,
-                                                 uint32_t **, void *, hipStream_t);
+                                                 uint32_t **, void *, hipStream_t, bool);
 template bgv_status onesweep_sort_keys<uint64_t>(uint64_t *, uint64_t *, int64_t, const unsigned long long *, int,
-                                                 uint64_t **, void *, hipStream_t);
+                                                 uint64_t **, void *, hipStream_t, bool);
 
 int os_items(int64_t n) { return n <= (int64_t)(1 << 16) ? 4 : n <= (int64_t)(1 << 20) ? 8 : 16; }
 

@@ -206,12 +206,19 @@ constexpr int kKeyItems = 16;  // edges per thread; a block compacts kSgThreads*
 // (sid of the smaller label, sid of the larger).
 // 32-bit keys when 2 * kbits <= 32; then the supernode ids are gathered as 16-bit values
 // (half the footprint of the random gathers, which bound this kernel)
+// With bcnt, each workgroup also counts the digits of its keys for the one-sweep sort
+// (8-bit digits, `passes` of them) and writes its counts as row blockIdx.x of bcnt.
+constexpr int kKeyMaxPasses = 8;
 template <typename KT, typename NT>
 __global__ void __launch_bounds__(kSgThreads) k_sg_edge_keys(const int2 *__restrict__ edges, int64_t m,
                                                               const NT *__restrict__ nsid, int kbits,
                                                               KT *__restrict__ keys,
-                                                              unsigned long long *__restrict__ nkeys) {
+                                                              unsigned long long *__restrict__ nkeys,
+                                                              uint32_t *__restrict__ bcnt, int passes) {
     __shared__ unsigned long long s_base;
+    __shared__ uint32_t hist[kKeyMaxPasses * 256];
+    if (bcnt)
+        for (int q = 0; q < passes; ++q) hist[q * 256 + threadIdx.x] = 0u;
     const int64_t tile = (int64_t)blockIdx.x * (kSgThreads * kKeyItems);
     KT k[kKeyItems];
     uint32_t flags = 0, cnt = 0;
@@ -239,6 +246,15 @@ __global__ void __launch_bounds__(kSgThreads) k_sg_edge_keys(const int2 *__restr
 #pragma unroll
     for (int j = 0; j < kKeyItems; ++j)
         if ((flags >> j) & 1u) keys[at++] = k[j];
+    if (bcnt) {  // uniform
+#pragma unroll
+        for (int j = 0; j < kKeyItems; ++j)
+            if ((flags >> j) & 1u)
+                for (int q = 0; q < passes; ++q) atomicAdd(&hist[q * 256 + ((uint32_t)(k[j] >> (8 * q)) & 255u)], 1u);
+        __syncthreads();
+        for (int q = 0; q < passes; ++q)
+            bcnt[((int64_t)blockIdx.x * passes + q) * 256 + threadIdx.x] = hist[q * 256 + threadIdx.x];
+    }
 }
 
 // Distinct sorted keys, in tiles of kUqTile: k_sg_unique_count counts each tile's run
@@ -792,12 +808,22 @@ extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges,
     const auto k_sg_edge_keys_64 = k_sg_edge_keys<uint64_t, uint32_t>;
     const bool k32 = 2 * kbits <= 32;  // keys in 32 bits: half the sort traffic
     uint32_t *keys32 = reinterpret_cast<uint32_t *>(w.keys), *keys32_alt = reinterpret_cast<uint32_t *>(w.keys_alt);
+    // the one-sweep sort's digit counts come from the key launch, its workgroups' counts
+    // written into the sort's second key buffer (free until the first pass; 256 words
+    // per workgroup and pass, at most 2 words per edge)
+    const int64_t nkb = (m + kSgThreads * kKeyItems - 1) / (kSgThreads * kKeyItems);
+    const int passes = onesweep_key_passes(2 * kbits);
+    const bool fused_count = sg_onesweep(m) && nkb * passes * 256 <= 2 * m;
+    uint32_t *bcnt = fused_count ? reinterpret_cast<uint32_t *>(w.keys_alt) : nullptr;
     if (m > 0) {
-        const dim3 gkey((unsigned)((m + kSgThreads * kKeyItems - 1) / (kSgThreads * kKeyItems)));
+        const dim3 gkey((unsigned)nkb);
         if (k32)
-            BGV_LAUNCH(k_sg_edge_keys_32, gkey, dim3(kSgThreads), 0, s, e2, m, w.nsid16, kbits, keys32, nkeys_d);
+            BGV_LAUNCH(k_sg_edge_keys_32, gkey, dim3(kSgThreads), 0, s, e2, m, w.nsid16, kbits, keys32, nkeys_d, bcnt,
+                       passes);
         else
-            BGV_LAUNCH(k_sg_edge_keys_64, gkey, dim3(kSgThreads), 0, s, e2, m, w.nsid, kbits, w.keys, nkeys_d);
+            BGV_LAUNCH(k_sg_edge_keys_64, gkey, dim3(kSgThreads), 0, s, e2, m, w.nsid, kbits, w.keys, nkeys_d, bcnt,
+                       passes);
+        if (fused_count) BGV_TRY(onesweep_keys_counted(bcnt, nkb, m, 2 * kbits, !k32, w.sort_scratch, s));
     }
     // the key count stays on the device: everything below is sized by the edge count m,
     // which bounds it, and reads the count itself, so no host round trip is needed here
@@ -809,10 +835,10 @@ extern "C" bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges,
         if (sg_onesweep(m)) {
             if (k32)
                 BGV_TRY(onesweep_sort_keys<uint32_t>(keys32, keys32_alt, m, nkeys_d, 2 * kbits, &sorted32,
-                                                     w.sort_scratch, s));
+                                                     w.sort_scratch, s, fused_count));
             else
                 BGV_TRY(onesweep_sort_keys<uint64_t>(w.keys, w.keys_alt, m, nkeys_d, 2 * kbits, &sorted,
-                                                     w.sort_scratch, s));
+                                                     w.sort_scratch, s, fused_count));
         } else if (k32) {
             BGV_TRY(radix_sort_u32(keys32, keys32_alt, nullptr, nullptr, m, 2 * kbits, &sorted32, nullptr,
                                    w.sort_scratch, s, false, nkeys_d));
