@@ -388,6 +388,19 @@ def test_supergraph_key_width_boundary(bgv, K):
         assert ref["K"] == K
 
 
+@pytest.mark.parametrize("K,m", [(70_000, 500), (70_000, 5_000), (1_000, 300), (1_000, 20_000)])
+def test_supergraph_short_key_lists(bgv, K, m):
+    """Every node its own community, few edges: key lists short enough that the sort
+    counts the digits in a launch of its own (500 and 300 keys), and just long enough
+    for the key launch to count them (5,000 and 20,000 keys); 34-bit and 20-bit keys."""
+    rng = np.random.default_rng(K + m)
+    e = rng.integers(0, K, (m, 2)).astype(np.int32)
+    lab = np.arange(K, dtype=np.int32)
+    deg = np.bincount(e[e[:, 0] != e[:, 1]].ravel(), minlength=K).astype(np.int32)
+    sg, ref = check_supergraph(bgv, K, e, lab, deg, 3, 1 << 12, 11)
+    assert ref["K"] == K
+
+
 # ---------------------------------------------------------------- ForceAtlas2 ----
 @pytest.fixture(scope="module")
 def planted_sg(planted):
