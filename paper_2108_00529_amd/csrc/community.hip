@@ -407,7 +407,9 @@ __device__ __forceinline__ void cd_segment(const uint32_t *__restrict__ tab, int
     *q1 = row[b + 1];
 }
 
-template <int kB>
+// kEnds: the launch also adds grouped endpoint increments (pass 0); without them the
+// workgroup needs no increment array and two fit a compute unit's LDS.
+template <int kB, bool kEnds>
 __global__ void __launch_bounds__(kCdResolveThreads) k_cd_resolve(int32_t *__restrict__ cnt,
                                                                    int32_t *__restrict__ lab, int32_t n, int32_t nb,
                                                                    const uint3 *__restrict__ props,
@@ -417,12 +419,12 @@ __global__ void __launch_bounds__(kCdResolveThreads) k_cd_resolve(int32_t *__res
                                                                    int32_t lanes, uint8_t *__restrict__ cnt8,
                                                                    uint16_t *__restrict__ cnt16) {
     __shared__ unsigned long long win[1 << kB];
-    __shared__ uint32_t inc[1 << kB];
+    __shared__ uint32_t inc[kEnds ? (1 << kB) : 1];
     const int32_t b = cd_resolve_bucket((int32_t)blockIdx.x, nb);
     if (b >= nb) return;  // the grid is rounded up to a multiple of the XCD count
     for (int32_t k = threadIdx.x; k < (1 << kB); k += kCdResolveThreads) {
         win[k] = ~0ull;
-        inc[k] = 0u;
+        if (kEnds) inc[k] = 0u;
     }
     __syncthreads();
     const int32_t tiles = max(ptiles, etiles);
@@ -442,6 +444,7 @@ __global__ void __launch_bounds__(kCdResolveThreads) k_cd_resolve(int32_t *__res
             for (int u = 0; u < 4; ++u)
                 if (q + u * L < p1) atomicMin(&win[v[u].x], ((unsigned long long)v[u].y << 32) | v[u].z);
         }
+        if (!kEnds) continue;
         const uint16_t *es = ends + (int64_t)t * (2 * kCdTile);
         for (uint32_t q = e0 + sub; q < e1; q += 8 * L) {
             uint32_t v[8];
@@ -458,7 +461,7 @@ __global__ void __launch_bounds__(kCdResolveThreads) k_cd_resolve(int32_t *__res
     const int32_t span = min(1 << kB, n - (b << kB));
     for (int32_t k = threadIdx.x; k < span; k += kCdResolveThreads) {
         const unsigned long long w = win[k];
-        const uint32_t c = inc[k];
+        const uint32_t c = kEnds ? inc[k] : 0u;
         if (w != ~0ull) lab[base + k] = (int32_t)(uint32_t)w;
         if (c) {
             const int32_t v = cnt[base + k] + (int32_t)c;
@@ -715,7 +718,8 @@ static bgv_status cd_run_bucketed(int32_t n, int64_t m, const int2 *e2, const bg
     const int64_t nchunk = (m + B - 1) / B;
     const int32_t nb = cd_buckets(n, kB);
     // one profiler name per kernel, whatever the bucket size
-    const auto k_cd_resolve = bgv::k_cd_resolve<kB>;
+    const auto k_cd_resolve = bgv::k_cd_resolve<kB, true>;
+    const auto k_cd_resolve_props = bgv::k_cd_resolve<kB, false>;  // no endpoint increments
     const auto k_cd_group = k_cd_step<-1, kB, int32_t>;
     const auto k_cd_step0 = k_cd_step<0, kB, C0>;
     const auto k_cd_step1 = k_cd_step<1, kB, C0>;
@@ -760,9 +764,12 @@ static bgv_status cd_run_bucketed(int32_t n, int64_t m, const int2 *e2, const bg
             const int64_t cs = k * B, ce = (cs + B < m) ? cs + B : m;
             const int32_t tiles = tiles_of(k);
             // proposals of the previous chunk and, in pass 0, this chunk's increments
-            if (ptiles > 0 || etiles > 0)
+            if (etiles > 0)
                 BGV_LAUNCH(k_cd_resolve, dim3(cd_resolve_grid(nb)), dim3(kCdResolveThreads), 0, s, w.cnt, w.lab, n, nb, w.props, w.ptab,
                            ptiles, w.ends, w.etab, etiles, cd_resolve_lanes(std::max(ptiles, etiles), nb), cnt8, cnt16);
+            else if (ptiles > 0)
+                BGV_LAUNCH(k_cd_resolve_props, dim3(cd_resolve_grid(nb)), dim3(kCdResolveThreads), 0, s, w.cnt, w.lab, n, nb,
+                           w.props, w.ptab, ptiles, w.ends, w.etab, 0, cd_resolve_lanes(ptiles, nb), cnt8, cnt16);
             // counters are incremented in pass 0 only (later passes use the closed form):
             // the next chunk's endpoints are grouped by this launch in pass 0
             const bool group_next = pass == 0 && k + 1 < nchunk;
@@ -787,16 +794,16 @@ static bgv_status cd_run_bucketed(int32_t n, int64_t m, const int2 *e2, const bg
         }
         if (pass_labels) {
             if (ptiles > 0)
-                BGV_LAUNCH(k_cd_resolve, dim3(cd_resolve_grid(nb)), dim3(kCdResolveThreads), 0, s, w.cnt, w.lab, n, nb, w.props,
-                           w.ptab, ptiles, w.ends, w.etab, 0, cd_resolve_lanes(ptiles, nb), cnt8, cnt16);
+                BGV_LAUNCH(k_cd_resolve_props, dim3(cd_resolve_grid(nb)), dim3(kCdResolveThreads), 0, s, w.cnt, w.lab, n,
+                           nb, w.props, w.ptab, ptiles, w.ends, w.etab, 0, cd_resolve_lanes(ptiles, nb), cnt8, cnt16);
             ptiles = 0;
             BGV_LAUNCH(k_cd_copy_labels, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, w.lab, 1,
                        n, pass_labels + (int64_t)pass * n);
         }
     }
     if (ptiles > 0)
-        BGV_LAUNCH(k_cd_resolve, dim3(cd_resolve_grid(nb)), dim3(kCdResolveThreads), 0, s, w.cnt, w.lab, n, nb, w.props, w.ptab, ptiles, w.ends,
-                   w.etab, 0, cd_resolve_lanes(ptiles, nb), cnt8, cnt16);
+        BGV_LAUNCH(k_cd_resolve_props, dim3(cd_resolve_grid(nb)), dim3(kCdResolveThreads), 0, s, w.cnt, w.lab, n, nb,
+                   w.props, w.ptab, ptiles, w.ends, w.etab, 0, cd_resolve_lanes(ptiles, nb), cnt8, cnt16);
     BGV_LAUNCH(k_cd_finish_b, dim3(grid_for(n, kCdThreads, 65536)), dim3(kCdThreads), 0, s, w.cnt, w.lab, n,
                labels, degree, reinterpret_cast<unsigned long long *>(volume));
     return BGV_OK;
