@@ -200,7 +200,9 @@ size_t bgv_supergraph_workspace(int32_t n, int64_t m, const bgv_sketch_params *s
  *   se_weight    dev uint32[cap m]   sketch-2 estimate of the superedge multiplicity
  *   se_count     dev uint32[cap m] or NULL   exact multiplicity (number of edges)
  *   M1, M2       dev uint32[rows][cols] the two sketches (required)
- * Synchronises `stream` (K and E_S are returned on the host).
+ * Synchronises `stream` (K and E_S are returned on the host): twice, each time by
+ * polling an event with the calling thread (which stays busy until the work queued
+ * before it has run) rather than sleeping on it.
  */
 bgv_status bgv_supergraph(int32_t n, int64_t m, const int32_t *edges, const int32_t *labels,
                           const int32_t *degree, const bgv_sketch_params *s,
